@@ -1,0 +1,381 @@
+"""Pins for the CPU oracle: values, closed forms, identities and a second brute
+force that the paper and the mathematics fix independently of the oracle's own
+code.  No GPU needed."""
+import itertools
+import math
+import os
+from collections import Counter
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import tm_inputs as ti
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def arr(edges):
+    s = np.array([e[0] for e in edges], dtype=np.int32)
+    d = np.array([e[1] for e in edges], dtype=np.int32)
+    t = np.array([e[2] for e in edges], dtype=np.int64)
+    return s, d, t
+
+
+def ocount(edges, motif, delta, win=None):
+    s, d, t = arr(edges)
+    return oracle.count(s, d, t, motif, delta, win=win)
+
+
+def hist_of(counter, delta):
+    h = np.zeros(delta + 1, dtype=np.uint64)
+    for k, v in counter.items():
+        h[k] = v
+    return h
+
+
+# ------------------------------------------------------------------ Philox
+
+def test_philox_known_answers():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append([int(x, 16) for x in line.split()])
+    assert len(rows) == 3
+    for r in rows:
+        assert oracle.philox4x32_10(r[0:4], r[4:6]) == r[6:10]
+
+
+def test_draw_layout_and_uniformity():
+    # draw = (word1 << 32) | word0 of counter (lo j, hi j, k, domain), key = seed
+    seed, j = 0x0123456789ABCDEF, (5 << 32) | 7
+    w = oracle.philox4x32_10([7, 5, 0, 1], [0x89ABCDEF, 0x01234567])
+    assert oracle.draw(seed, j, 0, 1) == (w[1] << 32) | w[0]
+    # chi-square of the top 4 bits over 8000 draws (15 dof, 0.1% critical ~37.7)
+    cnt = Counter(oracle.draw(3, jj, 0, 1) >> 60 for jj in range(8000))
+    chi = sum((cnt[b] - 500) ** 2 / 500 for b in range(16))
+    assert chi < 37.7
+
+
+# ------------------------------------------------------------ hand fixtures
+
+TRI = ti.TRIANGLE
+
+
+def test_h1_single_triangle():
+    e = [(0, 1, 1), (1, 2, 2), (2, 0, 3)]
+    for delta in (2, 3, 10):
+        n, h = ocount(e, TRI, delta)
+        assert n == 1 and h[2] == 1
+    assert ocount(e, TRI, 1)[0] == 0
+    # a rotation of the times is still a cyclic triangle ...
+    assert ocount([(0, 1, 2), (1, 2, 3), (2, 0, 1)], TRI, 10)[0] == 1
+    # ... but a reversal or a swap of the last two edges is not
+    assert ocount([(0, 1, 3), (1, 2, 2), (2, 0, 1)], TRI, 10)[0] == 0
+    assert ocount([(0, 1, 1), (1, 2, 3), (2, 0, 2)], TRI, 10)[0] == 0
+
+
+def test_h2_tied_times_never_share_an_instance():
+    assert ocount([(0, 1, 1), (1, 2, 1), (2, 0, 2)], TRI, 10)[0] == 0
+    assert ocount([(0, 1, 1), (1, 2, 2), (2, 0, 2)], TRI, 10)[0] == 0
+    assert ocount([(0, 1, 1), (1, 2, 2), (2, 0, 3)], TRI, 10)[0] == 1
+
+
+@pytest.mark.parametrize("nab,nbc,nca", [(1, 1, 1), (3, 2, 4), (5, 1, 2)])
+def test_h3_blocks_multiply(nab, nbc, nca):
+    e, t = [], 0
+    for (u, v, k) in ((0, 1, nab), (1, 2, nbc), (2, 0, nca)):
+        for _ in range(k):
+            t += 1
+            e.append((u, v, t))
+    assert ocount(e, TRI, t)[0] == nab * nbc * nca
+
+
+def test_h4_single_pair_closed_form():
+    Lc = 9
+    e = [(0, 1, t) for t in range(1, Lc + 1)]
+    m3 = ((0, 1), (0, 1), (0, 1))
+    assert ocount(e, m3, Lc - 1)[0] == math.comb(Lc, 3)
+    for delta in range(0, Lc + 1):
+        expect = sum(math.comb(min(Lc - i, delta), 2) for i in range(1, Lc + 1))
+        n, h = ocount(e, m3, delta)
+        assert n == expect
+        # durations: instance (i, j, k) has duration k - i; count per duration d
+        # = (d - 1) middles times (Lc - d) anchors
+        for d in range(delta + 1):
+            assert int(h[d]) == (max(d - 1, 0) * (Lc - d) if d >= 2 else 0)
+
+
+def test_h5_ex23_off_by_one_reading():
+    e = [(0, 1, 1), (1, 0, 2), (0, 1, 3)]
+    assert ocount(e, ti.TWO_NODE_ALT, 5)[0] == 1
+    c = oracle.ex23(e, 5)
+    assert sum(c.values()) == 1 and c[2] == 1
+
+
+def test_h6_fig1_fragment():
+    edges, motif, cases = [], None, []
+    with open(os.path.join(GOLDEN, "fig1_fragment.txt")) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            p = line.split()
+            if p[0] == "motif":
+                v = [int(x) for x in p[1:]]
+                motif = tuple(zip(v[0::2], v[1::2]))
+            elif len(p) == 3 and p[2] != "-" and len(edges) < 4:
+                edges.append(tuple(int(x) for x in p))
+            else:
+                cases.append((int(p[0]), int(p[1]), None if p[2] == "-" else int(p[2])))
+    assert len(edges) == 4 and motif == ti.STAR4 and len(cases) == 4
+    for delta, n_exp, dur in cases:
+        n, h = ocount(edges, motif, delta)
+        assert n == n_exp
+        if dur is not None:
+            assert h[dur] == 1
+
+
+@pytest.mark.parametrize("d,k", [(5, 2), (6, 3), (7, 4), (4, 4)])
+def test_h7_static_star_binomial(d, k):
+    e = [(0, 1 + i, 1 + i) for i in range(d)]
+    motif = tuple((0, 1 + j) for j in range(k))
+    assert ocount(e, motif, d - 1)[0] == math.comb(d, k)
+    assert ocount(e, motif, k - 2)[0] == 0
+
+
+def test_h8_bijection_trap():
+    e = [(0, 1, 1), (1, 0, 2), (0, 1, 3)]
+    assert ocount(e, TRI, 10)[0] == 0
+    # the same edges are one instance of the two-node motif
+    assert ocount(e, ti.TWO_NODE_ALT, 10)[0] == 1
+
+
+def test_h9_window_boundaries_every_shift():
+    # delta = 5, c = 2 -> L = 10; the triangle spans times 8..12 (Delta = 4)
+    e = [(0, 1, 0), (5, 6, 8), (6, 7, 10), (7, 5, 12), (3, 4, 25)]
+    s, d, t = arr(e)
+    delta, c = 5, 2
+    L = c * delta
+    for shift in range(-L + 1, 1):
+        r = oracle.estimate(s, d, t, TRI, delta, c, 1.0, 0, force_shift=shift)
+        # the instance is inside window j iff [8, 12] is inside [s+(j-1)L, s+jL-1]
+        inside = any(shift + (j - 1) * L <= 8 and 12 <= shift + j * L - 1 for j in range(1, r["J"] + 1))
+        assert int(r["win_counts"].sum()) == (1 if inside else 0)
+        assert r["J"] == 1 + -(-25 // L)
+
+
+# ------------------------------------------------- second brute force (tier B)
+
+MOTIFS = ti.three_edge_motifs() + [ti.CYCLE4, ti.STAR4, ti.OUTSTAR5, ((0, 1),), ((0, 1), (1, 0)),
+                                    ((0, 1), (2, 0)), ((0, 1), (1, 2), (2, 3))]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_tier_a_equals_tuple_brute_force(seed):
+    g = ti.random_small_graph(4 + seed % 2, 13, 10, seed, allow_self_loops=(seed % 3 == 0))
+    edges = list(zip(g.src.tolist(), g.dst.tolist(), g.t.tolist()))
+    for M in MOTIFS:
+        for delta in (0, 2, 6):
+            b = oracle.brute(edges, M, delta)
+            n, h = ocount(edges, M, delta)
+            assert n == sum(b.values()), (M, delta)
+            assert (h == hist_of(b, delta)).all(), (M, delta)
+            win = (2, 7)
+            bw = oracle.brute(edges, M, delta, win=win)
+            nw, hw = ocount(edges, M, delta, win=win)
+            assert nw == sum(bw.values()) and (hw == hist_of(bw, delta)).all()
+
+
+def test_three_edge_motif_catalogue():
+    mot = ti.three_edge_motifs()
+    assert len(mot) == 36
+    two = [m for m in mot if len({x for e in m for x in e}) == 2]
+    assert len(two) == 4
+    # 3-node motifs: stars have one node on all three edges, the rest are triangles
+    three = [m for m in mot if m not in two]
+    star = [m for m in three if any(all(x in e for e in m) for x in range(3))]
+    assert len(star) == 24 and len(three) - len(star) == 8
+    assert ti.TRIANGLE in mot and ti.TWO_NODE_ALT in mot
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_ex23_equals_oracle(seed):
+    rng = np.random.default_rng(100 + seed)
+    m = 40
+    src = rng.integers(0, 4, m)
+    dst = (src + rng.integers(1, 4, m)) % 4
+    t = rng.permutation(300)[:m]
+    edges = list(zip(src.tolist(), dst.tolist(), t.tolist()))
+    for delta in (10, 60, 300):
+        c = {d: n for d, n in oracle.ex23(edges, delta).items() if n}
+        n, h = oracle.count(src, dst, t, ti.TWO_NODE_ALT, delta)
+        assert c == {d: int(v) for d, v in enumerate(h) if v}
+
+
+# ------------------------------------------------------------- hardness
+
+def hardness_instance(n, gedges, k):
+    """Temporal graph and star motif of the reduction from k-Clique (Sec. 3).
+    Graph nodes 1..n, center 0.  Motif nodes: center 0, leaves 1..k."""
+    T = []
+    B = n + 2
+    for (u, v) in gedges:
+        T.append((0, u, (v - 1) * B + u + 1))
+        T.append((0, v, (u - 1) * B + v + 1))
+    for u in range(1, n + 1):
+        T.append((u, 0, (u - 1) * B + 1))
+        T.append((u, 0, u * B))
+    S = []
+    for leaf in range(1, k + 1):
+        S.append((leaf, 0))
+        S.extend((0, other) for other in range(1, k + 1) if other != leaf)
+        S.append((leaf, 0))
+    return T, tuple(S)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_hardness_reduction_counts_cliques(seed):
+    rng = np.random.default_rng(seed)
+    n = 6
+    gedges = [(u, v) for u in range(1, n + 1) for v in range(u + 1, n + 1) if rng.random() < 0.55]
+    adj = set(gedges) | {(v, u) for u, v in gedges}
+    for k in (2, 3):
+        T, S = hardness_instance(n, gedges, k)
+        s, d, t = arr(T)
+        cnt, _ = oracle.count(s, d, t, S, oracle.INT64_MAX, hist=False)
+        cliques = sum(1 for c in itertools.combinations(range(1, n + 1), k)
+                      if all((a, b) in adj for a, b in itertools.combinations(c, 2)))
+        assert cnt == cliques
+
+
+# --------------------------------------------------- estimator identities
+
+def small_cases():
+    out = []
+    for seed in range(4):
+        g = ti.random_small_graph(4, 11, 14, 500 + seed)
+        out.append(list(zip(g.src.tolist(), g.dst.tolist(), g.t.tolist())))
+    return out
+
+
+@pytest.mark.parametrize("motif", [ti.TRIANGLE, ti.TWO_NODE_ALT, ((0, 1), (0, 2), (0, 1))])
+@pytest.mark.parametrize("c", [2, 3])
+def test_window_identities_every_shift(motif, c):
+    """For every duration d: sum over all L shifts of the within-window
+    histogram equals (L - d) * H(d)  (containment probability 1 - d/L), and
+    the mean over shifts of ||Y_s||_1 equals C_M exactly (Lemma Ys_unbiased);
+    the variance over shifts is at most C_M^2 / (c - 1) (Lemma var_Ys)."""
+    delta = 3
+    L = c * delta
+    for edges in small_cases():
+        H = oracle.brute(edges, motif, delta)
+        CM = sum(H.values())
+        per_s = oracle.windows_all_shifts(edges, motif, delta, c)
+        assert len(per_s) == L
+        tot = Counter()
+        ys = []
+        for s, wins in per_s.items():
+            for w in wins:
+                tot.update(w)
+            ys.append(oracle.y_norm_exact(wins, L))
+        for d in range(delta + 1):
+            assert tot[d] == (L - d) * H[d]
+        mean = sum(ys, Fraction(0)) / L
+        assert mean == CM
+        var = sum(((y - mean) ** 2 for y in ys), Fraction(0)) / L
+        assert var <= Fraction(CM * CM, c - 1)
+        # the C oracle's windowed counts agree with the tuple brute force
+        s_, d_, t_ = arr(edges)
+        for s in (-L + 1, -1, 0):
+            r = oracle.estimate(s_, d_, t_, motif, delta, c, 1.0, 0, force_shift=s)
+            assert r["n_kept"] == len(per_s[s])
+            assert [int(x) for x in r["win_counts"]] == [sum(w.values()) for w in per_s[s]]
+            # p = 1: Z equals ||Y_s||_1 for that shift
+            y = oracle.y_norm_exact(per_s[s], L)
+            assert abs(r["Z"] - float(y)) <= 1e-12 * max(1.0, float(y))
+
+
+def test_p1_equals_norm_minus_straddlers():
+    """At p = 1 the kept windows are all windows; their total equals C_M minus
+    the instances that straddle a window boundary (exact integers)."""
+    g = ti.random_small_graph(5, 60, 200, 77)
+    edges = list(zip(g.src.tolist(), g.dst.tolist(), g.t.tolist()))
+    s_, d_, t_ = arr(edges)
+    delta, c = 20, 3
+    L = c * delta
+    tmin = int(t_.min())
+    for seed in range(5):
+        r = oracle.estimate(s_, d_, t_, ti.TRIANGLE, delta, c, 1.0, seed)
+        sh = r["s"]
+        win_of = lambda tt: (tt - tmin - sh) // L
+        total, straddle = 0, 0
+        for tup in itertools.permutations(range(len(edges)), 3):
+            es = [edges[i] for i in tup]
+            if not (es[0][2] < es[1][2] < es[2][2]) or es[2][2] - es[0][2] > delta:
+                continue
+            f = {}
+            ok = True
+            for (mu, mv), (gu, gv, _) in zip(ti.TRIANGLE, es):
+                if f.setdefault(mu, gu) != gu or f.setdefault(mv, gv) != gv:
+                    ok = False
+            if not ok or len(set(f.values())) != 3:
+                continue
+            total += 1
+            straddle += win_of(es[0][2]) != win_of(es[2][2])
+        assert int(r["win_counts"].sum()) == total - straddle
+
+
+def test_conditional_variance_lemma():
+    """Lemma var_Zs: with the shift held fixed, Var[Z | s] = sum_j
+    Y_{s,j}^2 (1/q_j - 1).  Closed form from exact per-window weights versus
+    the empirical variance over 3000 seeds."""
+    g = ti.random_small_graph(4, 70, 400, 9)
+    edges = list(zip(g.src.tolist(), g.dst.tolist(), g.t.tolist()))
+    s_, d_, t_ = arr(edges)
+    delta, c, p = 15, 2, 0.3
+    L = c * delta
+    shift = -7
+    tmin = int(t_.min())
+    tn = t_ - tmin
+    J = 1 + -(-int(tn.max()) // L)
+    ys = []
+    for j in range(1, J + 1):
+        _, h = oracle.count(s_, d_, tn, ti.TWO_NODE_ALT, delta, win=(shift + (j - 1) * L, shift + j * L - 1))
+        ys.append(sum(Fraction(int(n) * L, L - dd) for dd, n in enumerate(h) if n))
+    ynorm = float(sum(ys))
+    var_cf = float(sum(y * y for y in ys) * (1 / Fraction(p) - 1))
+    assert var_cf > 0
+    zs = np.array([oracle.estimate(s_, d_, t_, ti.TWO_NODE_ALT, delta, c, p, seed, force_shift=shift)["Z"]
+                   for seed in range(3000)])
+    assert abs(zs.mean() - ynorm) < 4 * math.sqrt(var_cf / len(zs))
+    assert abs(zs.var() / var_cf - 1) < 0.12
+
+
+def test_weight_matches_exact_rational():
+    rng = np.random.default_rng(5)
+    for delta, c, p in ((50, 2, 0.1), (3600, 30, 0.01), (7, 3, 1.0)):
+        L = c * delta
+        lo = rng.integers(0, 1 << 62, size=delta + 1, dtype=np.int64).astype(np.uint64)
+        lo[rng.random(delta + 1) < 0.3] = 0
+        hi = rng.integers(0, 4, size=delta + 1, dtype=np.int64).astype(np.uint64)
+        z = oracle.weight(lo, delta, L, p, hist_hi=hi)
+        exact = sum((Fraction((int(h) << 64) + int(l_) ) * Fraction(L, L - d) for d, (l_, h) in
+                     enumerate(zip(lo, hi))), Fraction(0)) / Fraction(p)
+        assert abs(Fraction(z) - exact) <= Fraction(1, 10 ** 12) * exact
+
+
+@pytest.mark.slow
+def test_estimator_unbiased_over_1000_seeds():
+    """Mean of Z over seeds 0..999 lies within 3 standard errors of the exact
+    count (the unbiasedness theorem of Sec. 4), on the 50-node version of the
+    small uniform workload (triangle, delta 3600, c 30, p 0.1)."""
+    g = ti.config_small_dense()
+    delta, c, p = 3600, 30, 0.1
+    CM, _ = oracle.count(g.src, g.dst, g.t, ti.TRIANGLE, delta, hist=False)
+    assert CM > 100
+    zs = np.array([oracle.estimate(g.src, g.dst, g.t, ti.TRIANGLE, delta, c, p, seed)["Z"]
+                   for seed in range(1000)])
+    se = zs.std(ddof=1) / math.sqrt(len(zs))
+    assert abs(zs.mean() - CM) < 3 * se
