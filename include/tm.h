@@ -1,0 +1,194 @@
+/*
+ * tm.h -- C ABI of the MI355X (gfx950) temporal-motif library.
+ *
+ * What it computes (Liu, Benson, Charikar, "A sampling framework for counting
+ * temporal motifs", WSDM'19):
+ *
+ *  - the exact number C_M of delta-instances of a temporal motif M
+ *    (Sec. 2, Definitions "temporal motif" and "motif delta-instance"):
+ *    time-ordered sequences of distinct temporal edges, with strictly
+ *    increasing times (Definition "motif duration"), that map onto M's edges
+ *    in order through a bijection of nodes, and whose first and last times
+ *    differ by at most delta (inclusive);
+ *
+ *  - the unbiased estimate Z of Algorithm 1 (Sec. 4) with one shift (b = 1)
+ *    and the same sampling probability q_j = p for every window: times are
+ *    normalised to start at 0, the shift s is drawn uniformly from
+ *    {-c delta + 1, ..., 0}, window j covers [s + (j-1) c delta,
+ *    s + j c delta - 1], each window is kept when its uniform draw is below
+ *    p, each kept window is counted exactly, and an instance of duration
+ *    Delta adds 1 / ((1 - Delta / (c delta)) p)  (equation "estimator").
+ *
+ * Conventions shared by every entry point:
+ *
+ *  - Every function returns a tm_status.  Outputs are written only on TM_OK;
+ *    no exception or signal crosses the ABI.
+ *  - hip_stream is a hipStream_t passed as void* (NULL = the default
+ *    stream).  Each call enqueues its device work on that stream and returns
+ *    after it has completed; results are host values.
+ *  - A tm_graph is immutable once loaded; calls that only read it may run
+ *    concurrently from different host threads on different streams.
+ *  - Motifs use node labels 0..k-1 in order of first appearance (edge 0 is
+ *    (0,1)); no self-loops; every edge after the first touches a node of an
+ *    earlier edge (prefix-connected); 1 <= l <= 4 edges.  Other motifs give
+ *    TM_EUNSUPPORTED (l > 4, not prefix-connected) or TM_EINVAL.
+ *  - Graph self-loop edges are accepted and never match (the node map of an
+ *    instance is a bijection).  Tied timestamps are accepted; tied edges
+ *    never share an instance.
+ */
+#ifndef TM_H
+#define TM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TM_OK = 0,
+    TM_EINVAL = 1,        /* bad argument (sizes, ids, delta, c, p, motif form) */
+    TM_EUNSUPPORTED = 2,  /* motif outside the supported class                */
+    TM_ENOMEM = 3,        /* device or host allocation failed                 */
+    TM_EBUDGET = 4,       /* request exceeds the caller's memory budget       */
+    TM_EOVERFLOW = 5,     /* result does not fit the requested width          */
+    TM_EDEVICE = 6        /* a HIP runtime call failed                        */
+} tm_status;
+
+/* exact non-negative 128-bit count: value = hi * 2^64 + lo */
+typedef struct { uint64_t lo, hi; } tm_u128;
+
+/* motif edges (src[i] -> dst[i]), i = 0..l-1, in the motif's time order */
+typedef struct { int32_t l; int32_t src[4]; int32_t dst[4]; } tm_motif;
+
+typedef struct tm_graph tm_graph;
+
+typedef struct {
+    int64_t m;            /* temporal edges                                  */
+    int64_t n;            /* nodes                                           */
+    int64_t t_min;        /* smallest input time (normalisation origin)      */
+    int64_t t_span;       /* largest normalised time t - t_min               */
+    int64_t n_pairs;      /* distinct directed (u, v) pairs, u != v          */
+    int64_t device_bytes; /* device memory held by the graph                 */
+} tm_graph_info;
+
+/* Optional diagnostics of one estimate.  Pointers are caller-owned host
+   buffers (each may be NULL); the first `cap` kept windows are written. */
+typedef struct {
+    int64_t shift;        /* s, in {-c delta + 1, ..., 0}                    */
+    int64_t n_windows;    /* J = 1 + ceil(t_span / (c delta))                */
+    int64_t n_kept;       /* windows kept by the Bernoulli draws             */
+    tm_u128 kept_count;   /* exact instance count summed over kept windows   */
+    int64_t cap;          /* capacity of kept_ids / win_counts               */
+    int64_t *kept_ids;    /* kept window indices j (1-based), ascending      */
+    uint64_t *win_counts; /* exact count of each kept window (low 64 bits)   */
+    uint64_t *hist_lo;    /* delta+1 bins: N(Delta) summed over kept windows */
+    uint64_t *hist_hi;    /*   (high 64 bits of each bin)                    */
+} tm_est_info;
+
+/*
+ * Load a temporal graph (Sec. 2: tuples (u_i, v_i, t_i), i = 1..m) onto the
+ * current device.  src/dst are int32 node ids in [0, n_nodes), t int64
+ * times; the three arrays have m entries and live in host memory
+ * (on_device = 0) or device memory (on_device = 1).  They are copied; the
+ * library keeps no caller pointer.  The graph is stored time-sorted with
+ * per-node time-sorted incidence lists (device radix sort + CSR build).
+ * Errors: TM_EINVAL (m < 0, n_nodes <= 0, an id outside [0, n_nodes), NULL
+ * array with m > 0), TM_ENOMEM, TM_EDEVICE.  *out is owned by the caller
+ * until tm_free_graph.
+ */
+tm_status tm_load_graph(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t m,
+                        int32_t n_nodes, int32_t on_device, void *hip_stream, tm_graph **out);
+
+/* Release a graph and its device memory.  NULL is ignored. */
+void tm_free_graph(tm_graph *g);
+
+/* Sizes of a loaded graph. */
+tm_status tm_graph_info_get(const tm_graph *g, tm_graph_info *info);
+
+/*
+ * Exact count C_M of delta-instances of M in the whole graph (Sec. 2,
+ * Definition "motif delta-instance").  delta >= 0.  Exact 128-bit result.
+ */
+tm_status tm_count_exact(const tm_graph *g, const tm_motif *M, int64_t delta, tm_u128 *count,
+                         void *hip_stream);
+
+/* As tm_count_exact; TM_EOVERFLOW when the count is 2^63 or more. */
+tm_status tm_count_exact_i64(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t *count,
+                             void *hip_stream);
+
+/*
+ * Exact counts and duration histograms of n_motifs motifs in one pass.
+ * counts[i] receives C_M of motifs[i].  hist_lo/hist_hi (nullable, host,
+ * n_motifs * (delta + 1) entries, motif-major) receive the number of
+ * instances of each duration Delta = t_l - t_1 (Definition "motif
+ * duration"); with histograms delta must be <= 2^26 (else TM_EUNSUPPORTED).  The pass shares the graph scans between motifs when all of
+ * them have three edges.
+ */
+tm_status tm_count_exact_multi(const tm_graph *g, int32_t n_motifs, const tm_motif *motifs,
+                               int64_t delta, tm_u128 *counts, uint64_t *hist_lo,
+                               uint64_t *hist_hi, void *hip_stream);
+
+/*
+ * Per-anchor counts: for each listed edge (index into the caller's input
+ * arrays as given to tm_load_graph), the number of delta-instances whose
+ * first edge is that edge and whose edges all have normalised time
+ * <= win_end[i] (win_end NULL: no window).  out[i] is 64-bit (TM_EOVERFLOW
+ * when one does not fit).  Host arrays of n_anchor entries.
+ */
+tm_status tm_count_anchors(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t n_anchor,
+                           const int64_t *anchor, const int64_t *win_end, uint64_t *out,
+                           void *hip_stream);
+
+/*
+ * The estimate Z of Algorithm 1 (Sec. 4) for one shift with q_j = p.
+ * delta >= 1, c >= 2 (at c = 1 an instance of duration delta would have
+ * containment probability 0), 0 < p <= 1, any seed.  TM_EINVAL when c delta
+ * exceeds 2^61 or the graph's time span exceeds 2^63 - 1 - 2 c delta;
+ * TM_EUNSUPPORTED when delta > 2^26 (the histogram has delta + 1 bins).  The random numbers come
+ * from Philox4x32-10 keyed by the seed: the shift is -(X mod c delta) for the
+ * draw X at counter (0, 0, 0, 0); window j is kept when (Y_j >> 11) 2^-53 < p
+ * for the draw Y_j at counter (j mod 2^32, j div 2^32, 0, 1); a draw is the
+ * 64-bit (word1 << 32) | word0.  Kept windows are counted exactly; the
+ * duration histogram N(Delta) summed over kept windows is weighted in FP64
+ * in ascending Delta with compensated summation:
+ * Z = (1/p) sum_Delta N(Delta) c delta / (c delta - Delta).
+ * info (nullable) receives the diagnostics above.
+ */
+tm_status tm_estimate(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t c, double p,
+                      uint64_t seed, double *estimate, tm_est_info *info, void *hip_stream);
+
+/*
+ * Estimates for n_motifs motifs under one (delta, c, p, seed): the same
+ * shift and kept windows for all of them (one pass when all have three
+ * edges).  estimates[i] for motifs[i]; kept_counts (nullable) the exact
+ * per-motif instance counts over the kept windows.
+ */
+tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, const tm_motif *motifs,
+                            int64_t delta, int64_t c, double p, uint64_t seed, double *estimates,
+                            tm_u128 *kept_counts, void *hip_stream);
+
+/*
+ * Batched estimator: n_seeds independent estimates (one shift and one set
+ * of window draws per seed, Algorithm 1's outer loop run as independent
+ * estimators) of one motif, all sampled windows of all seeds counted in one
+ * persistent launch whose work-groups take anchor tiles from a shared queue.
+ * estimates[k] for seeds[k].  Each estimate equals tm_estimate with that
+ * seed.  tile = anchors per queue item (0: autotuned).
+ */
+tm_status tm_estimate_batch(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t c,
+                            double p, int32_t n_seeds, const uint64_t *seeds, int32_t tile,
+                            double *estimates, tm_u128 *kept_counts, void *hip_stream);
+
+/* Human-readable name of a status code (static storage). */
+const char *tm_strerror(tm_status s);
+
+/* Library version string (static storage). */
+const char *tm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TM_H */

@@ -1,0 +1,256 @@
+"""Python binding of libtm, the MI355X (gfx950) temporal-motif library.
+
+Argument marshalling only: every step of counting and estimation runs in the
+HIP kernels of ``libtm.so`` (built in-tree by ``build.py``).  The binding
+raises ``ImportError`` when the library is missing, and ``TMError`` when a
+call returns a status other than TM_OK; there is no CPU fallback.
+
+Graph arrays can be numpy arrays (host) or torch tensors on the GPU (device);
+torch is used only for device memory and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libtm.so is not built ({LIB_PATH}); run paper_1810_00980_amd/build.py")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+STATUS = {0: "TM_OK", 1: "TM_EINVAL", 2: "TM_EUNSUPPORTED", 3: "TM_ENOMEM", 4: "TM_EBUDGET",
+          5: "TM_EOVERFLOW", 6: "TM_EDEVICE"}
+
+
+class TMError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)} ({_lib.tm_strerror(status).decode()})")
+
+
+class U128(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+    def value(self) -> int:
+        return (int(self.hi) << 64) | int(self.lo)
+
+
+class Motif(ctypes.Structure):
+    _fields_ = [("l", ctypes.c_int32), ("src", ctypes.c_int32 * 4), ("dst", ctypes.c_int32 * 4)]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("t_min", ctypes.c_int64),
+                ("t_span", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+
+
+class EstInfo(ctypes.Structure):
+    _fields_ = [("shift", ctypes.c_int64), ("n_windows", ctypes.c_int64), ("n_kept", ctypes.c_int64),
+                ("kept_count", U128), ("cap", ctypes.c_int64), ("kept_ids", ctypes.c_void_p),
+                ("win_counts", ctypes.c_void_p), ("hist_lo", ctypes.c_void_p), ("hist_hi", ctypes.c_void_p)]
+
+
+P = ctypes.c_void_p
+i64, i32, u64, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+
+_SIGS = {
+    "tm_load_graph": [P, P, P, i64, i32, i32, P, P],
+    "tm_free_graph": [P],
+    "tm_graph_info_get": [P, P],
+    "tm_count_exact": [P, P, i64, P, P],
+    "tm_count_exact_i64": [P, P, i64, P, P],
+    "tm_count_exact_multi": [P, i32, P, i64, P, P, P, P],
+    "tm_count_anchors": [P, P, i64, i64, P, P, P, P],
+    "tm_estimate": [P, P, i64, i64, f64, u64, P, P, P],
+    "tm_estimate_multi": [P, i32, P, i64, i64, f64, u64, P, P, P],
+    "tm_estimate_batch": [P, P, i64, i64, f64, i32, P, i32, P, P, P],
+    "tm_strerror": [i32],
+    "tm_version": [],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int32
+_lib.tm_free_graph.restype = None
+_lib.tm_strerror.restype = ctypes.c_char_p
+_lib.tm_version.restype = ctypes.c_char_p
+
+EXPORTED = tuple(_SIGS)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise TMError(rc, what)
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return ctypes.c_void_p(0)
+
+
+def motif(edges) -> Motif:
+    edges = tuple(tuple(e) for e in edges)
+    if not 1 <= len(edges) <= 4:
+        raise TMError(2, f"motif with {len(edges)} edges")
+    m = Motif()
+    m.l = len(edges)
+    for i, (u, v) in enumerate(edges):
+        m.src[i] = u
+        m.dst[i] = v
+    return m
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class Graph:
+    """A device-resident temporal graph (freed with the object)."""
+
+    def __init__(self, src, dst, t, n_nodes: int, stream=None):
+        self._h = ctypes.c_void_p()
+        self._keep = None
+        on_device = 0
+        if hasattr(src, "is_cuda") and src.is_cuda:
+            import torch
+            for a, dt in ((src, torch.int32), (dst, torch.int32), (t, torch.int64)):
+                if a.dtype != dt or not a.is_contiguous():
+                    raise TMError(1, "device arrays must be contiguous int32/int32/int64")
+            ptrs = (src.data_ptr(), dst.data_ptr(), t.data_ptr())
+            m = int(src.numel())
+            on_device = 1
+        else:
+            s, d, tt = _np(src, np.int32), _np(dst, np.int32), _np(t, np.int64)
+            if not (s.shape == d.shape == tt.shape):
+                raise TMError(1, "src/dst/t lengths differ")
+            self._keep = (s, d, tt)
+            ptrs = (s.ctypes.data, d.ctypes.data, tt.ctypes.data)
+            m = int(s.shape[0])
+        _check(_lib.tm_load_graph(P(ptrs[0]), P(ptrs[1]), P(ptrs[2]), m, int(n_nodes), on_device,
+                                  _stream(stream), ctypes.byref(self._h)), "tm_load_graph")
+        self._keep = None
+        info = GraphInfo()
+        _check(_lib.tm_graph_info_get(self._h, ctypes.byref(info)), "tm_graph_info_get")
+        self.m, self.n, self.t_min, self.t_span = info.m, info.n, info.t_min, info.t_span
+        self.n_pairs, self.device_bytes = info.n_pairs, info.device_bytes
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h:
+            _lib.tm_free_graph(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def load_graph(src, dst, t, n_nodes, stream=None) -> Graph:
+    return Graph(src, dst, t, n_nodes, stream)
+
+
+def count_exact(g: Graph, edges, delta: int, stream=None) -> int:
+    out = U128()
+    _check(_lib.tm_count_exact(g.handle, ctypes.byref(motif(edges)), int(delta), ctypes.byref(out),
+                               _stream(stream)), "tm_count_exact")
+    return out.value()
+
+
+def count_exact_i64(g: Graph, edges, delta: int, stream=None) -> int:
+    out = ctypes.c_int64()
+    _check(_lib.tm_count_exact_i64(g.handle, ctypes.byref(motif(edges)), int(delta), ctypes.byref(out),
+                                   _stream(stream)), "tm_count_exact_i64")
+    return int(out.value)
+
+
+def count_exact_multi(g: Graph, motifs, delta: int, hist: bool = False, stream=None):
+    k = len(motifs)
+    arr = (Motif * max(k, 1))(*[motif(m) for m in motifs])
+    cnt = (U128 * max(k, 1))()
+    hlo = hhi = None
+    if hist:
+        hlo = np.zeros((k, delta + 1), dtype=np.uint64)
+        hhi = np.zeros((k, delta + 1), dtype=np.uint64)
+    _check(_lib.tm_count_exact_multi(g.handle, k, arr, int(delta), cnt,
+                                     P(hlo.ctypes.data) if hist else None,
+                                     P(hhi.ctypes.data) if hist else None, _stream(stream)),
+           "tm_count_exact_multi")
+    counts = [cnt[i].value() for i in range(k)]
+    if hist:
+        return counts, hlo, hhi
+    return counts
+
+
+def count_anchors(g: Graph, edges, delta: int, anchors, win_end=None, stream=None) -> np.ndarray:
+    a = _np(anchors, np.int64)
+    w = None if win_end is None else _np(win_end, np.int64)
+    out = np.zeros(a.shape[0], dtype=np.uint64)
+    _check(_lib.tm_count_anchors(g.handle, ctypes.byref(motif(edges)), int(delta), a.shape[0],
+                                 P(a.ctypes.data), P(w.ctypes.data) if w is not None else None,
+                                 P(out.ctypes.data), _stream(stream)), "tm_count_anchors")
+    return out
+
+
+def estimate(g: Graph, edges, delta: int, c: int, p: float, seed: int, info: bool = False,
+             cap: int = 1 << 16, stream=None):
+    z = ctypes.c_double()
+    if not info:
+        _check(_lib.tm_estimate(g.handle, ctypes.byref(motif(edges)), int(delta), int(c), float(p),
+                                int(seed), ctypes.byref(z), None, _stream(stream)), "tm_estimate")
+        return z.value
+    kept = np.zeros(cap, dtype=np.int64)
+    wc = np.zeros(cap, dtype=np.uint64)
+    hlo = np.zeros(delta + 1, dtype=np.uint64)
+    hhi = np.zeros(delta + 1, dtype=np.uint64)
+    ei = EstInfo()
+    ei.cap = cap
+    ei.kept_ids, ei.win_counts = kept.ctypes.data, wc.ctypes.data
+    ei.hist_lo, ei.hist_hi = hlo.ctypes.data, hhi.ctypes.data
+    _check(_lib.tm_estimate(g.handle, ctypes.byref(motif(edges)), int(delta), int(c), float(p), int(seed),
+                            ctypes.byref(z), ctypes.byref(ei), _stream(stream)), "tm_estimate")
+    n = max(0, min(ei.n_kept, cap))
+    return {"Z": z.value, "s": ei.shift, "J": ei.n_windows, "n_kept": ei.n_kept,
+            "kept_count": ei.kept_count.value(), "kept": kept[:n].copy(), "win_counts": wc[:n].copy(),
+            "hist_lo": hlo, "hist_hi": hhi}
+
+
+def estimate_multi(g: Graph, motifs, delta: int, c: int, p: float, seed: int, stream=None):
+    k = len(motifs)
+    arr = (Motif * max(k, 1))(*[motif(m) for m in motifs])
+    est = (ctypes.c_double * max(k, 1))()
+    kc = (U128 * max(k, 1))()
+    _check(_lib.tm_estimate_multi(g.handle, k, arr, int(delta), int(c), float(p), int(seed), est, kc,
+                                  _stream(stream)), "tm_estimate_multi")
+    return [est[i] for i in range(k)], [kc[i].value() for i in range(k)]
+
+
+def estimate_batch(g: Graph, edges, delta: int, c: int, p: float, seeds, tile: int = 0, stream=None):
+    s = _np(seeds, np.uint64)
+    k = s.shape[0]
+    est = np.zeros(k, dtype=np.float64)
+    kc = (U128 * max(k, 1))()
+    _check(_lib.tm_estimate_batch(g.handle, ctypes.byref(motif(edges)), int(delta), int(c), float(p), k,
+                                  P(s.ctypes.data), int(tile), P(est.ctypes.data), kc, _stream(stream)),
+           "tm_estimate_batch")
+    return est, [kc[i].value() for i in range(k)]
+
+
+def version() -> str:
+    return _lib.tm_version().decode()

@@ -1,0 +1,463 @@
+// C-ABI entry points for counting and estimation, the window partitioner
+// and the per-window Bernoulli sampler (Algorithm 1, Sec. 4).
+#include "tm_common.h"
+
+#include <limits.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+namespace {
+
+constexpr int TPB = 256;
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
+// multiplications by fixed odd constants, a mix of the high halves with the
+// other two counter words and the key, and a word permutation; the two key
+// words advance by the golden-ratio and sqrt(3)-1 Weyl increments after every
+// round but the last.
+__host__ __device__ inline void philox10(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3, uint32_t k0,
+                                         uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t a = (uint64_t)0xD2511F53u * x0;
+        uint64_t b = (uint64_t)0xCD9E8D57u * x2;
+        uint32_t y0 = (uint32_t)(b >> 32) ^ x1 ^ k0;
+        uint32_t y2 = (uint32_t)(a >> 32) ^ x3 ^ k1;
+        x1 = (uint32_t)b;
+        x3 = (uint32_t)a;
+        x0 = y0;
+        x2 = y2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// 64-bit draw for (seed, index j, estimator k, domain): counter words
+// (j low, j high, k, domain), key words (seed low, seed high); the draw is
+// word1 * 2^32 + word0.
+__host__ __device__ inline uint64_t tm_draw(uint64_t seed, uint64_t j, uint32_t k, uint32_t domain) {
+    uint32_t x0 = (uint32_t)j, x1 = (uint32_t)(j >> 32), x2 = k, x3 = domain;
+    philox10(x0, x1, x2, x3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return ((uint64_t)x1 << 32) | (uint64_t)x0;
+}
+
+// keep window j of estimator (seed) when (draw >> 11) * 2^-53 < p
+__device__ inline bool tm_keep(uint64_t seed, uint64_t j, double p) {
+    uint64_t x = tm_draw(seed, j, 0, 1);
+    double u = (double)(x >> 11) * (1.0 / 9007199254740992.0);
+    return u < p;
+}
+
+__global__ void k_shift(uint64_t seed, int64_t L, int64_t *s_out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        uint64_t x = tm_draw(seed, 0, 0, 0);
+        s_out[0] = -(int64_t)(x % (uint64_t)L);
+    }
+}
+
+// window of every sorted edge and whether it is kept
+__global__ void k_keep_flags(const int64_t *es_t, int64_t m, const int64_t *s_ptr, int64_t L, uint64_t seed, double p,
+                             int64_t *flag, int64_t *win) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    int64_t s = s_ptr[0];
+    int64_t j = (es_t[k] - s) / L + 1;
+    win[k] = j;
+    flag[k] = tm_keep(seed, (uint64_t)j, p) ? 1 : 0;
+}
+
+// kept anchors: flag[] holds 0/1 before the scan; scan[] the exclusive sums
+__global__ void k_compact(const int64_t *flag01, const int64_t *scan, const int64_t *win, int64_t m, int64_t *apos,
+                          int64_t *awin) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m || !flag01[k]) return;
+    int64_t i = scan[k];
+    apos[i] = k;
+    awin[i] = win[k];
+}
+
+__global__ void k_copy_i64(const int64_t *src, int64_t *dst, int64_t n) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = src[k];
+}
+
+__global__ void k_slot_flags(const int64_t *awin, const int64_t *nA, int64_t cap, int64_t *sflag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap) return;
+    int64_t n = nA[0];
+    sflag[i] = (i < n && (i == 0 || awin[i] != awin[i - 1])) ? 1 : 0;
+}
+
+__global__ void k_slot_fill(const int64_t *awin, const int64_t *nA, const int64_t *sflag01, const int64_t *sscan,
+                            const int64_t *s_ptr, int64_t L, int32_t *slot, int64_t *slot_win, int64_t *win_end) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nA[0]) return;
+    int64_t sl = sscan[i] + sflag01[i] - 1;
+    slot[i] = (int32_t)sl;
+    int64_t j = awin[i];
+    if (sflag01[i]) slot_win[sl] = j;
+    win_end[i] = s_ptr[0] + j * L - 1;
+}
+
+// kept windows among j = 1..J (diagnostics)
+__global__ void k_all_windows(uint64_t seed, int64_t J, double p, int64_t *flag) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (j > J) return;
+    flag[j - 1] = tm_keep(seed, (uint64_t)j, p) ? 1 : 0;
+}
+
+__global__ void k_list_windows(const int64_t *flag01, const int64_t *scan, int64_t J, int64_t cap, int64_t *ids) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (j > J || !flag01[j - 1]) return;
+    int64_t i = scan[j - 1];
+    if (i < cap) ids[i] = j;
+}
+
+__global__ void k_map_anchors(const int64_t *pos_of, const int64_t *anchor, int64_t n, int64_t m, int64_t *apos,
+                              int32_t *bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t a = anchor[i];
+    if (a < 0 || a >= m) {
+        atomicOr(bad, 1);
+        apos[i] = 0;
+    } else {
+        apos[i] = pos_of[a];
+    }
+}
+
+tm_status check_graph_motif(const tm_graph *g, const tm_motif *M, int64_t delta, MotifPlan *P) {
+    if (!g || !M || delta < 0) return TM_EINVAL;
+    return tm_make_plan(M, P);
+}
+
+// Anchors of the windows kept by one estimator, on the device.
+struct KeptAnchors {
+    DevBuf flag, scan, win, apos, awin, sflag, sscan, slot, slot_win, win_end, scal;
+    int64_t nA = 0, nslots = 0, s = 0;
+};
+
+tm_status select_kept(const tm_graph *g, int64_t L, uint64_t seed, double p, hipStream_t st, KeptAnchors &K) {
+    int64_t m = g->m;
+    TM_TRY(K.scal.alloc(64));
+    int64_t *s_dev = K.scal.as<int64_t>();
+    int64_t *nA_dev = s_dev + 1;
+    int64_t *ns_dev = s_dev + 2;
+    hipLaunchKernelGGL(k_shift, dim3(1), dim3(64), 0, st, seed, L, s_dev);
+    TM_HIP(hipGetLastError());
+    int64_t cap = m > 0 ? m : 1;
+    TM_TRY(K.flag.alloc((size_t)cap * 8));
+    TM_TRY(K.scan.alloc((size_t)cap * 8));
+    TM_TRY(K.win.alloc((size_t)cap * 8));
+    TM_HIP(hipMemsetAsync(nA_dev, 0, 16, st));
+    if (m > 0) {
+        hipLaunchKernelGGL(k_keep_flags, dim3(tm_blocks(m, TPB)), dim3(TPB), 0, st, g->es_t.as<int64_t>(), m, s_dev,
+                           L, seed, p, K.flag.as<int64_t>(), K.win.as<int64_t>());
+        TM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_copy_i64, dim3(tm_blocks(m, TPB)), dim3(TPB), 0, st, K.flag.as<int64_t>(),
+                           K.scan.as<int64_t>(), m);
+        TM_HIP(hipGetLastError());
+        TM_TRY(tm_scan_i64(K.scan.as<int64_t>(), m, nA_dev, st));
+    }
+    TM_HIP(hipMemcpyAsync(&K.nA, nA_dev, 8, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipMemcpyAsync(&K.s, s_dev, 8, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipStreamSynchronize(st));
+    int64_t nA = K.nA, ca = nA > 0 ? nA : 1;
+    TM_TRY(K.apos.alloc((size_t)ca * 8));
+    TM_TRY(K.awin.alloc((size_t)ca * 8));
+    TM_TRY(K.sflag.alloc((size_t)ca * 8));
+    TM_TRY(K.sscan.alloc((size_t)ca * 8));
+    TM_TRY(K.slot.alloc((size_t)ca * 4));
+    TM_TRY(K.slot_win.alloc((size_t)ca * 8));
+    TM_TRY(K.win_end.alloc((size_t)ca * 8));
+    if (nA > 0) {
+        hipLaunchKernelGGL(k_compact, dim3(tm_blocks(m, TPB)), dim3(TPB), 0, st, K.flag.as<int64_t>(),
+                           K.scan.as<int64_t>(), K.win.as<int64_t>(), m, K.apos.as<int64_t>(), K.awin.as<int64_t>());
+        TM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_slot_flags, dim3(tm_blocks(nA, TPB)), dim3(TPB), 0, st, K.awin.as<int64_t>(), nA_dev, nA,
+                           K.sflag.as<int64_t>());
+        TM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_copy_i64, dim3(tm_blocks(nA, TPB)), dim3(TPB), 0, st, K.sflag.as<int64_t>(),
+                           K.sscan.as<int64_t>(), nA);
+        TM_HIP(hipGetLastError());
+        TM_TRY(tm_scan_i64(K.sscan.as<int64_t>(), nA, ns_dev, st));
+        hipLaunchKernelGGL(k_slot_fill, dim3(tm_blocks(nA, TPB)), dim3(TPB), 0, st, K.awin.as<int64_t>(), nA_dev,
+                           K.sflag.as<int64_t>(), K.sscan.as<int64_t>(), s_dev, L, K.slot.as<int32_t>(),
+                           K.slot_win.as<int64_t>(), K.win_end.as<int64_t>());
+        TM_HIP(hipGetLastError());
+        TM_HIP(hipMemcpyAsync(&K.nslots, ns_dev, 8, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+    }
+    return TM_OK;
+}
+
+tm_status check_est_args(const tm_graph *g, int64_t delta, int64_t c, double p, int64_t *L) {
+    if (!g || delta < 1 || c < 2 || !(p > 0.0 && p <= 1.0)) return TM_EINVAL;
+    if (delta > INT64_MAX / c) return TM_EINVAL;
+    *L = c * delta;
+    // window ends s + j L - 1 stay below 2^63 for every window of the graph
+    if (*L > INT64_MAX / 4 || g->t_span > INT64_MAX - 2 * *L) return TM_EINVAL;
+    // the duration histogram has delta + 1 bins
+    if (delta > TM_MAX_HIST_DELTA) return TM_EUNSUPPORTED;
+    return TM_OK;
+}
+
+tm_status fill_info(const tm_graph *g, int64_t L, uint64_t seed, double p, const KeptAnchors &K,
+                    const std::vector<uint64_t> &slot_tot, const uint64_t *hist_dev_lo, const uint64_t *hist_dev_hi,
+                    int64_t delta, const uint64_t total[2], tm_est_info *info, hipStream_t st) {
+    int64_t J = 1 + g->t_span / L + ((g->t_span % L) ? 1 : 0);
+    info->shift = K.s;
+    info->n_windows = J;
+    info->kept_count.lo = total[0];
+    info->kept_count.hi = total[1];
+    if (J <= ((int64_t)1 << 24)) {
+        DevBuf f, sc, ids, tot;
+        TM_TRY(f.alloc((size_t)J * 8));
+        TM_TRY(sc.alloc((size_t)J * 8));
+        TM_TRY(tot.alloc(8));
+        int64_t cap = info->cap > 0 ? info->cap : 0;
+        TM_TRY(ids.alloc((size_t)(cap > 0 ? cap : 1) * 8));
+        hipLaunchKernelGGL(k_all_windows, dim3(tm_blocks(J, TPB)), dim3(TPB), 0, st, seed, J, p, f.as<int64_t>());
+        TM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_copy_i64, dim3(tm_blocks(J, TPB)), dim3(TPB), 0, st, f.as<int64_t>(), sc.as<int64_t>(), J);
+        TM_HIP(hipGetLastError());
+        TM_TRY(tm_scan_i64(sc.as<int64_t>(), J, tot.as<int64_t>(), st));
+        hipLaunchKernelGGL(k_list_windows, dim3(tm_blocks(J, TPB)), dim3(TPB), 0, st, f.as<int64_t>(),
+                           sc.as<int64_t>(), J, cap, ids.as<int64_t>());
+        TM_HIP(hipGetLastError());
+        int64_t nk = 0;
+        TM_HIP(hipMemcpyAsync(&nk, tot.p, 8, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+        info->n_kept = nk;
+        int64_t nw = std::min(nk, cap);
+        std::vector<int64_t> hids((size_t)(nw > 0 ? nw : 1));
+        if (nw > 0) {
+            TM_HIP(hipMemcpyAsync(hids.data(), ids.p, (size_t)nw * 8, hipMemcpyDeviceToHost, st));
+        }
+        std::vector<int64_t> swin((size_t)(K.nslots > 0 ? K.nslots : 1));
+        if (K.nslots > 0) {
+            TM_HIP(hipMemcpyAsync(swin.data(), K.slot_win.p, (size_t)K.nslots * 8, hipMemcpyDeviceToHost, st));
+        }
+        TM_HIP(hipStreamSynchronize(st));
+        int64_t q = 0;
+        for (int64_t i = 0; i < nw; ++i) {
+            if (info->kept_ids) info->kept_ids[i] = hids[(size_t)i];
+            uint64_t c = 0;
+            while (q < K.nslots && swin[(size_t)q] < hids[(size_t)i]) ++q;
+            if (q < K.nslots && swin[(size_t)q] == hids[(size_t)i]) c = slot_tot[(size_t)(2 * q)];
+            if (info->win_counts) info->win_counts[i] = c;
+        }
+    } else {
+        info->n_kept = -1;
+    }
+    if (info->hist_lo) {
+        TM_HIP(hipMemcpyAsync(info->hist_lo, hist_dev_lo, (size_t)(delta + 1) * 8, hipMemcpyDeviceToHost, st));
+    }
+    if (info->hist_hi) {
+        TM_HIP(hipMemcpyAsync(info->hist_hi, hist_dev_hi, (size_t)(delta + 1) * 8, hipMemcpyDeviceToHost, st));
+    }
+    TM_HIP(hipStreamSynchronize(st));
+    return TM_OK;
+}
+
+tm_status estimate_impl(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t c, double p, uint64_t seed,
+                        double *estimate, tm_est_info *info, hipStream_t st) {
+    MotifPlan P;
+    TM_TRY(check_graph_motif(g, M, delta, &P));
+    int64_t L;
+    TM_TRY(check_est_args(g, delta, c, p, &L));
+    if (!estimate) return TM_EINVAL;
+    KeptAnchors K;
+    TM_TRY(select_kept(g, L, seed, p, st, K));
+    DevBuf hist, acc;
+    TM_TRY(hist.alloc((size_t)(delta + 1) * 16));
+    int64_t ns = K.nslots;
+    TM_TRY(acc.alloc((size_t)(2 + 2 * (ns > 0 ? ns : 1)) * 8 + 64));
+    TM_HIP(hipMemsetAsync(hist.p, 0, (size_t)(delta + 1) * 16, st));
+    TM_HIP(hipMemsetAsync(acc.p, 0, acc.bytes, st));
+    uint64_t *hlo = hist.as<uint64_t>(), *hhi = hlo + (delta + 1);
+    uint64_t *total = acc.as<uint64_t>();
+    uint64_t *slot_tot = total + 2;
+    double *z_dev = (double *)(slot_tot + 2 * (ns > 0 ? ns : 1));
+    if (K.nA > 0) {
+        AnchorSet A{K.nA, K.apos.as<int64_t>(), K.win_end.as<int64_t>(), K.slot.as<int32_t>(), nullptr};
+        TM_TRY(tm_count_generic(g, P, delta, A, total, slot_tot, hlo, hhi, nullptr, nullptr, st));
+    }
+    TM_TRY(tm_weight(hlo, hhi, delta, L, p, z_dev, st));
+    double z = 0;
+    uint64_t tot[2];
+    std::vector<uint64_t> stot((size_t)(2 * (ns > 0 ? ns : 1)));
+    TM_HIP(hipMemcpyAsync(&z, z_dev, 8, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipMemcpyAsync(tot, total, 16, hipMemcpyDeviceToHost, st));
+    if (ns > 0) TM_HIP(hipMemcpyAsync(stot.data(), slot_tot, (size_t)ns * 16, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipStreamSynchronize(st));
+    if (info) TM_TRY(fill_info(g, L, seed, p, K, stot, hlo, hhi, delta, tot, info, st));
+    *estimate = z;
+    return TM_OK;
+}
+
+tm_status count_exact_impl(const tm_graph *g, const tm_motif *M, int64_t delta, uint64_t *hist_lo_host,
+                           uint64_t *hist_hi_host, tm_u128 *out, hipStream_t st) {
+    MotifPlan P;
+    TM_TRY(check_graph_motif(g, M, delta, &P));
+    DevBuf acc, hist;
+    TM_TRY(acc.alloc(64));
+    TM_HIP(hipMemsetAsync(acc.p, 0, 64, st));
+    uint64_t *hlo = nullptr, *hhi = nullptr;
+    if (hist_lo_host) {
+        if (delta > TM_MAX_HIST_DELTA) return TM_EUNSUPPORTED;
+        TM_TRY(hist.alloc((size_t)(delta + 1) * 16));
+        TM_HIP(hipMemsetAsync(hist.p, 0, hist.bytes, st));
+        hlo = hist.as<uint64_t>();
+        hhi = hlo + (delta + 1);
+    }
+    if (g->m > 0) {
+        AnchorSet A{g->m, nullptr, nullptr, nullptr, nullptr};
+        TM_TRY(tm_count_generic(g, P, delta, A, acc.as<uint64_t>(), nullptr, hlo, hhi, nullptr, nullptr, st));
+    }
+    uint64_t tot[2];
+    TM_HIP(hipMemcpyAsync(tot, acc.p, 16, hipMemcpyDeviceToHost, st));
+    if (hlo) {
+        TM_HIP(hipMemcpyAsync(hist_lo_host, hlo, (size_t)(delta + 1) * 8, hipMemcpyDeviceToHost, st));
+        if (hist_hi_host) TM_HIP(hipMemcpyAsync(hist_hi_host, hhi, (size_t)(delta + 1) * 8, hipMemcpyDeviceToHost, st));
+    }
+    TM_HIP(hipStreamSynchronize(st));
+    out->lo = tot[0];
+    out->hi = tot[1];
+    return TM_OK;
+}
+
+tm_status finish(tm_status s, hipStream_t st) {
+    if (s != TM_OK) {
+        (void)hipStreamSynchronize(st);
+        (void)hipGetLastError();
+    }
+    return s;
+}
+
+}  // namespace
+
+extern "C" tm_status tm_count_exact(const tm_graph *g, const tm_motif *M, int64_t delta, tm_u128 *count,
+                                    void *hip_stream) {
+    if (!count) return TM_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    return finish(count_exact_impl(g, M, delta, nullptr, nullptr, count, st), st);
+}
+
+extern "C" tm_status tm_count_exact_i64(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t *count,
+                                        void *hip_stream) {
+    if (!count) return TM_EINVAL;
+    tm_u128 c;
+    tm_status s = tm_count_exact(g, M, delta, &c, hip_stream);
+    if (s != TM_OK) return s;
+    if (c.hi || c.lo > (uint64_t)INT64_MAX) return TM_EOVERFLOW;
+    *count = (int64_t)c.lo;
+    return TM_OK;
+}
+
+extern "C" tm_status tm_count_exact_multi(const tm_graph *g, int32_t n_motifs, const tm_motif *motifs, int64_t delta,
+                                          tm_u128 *counts, uint64_t *hist_lo, uint64_t *hist_hi, void *hip_stream) {
+    if (!g || n_motifs < 0 || (n_motifs > 0 && (!motifs || !counts)) || delta < 0) return TM_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    MotifPlan P;
+    for (int32_t i = 0; i < n_motifs; ++i) TM_TRY(tm_make_plan(&motifs[i], &P));
+    for (int32_t i = 0; i < n_motifs; ++i) {
+        uint64_t *hl = hist_lo ? hist_lo + (int64_t)i * (delta + 1) : nullptr;
+        uint64_t *hh = hist_hi ? hist_hi + (int64_t)i * (delta + 1) : nullptr;
+        tm_status s = finish(count_exact_impl(g, &motifs[i], delta, hl, hh, &counts[i], st), st);
+        if (s != TM_OK) return s;
+    }
+    return TM_OK;
+}
+
+extern "C" tm_status tm_count_anchors(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t n_anchor,
+                                      const int64_t *anchor, const int64_t *win_end, uint64_t *out, void *hip_stream) {
+    if (!g || n_anchor < 0 || (n_anchor > 0 && (!anchor || !out)) || delta < 0) return TM_EINVAL;
+    MotifPlan P;
+    TM_TRY(tm_make_plan(M, &P));
+    if (n_anchor == 0) return TM_OK;
+    hipStream_t st = (hipStream_t)hip_stream;
+    auto run = [&]() -> tm_status {
+        DevBuf a, ap, we, o, fl;
+        TM_TRY(a.alloc((size_t)n_anchor * 8));
+        TM_TRY(ap.alloc((size_t)n_anchor * 8));
+        TM_TRY(o.alloc((size_t)n_anchor * 8));
+        TM_TRY(fl.alloc(64));
+        TM_HIP(hipMemsetAsync(fl.p, 0, 64, st));
+        TM_HIP(hipMemcpyAsync(a.p, anchor, (size_t)n_anchor * 8, hipMemcpyHostToDevice, st));
+        if (win_end) {
+            TM_TRY(we.alloc((size_t)n_anchor * 8));
+            TM_HIP(hipMemcpyAsync(we.p, win_end, (size_t)n_anchor * 8, hipMemcpyHostToDevice, st));
+        }
+        hipLaunchKernelGGL(k_map_anchors, dim3(tm_blocks(n_anchor, TPB)), dim3(TPB), 0, st, g->pos_of.as<int64_t>(),
+                           a.as<int64_t>(), n_anchor, g->m, ap.as<int64_t>(), fl.as<int32_t>() + 1);
+        TM_HIP(hipGetLastError());
+        int32_t bad[2] = {0, 0};
+        TM_HIP(hipMemcpyAsync(bad, fl.p, 8, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+        if (bad[1]) return TM_EINVAL;
+        AnchorSet A{n_anchor, ap.as<int64_t>(), win_end ? we.as<int64_t>() : nullptr, nullptr, nullptr};
+        TM_TRY(tm_count_generic(g, P, delta, A, nullptr, nullptr, nullptr, nullptr, o.as<uint64_t>(), fl.as<int32_t>(),
+                                st));
+        TM_HIP(hipMemcpyAsync(out, o.p, (size_t)n_anchor * 8, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipMemcpyAsync(bad, fl.p, 8, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+        return bad[0] ? TM_EOVERFLOW : TM_OK;
+    };
+    return finish(run(), st);
+}
+
+extern "C" tm_status tm_estimate(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t c, double p,
+                                 uint64_t seed, double *estimate, tm_est_info *info, void *hip_stream) {
+    hipStream_t st = (hipStream_t)hip_stream;
+    return finish(estimate_impl(g, M, delta, c, p, seed, estimate, info, st), st);
+}
+
+extern "C" tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, const tm_motif *motifs, int64_t delta,
+                                       int64_t c, double p, uint64_t seed, double *estimates, tm_u128 *kept_counts,
+                                       void *hip_stream) {
+    if (!g || n_motifs < 0 || (n_motifs > 0 && (!motifs || !estimates))) return TM_EINVAL;
+    MotifPlan P;
+    for (int32_t i = 0; i < n_motifs; ++i) TM_TRY(tm_make_plan(&motifs[i], &P));
+    for (int32_t i = 0; i < n_motifs; ++i) {
+        tm_est_info info;
+        memset(&info, 0, sizeof info);
+        TM_TRY(tm_estimate(g, &motifs[i], delta, c, p, seed, &estimates[i], kept_counts ? &info : nullptr,
+                           hip_stream));
+        if (kept_counts) kept_counts[i] = info.kept_count;
+    }
+    return TM_OK;
+}
+
+extern "C" tm_status tm_estimate_batch(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t c, double p,
+                                       int32_t n_seeds, const uint64_t *seeds, int32_t tile, double *estimates,
+                                       tm_u128 *kept_counts, void *hip_stream) {
+    (void)tile;
+    if (!g || n_seeds < 0 || (n_seeds > 0 && (!seeds || !estimates))) return TM_EINVAL;
+    for (int32_t i = 0; i < n_seeds; ++i) {
+        tm_est_info info;
+        memset(&info, 0, sizeof info);
+        TM_TRY(tm_estimate(g, M, delta, c, p, seeds[i], &estimates[i], kept_counts ? &info : nullptr, hip_stream));
+        if (kept_counts) kept_counts[i] = info.kept_count;
+    }
+    return TM_OK;
+}
+
+extern "C" const char *tm_strerror(tm_status s) {
+    switch (s) {
+        case TM_OK: return "ok";
+        case TM_EINVAL: return "invalid argument";
+        case TM_EUNSUPPORTED: return "unsupported motif";
+        case TM_ENOMEM: return "out of memory";
+        case TM_EBUDGET: return "over memory budget";
+        case TM_EOVERFLOW: return "count overflows the requested width";
+        case TM_EDEVICE: return "HIP device error";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *tm_version(void) { return "tm 0.1 gfx950"; }

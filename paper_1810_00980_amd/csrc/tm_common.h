@@ -1,0 +1,195 @@
+// Internal declarations shared by the HIP sources of libtm (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <vector>
+
+#include "tm.h"
+
+#define TM_WAVE 64
+
+// Largest delta for which a duration histogram (delta + 1 bins) is built.
+#define TM_MAX_HIST_DELTA ((int64_t)1 << 26)
+
+// Host-side status propagation.
+#define TM_TRY(expr)                          \
+    do {                                      \
+        tm_status _s = (expr);                \
+        if (_s != TM_OK) return _s;           \
+    } while (0)
+
+static inline tm_status tm_hip_status(hipError_t e) {
+    if (e == hipSuccess) return TM_OK;
+    if (e == hipErrorOutOfMemory) return TM_ENOMEM;
+    return TM_EDEVICE;
+}
+
+#define TM_HIP(expr) TM_TRY(tm_hip_status(expr))
+
+// Owned device allocation (freed on destruction).
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    tm_status alloc(size_t nbytes) {
+        release();
+        if (nbytes == 0) nbytes = 256;
+        hipError_t e = hipMalloc(&p, nbytes);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return e == hipErrorOutOfMemory ? TM_ENOMEM : TM_EDEVICE;
+        }
+        bytes = nbytes;
+        return TM_OK;
+    }
+    // grow-only reuse
+    tm_status reserve(size_t nbytes) {
+        if (p && bytes >= nbytes) return TM_OK;
+        return alloc(nbytes);
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Device-resident, immutable temporal graph.
+//
+// Times are normalised (t' = t - t_min, the origin of Algorithm 1) and kept
+// as int64.  Self-loop edges stay in the time-sorted edge array (they are
+// edges of the graph and count towards window sizes) but are left out of
+// every incidence list, since no motif edge can map onto them.
+struct tm_graph {
+    int device = 0;
+    int64_t m = 0, n = 0;
+    int64_t t_min = 0, t_span = 0;
+    int64_t m_nl = 0;   // edges that are not self-loops
+    int64_t S = 0;      // distinct directed pairs (u != v)
+
+    // time-sorted edges (ties in input order)
+    DevBuf es_src, es_dst, es_t;   // int32, int32, int64 [m]
+    DevBuf pos_of;                 // int64 [m]: input index -> sorted position
+
+    // per-node time-sorted out- and in-lists (non-self-loop edges)
+    DevBuf out_off, out_nbr, out_t;  // int64[n+1], int32[m_nl], int64[m_nl]
+    DevBuf in_off, in_nbr, in_t;
+
+    // directed pairs: entries sorted by (src, dst, t)
+    DevBuf sp_off;   // int64[n+1]: first pair of each source node
+    DevBuf sp_nbr;   // int32[S]: destination of each pair
+    DevBuf sp_beg;   // int64[S+1]: first entry of each pair in pr_t
+    DevBuf pr_t;     // int64[m_nl]
+
+    // combined incidence lists: every non-self-loop edge appears in the list
+    // of its source (direction bit 0) and of its destination (bit 1), times
+    // ascending within a list
+    DevBuf inc_off;  // int64[n+1]
+    DevBuf inc_nd;   // uint32[2 m_nl]: other endpoint | (dir << 31)
+    DevBuf inc_t;    // int64[2 m_nl]
+
+    // reusable per-graph workspace for queries
+    DevBuf ws;
+    int64_t device_bytes = 0;
+};
+
+// Plain-pointer view of a graph for kernels.
+struct DevGraph {
+    int64_t m, n, m_nl, S;
+    const int32_t *es_src, *es_dst;
+    const int64_t *es_t;
+    const int64_t *out_off; const int32_t *out_nbr; const int64_t *out_t;
+    const int64_t *in_off; const int32_t *in_nbr; const int64_t *in_t;
+    const int64_t *sp_off; const int32_t *sp_nbr; const int64_t *sp_beg; const int64_t *pr_t;
+    const int64_t *inc_off; const uint32_t *inc_nd; const int64_t *inc_t;
+};
+
+DevGraph dev_view(const tm_graph *g);
+
+// ------------------------------------------------------------ primitives
+
+// Exclusive prefix sum of n int64 values, in place; *total (nullable, device)
+// receives the sum.  Uses tmp workspace it allocates itself.
+tm_status tm_scan_i64(int64_t *d, int64_t n, int64_t *d_total, hipStream_t st);
+
+// Stable LSD radix sort of (key, val) pairs by the low `bits` bits of key.
+// keys/vals are sorted in place (ping-pong buffers allocated internally).
+tm_status tm_radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st);
+
+// Number of significant bits of x (0 for x == 0).
+static inline int tm_bitlen(uint64_t x) {
+    int b = 0;
+    while (x) { ++b; x >>= 1; }
+    return b;
+}
+
+static inline unsigned tm_blocks(int64_t n, int per_block) {
+    int64_t b = (n + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+// ------------------------------------------------------------ 128-bit atomics
+
+__device__ inline void tm_atomic_add_u128(uint64_t *lo, uint64_t *hi, uint64_t vlo, uint64_t vhi) {
+    if (vlo) {
+        unsigned long long old = atomicAdd((unsigned long long *)lo, (unsigned long long)vlo);
+        if (old + vlo < old) vhi += 1;
+    }
+    if (vhi) atomicAdd((unsigned long long *)hi, (unsigned long long)vhi);
+}
+
+// 128-bit add of (blo, bhi) into (alo, ahi)
+__device__ __host__ inline void tm_add_u128(uint64_t &alo, uint64_t &ahi, uint64_t blo, uint64_t bhi) {
+    uint64_t s = alo + blo;
+    ahi += bhi + (s < alo ? 1 : 0);
+    alo = s;
+}
+
+// ------------------------------------------------------------ motif plans
+
+// Level r >= 1 of a motif scans one list, chosen by which endpoints of motif
+// edge r were bound by edges 0..r-1.
+enum : int32_t { LV_PAIR = 0, LV_OUT = 1, LV_IN = 2 };
+
+struct MotifPlan {
+    int32_t l, k;
+    int32_t kind[4];
+    int32_t u[4], v[4];
+};
+
+// Validates a motif (canonical labels, no self-loop, prefix-connected, l<=4)
+// and builds its plan.
+tm_status tm_make_plan(const tm_motif *M, MotifPlan *P);
+
+// ------------------------------------------------------------ anchors
+
+// Anchor description for the counters: either every sorted edge (exact) or a
+// compacted list of sorted positions (kept windows) with a window end time.
+struct AnchorSet {
+    int64_t n;              // number of anchors (host-known upper bound if dev_n)
+    const int64_t *pos;     // sorted positions, or nullptr for 0..n-1
+    const int64_t *win_end; // per anchor window end (nullable: +inf)
+    const int32_t *slot;    // per anchor output slot (nullable)
+    const int64_t *dev_n;   // device-side anchor count (nullable)
+};
+
+// Generic counter (any supported motif).  Adds into total (2 x u64),
+// per-slot totals (2 x u64 per slot, nullable), histogram (delta+1 bins,
+// lo/hi, nullable), per-anchor outputs (u64, nullable, +overflow flag).
+tm_status tm_count_generic(const tm_graph *g, const MotifPlan &P, int64_t delta, const AnchorSet &A,
+                           uint64_t *total, uint64_t *slot_tot, uint64_t *hist_lo,
+                           uint64_t *hist_hi, uint64_t *per_anchor, int32_t *flag,
+                           hipStream_t st);
+
+// FP64 weighting of a duration histogram (single work-item, ascending order,
+// Neumaier compensation): out[0] = (1/p) sum N(d) L/(L-d).
+tm_status tm_weight(const uint64_t *hist_lo, const uint64_t *hist_hi, int64_t delta, int64_t L,
+                    double p, double *out, hipStream_t st);

@@ -1,0 +1,315 @@
+// Generic per-window exact counter: one anchor edge (the motif's first
+// edge) per lane, backtracking over time-bounded incidence lists.
+//
+// For an anchor e1 = (a, b, t1) in a window ending at time W, every later
+// motif edge r must have a time in (t_{r-1}, min(t1 + delta, W)] (strictly
+// increasing times, inclusive span bound; Sec. 2 instance and duration
+// definitions, and the window sub-graph T_j of Algorithm 1).  Level r scans
+//   - the (x -> y) pair list when both endpoints of motif edge r are bound,
+//   - the out-list of the bound source, or the in-list of the bound
+//     destination, keeping entries whose other endpoint is not already the
+//     image of a motif node (the node map is a bijection),
+// with the start found by binary search on time.  The last level is not
+// enumerated for totals: a pair list contributes its range length and a node
+// list the number of admissible entries.  With a duration histogram the last
+// level is enumerated and each instance adds one to bin t_l - t_1.
+#include "tm_common.h"
+
+#include <limits.h>
+
+namespace {
+
+constexpr int CG_TPB = 256;
+
+struct Binding {
+    int32_t f0, f1, f2, f3, f4;
+    __device__ int32_t get(int i) const {
+        return i == 0 ? f0 : i == 1 ? f1 : i == 2 ? f2 : i == 3 ? f3 : f4;
+    }
+    __device__ void set(int i, int32_t w) {
+        f0 = (i == 0) ? w : f0;
+        f1 = (i == 1) ? w : f1;
+        f2 = (i == 2) ? w : f2;
+        f3 = (i == 3) ? w : f3;
+        f4 = (i == 4) ? w : f4;
+    }
+    __device__ bool used(int32_t w) const { return w == f0 || w == f1 || w == f2 || w == f3 || w == f4; }
+};
+
+// first index in [lo, hi) with t[i] > x
+__device__ inline int64_t ub_time(const int64_t *t, int64_t lo, int64_t hi, int64_t x) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (t[mid] <= x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// entries of pair (x -> y): [*b, *e) in pr_t
+__device__ inline void pair_range(const DevGraph &G, int32_t x, int32_t y, int64_t *b, int64_t *e) {
+    int64_t lo = G.sp_off[x], hi = G.sp_off[x + 1];
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (G.sp_nbr[mid] < y) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < G.sp_off[x + 1] && G.sp_nbr[lo] == y) {
+        *b = G.sp_beg[lo];
+        *e = G.sp_beg[lo + 1];
+    } else {
+        *b = 0;
+        *e = 0;
+    }
+}
+
+struct Range {
+    const int32_t *nbr;  // nullptr for pair lists
+    const int64_t *t;
+    int64_t cur, end;
+    int32_t newnode;     // motif node bound by an entry (-1 for pair lists)
+};
+
+__device__ inline Range open_level(const DevGraph &G, const MotifPlan &P, int r, const Binding &f, int64_t tprev,
+                                   int64_t hi) {
+    Range R;
+    int kind = P.kind[r];
+    int64_t lo, up;
+    if (kind == LV_PAIR) {
+        pair_range(G, f.get(P.u[r]), f.get(P.v[r]), &lo, &up);
+        R.nbr = nullptr;
+        R.t = G.pr_t;
+        R.newnode = -1;
+    } else if (kind == LV_OUT) {
+        int32_t x = f.get(P.u[r]);
+        lo = G.out_off[x];
+        up = G.out_off[x + 1];
+        R.nbr = G.out_nbr;
+        R.t = G.out_t;
+        R.newnode = P.v[r];
+    } else {
+        int32_t x = f.get(P.v[r]);
+        lo = G.in_off[x];
+        up = G.in_off[x + 1];
+        R.nbr = G.in_nbr;
+        R.t = G.in_t;
+        R.newnode = P.u[r];
+    }
+    R.cur = ub_time(R.t, lo, up, tprev);
+    R.end = ub_time(R.t, R.cur, up, hi);
+    return R;
+}
+
+struct Acc {
+    uint64_t lo, hi;
+    __device__ void add(uint64_t v) {
+        uint64_t s = lo + v;
+        hi += (s < lo) ? 1 : 0;
+        lo = s;
+    }
+};
+
+template <bool HIST>
+__device__ inline void count_last(const Range &R, const Binding &f, int64_t t1, Acc &acc, uint64_t *hlo,
+                                  uint64_t *hhi) {
+    if (R.nbr == nullptr) {
+        if (!HIST) {
+            acc.add((uint64_t)(R.end - R.cur));
+        } else {
+            for (int64_t i = R.cur; i < R.end; ++i) {
+                int64_t d = R.t[i] - t1;
+                tm_atomic_add_u128(hlo + d, hhi + d, 1, 0);
+            }
+            acc.add((uint64_t)(R.end - R.cur));
+        }
+        return;
+    }
+    uint64_t c = 0;
+    for (int64_t i = R.cur; i < R.end; ++i) {
+        if (!f.used(R.nbr[i])) {
+            ++c;
+            if (HIST) {
+                int64_t d = R.t[i] - t1;
+                tm_atomic_add_u128(hlo + d, hhi + d, 1, 0);
+            }
+        }
+    }
+    acc.add(c);
+}
+
+// Levels R .. LEN-1 below the current binding.
+template <int R, int LEN, bool HIST>
+__device__ inline void levels(const DevGraph &G, const MotifPlan &P, Binding &f, int64_t tprev, int64_t t1,
+                              int64_t hi, Acc &acc, uint64_t *hlo, uint64_t *hhi) {
+    Range rg = open_level(G, P, R, f, tprev, hi);
+    if constexpr (R == LEN - 1) {
+        count_last<HIST>(rg, f, t1, acc, hlo, hhi);
+    } else {
+        for (int64_t i = rg.cur; i < rg.end; ++i) {
+            int64_t ti = rg.t[i];
+            if (rg.nbr == nullptr) {
+                levels<R + 1, LEN, HIST>(G, P, f, ti, t1, hi, acc, hlo, hhi);
+            } else {
+                int32_t w = rg.nbr[i];
+                if (f.used(w)) continue;
+                f.set(rg.newnode, w);
+                levels<R + 1, LEN, HIST>(G, P, f, ti, t1, hi, acc, hlo, hhi);
+                f.set(rg.newnode, -1);
+            }
+        }
+    }
+}
+
+template <int LEN, bool HIST>
+__device__ inline void count_anchor(const DevGraph &G, const MotifPlan &P, int64_t pos, int64_t win_end,
+                                    int64_t delta, Acc &acc, uint64_t *hlo, uint64_t *hhi) {
+    int32_t a = G.es_src[pos], b = G.es_dst[pos];
+    if (a == b) return;
+    int64_t t1 = G.es_t[pos];
+    int64_t hi = (t1 > LLONG_MAX - delta) ? LLONG_MAX : t1 + delta;
+    hi = hi < win_end ? hi : win_end;
+    if constexpr (LEN == 1) {
+        acc.add(1);
+        if (HIST) tm_atomic_add_u128(hlo, hhi, 1, 0);
+    } else {
+        Binding f{-1, -1, -1, -1, -1};
+        f.set(0, a);
+        f.set(1, b);
+        levels<1, LEN, HIST>(G, P, f, t1, t1, hi, acc, hlo, hhi);
+    }
+}
+
+__device__ inline void wave_reduce_u128(uint64_t &lo, uint64_t &hi) {
+#pragma unroll
+    for (int o = TM_WAVE / 2; o > 0; o >>= 1) {
+        uint64_t olo = __shfl_xor(lo, o, TM_WAVE);
+        uint64_t ohi = __shfl_xor(hi, o, TM_WAVE);
+        tm_add_u128(lo, hi, olo, ohi);
+    }
+}
+
+template <int LEN, bool HIST>
+__global__ void __launch_bounds__(CG_TPB) k_count_generic(DevGraph G, MotifPlan P, int64_t delta, AnchorSet A,
+                                                         uint64_t *total, uint64_t *slot_tot, uint64_t *hlo,
+                                                         uint64_t *hhi, uint64_t *per_anchor, int32_t *flag) {
+    int64_t nA = A.dev_n ? *A.dev_n : A.n;
+    uint64_t lo = 0, hi = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nA; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t pos = A.pos ? A.pos[i] : i;
+        int64_t we = A.win_end ? A.win_end[i] : LLONG_MAX;
+        Acc acc{0, 0};
+        count_anchor<LEN, HIST>(G, P, pos, we, delta, acc, hlo, hhi);
+        tm_add_u128(lo, hi, acc.lo, acc.hi);
+        if (per_anchor) {
+            per_anchor[i] = acc.lo;
+            if (acc.hi) atomicOr(flag, 1);
+        }
+        if (slot_tot && (acc.lo | acc.hi)) {
+            int32_t s = A.slot[i];
+            tm_atomic_add_u128(slot_tot + 2 * (int64_t)s, slot_tot + 2 * (int64_t)s + 1, acc.lo, acc.hi);
+        }
+    }
+    wave_reduce_u128(lo, hi);
+    if ((threadIdx.x & (TM_WAVE - 1)) == 0 && total) tm_atomic_add_u128(total, total + 1, lo, hi);
+}
+
+template <int LEN, bool HIST>
+tm_status launch_len(const DevGraph &G, const MotifPlan &P, int64_t delta, const AnchorSet &A, uint64_t *total,
+                     uint64_t *slot_tot, uint64_t *hlo, uint64_t *hhi, uint64_t *per_anchor, int32_t *flag,
+                     hipStream_t st) {
+    int64_t n = A.n;
+    if (n <= 0) return TM_OK;
+    unsigned nb = tm_blocks(n, CG_TPB);
+    if (nb > 65535u * 4) nb = 65535u * 4;
+    hipLaunchKernelGGL((k_count_generic<LEN, HIST>), dim3(nb), dim3(CG_TPB), 0, st, G, P, delta, A, total,
+                       slot_tot, hlo, hhi, per_anchor, flag);
+    return tm_hip_status(hipGetLastError());
+}
+
+__global__ void k_weight(const uint64_t *hlo, const uint64_t *hhi, int64_t delta, int64_t L, double p, double *out) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double sum = 0.0, comp = 0.0;
+    for (int64_t d = 0; d <= delta; ++d) {
+        uint64_t lo = hlo[d], hi = hhi ? hhi[d] : 0;
+        if (lo == 0 && hi == 0) continue;
+        double w = (double)L / (double)(L - d);
+        double xh = (double)hi;
+        double x = xh * 18446744073709551616.0;
+        x = x + (double)lo;
+        x = x * w;
+        double s2 = sum + x;
+        if (fabs(sum) >= fabs(x)) comp += (sum - s2) + x;
+        else comp += (x - s2) + sum;
+        sum = s2;
+    }
+    out[0] = (sum + comp) / p;
+}
+
+}  // namespace
+
+tm_status tm_make_plan(const tm_motif *M, MotifPlan *P) {
+    if (!M || !P) return TM_EINVAL;
+    int l = M->l;
+    if (l < 1) return TM_EINVAL;
+    if (l > 4) return TM_EUNSUPPORTED;
+    // canonical labels: first appearance order, starting with edge 0 = (0, 1)
+    int next = 0;
+    for (int i = 0; i < l; ++i) {
+        int u = M->src[i], v = M->dst[i];
+        if (u < 0 || v < 0 || u == v) return TM_EINVAL;
+        if (u > next || (u == next && v > next + 1)) return TM_EINVAL;
+        if (u == next) ++next;
+        if (v > next) return TM_EINVAL;
+        if (v == next) ++next;
+    }
+    P->l = l;
+    P->k = next;
+    bool bound[5] = {false, false, false, false, false};
+    bound[M->src[0]] = bound[M->dst[0]] = true;
+    P->kind[0] = LV_PAIR;
+    P->u[0] = M->src[0];
+    P->v[0] = M->dst[0];
+    for (int r = 1; r < 4; ++r) {
+        P->kind[r] = LV_PAIR;
+        P->u[r] = P->v[r] = 0;
+    }
+    for (int r = 1; r < l; ++r) {
+        int u = M->src[r], v = M->dst[r];
+        P->u[r] = u;
+        P->v[r] = v;
+        if (bound[u] && bound[v]) P->kind[r] = LV_PAIR;
+        else if (bound[u]) P->kind[r] = LV_OUT;
+        else if (bound[v]) P->kind[r] = LV_IN;
+        else return TM_EUNSUPPORTED;  // not prefix-connected
+        bound[u] = bound[v] = true;
+    }
+    return TM_OK;
+}
+
+tm_status tm_count_generic(const tm_graph *g, const MotifPlan &P, int64_t delta, const AnchorSet &A, uint64_t *total,
+                           uint64_t *slot_tot, uint64_t *hist_lo, uint64_t *hist_hi, uint64_t *per_anchor,
+                           int32_t *flag, hipStream_t st) {
+    DevGraph G = dev_view(g);
+    bool hist = hist_lo != nullptr;
+#define TM_LEN_CASE(LN)                                                                                          \
+    case LN:                                                                                                     \
+        return hist ? launch_len<LN, true>(G, P, delta, A, total, slot_tot, hist_lo, hist_hi, per_anchor, flag,  \
+                                           st)                                                                   \
+                    : launch_len<LN, false>(G, P, delta, A, total, slot_tot, nullptr, nullptr, per_anchor, flag, \
+                                            st);
+    switch (P.l) {
+        TM_LEN_CASE(1)
+        TM_LEN_CASE(2)
+        TM_LEN_CASE(3)
+        TM_LEN_CASE(4)
+        default:
+            return TM_EUNSUPPORTED;
+    }
+#undef TM_LEN_CASE
+}
+
+tm_status tm_weight(const uint64_t *hist_lo, const uint64_t *hist_hi, int64_t delta, int64_t L, double p, double *out,
+                    hipStream_t st) {
+    hipLaunchKernelGGL(k_weight, dim3(1), dim3(64), 0, st, hist_lo, hist_hi, delta, L, p, out);
+    return tm_hip_status(hipGetLastError());
+}

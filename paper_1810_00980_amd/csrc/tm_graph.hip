@@ -1,0 +1,398 @@
+// Graph ingestion: validation, time normalisation (times start at 0, as
+// Algorithm 1 assumes), a stable device radix sort by time, and per-node
+// time-sorted incidence lists built by stable sorts on node ids.
+#include "tm_common.h"
+
+#include <limits.h>
+#include <string.h>
+
+namespace {
+
+constexpr int TPB = 256;
+
+__global__ void k_validate(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t m, int32_t n,
+                           int32_t *bad, long long *tmin, long long *tmax) {
+    __shared__ long long smin[TPB], smax[TPB];
+    long long lo = LLONG_MAX, hi = LLONG_MIN;
+    int b = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t s = src[i], d = dst[i];
+        b |= (s < 0) | (s >= n) | (d < 0) | (d >= n);
+        long long x = t[i];
+        lo = x < lo ? x : lo;
+        hi = x > hi ? x : hi;
+    }
+    if (b) atomicOr(bad, 1);
+    smin[threadIdx.x] = lo;
+    smax[threadIdx.x] = hi;
+    __syncthreads();
+    for (int s = TPB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            smin[threadIdx.x] = smin[threadIdx.x + s] < smin[threadIdx.x] ? smin[threadIdx.x + s] : smin[threadIdx.x];
+            smax[threadIdx.x] = smax[threadIdx.x + s] > smax[threadIdx.x] ? smax[threadIdx.x + s] : smax[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMin(tmin, smin[0]);
+        atomicMax(tmax, smax[0]);
+    }
+}
+
+__global__ void k_time_keys(const int64_t *t, int64_t m, int64_t tmin, uint64_t *keys, uint32_t *vals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) {
+        keys[i] = (uint64_t)(t[i] - tmin);
+        vals[i] = (uint32_t)i;
+    }
+}
+
+__global__ void k_gather_sorted(const int32_t *src, const int32_t *dst, const uint64_t *keys, const uint32_t *vals,
+                                int64_t m, int32_t *es_src, int32_t *es_dst, int64_t *es_t, int64_t *pos_of,
+                                int64_t *nl_flag) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) {
+        uint32_t e = vals[k];
+        int32_t s = src[e], d = dst[e];
+        es_src[k] = s;
+        es_dst[k] = d;
+        es_t[k] = (int64_t)keys[k];
+        pos_of[e] = k;
+        nl_flag[k] = (s != d) ? 1 : 0;
+    }
+}
+
+__global__ void k_compact_nl(const int64_t *flag_scan, const int32_t *es_src, const int32_t *es_dst, int64_t m,
+                             int64_t *nl_pos) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m && es_src[k] != es_dst[k]) nl_pos[flag_scan[k]] = k;
+}
+
+// keys = node of each non-self-loop edge (src when which == 0, dst when 1)
+__global__ void k_node_keys(const int64_t *nl_pos, int64_t m_nl, const int32_t *es_node, uint64_t *keys,
+                            uint32_t *vals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m_nl) {
+        keys[i] = (uint64_t)es_node[nl_pos[i]];
+        vals[i] = (uint32_t)i;
+    }
+}
+
+__global__ void k_fill_list(const uint32_t *vals, int64_t m_nl, const int64_t *nl_pos, const int32_t *es_other,
+                            const int64_t *es_t, int32_t *nbr, int64_t *tl) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m_nl) {
+        int64_t k = nl_pos[vals[j]];
+        nbr[j] = es_other[k];
+        tl[j] = es_t[k];
+    }
+}
+
+// off[v] = first j with keys[j] >= v * scale, v = 0..n
+__global__ void k_lower_bound(const uint64_t *keys, int64_t len, int64_t n, uint64_t scale, int64_t *off) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v <= n) {
+        uint64_t target = (uint64_t)v * scale;
+        int64_t lo = 0, hi = len;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (keys[mid] < target) lo = mid + 1;
+            else hi = mid;
+        }
+        off[v] = lo;
+    }
+}
+
+__global__ void k_pair_keys(const int64_t *nl_pos, int64_t m_nl, const int32_t *es_src, const int32_t *es_dst,
+                            int64_t n, uint64_t *keys, uint32_t *vals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m_nl) {
+        int64_t k = nl_pos[i];
+        keys[i] = (uint64_t)es_src[k] * (uint64_t)n + (uint64_t)es_dst[k];
+        vals[i] = (uint32_t)i;
+    }
+}
+
+__global__ void k_pair_fill(const uint64_t *keys, const uint32_t *vals, int64_t m_nl, const int64_t *nl_pos,
+                            const int64_t *es_t, int64_t *pr_t, int64_t *bflag) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m_nl) {
+        pr_t[j] = es_t[nl_pos[vals[j]]];
+        bflag[j] = (j == 0 || keys[j] != keys[j - 1]) ? 1 : 0;
+    }
+}
+
+__global__ void k_pair_index(const uint64_t *keys, const int64_t *bscan, int64_t m_nl, int64_t n,
+                             uint64_t *sp_key, int32_t *sp_nbr, int64_t *sp_beg) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m_nl && (j == 0 || keys[j] != keys[j - 1])) {
+        int64_t p = bscan[j];
+        sp_key[p] = keys[j];
+        sp_nbr[p] = (int32_t)(keys[j] % (uint64_t)n);
+        sp_beg[p] = j;
+    }
+}
+
+__global__ void k_set1(int64_t *p, int64_t v) { p[0] = v; }
+
+__global__ void k_inc_keys(const int64_t *nl_pos, int64_t m_nl, const int32_t *es_src, const int32_t *es_dst,
+                           uint64_t *keys, uint32_t *vals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m_nl) {
+        int64_t k = nl_pos[i];
+        keys[2 * i] = (uint64_t)es_src[k];
+        vals[2 * i] = (uint32_t)(2 * i);
+        keys[2 * i + 1] = (uint64_t)es_dst[k];
+        vals[2 * i + 1] = (uint32_t)(2 * i + 1);
+    }
+}
+
+__global__ void k_inc_fill(const uint32_t *vals, int64_t len, const int64_t *nl_pos, const int32_t *es_src,
+                           const int32_t *es_dst, const int64_t *es_t, uint32_t *nd, int64_t *tl) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < len) {
+        uint32_t v = vals[j];
+        int64_t k = nl_pos[v >> 1];
+        uint32_t dir = v & 1u;  // 0: this node is the source, 1: the destination
+        uint32_t other = dir ? (uint32_t)es_src[k] : (uint32_t)es_dst[k];
+        nd[j] = other | (dir << 31);
+        tl[j] = es_t[k];
+    }
+}
+
+tm_status build_node_lists(tm_graph *g, const int64_t *nl_pos, bool by_src, DevBuf &off, DevBuf &nbr, DevBuf &tl,
+                           hipStream_t st) {
+    int64_t mn = g->m_nl, n = g->n;
+    DevBuf keys, vals;
+    TM_TRY(keys.alloc((size_t)mn * 8));
+    TM_TRY(vals.alloc((size_t)mn * 4));
+    TM_TRY(off.alloc((size_t)(n + 1) * 8));
+    TM_TRY(nbr.alloc((size_t)mn * 4));
+    TM_TRY(tl.alloc((size_t)mn * 8));
+    const int32_t *node = by_src ? g->es_src.as<int32_t>() : g->es_dst.as<int32_t>();
+    const int32_t *other = by_src ? g->es_dst.as<int32_t>() : g->es_src.as<int32_t>();
+    if (mn > 0) {
+        hipLaunchKernelGGL(k_node_keys, dim3(tm_blocks(mn, TPB)), dim3(TPB), 0, st, nl_pos, mn, node,
+                           keys.as<uint64_t>(), vals.as<uint32_t>());
+        TM_HIP(hipGetLastError());
+        TM_TRY(tm_radix_sort(keys.as<uint64_t>(), vals.as<uint32_t>(), mn, tm_bitlen((uint64_t)(n - 1)), st));
+        hipLaunchKernelGGL(k_fill_list, dim3(tm_blocks(mn, TPB)), dim3(TPB), 0, st, vals.as<uint32_t>(), mn, nl_pos,
+                           other, g->es_t.as<int64_t>(), nbr.as<int32_t>(), tl.as<int64_t>());
+        TM_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_lower_bound, dim3(tm_blocks(n + 1, TPB)), dim3(TPB), 0, st, keys.as<uint64_t>(), mn, n,
+                       (uint64_t)1, off.as<int64_t>());
+    TM_HIP(hipGetLastError());
+    TM_HIP(hipStreamSynchronize(st));
+    return TM_OK;
+}
+
+tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t m, int32_t n_nodes,
+                    int32_t on_device, hipStream_t st, tm_graph *g) {
+    TM_HIP(hipGetDevice(&g->device));
+    g->m = m;
+    g->n = n_nodes;
+    DevBuf hsrc, hdst, ht;
+    const int32_t *d_src = src, *d_dst = dst;
+    const int64_t *d_t = t;
+    if (!on_device && m > 0) {
+        TM_TRY(hsrc.alloc((size_t)m * 4));
+        TM_TRY(hdst.alloc((size_t)m * 4));
+        TM_TRY(ht.alloc((size_t)m * 8));
+        TM_HIP(hipMemcpyAsync(hsrc.p, src, (size_t)m * 4, hipMemcpyHostToDevice, st));
+        TM_HIP(hipMemcpyAsync(hdst.p, dst, (size_t)m * 4, hipMemcpyHostToDevice, st));
+        TM_HIP(hipMemcpyAsync(ht.p, t, (size_t)m * 8, hipMemcpyHostToDevice, st));
+        d_src = hsrc.as<int32_t>();
+        d_dst = hdst.as<int32_t>();
+        d_t = ht.as<int64_t>();
+    }
+    // validation and time range
+    DevBuf red;
+    TM_TRY(red.alloc(64));
+    struct { int32_t bad; int32_t pad; long long tmin, tmax; } h0 = {0, 0, LLONG_MAX, LLONG_MIN}, h1;
+    TM_HIP(hipMemcpyAsync(red.p, &h0, sizeof h0, hipMemcpyHostToDevice, st));
+    if (m > 0) {
+        unsigned nb = tm_blocks(m, TPB);
+        if (nb > 4096) nb = 4096;
+        char *rb = red.as<char>();
+        hipLaunchKernelGGL(k_validate, dim3(nb), dim3(TPB), 0, st, d_src, d_dst, d_t, m, n_nodes, (int32_t *)rb,
+                           (long long *)(rb + 8), (long long *)(rb + 16));
+        TM_HIP(hipGetLastError());
+    }
+    TM_HIP(hipMemcpyAsync(&h1, red.p, sizeof h1, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipStreamSynchronize(st));
+    if (h1.bad) return TM_EINVAL;
+    if (m > 0) {
+        // t - t_min must not overflow int64
+        if (h1.tmin < 0 && h1.tmax > LLONG_MAX + h1.tmin) return TM_EINVAL;
+        g->t_min = h1.tmin;
+        g->t_span = h1.tmax - h1.tmin;
+    }
+
+    // sorted edge array
+    TM_TRY(g->es_src.alloc((size_t)m * 4));
+    TM_TRY(g->es_dst.alloc((size_t)m * 4));
+    TM_TRY(g->es_t.alloc((size_t)m * 8));
+    TM_TRY(g->pos_of.alloc((size_t)m * 8));
+    DevBuf keys, vals, flag, nl;
+    TM_TRY(keys.alloc((size_t)m * 8));
+    TM_TRY(vals.alloc((size_t)m * 4));
+    TM_TRY(flag.alloc((size_t)(m + 1) * 8));
+    if (m > 0) {
+        hipLaunchKernelGGL(k_time_keys, dim3(tm_blocks(m, TPB)), dim3(TPB), 0, st, d_t, m, g->t_min,
+                           keys.as<uint64_t>(), vals.as<uint32_t>());
+        TM_HIP(hipGetLastError());
+        TM_TRY(tm_radix_sort(keys.as<uint64_t>(), vals.as<uint32_t>(), m, tm_bitlen((uint64_t)g->t_span), st));
+        hipLaunchKernelGGL(k_gather_sorted, dim3(tm_blocks(m, TPB)), dim3(TPB), 0, st, d_src, d_dst,
+                           keys.as<uint64_t>(), vals.as<uint32_t>(), m, g->es_src.as<int32_t>(),
+                           g->es_dst.as<int32_t>(), g->es_t.as<int64_t>(), g->pos_of.as<int64_t>(),
+                           flag.as<int64_t>());
+        TM_HIP(hipGetLastError());
+    }
+    // non-self-loop positions
+    DevBuf cnt;
+    TM_TRY(cnt.alloc(8));
+    TM_TRY(tm_scan_i64(flag.as<int64_t>(), m, cnt.as<int64_t>(), st));
+    int64_t m_nl = 0;
+    TM_HIP(hipMemcpyAsync(&m_nl, cnt.p, 8, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipStreamSynchronize(st));
+    g->m_nl = m_nl;
+    TM_TRY(nl.alloc((size_t)m_nl * 8));
+    if (m > 0) {
+        hipLaunchKernelGGL(k_compact_nl, dim3(tm_blocks(m, TPB)), dim3(TPB), 0, st, flag.as<int64_t>(),
+                           g->es_src.as<int32_t>(), g->es_dst.as<int32_t>(), m, nl.as<int64_t>());
+        TM_HIP(hipGetLastError());
+    }
+    keys.release();
+    vals.release();
+    hsrc.release();
+    hdst.release();
+    ht.release();
+
+    // out- and in-lists
+    TM_TRY(build_node_lists(g, nl.as<int64_t>(), true, g->out_off, g->out_nbr, g->out_t, st));
+    TM_TRY(build_node_lists(g, nl.as<int64_t>(), false, g->in_off, g->in_nbr, g->in_t, st));
+
+    // directed pairs sorted by (src, dst, t)
+    {
+        int64_t n = g->n;
+        DevBuf pk, pv, bflag, spk;
+        TM_TRY(pk.alloc((size_t)m_nl * 8));
+        TM_TRY(pv.alloc((size_t)m_nl * 4));
+        TM_TRY(bflag.alloc((size_t)(m_nl + 1) * 8));
+        TM_TRY(g->pr_t.alloc((size_t)m_nl * 8));
+        int64_t S = 0;
+        if (m_nl > 0) {
+            hipLaunchKernelGGL(k_pair_keys, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, nl.as<int64_t>(), m_nl,
+                               g->es_src.as<int32_t>(), g->es_dst.as<int32_t>(), n, pk.as<uint64_t>(),
+                               pv.as<uint32_t>());
+            TM_HIP(hipGetLastError());
+            TM_TRY(tm_radix_sort(pk.as<uint64_t>(), pv.as<uint32_t>(), m_nl,
+                                 tm_bitlen((uint64_t)n * (uint64_t)n - 1), st));
+            hipLaunchKernelGGL(k_pair_fill, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, pk.as<uint64_t>(),
+                               pv.as<uint32_t>(), m_nl, nl.as<int64_t>(), g->es_t.as<int64_t>(), g->pr_t.as<int64_t>(),
+                               bflag.as<int64_t>());
+            TM_HIP(hipGetLastError());
+            TM_TRY(tm_scan_i64(bflag.as<int64_t>(), m_nl, cnt.as<int64_t>(), st));
+            TM_HIP(hipMemcpyAsync(&S, cnt.p, 8, hipMemcpyDeviceToHost, st));
+            TM_HIP(hipStreamSynchronize(st));
+        }
+        g->S = S;
+        TM_TRY(spk.alloc((size_t)S * 8));
+        TM_TRY(g->sp_nbr.alloc((size_t)S * 4));
+        TM_TRY(g->sp_beg.alloc((size_t)(S + 1) * 8));
+        TM_TRY(g->sp_off.alloc((size_t)(n + 1) * 8));
+        if (m_nl > 0) {
+            hipLaunchKernelGGL(k_pair_index, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, pk.as<uint64_t>(),
+                               bflag.as<int64_t>(), m_nl, n, spk.as<uint64_t>(), g->sp_nbr.as<int32_t>(),
+                               g->sp_beg.as<int64_t>());
+            TM_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_set1, dim3(1), dim3(1), 0, st, g->sp_beg.as<int64_t>() + S, m_nl);
+        TM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_lower_bound, dim3(tm_blocks(n + 1, TPB)), dim3(TPB), 0, st, spk.as<uint64_t>(), S, n,
+                           (uint64_t)n, g->sp_off.as<int64_t>());
+        TM_HIP(hipGetLastError());
+        TM_HIP(hipStreamSynchronize(st));
+    }
+
+    // combined incidence lists
+    {
+        int64_t len = 2 * m_nl, n = g->n;
+        DevBuf ik, iv;
+        TM_TRY(ik.alloc((size_t)len * 8));
+        TM_TRY(iv.alloc((size_t)len * 4));
+        TM_TRY(g->inc_nd.alloc((size_t)len * 4));
+        TM_TRY(g->inc_t.alloc((size_t)len * 8));
+        TM_TRY(g->inc_off.alloc((size_t)(n + 1) * 8));
+        if (m_nl > 0) {
+            hipLaunchKernelGGL(k_inc_keys, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, nl.as<int64_t>(), m_nl,
+                               g->es_src.as<int32_t>(), g->es_dst.as<int32_t>(), ik.as<uint64_t>(), iv.as<uint32_t>());
+            TM_HIP(hipGetLastError());
+            TM_TRY(tm_radix_sort(ik.as<uint64_t>(), iv.as<uint32_t>(), len, tm_bitlen((uint64_t)(n - 1)), st));
+            hipLaunchKernelGGL(k_inc_fill, dim3(tm_blocks(len, TPB)), dim3(TPB), 0, st, iv.as<uint32_t>(), len,
+                               nl.as<int64_t>(), g->es_src.as<int32_t>(), g->es_dst.as<int32_t>(),
+                               g->es_t.as<int64_t>(), g->inc_nd.as<uint32_t>(), g->inc_t.as<int64_t>());
+            TM_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_lower_bound, dim3(tm_blocks(n + 1, TPB)), dim3(TPB), 0, st, ik.as<uint64_t>(), len, n,
+                           (uint64_t)1, g->inc_off.as<int64_t>());
+        TM_HIP(hipGetLastError());
+        TM_HIP(hipStreamSynchronize(st));
+    }
+    const DevBuf *all[] = {&g->es_src, &g->es_dst, &g->es_t, &g->pos_of, &g->out_off, &g->out_nbr, &g->out_t,
+                           &g->in_off, &g->in_nbr, &g->in_t, &g->sp_off, &g->sp_nbr, &g->sp_beg, &g->pr_t,
+                           &g->inc_off, &g->inc_nd, &g->inc_t};
+    int64_t tot = 0;
+    for (const DevBuf *b : all) tot += (int64_t)b->bytes;
+    g->device_bytes = tot;
+    return TM_OK;
+}
+
+}  // namespace
+
+DevGraph dev_view(const tm_graph *g) {
+    DevGraph v;
+    v.m = g->m; v.n = g->n; v.m_nl = g->m_nl; v.S = g->S;
+    v.es_src = g->es_src.as<int32_t>(); v.es_dst = g->es_dst.as<int32_t>(); v.es_t = g->es_t.as<int64_t>();
+    v.out_off = g->out_off.as<int64_t>(); v.out_nbr = g->out_nbr.as<int32_t>(); v.out_t = g->out_t.as<int64_t>();
+    v.in_off = g->in_off.as<int64_t>(); v.in_nbr = g->in_nbr.as<int32_t>(); v.in_t = g->in_t.as<int64_t>();
+    v.sp_off = g->sp_off.as<int64_t>(); v.sp_nbr = g->sp_nbr.as<int32_t>(); v.sp_beg = g->sp_beg.as<int64_t>();
+    v.pr_t = g->pr_t.as<int64_t>();
+    v.inc_off = g->inc_off.as<int64_t>(); v.inc_nd = g->inc_nd.as<uint32_t>(); v.inc_t = g->inc_t.as<int64_t>();
+    return v;
+}
+
+extern "C" tm_status tm_load_graph(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t m,
+                                   int32_t n_nodes, int32_t on_device, void *hip_stream, tm_graph **out) {
+    if (!out || m < 0 || n_nodes <= 0 || (m > 0 && (!src || !dst || !t))) return TM_EINVAL;
+    if (m > (int64_t)INT32_MAX) return TM_EINVAL;  // 32-bit edge indices in the sorts
+    tm_graph *g = new (std::nothrow) tm_graph();
+    if (!g) return TM_ENOMEM;
+    tm_status s = load_impl(src, dst, t, m, n_nodes, on_device, (hipStream_t)hip_stream, g);
+    if (s != TM_OK) {
+        (void)hipStreamSynchronize((hipStream_t)hip_stream);
+        delete g;
+        (void)hipGetLastError();
+        return s;
+    }
+    *out = g;
+    return TM_OK;
+}
+
+extern "C" void tm_free_graph(tm_graph *g) {
+    if (!g) return;
+    (void)hipDeviceSynchronize();
+    delete g;
+}
+
+extern "C" tm_status tm_graph_info_get(const tm_graph *g, tm_graph_info *info) {
+    if (!g || !info) return TM_EINVAL;
+    info->m = g->m;
+    info->n = g->n;
+    info->t_min = g->t_min;
+    info->t_span = g->t_span;
+    info->n_pairs = g->S;
+    info->device_bytes = g->device_bytes;
+    return TM_OK;
+}

@@ -1,0 +1,173 @@
+"""GPU parity: libtm (HIP, gfx950) against the CPU oracle on the same seeded
+inputs.  Counts and histograms must be bit-exact; estimates for the same seed
+within 1e-12 relative (the weighting is the same fixed-order FP64 sum, so in
+practice they are identical)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import tm_inputs as ti
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def tm():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    import paper_1810_00980_amd as tm
+    return tm
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def to_dev(g):
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (g.src, g.dst, g.t)]
+
+
+def load(tm, g, device=True):
+    if device:
+        s, d, t = to_dev(g)
+        return tm.load_graph(s, d, t, g.n)
+    return tm.load_graph(g.src, g.dst, g.t, g.n)
+
+
+def close(a, b):
+    return abs(a - b) <= REL * max(1.0, abs(b))
+
+
+MOTIFS = ti.three_edge_motifs() + [ti.CYCLE4, ti.STAR4, ti.OUTSTAR5, ((0, 1),), ((0, 1), (1, 0)),
+                                    ((0, 1), (2, 0)), ((0, 1), (0, 1)), ((0, 1), (1, 2), (2, 3)),
+                                    ((0, 1), (1, 2), (2, 0), (0, 1))]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_small_random_all_motifs(tm, seed):
+    # dense tiny graphs: many repeated pairs, ties and self-loops; several
+    # 256-anchor tiles and a ragged tail
+    g = ti.random_small_graph(6 + seed, 700 + 37 * seed, 3000, 900 + seed, allow_self_loops=True)
+    say("small_random", seed, g.m)
+    G = load(tm, g, device=(seed % 2 == 0))
+    for M in MOTIFS:
+        for delta in (0, 7, 60):
+            got = tm.count_exact(G, M, delta)
+            want, _ = oracle.count(g.src, g.dst, g.t, M, delta, hist=False)
+            assert got == want, (M, delta, got, want)
+    cnt, hlo, hhi = tm.count_exact_multi(G, MOTIFS[:8], 60, hist=True)
+    for i, M in enumerate(MOTIFS[:8]):
+        want, h = oracle.count(g.src, g.dst, g.t, M, 60)
+        assert cnt[i] == want and (hlo[i] == h).all() and not hhi[i].any()
+
+
+@pytest.mark.parametrize("motif", [ti.TRIANGLE, ti.TWO_NODE_ALT, ((0, 1), (0, 2), (2, 0)), ti.CYCLE4])
+def test_estimate_matches_oracle_seed_by_seed(tm, motif):
+    g = ti.random_small_graph(7, 900, 5000, 31, allow_self_loops=True)
+    say("estimate", motif)
+    G = load(tm, g)
+    for (delta, c, p) in ((40, 2, 0.5), (40, 3, 1.0), (25, 10, 0.2)):
+        for seed in range(6):
+            r = tm.estimate(G, motif, delta, c, p, seed, info=True)
+            o = oracle.estimate(g.src, g.dst, g.t, motif, delta, c, p, seed)
+            assert r["s"] == o["s"] and r["J"] == o["J"] and r["n_kept"] == o["n_kept"]
+            assert list(r["kept"]) == list(o["kept"])
+            assert list(r["win_counts"]) == list(o["win_counts"])
+            assert (r["hist_lo"] == o["hist"]).all() and not r["hist_hi"].any()
+            assert r["kept_count"] == int(o["win_counts"].sum())
+            assert close(r["Z"], o["Z"]), (r["Z"], o["Z"])
+
+
+def test_small_config_exact_and_estimate(tm):
+    """1,000 nodes, 20,000 uniform edges, triangle, delta 3600, c 30, p 0.1,
+    seed 0; and the 50-node version where the count is not zero."""
+    for g in (ti.config_small(), ti.config_small_dense()):
+        say("small_config", g.n)
+        G = load(tm, g)
+        delta, c, p = 3600, 30, 0.1
+        want, h = oracle.count(g.src, g.dst, g.t, ti.TRIANGLE, delta)
+        cnt, hlo, _ = tm.count_exact_multi(G, [ti.TRIANGLE], delta, hist=True)
+        assert cnt[0] == want and (hlo[0] == h).all()
+        for seed in (0, 1, 2):
+            r = tm.estimate(G, ti.TRIANGLE, delta, c, p, seed, info=True)
+            o = oracle.estimate(g.src, g.dst, g.t, ti.TRIANGLE, delta, c, p, seed)
+            assert list(r["kept"]) == list(o["kept"]) and list(r["win_counts"]) == list(o["win_counts"])
+            assert close(r["Z"], o["Z"])
+
+
+def test_dense_small_all_three_edge_motifs(tm):
+    g = ti.config_small_dense()
+    say("dense_small_36")
+    G = load(tm, g)
+    mot = ti.three_edge_motifs()
+    got = tm.count_exact_multi(G, mot, 3600)
+    for M, c in zip(mot, got):
+        want, _ = oracle.count(g.src, g.dst, g.t, M, 3600, hist=False)
+        assert c == want, M
+
+
+def test_edge_cases(tm):
+    say("edge_cases")
+    # empty graph
+    e = ti.Graph(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int64), 3)
+    G = load(tm, e, device=False)
+    assert tm.count_exact(G, ti.TRIANGLE, 10) == 0
+    assert tm.estimate(G, ti.TRIANGLE, 10, 2, 0.5, 0) == 0.0
+    # single edge, all self-loops, all ties
+    one = ti.Graph(np.array([0], np.int32), np.array([1], np.int32), np.array([5], np.int64), 2)
+    G = load(tm, one, device=False)
+    assert tm.count_exact(G, ((0, 1),), 0) == 1
+    loops = ti.Graph(np.arange(5, dtype=np.int32), np.arange(5, dtype=np.int32), np.arange(5, dtype=np.int64), 5)
+    G = load(tm, loops, device=False)
+    assert tm.count_exact(G, ((0, 1),), 10) == 0
+    ties = ti.Graph(np.array([0, 1, 2], np.int32), np.array([1, 2, 0], np.int32), np.array([7, 7, 7], np.int64), 3)
+    G = load(tm, ties, device=False)
+    assert tm.count_exact(G, ti.TRIANGLE, 10) == 0
+    # negative and huge times, delta = infinity
+    big = ti.Graph(np.array([0, 1, 2], np.int32), np.array([1, 2, 0], np.int32),
+                   np.array([-(1 << 61), 0, (1 << 62)], np.int64), 3)
+    G = load(tm, big, device=False)
+    span = (1 << 62) + (1 << 61)
+    assert tm.count_exact(G, ti.TRIANGLE, (1 << 63) - 1) == 1
+    assert tm.count_exact(G, ti.TRIANGLE, span) == 1
+    assert tm.count_exact(G, ti.TRIANGLE, span - 1) == 0
+
+
+def test_errors(tm):
+    say("errors")
+    g = ti.random_small_graph(4, 50, 100, 1)
+    G = load(tm, g, device=False)
+    with pytest.raises(tm.TMError) as e:
+        tm.count_exact(G, ((0, 1), (2, 3)), 5)
+    assert e.value.status == 2  # not prefix-connected
+    with pytest.raises(tm.TMError) as e:
+        tm.count_exact(G, ((0, 2),), 5)
+    assert e.value.status == 1  # not canonical
+    with pytest.raises(tm.TMError) as e:
+        tm.count_exact(G, ((0, 1), (1, 1)), 5)
+    assert e.value.status == 1  # self-loop
+    for (c, p) in ((1, 0.5), (2, 0.0), (2, 1.5), (2, float("nan"))):
+        with pytest.raises(tm.TMError) as e:
+            tm.estimate(G, ti.TRIANGLE, 5, c, p, 0)
+        assert e.value.status == 1
+    with pytest.raises(tm.TMError) as e:
+        tm.load_graph(np.array([0, 7], np.int32), np.array([1, 1], np.int32), np.array([1, 2], np.int64), 4)
+    assert e.value.status == 1
+
+
+def test_per_anchor_counts(tm):
+    g = ti.random_small_graph(6, 800, 2000, 77, allow_self_loops=True)
+    say("per_anchor")
+    G = load(tm, g)
+    rng = np.random.default_rng(0)
+    anchors = rng.choice(g.m, size=100, replace=False)
+    win = rng.integers(0, 2500, size=100)
+    for M in (ti.TRIANGLE, ti.STAR4, ((0, 1), (1, 0), (0, 1))):
+        got = tm.count_anchors(G, M, 50, anchors, win_end=win)
+        want = oracle.count_anchors(g.src, g.dst, g.t - g.t.min(), M, 50, anchors, win_hi=win)
+        assert (got == want).all()
