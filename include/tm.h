@@ -131,6 +131,15 @@ tm_status tm_count_exact_multi(const tm_graph *g, int32_t n_motifs, const tm_mot
                                uint64_t *hist_hi, void *hip_stream);
 
 /*
+ * Exact counts inside one time window: the counting subroutine A(T', M,
+ * delta) of Sec. 4 applied to the sub-graph T' of edges with input time in
+ * [t_lo, t_hi] (the per-window step of Algorithm 1).  counts[i] for
+ * motifs[i]; all three-edge motifs share one pass.
+ */
+tm_status tm_count_window(const tm_graph *g, int32_t n_motifs, const tm_motif *motifs, int64_t delta,
+                          int64_t t_lo, int64_t t_hi, tm_u128 *counts, void *hip_stream);
+
+/*
  * Per-anchor counts: for each listed edge (index into the caller's input
  * arrays as given to tm_load_graph), the number of delta-instances whose
  * first edge is that edge and whose edges all have normalised time

@@ -66,6 +66,7 @@ _SIGS = {
     "tm_count_exact_i64": [P, P, i64, P, P],
     "tm_count_exact_multi": [P, i32, P, i64, P, P, P, P],
     "tm_count_anchors": [P, P, i64, i64, P, P, P, P],
+    "tm_count_window": [P, i32, P, i64, i64, i64, P, P],
     "tm_estimate": [P, P, i64, i64, f64, u64, P, P, P],
     "tm_estimate_multi": [P, i32, P, i64, i64, f64, u64, P, P, P],
     "tm_estimate_batch": [P, P, i64, i64, f64, i32, P, i32, P, P, P],
@@ -196,6 +197,16 @@ def count_exact_multi(g: Graph, motifs, delta: int, hist: bool = False, stream=N
     if hist:
         return counts, hlo, hhi
     return counts
+
+
+def count_window(g: Graph, motifs, delta: int, t_lo: int, t_hi: int, stream=None):
+    """Exact counts of each motif among edges with input time in [t_lo, t_hi]."""
+    k = len(motifs)
+    arr = (Motif * max(k, 1))(*[motif(m) for m in motifs])
+    cnt = (U128 * max(k, 1))()
+    _check(_lib.tm_count_window(g.handle, k, arr, int(delta), int(t_lo), int(t_hi), cnt, _stream(stream)),
+           "tm_count_window")
+    return [cnt[i].value() for i in range(k)]
 
 
 def count_anchors(g: Graph, edges, delta: int, anchors, win_end=None, stream=None) -> np.ndarray:

@@ -300,10 +300,93 @@ tm_status estimate_impl(const tm_graph *g, const tm_motif *M, int64_t delta, int
     return TM_OK;
 }
 
+// ---------------------------------------------------------------- sweep path
+
+struct SweepOut {
+    uint64_t v[36 * 4];
+};
+
+static double u128_scaled(uint64_t lo, uint64_t hi, double scale) {
+    double x = (double)hi * 18446744073709551616.0;
+    x = x + (double)lo;
+    return x * scale;
+}
+
+// Runs the 3-edge sweep for the codes in mask; copies the 36 x 4 results and
+// (mode 2) the histograms of the requested codes to the host.
+tm_status run_sweep(const tm_graph *g, uint64_t mask, int mode, int64_t delta, int windowed, int64_t s, int64_t L,
+                    uint64_t seed, double p, SweepOut *out, const std::vector<int> &hist_codes,
+                    std::vector<uint64_t> *hist_host, hipStream_t st) {
+    DevBuf o, h, w, ctr;
+    TM_TRY(o.alloc(36 * 4 * 8));
+    TM_TRY(ctr.alloc(64));
+    if (mode == 2) TM_TRY(h.alloc((size_t)36 * (delta + 1) * 16));
+    if (mode == 1) TM_TRY(w.alloc((size_t)(delta + 1) * 8));
+    TM_TRY(tm_sweep3(g, mask, mode, delta, windowed, s, L, seed, p, o.as<uint64_t>(), h.as<uint64_t>(),
+                     w.as<uint64_t>(), ctr.as<int64_t>(), st));
+    TM_HIP(hipMemcpyAsync(out->v, o.p, sizeof out->v, hipMemcpyDeviceToHost, st));
+    if (mode == 2 && hist_host) {
+        hist_host->assign(hist_codes.size() * (size_t)(delta + 1) * 2, 0);
+        for (size_t k = 0; k < hist_codes.size(); ++k) {
+            TM_HIP(hipMemcpyAsync(hist_host->data() + k * (size_t)(delta + 1) * 2,
+                                  h.as<uint64_t>() + (size_t)hist_codes[k] * (delta + 1) * 2,
+                                  (size_t)(delta + 1) * 16, hipMemcpyDeviceToHost, st));
+        }
+    }
+    TM_HIP(hipStreamSynchronize(st));
+    return TM_OK;
+}
+
+bool all_sweep_codes(int32_t n, const tm_motif *motifs, std::vector<int> *codes, uint64_t *mask) {
+    codes->clear();
+    *mask = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int c = tm_sweep_code_of(&motifs[i]);
+        if (c < 0) return false;
+        codes->push_back(c);
+        *mask |= 1ull << c;
+    }
+    return n > 0;
+}
+
+int64_t host_shift(uint64_t seed, int64_t L) {
+    uint64_t x = tm_draw(seed, 0, 0, 0);
+    return -(int64_t)(x % (uint64_t)L);
+}
+
+// estimates of 3-edge motifs through the sweep: Z = weight / 2^52 / p
+tm_status sweep_estimates(const tm_graph *g, int32_t n, const tm_motif *motifs, int64_t delta, int64_t c, double p,
+                          uint64_t seed, double *est, tm_u128 *kept, hipStream_t st) {
+    int64_t L;
+    TM_TRY(check_est_args(g, delta, c, p, &L));
+    std::vector<int> codes;
+    uint64_t mask;
+    if (!all_sweep_codes(n, motifs, &codes, &mask)) return TM_EUNSUPPORTED;
+    SweepOut so;
+    TM_TRY(run_sweep(g, mask, 1, delta, 1, host_shift(seed, L), L, seed, p, &so, {}, nullptr, st));
+    for (int32_t i = 0; i < n; ++i) {
+        const uint64_t *v = so.v + 4 * codes[(size_t)i];
+        est[i] = u128_scaled(v[2], v[3], 1.0 / 4503599627370496.0) / p;
+        if (kept) {
+            kept[i].lo = v[0];
+            kept[i].hi = v[1];
+        }
+    }
+    return TM_OK;
+}
+
 tm_status count_exact_impl(const tm_graph *g, const tm_motif *M, int64_t delta, uint64_t *hist_lo_host,
                            uint64_t *hist_hi_host, tm_u128 *out, hipStream_t st) {
     MotifPlan P;
     TM_TRY(check_graph_motif(g, M, delta, &P));
+    int code = tm_sweep_code_of(M);
+    if (code >= 0 && !hist_lo_host) {
+        SweepOut so;
+        TM_TRY(run_sweep(g, 1ull << code, 0, delta, 0, 0, 1, 0, 1.0, &so, {}, nullptr, st));
+        out->lo = so.v[4 * code];
+        out->hi = so.v[4 * code + 1];
+        return TM_OK;
+    }
     DevBuf acc, hist;
     TM_TRY(acc.alloc(64));
     TM_HIP(hipMemsetAsync(acc.p, 0, 64, st));
@@ -365,6 +448,27 @@ extern "C" tm_status tm_count_exact_multi(const tm_graph *g, int32_t n_motifs, c
     hipStream_t st = (hipStream_t)hip_stream;
     MotifPlan P;
     for (int32_t i = 0; i < n_motifs; ++i) TM_TRY(tm_make_plan(&motifs[i], &P));
+    std::vector<int> codes;
+    uint64_t mask;
+    if (all_sweep_codes(n_motifs, motifs, &codes, &mask) && (!hist_lo || delta <= TM_MAX_SWEEP_HIST_DELTA)) {
+        auto run = [&]() -> tm_status {
+            SweepOut so;
+            std::vector<uint64_t> hh;
+            TM_TRY(run_sweep(g, mask, hist_lo ? 2 : 0, delta, 0, 0, 1, 0, 1.0, &so, codes, &hh, st));
+            for (int32_t i = 0; i < n_motifs; ++i) {
+                counts[i].lo = so.v[4 * codes[(size_t)i]];
+                counts[i].hi = so.v[4 * codes[(size_t)i] + 1];
+                if (hist_lo) {
+                    for (int64_t d = 0; d <= delta; ++d) {
+                        hist_lo[(int64_t)i * (delta + 1) + d] = hh[((size_t)i * (delta + 1) + d) * 2];
+                        if (hist_hi) hist_hi[(int64_t)i * (delta + 1) + d] = hh[((size_t)i * (delta + 1) + d) * 2 + 1];
+                    }
+                }
+            }
+            return TM_OK;
+        };
+        return finish(run(), st);
+    }
     for (int32_t i = 0; i < n_motifs; ++i) {
         uint64_t *hl = hist_lo ? hist_lo + (int64_t)i * (delta + 1) : nullptr;
         uint64_t *hh = hist_hi ? hist_hi + (int64_t)i * (delta + 1) : nullptr;
@@ -414,6 +518,11 @@ extern "C" tm_status tm_count_anchors(const tm_graph *g, const tm_motif *M, int6
 extern "C" tm_status tm_estimate(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t c, double p,
                                  uint64_t seed, double *estimate, tm_est_info *info, void *hip_stream) {
     hipStream_t st = (hipStream_t)hip_stream;
+    if (!info && g && M && estimate && tm_sweep_code_of(M) >= 0) {
+        MotifPlan P;
+        TM_TRY(check_graph_motif(g, M, delta, &P));
+        return finish(sweep_estimates(g, 1, M, delta, c, p, seed, estimate, nullptr, st), st);
+    }
     return finish(estimate_impl(g, M, delta, c, p, seed, estimate, info, st), st);
 }
 
@@ -423,6 +532,12 @@ extern "C" tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, cons
     if (!g || n_motifs < 0 || (n_motifs > 0 && (!motifs || !estimates))) return TM_EINVAL;
     MotifPlan P;
     for (int32_t i = 0; i < n_motifs; ++i) TM_TRY(tm_make_plan(&motifs[i], &P));
+    std::vector<int> codes;
+    uint64_t mask;
+    if (all_sweep_codes(n_motifs, motifs, &codes, &mask)) {
+        hipStream_t st = (hipStream_t)hip_stream;
+        return finish(sweep_estimates(g, n_motifs, motifs, delta, c, p, seed, estimates, kept_counts, st), st);
+    }
     for (int32_t i = 0; i < n_motifs; ++i) {
         tm_est_info info;
         memset(&info, 0, sizeof info);
@@ -445,6 +560,70 @@ extern "C" tm_status tm_estimate_batch(const tm_graph *g, const tm_motif *M, int
         if (kept_counts) kept_counts[i] = info.kept_count;
     }
     return TM_OK;
+}
+
+extern "C" tm_status tm_count_window(const tm_graph *g, int32_t n_motifs, const tm_motif *motifs, int64_t delta,
+                                     int64_t t_lo, int64_t t_hi, tm_u128 *counts, void *hip_stream) {
+    if (!g || n_motifs < 0 || (n_motifs > 0 && (!motifs || !counts)) || delta < 0 || t_lo > t_hi) return TM_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    MotifPlan P;
+    for (int32_t i = 0; i < n_motifs; ++i) TM_TRY(tm_make_plan(&motifs[i], &P));
+    // normalised window bounds, clamped to the graph's time range
+    int64_t lo = (t_lo <= g->t_min) ? 0 : t_lo - g->t_min;
+    int64_t hi;
+    if (t_hi < g->t_min) {
+        for (int32_t i = 0; i < n_motifs; ++i) counts[i].lo = counts[i].hi = 0;
+        return TM_OK;
+    }
+    hi = (t_hi - g->t_min > g->t_span) ? g->t_span : t_hi - g->t_min;
+    std::vector<int> codes;
+    uint64_t mask;
+    if (all_sweep_codes(n_motifs, motifs, &codes, &mask)) {
+        auto run = [&]() -> tm_status {
+            SweepOut so;
+            TM_TRY(run_sweep(g, mask, 0, delta, 2, lo, hi, 0, 1.0, &so, {}, nullptr, st));
+            for (int32_t i = 0; i < n_motifs; ++i) {
+                counts[i].lo = so.v[4 * codes[(size_t)i]];
+                counts[i].hi = so.v[4 * codes[(size_t)i] + 1];
+            }
+            return TM_OK;
+        };
+        return finish(run(), st);
+    }
+    // other motifs: generic counter over the window's anchors
+    auto run = [&]() -> tm_status {
+        int64_t m = g->m;
+        std::vector<int64_t> tt((size_t)(m > 0 ? m : 1));
+        if (m > 0) TM_HIP(hipMemcpyAsync(tt.data(), g->es_t.p, (size_t)m * 8, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+        int64_t a0 = std::lower_bound(tt.begin(), tt.begin() + m, lo) - tt.begin();
+        int64_t a1 = std::upper_bound(tt.begin(), tt.begin() + m, hi) - tt.begin();
+        int64_t nA = a1 - a0;
+        for (int32_t i = 0; i < n_motifs; ++i) {
+            TM_TRY(tm_make_plan(&motifs[i], &P));
+            DevBuf acc, ap, we;
+            TM_TRY(acc.alloc(64));
+            TM_HIP(hipMemsetAsync(acc.p, 0, 64, st));
+            if (nA > 0) {
+                std::vector<int64_t> pos((size_t)nA), wend((size_t)nA, hi);
+                for (int64_t k = 0; k < nA; ++k) pos[(size_t)k] = a0 + k;
+                TM_TRY(ap.alloc((size_t)nA * 8));
+                TM_TRY(we.alloc((size_t)nA * 8));
+                TM_HIP(hipMemcpyAsync(ap.p, pos.data(), (size_t)nA * 8, hipMemcpyHostToDevice, st));
+                TM_HIP(hipMemcpyAsync(we.p, wend.data(), (size_t)nA * 8, hipMemcpyHostToDevice, st));
+                AnchorSet A{nA, ap.as<int64_t>(), we.as<int64_t>(), nullptr, nullptr};
+                TM_TRY(tm_count_generic(g, P, delta, A, acc.as<uint64_t>(), nullptr, nullptr, nullptr, nullptr, nullptr,
+                                        st));
+            }
+            uint64_t tot[2];
+            TM_HIP(hipMemcpyAsync(tot, acc.p, 16, hipMemcpyDeviceToHost, st));
+            TM_HIP(hipStreamSynchronize(st));
+            counts[i].lo = tot[0];
+            counts[i].hi = tot[1];
+        }
+        return TM_OK;
+    };
+    return finish(run(), st);
 }
 
 extern "C" const char *tm_strerror(tm_status s) {

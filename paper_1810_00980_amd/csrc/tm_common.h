@@ -193,3 +193,23 @@ tm_status tm_count_generic(const tm_graph *g, const MotifPlan &P, int64_t delta,
 // Neumaier compensation): out[0] = (1/p) sum N(d) L/(L-d).
 tm_status tm_weight(const uint64_t *hist_lo, const uint64_t *hist_hi, int64_t delta, int64_t L,
                     double p, double *out, hipStream_t st);
+
+// ------------------------------------------------------------ 3-edge sweep
+
+// The 36 motifs with three edges on two or three nodes, indexed 0..35 by the
+// sweep counter (canonical labels).
+void tm_sweep_code_motif(int code, tm_motif *M);
+int tm_sweep_code_of(const tm_motif *M);  // -1 when M is not one of them
+
+// Sweep counter.  mode 0: counts; 1: counts and fixed-point weighted sums
+// (weights round(2^52 L / (L - Delta)) written to wfx_dev); 2: counts and
+// duration histograms (hist_dev: 36 x (delta+1) x {lo, hi}).  out_dev:
+// 36 x {count lo, count hi, weight lo, weight hi}.  windowed: only anchors in
+// windows kept by (seed, p) under shift s and window length L.
+// counter_dev: 2 int64 work-queue heads.
+tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask, int mode, int64_t delta, int windowed, int64_t s,
+                    int64_t L, uint64_t seed, double p, uint64_t *out_dev, uint64_t *hist_dev, uint64_t *wfx_dev,
+                    int64_t *counter_dev, hipStream_t st);
+
+// Largest delta for the sweep counter's histogram mode (36 histograms).
+#define TM_MAX_SWEEP_HIST_DELTA ((int64_t)1 << 20)

@@ -171,3 +171,91 @@ def test_per_anchor_counts(tm):
         got = tm.count_anchors(G, M, 50, anchors, win_end=win)
         want = oracle.count_anchors(g.src, g.dst, g.t - g.t.min(), M, 50, anchors, win_hi=win)
         assert (got == want).all()
+
+
+THREE = ti.three_edge_motifs()
+
+
+def test_sweep_estimates_all_three_edge_motifs(tm):
+    """Estimates without diagnostics take the sweep counter (52-bit fixed-point
+    weights, exact integer sums); they match the oracle's FP64 value."""
+    g = ti.random_small_graph(6, 1200, 6000, 41, allow_self_loops=True)
+    say("sweep_estimates")
+    G = load(tm, g)
+    for (delta, c, p, seed) in ((40, 2, 0.5, 3), (60, 3, 1.0, 4), (25, 10, 0.3, 5)):
+        zs, kept = tm.estimate_multi(G, THREE, delta, c, p, seed)
+        for M, z, k in zip(THREE, zs, kept):
+            o = oracle.estimate(g.src, g.dst, g.t, M, delta, c, p, seed)
+            assert close(z, o["Z"]), (M, z, o["Z"])
+            assert k == int(o["win_counts"].sum()), M
+        for M in THREE[::5]:
+            assert close(tm.estimate(G, M, delta, c, p, seed), oracle.estimate(
+                g.src, g.dst, g.t, M, delta, c, p, seed)["Z"])
+
+
+def test_count_window(tm):
+    g = ti.random_small_graph(7, 1500, 8000, 43, allow_self_loops=True)
+    say("count_window")
+    G = load(tm, g)
+    for (lo, hi) in ((1000, 2500), (0, 8000), (7990, 9000), (-50, 3)):
+        for delta in (0, 30, 200):
+            got = tm.count_window(G, THREE + [ti.CYCLE4, ti.STAR4], delta, lo, hi)
+            for M, c in zip(THREE + [ti.CYCLE4, ti.STAR4], got):
+                want, _ = oracle.count(g.src, g.dst, g.t, M, delta, win=(lo, hi), hist=False)
+                assert c == want, (M, lo, hi, delta)
+
+
+@pytest.fixture(scope="module")
+def zipf10m():
+    return ti.config_zipf10m()
+
+
+def test_zipf10m_sampled_windows(tm, zipf10m):
+    """Full-size 10M-edge Zipf(1.8) graph: exact counts of the 36 three-edge
+    motifs inside sampled windows (the per-window counting step) against the
+    oracle on the same window sub-graphs."""
+    g = zipf10m
+    say("zipf10m windows: load")
+    G = load(tm, g)
+    delta = 3600
+    tsort = np.sort(g.t)
+    rng = np.random.default_rng(7)
+    wins = []
+    for _ in range(4000):
+        lo = int(rng.integers(0, 30_000_000 - 7200))
+        hi = lo + 7199
+        k = np.searchsorted(tsort, hi, side="right") - np.searchsorted(tsort, lo, side="left")
+        if 150 <= k <= 450:
+            wins.append((lo, hi))
+        if len(wins) == 3:
+            break
+    assert len(wins) == 3
+    for (lo, hi) in wins:
+        say("zipf10m window", lo, hi)
+        got = tm.count_window(G, THREE, delta, lo, hi)
+        sel = (g.t >= lo) & (g.t <= hi)
+        for M, c in zip(THREE, got):
+            want, _ = oracle.count(g.src[sel], g.dst[sel], g.t[sel], M, delta, hist=False)
+            assert c == want, (M, lo, hi)
+
+
+def test_zipf10m_sampled_anchors(tm, zipf10m):
+    """Full size: per-anchor counts (generic counter) for sampled anchors,
+    hub anchors included, against the oracle's per-anchor brute force."""
+    g = zipf10m
+    G = load(tm, g)
+    rng = np.random.default_rng(11)
+    deg = np.bincount(g.src, minlength=g.n) + np.bincount(g.dst, minlength=g.n)
+    hub = int(np.argmax(deg))
+    # anchors whose delta-window holds at most 4000 edges keep the brute force short
+    tsort = np.sort(g.t)
+    w = np.searchsorted(tsort, g.t + 3600, side="right") - np.searchsorted(tsort, g.t, side="left")
+    ok = np.nonzero(w <= 4000)[0]
+    hub_ok = ok[(g.src[ok] == hub) | (g.dst[ok] == hub)]
+    anchors = np.concatenate([rng.choice(ok, 6, replace=False), rng.choice(hub_ok, 2, replace=False)])
+    tn = g.t - g.t.min()
+    for M in (ti.TRIANGLE, ti.TWO_NODE_ALT, ((0, 1), (0, 2), (0, 2))):
+        say("zipf10m anchors", M)
+        got = tm.count_anchors(G, M, 3600, anchors)
+        want = oracle.count_anchors(g.src, g.dst, tn, M, 3600, anchors)
+        assert (got == want).all(), (M, got, want)
