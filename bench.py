@@ -2,14 +2,28 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-One step = one pass of the whole path over one synthetic graph already in
-HBM: load (validate, normalise, radix sort, incidence lists), exact counts
-of the workload's motifs, and its estimates (window partition, Philox
-sampling, per-window exact counts, FP64 weighting).  Prints one JSON line.
+One step is one pass of the whole path over one synthetic temporal graph
+whose arrays are already in HBM:
+  load       validate ids, normalise times, radix-sort by time, build the
+             per-node incidence lists and pair indexes;
+  exact      exact counts of every motif of the workload (one sweep);
+  estimates  for each (c, p) of the workload and every motif: shift draw,
+             window partition, Philox window sampling, exact counts of the
+             kept windows and the weighted sum (one sweep per (c, p));
+then the graph is freed.  Prints one JSON line on stdout.
+
+value = temporal edges x motif queries answered per step / seconds per step
+(a motif query is one motif's exact count or one motif's estimate at one
+(c, p)).  The roofline object reports the forward sweep kernel of the exact
+pass (the dominant kernel): algorithmic bytes per launch (12 bytes per
+incidence entry read: the anchor's own entry plus every entry its forward
+sweep scans, from the work census) over its average launch time, measured
+with HIP events on the launch stream inside the library.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,12 +36,25 @@ sys.path.insert(0, ROOT)
 
 import tm_inputs as ti  # noqa: E402
 
+THREE = ti.three_edge_motifs()
+HBM_PEAK_GBS = 8000.0
+DOMINANT = "sweep3_fwd_count"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep3_fwd_count_zipf10m_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1810_00980_amd", "csrc", "tm_sweep3.hip")
+
 WORKLOADS = {
-    # name: (graph factory, motifs, delta, [(c, p)], description)
-    "small": (ti.config_small, [ti.TRIANGLE], 3600, [(30, 0.1)],
-              "1k nodes, 20k uniform edges over [0,1e6), triangle, delta 3600, c 30, p 0.1"),
-    "small_dense": (ti.config_small_dense, [ti.TRIANGLE], 3600, [(30, 0.1)],
-                    "50 nodes, 20k uniform edges over [0,1e6), triangle, delta 3600, c 30, p 0.1"),
+    "zipf10m": dict(
+        graph=ti.config_zipf10m, motifs=THREE, delta=3600,
+        est=[(10, 0.01), (10, 0.1), (30, 0.01), (30, 0.1)],
+        desc="100k nodes, 10M edges, Zipf(1.8) endpoints, bursty Poisson times over [0,3e7) s; "
+             "all 36 three-edge motifs (32 three-node + 4 two-node), delta 3600; exact + estimates "
+             "at c in {10,30} x p in {0.01,0.1}, seed 0"),
+    "small": dict(
+        graph=ti.config_small, motifs=[ti.TRIANGLE], delta=3600, est=[(30, 0.1)],
+        desc="1k nodes, 20k uniform edges over [0,1e6), triangle, delta 3600, c 30, p 0.1, seed 0"),
+    "small_dense": dict(
+        graph=ti.config_small_dense, motifs=[ti.TRIANGLE], delta=3600, est=[(30, 0.1)],
+        desc="50 nodes, 20k uniform edges over [0,1e6), triangle, delta 3600, c 30, p 0.1, seed 0"),
 }
 
 
@@ -35,59 +62,149 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_baseline(g, motifs, delta, budget_s=15.0, seed=123, max_edges=3000):
+    """The oracle (single-threaded C brute force) on sampled windows of the
+    same graph: windows of length 2*delta around edges drawn uniformly (so
+    busy periods are sampled in proportion to their edges), skipping windows
+    above max_edges edges, every motif counted on each window, until the time
+    budget is spent.  Rate = window edges x motifs / seconds."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    tsort = np.sort(g.t)
+    order = np.argsort(g.t, kind="stable")
+    edges_done, secs, nwin, skipped = 0, 0.0, 0, 0
+    while secs < budget_s and nwin < 10000:
+        e = int(rng.integers(0, g.m))
+        lo = int(g.t[e]) - delta
+        hi = lo + 2 * delta - 1
+        a, b = np.searchsorted(tsort, lo), np.searchsorted(tsort, hi, side="right")
+        if b - a > max_edges or b - a == 0:
+            skipped += 1
+            continue
+        sel = order[a:b]
+        s, d, t = g.src[sel], g.dst[sel], g.t[sel]
+        t0 = time.perf_counter()
+        for M in motifs:
+            oracle.count(s, d, t, M, delta, hist=False)
+        secs += time.perf_counter() - t0
+        edges_done += b - a
+        nwin += 1
+    return {"value": edges_done * len(motifs) / secs, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nwin} windows of 2*delta around uniformly drawn edges ({edges_done} edges, windows over "
+                      f"{max_edges} edges skipped: {skipped}), {len(motifs)} motifs each, single-threaded C brute "
+                      f"force, {secs:.1f} s"}
+
+
+def traffic_record():
+    """HBM traffic of the dominant kernel from the committed rocprofv3 --pmc
+    summary, valid only while the kernel source is unchanged."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = json.load(open(TRAFFIC_FILE))
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if rec.get("kernel_src_sha256") != sha:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="small")
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="zipf10m", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design "
-              "note, not an implemented path", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU sharding of "
+              "windows is a design, not a path this build runs)", file=sys.stderr)
         sys.exit(2)
+    if int(os.environ.get("RANK", "0")) != 0:
+        return
 
     import torch
     import paper_1810_00980_amd as tm
 
-    assert torch.cuda.is_available()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    fac, motifs, delta, est, desc = WORKLOADS[args.workload]
+    W = WORKLOADS[args.workload]
+    motifs, delta = W["motifs"], W["delta"]
     log("generating", args.workload)
-    g = fac()
+    g = W["graph"]()
     src, dst, t = (torch.from_numpy(a).cuda() for a in (g.src, g.dst, g.t))
     torch.cuda.synchronize()
 
-    def step():
+    if args.copy_calib:
+        x = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
+
+    def step(times):
+        t0 = time.perf_counter()
         G = tm.load_graph(src, dst, t, g.n)
+        t1 = time.perf_counter()
         exact = tm.count_exact_multi(G, motifs, delta)
+        t2 = time.perf_counter()
         ests = []
-        for (c, p) in est:
+        for (c, p) in W["est"]:
             z, _ = tm.estimate_multi(G, motifs, delta, c, p, 0)
             ests.append(z)
+        t3 = time.perf_counter()
         G.free()
+        if times is not None:
+            times["load"].append(t1 - t0)
+            times["exact"].append(t2 - t1)
+            times["est"].append(t3 - t2)
         return exact, ests
 
     for i in range(args.warmup):
-        step()
+        step(None)
         log("warmup", i)
+    tm.profile_reset()
+    tm.profile_enable(True)
+    times = {"load": [], "exact": [], "est": []}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        exact, ests = step()
-        log("step", i)
+        exact, ests = step(times)
+        log("step", i, f"{time.perf_counter() - t0:.2f}s")
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    q = len(motifs) * (1 + len(est))
-    value = g.m * q / dt
+    tm.profile_enable(False)
+    kms, kn = tm.profile_read(DOMINANT)
+
+    q = len(motifs) * (1 + len(W["est"]))
+    G = tm.load_graph(src, dst, t, g.n)
+    anchors, fwd, bwd = tm.sweep_census(G, delta)
+    G.free()
+    roofline = None
+    if kn > 0:
+        bytes_per_launch = 12 * (anchors + fwd)
+        avg_s = kms / kn / 1e3
+        ach = bytes_per_launch / avg_s / 1e9
+        roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": ach / HBM_PEAK_GBS, "traffic": traffic_record(),
+                    "kernel": DOMINANT, "avg_launch_ms": kms / kn, "launches": kn,
+                    "algorithmic_bytes_per_launch": bytes_per_launch,
+                    "census": {"anchors": anchors, "fwd_entries": fwd, "bwd_entries": bwd}}
     out = {
-        "metric": "temporal edges/s per motif query (exact & p=0.1 estimate)",
-        "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "metric": "temporal edges/s per motif query (exact & p=0.1 estimate) vs CPU",
+        "value": g.m * q / dt, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int64", "data": "synthetic",
-        "config": {"workload": desc, "m": g.m, "n": g.n, "queries_per_step": q},
+        "config": {"workload": W["desc"], "m": g.m, "n": g.n, "motif_queries_per_step": q},
+        "phases_ms": {k: 1e3 * float(np.mean(v)) for k, v in times.items()},
+        "exact_edges_per_s_per_query": g.m * len(motifs) / float(np.mean(times["exact"])),
+        "roofline": roofline,
     }
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(g, motifs, delta)
+        out["cpu_baseline"]["host_cpus"] = os.cpu_count()
     print(json.dumps(out), flush=True)
 
 

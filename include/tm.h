@@ -190,6 +190,27 @@ tm_status tm_estimate_batch(const tm_graph *g, const tm_motif *M, int64_t delta,
                             double p, int32_t n_seeds, const uint64_t *seeds, int32_t tile,
                             double *estimates, tm_u128 *kept_counts, void *hip_stream);
 
+/*
+ * Kernel timing (off by default).  When enabled, the library brackets its
+ * main kernel launches with HIP events on the caller's stream and adds the
+ * elapsed times per kernel name ("sweep3_fwd_count", "sweep3_bwd_count",
+ * "sweep3_fwd_weight", "sweep3_bwd_weight", "sweep3_fwd_hist",
+ * "sweep3_bwd_hist", "count_generic", "count_batch").  tm_profile_read
+ * returns the total milliseconds and the number of launches so far.
+ */
+tm_status tm_profile_enable(int32_t on);
+tm_status tm_profile_reset(void);
+tm_status tm_profile_read(const char *kernel, double *total_ms, int64_t *launches);
+
+/*
+ * Work census of the three-edge sweep over the whole graph: the number of
+ * anchors (incidence entries, two per non-self-loop edge) and the number of
+ * list entries the forward and backward sweeps scan at span delta.  Used to
+ * express kernel time as algorithmic bytes per second.
+ */
+tm_status tm_sweep_census(const tm_graph *g, int64_t delta, int64_t *anchors, int64_t *fwd_entries,
+                          int64_t *bwd_entries, void *hip_stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *tm_strerror(tm_status s);
 

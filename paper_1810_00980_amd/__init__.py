@@ -70,6 +70,10 @@ _SIGS = {
     "tm_estimate": [P, P, i64, i64, f64, u64, P, P, P],
     "tm_estimate_multi": [P, i32, P, i64, i64, f64, u64, P, P, P],
     "tm_estimate_batch": [P, P, i64, i64, f64, i32, P, i32, P, P, P],
+    "tm_profile_enable": [i32],
+    "tm_profile_reset": [],
+    "tm_profile_read": [ctypes.c_char_p, P, P],
+    "tm_sweep_census": [P, i64, P, P, P, P],
     "tm_strerror": [i32],
     "tm_version": [],
 }
@@ -261,6 +265,29 @@ def estimate_batch(g: Graph, edges, delta: int, c: int, p: float, seeds, tile: i
                                   P(s.ctypes.data), int(tile), P(est.ctypes.data), kc, _stream(stream)),
            "tm_estimate_batch")
     return est, [kc[i].value() for i in range(k)]
+
+
+def profile_enable(on: bool = True):
+    _check(_lib.tm_profile_enable(1 if on else 0), "tm_profile_enable")
+
+
+def profile_reset():
+    _check(_lib.tm_profile_reset(), "tm_profile_reset")
+
+
+def profile_read(kernel: str):
+    """(total milliseconds, launches) of a library kernel since the last reset."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(_lib.tm_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)), "tm_profile_read")
+    return ms.value, n.value
+
+
+def sweep_census(g: Graph, delta: int, stream=None):
+    """(anchors, forward-scanned entries, backward-scanned entries) of the exact sweep."""
+    a, f, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.tm_sweep_census(g.handle, int(delta), ctypes.byref(a), ctypes.byref(f), ctypes.byref(b),
+                                _stream(stream)), "tm_sweep_census")
+    return a.value, f.value, b.value
 
 
 def version() -> str:

@@ -6,8 +6,79 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
+
+// ---------------------------------------------------------------- profiling
+namespace {
+struct ProfEvent {
+    const char *name;
+    hipEvent_t a, b;
+};
+struct ProfState {
+    std::mutex mu;
+    bool on = false;
+    std::vector<ProfEvent> pending;
+    std::map<std::string, std::pair<double, int64_t>> total;
+};
+ProfState &prof() {
+    static ProfState s;
+    return s;
+}
+}  // namespace
+
+void *tm_prof_begin(const char *name, hipStream_t st) {
+    ProfState &P = prof();
+    {
+        std::lock_guard<std::mutex> lk(P.mu);
+        if (!P.on) return nullptr;
+    }
+    ProfEvent *e = new (std::nothrow) ProfEvent{name, nullptr, nullptr};
+    if (!e) return nullptr;
+    if (hipEventCreate(&e->a) != hipSuccess || hipEventCreate(&e->b) != hipSuccess ||
+        hipEventRecord(e->a, st) != hipSuccess) {
+        (void)hipGetLastError();
+        delete e;
+        return nullptr;
+    }
+    return e;
+}
+
+void tm_prof_end(void *token, hipStream_t st) {
+    if (!token) return;
+    ProfEvent *e = static_cast<ProfEvent *>(token);
+    if (hipEventRecord(e->b, st) != hipSuccess) {
+        (void)hipGetLastError();
+        delete e;
+        return;
+    }
+    ProfState &P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.pending.push_back(*e);
+    delete e;
+}
+
+void tm_prof_collect() {
+    ProfState &P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    for (ProfEvent &e : P.pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+            auto &t = P.total[e.name];
+            t.first += ms;
+            t.second += 1;
+        }
+        (void)hipGetLastError();
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    P.pending.clear();
+}
+
+tm_status tm_sweep_census_impl(const tm_graph *g, int64_t delta, int64_t *fwd, int64_t *bwd, hipStream_t st);
 
 namespace {
 
@@ -334,6 +405,7 @@ tm_status run_sweep(const tm_graph *g, uint64_t mask, int mode, int64_t delta, i
         }
     }
     TM_HIP(hipStreamSynchronize(st));
+    tm_prof_collect();
     return TM_OK;
 }
 
@@ -419,6 +491,7 @@ tm_status finish(tm_status s, hipStream_t st) {
         (void)hipStreamSynchronize(st);
         (void)hipGetLastError();
     }
+    tm_prof_collect();
     return s;
 }
 
@@ -624,6 +697,45 @@ extern "C" tm_status tm_count_window(const tm_graph *g, int32_t n_motifs, const 
         return TM_OK;
     };
     return finish(run(), st);
+}
+
+extern "C" tm_status tm_profile_enable(int32_t on) {
+    ProfState &P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.on = on != 0;
+    return TM_OK;
+}
+
+extern "C" tm_status tm_profile_reset(void) {
+    tm_prof_collect();
+    ProfState &P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.total.clear();
+    return TM_OK;
+}
+
+extern "C" tm_status tm_profile_read(const char *kernel, double *total_ms, int64_t *launches) {
+    if (!kernel || !total_ms || !launches) return TM_EINVAL;
+    tm_prof_collect();
+    ProfState &P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    auto it = P.total.find(kernel);
+    if (it == P.total.end()) {
+        *total_ms = 0.0;
+        *launches = 0;
+    } else {
+        *total_ms = it->second.first;
+        *launches = it->second.second;
+    }
+    return TM_OK;
+}
+
+extern "C" tm_status tm_sweep_census(const tm_graph *g, int64_t delta, int64_t *anchors, int64_t *fwd_entries,
+                                     int64_t *bwd_entries, void *hip_stream) {
+    if (!g || delta < 0 || !anchors || !fwd_entries || !bwd_entries) return TM_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    *anchors = 2 * g->m_nl;
+    return finish(tm_sweep_census_impl(g, delta, fwd_entries, bwd_entries, st), st);
 }
 
 extern "C" const char *tm_strerror(tm_status s) {

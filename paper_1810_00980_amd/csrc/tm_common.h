@@ -95,6 +95,21 @@ struct tm_graph {
     DevBuf inc_nd;   // uint32[2 m_nl]: other endpoint | (dir << 31)
     DevBuf inc_t;    // int64[2 m_nl]
 
+    // unordered pair hash (open addressing, linear probing): key
+    // (min << 32 | max), value the directed pair ids (min -> max, max -> min),
+    // -1 when absent
+    DevBuf ph_key;   // uint64[ph_cap], ~0 = empty
+    DevBuf ph_val;   // int32[2 ph_cap]
+    int64_t ph_cap = 0;
+    // per directed pair time buckets: bucket b of pair p covers times
+    // [t_first + b 2^shift, t_first + (b+1) 2^shift); pb_idx holds, per bucket,
+    // the index (relative to the pair's first entry) of its first entry, plus
+    // a sentinel equal to the pair's size
+    DevBuf pb_tfirst;  // int64[S]
+    DevBuf pb_meta;    // int32[2 S]: shift, number of buckets
+    DevBuf pb_off;     // int64[S]: first bucket of the pair in pb_idx
+    DevBuf pb_idx;     // int32[sum (nb + 1)]
+
     // reusable per-graph workspace for queries
     DevBuf ws;
     int64_t device_bytes = 0;
@@ -109,7 +124,13 @@ struct DevGraph {
     const int64_t *in_off; const int32_t *in_nbr; const int64_t *in_t;
     const int64_t *sp_off; const int32_t *sp_nbr; const int64_t *sp_beg; const int64_t *pr_t;
     const int64_t *inc_off; const uint32_t *inc_nd; const int64_t *inc_t;
+    const uint64_t *ph_key; const int32_t *ph_val; int64_t ph_cap;
+    const int64_t *pb_tfirst; const int32_t *pb_meta; const int64_t *pb_off; const int32_t *pb_idx;
 };
+
+__device__ inline uint64_t tm_pair_hash(uint64_t key, int64_t cap) {
+    return (key * 0x9E3779B97F4A7C15ull) >> (64 - __builtin_ctzll((unsigned long long)cap));
+}
 
 DevGraph dev_view(const tm_graph *g);
 
@@ -213,3 +234,13 @@ tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask, int mode, int64_t del
 
 // Largest delta for the sweep counter's histogram mode (36 histograms).
 #define TM_MAX_SWEEP_HIST_DELTA ((int64_t)1 << 20)
+
+// ------------------------------------------------------------ profiling
+
+// Opt-in kernel timing with HIP events recorded on the launch stream.
+// tm_prof_begin returns a token (nullptr when profiling is off) that
+// tm_prof_end closes; tm_prof_collect resolves finished events into the
+// per-kernel totals (call after the stream has been synchronised).
+void *tm_prof_begin(const char *name, hipStream_t st);
+void tm_prof_end(void *token, hipStream_t st);
+void tm_prof_collect();

@@ -221,9 +221,12 @@ tm_status launch_len(const DevGraph &G, const MotifPlan &P, int64_t delta, const
     if (n <= 0) return TM_OK;
     unsigned nb = tm_blocks(n, CG_TPB);
     if (nb > 65535u * 4) nb = 65535u * 4;
+    void *tok = tm_prof_begin("count_generic", st);
     hipLaunchKernelGGL((k_count_generic<LEN, HIST>), dim3(nb), dim3(CG_TPB), 0, st, G, P, delta, A, total,
                        slot_tot, hlo, hhi, per_anchor, flag);
-    return tm_hip_status(hipGetLastError());
+    tm_status s = tm_hip_status(hipGetLastError());
+    tm_prof_end(tok, st);
+    return s;
 }
 
 __global__ void k_weight(const uint64_t *hlo, const uint64_t *hhi, int64_t delta, int64_t L, double p, double *out) {

@@ -160,6 +160,87 @@ __global__ void k_inc_fill(const uint32_t *vals, int64_t len, const int64_t *nl_
     }
 }
 
+
+__global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// source node of directed pair p: largest u with sp_off[u] <= p
+__device__ inline int32_t pair_src(const int64_t *sp_off, int64_t n, int64_t p) {
+    int64_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (sp_off[mid] <= p) lo = mid;
+        else hi = mid;
+    }
+    return (int32_t)lo;
+}
+
+__global__ void k_pair_hash_insert(const int64_t *sp_off, const int32_t *sp_nbr, int64_t S, int64_t n, uint64_t *keys,
+                                   int32_t *vals, int64_t cap) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= S) return;
+    uint32_t u = (uint32_t)pair_src(sp_off, n, p), v = (uint32_t)sp_nbr[p];
+    uint32_t a = u < v ? u : v, b = u < v ? v : u;
+    uint64_t key = ((uint64_t)a << 32) | b;
+    uint64_t h = tm_pair_hash(key, cap);
+    for (int64_t probe = 0; probe < cap; ++probe) {
+        unsigned long long prev = atomicCAS((unsigned long long *)&keys[h], ~0ull, (unsigned long long)key);
+        if (prev == ~0ull || prev == key) {
+            vals[2 * h + (u < v ? 0 : 1)] = (int32_t)p;
+            return;
+        }
+        h = (h + 1) & (uint64_t)(cap - 1);
+    }
+}
+
+// per pair: first time, bucket shift (about two entries per bucket), count
+__global__ void k_pair_bucket_meta(const int64_t *sp_beg, const int64_t *pr_t, int64_t S, int64_t *tfirst,
+                                   int32_t *meta, int64_t *nbk) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= S) return;
+    int64_t b = sp_beg[p], e = sp_beg[p + 1], k = e - b;
+    int64_t t0 = pr_t[b], span = pr_t[e - 1] - t0;
+    int64_t target = k / 2 > 1 ? k / 2 : 1;  // buckets wanted
+    int shift = 0;
+    while (shift < 62 && (span >> shift) + 1 > target) ++shift;
+    int64_t nb = (span >> shift) + 1;
+    tfirst[p] = t0;
+    meta[2 * p] = shift;
+    meta[2 * p + 1] = (int32_t)nb;
+    nbk[p] = nb + 1;  // with sentinel
+}
+
+// entry i of pair p is the first entry of buckets (bucket(i-1), bucket(i)]
+__global__ void k_pair_bucket_fill(const int64_t *sp_off, const int32_t *sp_nbr, const int64_t *sp_beg,
+                                   const int64_t *pr_t, int64_t S, int64_t m_nl, const int64_t *tfirst,
+                                   const int32_t *meta, const int64_t *boff, int32_t *bidx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m_nl) return;
+    // pair of entry i: largest p with sp_beg[p] <= i
+    int64_t lo = 0, hi = S;
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (sp_beg[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    int64_t p = lo, b0 = sp_beg[p], k = sp_beg[p + 1] - b0, r = i - b0;
+    int shift = meta[2 * p];
+    int32_t nb = meta[2 * p + 1];
+    int64_t bi = (pr_t[i] - tfirst[p]) >> shift;
+    int64_t bprev = r == 0 ? -1 : ((pr_t[i - 1] - tfirst[p]) >> shift);
+    for (int64_t bb = bprev + 1; bb <= bi; ++bb) bidx[boff[p] + bb] = (int32_t)r;
+    if (r == k - 1) bidx[boff[p] + nb] = (int32_t)k;  // sentinel (bi == nb - 1 here)
+    (void)sp_off;
+    (void)sp_nbr;
+}
+
 tm_status build_node_lists(tm_graph *g, const int64_t *nl_pos, bool by_src, DevBuf &off, DevBuf &nbr, DevBuf &tl,
                            hipStream_t st) {
     int64_t mn = g->m_nl, n = g->n;
@@ -316,6 +397,46 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
         TM_HIP(hipStreamSynchronize(st));
     }
 
+    // pair hash and per-pair time buckets
+    {
+        int64_t S = g->S, n = g->n;
+        int64_t cap = 1024;
+        while (cap < 2 * S) cap <<= 1;
+        g->ph_cap = cap;
+        TM_TRY(g->ph_key.alloc((size_t)cap * 8));
+        TM_TRY(g->ph_val.alloc((size_t)cap * 8));
+        hipLaunchKernelGGL(k_fill_u64, dim3(tm_blocks(cap, TPB)), dim3(TPB), 0, st, g->ph_key.as<uint64_t>(), cap, ~0ull);
+        TM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_fill_i32, dim3(tm_blocks(2 * cap, TPB)), dim3(TPB), 0, st, g->ph_val.as<int32_t>(), 2 * cap,
+                           (int32_t)-1);
+        TM_HIP(hipGetLastError());
+        TM_TRY(g->pb_tfirst.alloc((size_t)S * 8));
+        TM_TRY(g->pb_meta.alloc((size_t)S * 8));
+        TM_TRY(g->pb_off.alloc((size_t)(S + 1) * 8));
+        int64_t nbk_total = 0;
+        if (S > 0) {
+            hipLaunchKernelGGL(k_pair_hash_insert, dim3(tm_blocks(S, TPB)), dim3(TPB), 0, st, g->sp_off.as<int64_t>(),
+                               g->sp_nbr.as<int32_t>(), S, n, g->ph_key.as<uint64_t>(), g->ph_val.as<int32_t>(), cap);
+            TM_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_pair_bucket_meta, dim3(tm_blocks(S, TPB)), dim3(TPB), 0, st, g->sp_beg.as<int64_t>(),
+                               g->pr_t.as<int64_t>(), S, g->pb_tfirst.as<int64_t>(), g->pb_meta.as<int32_t>(),
+                               g->pb_off.as<int64_t>());
+            TM_HIP(hipGetLastError());
+            TM_TRY(tm_scan_i64(g->pb_off.as<int64_t>(), S, cnt.as<int64_t>(), st));
+            TM_HIP(hipMemcpyAsync(&nbk_total, cnt.p, 8, hipMemcpyDeviceToHost, st));
+            TM_HIP(hipStreamSynchronize(st));
+        }
+        TM_TRY(g->pb_idx.alloc((size_t)(nbk_total > 0 ? nbk_total : 1) * 4));
+        if (S > 0) {
+            hipLaunchKernelGGL(k_pair_bucket_fill, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, g->sp_off.as<int64_t>(),
+                               g->sp_nbr.as<int32_t>(), g->sp_beg.as<int64_t>(), g->pr_t.as<int64_t>(), S, m_nl,
+                               g->pb_tfirst.as<int64_t>(), g->pb_meta.as<int32_t>(), g->pb_off.as<int64_t>(),
+                               g->pb_idx.as<int32_t>());
+            TM_HIP(hipGetLastError());
+        }
+        TM_HIP(hipStreamSynchronize(st));
+    }
+
     // combined incidence lists
     {
         int64_t len = 2 * m_nl, n = g->n;
@@ -342,7 +463,8 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
     }
     const DevBuf *all[] = {&g->es_src, &g->es_dst, &g->es_t, &g->pos_of, &g->out_off, &g->out_nbr, &g->out_t,
                            &g->in_off, &g->in_nbr, &g->in_t, &g->sp_off, &g->sp_nbr, &g->sp_beg, &g->pr_t,
-                           &g->inc_off, &g->inc_nd, &g->inc_t};
+                           &g->inc_off, &g->inc_nd, &g->inc_t, &g->ph_key, &g->ph_val, &g->pb_tfirst,
+                           &g->pb_meta, &g->pb_off, &g->pb_idx};
     int64_t tot = 0;
     for (const DevBuf *b : all) tot += (int64_t)b->bytes;
     g->device_bytes = tot;
@@ -360,6 +482,9 @@ DevGraph dev_view(const tm_graph *g) {
     v.sp_off = g->sp_off.as<int64_t>(); v.sp_nbr = g->sp_nbr.as<int32_t>(); v.sp_beg = g->sp_beg.as<int64_t>();
     v.pr_t = g->pr_t.as<int64_t>();
     v.inc_off = g->inc_off.as<int64_t>(); v.inc_nd = g->inc_nd.as<uint32_t>(); v.inc_t = g->inc_t.as<int64_t>();
+    v.ph_key = g->ph_key.as<uint64_t>(); v.ph_val = g->ph_val.as<int32_t>(); v.ph_cap = g->ph_cap;
+    v.pb_tfirst = g->pb_tfirst.as<int64_t>(); v.pb_meta = g->pb_meta.as<int32_t>(); v.pb_off = g->pb_off.as<int64_t>();
+    v.pb_idx = g->pb_idx.as<int32_t>();
     return v;
 }
 

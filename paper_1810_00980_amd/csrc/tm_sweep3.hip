@@ -91,31 +91,50 @@ __device__ inline int64_t owner_of(const int64_t *off, int64_t n, int64_t i) {
     return lo;
 }
 
-// number of entries of pair (u -> v) with tlo < t < thi
-__device__ inline uint64_t pair_between(const DevGraph &G, uint32_t u, uint32_t v, int64_t tlo, int64_t thi) {
-    int64_t lo = G.sp_off[u], hi = G.sp_off[u + 1];
+// number of entries of directed pair p with time < t
+__device__ inline int64_t pair_before(const DevGraph &G, int32_t p, int64_t t) {
+    int64_t t0 = G.pb_tfirst[p];
+    if (t <= t0) return 0;
+    int shift = G.pb_meta[2 * p];
+    int64_t nb = G.pb_meta[2 * p + 1];
+    int64_t b = (t - t0) >> shift;
+    int64_t base = G.sp_beg[p];
+    if (b >= nb) return G.sp_beg[p + 1] - base;
+    const int32_t *bi = G.pb_idx + G.pb_off[p];
+    int64_t lo = bi[b], hi = bi[b + 1];
     while (lo < hi) {
         int64_t mid = (lo + hi) >> 1;
-        if ((uint32_t)G.sp_nbr[mid] < v) lo = mid + 1;
+        if (G.pr_t[base + mid] < t) lo = mid + 1;
         else hi = mid;
     }
-    if (lo >= G.sp_off[u + 1] || (uint32_t)G.sp_nbr[lo] != v) return 0;
-    int64_t b = G.sp_beg[lo], e = G.sp_beg[lo + 1];
-    // first entry with t > tlo
-    int64_t a0 = b, a1 = e;
-    while (a0 < a1) {
-        int64_t mid = (a0 + a1) >> 1;
-        if (G.pr_t[mid] <= tlo) a0 = mid + 1;
-        else a1 = mid;
+    return lo;
+}
+
+// directed pair ids (u -> v, v -> u) of the unordered pair {u, v}; -1 if absent
+__device__ inline void pair_ids(const DevGraph &G, uint32_t u, uint32_t v, int32_t *puv, int32_t *pvu) {
+    uint32_t a = u < v ? u : v, b = u < v ? v : u;
+    uint64_t key = ((uint64_t)a << 32) | b;
+    int64_t cap = G.ph_cap;
+    uint64_t h = tm_pair_hash(key, cap);
+    *puv = -1;
+    *pvu = -1;
+    for (int64_t probe = 0; probe < cap; ++probe) {
+        uint64_t k = G.ph_key[h];
+        if (k == key) {
+            int32_t f = G.ph_val[2 * h], r = G.ph_val[2 * h + 1];  // a -> b, b -> a
+            *puv = u < v ? f : r;
+            *pvu = u < v ? r : f;
+            return;
+        }
+        if (k == ~0ull) return;
+        h = (h + 1) & (uint64_t)(cap - 1);
     }
-    // first entry with t >= thi
-    int64_t c0 = a0, c1 = e;
-    while (c0 < c1) {
-        int64_t mid = (c0 + c1) >> 1;
-        if (G.pr_t[mid] < thi) c0 = mid + 1;
-        else c1 = mid;
-    }
-    return (uint64_t)(c0 - a0);
+}
+
+// entries of pair p with tlo < t < thi
+__device__ inline uint64_t pair_between_id(const DevGraph &G, int32_t p, int64_t tlo, int64_t thi) {
+    if (p < 0) return 0;
+    return (uint64_t)(pair_before(G, p, thi) - pair_before(G, p, tlo + 1));
 }
 
 // Per-lane accumulator of up to 16 motif codes.
@@ -228,8 +247,10 @@ __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t 
                 acc_add<MODE, 16>(A, 10, dj, cs1, w, a.hist, 14 + 4 * (int)d1, dlt, a.delta);
             }
             if (tri) {
-                uint64_t c01 = pair_between(G, y1, yj, t1, tj);
-                uint64_t c10 = pair_between(G, yj, y1, t1, tj);
+                int32_t p01, p10;
+                pair_ids(G, y1, yj, &p01, &p10);
+                uint64_t c01 = pair_between_id(G, p01, t1, tj);
+                uint64_t c10 = pair_between_id(G, p10, t1, tj);
                 acc_add<MODE, 16>(A, 12, dj, c01, w, a.hist, 20 + 4 * (int)d1, dlt, a.delta);
                 acc_add<MODE, 16>(A, 14, dj, c10, w, a.hist, 22 + 4 * (int)d1, dlt, a.delta);
             }
@@ -388,22 +409,89 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, hipStr
     int64_t nb = (int64_t)ncu * 8;
     if (nb > want_blocks) nb = want_blocks;
     if (nb < 1) nb = 1;
+    static const char *names[3][2] = {{"sweep3_fwd_count", "sweep3_bwd_count"},
+                                      {"sweep3_fwd_weight", "sweep3_bwd_weight"},
+                                      {"sweep3_fwd_hist", "sweep3_bwd_hist"}};
     if (fwd) {
         TM_HIP(hipMemsetAsync(a.counter, 0, 8, st));
+        void *tok = tm_prof_begin(names[MODE][0], st);
         hipLaunchKernelGGL((k_sweep3<MODE, true>), dim3((unsigned)nb), dim3(SW_TPB), 0, st, G, a);
         TM_HIP(hipGetLastError());
+        tm_prof_end(tok, st);
     }
     if (bwd) {
         TM_HIP(hipMemsetAsync(a.counter + 1, 0, 8, st));
         SweepArgs b = a;
         b.counter = a.counter + 1;
+        void *tok = tm_prof_begin(names[MODE][1], st);
         hipLaunchKernelGGL((k_sweep3<MODE, false>), dim3((unsigned)nb), dim3(SW_TPB), 0, st, G, b);
         TM_HIP(hipGetLastError());
+        tm_prof_end(tok, st);
     }
     return TM_OK;
 }
 
+// entries scanned by the forward and backward sweeps of every anchor
+__global__ void k_census(DevGraph G, int64_t delta, unsigned long long *out) {
+    __shared__ unsigned long long sf[SW_TPB], sb[SW_TPB];
+    unsigned long long f = 0, b = 0;
+    int64_t nE = 2 * G.m_nl;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nE; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t x = owner_of(G.inc_off, G.n, i);
+        int64_t lb = G.inc_off[x], le = G.inc_off[x + 1];
+        int64_t t = G.inc_t[i];
+        int64_t hi = (t > LLONG_MAX - delta) ? LLONG_MAX : t + delta;
+        int64_t lo = (t < LLONG_MIN + delta) ? LLONG_MIN : t - delta;
+        int64_t a0 = i + 1, a1 = le;  // first entry after i with time > hi
+        while (a0 < a1) {
+            int64_t mid = (a0 + a1) >> 1;
+            if (G.inc_t[mid] <= hi) a0 = mid + 1;
+            else a1 = mid;
+        }
+        int64_t c0 = lb, c1 = i;  // first entry with time >= lo
+        while (c0 < c1) {
+            int64_t mid = (c0 + c1) >> 1;
+            if (G.inc_t[mid] < lo) c0 = mid + 1;
+            else c1 = mid;
+        }
+        f += (unsigned long long)(a0 - i - 1);
+        b += (unsigned long long)(i - c0);
+    }
+    sf[threadIdx.x] = f;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = SW_TPB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sf[threadIdx.x] += sf[threadIdx.x + s];
+            sb[threadIdx.x] += sb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(&out[0], sf[0]);
+        atomicAdd(&out[1], sb[0]);
+    }
+}
+
 }  // namespace
+
+tm_status tm_sweep_census_impl(const tm_graph *g, int64_t delta, int64_t *fwd, int64_t *bwd, hipStream_t st) {
+    DevBuf o;
+    TM_TRY(o.alloc(64));
+    TM_HIP(hipMemsetAsync(o.p, 0, 16, st));
+    if (g->m_nl > 0) {
+        unsigned nb = tm_blocks(2 * g->m_nl, SW_TPB);
+        if (nb > 8192) nb = 8192;
+        hipLaunchKernelGGL(k_census, dim3(nb), dim3(SW_TPB), 0, st, dev_view(g), delta, o.as<unsigned long long>());
+        TM_HIP(hipGetLastError());
+    }
+    int64_t h[2];
+    TM_HIP(hipMemcpyAsync(h, o.p, 16, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipStreamSynchronize(st));
+    *fwd = h[0];
+    *bwd = h[1];
+    return TM_OK;
+}
 
 // Motif of each of the 36 codes, in canonical form.
 void tm_sweep_code_motif(int code, tm_motif *M) {
