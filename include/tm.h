@@ -179,16 +179,31 @@ tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, const tm_motif 
                             tm_u128 *kept_counts, void *hip_stream);
 
 /*
- * Batched estimator: n_seeds independent estimates (one shift and one set
- * of window draws per seed, Algorithm 1's outer loop run as independent
- * estimators) of one motif, all sampled windows of all seeds counted in one
- * persistent launch whose work-groups take anchor tiles from a shared queue.
- * estimates[k] for seeds[k].  Each estimate equals tm_estimate with that
- * seed.  tile = anchors per queue item (0: autotuned).
+ * Batched estimator: n_seeds independent estimates of one motif (each seed
+ * draws its own shift and window samples, Algorithm 1's loop over shifts run
+ * as separate estimators); estimates[k] equals tm_estimate with seeds[k].
+ * For the 36 three-edge motifs all kept windows of all seeds are counted in
+ * one persistent launch: node-aligned tiles of at most `tile` anchors are
+ * queued per (seed, tile) that meets a kept window, and resident
+ * work-groups take tasks from the shared queue (work stealing).  The kernel
+ * sequence is captured once as a hipGraph per (graph, motif, delta, c, p,
+ * n_seeds, tile, grid) and replayed with the new seeds.  tile = 0 uses the
+ * autotuned tile and grid (tm_batch_config).  Other motifs run seed by seed.
+ * kept_counts (nullable) receives each seed's exact count over its kept
+ * windows.  Plans are cached with the graph and released by tm_free_graph.
  */
 tm_status tm_estimate_batch(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t c,
                             double p, int32_t n_seeds, const uint64_t *seeds, int32_t tile,
                             double *estimates, tm_u128 *kept_counts, void *hip_stream);
+
+/*
+ * Autotuner of the batched estimator: times candidate tile sizes
+ * {256, 1024, 4096} and resident work-groups per CU {2, 4, 8} on 8 seeds and
+ * returns (and caches for the graph) the fastest pair.  Three-edge motifs
+ * only (TM_EUNSUPPORTED otherwise).
+ */
+tm_status tm_batch_config(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t c, double p,
+                          int32_t *tile, int32_t *blocks_per_cu, void *hip_stream);
 
 /*
  * Kernel timing (off by default).  When enabled, the library brackets its

@@ -70,6 +70,7 @@ _SIGS = {
     "tm_estimate": [P, P, i64, i64, f64, u64, P, P, P],
     "tm_estimate_multi": [P, i32, P, i64, i64, f64, u64, P, P, P],
     "tm_estimate_batch": [P, P, i64, i64, f64, i32, P, i32, P, P, P],
+    "tm_batch_config": [P, P, i64, i64, f64, P, P, P],
     "tm_profile_enable": [i32],
     "tm_profile_reset": [],
     "tm_profile_read": [ctypes.c_char_p, P, P],
@@ -288,6 +289,14 @@ def sweep_census(g: Graph, delta: int, stream=None):
     _check(_lib.tm_sweep_census(g.handle, int(delta), ctypes.byref(a), ctypes.byref(f), ctypes.byref(b),
                                 _stream(stream)), "tm_sweep_census")
     return a.value, f.value, b.value
+
+
+def batch_config(g: Graph, edges, delta: int, c: int, p: float, stream=None):
+    """Autotuned (tile, work-groups per CU) of the batched estimator."""
+    t, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.tm_batch_config(g.handle, ctypes.byref(motif(edges)), int(delta), int(c), float(p),
+                                ctypes.byref(t), ctypes.byref(b), _stream(stream)), "tm_batch_config")
+    return t.value, b.value
 
 
 def version() -> str:

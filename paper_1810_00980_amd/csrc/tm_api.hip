@@ -624,14 +624,46 @@ extern "C" tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, cons
 extern "C" tm_status tm_estimate_batch(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t c, double p,
                                        int32_t n_seeds, const uint64_t *seeds, int32_t tile, double *estimates,
                                        tm_u128 *kept_counts, void *hip_stream) {
-    (void)tile;
-    if (!g || n_seeds < 0 || (n_seeds > 0 && (!seeds || !estimates))) return TM_EINVAL;
+    if (!g || !M || n_seeds < 0 || (n_seeds > 0 && (!seeds || !estimates)) || tile < 0) return TM_EINVAL;
+    MotifPlan P;
+    TM_TRY(check_graph_motif(g, M, delta, &P));
+    int64_t L;
+    TM_TRY(check_est_args(g, delta, c, p, &L));
+    hipStream_t st = (hipStream_t)hip_stream;
+    int code = tm_sweep_code_of(M);
+    int64_t J = 1 + g->t_span / L + ((g->t_span % L) ? 1 : 0);
+    if (code >= 0 && n_seeds > 0 && (J + 1) * (int64_t)n_seeds <= ((int64_t)1 << 28)) {
+        auto run = [&]() -> tm_status {
+            int64_t t = tile, b = 4;
+            if (t == 0) TM_TRY(tm_batch_tune(g, code, delta, L, p, &t, &b, st));
+            return tm_batch_run(g, code, delta, L, p, n_seeds, seeds, t, b, estimates, kept_counts, st);
+        };
+        return finish(run(), st);
+    }
     for (int32_t i = 0; i < n_seeds; ++i) {
         tm_est_info info;
         memset(&info, 0, sizeof info);
         TM_TRY(tm_estimate(g, M, delta, c, p, seeds[i], &estimates[i], kept_counts ? &info : nullptr, hip_stream));
         if (kept_counts) kept_counts[i] = info.kept_count;
     }
+    return TM_OK;
+}
+
+extern "C" tm_status tm_batch_config(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t c, double p,
+                                     int32_t *tile, int32_t *blocks_per_cu, void *hip_stream) {
+    if (!g || !M || !tile || !blocks_per_cu) return TM_EINVAL;
+    MotifPlan P;
+    TM_TRY(check_graph_motif(g, M, delta, &P));
+    int64_t L;
+    TM_TRY(check_est_args(g, delta, c, p, &L));
+    int code = tm_sweep_code_of(M);
+    if (code < 0) return TM_EUNSUPPORTED;
+    hipStream_t st = (hipStream_t)hip_stream;
+    int64_t t = 0, b = 0;
+    tm_status s = finish(g->m_nl > 0 ? tm_batch_tune(g, code, delta, L, p, &t, &b, st) : TM_OK, st);
+    if (s != TM_OK) return s;
+    *tile = (int32_t)t;
+    *blocks_per_cu = (int32_t)b;
     return TM_OK;
 }
 

@@ -94,6 +94,7 @@ struct tm_graph {
     DevBuf inc_off;  // int64[n+1]
     DevBuf inc_nd;   // uint32[2 m_nl]: other endpoint | (dir << 31)
     DevBuf inc_t;    // int64[2 m_nl]
+    DevBuf inc_twin; // uint32[2 m_nl]: position of the same edge in its other endpoint's list
 
     // unordered pair hash (open addressing, linear probing): key
     // (min << 32 | max), value the directed pair ids (min -> max, max -> min),
@@ -123,7 +124,7 @@ struct DevGraph {
     const int64_t *out_off; const int32_t *out_nbr; const int64_t *out_t;
     const int64_t *in_off; const int32_t *in_nbr; const int64_t *in_t;
     const int64_t *sp_off; const int32_t *sp_nbr; const int64_t *sp_beg; const int64_t *pr_t;
-    const int64_t *inc_off; const uint32_t *inc_nd; const int64_t *inc_t;
+    const int64_t *inc_off; const uint32_t *inc_nd; const int64_t *inc_t; const uint32_t *inc_twin;
     const uint64_t *ph_key; const int32_t *ph_val; int64_t ph_cap;
     const int64_t *pb_tfirst; const int32_t *pb_meta; const int64_t *pb_off; const int32_t *pb_idx;
 };
@@ -244,3 +245,15 @@ tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask, int mode, int64_t del
 void *tm_prof_begin(const char *name, hipStream_t st);
 void tm_prof_end(void *token, hipStream_t st);
 void tm_prof_collect();
+
+// ------------------------------------------------------------ batching
+
+// Batched estimates of one three-edge motif (sweep code) for n_seeds seeds in
+// one persistent, hipGraph-captured launch (see tm_batch.hip).
+tm_status tm_batch_run(const tm_graph *g, int32_t code, int64_t delta, int64_t L, double p, int64_t n_seeds,
+                       const uint64_t *seeds, int64_t tile, int64_t bpc, double *est, tm_u128 *kept,
+                       hipStream_t st);
+// Autotuned (tile, work-groups per CU) for the batched estimator.
+tm_status tm_batch_tune(const tm_graph *g, int32_t code, int64_t delta, int64_t L, double p, int64_t *tile,
+                        int64_t *bpc, hipStream_t st);
+void tm_batch_forget(const tm_graph *g);

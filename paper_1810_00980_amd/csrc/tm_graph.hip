@@ -147,6 +147,14 @@ __global__ void k_inc_keys(const int64_t *nl_pos, int64_t m_nl, const int32_t *e
     }
 }
 
+__global__ void k_inc_twin(const uint32_t *vals, int64_t len, uint32_t *posv, uint32_t *twin, int pass) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= len) return;
+    uint32_t v = vals[j];
+    if (pass == 0) posv[v] = (uint32_t)j;
+    else twin[j] = posv[v ^ 1u];
+}
+
 __global__ void k_inc_fill(const uint32_t *vals, int64_t len, const int64_t *nl_pos, const int32_t *es_src,
                            const int32_t *es_dst, const int64_t *es_t, uint32_t *nd, int64_t *tl) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -445,6 +453,7 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
         TM_TRY(iv.alloc((size_t)len * 4));
         TM_TRY(g->inc_nd.alloc((size_t)len * 4));
         TM_TRY(g->inc_t.alloc((size_t)len * 8));
+        TM_TRY(g->inc_twin.alloc((size_t)len * 4));
         TM_TRY(g->inc_off.alloc((size_t)(n + 1) * 8));
         if (m_nl > 0) {
             hipLaunchKernelGGL(k_inc_keys, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, nl.as<int64_t>(), m_nl,
@@ -455,6 +464,14 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
                                nl.as<int64_t>(), g->es_src.as<int32_t>(), g->es_dst.as<int32_t>(),
                                g->es_t.as<int64_t>(), g->inc_nd.as<uint32_t>(), g->inc_t.as<int64_t>());
             TM_HIP(hipGetLastError());
+            DevBuf posv;
+            TM_TRY(posv.alloc((size_t)len * 4));
+            for (int pass = 0; pass < 2; ++pass) {
+                hipLaunchKernelGGL(k_inc_twin, dim3(tm_blocks(len, TPB)), dim3(TPB), 0, st, iv.as<uint32_t>(), len,
+                                   posv.as<uint32_t>(), g->inc_twin.as<uint32_t>(), pass);
+                TM_HIP(hipGetLastError());
+            }
+            TM_HIP(hipStreamSynchronize(st));
         }
         hipLaunchKernelGGL(k_lower_bound, dim3(tm_blocks(n + 1, TPB)), dim3(TPB), 0, st, ik.as<uint64_t>(), len, n,
                            (uint64_t)1, g->inc_off.as<int64_t>());
@@ -463,7 +480,7 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
     }
     const DevBuf *all[] = {&g->es_src, &g->es_dst, &g->es_t, &g->pos_of, &g->out_off, &g->out_nbr, &g->out_t,
                            &g->in_off, &g->in_nbr, &g->in_t, &g->sp_off, &g->sp_nbr, &g->sp_beg, &g->pr_t,
-                           &g->inc_off, &g->inc_nd, &g->inc_t, &g->ph_key, &g->ph_val, &g->pb_tfirst,
+                           &g->inc_off, &g->inc_nd, &g->inc_t, &g->inc_twin, &g->ph_key, &g->ph_val, &g->pb_tfirst,
                            &g->pb_meta, &g->pb_off, &g->pb_idx};
     int64_t tot = 0;
     for (const DevBuf *b : all) tot += (int64_t)b->bytes;
@@ -482,6 +499,7 @@ DevGraph dev_view(const tm_graph *g) {
     v.sp_off = g->sp_off.as<int64_t>(); v.sp_nbr = g->sp_nbr.as<int32_t>(); v.sp_beg = g->sp_beg.as<int64_t>();
     v.pr_t = g->pr_t.as<int64_t>();
     v.inc_off = g->inc_off.as<int64_t>(); v.inc_nd = g->inc_nd.as<uint32_t>(); v.inc_t = g->inc_t.as<int64_t>();
+    v.inc_twin = g->inc_twin.as<uint32_t>();
     v.ph_key = g->ph_key.as<uint64_t>(); v.ph_val = g->ph_val.as<int32_t>(); v.ph_cap = g->ph_cap;
     v.pb_tfirst = g->pb_tfirst.as<int64_t>(); v.pb_meta = g->pb_meta.as<int32_t>(); v.pb_off = g->pb_off.as<int64_t>();
     v.pb_idx = g->pb_idx.as<int32_t>();
@@ -508,6 +526,7 @@ extern "C" tm_status tm_load_graph(const int32_t *src, const int32_t *dst, const
 extern "C" void tm_free_graph(tm_graph *g) {
     if (!g) return;
     (void)hipDeviceSynchronize();
+    tm_batch_forget(g);
     delete g;
 }
 

@@ -35,288 +35,11 @@
 
 #include <limits.h>
 
+#include "tm_sweep_dev.h"
+
 namespace {
 
-constexpr int SW_TPB = 256;
-constexpr int SW_WAVES = SW_TPB / TM_WAVE;
-
-enum : int { MODE_COUNT = 0, MODE_WEIGHT = 1, MODE_HIST = 2 };
-
-struct SweepArgs {
-    int64_t delta;
-    // windows (estimate): anchor kept when its window's draw is below p
-    int32_t windowed;      // 0 none, 1 kept windows of (s, L, seed, p), 2 one window [s, L]
-    int64_t s, L;
-    uint64_t seed;
-    double p;
-    const uint64_t *wfx;   // delta+1 fixed-point weights (MODE_WEIGHT)
-    uint64_t *hist;        // 36 x (delta+1) x {lo, hi} (MODE_HIST)
-    uint64_t *out;         // 36 x {count lo, count hi, weight lo, weight hi}
-    int64_t *counter;      // work queue head
-    uint32_t want_fwd;     // bit mask: 1 two-node, 2 star B, 4 star A, 8 triangle
-    int64_t n_entries;
-};
-
-__device__ inline void philox10_d(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3, uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        uint64_t a = (uint64_t)0xD2511F53u * x0;
-        uint64_t b = (uint64_t)0xCD9E8D57u * x2;
-        uint32_t y0 = (uint32_t)(b >> 32) ^ x1 ^ k0;
-        uint32_t y2 = (uint32_t)(a >> 32) ^ x3 ^ k1;
-        x1 = (uint32_t)b;
-        x3 = (uint32_t)a;
-        x0 = y0;
-        x2 = y2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
-__device__ inline bool keep_window(uint64_t seed, uint64_t j, double p) {
-    uint32_t x0 = (uint32_t)j, x1 = (uint32_t)(j >> 32), x2 = 0, x3 = 1;
-    philox10_d(x0, x1, x2, x3, (uint32_t)seed, (uint32_t)(seed >> 32));
-    uint64_t x = ((uint64_t)x1 << 32) | (uint64_t)x0;
-    return (double)(x >> 11) * (1.0 / 9007199254740992.0) < p;
-}
-
-__device__ inline int64_t owner_of(const int64_t *off, int64_t n, int64_t i) {
-    // largest x with off[x] <= i
-    int64_t lo = 0, hi = n;  // off[0] = 0 <= i < off[n]
-    while (hi - lo > 1) {
-        int64_t mid = (lo + hi) >> 1;
-        if (off[mid] <= i) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// number of entries of directed pair p with time < t
-__device__ inline int64_t pair_before(const DevGraph &G, int32_t p, int64_t t) {
-    int64_t t0 = G.pb_tfirst[p];
-    if (t <= t0) return 0;
-    int shift = G.pb_meta[2 * p];
-    int64_t nb = G.pb_meta[2 * p + 1];
-    int64_t b = (t - t0) >> shift;
-    int64_t base = G.sp_beg[p];
-    if (b >= nb) return G.sp_beg[p + 1] - base;
-    const int32_t *bi = G.pb_idx + G.pb_off[p];
-    int64_t lo = bi[b], hi = bi[b + 1];
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (G.pr_t[base + mid] < t) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// directed pair ids (u -> v, v -> u) of the unordered pair {u, v}; -1 if absent
-__device__ inline void pair_ids(const DevGraph &G, uint32_t u, uint32_t v, int32_t *puv, int32_t *pvu) {
-    uint32_t a = u < v ? u : v, b = u < v ? v : u;
-    uint64_t key = ((uint64_t)a << 32) | b;
-    int64_t cap = G.ph_cap;
-    uint64_t h = tm_pair_hash(key, cap);
-    *puv = -1;
-    *pvu = -1;
-    for (int64_t probe = 0; probe < cap; ++probe) {
-        uint64_t k = G.ph_key[h];
-        if (k == key) {
-            int32_t f = G.ph_val[2 * h], r = G.ph_val[2 * h + 1];  // a -> b, b -> a
-            *puv = u < v ? f : r;
-            *pvu = u < v ? r : f;
-            return;
-        }
-        if (k == ~0ull) return;
-        h = (h + 1) & (uint64_t)(cap - 1);
-    }
-}
-
-// entries of pair p with tlo < t < thi
-__device__ inline uint64_t pair_between_id(const DevGraph &G, int32_t p, int64_t tlo, int64_t thi) {
-    if (p < 0) return 0;
-    return (uint64_t)(pair_before(G, p, thi) - pair_before(G, p, tlo + 1));
-}
-
-// Per-lane accumulator of up to 16 motif codes.
-template <int MODE, int NC>
-struct Acc {
-    uint64_t c[NC];
-    uint64_t wl[MODE == MODE_WEIGHT ? NC : 1];
-    uint64_t wh[MODE == MODE_WEIGHT ? NC : 1];
-    __device__ void clear() {
-#pragma unroll
-        for (int k = 0; k < NC; ++k) c[k] = 0;
-        if constexpr (MODE == MODE_WEIGHT) {
-#pragma unroll
-            for (int k = 0; k < NC; ++k) wl[k] = wh[k] = 0;
-        }
-    }
-};
-
-// add v at code slot (base + dsel) where dsel in {0,1} is runtime
-template <int MODE, int NC>
-__device__ inline void acc_add(Acc<MODE, NC> &A, int base, uint32_t dsel, uint64_t v, uint64_t w, uint64_t *hist,
-                               int code_base, int64_t dlt, int64_t delta) {
-    uint64_t v0 = dsel ? 0 : v, v1 = dsel ? v : 0;
-    A.c[base] += v0;
-    A.c[base + 1] += v1;
-    if constexpr (MODE == MODE_WEIGHT) {
-        // (v * w) as 128 bits
-        uint64_t plo = v * w;
-        uint64_t phi = __umul64hi(v, w);
-        uint64_t l0 = dsel ? 0 : plo, h0 = dsel ? 0 : phi;
-        uint64_t l1 = dsel ? plo : 0, h1 = dsel ? phi : 0;
-        tm_add_u128(A.wl[base], A.wh[base], l0, h0);
-        tm_add_u128(A.wl[base + 1], A.wh[base + 1], l1, h1);
-    }
-    if constexpr (MODE == MODE_HIST) {
-        if (hist && v) {
-            int64_t code = code_base + dsel;
-            uint64_t *h = hist + (code * (delta + 1) + dlt) * 2;
-            tm_atomic_add_u128(h, h + 1, v, 0);
-        }
-    }
-}
-
-__device__ inline void lds_add_u128(unsigned long long *lo, unsigned long long *hi, uint64_t vlo, uint64_t vhi) {
-    if (vlo) {
-        unsigned long long old = atomicAdd(lo, (unsigned long long)vlo);
-        if (old + vlo < old) vhi += 1;
-    }
-    if (vhi) atomicAdd(hi, (unsigned long long)vhi);
-}
-
-template <int MODE, int NC>
-__device__ inline void flush(const Acc<MODE, NC> &A, const int *codes, unsigned long long *lds) {
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        int code = codes[k];
-        if (code < 0) continue;
-        if (A.c[k]) lds_add_u128(&lds[4 * code], &lds[4 * code + 1], A.c[k], 0);
-        if constexpr (MODE == MODE_WEIGHT) {
-            if (A.wl[k] | A.wh[k]) lds_add_u128(&lds[4 * code + 2], &lds[4 * code + 3], A.wl[k], A.wh[k]);
-        }
-    }
-}
-
-template <int MODE>
-__device__ inline uint64_t weight_of(const SweepArgs &a, int64_t dlt) {
-    if constexpr (MODE == MODE_WEIGHT) return a.wfx[dlt];
-    return 0;
-}
-
-// forward sweep of one anchor (codes 0..27)
-template <int MODE>
-__device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t i, int64_t end, uint32_t y1,
-                                 uint32_t d1, int64_t t1, int64_t hi, unsigned long long *lds) {
-    // slots: 0..3 two-node [2*d2+d3], 4..7 star B, 8..11 star A, 12..15 triangle
-    Acc<MODE, 16> A;
-    A.clear();
-    const bool two = (a.want_fwd & 1u) && d1 == 0;
-    const bool sb = a.want_fwd & 2u, sa = a.want_fwd & 4u, tri = a.want_fwd & 8u;
-    uint64_t cs0 = 0, cs1 = 0, ca0 = 0, ca1 = 0;  // middles before the current time group
-    uint64_t ps0 = 0, ps1 = 0, pa0 = 0, pa1 = 0;  // entries of the current time group
-    int64_t tg = t1;
-    for (int64_t j = i + 1; j < end; ++j) {
-        int64_t tj = G.inc_t[j];
-        if (tj > hi) break;
-        if (tj == t1) continue;
-        if (tj != tg) {
-            cs0 += ps0; cs1 += ps1; ca0 += pa0; ca1 += pa1;
-            ps0 = ps1 = pa0 = pa1 = 0;
-            tg = tj;
-        }
-        uint32_t nd = G.inc_nd[j];
-        uint32_t yj = nd & 0x7FFFFFFFu, dj = nd >> 31;
-        int64_t dlt = tj - t1;
-        uint64_t w = 0;
-        if constexpr (MODE == MODE_WEIGHT) w = weight_of<MODE>(a, dlt);
-        if (yj == y1) {
-            if (two) {
-                acc_add<MODE, 16>(A, 0, dj, cs0, w, a.hist, 0, dlt, a.delta);
-                acc_add<MODE, 16>(A, 2, dj, cs1, w, a.hist, 2, dlt, a.delta);
-            }
-            if (sb) {
-                acc_add<MODE, 16>(A, 4, dj, ca0 - cs0, w, a.hist, 4 + 4 * (int)d1, dlt, a.delta);
-                acc_add<MODE, 16>(A, 6, dj, ca1 - cs1, w, a.hist, 6 + 4 * (int)d1, dlt, a.delta);
-            }
-            if (dj) ++ps1; else ++ps0;
-        } else {
-            if (sa) {
-                acc_add<MODE, 16>(A, 8, dj, cs0, w, a.hist, 12 + 4 * (int)d1, dlt, a.delta);
-                acc_add<MODE, 16>(A, 10, dj, cs1, w, a.hist, 14 + 4 * (int)d1, dlt, a.delta);
-            }
-            if (tri) {
-                int32_t p01, p10;
-                pair_ids(G, y1, yj, &p01, &p10);
-                uint64_t c01 = pair_between_id(G, p01, t1, tj);
-                uint64_t c10 = pair_between_id(G, p10, t1, tj);
-                acc_add<MODE, 16>(A, 12, dj, c01, w, a.hist, 20 + 4 * (int)d1, dlt, a.delta);
-                acc_add<MODE, 16>(A, 14, dj, c10, w, a.hist, 22 + 4 * (int)d1, dlt, a.delta);
-            }
-        }
-        if (dj) ++pa1; else ++pa0;
-    }
-    int codes[16];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        codes[k] = two ? k : -1;
-        codes[4 + k] = 4 + 4 * (int)d1 + k;
-        codes[8 + k] = 12 + 4 * (int)d1 + k;
-        codes[12 + k] = 20 + 4 * (int)d1 + k;
-    }
-    flush<MODE, 16>(A, codes, lds);
-}
-
-// backward sweep of one anchor (codes 28..35): star with e2 on e3's pair
-template <int MODE>
-__device__ inline void sweep_bwd(const DevGraph &G, const SweepArgs &a, int64_t jj, int64_t beg, uint32_t y3,
-                                 uint32_t d3, int64_t t3, int64_t lo, unsigned long long *lds) {
-    // slots [2*d1 + d2]: v is added at slot (2*d1 + d2), d1 runtime -> use base 2*d2 with dsel = d1
-    Acc<MODE, 4> A;  // slot index: d2 * 2 + d1
-    A.clear();
-    uint64_t cs0 = 0, cs1 = 0, ps0 = 0, ps1 = 0;
-    int64_t tg = t3;
-    for (int64_t i = jj - 1; i >= beg; --i) {
-        int64_t ti = G.inc_t[i];
-        if (ti < lo) break;
-        if (ti == t3) continue;
-        if (ti != tg) {
-            cs0 += ps0; cs1 += ps1;
-            ps0 = ps1 = 0;
-            tg = ti;
-        }
-        uint32_t nd = G.inc_nd[i];
-        uint32_t yi = nd & 0x7FFFFFFFu, di = nd >> 31;
-        if (yi != y3) {
-            int64_t dlt = t3 - ti;
-            uint64_t w = 0;
-            if constexpr (MODE == MODE_WEIGHT) w = weight_of<MODE>(a, dlt);
-            // code 28 + 4*d1 + 2*d2 + d3, kept in slot 2*d2 + d1
-            if constexpr (MODE == MODE_HIST) {
-                if (cs0) {
-                    uint64_t *h = a.hist + ((int64_t)(28 + 4 * di + 0 + d3) * (a.delta + 1) + dlt) * 2;
-                    tm_atomic_add_u128(h, h + 1, cs0, 0);
-                }
-                if (cs1) {
-                    uint64_t *h = a.hist + ((int64_t)(28 + 4 * di + 2 + d3) * (a.delta + 1) + dlt) * 2;
-                    tm_atomic_add_u128(h, h + 1, cs1, 0);
-                }
-            }
-            acc_add<MODE, 4>(A, 0, di, cs0, w, nullptr, 0, dlt, a.delta);
-            acc_add<MODE, 4>(A, 2, di, cs1, w, nullptr, 0, dlt, a.delta);
-        } else {
-            if (di) ++ps1; else ++ps0;
-        }
-    }
-    int codes[4];
-    // slot (2*d2 + d1) -> code 28 + 4*d1 + 2*d2 + d3
-    codes[0] = 28 + 0 + 0 + (int)d3;  // d2=0,d1=0
-    codes[1] = 28 + 4 + 0 + (int)d3;  // d2=0,d1=1
-    codes[2] = 28 + 0 + 2 + (int)d3;  // d2=1,d1=0
-    codes[3] = 28 + 4 + 2 + (int)d3;  // d2=1,d1=1
-    flush<MODE, 4>(A, codes, lds);
-}
+using namespace sweepdev;
 
 template <int MODE, bool FWD>
 __global__ void __launch_bounds__(SW_TPB) k_sweep3(DevGraph G, SweepArgs a) {
