@@ -205,6 +205,59 @@ tm_status tm_estimate_batch(const tm_graph *g, const tm_motif *M, int64_t delta,
 tm_status tm_batch_config(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t c, double p,
                           int32_t *tile, int32_t *blocks_per_cu, void *hip_stream);
 
+/* ------------------------------------------------------------------ serving */
+
+typedef struct tm_server tm_server;
+
+typedef struct {
+    int32_t graph;     /* id from tm_server_add_graph                         */
+    int32_t kind;      /* 0: exact count (tm_count_exact); 1: estimate         */
+    tm_motif motif;
+    int64_t delta;
+    int64_t c;         /* estimate only                                       */
+    double p;          /* estimate only                                       */
+    uint64_t seed;     /* estimate only                                       */
+} tm_query;
+
+typedef struct {
+    tm_status status;    /* TM_EBUDGET when the query alone exceeds the budget */
+    tm_u128 count;       /* exact count; for estimates the kept-window count   */
+    double estimate;     /* kind 1                                            */
+    double latency_ms;   /* submit to result                                  */
+    double queue_ms;     /* submit to start on a slot                         */
+    int32_t batch_size;  /* queries answered by the same device pass          */
+    int32_t slot;
+} tm_result;
+
+typedef struct {
+    int64_t submitted, completed, rejected, batches;
+    double p50_ms, p99_ms, mean_ms;   /* nearest-rank latency percentiles   */
+    double wall_s;                    /* first submit to last completion     */
+    double edges_per_s;               /* graph edges of completed queries / wall_s */
+    int64_t budget_bytes, peak_bytes; /* admitted workspace, high-water mark */
+} tm_server_stats;
+
+/*
+ * Query server with continuous batching.  `slots` worker threads, each with
+ * its own HIP stream, run batches concurrently; a dispatcher admits the
+ * oldest queued query whose device workspace fits what is left of
+ * budget_bytes, merges every queued query that can share its device pass
+ * (exact counts of three-edge motifs on the same graph and delta; estimates
+ * of three-edge motifs with the same graph, delta, c, p and seed), and
+ * starts it on a free slot.  Queries that arrive while others run are
+ * admitted as slots and memory free up.  A result is the same whether its
+ * query ran alone or in a batch.  Graphs must stay loaded while the server
+ * uses them.  tm_server_wait blocks until the ticket's result is ready
+ * (TM_EINVAL for an unknown or already collected ticket); tm_server_destroy
+ * completes queued queries with TM_EDEVICE and joins the threads.
+ */
+tm_status tm_server_create(int32_t slots, int64_t budget_bytes, tm_server **out);
+tm_status tm_server_add_graph(tm_server *s, const tm_graph *g, int32_t *graph_id);
+tm_status tm_server_submit(tm_server *s, const tm_query *q, int64_t *ticket);
+tm_status tm_server_wait(tm_server *s, int64_t ticket, tm_result *result);
+tm_status tm_server_stats_get(tm_server *s, tm_server_stats *stats);
+void tm_server_destroy(tm_server *s);
+
 /*
  * Kernel timing (off by default).  When enabled, the library brackets its
  * main kernel launches with HIP events on the caller's stream and adds the

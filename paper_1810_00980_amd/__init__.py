@@ -55,6 +55,24 @@ class EstInfo(ctypes.Structure):
                 ("win_counts", ctypes.c_void_p), ("hist_lo", ctypes.c_void_p), ("hist_hi", ctypes.c_void_p)]
 
 
+class Query(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_int32), ("kind", ctypes.c_int32), ("motif", Motif), ("delta", ctypes.c_int64),
+                ("c", ctypes.c_int64), ("p", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("count", U128), ("estimate", ctypes.c_double),
+                ("latency_ms", ctypes.c_double), ("queue_ms", ctypes.c_double), ("batch_size", ctypes.c_int32),
+                ("slot", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("wall_s", ctypes.c_double), ("edges_per_s", ctypes.c_double),
+                ("budget_bytes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64)]
+
+
 P = ctypes.c_void_p
 i64, i32, u64, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
 
@@ -71,6 +89,12 @@ _SIGS = {
     "tm_estimate_multi": [P, i32, P, i64, i64, f64, u64, P, P, P],
     "tm_estimate_batch": [P, P, i64, i64, f64, i32, P, i32, P, P, P],
     "tm_batch_config": [P, P, i64, i64, f64, P, P, P],
+    "tm_server_create": [i32, i64, P],
+    "tm_server_add_graph": [P, P, P],
+    "tm_server_submit": [P, P, P],
+    "tm_server_wait": [P, i64, P],
+    "tm_server_stats_get": [P, P],
+    "tm_server_destroy": [P],
     "tm_profile_enable": [i32],
     "tm_profile_reset": [],
     "tm_profile_read": [ctypes.c_char_p, P, P],
@@ -83,6 +107,7 @@ for _name, _args in _SIGS.items():
     _f.argtypes = _args
     _f.restype = ctypes.c_int32
 _lib.tm_free_graph.restype = None
+_lib.tm_server_destroy.restype = None
 _lib.tm_strerror.restype = ctypes.c_char_p
 _lib.tm_version.restype = ctypes.c_char_p
 
@@ -297,6 +322,49 @@ def batch_config(g: Graph, edges, delta: int, c: int, p: float, stream=None):
     _check(_lib.tm_batch_config(g.handle, ctypes.byref(motif(edges)), int(delta), int(c), float(p),
                                 ctypes.byref(t), ctypes.byref(b), _stream(stream)), "tm_batch_config")
     return t.value, b.value
+
+
+class Server:
+    """Continuous-batching query server over loaded graphs (see tm.h)."""
+
+    def __init__(self, slots: int = 4, budget_bytes: int = 1 << 30):
+        self._h = ctypes.c_void_p()
+        _check(_lib.tm_server_create(int(slots), int(budget_bytes), ctypes.byref(self._h)), "tm_server_create")
+        self._graphs = []
+
+    def add_graph(self, g: Graph) -> int:
+        gid = ctypes.c_int32()
+        _check(_lib.tm_server_add_graph(self._h, g.handle, ctypes.byref(gid)), "tm_server_add_graph")
+        self._graphs.append(g)
+        return gid.value
+
+    def submit(self, graph: int, edges, delta: int, kind: int = 0, c: int = 0, p: float = 0.0, seed: int = 0) -> int:
+        q = Query(graph, kind, motif(edges), int(delta), int(c), float(p), int(seed))
+        t = ctypes.c_int64()
+        _check(_lib.tm_server_submit(self._h, ctypes.byref(q), ctypes.byref(t)), "tm_server_submit")
+        return t.value
+
+    def wait(self, ticket: int) -> dict:
+        r = Result()
+        _check(_lib.tm_server_wait(self._h, int(ticket), ctypes.byref(r)), "tm_server_wait")
+        return {"status": r.status, "count": r.count.value(), "estimate": r.estimate, "latency_ms": r.latency_ms,
+                "queue_ms": r.queue_ms, "batch_size": r.batch_size, "slot": r.slot}
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(_lib.tm_server_stats_get(self._h, ctypes.byref(s)), "tm_server_stats_get")
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            _lib.tm_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version() -> str:

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtm.so")
-SOURCES = ["tm_prims.hip", "tm_graph.hip", "tm_count_generic.hip", "tm_sweep3.hip", "tm_batch.hip", "tm_api.hip"]
+SOURCES = ["tm_prims.hip", "tm_graph.hip", "tm_count_generic.hip", "tm_sweep3.hip", "tm_batch.hip", "tm_server.hip", "tm_api.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",
@@ -41,7 +41,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     while procs:
         _wait(procs.pop(0))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)

@@ -385,14 +385,22 @@ static double u128_scaled(uint64_t lo, uint64_t hi, double scale) {
 
 // Runs the 3-edge sweep for the codes in mask; copies the 36 x 4 results and
 // (mode 2) the histograms of the requested codes to the host.
+// Per host thread, grow-only device workspace of the sweep path: after the
+// first calls a query allocates nothing, so queries in flight on different
+// threads and streams do not serialise on allocation.
+struct SweepWs {
+    DevBuf o, h, w, ctr;
+};
+thread_local SweepWs t_ws;
+
 tm_status run_sweep(const tm_graph *g, uint64_t mask, int mode, int64_t delta, int windowed, int64_t s, int64_t L,
                     uint64_t seed, double p, SweepOut *out, const std::vector<int> &hist_codes,
                     std::vector<uint64_t> *hist_host, hipStream_t st) {
-    DevBuf o, h, w, ctr;
-    TM_TRY(o.alloc(36 * 4 * 8));
-    TM_TRY(ctr.alloc(64));
-    if (mode == 2) TM_TRY(h.alloc((size_t)36 * (delta + 1) * 16));
-    if (mode == 1) TM_TRY(w.alloc((size_t)(delta + 1) * 8));
+    DevBuf &o = t_ws.o, &h = t_ws.h, &w = t_ws.w, &ctr = t_ws.ctr;
+    TM_TRY(o.reserve(36 * 4 * 8));
+    TM_TRY(ctr.reserve(64));
+    if (mode == 2) TM_TRY(h.reserve((size_t)36 * (delta + 1) * 16));
+    if (mode == 1) TM_TRY(w.reserve((size_t)(delta + 1) * 8));
     TM_TRY(tm_sweep3(g, mask, mode, delta, windowed, s, L, seed, p, o.as<uint64_t>(), h.as<uint64_t>(),
                      w.as<uint64_t>(), ctr.as<int64_t>(), st));
     TM_HIP(hipMemcpyAsync(out->v, o.p, sizeof out->v, hipMemcpyDeviceToHost, st));

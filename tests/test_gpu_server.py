@@ -1,0 +1,103 @@
+"""GPU tests of the continuous-batching query server: every result is the
+same as the same query run alone (mix invariance), compatible queries share
+device passes, and the memory budget is enforced."""
+import numpy as np
+import pytest
+
+import oracle
+import tm_inputs as ti
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tm():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    import paper_1810_00980_amd as tm
+    return tm
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def make_queries(rng, n_graphs, k):
+    motifs = ti.three_edge_motifs() + [ti.CYCLE4]
+    qs = []
+    for _ in range(k):
+        gi = int(rng.integers(0, n_graphs))
+        M = motifs[int(rng.integers(0, len(motifs)))]
+        delta = int(rng.choice([20, 60]))
+        if rng.random() < 0.3:
+            qs.append(dict(graph=gi, edges=M, delta=delta, kind=0))
+        else:
+            qs.append(dict(graph=gi, edges=M, delta=delta, kind=1, c=3, p=float(rng.choice([0.3, 1.0])),
+                           seed=int(rng.integers(0, 3))))
+    return qs
+
+
+def alone(tm, Gs, q):
+    G = Gs[q["graph"]]
+    if q["kind"] == 0:
+        return tm.count_exact(G, q["edges"], q["delta"])
+    if ti.CYCLE4 == q["edges"]:
+        return tm.estimate(G, q["edges"], q["delta"], q["c"], q["p"], q["seed"], info=True)["Z"]
+    return tm.estimate(G, q["edges"], q["delta"], q["c"], q["p"], q["seed"])
+
+
+def test_server_mix_invariance(tm):
+    graphs = [ti.random_small_graph(6, m, 4000, 300 + m, allow_self_loops=True) for m in (600, 1500, 3000)]
+    Gs = [tm.load_graph(g.src, g.dst, g.t, g.n) for g in graphs]
+    rng = np.random.default_rng(5)
+    qs = make_queries(rng, len(Gs), 80)
+    say("server alone")
+    want = [alone(tm, Gs, q) for q in qs]
+    # spot-check the alone results against the oracle
+    for q, w in list(zip(qs, want))[:10]:
+        g = graphs[q["graph"]]
+        if q["kind"] == 0:
+            assert w == oracle.count(g.src, g.dst, g.t, q["edges"], q["delta"], hist=False)[0]
+        else:
+            o = oracle.estimate(g.src, g.dst, g.t, q["edges"], q["delta"], q["c"], q["p"], q["seed"])["Z"]
+            assert abs(w - o) <= 1e-12 * max(1.0, abs(o))
+    say("server mix")
+    S = tm.Server(slots=4, budget_bytes=1 << 30)
+    ids = [S.add_graph(G) for G in Gs]
+    tickets = [S.submit(ids[q["graph"]], q["edges"], q["delta"], q["kind"], q.get("c", 0), q.get("p", 0.0),
+                        q.get("seed", 0)) for q in qs]
+    res = [S.wait(t) for t in tickets]
+    for q, r, w in zip(qs, res, want):
+        assert r["status"] == 0
+        if q["kind"] == 0:
+            assert r["count"] == w, q
+        else:
+            assert r["estimate"] == w, (q, r["estimate"], w)
+    st = S.stats()
+    assert st["completed"] == len(qs) and st["rejected"] == 0
+    assert st["batches"] < len(qs)  # some queries shared a device pass
+    assert max(r["batch_size"] for r in res) > 1
+    assert 0 < st["p50_ms"] <= st["p99_ms"]
+    with pytest.raises(tm.TMError):
+        S.wait(tickets[0])  # already collected
+    S.close()
+
+
+def test_server_budget(tm):
+    g = ti.random_small_graph(6, 2000, 4000, 77)
+    G = tm.load_graph(g.src, g.dst, g.t, g.n)
+    say("server budget")
+    # 4 KiB: three-edge queries fit one at a time, the generic four-edge path does not
+    S = tm.Server(slots=3, budget_bytes=4096)
+    gid = S.add_graph(G)
+    tks = [S.submit(gid, ti.TRIANGLE, 30) for _ in range(6)]
+    tks.append(S.submit(gid, ti.CYCLE4, 30))
+    tks.append(S.submit(gid, ti.TWO_NODE_ALT, 30, kind=1, c=3, p=0.5, seed=4))
+    res = [S.wait(t) for t in tks]
+    want = tm.count_exact(G, ti.TRIANGLE, 30)
+    assert all(r["status"] == 0 and r["count"] == want for r in res[:6])
+    assert res[6]["status"] == 4  # TM_EBUDGET
+    assert res[7]["status"] == 0 and res[7]["estimate"] == tm.estimate(G, ti.TWO_NODE_ALT, 30, 3, 0.5, 4)
+    st = S.stats()
+    assert st["peak_bytes"] <= 4096 and st["rejected"] == 1
+    S.close()
