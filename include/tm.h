@@ -198,7 +198,7 @@ tm_status tm_estimate_batch(const tm_graph *g, const tm_motif *M, int64_t delta,
 
 /*
  * Autotuner of the batched estimator: times candidate tile sizes
- * {256, 1024, 4096} and resident work-groups per CU {2, 4, 8} on 8 seeds and
+ * {256, 1024, 4096} and resident work-groups per CU {2, 8} on 4 seeds and
  * returns (and caches for the graph) the fastest pair.  Three-edge motifs
  * only (TM_EUNSUPPORTED otherwise).
  */

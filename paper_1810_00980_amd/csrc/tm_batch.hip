@@ -447,9 +447,10 @@ tm_status tm_batch_tune(const tm_graph *g, int32_t code, int64_t delta, int64_t 
         }
     }
     const int64_t tiles[] = {256, 1024, 4096};
-    const int64_t bpcs[] = {2, 4, 8};
-    uint64_t seeds[8];
-    for (int i = 0; i < 8; ++i) seeds[i] = 0x5EED0000ull + (uint64_t)i;
+    const int64_t bpcs[] = {2, 8};
+    const int64_t NS = 4;
+    uint64_t seeds[NS];
+    for (int i = 0; i < NS; ++i) seeds[i] = 0x5EED0000ull + (uint64_t)i;
     double best = 1e300;
     int64_t bt = 1024, bb = 4;
     hipEvent_t e0, e1;
@@ -458,14 +459,13 @@ tm_status tm_batch_tune(const tm_graph *g, int32_t code, int64_t delta, int64_t 
     for (int64_t t : tiles) {
         for (int64_t b : bpcs) {
             BatchPlan *B = nullptr;
-            tm_status s = get_plan(g, code, delta, L, p, 8, t, b, false, &B, st);
+            tm_status s = get_plan(g, code, delta, L, p, NS, t, b, false, &B, st);
             if (s != TM_OK) {
                 (void)hipEventDestroy(e0);
                 (void)hipEventDestroy(e1);
                 return s;
             }
-            // one untimed run, one timed
-            (void)run_plan(g, *B, seeds, nullptr, nullptr, false, st);
+            (void)hipMemcpyAsync(B->seeds.p, seeds, sizeof seeds, hipMemcpyHostToDevice, st);
             (void)hipEventRecord(e0, st);
             (void)enqueue(g, *B, st);
             (void)hipEventRecord(e1, st);
@@ -485,7 +485,7 @@ tm_status tm_batch_tune(const tm_graph *g, int32_t code, int64_t delta, int64_t 
         // tuning plans (8 seeds, uncaptured) are not needed any more
         std::lock_guard<std::mutex> lk(C.mu);
         for (auto it = C.plans.begin(); it != C.plans.end();) {
-            if (std::get<0>(it->first) == g && std::get<5>(it->first) == 8 && !it->second->exec)
+            if (std::get<0>(it->first) == g && std::get<5>(it->first) == 4 && !it->second->exec)
                 it = C.plans.erase(it);
             else
                 ++it;

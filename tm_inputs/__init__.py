@@ -155,6 +155,12 @@ def config_zipf10m(seed: int = 2) -> Graph:
     return zipf_graph(100_000, 10_000_000, 1.8, 30_000_000, seed)
 
 
+def config_batch50m(seed: int = 4) -> Graph:
+    """500k nodes, 50M edges, Zipf(1.8), bursty times over [0, 3e8) with 30% of
+    the hours silent: windows of 30 hours hold from tens to ~5e5 edges."""
+    return zipf_graph(500_000, 50_000_000, 1.8, 300_000_000, seed, sigma=1.5, phi=0.95, gap_frac=0.3)
+
+
 def config_zipf(m: int, n: int, alpha: float, t_hi: int, seed: int, **kw) -> Graph:
     return zipf_graph(n, m, alpha, t_hi, seed, **kw)
 
