@@ -40,7 +40,8 @@ THREE = ti.three_edge_motifs()
 HBM_PEAK_GBS = 8000.0
 DOMINANT = "sweep3_fwd_count"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep3_fwd_count_zipf10m_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1810_00980_amd", "csrc", "tm_sweep3.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1810_00980_amd", "csrc", f)
+               for f in ("tm_sweep3.hip", "tm_sweep_dev.h", "tm_common.h")]
 
 WORKLOADS = {
     "zipf10m": dict(
@@ -136,6 +137,19 @@ def run_batch(args):
     assert all(a == b for a, b in zip(one, est)), "batched estimates differ from single calls"
     dt = float(np.mean(ts))
     mean, var = float(np.mean(est)), float(np.var(est, ddof=1))
+    # the same comparison where one estimate is far from filling the GPU
+    gs = ti.config_small_dense()
+    Gs = tm.load_graph(gs.src, gs.dst, gs.t, gs.n)
+    tm.estimate_batch(Gs, M, delta, c, p, seeds, tile=64)
+    t0 = time.perf_counter()
+    tm.estimate_batch(Gs, M, delta, c, p, seeds + 7, tile=64)
+    small_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for sd in seeds + 7:
+        tm.estimate(Gs, M, delta, c, p, int(sd))
+    small_seq = time.perf_counter() - t0
+    Gs.free()
+    log("small graph: batched", f"{small_batch * 1e3:.2f} ms, one at a time {small_seq * 1e3:.2f} ms")
     return {
         "metric": "temporal edges/s per motif query (batched p=0.1 estimates)", "value": g.m * 64 / dt,
         "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": dt * 1e3,
@@ -150,18 +164,28 @@ def run_batch(args):
         "estimates": {"mean": mean, "variance": var, "std_error": (var / 64) ** 0.5,
                       "rel_error_of_mean": (mean - exact) / exact if exact else None},
         "one_at_a_time_s": t_seq, "batched_s": dt, "batch_speedup": t_seq / dt,
+        "small_graph_64_seeds": {"workload": "50 nodes, 20k uniform edges, triangle, delta 3600, c 30, p 0.1",
+                                 "batched_ms": small_batch * 1e3, "one_at_a_time_ms": small_seq * 1e3,
+                                 "speedup": small_seq / small_batch},
     }
 
 
 def serving_queries(rng, graphs, n, qps):
+    """Poisson arrivals; 25% exact / 75% estimate; motif uniform over the 36
+    three-edge motifs and the 4-cycle, delta in {600, 3600, 86400}, p in
+    {0.01, 0.1, 1}, c 30, seed from a pool of 4.  The 4-cycle (with delta at
+    most 3600) and delta 86400 are drawn only on graphs of at most 4e4 edges:
+    on the larger serving graphs, whose times are packed into 1e6 s, those
+    queries cost seconds to minutes each."""
     motifs = THREE + [ti.CYCLE4]
     qs, t = [], 0.0
     for _ in range(n):
         t += rng.exponential(1.0 / qps)
         gi = int(rng.integers(0, len(graphs)))
-        big = graphs[gi].m > 150_000
-        M = motifs[int(rng.integers(0, len(motifs) - (1 if big else 0)))]
-        delta = int(rng.choice([600, 3600] if big else [600, 3600, 86400]))
+        small = graphs[gi].m <= 40_000
+        M = motifs[int(rng.integers(0, len(motifs) - (0 if small else 1)))]
+        deltas = [600, 3600, 86400] if (small and M != ti.CYCLE4) else [600, 3600]
+        delta = int(rng.choice(deltas))
         if rng.random() < 0.25:
             qs.append(dict(at=t, graph=gi, edges=M, delta=delta, kind=0))
         else:
@@ -170,41 +194,9 @@ def serving_queries(rng, graphs, n, qps):
     return qs
 
 
-def run_serve(args):
-    """Poisson stream of count/estimate queries over 6 resident graphs of
-    1e4 .. 7.2e6 edges, served by the continuous-batching server (4 slots,
-    4 GiB budget) and, for comparison, one query at a time on the GPU."""
-    import torch
-    import paper_1810_00980_amd as tm
-    graphs = [ti.serving_graph(i) for i in range(6)]
-    Gs = []
-    for g in graphs:
-        s, d, t = (torch.from_numpy(a).cuda() for a in (g.src, g.dst, g.t))
-        Gs.append(tm.load_graph(s, d, t, g.n))
-    log("graphs", [g.m for g in graphs])
-    rng = np.random.default_rng(2024)
-    qs = serving_queries(rng, graphs, args.queries, args.qps)
-
-    def direct(q):
-        G = Gs[q["graph"]]
-        if q["kind"] == 0:
-            return tm.count_exact(G, q["edges"], q["delta"])
-        return tm.estimate(G, q["edges"], q["delta"], q["c"], q["p"], q["seed"], info=(q["edges"] == ti.CYCLE4))
-
-    for q in qs[:20]:
-        direct(q)  # warm up kernels and workspaces
-    torch.cuda.synchronize()
-    log("one at a time")
-    lat, t0 = [], time.perf_counter()
-    for q in qs:
-        now = time.perf_counter() - t0
-        if now < q["at"]:
-            time.sleep(q["at"] - now)
-        direct(q)
-        lat.append(time.perf_counter() - t0 - q["at"])
-    seq_wall = time.perf_counter() - t0
-    log("server")
-    S = tm.Server(slots=4, budget_bytes=4 << 30)
+def serve_once(tm, Gs, graphs, qs, slots, budget):
+    """Submit qs at their arrival times to a server; returns its statistics."""
+    S = tm.Server(slots=slots, budget_bytes=budget)
     ids = [S.add_graph(G) for G in Gs]
     tickets, t0 = [], time.perf_counter()
     for q in qs:
@@ -216,28 +208,85 @@ def run_serve(args):
     res = [S.wait(tk) for tk in tickets]
     st = S.stats()
     S.close()
-    edges = sum(graphs[q["graph"]].m for q in qs)
-    lat_ms = np.sort(np.array(lat) * 1e3)
-    pct = lambda a, f: float(a[max(0, int(np.ceil(f * len(a))) - 1)])
+    return {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "wall_s": st["wall_s"],
+            "edges_per_s": st["edges_per_s"], "batches": st["batches"], "queries": st["completed"],
+            "rejected": st["rejected"], "peak_workspace_bytes": st["peak_bytes"],
+            "max_batch": max(r["batch_size"] for r in res)}, res
+
+
+def run_serve(args):
+    """Poisson streams of count/estimate queries over 6 resident graphs of
+    1e4 .. 7.2e6 edges at several arrival rates, served by the
+    continuous-batching server (4 slots, 4 GiB budget) and, for comparison,
+    one query at a time on the GPU in arrival order."""
+    import torch
+    import paper_1810_00980_amd as tm
+    graphs = [ti.serving_graph(i) for i in range(6)]
+    Gs = []
+    for g in graphs:
+        s, d, t = (torch.from_numpy(a).cuda() for a in (g.src, g.dst, g.t))
+        Gs.append(tm.load_graph(s, d, t, g.n))
+    log("graphs", [g.m for g in graphs])
+
+    def direct(q):
+        G = Gs[q["graph"]]
+        if q["kind"] == 0:
+            return tm.count_exact(G, q["edges"], q["delta"])
+        return tm.estimate(G, q["edges"], q["delta"], q["c"], q["p"], q["seed"], info=(q["edges"] == ti.CYCLE4))
+
+    warm = serving_queries(np.random.default_rng(1), graphs, 40, 1000.0)
+    for q in warm:
+        direct(q)
+    serve_once(tm, Gs, graphs, warm, 4, 4 << 30)
+    torch.cuda.synchronize()
+    sweeps = []
+    for qps in args.qps_list:
+        qs = serving_queries(np.random.default_rng(2024), graphs, args.queries, qps)
+        edges = sum(graphs[q["graph"]].m for q in qs)
+        log("qps", qps, "one at a time")
+        lat, t0 = [], time.perf_counter()
+        for qi, q in enumerate(qs):
+            now = time.perf_counter() - t0
+            if now < q["at"]:
+                time.sleep(q["at"] - now)
+            direct(q)
+            lat.append(time.perf_counter() - t0 - q["at"])
+            if qi % 100 == 99:
+                log("  done", qi + 1, f"{time.perf_counter() - t0:.1f}s")
+        seq_wall = time.perf_counter() - t0
+        log("qps", qps, "server")
+        srv, res = serve_once(tm, Gs, graphs, qs, 4, 4 << 30)
+        lat_ms = np.sort(np.array(lat) * 1e3)
+        pct = lambda a, f: float(a[max(0, int(np.ceil(f * len(a))) - 1)])
+        sweeps.append({"qps": qps, "queries": len(qs), "server": srv,
+                       "one_at_a_time": {"p50_ms": pct(lat_ms, 0.5), "p99_ms": pct(lat_ms, 0.99),
+                                         "wall_s": seq_wall, "edges_per_s": edges / seq_wall}})
+        log("qps", qps, "server edges/s", f"{srv['edges_per_s']:.3e}", "p99", f"{srv['p99_ms']:.1f}",
+            "| one at a time", f"{edges / seq_wall:.3e}", "p99", f"{pct(lat_ms, 0.99):.1f}")
+    top = sweeps[-1]
     out = {
-        "metric": "temporal edges/s per motif query (served stream); p50/p99 latency", "value": st["edges_per_s"],
-        "unit": "edges/s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": st["wall_s"] * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-        "config": {"workload": f"{len(qs)} Poisson queries at {args.qps}/s over 6 graphs of 1e4..7.2e6 edges "
+        "metric": "temporal edges/s per motif query (served stream); p50/p99 latency",
+        "value": top["server"]["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": top["server"]["wall_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"{args.queries} Poisson queries per arrival rate over 6 graphs of 1e4..7.2e6 edges "
                                "(Zipf 1.8, bursty); 25% exact / 75% estimate; motif uniform over 36 three-edge "
-                               "motifs + 4-cycle (4-cycle and delta 86400 on graphs up to 1.5e5 edges); delta in "
-                               "{600,3600,86400}; p in {0.01,0.1,1}; c 30; seeds from a pool of 4",
-                   "slots": 4, "budget_bytes": 4 << 30},
-        "server": {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "wall_s": st["wall_s"],
-                   "edges_per_s": st["edges_per_s"], "batches": st["batches"], "queries": st["completed"],
-                   "rejected": st["rejected"], "peak_workspace_bytes": st["peak_bytes"],
-                   "max_batch": max(r["batch_size"] for r in res)},
-        "one_at_a_time": {"p50_ms": pct(lat_ms, 0.5), "p99_ms": pct(lat_ms, 0.99), "wall_s": seq_wall,
-                          "edges_per_s": edges / seq_wall},
+                               "motifs + 4-cycle (4-cycle, with delta <= 3600, and delta 86400 on graphs up to 4e4 "
+                               "edges); delta in "
+                               "{600,3600,86400}; p in {0.01,0.1,1}; c 30; seeds from a pool of 4; value at the "
+                               "highest rate", "slots": 4, "budget_bytes": 4 << 30, "qps": args.qps_list},
+        "sweep": sweeps,
     }
     for G in Gs:
         G.free()
     return out
+
+
+def kernel_src_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def traffic_record():
@@ -246,7 +295,7 @@ def traffic_record():
     if not os.path.exists(TRAFFIC_FILE):
         return None
     rec = json.load(open(TRAFFIC_FILE))
-    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    sha = kernel_src_sha()
     if rec.get("kernel_src_sha256") != sha:
         return None
     return rec.get("traffic_bytes_per_launch")
@@ -258,8 +307,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="zipf10m", choices=sorted(WORKLOADS) + ["batch50m", "serve"])
-    ap.add_argument("--qps", type=float, default=20.0, help="serve: arrival rate")
-    ap.add_argument("--queries", type=int, default=200, help="serve: number of queries")
+    ap.add_argument("--qps-list", type=float, nargs="+", default=[50.0, 400.0], help="serve: arrival rates")
+    ap.add_argument("--queries", type=int, default=400, help="serve: queries per arrival rate")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")

@@ -185,10 +185,11 @@ tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, const tm_motif 
  * For the 36 three-edge motifs all kept windows of all seeds are counted in
  * one persistent launch: node-aligned tiles of at most `tile` anchors are
  * queued per (seed, tile) that meets a kept window, and resident
- * work-groups take tasks from the shared queue (work stealing).  The kernel
+ * wavefronts take tasks from the shared queue (work stealing).  The kernel
  * sequence is captured once as a hipGraph per (graph, motif, delta, c, p,
  * n_seeds, tile, grid) and replayed with the new seeds.  tile = 0 uses the
- * autotuned tile and grid (tm_batch_config).  Other motifs run seed by seed.
+ * autotuned tile and grid (tm_batch_config); a nonzero tile runs with 8
+ * work-groups per CU.  Other motifs run seed by seed.
  * kept_counts (nullable) receives each seed's exact count over its kept
  * windows.  Plans are cached with the graph and released by tm_free_graph.
  */
@@ -198,7 +199,7 @@ tm_status tm_estimate_batch(const tm_graph *g, const tm_motif *M, int64_t delta,
 
 /*
  * Autotuner of the batched estimator: times candidate tile sizes
- * {256, 1024, 4096} and resident work-groups per CU {2, 8} on 4 seeds and
+ * {64, 256, 1024} and work-groups per CU {8, 16} on 2 seeds and
  * returns (and caches for the graph) the fastest pair.  Three-edge motifs
  * only (TM_EUNSUPPORTED otherwise).
  */

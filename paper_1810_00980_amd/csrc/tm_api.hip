@@ -642,7 +642,7 @@ extern "C" tm_status tm_estimate_batch(const tm_graph *g, const tm_motif *M, int
     int64_t J = 1 + g->t_span / L + ((g->t_span % L) ? 1 : 0);
     if (code >= 0 && n_seeds > 0 && (J + 1) * (int64_t)n_seeds <= ((int64_t)1 << 28)) {
         auto run = [&]() -> tm_status {
-            int64_t t = tile, b = 4;
+            int64_t t = tile, b = 8;
             if (t == 0) TM_TRY(tm_batch_tune(g, code, delta, L, p, &t, &b, st));
             return tm_batch_run(g, code, delta, L, p, n_seeds, seeds, t, b, estimates, kept_counts, st);
         };

@@ -3,15 +3,17 @@
 // separate estimators) of one three-edge motif in one persistent launch.
 //
 // Work is split into anchor tiles: runs of at most `tile` consecutive entries
-// of one node's time-sorted incidence list.  For every (seed, tile) whose time
-// range meets a window that seed keeps, a task is appended to a device queue;
-// persistent work-groups pop tasks (work stealing through one atomic head),
-// sweep the tile's anchors that lie in kept windows, and add the motif's
-// count and fixed-point weighted sum into that seed's accumulator.  A last
-// kernel turns each seed's sum into its estimate.  The four kernels run as
-// one hipGraph, captured once per (graph, motif, delta, c, p, seeds, tile,
-// grid) and replayed with new seeds; counters are cleared by fill kernels,
-// never by memset nodes.
+// of one node's time-sorted incidence list.  The candidate tasks are the
+// (tile, seed) pairs in tile-major order, so that at any moment the resident
+// wavefronts work on the same region of the graph for every seed and share
+// its cache lines.  Persistent wavefronts claim one tile's candidates (up to
+// 64 seeds) at a time from one atomic counter (work stealing), keep those whose tile meets a window the
+// seed keeps (one ballot), sweep each kept task's anchors that lie in kept
+// windows, and add the motif's count and fixed-point weighted sum into that
+// seed's accumulator.  A last kernel turns each seed's sum into its estimate.
+// The kernels run as one hipGraph, captured once per (graph, motif, delta,
+// c, p, seeds, tile, grid) and replayed with new seeds; counters are cleared
+// by fill kernels, never by memset nodes.
 //
 // The tile size and the number of resident work-groups per CU are chosen by
 // timing candidates on the first call (autotuner), per (graph, motif, delta,
@@ -44,8 +46,7 @@ struct BatchArgs {
     const int64_t *tiles;     // [n_tiles + 1] entry starts
     const int32_t *tile_node; // [n_tiles]
     int64_t n_tiles;
-    int64_t *tasks;           // [n_seeds * n_tiles]
-    unsigned long long *qctl; // [0] task count, [1] head
+    unsigned long long *qctl; // [0] candidate counter
     uint64_t *out;            // [n_seeds][4]: count lo/hi, weight lo/hi
     const uint64_t *wfx;
     int32_t code;             // the motif's sweep code
@@ -96,81 +97,90 @@ __global__ void __launch_bounds__(BT_TPB) k_batch_flags(BatchArgs a) {
     }
 }
 
-// one work-item per (seed, tile): queue the tile when a kept window meets it
-__global__ void k_batch_tasks(DevGraph G, BatchArgs a) {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= a.n_seeds * a.n_tiles) return;
-    int64_t k = id / a.n_tiles, t = id - k * a.n_tiles;
-    int64_t e0 = a.tiles[t], e1 = a.tiles[t + 1];
-    int64_t s = a.shifts[k];
-    int64_t j0 = (G.inc_t[e0] - s) / a.L + 1, j1 = (G.inc_t[e1 - 1] - s) / a.L + 1;
-    if (j1 > a.J) j1 = a.J;
-    const int32_t *kp = a.kept_prefix + k * (a.J + 1);
-    if (kp[j1] - kp[j0 - 1] > 0) {
-        unsigned long long q = atomicAdd(&a.qctl[0], 1ull);
-        a.tasks[q] = id;
+__device__ inline void wave_sum_u128(uint64_t &lo, uint64_t &hi) {
+#pragma unroll
+    for (int o = TM_WAVE / 2; o > 0; o >>= 1) {
+        uint64_t olo = __shfl_xor(lo, o, TM_WAVE);
+        uint64_t ohi = __shfl_xor(hi, o, TM_WAVE);
+        tm_add_u128(lo, hi, olo, ohi);
     }
 }
 
-// persistent work-groups: pop a task, sweep its kept anchors, add the sums
+// persistent wavefronts: claim (tile, seed) candidates, keep those whose
+// tile meets a kept window of the seed, and for each kept task sweep the
+// tile's anchors in kept windows with the lanes' own sums, reduce them across
+// the wave and add them to the seed
 template <int MODE>
 __global__ void __launch_bounds__(BT_TPB) k_batch_sweep(DevGraph G, BatchArgs a) {
-    __shared__ unsigned long long lds[36 * 4];
-    __shared__ int64_t task;
-    const unsigned long long ntask = a.qctl[0];
+    const int lane = threadIdx.x & (TM_WAVE - 1);
+    const int64_t total = a.n_tiles * a.n_seeds;
+    // one claim covers one tile for up to 64 seeds
+    const int64_t claim = a.n_seeds < TM_WAVE ? a.n_seeds : TM_WAVE;
     while (true) {
-        if (threadIdx.x == 0) {
-            unsigned long long h = atomicAdd(&a.qctl[1], 1ull);
-            task = h < ntask ? a.tasks[h] : -1;
+        int64_t base = 0;
+        if (lane == 0) base = (int64_t)atomicAdd(&a.qctl[0], (unsigned long long)claim);
+        base = __shfl(base, 0, TM_WAVE);
+        if (base >= total) break;
+        int64_t cand = base + lane;
+        bool kept = false;
+        if (lane < claim && cand < total) {
+            int64_t t = cand / a.n_seeds, k = cand - t * a.n_seeds;
+            int64_t s = a.shifts[k];
+            int64_t e0 = a.tiles[t], e1 = a.tiles[t + 1];
+            int64_t j0 = (G.inc_t[e0] - s) / a.L + 1, j1 = (G.inc_t[e1 - 1] - s) / a.L + 1;
+            if (j1 > a.J) j1 = a.J;
+            const int32_t *kp = a.kept_prefix + k * (a.J + 1);
+            kept = kp[j1] - kp[j0 - 1] > 0;
         }
-        for (int q = threadIdx.x; q < 4; q += BT_TPB) lds[4 * a.code + q] = 0;
-        __syncthreads();
-        int64_t id = task;
-        if (id < 0) break;
-        int64_t k = id / a.n_tiles, t = id - k * a.n_tiles;
-        int64_t e0 = a.tiles[t], e1 = a.tiles[t + 1];
-        int64_t x = a.tile_node[t];
-        int64_t lb = G.inc_off[x], le = G.inc_off[x + 1];
-        SweepArgs sa;
-        sa.delta = a.delta;
-        sa.windowed = 1;
-        sa.s = a.shifts[k];
-        sa.L = a.L;
-        sa.seed = a.seeds[k];
-        sa.p = a.p;
-        sa.wfx = a.wfx;
-        sa.hist = nullptr;
-        sa.out = nullptr;
-        sa.counter = nullptr;
-        sa.want_fwd = a.want_fwd;
-        sa.n_entries = 0;
-        for (int64_t i = e0 + threadIdx.x; i < e1; i += BT_TPB) {
-            uint32_t nd = G.inc_nd[i];
-            uint32_t y = nd & 0x7FFFFFFFu, d = nd >> 31;
-            int64_t tt = G.inc_t[i];
-            int64_t j = (tt - sa.s) / sa.L + 1;
-            if (!keep_window(sa.seed, (uint64_t)j, sa.p)) continue;
-            int64_t wlo = sa.s + (j - 1) * sa.L, whi = sa.s + j * sa.L - 1;
-            if (a.want_fwd) {
-                int64_t hi = (tt > LLONG_MAX - a.delta) ? LLONG_MAX : tt + a.delta;
-                hi = hi < whi ? hi : whi;
-                sweep_fwd<MODE>(G, sa, i, le, y, d, tt, hi, lds);
+        unsigned long long todo = __ballot(kept);
+        while (todo) {
+            int b = __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
+            int64_t id = base + b;
+            int64_t t = id / a.n_seeds, k = id - t * a.n_seeds;
+            int64_t e0 = a.tiles[t], e1 = a.tiles[t + 1];
+            int64_t x = a.tile_node[t];
+            int64_t lb = G.inc_off[x], le = G.inc_off[x + 1];
+            SweepArgs sa;
+            sa.delta = a.delta;
+            sa.windowed = 1;
+            sa.s = a.shifts[k];
+            sa.L = a.L;
+            sa.seed = a.seeds[k];
+            sa.p = a.p;
+            sa.wfx = a.wfx;
+            sa.hist = nullptr;
+            sa.out = nullptr;
+            sa.counter = nullptr;
+            sa.want_fwd = a.want_fwd;
+            sa.n_entries = 0;
+            OneCode one{a.code, 0, 0, 0, 0};
+            for (int64_t i = e0 + lane; i < e1; i += TM_WAVE) {
+                uint32_t nd = G.inc_nd[i];
+                uint32_t y = nd & 0x7FFFFFFFu, d = nd >> 31;
+                int64_t tt = G.inc_t[i];
+                int64_t j = (tt - sa.s) / sa.L + 1;
+                if (!keep_window(sa.seed, (uint64_t)j, sa.p)) continue;
+                int64_t wlo = sa.s + (j - 1) * sa.L, whi = sa.s + j * sa.L - 1;
+                if (a.want_fwd) {
+                    int64_t hi = (tt > LLONG_MAX - a.delta) ? LLONG_MAX : tt + a.delta;
+                    hi = hi < whi ? hi : whi;
+                    sweep_fwd<MODE>(G, sa, i, le, y, d, tt, hi, nullptr, &one);
+                }
+                if (a.want_bwd) {
+                    int64_t lo = (tt < LLONG_MIN + a.delta) ? LLONG_MIN : tt - a.delta;
+                    lo = lo > wlo ? lo : wlo;
+                    sweep_bwd<MODE>(G, sa, i, lb, y, d, tt, lo, nullptr, &one);
+                }
             }
-            if (a.want_bwd) {
-                int64_t lo = (tt < LLONG_MIN + a.delta) ? LLONG_MIN : tt - a.delta;
-                lo = lo > wlo ? lo : wlo;
-                sweep_bwd<MODE>(G, sa, i, lb, y, d, tt, lo, lds);
+            wave_sum_u128(one.cl, one.ch);
+            wave_sum_u128(one.wl, one.wh);
+            if (lane == 0) {
+                uint64_t *o = a.out + 4 * k;
+                if (one.cl | one.ch) tm_atomic_add_u128(o, o + 1, one.cl, one.ch);
+                if (one.wl | one.wh) tm_atomic_add_u128(o + 2, o + 3, one.wl, one.wh);
             }
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint64_t *o = a.out + 4 * k;
-            uint64_t c0 = lds[4 * a.code], c1 = lds[4 * a.code + 1];
-            uint64_t w0 = lds[4 * a.code + 2], w1 = lds[4 * a.code + 3];
-            if (c0 | c1) tm_atomic_add_u128(o, o + 1, c0, c1);
-            if (w0 | w1) tm_atomic_add_u128(o + 2, o + 3, w0, w1);
-        }
-        __syncthreads();
     }
 }
 
@@ -230,7 +240,7 @@ struct BatchPlan {
     int64_t tile = 0, bpc = 0, n_seeds = 0, delta = 0, L = 0, J = 0, n_tiles = 0;
     int32_t code = -1;
     double p = 0;
-    DevBuf tiles, tnode, seeds, shifts, kp, tasks, qctl, out, wfx, z;
+    DevBuf tiles, tnode, seeds, shifts, kp, qctl, out, wfx, z;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap_stream = nullptr;
     ~BatchPlan() {
@@ -265,7 +275,6 @@ BatchArgs make_args(BatchPlan &B, uint32_t want_fwd, int32_t want_bwd) {
     a.tiles = B.tiles.as<int64_t>();
     a.tile_node = B.tnode.as<int32_t>();
     a.n_tiles = B.n_tiles;
-    a.tasks = B.tasks.as<int64_t>();
     a.qctl = B.qctl.as<unsigned long long>();
     a.out = B.out.as<uint64_t>();
     a.wfx = B.wfx.as<uint64_t>();
@@ -295,8 +304,6 @@ tm_status enqueue(const tm_graph *g, BatchPlan &B, hipStream_t st) {
                        0ull);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, a.qctl, (int64_t)2, 0ull);
     hipLaunchKernelGGL(k_batch_flags, dim3((unsigned)B.n_seeds), dim3(BT_TPB), 0, st, a);
-    int64_t nt = B.n_seeds * B.n_tiles;
-    if (nt > 0) hipLaunchKernelGGL(k_batch_tasks, dim3(tm_blocks(nt, 256)), dim3(256), 0, st, G, a);
     int dev = g->device, ncu = 0;
     TM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     if (ncu <= 0) ncu = 256;
@@ -329,7 +336,6 @@ tm_status build_plan(const tm_graph *g, BatchPlan &B, hipStream_t st) {
     TM_TRY(B.seeds.alloc((size_t)B.n_seeds * 8));
     TM_TRY(B.shifts.alloc((size_t)B.n_seeds * 8));
     TM_TRY(B.kp.alloc((size_t)B.n_seeds * (B.J + 1) * 4));
-    TM_TRY(B.tasks.alloc((size_t)(B.n_seeds * ntile > 0 ? B.n_seeds * ntile : 1) * 8));
     TM_TRY(B.qctl.alloc(64));
     TM_TRY(B.out.alloc((size_t)B.n_seeds * 32));
     TM_TRY(B.wfx.alloc((size_t)(B.delta + 1) * 8));
@@ -446,9 +452,9 @@ tm_status tm_batch_tune(const tm_graph *g, int32_t code, int64_t delta, int64_t 
             return TM_OK;
         }
     }
-    const int64_t tiles[] = {256, 1024, 4096};
-    const int64_t bpcs[] = {2, 8};
-    const int64_t NS = 4;
+    const int64_t tiles[] = {64, 256, 1024};
+    const int64_t bpcs[] = {8, 16};
+    const int64_t NS = 2;
     uint64_t seeds[NS];
     for (int i = 0; i < NS; ++i) seeds[i] = 0x5EED0000ull + (uint64_t)i;
     double best = 1e300;
@@ -485,7 +491,7 @@ tm_status tm_batch_tune(const tm_graph *g, int32_t code, int64_t delta, int64_t 
         // tuning plans (8 seeds, uncaptured) are not needed any more
         std::lock_guard<std::mutex> lk(C.mu);
         for (auto it = C.plans.begin(); it != C.plans.end();) {
-            if (std::get<0>(it->first) == g && std::get<5>(it->first) == 4 && !it->second->exec)
+            if (std::get<0>(it->first) == g && std::get<5>(it->first) == 2 && !it->second->exec)
                 it = C.plans.erase(it);
             else
                 ++it;

@@ -96,24 +96,34 @@ struct tm_graph {
     DevBuf inc_t;    // int64[2 m_nl]
     DevBuf inc_twin; // uint32[2 m_nl]: position of the same edge in its other endpoint's list
 
-    // unordered pair hash (open addressing, linear probing): key
-    // (min << 32 | max), value the directed pair ids (min -> max, max -> min),
-    // -1 when absent
-    DevBuf ph_key;   // uint64[ph_cap], ~0 = empty
-    DevBuf ph_val;   // int32[2 ph_cap]
+    // unordered pair hash (open addressing, linear probing): slot = key
+    // (min << 32 | max, ~0 when empty) and the directed pair ids (min -> max,
+    // max -> min; -1 when absent)
+    DevBuf ph_slot;  // PairSlot[ph_cap]
     int64_t ph_cap = 0;
     // per directed pair time buckets: bucket b of pair p covers times
     // [t_first + b 2^shift, t_first + (b+1) 2^shift); pb_idx holds, per bucket,
     // the index (relative to the pair's first entry) of its first entry, plus
     // a sentinel equal to the pair's size
-    DevBuf pb_tfirst;  // int64[S]
-    DevBuf pb_meta;    // int32[2 S]: shift, number of buckets
-    DevBuf pb_off;     // int64[S]: first bucket of the pair in pb_idx
-    DevBuf pb_idx;     // int32[sum (nb + 1)]
+    DevBuf pmeta;    // PairMeta[S]
+    DevBuf pb_idx;   // int32[sum (nb + 1)]
 
     // reusable per-graph workspace for queries
     DevBuf ws;
     int64_t device_bytes = 0;
+};
+
+struct __attribute__((aligned(16))) PairSlot {
+    uint64_t key;
+    int32_t fwd, rev;
+};
+
+struct __attribute__((aligned(32))) PairMeta {
+    int64_t t0;    // time of the pair's first entry
+    int64_t base;  // index of its first entry in pr_t
+    int64_t boff;  // its first bucket in pb_idx
+    int32_t shift; // bucket width 2^shift
+    int32_t nb;    // buckets (pb_idx[boff + nb] = number of entries)
 };
 
 // Plain-pointer view of a graph for kernels.
@@ -125,8 +135,8 @@ struct DevGraph {
     const int64_t *in_off; const int32_t *in_nbr; const int64_t *in_t;
     const int64_t *sp_off; const int32_t *sp_nbr; const int64_t *sp_beg; const int64_t *pr_t;
     const int64_t *inc_off; const uint32_t *inc_nd; const int64_t *inc_t; const uint32_t *inc_twin;
-    const uint64_t *ph_key; const int32_t *ph_val; int64_t ph_cap;
-    const int64_t *pb_tfirst; const int32_t *pb_meta; const int64_t *pb_off; const int32_t *pb_idx;
+    const PairSlot *ph_slot; int64_t ph_cap;
+    const PairMeta *pmeta; const int32_t *pb_idx;
 };
 
 __device__ inline uint64_t tm_pair_hash(uint64_t key, int64_t cap) {

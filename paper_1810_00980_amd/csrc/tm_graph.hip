@@ -190,8 +190,17 @@ __device__ inline int32_t pair_src(const int64_t *sp_off, int64_t n, int64_t p) 
     return (int32_t)lo;
 }
 
-__global__ void k_pair_hash_insert(const int64_t *sp_off, const int32_t *sp_nbr, int64_t S, int64_t n, uint64_t *keys,
-                                   int32_t *vals, int64_t cap) {
+__global__ void k_slot_init(PairSlot *slots, int64_t cap) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cap) {
+        slots[i].key = ~0ull;
+        slots[i].fwd = -1;
+        slots[i].rev = -1;
+    }
+}
+
+__global__ void k_pair_hash_insert(const int64_t *sp_off, const int32_t *sp_nbr, int64_t S, int64_t n, PairSlot *slots,
+                                   int64_t cap) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= S) return;
     uint32_t u = (uint32_t)pair_src(sp_off, n, p), v = (uint32_t)sp_nbr[p];
@@ -199,13 +208,27 @@ __global__ void k_pair_hash_insert(const int64_t *sp_off, const int32_t *sp_nbr,
     uint64_t key = ((uint64_t)a << 32) | b;
     uint64_t h = tm_pair_hash(key, cap);
     for (int64_t probe = 0; probe < cap; ++probe) {
-        unsigned long long prev = atomicCAS((unsigned long long *)&keys[h], ~0ull, (unsigned long long)key);
+        unsigned long long prev = atomicCAS((unsigned long long *)&slots[h].key, ~0ull, (unsigned long long)key);
         if (prev == ~0ull || prev == key) {
-            vals[2 * h + (u < v ? 0 : 1)] = (int32_t)p;
+            if (u < v) slots[h].fwd = (int32_t)p;
+            else slots[h].rev = (int32_t)p;
             return;
         }
         h = (h + 1) & (uint64_t)(cap - 1);
     }
+}
+
+__global__ void k_pair_meta_pack(const int64_t *sp_beg, const int64_t *tfirst, const int32_t *meta,
+                                 const int64_t *boff, int64_t S, PairMeta *pm) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= S) return;
+    PairMeta m;
+    m.t0 = tfirst[p];
+    m.base = sp_beg[p];
+    m.boff = boff[p];
+    m.shift = meta[2 * p];
+    m.nb = meta[2 * p + 1];
+    pm[p] = m;
 }
 
 // per pair: first time, bucket shift (about two entries per bucket), count
@@ -411,26 +434,23 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
         int64_t cap = 1024;
         while (cap < 2 * S) cap <<= 1;
         g->ph_cap = cap;
-        TM_TRY(g->ph_key.alloc((size_t)cap * 8));
-        TM_TRY(g->ph_val.alloc((size_t)cap * 8));
-        hipLaunchKernelGGL(k_fill_u64, dim3(tm_blocks(cap, TPB)), dim3(TPB), 0, st, g->ph_key.as<uint64_t>(), cap, ~0ull);
+        TM_TRY(g->ph_slot.alloc((size_t)cap * sizeof(PairSlot)));
+        hipLaunchKernelGGL(k_slot_init, dim3(tm_blocks(cap, TPB)), dim3(TPB), 0, st, g->ph_slot.as<PairSlot>(), cap);
         TM_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_fill_i32, dim3(tm_blocks(2 * cap, TPB)), dim3(TPB), 0, st, g->ph_val.as<int32_t>(), 2 * cap,
-                           (int32_t)-1);
-        TM_HIP(hipGetLastError());
-        TM_TRY(g->pb_tfirst.alloc((size_t)S * 8));
-        TM_TRY(g->pb_meta.alloc((size_t)S * 8));
-        TM_TRY(g->pb_off.alloc((size_t)(S + 1) * 8));
+        DevBuf tfirst, meta, boff;
+        TM_TRY(tfirst.alloc((size_t)S * 8));
+        TM_TRY(meta.alloc((size_t)S * 8));
+        TM_TRY(boff.alloc((size_t)(S + 1) * 8));
+        TM_TRY(g->pmeta.alloc((size_t)(S > 0 ? S : 1) * sizeof(PairMeta)));
         int64_t nbk_total = 0;
         if (S > 0) {
             hipLaunchKernelGGL(k_pair_hash_insert, dim3(tm_blocks(S, TPB)), dim3(TPB), 0, st, g->sp_off.as<int64_t>(),
-                               g->sp_nbr.as<int32_t>(), S, n, g->ph_key.as<uint64_t>(), g->ph_val.as<int32_t>(), cap);
+                               g->sp_nbr.as<int32_t>(), S, n, g->ph_slot.as<PairSlot>(), cap);
             TM_HIP(hipGetLastError());
             hipLaunchKernelGGL(k_pair_bucket_meta, dim3(tm_blocks(S, TPB)), dim3(TPB), 0, st, g->sp_beg.as<int64_t>(),
-                               g->pr_t.as<int64_t>(), S, g->pb_tfirst.as<int64_t>(), g->pb_meta.as<int32_t>(),
-                               g->pb_off.as<int64_t>());
+                               g->pr_t.as<int64_t>(), S, tfirst.as<int64_t>(), meta.as<int32_t>(), boff.as<int64_t>());
             TM_HIP(hipGetLastError());
-            TM_TRY(tm_scan_i64(g->pb_off.as<int64_t>(), S, cnt.as<int64_t>(), st));
+            TM_TRY(tm_scan_i64(boff.as<int64_t>(), S, cnt.as<int64_t>(), st));
             TM_HIP(hipMemcpyAsync(&nbk_total, cnt.p, 8, hipMemcpyDeviceToHost, st));
             TM_HIP(hipStreamSynchronize(st));
         }
@@ -438,8 +458,11 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
         if (S > 0) {
             hipLaunchKernelGGL(k_pair_bucket_fill, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, g->sp_off.as<int64_t>(),
                                g->sp_nbr.as<int32_t>(), g->sp_beg.as<int64_t>(), g->pr_t.as<int64_t>(), S, m_nl,
-                               g->pb_tfirst.as<int64_t>(), g->pb_meta.as<int32_t>(), g->pb_off.as<int64_t>(),
-                               g->pb_idx.as<int32_t>());
+                               tfirst.as<int64_t>(), meta.as<int32_t>(), boff.as<int64_t>(), g->pb_idx.as<int32_t>());
+            TM_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_pair_meta_pack, dim3(tm_blocks(S, TPB)), dim3(TPB), 0, st, g->sp_beg.as<int64_t>(),
+                               tfirst.as<int64_t>(), meta.as<int32_t>(), boff.as<int64_t>(), S,
+                               g->pmeta.as<PairMeta>());
             TM_HIP(hipGetLastError());
         }
         TM_HIP(hipStreamSynchronize(st));
@@ -480,8 +503,7 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
     }
     const DevBuf *all[] = {&g->es_src, &g->es_dst, &g->es_t, &g->pos_of, &g->out_off, &g->out_nbr, &g->out_t,
                            &g->in_off, &g->in_nbr, &g->in_t, &g->sp_off, &g->sp_nbr, &g->sp_beg, &g->pr_t,
-                           &g->inc_off, &g->inc_nd, &g->inc_t, &g->inc_twin, &g->ph_key, &g->ph_val, &g->pb_tfirst,
-                           &g->pb_meta, &g->pb_off, &g->pb_idx};
+                           &g->inc_off, &g->inc_nd, &g->inc_t, &g->inc_twin, &g->ph_slot, &g->pmeta, &g->pb_idx};
     int64_t tot = 0;
     for (const DevBuf *b : all) tot += (int64_t)b->bytes;
     g->device_bytes = tot;
@@ -500,8 +522,8 @@ DevGraph dev_view(const tm_graph *g) {
     v.pr_t = g->pr_t.as<int64_t>();
     v.inc_off = g->inc_off.as<int64_t>(); v.inc_nd = g->inc_nd.as<uint32_t>(); v.inc_t = g->inc_t.as<int64_t>();
     v.inc_twin = g->inc_twin.as<uint32_t>();
-    v.ph_key = g->ph_key.as<uint64_t>(); v.ph_val = g->ph_val.as<int32_t>(); v.ph_cap = g->ph_cap;
-    v.pb_tfirst = g->pb_tfirst.as<int64_t>(); v.pb_meta = g->pb_meta.as<int32_t>(); v.pb_off = g->pb_off.as<int64_t>();
+    v.ph_slot = g->ph_slot.as<PairSlot>(); v.ph_cap = g->ph_cap;
+    v.pmeta = g->pmeta.as<PairMeta>();
     v.pb_idx = g->pb_idx.as<int32_t>();
     return v;
 }

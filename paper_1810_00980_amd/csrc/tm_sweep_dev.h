@@ -63,20 +63,23 @@ __device__ inline int64_t owner_of(const int64_t *off, int64_t n, int64_t i) {
     return lo;
 }
 
+// number of entries of directed pair p
+__device__ inline int64_t pair_size(const DevGraph &G, int32_t p) {
+    const PairMeta m = G.pmeta[p];
+    return G.pb_idx[m.boff + m.nb];
+}
+
 // number of entries of directed pair p with time < t
 __device__ inline int64_t pair_before(const DevGraph &G, int32_t p, int64_t t) {
-    int64_t t0 = G.pb_tfirst[p];
-    if (t <= t0) return 0;
-    int shift = G.pb_meta[2 * p];
-    int64_t nb = G.pb_meta[2 * p + 1];
-    int64_t b = (t - t0) >> shift;
-    int64_t base = G.sp_beg[p];
-    if (b >= nb) return G.sp_beg[p + 1] - base;
-    const int32_t *bi = G.pb_idx + G.pb_off[p];
+    const PairMeta m = G.pmeta[p];
+    if (t <= m.t0) return 0;
+    const int32_t *bi = G.pb_idx + m.boff;
+    int64_t b = (t - m.t0) >> m.shift;
+    if (b >= m.nb) return bi[m.nb];
     int64_t lo = bi[b], hi = bi[b + 1];
     while (lo < hi) {
         int64_t mid = (lo + hi) >> 1;
-        if (G.pr_t[base + mid] < t) lo = mid + 1;
+        if (G.pr_t[m.base + mid] < t) lo = mid + 1;
         else hi = mid;
     }
     return lo;
@@ -91,14 +94,13 @@ __device__ inline void pair_ids(const DevGraph &G, uint32_t u, uint32_t v, int32
     *puv = -1;
     *pvu = -1;
     for (int64_t probe = 0; probe < cap; ++probe) {
-        uint64_t k = G.ph_key[h];
-        if (k == key) {
-            int32_t f = G.ph_val[2 * h], r = G.ph_val[2 * h + 1];  // a -> b, b -> a
-            *puv = u < v ? f : r;
-            *pvu = u < v ? r : f;
+        const PairSlot sl = G.ph_slot[h];
+        if (sl.key == key) {
+            *puv = u < v ? sl.fwd : sl.rev;
+            *pvu = u < v ? sl.rev : sl.fwd;
             return;
         }
-        if (k == ~0ull) return;
+        if (sl.key == ~0ull) return;
         h = (h + 1) & (uint64_t)(cap - 1);
     }
 }
@@ -106,7 +108,7 @@ __device__ inline void pair_ids(const DevGraph &G, uint32_t u, uint32_t v, int32
 // entries of pair p with tlo < t <= thi
 __device__ inline uint64_t pair_after_upto(const DevGraph &G, int32_t p, int64_t tlo, int64_t thi) {
     if (p < 0) return 0;
-    int64_t up = (thi == LLONG_MAX) ? (G.sp_beg[p + 1] - G.sp_beg[p]) : pair_before(G, p, thi + 1);
+    int64_t up = (thi == LLONG_MAX) ? pair_size(G, p) : pair_before(G, p, thi + 1);
     return (uint64_t)(up - pair_before(G, p, tlo + 1));
 }
 
@@ -165,12 +167,26 @@ __device__ inline void lds_add_u128(unsigned long long *lo, unsigned long long *
     if (vhi) atomicAdd(hi, (unsigned long long)vhi);
 }
 
+// Per-lane sums of one motif code (count and weighted sum, 128 bits each),
+// used by the batched kernel instead of the shared accumulators.
+struct OneCode {
+    int32_t code;
+    uint64_t cl, ch, wl, wh;
+};
+
 template <int MODE, int NC>
-__device__ inline void flush(const Acc<MODE, NC> &A, const int *codes, unsigned long long *lds) {
+__device__ inline void flush(const Acc<MODE, NC> &A, const int *codes, unsigned long long *lds, OneCode *one) {
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         int code = codes[k];
         if (code < 0) continue;
+        if (one) {
+            if (code == one->code) {
+                tm_add_u128(one->cl, one->ch, A.c[k], 0);
+                if constexpr (MODE == MODE_WEIGHT) tm_add_u128(one->wl, one->wh, A.wl[k], A.wh[k]);
+            }
+            continue;
+        }
         if (A.c[k]) lds_add_u128(&lds[4 * code], &lds[4 * code + 1], A.c[k], 0);
         if constexpr (MODE == MODE_WEIGHT) {
             if (A.wl[k] | A.wh[k]) lds_add_u128(&lds[4 * code + 2], &lds[4 * code + 3], A.wl[k], A.wh[k]);
@@ -187,7 +203,8 @@ __device__ inline uint64_t weight_of(const SweepArgs &a, int64_t dlt) {
 // forward sweep of one anchor (codes 0..27)
 template <int MODE>
 __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t i, int64_t end, uint32_t y1,
-                                 uint32_t d1, int64_t t1, int64_t hi, unsigned long long *lds) {
+                                 uint32_t d1, int64_t t1, int64_t hi, unsigned long long *lds,
+                                 OneCode *one = nullptr) {
     // slots: 0..3 two-node [2*d2+d3], 4..7 star B, 8..11 star A, 12..15 triangle
     Acc<MODE, 16> A;
     A.clear();
@@ -291,13 +308,14 @@ __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t 
         codes[8 + k] = 12 + 4 * (int)d1 + k;
         codes[12 + k] = 20 + 4 * (int)d1 + k;
     }
-    flush<MODE, 16>(A, codes, lds);
+    flush<MODE, 16>(A, codes, lds, one);
 }
 
 // backward sweep of one anchor (codes 28..35): star with e2 on e3's pair
 template <int MODE>
 __device__ inline void sweep_bwd(const DevGraph &G, const SweepArgs &a, int64_t jj, int64_t beg, uint32_t y3,
-                                 uint32_t d3, int64_t t3, int64_t lo, unsigned long long *lds) {
+                                 uint32_t d3, int64_t t3, int64_t lo, unsigned long long *lds,
+                                 OneCode *one = nullptr) {
     // slots [2*d1 + d2]: v is added at slot (2*d1 + d2), d1 runtime -> use base 2*d2 with dsel = d1
     Acc<MODE, 4> A;  // slot index: d2 * 2 + d1
     A.clear();
@@ -341,7 +359,7 @@ __device__ inline void sweep_bwd(const DevGraph &G, const SweepArgs &a, int64_t 
     codes[1] = 28 + 4 + 0 + (int)d3;  // d2=0,d1=1
     codes[2] = 28 + 0 + 2 + (int)d3;  // d2=1,d1=0
     codes[3] = 28 + 4 + 2 + (int)d3;  // d2=1,d1=1
-    flush<MODE, 4>(A, codes, lds);
+    flush<MODE, 4>(A, codes, lds, one);
 }
 
 }  // namespace sweepdev
