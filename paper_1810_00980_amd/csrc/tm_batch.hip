@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(BT_TPB) k_batch_sweep(DevGraph G, BatchArgs a)
                 if (a.want_fwd) {
                     int64_t hi = (tt > LLONG_MAX - a.delta) ? LLONG_MAX : tt + a.delta;
                     hi = hi < whi ? hi : whi;
-                    sweep_fwd<MODE>(G, sa, i, le, y, d, tt, hi, nullptr, &one);
+                    sweep_fwd<MODE>(G, sa, i, le, y, d, tt, hi, wlo, nullptr, &one);
                 }
                 if (a.want_bwd) {
                     int64_t lo = (tt < LLONG_MIN + a.delta) ? LLONG_MIN : tt - a.delta;

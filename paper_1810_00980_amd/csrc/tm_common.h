@@ -95,6 +95,8 @@ struct tm_graph {
     DevBuf inc_nd;   // uint32[2 m_nl]: other endpoint | (dir << 31)
     DevBuf inc_t;    // int64[2 m_nl]
     DevBuf inc_twin; // uint32[2 m_nl]: position of the same edge in its other endpoint's list
+    DevBuf inc_hi;   // uint8[2 m_nl]: 1 when the other endpoint ranks above the list's owner
+                     // (rank = (incidence-list length, node id))
 
     // unordered pair hash (open addressing, linear probing): slot = key
     // (min << 32 | max, ~0 when empty) and the directed pair ids (min -> max,
@@ -135,6 +137,7 @@ struct DevGraph {
     const int64_t *in_off; const int32_t *in_nbr; const int64_t *in_t;
     const int64_t *sp_off; const int32_t *sp_nbr; const int64_t *sp_beg; const int64_t *pr_t;
     const int64_t *inc_off; const uint32_t *inc_nd; const int64_t *inc_t; const uint32_t *inc_twin;
+    const uint8_t *inc_hi;
     const PairSlot *ph_slot; int64_t ph_cap;
     const PairMeta *pmeta; const int32_t *pb_idx;
 };

@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(SW_TPB) k_sweep3(DevGraph G, SweepArgs a) {
                 if (FWD) {
                     int64_t hi = (t > LLONG_MAX - a.delta) ? LLONG_MAX : t + a.delta;
                     hi = hi < whi ? hi : whi;
-                    sweep_fwd<MODE>(G, a, i, le, y, d, t, hi, lds);
+                    sweep_fwd<MODE>(G, a, i, le, y, d, t, hi, wlo, lds);
                 } else {
                     int64_t lo = (t < LLONG_MIN + a.delta) ? LLONG_MIN : t - a.delta;
                     lo = lo > wlo ? lo : wlo;

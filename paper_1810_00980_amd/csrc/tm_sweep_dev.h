@@ -200,62 +200,66 @@ __device__ inline uint64_t weight_of(const SweepArgs &a, int64_t dlt) {
     return 0;
 }
 
+// add v to tc[4*d1 + 2*d2 + d3] (runtime index, kept in registers)
+__device__ inline void tc_add(uint64_t *tc, uint32_t idx, uint64_t v) {
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) tc[k] += (k == idx) ? v : 0;
+}
+
+// Exact triangle counts at the lowest-ranked node.  Entries i (time ti) and
+// j (time tj > ti) of v's list lead to distinct nodes yi, yj that both rank
+// above v; every triangle instance with two edges at v has them as (i, j)
+// for exactly one of three roles of v, and its third edge lies on the pair
+// {yi, yj}:
+//   v = x  (shared by first and last edge): middle in (ti, tj)
+//   v = y1 (first and middle edge at v):    last edge in (tj, hi]
+//   v = y3 (middle and last edge at v):     first edge in [max(tj - delta, lo_win), ti)
+// Counting each instance only at its lowest-ranked node counts it once, and
+// high-degree nodes, whose lists are long, never do the pair lookups.
+__device__ inline void tri_rank(const DevGraph &G, uint32_t yi, uint32_t di, int64_t ti, uint32_t yj, uint32_t dj,
+                                int64_t tj, int64_t hi, int64_t lo_win, int64_t delta, uint64_t *tc) {
+    int32_t pp[2];
+    pair_ids(G, yi, yj, &pp[0], &pp[1]);  // yi -> yj, yj -> yi
+    int64_t lo3 = (tj < LLONG_MIN + delta) ? LLONG_MIN : tj - delta;
+    lo3 = lo3 > lo_win ? lo3 : lo_win;
+#pragma unroll
+    for (uint32_t dir = 0; dir < 2; ++dir) {
+        int32_t p = pp[dir];
+        if (p < 0) continue;
+        int64_t f_ti = pair_before(G, p, ti);
+        int64_t f_ti1 = (ti == LLONG_MAX) ? pair_size(G, p) : pair_before(G, p, ti + 1);
+        int64_t f_tj = pair_before(G, p, tj);
+        int64_t f_tj1 = (tj == LLONG_MAX) ? pair_size(G, p) : pair_before(G, p, tj + 1);
+        int64_t f_hi1 = (hi == LLONG_MAX) ? pair_size(G, p) : pair_before(G, p, hi + 1);
+        int64_t f_lo3 = pair_before(G, p, lo3);
+        // v = x: d1 = di, d2 = dir, d3 = dj
+        tc_add(tc, 4 * di + 2 * dir + dj, (uint64_t)(f_tj - f_ti1));
+        // v = y1: d1 = 1 - di, d2 = dj, d3 = dir
+        tc_add(tc, 4 * (1 - di) + 2 * dj + dir, (uint64_t)(f_hi1 - f_tj1));
+        // v = y3: d1 = 1 - dir, d2 = 1 - di, d3 = 1 - dj
+        tc_add(tc, 4 * (1 - dir) + 2 * (1 - di) + (1 - dj), (uint64_t)(f_ti - f_lo3));
+    }
+}
+
 // forward sweep of one anchor (codes 0..27)
 template <int MODE>
 __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t i, int64_t end, uint32_t y1,
-                                 uint32_t d1, int64_t t1, int64_t hi, unsigned long long *lds,
+                                 uint32_t d1, int64_t t1, int64_t hi, int64_t lo_win, unsigned long long *lds,
                                  OneCode *one = nullptr) {
     // slots: 0..3 two-node [2*d2+d3], 4..7 star B, 8..11 star A, 12..15 triangle
     Acc<MODE, 16> A;
     A.clear();
     const bool two = (a.want_fwd & 1u) && d1 == 0;
     const bool sb = a.want_fwd & 2u, sa = a.want_fwd & 4u, tri = a.want_fwd & 8u;
-    // Exact totals need no duration per last edge, so the triangle class may
-    // walk the smaller of the two windows: x's list (last edges e3, middle
-    // counted on pair {y1, y3}) or y1's list (middles e2 = y1 - y3, last
-    // edges counted on pair {x, y3}).
+    // Exact totals (no duration per instance needed) count triangles at their
+    // lowest-ranked node (tri_rank); estimates and histograms keep one pair
+    // lookup per last edge of x's list, which carries each duration.
     bool tri_x = tri;
+    bool tri_r = false;
+    uint64_t tc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if constexpr (MODE == MODE_COUNT) {
-        if (tri) {
-            int64_t a0 = i + 1, a1 = end;
-            while (a0 < a1) {
-                int64_t mid = (a0 + a1) >> 1;
-                if (G.inc_t[mid] <= hi) a0 = mid + 1;
-                else a1 = mid;
-            }
-            int64_t tw = G.inc_twin[i];
-            int64_t yend = G.inc_off[y1 + 1];
-            int64_t b0 = tw + 1, b1 = yend;
-            while (b0 < b1) {
-                int64_t mid = (b0 + b1) >> 1;
-                if (G.inc_t[mid] < hi) b0 = mid + 1;
-                else b1 = mid;
-            }
-            if (b0 - (tw + 1) < a0 - (i + 1)) {
-                tri_x = false;
-                uint32_t x = G.inc_nd[tw] & 0x7FFFFFFFu;  // the twin entry's other endpoint is x
-                uint32_t ylast = 0xFFFFFFFFu;
-                int32_t px3 = -1, p3x = -1;
-                for (int64_t k = tw + 1; k < b0; ++k) {
-                    int64_t tk = G.inc_t[k];
-                    if (tk == t1) continue;
-                    uint32_t nd = G.inc_nd[k];
-                    uint32_t y3 = nd & 0x7FFFFFFFu, d2 = nd >> 31;
-                    if (y3 == x) continue;
-                    if (y3 != ylast) {
-                        pair_ids(G, x, y3, &px3, &p3x);
-                        ylast = y3;
-                    }
-                    uint64_t c0 = pair_after_upto(G, px3, tk, hi);  // e3 = x -> y3
-                    uint64_t c1 = pair_after_upto(G, p3x, tk, hi);  // e3 = y3 -> x
-                    // slot 12 + 2*d2 + d3
-                    A.c[12] += d2 ? 0 : c0;
-                    A.c[13] += d2 ? 0 : c1;
-                    A.c[14] += d2 ? c0 : 0;
-                    A.c[15] += d2 ? c1 : 0;
-                }
-            }
-        }
+        tri_x = false;
+        tri_r = tri && G.inc_hi[i];
     }
     uint64_t cs0 = 0, cs1 = 0, ca0 = 0, ca1 = 0;  // middles before the current time group
     uint64_t ps0 = 0, ps1 = 0, pa0 = 0, pa1 = 0;  // entries of the current time group
@@ -289,6 +293,7 @@ __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t 
                 acc_add<MODE, 16>(A, 8, dj, cs0, w, a.hist, 12 + 4 * (int)d1, dlt, a.delta);
                 acc_add<MODE, 16>(A, 10, dj, cs1, w, a.hist, 14 + 4 * (int)d1, dlt, a.delta);
             }
+            if (tri_r && G.inc_hi[j]) tri_rank(G, y1, d1, t1, yj, dj, tj, hi, lo_win, a.delta, tc);
             if (tri_x) {
                 int32_t p01, p10;
                 pair_ids(G, y1, yj, &p01, &p10);
@@ -309,6 +314,19 @@ __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t 
         codes[12 + k] = 20 + 4 * (int)d1 + k;
     }
     flush<MODE, 16>(A, codes, lds, one);
+    if constexpr (MODE == MODE_COUNT) {
+        if (tri) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (!tc[k]) continue;
+                if (one) {
+                    if (one->code == 20 + k) tm_add_u128(one->cl, one->ch, tc[k], 0);
+                } else {
+                    lds_add_u128(&lds[4 * (20 + k)], &lds[4 * (20 + k) + 1], tc[k], 0);
+                }
+            }
+        }
+    }
 }
 
 // backward sweep of one anchor (codes 28..35): star with e2 on e3's pair
