@@ -85,6 +85,35 @@ __device__ inline int64_t pair_before(const DevGraph &G, int32_t p, int64_t t) {
     return lo;
 }
 
+// entries of pair p with time < t (*lt) and with time <= t (*le): one bucket
+// lookup, then the entries equal to t (usually none) are stepped over
+__device__ inline void pair_before_at(const DevGraph &G, int32_t p, int64_t t, int64_t *lt, int64_t *le) {
+    const PairMeta m = G.pmeta[p];
+    const int32_t *bi = G.pb_idx + m.boff;
+    int64_t n = bi[m.nb];
+    int64_t lo;
+    if (t <= m.t0) {
+        lo = 0;
+    } else {
+        int64_t b = (t - m.t0) >> m.shift;
+        if (b >= m.nb) {
+            lo = n;
+        } else {
+            lo = bi[b];
+            int64_t hi = bi[b + 1];
+            while (lo < hi) {
+                int64_t mid = (lo + hi) >> 1;
+                if (G.pr_t[m.base + mid] < t) lo = mid + 1;
+                else hi = mid;
+            }
+        }
+    }
+    int64_t e = lo;
+    while (e < n && G.pr_t[m.base + e] == t) ++e;
+    *lt = lo;
+    *le = e;
+}
+
 // directed pair ids (u -> v, v -> u) of the unordered pair {u, v}; -1 if absent
 __device__ inline void pair_ids(const DevGraph &G, uint32_t u, uint32_t v, int32_t *puv, int32_t *pvu) {
     uint32_t a = u < v ? u : v, b = u < v ? v : u;
@@ -226,10 +255,9 @@ __device__ inline void tri_rank(const DevGraph &G, uint32_t yi, uint32_t di, int
     for (uint32_t dir = 0; dir < 2; ++dir) {
         int32_t p = pp[dir];
         if (p < 0) continue;
-        int64_t f_ti = pair_before(G, p, ti);
-        int64_t f_ti1 = (ti == LLONG_MAX) ? pair_size(G, p) : pair_before(G, p, ti + 1);
-        int64_t f_tj = pair_before(G, p, tj);
-        int64_t f_tj1 = (tj == LLONG_MAX) ? pair_size(G, p) : pair_before(G, p, tj + 1);
+        int64_t f_ti, f_ti1, f_tj, f_tj1;
+        pair_before_at(G, p, ti, &f_ti, &f_ti1);
+        pair_before_at(G, p, tj, &f_tj, &f_tj1);
         int64_t f_hi1 = (hi == LLONG_MAX) ? pair_size(G, p) : pair_before(G, p, hi + 1);
         int64_t f_lo3 = pair_before(G, p, lo3);
         // v = x: d1 = di, d2 = dir, d3 = dj
