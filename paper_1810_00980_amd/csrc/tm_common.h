@@ -98,16 +98,21 @@ struct tm_graph {
     DevBuf inc_hi;   // uint8[2 m_nl]: 1 when the other endpoint ranks above the list's owner
                      // (rank = (incidence-list length, node id))
 
+    // unordered pairs {a < b}: one time-sorted timeline per pair holding the
+    // edges of both directions; entry e carries its time and the number of
+    // a -> b edges among the pair's earlier entries, and a sentinel entry
+    // after the last one carries the pair's a -> b total
+    int64_t U = 0;   // distinct unordered pairs
+    DevBuf up_ent;   // PairEnt[m_nl + U]
     // unordered pair hash (open addressing, linear probing): slot = key
-    // (min << 32 | max, ~0 when empty) and the directed pair ids (min -> max,
-    // max -> min; -1 when absent)
+    // (min << 32 | max, ~0 when empty) and the unordered pair id
     DevBuf ph_slot;  // PairSlot[ph_cap]
     int64_t ph_cap = 0;
-    // per directed pair time buckets: bucket b of pair p covers times
+    // per unordered pair time buckets: bucket b of pair p covers times
     // [t_first + b 2^shift, t_first + (b+1) 2^shift); pb_idx holds, per bucket,
     // the index (relative to the pair's first entry) of its first entry, plus
     // a sentinel equal to the pair's size
-    DevBuf pmeta;    // PairMeta[S]
+    DevBuf pmeta;    // PairMeta[U]
     DevBuf pb_idx;   // int32[sum (nb + 1)]
 
     // reusable per-graph workspace for queries
@@ -117,12 +122,18 @@ struct tm_graph {
 
 struct __attribute__((aligned(16))) PairSlot {
     uint64_t key;
-    int32_t fwd, rev;
+    int32_t id;    // unordered pair id, -1 when empty
+    int32_t pad;
+};
+
+struct __attribute__((aligned(16))) PairEnt {
+    int64_t t;     // time (LLONG_MAX in the sentinel)
+    int64_t c0;    // a -> b edges among the pair's earlier entries
 };
 
 struct __attribute__((aligned(32))) PairMeta {
     int64_t t0;    // time of the pair's first entry
-    int64_t base;  // index of its first entry in pr_t
+    int64_t base;  // index of its first entry in up_ent
     int64_t boff;  // its first bucket in pb_idx
     int32_t shift; // bucket width 2^shift
     int32_t nb;    // buckets (pb_idx[boff + nb] = number of entries)
@@ -140,6 +151,7 @@ struct DevGraph {
     const uint8_t *inc_hi;
     const PairSlot *ph_slot; int64_t ph_cap;
     const PairMeta *pmeta; const int32_t *pb_idx;
+    const PairEnt *up_ent;
 };
 
 __device__ inline uint64_t tm_pair_hash(uint64_t key, int64_t cap) {

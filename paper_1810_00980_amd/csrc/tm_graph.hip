@@ -193,52 +193,95 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
-// source node of directed pair p: largest u with sp_off[u] <= p
-__device__ inline int32_t pair_src(const int64_t *sp_off, int64_t n, int64_t p) {
-    int64_t lo = 0, hi = n;
-    while (hi - lo > 1) {
-        int64_t mid = (lo + hi) >> 1;
-        if (sp_off[mid] <= p) lo = mid;
-        else hi = mid;
-    }
-    return (int32_t)lo;
-}
-
 __global__ void k_slot_init(PairSlot *slots, int64_t cap) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < cap) {
         slots[i].key = ~0ull;
-        slots[i].fwd = -1;
-        slots[i].rev = -1;
+        slots[i].id = -1;
+        slots[i].pad = 0;
     }
 }
 
-__global__ void k_pair_hash_insert(const int64_t *sp_off, const int32_t *sp_nbr, int64_t S, int64_t n, PairSlot *slots,
-                                   int64_t cap) {
+// unordered pair key (min * n + max) of every non-self-loop edge, in time order
+__global__ void k_upair_keys(const int64_t *nl_pos, int64_t m_nl, const int32_t *es_src, const int32_t *es_dst,
+                             int64_t n, uint64_t *keys, uint32_t *vals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m_nl) {
+        int64_t k = nl_pos[i];
+        uint64_t u = (uint64_t)es_src[k], v = (uint64_t)es_dst[k];
+        keys[i] = (u < v ? u : v) * (uint64_t)n + (u < v ? v : u);
+        vals[i] = (uint32_t)i;
+    }
+}
+
+__device__ inline bool upair_start(const uint64_t *keys, int64_t j) { return j == 0 || keys[j] != keys[j - 1]; }
+
+// after the stable sort by key: pair-start flags and min -> max flags
+__global__ void k_upair_flags(const uint64_t *keys, const uint32_t *vals, int64_t m_nl, const int64_t *nl_pos,
+                              const int32_t *es_src, const int32_t *es_dst, int64_t *bflag, int64_t *c0) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m_nl) {
+        int64_t k = nl_pos[vals[j]];
+        bflag[j] = upair_start(keys, j) ? 1 : 0;
+        c0[j] = es_src[k] < es_dst[k] ? 1 : 0;
+    }
+}
+
+__global__ void k_upair_index(const uint64_t *keys, const int64_t *bscan, int64_t m_nl, uint64_t *u_key,
+                              int64_t *up_beg) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m_nl && upair_start(keys, j)) {
+        int64_t p = bscan[j];
+        u_key[p] = keys[j];
+        up_beg[p] = j;
+    }
+}
+
+// entry j of pair p goes to j + p (each earlier pair has one sentinel); the
+// last entry of a pair also writes the sentinel after it
+__global__ void k_upair_place(const uint64_t *keys, const uint32_t *vals, int64_t m_nl, const int64_t *nl_pos,
+                              const int32_t *es_src, const int32_t *es_dst, const int64_t *es_t,
+                              const int64_t *bscan, const int64_t *g0, const int64_t *up_beg, PairEnt *ent) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m_nl) return;
+    int64_t pid = bscan[j] + (upair_start(keys, j) ? 1 : 0) - 1;
+    int64_t b = up_beg[pid];
+    int64_t k = nl_pos[vals[j]];
+    PairEnt e;
+    e.t = es_t[k];
+    e.c0 = g0[j] - g0[b];
+    ent[j + pid] = e;
+    if (j + 1 == m_nl || keys[j + 1] != keys[j]) {
+        PairEnt z;
+        z.t = LLONG_MAX;
+        z.c0 = e.c0 + (es_src[k] < es_dst[k] ? 1 : 0);
+        ent[j + pid + 1] = z;
+    }
+}
+
+__global__ void k_pair_hash_insert(const uint64_t *u_key, int64_t U, int64_t n, PairSlot *slots, int64_t cap) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= S) return;
-    uint32_t u = (uint32_t)pair_src(sp_off, n, p), v = (uint32_t)sp_nbr[p];
-    uint32_t a = u < v ? u : v, b = u < v ? v : u;
-    uint64_t key = ((uint64_t)a << 32) | b;
+    if (p >= U) return;
+    uint64_t a = u_key[p] / (uint64_t)n, b = u_key[p] % (uint64_t)n;
+    uint64_t key = (a << 32) | b;
     uint64_t h = tm_pair_hash(key, cap);
     for (int64_t probe = 0; probe < cap; ++probe) {
         unsigned long long prev = atomicCAS((unsigned long long *)&slots[h].key, ~0ull, (unsigned long long)key);
-        if (prev == ~0ull || prev == key) {
-            if (u < v) slots[h].fwd = (int32_t)p;
-            else slots[h].rev = (int32_t)p;
+        if (prev == ~0ull) {
+            slots[h].id = (int32_t)p;
             return;
         }
         h = (h + 1) & (uint64_t)(cap - 1);
     }
 }
 
-__global__ void k_pair_meta_pack(const int64_t *sp_beg, const int64_t *tfirst, const int32_t *meta,
-                                 const int64_t *boff, int64_t S, PairMeta *pm) {
+__global__ void k_pair_meta_pack(const int64_t *up_beg, const int64_t *tfirst, const int32_t *meta,
+                                 const int64_t *boff, int64_t U, PairMeta *pm) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= S) return;
+    if (p >= U) return;
     PairMeta m;
     m.t0 = tfirst[p];
-    m.base = sp_beg[p];
+    m.base = up_beg[p] + p;
     m.boff = boff[p];
     m.shift = meta[2 * p];
     m.nb = meta[2 * p + 1];
@@ -246,12 +289,12 @@ __global__ void k_pair_meta_pack(const int64_t *sp_beg, const int64_t *tfirst, c
 }
 
 // per pair: first time, bucket shift (about two entries per bucket), count
-__global__ void k_pair_bucket_meta(const int64_t *sp_beg, const int64_t *pr_t, int64_t S, int64_t *tfirst,
+__global__ void k_pair_bucket_meta(const int64_t *up_beg, const PairEnt *ent, int64_t U, int64_t *tfirst,
                                    int32_t *meta, int64_t *nbk) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= S) return;
-    int64_t b = sp_beg[p], e = sp_beg[p + 1], k = e - b;
-    int64_t t0 = pr_t[b], span = pr_t[e - 1] - t0;
+    if (p >= U) return;
+    int64_t b = up_beg[p], e = up_beg[p + 1], k = e - b, base = b + p;
+    int64_t t0 = ent[base].t, span = ent[base + k - 1].t - t0;
     int64_t target = k / 2 > 1 ? k / 2 : 1;  // buckets wanted
     int shift = 0;
     while (shift < 62 && (span >> shift) + 1 > target) ++shift;
@@ -262,28 +305,20 @@ __global__ void k_pair_bucket_meta(const int64_t *sp_beg, const int64_t *pr_t, i
     nbk[p] = nb + 1;  // with sentinel
 }
 
-// entry i of pair p is the first entry of buckets (bucket(i-1), bucket(i)]
-__global__ void k_pair_bucket_fill(const int64_t *sp_off, const int32_t *sp_nbr, const int64_t *sp_beg,
-                                   const int64_t *pr_t, int64_t S, int64_t m_nl, const int64_t *tfirst,
-                                   const int32_t *meta, const int64_t *boff, int32_t *bidx) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m_nl) return;
-    // pair of entry i: largest p with sp_beg[p] <= i
-    int64_t lo = 0, hi = S;
-    while (hi - lo > 1) {
-        int64_t mid = (lo + hi) >> 1;
-        if (sp_beg[mid] <= i) lo = mid;
-        else hi = mid;
-    }
-    int64_t p = lo, b0 = sp_beg[p], k = sp_beg[p + 1] - b0, r = i - b0;
+// entry r of pair p is the first entry of buckets (bucket(r-1), bucket(r)]
+__global__ void k_pair_bucket_fill(const uint64_t *keys, const int64_t *bscan, const int64_t *up_beg,
+                                   const PairEnt *ent, int64_t m_nl, const int64_t *tfirst, const int32_t *meta,
+                                   const int64_t *boff, int32_t *bidx) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m_nl) return;
+    int64_t p = bscan[j] + (upair_start(keys, j) ? 1 : 0) - 1;
+    int64_t b0 = up_beg[p], k = up_beg[p + 1] - b0, r = j - b0, base = b0 + p;
     int shift = meta[2 * p];
     int32_t nb = meta[2 * p + 1];
-    int64_t bi = (pr_t[i] - tfirst[p]) >> shift;
-    int64_t bprev = r == 0 ? -1 : ((pr_t[i - 1] - tfirst[p]) >> shift);
+    int64_t bi = (ent[base + r].t - tfirst[p]) >> shift;
+    int64_t bprev = r == 0 ? -1 : ((ent[base + r - 1].t - tfirst[p]) >> shift);
     for (int64_t bb = bprev + 1; bb <= bi; ++bb) bidx[boff[p] + bb] = (int32_t)r;
     if (r == k - 1) bidx[boff[p] + nb] = (int32_t)k;  // sentinel (bi == nb - 1 here)
-    (void)sp_off;
-    (void)sp_nbr;
 }
 
 tm_status build_node_lists(tm_graph *g, const int64_t *nl_pos, bool by_src, DevBuf &off, DevBuf &nbr, DevBuf &tl,
@@ -442,40 +477,82 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
         TM_HIP(hipStreamSynchronize(st));
     }
 
-    // pair hash and per-pair time buckets
+    // unordered pair timelines, pair hash and per-pair time buckets
     {
-        int64_t S = g->S, n = g->n;
+        int64_t n = g->n;
+        DevBuf uk, uv, bscan, g0, ukey, ubeg;
+        TM_TRY(uk.alloc((size_t)m_nl * 8));
+        TM_TRY(uv.alloc((size_t)m_nl * 4));
+        TM_TRY(bscan.alloc((size_t)(m_nl + 1) * 8));
+        TM_TRY(g0.alloc((size_t)(m_nl + 1) * 8));
+        int64_t U = 0;
+        if (m_nl > 0) {
+            hipLaunchKernelGGL(k_upair_keys, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, nl.as<int64_t>(), m_nl,
+                               g->es_src.as<int32_t>(), g->es_dst.as<int32_t>(), n, uk.as<uint64_t>(),
+                               uv.as<uint32_t>());
+            TM_HIP(hipGetLastError());
+            TM_TRY(tm_radix_sort(uk.as<uint64_t>(), uv.as<uint32_t>(), m_nl,
+                                 tm_bitlen((uint64_t)n * (uint64_t)n - 1), st));
+            hipLaunchKernelGGL(k_upair_flags, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, uk.as<uint64_t>(),
+                               uv.as<uint32_t>(), m_nl, nl.as<int64_t>(), g->es_src.as<int32_t>(),
+                               g->es_dst.as<int32_t>(), bscan.as<int64_t>(), g0.as<int64_t>());
+            TM_HIP(hipGetLastError());
+            TM_TRY(tm_scan_i64(g0.as<int64_t>(), m_nl, nullptr, st));
+            TM_TRY(tm_scan_i64(bscan.as<int64_t>(), m_nl, cnt.as<int64_t>(), st));
+            TM_HIP(hipMemcpyAsync(&U, cnt.p, 8, hipMemcpyDeviceToHost, st));
+            TM_HIP(hipStreamSynchronize(st));
+        }
+        g->U = U;
+        TM_TRY(ukey.alloc((size_t)(U > 0 ? U : 1) * 8));
+        TM_TRY(ubeg.alloc((size_t)(U + 1) * 8));
+        TM_TRY(g->up_ent.alloc((size_t)(m_nl + U > 0 ? m_nl + U : 1) * sizeof(PairEnt)));
+        if (m_nl > 0) {
+            hipLaunchKernelGGL(k_upair_index, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, uk.as<uint64_t>(),
+                               bscan.as<int64_t>(), m_nl, ukey.as<uint64_t>(), ubeg.as<int64_t>());
+            TM_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_set1, dim3(1), dim3(1), 0, st, ubeg.as<int64_t>() + U, m_nl);
+        TM_HIP(hipGetLastError());
+        if (m_nl > 0) {
+            hipLaunchKernelGGL(k_upair_place, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, uk.as<uint64_t>(),
+                               uv.as<uint32_t>(), m_nl, nl.as<int64_t>(), g->es_src.as<int32_t>(),
+                               g->es_dst.as<int32_t>(), g->es_t.as<int64_t>(), bscan.as<int64_t>(),
+                               g0.as<int64_t>(), ubeg.as<int64_t>(), g->up_ent.as<PairEnt>());
+            TM_HIP(hipGetLastError());
+        }
+
         int64_t cap = 1024;
-        while (cap < 2 * S) cap <<= 1;
+        while (cap < 2 * U) cap <<= 1;
         g->ph_cap = cap;
         TM_TRY(g->ph_slot.alloc((size_t)cap * sizeof(PairSlot)));
         hipLaunchKernelGGL(k_slot_init, dim3(tm_blocks(cap, TPB)), dim3(TPB), 0, st, g->ph_slot.as<PairSlot>(), cap);
         TM_HIP(hipGetLastError());
         DevBuf tfirst, meta, boff;
-        TM_TRY(tfirst.alloc((size_t)S * 8));
-        TM_TRY(meta.alloc((size_t)S * 8));
-        TM_TRY(boff.alloc((size_t)(S + 1) * 8));
-        TM_TRY(g->pmeta.alloc((size_t)(S > 0 ? S : 1) * sizeof(PairMeta)));
+        TM_TRY(tfirst.alloc((size_t)(U > 0 ? U : 1) * 8));
+        TM_TRY(meta.alloc((size_t)(U > 0 ? U : 1) * 8));
+        TM_TRY(boff.alloc((size_t)(U + 1) * 8));
+        TM_TRY(g->pmeta.alloc((size_t)(U > 0 ? U : 1) * sizeof(PairMeta)));
         int64_t nbk_total = 0;
-        if (S > 0) {
-            hipLaunchKernelGGL(k_pair_hash_insert, dim3(tm_blocks(S, TPB)), dim3(TPB), 0, st, g->sp_off.as<int64_t>(),
-                               g->sp_nbr.as<int32_t>(), S, n, g->ph_slot.as<PairSlot>(), cap);
+        if (U > 0) {
+            hipLaunchKernelGGL(k_pair_hash_insert, dim3(tm_blocks(U, TPB)), dim3(TPB), 0, st, ukey.as<uint64_t>(), U,
+                               n, g->ph_slot.as<PairSlot>(), cap);
             TM_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_pair_bucket_meta, dim3(tm_blocks(S, TPB)), dim3(TPB), 0, st, g->sp_beg.as<int64_t>(),
-                               g->pr_t.as<int64_t>(), S, tfirst.as<int64_t>(), meta.as<int32_t>(), boff.as<int64_t>());
+            hipLaunchKernelGGL(k_pair_bucket_meta, dim3(tm_blocks(U, TPB)), dim3(TPB), 0, st, ubeg.as<int64_t>(),
+                               g->up_ent.as<PairEnt>(), U, tfirst.as<int64_t>(), meta.as<int32_t>(),
+                               boff.as<int64_t>());
             TM_HIP(hipGetLastError());
-            TM_TRY(tm_scan_i64(boff.as<int64_t>(), S, cnt.as<int64_t>(), st));
+            TM_TRY(tm_scan_i64(boff.as<int64_t>(), U, cnt.as<int64_t>(), st));
             TM_HIP(hipMemcpyAsync(&nbk_total, cnt.p, 8, hipMemcpyDeviceToHost, st));
             TM_HIP(hipStreamSynchronize(st));
         }
         TM_TRY(g->pb_idx.alloc((size_t)(nbk_total > 0 ? nbk_total : 1) * 4));
-        if (S > 0) {
-            hipLaunchKernelGGL(k_pair_bucket_fill, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, g->sp_off.as<int64_t>(),
-                               g->sp_nbr.as<int32_t>(), g->sp_beg.as<int64_t>(), g->pr_t.as<int64_t>(), S, m_nl,
+        if (U > 0) {
+            hipLaunchKernelGGL(k_pair_bucket_fill, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, uk.as<uint64_t>(),
+                               bscan.as<int64_t>(), ubeg.as<int64_t>(), g->up_ent.as<PairEnt>(), m_nl,
                                tfirst.as<int64_t>(), meta.as<int32_t>(), boff.as<int64_t>(), g->pb_idx.as<int32_t>());
             TM_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_pair_meta_pack, dim3(tm_blocks(S, TPB)), dim3(TPB), 0, st, g->sp_beg.as<int64_t>(),
-                               tfirst.as<int64_t>(), meta.as<int32_t>(), boff.as<int64_t>(), S,
+            hipLaunchKernelGGL(k_pair_meta_pack, dim3(tm_blocks(U, TPB)), dim3(TPB), 0, st, ubeg.as<int64_t>(),
+                               tfirst.as<int64_t>(), meta.as<int32_t>(), boff.as<int64_t>(), U,
                                g->pmeta.as<PairMeta>());
             TM_HIP(hipGetLastError());
         }
@@ -523,7 +600,7 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
     }
     const DevBuf *all[] = {&g->es_src, &g->es_dst, &g->es_t, &g->pos_of, &g->out_off, &g->out_nbr, &g->out_t,
                            &g->in_off, &g->in_nbr, &g->in_t, &g->sp_off, &g->sp_nbr, &g->sp_beg, &g->pr_t,
-                           &g->inc_off, &g->inc_nd, &g->inc_t, &g->inc_twin, &g->inc_hi, &g->ph_slot, &g->pmeta, &g->pb_idx};
+                           &g->inc_off, &g->inc_nd, &g->inc_t, &g->inc_twin, &g->inc_hi, &g->up_ent, &g->ph_slot, &g->pmeta, &g->pb_idx};
     int64_t tot = 0;
     for (const DevBuf *b : all) tot += (int64_t)b->bytes;
     g->device_bytes = tot;
@@ -546,6 +623,7 @@ DevGraph dev_view(const tm_graph *g) {
     v.ph_slot = g->ph_slot.as<PairSlot>(); v.ph_cap = g->ph_cap;
     v.pmeta = g->pmeta.as<PairMeta>();
     v.pb_idx = g->pb_idx.as<int32_t>();
+    v.up_ent = g->up_ent.as<PairEnt>();
     return v;
 }
 

@@ -63,33 +63,15 @@ __device__ inline int64_t owner_of(const int64_t *off, int64_t n, int64_t i) {
     return lo;
 }
 
-// number of entries of directed pair p
-__device__ inline int64_t pair_size(const DevGraph &G, int32_t p) {
-    const PairMeta m = G.pmeta[p];
-    return G.pb_idx[m.boff + m.nb];
-}
+// Unordered pair p = {a < b}: its entries are the edges of both directions,
+// time-sorted.  The counts below come as c[0] = a -> b and c[1] = b -> a.
 
-// number of entries of directed pair p with time < t
-__device__ inline int64_t pair_before(const DevGraph &G, int32_t p, int64_t t) {
-    const PairMeta m = G.pmeta[p];
-    if (t <= m.t0) return 0;
-    const int32_t *bi = G.pb_idx + m.boff;
-    int64_t b = (t - m.t0) >> m.shift;
-    if (b >= m.nb) return bi[m.nb];
-    int64_t lo = bi[b], hi = bi[b + 1];
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (G.pr_t[m.base + mid] < t) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// entries of pair p with time < t (*lt) and with time <= t (*le): one bucket
+// entries of pair p with time < t (lt) and with time <= t (le): one bucket
 // lookup, then the entries equal to t (usually none) are stepped over
-__device__ inline void pair_before_at(const DevGraph &G, int32_t p, int64_t t, int64_t *lt, int64_t *le) {
+__device__ inline void pair_count_at(const DevGraph &G, int32_t p, int64_t t, int64_t lt[2], int64_t le[2]) {
     const PairMeta m = G.pmeta[p];
     const int32_t *bi = G.pb_idx + m.boff;
+    const PairEnt *en = G.up_ent + m.base;
     int64_t n = bi[m.nb];
     int64_t lo;
     if (t <= m.t0) {
@@ -103,48 +85,74 @@ __device__ inline void pair_before_at(const DevGraph &G, int32_t p, int64_t t, i
             int64_t hi = bi[b + 1];
             while (lo < hi) {
                 int64_t mid = (lo + hi) >> 1;
-                if (G.pr_t[m.base + mid] < t) lo = mid + 1;
+                if (en[mid].t < t) lo = mid + 1;
                 else hi = mid;
             }
         }
     }
     int64_t e = lo;
-    while (e < n && G.pr_t[m.base + e] == t) ++e;
-    *lt = lo;
-    *le = e;
+    while (e < n && en[e].t == t) ++e;
+    int64_t c = en[lo].c0;
+    lt[0] = c;
+    lt[1] = lo - c;
+    c = en[e].c0;
+    le[0] = c;
+    le[1] = e - c;
 }
 
-// directed pair ids (u -> v, v -> u) of the unordered pair {u, v}; -1 if absent
-__device__ inline void pair_ids(const DevGraph &G, uint32_t u, uint32_t v, int32_t *puv, int32_t *pvu) {
+// entries of pair p with time < t
+__device__ inline void pair_count_lt(const DevGraph &G, int32_t p, int64_t t, int64_t lt[2]) {
+    const PairMeta m = G.pmeta[p];
+    const int32_t *bi = G.pb_idx + m.boff;
+    const PairEnt *en = G.up_ent + m.base;
+    int64_t lo;
+    if (t <= m.t0) {
+        lo = 0;
+    } else {
+        int64_t b = (t - m.t0) >> m.shift;
+        if (b >= m.nb) {
+            lo = bi[m.nb];
+        } else {
+            lo = bi[b];
+            int64_t hi = bi[b + 1];
+            while (lo < hi) {
+                int64_t mid = (lo + hi) >> 1;
+                if (en[mid].t < t) lo = mid + 1;
+                else hi = mid;
+            }
+        }
+    }
+    int64_t c = en[lo].c0;
+    lt[0] = c;
+    lt[1] = lo - c;
+}
+
+// entries of pair p with time <= t (all of them for t = LLONG_MAX)
+__device__ inline void pair_count_le(const DevGraph &G, int32_t p, int64_t t, int64_t le[2]) {
+    if (t == LLONG_MAX) {
+        const PairMeta m = G.pmeta[p];
+        int64_t n = G.pb_idx[m.boff + m.nb];
+        int64_t c = G.up_ent[m.base + n].c0;
+        le[0] = c;
+        le[1] = n - c;
+        return;
+    }
+    pair_count_lt(G, p, t + 1, le);
+}
+
+// unordered pair id of {u, v}, -1 if no edge joins them
+__device__ inline int32_t pair_id(const DevGraph &G, uint32_t u, uint32_t v) {
     uint32_t a = u < v ? u : v, b = u < v ? v : u;
     uint64_t key = ((uint64_t)a << 32) | b;
     int64_t cap = G.ph_cap;
     uint64_t h = tm_pair_hash(key, cap);
-    *puv = -1;
-    *pvu = -1;
     for (int64_t probe = 0; probe < cap; ++probe) {
         const PairSlot sl = G.ph_slot[h];
-        if (sl.key == key) {
-            *puv = u < v ? sl.fwd : sl.rev;
-            *pvu = u < v ? sl.rev : sl.fwd;
-            return;
-        }
-        if (sl.key == ~0ull) return;
+        if (sl.key == key) return sl.id;
+        if (sl.key == ~0ull) return -1;
         h = (h + 1) & (uint64_t)(cap - 1);
     }
-}
-
-// entries of pair p with tlo < t <= thi
-__device__ inline uint64_t pair_after_upto(const DevGraph &G, int32_t p, int64_t tlo, int64_t thi) {
-    if (p < 0) return 0;
-    int64_t up = (thi == LLONG_MAX) ? pair_size(G, p) : pair_before(G, p, thi + 1);
-    return (uint64_t)(up - pair_before(G, p, tlo + 1));
-}
-
-// entries of pair p with tlo < t < thi
-__device__ inline uint64_t pair_between_id(const DevGraph &G, int32_t p, int64_t tlo, int64_t thi) {
-    if (p < 0) return 0;
-    return (uint64_t)(pair_before(G, p, thi) - pair_before(G, p, tlo + 1));
+    return -1;
 }
 
 // Per-lane accumulator of up to 16 motif codes.
@@ -247,25 +255,25 @@ __device__ inline void tc_add(uint64_t *tc, uint32_t idx, uint64_t v) {
 // high-degree nodes, whose lists are long, never do the pair lookups.
 __device__ inline void tri_rank(const DevGraph &G, uint32_t yi, uint32_t di, int64_t ti, uint32_t yj, uint32_t dj,
                                 int64_t tj, int64_t hi, int64_t lo_win, int64_t delta, uint64_t *tc) {
-    int32_t pp[2];
-    pair_ids(G, yi, yj, &pp[0], &pp[1]);  // yi -> yj, yj -> yi
+    int32_t p = pair_id(G, yi, yj);
+    if (p < 0) return;
     int64_t lo3 = (tj < LLONG_MIN + delta) ? LLONG_MIN : tj - delta;
     lo3 = lo3 > lo_win ? lo3 : lo_win;
+    int64_t f_ti[2], f_ti1[2], f_tj[2], f_tj1[2], f_hi1[2], f_lo3[2];
+    pair_count_at(G, p, ti, f_ti, f_ti1);
+    pair_count_at(G, p, tj, f_tj, f_tj1);
+    pair_count_le(G, p, hi, f_hi1);
+    pair_count_lt(G, p, lo3, f_lo3);
+    const uint32_t sw = yi > yj ? 1u : 0u;  // index of yi -> yj in the pair's counts
 #pragma unroll
-    for (uint32_t dir = 0; dir < 2; ++dir) {
-        int32_t p = pp[dir];
-        if (p < 0) continue;
-        int64_t f_ti, f_ti1, f_tj, f_tj1;
-        pair_before_at(G, p, ti, &f_ti, &f_ti1);
-        pair_before_at(G, p, tj, &f_tj, &f_tj1);
-        int64_t f_hi1 = (hi == LLONG_MAX) ? pair_size(G, p) : pair_before(G, p, hi + 1);
-        int64_t f_lo3 = pair_before(G, p, lo3);
+    for (uint32_t dir = 0; dir < 2; ++dir) {  // dir 0: yi -> yj, 1: yj -> yi
+        const uint32_t k = dir ^ sw;
         // v = x: d1 = di, d2 = dir, d3 = dj
-        tc_add(tc, 4 * di + 2 * dir + dj, (uint64_t)(f_tj - f_ti1));
+        tc_add(tc, 4 * di + 2 * dir + dj, (uint64_t)(f_tj[k] - f_ti1[k]));
         // v = y1: d1 = 1 - di, d2 = dj, d3 = dir
-        tc_add(tc, 4 * (1 - di) + 2 * dj + dir, (uint64_t)(f_hi1 - f_tj1));
+        tc_add(tc, 4 * (1 - di) + 2 * dj + dir, (uint64_t)(f_hi1[k] - f_tj1[k]));
         // v = y3: d1 = 1 - dir, d2 = 1 - di, d3 = 1 - dj
-        tc_add(tc, 4 * (1 - dir) + 2 * (1 - di) + (1 - dj), (uint64_t)(f_ti - f_lo3));
+        tc_add(tc, 4 * (1 - dir) + 2 * (1 - di) + (1 - dj), (uint64_t)(f_ti[k] - f_lo3[k]));
     }
 }
 
@@ -323,12 +331,18 @@ __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t 
             }
             if (tri_r && G.inc_hi[j]) tri_rank(G, y1, d1, t1, yj, dj, tj, hi, lo_win, a.delta, tc);
             if (tri_x) {
-                int32_t p01, p10;
-                pair_ids(G, y1, yj, &p01, &p10);
-                uint64_t c01 = pair_between_id(G, p01, t1, tj);
-                uint64_t c10 = pair_between_id(G, p10, t1, tj);
-                acc_add<MODE, 16>(A, 12, dj, c01, w, a.hist, 20 + 4 * (int)d1, dlt, a.delta);
-                acc_add<MODE, 16>(A, 14, dj, c10, w, a.hist, 22 + 4 * (int)d1, dlt, a.delta);
+                // middles on {y1, yj} strictly between t1 and tj
+                int32_t p = pair_id(G, y1, yj);
+                if (p >= 0) {
+                    int64_t lo[2], up[2];
+                    pair_count_le(G, p, t1, lo);
+                    pair_count_lt(G, p, tj, up);
+                    const uint32_t sw = y1 > yj ? 1u : 0u;
+                    uint64_t c01 = (uint64_t)(up[sw] - lo[sw]);
+                    uint64_t c10 = (uint64_t)(up[sw ^ 1u] - lo[sw ^ 1u]);
+                    acc_add<MODE, 16>(A, 12, dj, c01, w, a.hist, 20 + 4 * (int)d1, dlt, a.delta);
+                    acc_add<MODE, 16>(A, 14, dj, c10, w, a.hist, 22 + 4 * (int)d1, dlt, a.delta);
+                }
             }
         }
         if (dj) ++pa1; else ++pa0;
