@@ -66,79 +66,58 @@ __device__ inline int64_t owner_of(const int64_t *off, int64_t n, int64_t i) {
 // Unordered pair p = {a < b}: its entries are the edges of both directions,
 // time-sorted.  The counts below come as c[0] = a -> b and c[1] = b -> a.
 
-// entries of pair p with time < t (lt) and with time <= t (le): one bucket
-// lookup, then the entries equal to t (usually none) are stepped over
-__device__ inline void pair_count_at(const DevGraph &G, int32_t p, int64_t t, int64_t lt[2], int64_t le[2]) {
-    const PairMeta m = G.pmeta[p];
+// lower bound of t in the pair described by m (entries en, n of them)
+__device__ inline int64_t pair_lower(const DevGraph &G, const PairMeta &m, const PairEnt *en, int64_t n, int64_t t) {
+    if (t <= m.t0) return 0;
+    int64_t b = (t - m.t0) >> m.shift;
+    if (b >= m.nb) return n;
     const int32_t *bi = G.pb_idx + m.boff;
-    const PairEnt *en = G.up_ent + m.base;
-    int64_t n = bi[m.nb];
-    int64_t lo;
-    if (t <= m.t0) {
-        lo = 0;
-    } else {
-        int64_t b = (t - m.t0) >> m.shift;
-        if (b >= m.nb) {
-            lo = n;
-        } else {
-            lo = bi[b];
-            int64_t hi = bi[b + 1];
-            while (lo < hi) {
-                int64_t mid = (lo + hi) >> 1;
-                if (en[mid].t < t) lo = mid + 1;
-                else hi = mid;
-            }
-        }
+    int64_t lo = bi[b], hi = bi[b + 1];
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (en[mid].t < t) lo = mid + 1;
+        else hi = mid;
     }
-    int64_t e = lo;
-    while (e < n && en[e].t == t) ++e;
-    int64_t c = en[lo].c0;
-    lt[0] = c;
-    lt[1] = lo - c;
-    c = en[e].c0;
-    le[0] = c;
-    le[1] = e - c;
+    return lo;
 }
 
-// entries of pair p with time < t
-__device__ inline void pair_count_lt(const DevGraph &G, int32_t p, int64_t t, int64_t lt[2]) {
-    const PairMeta m = G.pmeta[p];
-    const int32_t *bi = G.pb_idx + m.boff;
-    const PairEnt *en = G.up_ent + m.base;
-    int64_t lo;
-    if (t <= m.t0) {
-        lo = 0;
-    } else {
-        int64_t b = (t - m.t0) >> m.shift;
-        if (b >= m.nb) {
-            lo = bi[m.nb];
-        } else {
-            lo = bi[b];
-            int64_t hi = bi[b + 1];
-            while (lo < hi) {
-                int64_t mid = (lo + hi) >> 1;
-                if (en[mid].t < t) lo = mid + 1;
-                else hi = mid;
-            }
-        }
+// One pair held in registers for repeated lookups.
+struct PairView {
+    PairMeta m;
+    const PairEnt *en;
+    int64_t n;
+    __device__ void load(const DevGraph &G, int32_t p) {
+        m = G.pmeta[p];
+        en = G.up_ent + m.base;
+        n = G.pb_idx[m.boff + m.nb];
     }
-    int64_t c = en[lo].c0;
-    lt[0] = c;
-    lt[1] = lo - c;
-}
-
-// entries of pair p with time <= t (all of them for t = LLONG_MAX)
-__device__ inline void pair_count_le(const DevGraph &G, int32_t p, int64_t t, int64_t le[2]) {
-    if (t == LLONG_MAX) {
-        const PairMeta m = G.pmeta[p];
-        int64_t n = G.pb_idx[m.boff + m.nb];
-        int64_t c = G.up_ent[m.base + n].c0;
-        le[0] = c;
-        le[1] = n - c;
-        return;
+    // entries with time < t
+    __device__ void lt(const DevGraph &G, int64_t t, int64_t c[2]) const {
+        int64_t lo = pair_lower(G, m, en, n, t);
+        int64_t k = en[lo].c0;
+        c[0] = k;
+        c[1] = lo - k;
     }
-    pair_count_lt(G, p, t + 1, le);
-}
+    // entries with time <= t (all of them for t = LLONG_MAX)
+    __device__ void le(const DevGraph &G, int64_t t, int64_t c[2]) const {
+        int64_t e = (t == LLONG_MAX) ? n : pair_lower(G, m, en, n, t + 1);
+        int64_t k = en[e].c0;
+        c[0] = k;
+        c[1] = e - k;
+    }
+    // both: one bucket lookup, then the entries equal to t are stepped over
+    __device__ void at(const DevGraph &G, int64_t t, int64_t c_lt[2], int64_t c_le[2]) const {
+        int64_t lo = pair_lower(G, m, en, n, t);
+        int64_t e = lo;
+        while (e < n && en[e].t == t) ++e;
+        int64_t k = en[lo].c0;
+        c_lt[0] = k;
+        c_lt[1] = lo - k;
+        k = en[e].c0;
+        c_le[0] = k;
+        c_le[1] = e - k;
+    }
+};
 
 // unordered pair id of {u, v}, -1 if no edge joins them
 __device__ inline int32_t pair_id(const DevGraph &G, uint32_t u, uint32_t v) {
@@ -253,27 +232,42 @@ __device__ inline void tc_add(uint64_t *tc, uint32_t idx, uint64_t v) {
 //   v = y3 (middle and last edge at v):     first edge in [max(tj - delta, lo_win), ti)
 // Counting each instance only at its lowest-ranked node counts it once, and
 // high-degree nodes, whose lists are long, never do the pair lookups.
+// Pair {yi, yc} of the last triangle lookup of an anchor with its counts at
+// the anchor's own times, reused while the next entries lead to yc again.
+struct TriCache {
+    uint32_t yc;
+    int32_t p;
+    PairView pv;
+    int64_t f_ti[2], f_ti1[2], f_hi1[2];
+};
+
 __device__ inline void tri_rank(const DevGraph &G, uint32_t yi, uint32_t di, int64_t ti, uint32_t yj, uint32_t dj,
-                                int64_t tj, int64_t hi, int64_t lo_win, int64_t delta, uint64_t *tc) {
-    int32_t p = pair_id(G, yi, yj);
-    if (p < 0) return;
+                                int64_t tj, int64_t hi, int64_t lo_win, int64_t delta, uint64_t *tc, TriCache &C) {
+    if (yj != C.yc) {
+        C.yc = yj;
+        C.p = pair_id(G, yi, yj);
+        if (C.p >= 0) {
+            C.pv.load(G, C.p);
+            C.pv.at(G, ti, C.f_ti, C.f_ti1);
+            C.pv.le(G, hi, C.f_hi1);
+        }
+    }
+    if (C.p < 0) return;
     int64_t lo3 = (tj < LLONG_MIN + delta) ? LLONG_MIN : tj - delta;
     lo3 = lo3 > lo_win ? lo3 : lo_win;
-    int64_t f_ti[2], f_ti1[2], f_tj[2], f_tj1[2], f_hi1[2], f_lo3[2];
-    pair_count_at(G, p, ti, f_ti, f_ti1);
-    pair_count_at(G, p, tj, f_tj, f_tj1);
-    pair_count_le(G, p, hi, f_hi1);
-    pair_count_lt(G, p, lo3, f_lo3);
+    int64_t f_tj[2], f_tj1[2], f_lo3[2];
+    C.pv.at(G, tj, f_tj, f_tj1);
+    C.pv.lt(G, lo3, f_lo3);
     const uint32_t sw = yi > yj ? 1u : 0u;  // index of yi -> yj in the pair's counts
 #pragma unroll
     for (uint32_t dir = 0; dir < 2; ++dir) {  // dir 0: yi -> yj, 1: yj -> yi
         const uint32_t k = dir ^ sw;
         // v = x: d1 = di, d2 = dir, d3 = dj
-        tc_add(tc, 4 * di + 2 * dir + dj, (uint64_t)(f_tj[k] - f_ti1[k]));
+        tc_add(tc, 4 * di + 2 * dir + dj, (uint64_t)(f_tj[k] - C.f_ti1[k]));
         // v = y1: d1 = 1 - di, d2 = dj, d3 = dir
-        tc_add(tc, 4 * (1 - di) + 2 * dj + dir, (uint64_t)(f_hi1[k] - f_tj1[k]));
+        tc_add(tc, 4 * (1 - di) + 2 * dj + dir, (uint64_t)(C.f_hi1[k] - f_tj1[k]));
         // v = y3: d1 = 1 - dir, d2 = 1 - di, d3 = 1 - dj
-        tc_add(tc, 4 * (1 - dir) + 2 * (1 - di) + (1 - dj), (uint64_t)(f_ti[k] - f_lo3[k]));
+        tc_add(tc, 4 * (1 - dir) + 2 * (1 - di) + (1 - dj), (uint64_t)(C.f_ti[k] - f_lo3[k]));
     }
 }
 
@@ -293,6 +287,9 @@ __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t 
     bool tri_x = tri;
     bool tri_r = false;
     uint64_t tc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    TriCache tcache;
+    tcache.yc = ~0u;
+    tcache.p = -1;
     if constexpr (MODE == MODE_COUNT) {
         tri_x = false;
         tri_r = tri && G.inc_hi[i];
@@ -329,17 +326,24 @@ __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t 
                 acc_add<MODE, 16>(A, 8, dj, cs0, w, a.hist, 12 + 4 * (int)d1, dlt, a.delta);
                 acc_add<MODE, 16>(A, 10, dj, cs1, w, a.hist, 14 + 4 * (int)d1, dlt, a.delta);
             }
-            if (tri_r && G.inc_hi[j]) tri_rank(G, y1, d1, t1, yj, dj, tj, hi, lo_win, a.delta, tc);
+            if (tri_r && G.inc_hi[j]) tri_rank(G, y1, d1, t1, yj, dj, tj, hi, lo_win, a.delta, tc, tcache);
             if (tri_x) {
-                // middles on {y1, yj} strictly between t1 and tj
-                int32_t p = pair_id(G, y1, yj);
-                if (p >= 0) {
-                    int64_t lo[2], up[2];
-                    pair_count_le(G, p, t1, lo);
-                    pair_count_lt(G, p, tj, up);
+                // middles on {y1, yj} strictly between t1 and tj; the pair and
+                // its count up to t1 are kept while entries lead to yj again
+                if (yj != tcache.yc) {
+                    tcache.yc = yj;
+                    tcache.p = pair_id(G, y1, yj);
+                    if (tcache.p >= 0) {
+                        tcache.pv.load(G, tcache.p);
+                        tcache.pv.le(G, t1, tcache.f_ti1);
+                    }
+                }
+                if (tcache.p >= 0) {
+                    int64_t up[2];
+                    tcache.pv.lt(G, tj, up);
                     const uint32_t sw = y1 > yj ? 1u : 0u;
-                    uint64_t c01 = (uint64_t)(up[sw] - lo[sw]);
-                    uint64_t c10 = (uint64_t)(up[sw ^ 1u] - lo[sw ^ 1u]);
+                    uint64_t c01 = (uint64_t)(up[sw] - tcache.f_ti1[sw]);
+                    uint64_t c10 = (uint64_t)(up[sw ^ 1u] - tcache.f_ti1[sw ^ 1u]);
                     acc_add<MODE, 16>(A, 12, dj, c01, w, a.hist, 20 + 4 * (int)d1, dlt, a.delta);
                     acc_add<MODE, 16>(A, 14, dj, c10, w, a.hist, 22 + 4 * (int)d1, dlt, a.delta);
                 }
