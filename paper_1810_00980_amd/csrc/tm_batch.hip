@@ -18,6 +18,16 @@
 // The tile size and the number of resident work-groups per CU are chosen by
 // timing candidates on the first call (autotuner), per (graph, motif, delta,
 // c, p).
+//
+// Stored anchor values: the weighted sum of the instances that start (or, for
+// the stars swept backwards, end) at an anchor does not depend on the seed
+// unless the anchor's delta-horizon crosses its window's edge.  When a batch
+// covers at least one full pass over the anchors (seeds x p >= 1), one
+// unclipped pass stores every anchor's count and weighted sum for the motif;
+// the batch then adds the stored value of each anchor in a kept window whose
+// horizon stays inside it and sweeps only the anchors within delta of the
+// window's edge.  The sums are exact integers, so every seed's estimate is
+// the same as the one the direct batch or a single call gives.
 #include "tm_common.h"
 
 #include <limits.h>
@@ -53,6 +63,7 @@ struct BatchArgs {
     uint32_t want_fwd;
     int32_t want_bwd;
     double *z;                // [n_seeds]
+    const uint64_t *vals;     // [entries][4] stored anchor values, or null
 };
 
 __global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
@@ -162,6 +173,12 @@ __global__ void __launch_bounds__(BT_TPB) k_batch_sweep(DevGraph G, BatchArgs a)
                 int64_t j = (tt - sa.s) / sa.L + 1;
                 if (!keep_window(sa.seed, (uint64_t)j, sa.p)) continue;
                 int64_t wlo = sa.s + (j - 1) * sa.L, whi = sa.s + j * sa.L - 1;
+                if (a.vals && (a.want_fwd ? tt <= whi - a.delta : tt >= wlo + a.delta)) {
+                    const uint64_t *v = a.vals + 4 * i;
+                    tm_add_u128(one.cl, one.ch, v[0], v[1]);
+                    tm_add_u128(one.wl, one.wh, v[2], v[3]);
+                    continue;
+                }
                 if (a.want_fwd) {
                     int64_t hi = (tt > LLONG_MAX - a.delta) ? LLONG_MAX : tt + a.delta;
                     hi = hi < whi ? hi : whi;
@@ -191,6 +208,51 @@ __global__ void k_batch_final(BatchArgs a) {
     double x = (double)o[3] * 18446744073709551616.0;
     x = x + (double)o[2];
     a.z[k] = x * (1.0 / 4503599627370496.0) / a.p;
+}
+
+// every anchor's unclipped count and weighted sum for one motif code
+template <bool FWD>
+__global__ void __launch_bounds__(BT_TPB) k_anchor_vals(DevGraph G, BatchArgs a, int64_t n_entries,
+                                                         unsigned long long *counter, uint64_t *vals) {
+    const int lane = threadIdx.x & (TM_WAVE - 1);
+    SweepArgs sa;
+    sa.delta = a.delta;
+    sa.windowed = 0;
+    sa.s = 0;
+    sa.L = a.L;
+    sa.seed = 0;
+    sa.p = 1.0;
+    sa.wfx = a.wfx;
+    sa.hist = nullptr;
+    sa.out = nullptr;
+    sa.counter = nullptr;
+    sa.want_fwd = a.want_fwd;
+    sa.n_entries = 0;
+    while (true) {
+        int64_t base = 0;
+        if (lane == 0) base = (int64_t)atomicAdd(counter, (unsigned long long)TM_WAVE);
+        base = __shfl(base, 0, TM_WAVE);
+        if (base >= n_entries) break;
+        int64_t i = base + lane;
+        if (i >= n_entries) continue;
+        int64_t x = owner_of(G.inc_off, G.n, i);
+        uint32_t nd = G.inc_nd[i];
+        uint32_t y = nd & 0x7FFFFFFFu, d = nd >> 31;
+        int64_t tt = G.inc_t[i];
+        OneCode one{a.code, 0, 0, 0, 0};
+        if (FWD) {
+            int64_t hi = (tt > LLONG_MAX - a.delta) ? LLONG_MAX : tt + a.delta;
+            sweep_fwd<MODE_WEIGHT>(G, sa, i, G.inc_off[x + 1], y, d, tt, hi, LLONG_MIN, nullptr, &one);
+        } else {
+            int64_t lo = (tt < LLONG_MIN + a.delta) ? LLONG_MIN : tt - a.delta;
+            sweep_bwd<MODE_WEIGHT>(G, sa, i, G.inc_off[x], y, d, tt, lo, nullptr, &one);
+        }
+        uint64_t *v = vals + 4 * i;
+        v[0] = one.cl;
+        v[1] = one.ch;
+        v[2] = one.wl;
+        v[3] = one.wh;
+    }
 }
 
 __global__ void k_weights_fx_b(int64_t delta, int64_t L, uint64_t *wfx) {
@@ -240,6 +302,7 @@ struct BatchPlan {
     int64_t tile = 0, bpc = 0, n_seeds = 0, delta = 0, L = 0, J = 0, n_tiles = 0;
     int32_t code = -1;
     double p = 0;
+    const uint64_t *vals = nullptr;  // stored anchor values (owned by the cache), or null
     DevBuf tiles, tnode, seeds, shifts, kp, qctl, out, wfx, z;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap_stream = nullptr;
@@ -251,11 +314,13 @@ struct BatchPlan {
 
 using PlanKey = std::tuple<const tm_graph *, int32_t, int64_t, int64_t, double, int64_t, int64_t, int64_t>;
 using TuneKey = std::tuple<const tm_graph *, int32_t, int64_t, int64_t, double>;
+using ValKey = std::tuple<const tm_graph *, int32_t, int64_t, int64_t>;
 
 struct BatchCache {
     std::mutex mu;
     std::map<PlanKey, std::unique_ptr<BatchPlan>> plans;
     std::map<TuneKey, std::pair<int64_t, int64_t>> tuned;
+    std::map<ValKey, std::unique_ptr<DevBuf>> vals;  // stored anchor values per (graph, code, delta, L)
 };
 BatchCache &bcache() {
     static BatchCache c;
@@ -282,6 +347,7 @@ BatchArgs make_args(BatchPlan &B, uint32_t want_fwd, int32_t want_bwd) {
     a.want_fwd = want_fwd;
     a.want_bwd = want_bwd;
     a.z = B.z.as<double>();
+    a.vals = B.vals;
     return a;
 }
 
@@ -368,7 +434,7 @@ tm_status capture(const tm_graph *g, BatchPlan &B) {
 tm_status run_plan(const tm_graph *g, BatchPlan &B, const uint64_t *seeds, double *est, tm_u128 *kept, bool use_graph,
                    hipStream_t st) {
     TM_HIP(hipMemcpyAsync(B.seeds.p, seeds, (size_t)B.n_seeds * 8, hipMemcpyHostToDevice, st));
-    void *tok = tm_prof_begin("count_batch", st);
+    void *tok = tm_prof_begin(B.vals ? "count_batch_stored" : "count_batch", st);
     if (use_graph && B.exec) {
         TM_HIP(hipGraphLaunch(B.exec, st));
     } else {
@@ -387,6 +453,54 @@ tm_status run_plan(const tm_graph *g, BatchPlan &B, const uint64_t *seeds, doubl
             kept[k].hi = o[(size_t)(4 * k + 1)];
         }
     }
+    return TM_OK;
+}
+
+// Stored anchor values of (graph, code, delta, L) for plan B, computed on
+// first use with B's weights; *vals stays null when they do not fit in a
+// quarter of the free device memory.
+tm_status anchor_vals(const tm_graph *g, BatchPlan &B, const uint64_t **vals, hipStream_t st) {
+    BatchCache &C = bcache();
+    ValKey key{g, B.code, B.delta, B.L};
+    {
+        std::lock_guard<std::mutex> lk(C.mu);
+        auto it = C.vals.find(key);
+        if (it != C.vals.end()) {
+            *vals = it->second->as<uint64_t>();
+            return TM_OK;
+        }
+    }
+    *vals = nullptr;
+    int64_t ne = 2 * g->m_nl;
+    size_t bytes = (size_t)ne * 32;
+    size_t fr = 0, tot = 0;
+    TM_HIP(hipMemGetInfo(&fr, &tot));
+    if (bytes > fr / 4) return TM_OK;
+    std::unique_ptr<DevBuf> V(new (std::nothrow) DevBuf());
+    if (!V) return TM_ENOMEM;
+    TM_TRY(V->alloc(bytes));
+    DevBuf ctr;
+    TM_TRY(ctr.alloc(64));
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, ctr.as<unsigned long long>(), (int64_t)1, 0ull);
+    DevGraph G = dev_view(g);
+    BatchArgs a = make_args(B, fwd_mask_of(B.code), B.code >= 28 ? 1 : 0);
+    int dev = g->device, ncu = 0;
+    TM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (ncu <= 0) ncu = 256;
+    void *tok = tm_prof_begin("batch_anchor_values", st);
+    if (a.want_bwd)
+        hipLaunchKernelGGL(k_anchor_vals<false>, dim3((unsigned)(ncu * 8)), dim3(BT_TPB), 0, st, G, a, ne,
+                           ctr.as<unsigned long long>(), V->as<uint64_t>());
+    else
+        hipLaunchKernelGGL(k_anchor_vals<true>, dim3((unsigned)(ncu * 8)), dim3(BT_TPB), 0, st, G, a, ne,
+                           ctr.as<unsigned long long>(), V->as<uint64_t>());
+    TM_HIP(hipGetLastError());
+    tm_prof_end(tok, st);
+    TM_HIP(hipStreamSynchronize(st));
+    std::lock_guard<std::mutex> lk(C.mu);
+    auto it = C.vals.find(key);
+    if (it == C.vals.end()) it = C.vals.emplace(key, std::move(V)).first;
+    *vals = it->second->as<uint64_t>();
     return TM_OK;
 }
 
@@ -413,6 +527,7 @@ tm_status get_plan(const tm_graph *g, int32_t code, int64_t delta, int64_t L, do
     B->code = code;
     B->J = 1 + g->t_span / L + ((g->t_span % L) ? 1 : 0);
     TM_TRY(build_plan(g, *B, st));
+    if ((double)n_seeds * p >= 1.0) TM_TRY(anchor_vals(g, *B, &B->vals, st));
     if (want_graph) TM_TRY(capture(g, *B));
     std::lock_guard<std::mutex> lk(C.mu);
     BatchPlan *raw = B.get();
@@ -433,6 +548,10 @@ void tm_batch_forget(const tm_graph *g) {
     }
     for (auto it = C.tuned.begin(); it != C.tuned.end();) {
         if (std::get<0>(it->first) == g) it = C.tuned.erase(it);
+        else ++it;
+    }
+    for (auto it = C.vals.begin(); it != C.vals.end();) {
+        if (std::get<0>(it->first) == g) it = C.vals.erase(it);
         else ++it;
     }
 }

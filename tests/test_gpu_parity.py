@@ -270,18 +270,26 @@ def test_batched_estimates_match_per_seed(tm):
     say("batch")
     G = load(tm, g)
     delta, c, p = 40, 3, 0.3
-    for M in (ti.TRIANGLE, ((0, 1), (0, 2), (0, 2)), ti.TWO_NODE_ALT):
-        for tile in (64, 0):
-            for rep in range(3):
-                seeds = np.arange(10, dtype=np.uint64) + 100 * rep + 7
-                est, kept = tm.estimate_batch(G, M, delta, c, p, seeds, tile=tile)
-                for k, sd in enumerate(seeds):
-                    o = oracle.estimate(g.src, g.dst, g.t, M, delta, c, p, int(sd))
-                    assert close(est[k], o["Z"]), (M, tile, rep, k, est[k], o["Z"])
-                    assert kept[k] == int(o["win_counts"].sum())
-                # eager work between replays
-                torch.zeros(1 << 20, device="cuda").sum().item()
-                assert close(tm.estimate(G, M, delta, c, p, int(seeds[0])), est[0])
+    # 10 seeds x p >= 1: stored anchor values plus boundary sweeps;
+    # 3 seeds x p < 1: every kept anchor swept
+    # triangle, star C (swept backwards), 2-node, star B, star A
+    for M in (ti.TRIANGLE, ((0, 1), (0, 2), (0, 2)), ti.TWO_NODE_ALT, ((0, 1), (0, 2), (0, 1)), ((0, 1), (0, 1), (0, 2))):
+        for n_seeds, plan in ((10, "count_batch_stored"), (3, "count_batch")):
+            for tile in (64, 0):
+                for rep in range(3):
+                    seeds = np.arange(n_seeds, dtype=np.uint64) + 100 * rep + 7
+                    tm.profile_reset()
+                    tm.profile_enable(True)
+                    est, kept = tm.estimate_batch(G, M, delta, c, p, seeds, tile=tile)
+                    tm.profile_enable(False)
+                    assert tm.profile_read(plan)[1] == 1, (M, n_seeds, plan)
+                    for k, sd in enumerate(seeds):
+                        o = oracle.estimate(g.src, g.dst, g.t, M, delta, c, p, int(sd))
+                        assert close(est[k], o["Z"]), (M, n_seeds, tile, rep, k, est[k], o["Z"])
+                        assert kept[k] == int(o["win_counts"].sum())
+                    # eager work between replays
+                    torch.zeros(1 << 20, device="cuda").sum().item()
+                    assert close(tm.estimate(G, M, delta, c, p, int(seeds[0])), est[0])
     t, b = tm.batch_config(G, ti.TRIANGLE, delta, c, p)
     assert t in (64, 256, 1024) and b in (8, 16)
     # a four-edge motif takes the seed-by-seed path
