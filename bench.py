@@ -38,8 +38,9 @@ import tm_inputs as ti  # noqa: E402
 
 THREE = ti.three_edge_motifs()
 HBM_PEAK_GBS = 8000.0
-DOMINANT = "sweep3_fwd_count"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep3_fwd_count_zipf10m_traffic.json")
+# library timing names of the three-edge sweep kernels (exact, then weighted)
+SWEEP_KERNELS = ("sweep3_fwd_count", "sweep3_tri_count", "sweep3_bwd_count",
+                 "sweep3_fwd_weight", "sweep3_tri_weight", "sweep3_bwd_weight")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1810_00980_amd", "csrc", f)
                for f in ("tm_sweep3.hip", "tm_sweep_dev.h", "tm_common.h")]
 
@@ -289,12 +290,16 @@ def kernel_src_sha():
     return h.hexdigest()
 
 
-def traffic_record():
-    """HBM traffic of the dominant kernel from the committed rocprofv3 --pmc
+def traffic_file(kernel):
+    return os.path.join(ROOT, "profiles", f"{kernel}_zipf10m_traffic.json")
+
+
+def traffic_record(kernel):
+    """HBM traffic of a sweep kernel from its committed rocprofv3 --pmc
     summary, valid only while the kernel source is unchanged."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(traffic_file(kernel)):
         return None
-    rec = json.load(open(TRAFFIC_FILE))
+    rec = json.load(open(traffic_file(kernel)))
     sha = kernel_src_sha()
     if rec.get("kernel_src_sha256") != sha:
         return None
@@ -375,22 +380,32 @@ def main():
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     tm.profile_enable(False)
-    kms, kn = tm.profile_read(DOMINANT)
+    kern = {k: tm.profile_read(k) for k in SWEEP_KERNELS}
 
     q = len(motifs) * (1 + len(W["est"]))
     G = tm.load_graph(src, dst, t, g.n)
-    anchors, fwd, bwd = tm.sweep_census(G, delta)
+    census = tm.sweep_census(G, delta)
     G.free()
+    anchors, fwd, bwd, r_anchors, r_fwd = census
+    # algorithmic bytes per launch of the exact sweeps: 12 B (time + endpoint
+    # word) per anchor and per scanned list entry
+    exact_bytes = {"sweep3_fwd_count": 12 * (anchors + fwd), "sweep3_tri_count": 12 * (r_anchors + r_fwd),
+                   "sweep3_bwd_count": 12 * (anchors + bwd)}
     roofline = None
-    if kn > 0:
-        bytes_per_launch = 12 * (anchors + fwd)
+    timed = {k: v for k, v in kern.items() if k in exact_bytes and v[1] > 0}
+    if timed:
+        dom = max(timed, key=lambda k: timed[k][0])
+        kms, kn = timed[dom]
+        bytes_per_launch = exact_bytes[dom]
         avg_s = kms / kn / 1e3
         ach = bytes_per_launch / avg_s / 1e9
         roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": ach / HBM_PEAK_GBS, "traffic": traffic_record(),
-                    "kernel": DOMINANT, "avg_launch_ms": kms / kn, "launches": kn,
+                    "frac": ach / HBM_PEAK_GBS, "traffic": traffic_record(dom),
+                    "kernel": dom, "avg_launch_ms": kms / kn, "launches": kn,
                     "algorithmic_bytes_per_launch": bytes_per_launch,
-                    "census": {"anchors": anchors, "fwd_entries": fwd, "bwd_entries": bwd}}
+                    "census": {"anchors": anchors, "fwd_entries": fwd, "bwd_entries": bwd,
+                               "ranked_anchors": r_anchors, "ranked_entries": r_fwd},
+                    "sweep_kernels_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()}}
     out = {
         "metric": "temporal edges/s per motif query (exact & p=0.1 estimate) vs CPU",
         "value": g.m * q / dt, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -274,11 +274,15 @@ tm_status tm_profile_read(const char *kernel, double *total_ms, int64_t *launche
 /*
  * Work census of the three-edge sweep over the whole graph: the number of
  * anchors (incidence entries, two per non-self-loop edge) and the number of
- * list entries the forward and backward sweeps scan at span delta.  Used to
- * express kernel time as algorithmic bytes per second.
+ * list entries the forward and backward sweeps scan at span delta, and the
+ * same two figures for the exact triangle sweep, which runs over the ranked
+ * sublists (entries whose other endpoint ranks above the list's owner, rank
+ * = (list length, node id)).  Used to express kernel time as algorithmic
+ * bytes per second.  All five outputs are required (TM_EINVAL otherwise).
  */
 tm_status tm_sweep_census(const tm_graph *g, int64_t delta, int64_t *anchors, int64_t *fwd_entries,
-                          int64_t *bwd_entries, void *hip_stream);
+                          int64_t *bwd_entries, int64_t *ranked_anchors, int64_t *ranked_entries,
+                          void *hip_stream);
 
 /* Human-readable name of a status code (static storage). */
 const char *tm_strerror(tm_status s);

@@ -98,7 +98,7 @@ _SIGS = {
     "tm_profile_enable": [i32],
     "tm_profile_reset": [],
     "tm_profile_read": [ctypes.c_char_p, P, P],
-    "tm_sweep_census": [P, i64, P, P, P, P],
+    "tm_sweep_census": [P, i64, P, P, P, P, P, P],
     "tm_strerror": [i32],
     "tm_version": [],
 }
@@ -309,11 +309,13 @@ def profile_read(kernel: str):
 
 
 def sweep_census(g: Graph, delta: int, stream=None):
-    """(anchors, forward-scanned entries, backward-scanned entries) of the exact sweep."""
-    a, f, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    _check(_lib.tm_sweep_census(g.handle, int(delta), ctypes.byref(a), ctypes.byref(f), ctypes.byref(b),
-                                _stream(stream)), "tm_sweep_census")
-    return a.value, f.value, b.value
+    """(anchors, forward-scanned entries, backward-scanned entries, ranked
+    anchors, ranked-scanned entries) of the exact sweeps; the last two are
+    the exact triangle sweep's, over the ranked sublists."""
+    v = [ctypes.c_int64() for _ in range(5)]
+    _check(_lib.tm_sweep_census(g.handle, int(delta), *(ctypes.byref(x) for x in v), _stream(stream)),
+           "tm_sweep_census")
+    return tuple(x.value for x in v)
 
 
 def batch_config(g: Graph, edges, delta: int, c: int, p: float, stream=None):

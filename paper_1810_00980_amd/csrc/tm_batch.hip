@@ -121,7 +121,7 @@ __device__ inline void wave_sum_u128(uint64_t &lo, uint64_t &hi) {
 // tile meets a kept window of the seed, and for each kept task sweep the
 // tile's anchors in kept windows with the lanes' own sums, reduce them across
 // the wave and add them to the seed
-template <int MODE>
+template <int MODE, unsigned CLS>
 __global__ void __launch_bounds__(BT_TPB) k_batch_sweep(DevGraph G, BatchArgs a) {
     const int lane = threadIdx.x & (TM_WAVE - 1);
     const int64_t total = a.n_tiles * a.n_seeds;
@@ -173,18 +173,17 @@ __global__ void __launch_bounds__(BT_TPB) k_batch_sweep(DevGraph G, BatchArgs a)
                 int64_t j = (tt - sa.s) / sa.L + 1;
                 if (!keep_window(sa.seed, (uint64_t)j, sa.p)) continue;
                 int64_t wlo = sa.s + (j - 1) * sa.L, whi = sa.s + j * sa.L - 1;
-                if (a.vals && (a.want_fwd ? tt <= whi - a.delta : tt >= wlo + a.delta)) {
+                if (a.vals && (CLS != 0u ? tt <= whi - a.delta : tt >= wlo + a.delta)) {
                     const uint64_t *v = a.vals + 4 * i;
                     tm_add_u128(one.cl, one.ch, v[0], v[1]);
                     tm_add_u128(one.wl, one.wh, v[2], v[3]);
                     continue;
                 }
-                if (a.want_fwd) {
+                if (CLS != 0u) {
                     int64_t hi = (tt > LLONG_MAX - a.delta) ? LLONG_MAX : tt + a.delta;
                     hi = hi < whi ? hi : whi;
-                    sweep_fwd<MODE>(G, sa, i, le, y, d, tt, hi, wlo, nullptr, &one);
-                }
-                if (a.want_bwd) {
+                    sweep_fwd<MODE, CLS>(G, sa, i, le, y, d, tt, hi, wlo, nullptr, &one);
+                } else {
                     int64_t lo = (tt < LLONG_MIN + a.delta) ? LLONG_MIN : tt - a.delta;
                     lo = lo > wlo ? lo : wlo;
                     sweep_bwd<MODE>(G, sa, i, lb, y, d, tt, lo, nullptr, &one);
@@ -211,7 +210,7 @@ __global__ void k_batch_final(BatchArgs a) {
 }
 
 // every anchor's unclipped count and weighted sum for one motif code
-template <bool FWD>
+template <bool FWD, unsigned CLS>
 __global__ void __launch_bounds__(BT_TPB) k_anchor_vals(DevGraph G, BatchArgs a, int64_t n_entries,
                                                          unsigned long long *counter, uint64_t *vals) {
     const int lane = threadIdx.x & (TM_WAVE - 1);
@@ -242,7 +241,7 @@ __global__ void __launch_bounds__(BT_TPB) k_anchor_vals(DevGraph G, BatchArgs a,
         OneCode one{a.code, 0, 0, 0, 0};
         if (FWD) {
             int64_t hi = (tt > LLONG_MAX - a.delta) ? LLONG_MAX : tt + a.delta;
-            sweep_fwd<MODE_WEIGHT>(G, sa, i, G.inc_off[x + 1], y, d, tt, hi, LLONG_MIN, nullptr, &one);
+            sweep_fwd<MODE_WEIGHT, CLS>(G, sa, i, G.inc_off[x + 1], y, d, tt, hi, LLONG_MIN, nullptr, &one);
         } else {
             int64_t lo = (tt < LLONG_MIN + a.delta) ? LLONG_MIN : tt - a.delta;
             sweep_bwd<MODE_WEIGHT>(G, sa, i, G.inc_off[x], y, d, tt, lo, nullptr, &one);
@@ -374,7 +373,13 @@ tm_status enqueue(const tm_graph *g, BatchPlan &B, hipStream_t st) {
     TM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     if (ncu <= 0) ncu = 256;
     unsigned nb = (unsigned)(ncu * B.bpc);
-    hipLaunchKernelGGL(k_batch_sweep<1>, dim3(nb), dim3(BT_TPB), 0, st, G, a);
+    switch (wf) {  // one kernel per sweep class, holding only that class's accumulators
+        case 1: hipLaunchKernelGGL((k_batch_sweep<1, 1u>), dim3(nb), dim3(BT_TPB), 0, st, G, a); break;
+        case 2: hipLaunchKernelGGL((k_batch_sweep<1, 2u>), dim3(nb), dim3(BT_TPB), 0, st, G, a); break;
+        case 4: hipLaunchKernelGGL((k_batch_sweep<1, 4u>), dim3(nb), dim3(BT_TPB), 0, st, G, a); break;
+        case 8: hipLaunchKernelGGL((k_batch_sweep<1, 8u>), dim3(nb), dim3(BT_TPB), 0, st, G, a); break;
+        default: hipLaunchKernelGGL((k_batch_sweep<1, 0u>), dim3(nb), dim3(BT_TPB), 0, st, G, a); break;
+    }
     hipLaunchKernelGGL(k_batch_final, dim3(tm_blocks(B.n_seeds, 64)), dim3(64), 0, st, a);
     return tm_hip_status(hipGetLastError());
 }
@@ -488,12 +493,16 @@ tm_status anchor_vals(const tm_graph *g, BatchPlan &B, const uint64_t **vals, hi
     TM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     if (ncu <= 0) ncu = 256;
     void *tok = tm_prof_begin("batch_anchor_values", st);
-    if (a.want_bwd)
-        hipLaunchKernelGGL(k_anchor_vals<false>, dim3((unsigned)(ncu * 8)), dim3(BT_TPB), 0, st, G, a, ne,
-                           ctr.as<unsigned long long>(), V->as<uint64_t>());
-    else
-        hipLaunchKernelGGL(k_anchor_vals<true>, dim3((unsigned)(ncu * 8)), dim3(BT_TPB), 0, st, G, a, ne,
-                           ctr.as<unsigned long long>(), V->as<uint64_t>());
+    dim3 grid((unsigned)(ncu * 8)), blk(BT_TPB);
+    unsigned long long *cp = ctr.as<unsigned long long>();
+    uint64_t *vp = V->as<uint64_t>();
+    switch (a.want_bwd ? 0u : a.want_fwd) {
+        case 1: hipLaunchKernelGGL((k_anchor_vals<true, 1u>), grid, blk, 0, st, G, a, ne, cp, vp); break;
+        case 2: hipLaunchKernelGGL((k_anchor_vals<true, 2u>), grid, blk, 0, st, G, a, ne, cp, vp); break;
+        case 4: hipLaunchKernelGGL((k_anchor_vals<true, 4u>), grid, blk, 0, st, G, a, ne, cp, vp); break;
+        case 8: hipLaunchKernelGGL((k_anchor_vals<true, 8u>), grid, blk, 0, st, G, a, ne, cp, vp); break;
+        default: hipLaunchKernelGGL((k_anchor_vals<false, 0u>), grid, blk, 0, st, G, a, ne, cp, vp); break;
+    }
     TM_HIP(hipGetLastError());
     tm_prof_end(tok, st);
     TM_HIP(hipStreamSynchronize(st));

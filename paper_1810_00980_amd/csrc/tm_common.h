@@ -95,8 +95,13 @@ struct tm_graph {
     DevBuf inc_nd;   // uint32[2 m_nl]: other endpoint | (dir << 31)
     DevBuf inc_t;    // int64[2 m_nl]
     DevBuf inc_twin; // uint32[2 m_nl]: position of the same edge in its other endpoint's list
-    DevBuf inc_hi;   // uint8[2 m_nl]: 1 when the other endpoint ranks above the list's owner
-                     // (rank = (incidence-list length, node id))
+    // ranked sublists: the entries of each combined list whose other endpoint
+    // ranks above the list's owner (rank = (incidence-list length, node id)),
+    // in the same time order
+    int64_t n_hi = 0;
+    DevBuf hi_off;   // int64[n+1]
+    DevBuf hi_nd;    // uint32[n_hi]
+    DevBuf hi_t;     // int64[n_hi]
 
     // unordered pairs {a < b}: one time-sorted timeline per pair holding the
     // edges of both directions; entry e carries its time and the number of
@@ -148,7 +153,7 @@ struct DevGraph {
     const int64_t *in_off; const int32_t *in_nbr; const int64_t *in_t;
     const int64_t *sp_off; const int32_t *sp_nbr; const int64_t *sp_beg; const int64_t *pr_t;
     const int64_t *inc_off; const uint32_t *inc_nd; const int64_t *inc_t; const uint32_t *inc_twin;
-    const uint8_t *inc_hi;
+    int64_t n_hi; const int64_t *hi_off; const uint32_t *hi_nd; const int64_t *hi_t;
     const PairSlot *ph_slot; int64_t ph_cap;
     const PairMeta *pmeta; const int32_t *pb_idx;
     const PairEnt *up_ent;

@@ -155,7 +155,7 @@ __global__ void k_inc_twin(const uint32_t *vals, int64_t len, uint32_t *posv, ui
     else twin[j] = posv[v ^ 1u];
 }
 
-__global__ void k_inc_rank(const int64_t *inc_off, const uint32_t *nd, int64_t len, int64_t n, uint8_t *hi) {
+__global__ void k_inc_rank(const int64_t *inc_off, const uint32_t *nd, int64_t len, int64_t n, int64_t *hi) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= len) return;
     int64_t lo = 0, up = n;  // owner: largest v with inc_off[v] <= j
@@ -167,6 +167,27 @@ __global__ void k_inc_rank(const int64_t *inc_off, const uint32_t *nd, int64_t l
     int64_t v = lo, y = nd[j] & 0x7FFFFFFFu;
     int64_t dv = inc_off[v + 1] - inc_off[v], dy = inc_off[y + 1] - inc_off[y];
     hi[j] = (dy > dv || (dy == dv && y > v)) ? 1 : 0;
+}
+
+// ranked sublists: entry j goes to pos[j] when it is flagged; node offsets
+// are the positions of the nodes' first entries
+__global__ void k_hi_fill(const int64_t *flag_pos, const int64_t *flag_orig_hi, const uint32_t *nd, const int64_t *tl,
+                          int64_t len, uint32_t *hnd, int64_t *ht) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < len && flag_orig_hi[j]) {
+        int64_t q = flag_pos[j];
+        hnd[q] = nd[j];
+        ht[q] = tl[j];
+    }
+}
+
+__global__ void k_hi_off(const int64_t *inc_off, const int64_t *flag_pos, int64_t n, int64_t len, int64_t n_hi,
+                         int64_t *hoff) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x <= n) {
+        int64_t o = inc_off[x];
+        hoff[x] = o < len ? flag_pos[o] : n_hi;
+    }
 }
 
 __global__ void k_inc_fill(const uint32_t *vals, int64_t len, const int64_t *nl_pos, const int32_t *es_src,
@@ -568,7 +589,6 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
         TM_TRY(g->inc_nd.alloc((size_t)len * 4));
         TM_TRY(g->inc_t.alloc((size_t)len * 8));
         TM_TRY(g->inc_twin.alloc((size_t)len * 4));
-        TM_TRY(g->inc_hi.alloc((size_t)len));
         TM_TRY(g->inc_off.alloc((size_t)(n + 1) * 8));
         if (m_nl > 0) {
             hipLaunchKernelGGL(k_inc_keys, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, nl.as<int64_t>(), m_nl,
@@ -591,16 +611,38 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
         hipLaunchKernelGGL(k_lower_bound, dim3(tm_blocks(n + 1, TPB)), dim3(TPB), 0, st, ik.as<uint64_t>(), len, n,
                            (uint64_t)1, g->inc_off.as<int64_t>());
         TM_HIP(hipGetLastError());
+        // ranked sublists
+        DevBuf hflag, hpos;
+        TM_TRY(hflag.alloc((size_t)(len + 1) * 8));
+        TM_TRY(hpos.alloc((size_t)(len + 1) * 8));
+        int64_t n_hi = 0;
         if (m_nl > 0) {
             hipLaunchKernelGGL(k_inc_rank, dim3(tm_blocks(len, TPB)), dim3(TPB), 0, st, g->inc_off.as<int64_t>(),
-                               g->inc_nd.as<uint32_t>(), len, n, g->inc_hi.as<uint8_t>());
+                               g->inc_nd.as<uint32_t>(), len, n, hflag.as<int64_t>());
+            TM_HIP(hipGetLastError());
+            TM_HIP(hipMemcpyAsync(hpos.p, hflag.p, (size_t)len * 8, hipMemcpyDeviceToDevice, st));
+            TM_TRY(tm_scan_i64(hpos.as<int64_t>(), len, cnt.as<int64_t>(), st));
+            TM_HIP(hipMemcpyAsync(&n_hi, cnt.p, 8, hipMemcpyDeviceToHost, st));
+            TM_HIP(hipStreamSynchronize(st));
+        }
+        g->n_hi = n_hi;
+        TM_TRY(g->hi_nd.alloc((size_t)(n_hi > 0 ? n_hi : 1) * 4));
+        TM_TRY(g->hi_t.alloc((size_t)(n_hi > 0 ? n_hi : 1) * 8));
+        TM_TRY(g->hi_off.alloc((size_t)(n + 1) * 8));
+        if (m_nl > 0) {
+            hipLaunchKernelGGL(k_hi_fill, dim3(tm_blocks(len, TPB)), dim3(TPB), 0, st, hpos.as<int64_t>(),
+                               hflag.as<int64_t>(), g->inc_nd.as<uint32_t>(), g->inc_t.as<int64_t>(), len,
+                               g->hi_nd.as<uint32_t>(), g->hi_t.as<int64_t>());
             TM_HIP(hipGetLastError());
         }
+        hipLaunchKernelGGL(k_hi_off, dim3(tm_blocks(n + 1, TPB)), dim3(TPB), 0, st, g->inc_off.as<int64_t>(),
+                           hpos.as<int64_t>(), n, len, n_hi, g->hi_off.as<int64_t>());
+        TM_HIP(hipGetLastError());
         TM_HIP(hipStreamSynchronize(st));
     }
     const DevBuf *all[] = {&g->es_src, &g->es_dst, &g->es_t, &g->pos_of, &g->out_off, &g->out_nbr, &g->out_t,
                            &g->in_off, &g->in_nbr, &g->in_t, &g->sp_off, &g->sp_nbr, &g->sp_beg, &g->pr_t,
-                           &g->inc_off, &g->inc_nd, &g->inc_t, &g->inc_twin, &g->inc_hi, &g->up_ent, &g->ph_slot, &g->pmeta, &g->pb_idx};
+                           &g->inc_off, &g->inc_nd, &g->inc_t, &g->inc_twin, &g->hi_off, &g->hi_nd, &g->hi_t, &g->up_ent, &g->ph_slot, &g->pmeta, &g->pb_idx};
     int64_t tot = 0;
     for (const DevBuf *b : all) tot += (int64_t)b->bytes;
     g->device_bytes = tot;
@@ -619,7 +661,10 @@ DevGraph dev_view(const tm_graph *g) {
     v.pr_t = g->pr_t.as<int64_t>();
     v.inc_off = g->inc_off.as<int64_t>(); v.inc_nd = g->inc_nd.as<uint32_t>(); v.inc_t = g->inc_t.as<int64_t>();
     v.inc_twin = g->inc_twin.as<uint32_t>();
-    v.inc_hi = g->inc_hi.as<uint8_t>();
+    v.n_hi = g->n_hi;
+    v.hi_off = g->hi_off.as<int64_t>();
+    v.hi_nd = g->hi_nd.as<uint32_t>();
+    v.hi_t = g->hi_t.as<int64_t>();
     v.ph_slot = g->ph_slot.as<PairSlot>(); v.ph_cap = g->ph_cap;
     v.pmeta = g->pmeta.as<PairMeta>();
     v.pb_idx = g->pb_idx.as<int32_t>();

@@ -41,13 +41,18 @@ namespace {
 
 using namespace sweepdev;
 
-template <int MODE, bool FWD>
+template <int MODE, bool FWD, unsigned CLS>
 __global__ void __launch_bounds__(SW_TPB) k_sweep3(DevGraph G, SweepArgs a) {
     __shared__ unsigned long long lds[36 * 4];
     for (int k = threadIdx.x; k < 36 * 4; k += SW_TPB) lds[k] = 0;
     __syncthreads();
     const int lane = threadIdx.x & (TM_WAVE - 1);
-    const int64_t nE = a.n_entries;
+    // exact triangles run over the ranked sublists
+    constexpr bool RANKED = MODE == MODE_COUNT && FWD && CLS == 8u;
+    const int64_t *off = RANKED ? G.hi_off : G.inc_off;
+    const uint32_t *ndv = RANKED ? G.hi_nd : G.inc_nd;
+    const int64_t *tv = RANKED ? G.hi_t : G.inc_t;
+    const int64_t nE = RANKED ? G.n_hi : a.n_entries;
     while (true) {
         int64_t base = 0;
         if (lane == 0) base = (int64_t)atomicAdd((unsigned long long *)a.counter, (unsigned long long)TM_WAVE);
@@ -55,11 +60,11 @@ __global__ void __launch_bounds__(SW_TPB) k_sweep3(DevGraph G, SweepArgs a) {
         if (base >= nE) break;
         int64_t i = base + lane;
         if (i < nE) {
-            int64_t x = owner_of(G.inc_off, G.n, i);
-            int64_t lb = G.inc_off[x], le = G.inc_off[x + 1];
-            uint32_t nd = G.inc_nd[i];
+            int64_t x = owner_of(off, G.n, i);
+            int64_t lb = off[x], le = off[x + 1];
+            uint32_t nd = ndv[i];
             uint32_t y = nd & 0x7FFFFFFFu, d = nd >> 31;
-            int64_t t = G.inc_t[i];
+            int64_t t = tv[i];
             bool go = true;
             int64_t wlo = LLONG_MIN, whi = LLONG_MAX;
             if (a.windowed == 1) {
@@ -76,7 +81,8 @@ __global__ void __launch_bounds__(SW_TPB) k_sweep3(DevGraph G, SweepArgs a) {
                 if (FWD) {
                     int64_t hi = (t > LLONG_MAX - a.delta) ? LLONG_MAX : t + a.delta;
                     hi = hi < whi ? hi : whi;
-                    sweep_fwd<MODE>(G, a, i, le, y, d, t, hi, wlo, lds);
+                    if constexpr (RANKED) sweep_tri_ranked(G, a, i, le, y, d, t, hi, wlo, lds);
+                    else sweep_fwd<MODE, CLS>(G, a, i, le, y, d, t, hi, wlo, lds);
                 } else {
                     int64_t lo = (t < LLONG_MIN + a.delta) ? LLONG_MIN : t - a.delta;
                     lo = lo > wlo ? lo : wlo;
@@ -132,13 +138,23 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, hipStr
     int64_t nb = (int64_t)ncu * 8;
     if (nb > want_blocks) nb = want_blocks;
     if (nb < 1) nb = 1;
-    static const char *names[3][2] = {{"sweep3_fwd_count", "sweep3_bwd_count"},
-                                      {"sweep3_fwd_weight", "sweep3_bwd_weight"},
-                                      {"sweep3_fwd_hist", "sweep3_bwd_hist"}};
-    if (fwd) {
+    static const char *names[3][3] = {{"sweep3_fwd_count", "sweep3_bwd_count", "sweep3_tri_count"},
+                                      {"sweep3_fwd_weight", "sweep3_bwd_weight", "sweep3_tri_weight"},
+                                      {"sweep3_fwd_hist", "sweep3_bwd_hist", "sweep3_tri_hist"}};
+    // forward sweeps: 2-node and stars in one kernel, triangles in another
+    if (fwd && (a.want_fwd & 7u)) {
         TM_HIP(hipMemsetAsync(a.counter, 0, 8, st));
         void *tok = tm_prof_begin(names[MODE][0], st);
-        hipLaunchKernelGGL((k_sweep3<MODE, true>), dim3((unsigned)nb), dim3(SW_TPB), 0, st, G, a);
+        hipLaunchKernelGGL((k_sweep3<MODE, true, 7u>), dim3((unsigned)nb), dim3(SW_TPB), 0, st, G, a);
+        TM_HIP(hipGetLastError());
+        tm_prof_end(tok, st);
+    }
+    if (fwd && (a.want_fwd & 8u)) {
+        TM_HIP(hipMemsetAsync(a.counter + 2, 0, 8, st));
+        SweepArgs b = a;
+        b.counter = a.counter + 2;
+        void *tok = tm_prof_begin(names[MODE][2], st);
+        hipLaunchKernelGGL((k_sweep3<MODE, true, 8u>), dim3((unsigned)nb), dim3(SW_TPB), 0, st, G, b);
         TM_HIP(hipGetLastError());
         tm_prof_end(tok, st);
     }
@@ -147,7 +163,7 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, hipStr
         SweepArgs b = a;
         b.counter = a.counter + 1;
         void *tok = tm_prof_begin(names[MODE][1], st);
-        hipLaunchKernelGGL((k_sweep3<MODE, false>), dim3((unsigned)nb), dim3(SW_TPB), 0, st, G, b);
+        hipLaunchKernelGGL((k_sweep3<MODE, false, 0u>), dim3((unsigned)nb), dim3(SW_TPB), 0, st, G, b);
         TM_HIP(hipGetLastError());
         tm_prof_end(tok, st);
     }
@@ -196,23 +212,59 @@ __global__ void k_census(DevGraph G, int64_t delta, unsigned long long *out) {
     }
 }
 
+// entries scanned by the exact triangle sweep over the ranked sublists
+__global__ void k_census_ranked(DevGraph G, int64_t delta, unsigned long long *out) {
+    __shared__ unsigned long long sf[SW_TPB];
+    unsigned long long f = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < G.n_hi;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t x = owner_of(G.hi_off, G.n, i);
+        int64_t le = G.hi_off[x + 1];
+        int64_t t = G.hi_t[i];
+        int64_t hi = (t > LLONG_MAX - delta) ? LLONG_MAX : t + delta;
+        int64_t a0 = i + 1, a1 = le;
+        while (a0 < a1) {
+            int64_t mid = (a0 + a1) >> 1;
+            if (G.hi_t[mid] <= hi) a0 = mid + 1;
+            else a1 = mid;
+        }
+        f += (unsigned long long)(a0 - i - 1);
+    }
+    sf[threadIdx.x] = f;
+    __syncthreads();
+    for (int s = SW_TPB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sf[threadIdx.x] += sf[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(&out[2], sf[0]);
+}
+
 }  // namespace
 
-tm_status tm_sweep_census_impl(const tm_graph *g, int64_t delta, int64_t *fwd, int64_t *bwd, hipStream_t st) {
+tm_status tm_sweep_census_impl(const tm_graph *g, int64_t delta, int64_t *fwd, int64_t *bwd, int64_t *ranked,
+                               hipStream_t st) {
     DevBuf o;
     TM_TRY(o.alloc(64));
-    TM_HIP(hipMemsetAsync(o.p, 0, 16, st));
+    TM_HIP(hipMemsetAsync(o.p, 0, 24, st));
     if (g->m_nl > 0) {
         unsigned nb = tm_blocks(2 * g->m_nl, SW_TPB);
         if (nb > 8192) nb = 8192;
         hipLaunchKernelGGL(k_census, dim3(nb), dim3(SW_TPB), 0, st, dev_view(g), delta, o.as<unsigned long long>());
         TM_HIP(hipGetLastError());
     }
-    int64_t h[2];
-    TM_HIP(hipMemcpyAsync(h, o.p, 16, hipMemcpyDeviceToHost, st));
+    if (g->n_hi > 0) {
+        unsigned nb = tm_blocks(g->n_hi, SW_TPB);
+        if (nb > 8192) nb = 8192;
+        hipLaunchKernelGGL(k_census_ranked, dim3(nb), dim3(SW_TPB), 0, st, dev_view(g), delta,
+                           o.as<unsigned long long>());
+        TM_HIP(hipGetLastError());
+    }
+    int64_t h[3];
+    TM_HIP(hipMemcpyAsync(h, o.p, 24, hipMemcpyDeviceToHost, st));
     TM_HIP(hipStreamSynchronize(st));
     *fwd = h[0];
     *bwd = h[1];
+    *ranked = h[2];
     return TM_OK;
 }
 

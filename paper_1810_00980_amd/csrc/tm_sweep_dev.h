@@ -271,29 +271,26 @@ __device__ inline void tri_rank(const DevGraph &G, uint32_t yi, uint32_t di, int
     }
 }
 
-// forward sweep of one anchor (codes 0..27)
-template <int MODE>
+// forward sweep of one anchor (codes 0..27); CLS (1 two-node, 2 star B,
+// 4 star A, 8 triangle) fixes at compile time which classes the kernel can
+// count, so that a kernel keeps registers only for its own accumulators
+template <int MODE, unsigned CLS>
 __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t i, int64_t end, uint32_t y1,
                                  uint32_t d1, int64_t t1, int64_t hi, int64_t lo_win, unsigned long long *lds,
                                  OneCode *one = nullptr) {
     // slots: 0..3 two-node [2*d2+d3], 4..7 star B, 8..11 star A, 12..15 triangle
     Acc<MODE, 16> A;
     A.clear();
-    const bool two = (a.want_fwd & 1u) && d1 == 0;
-    const bool sb = a.want_fwd & 2u, sa = a.want_fwd & 4u, tri = a.want_fwd & 8u;
-    // Exact totals (no duration per instance needed) count triangles at their
-    // lowest-ranked node (tri_rank); estimates and histograms keep one pair
-    // lookup per last edge of x's list, which carries each duration.
-    bool tri_x = tri;
-    bool tri_r = false;
-    uint64_t tc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const bool two = (CLS & 1u) && (a.want_fwd & 1u) && d1 == 0;
+    const bool sb = (CLS & 2u) && (a.want_fwd & 2u), sa = (CLS & 4u) && (a.want_fwd & 4u);
+    const bool tri = (CLS & 8u) && (a.want_fwd & 8u);
+    // Exact triangle totals are counted at the lowest-ranked node instead
+    // (sweep_tri_ranked); here triangles are counted only with durations, by
+    // one pair lookup per last edge of x's list.
+    static_assert(MODE != MODE_COUNT || (CLS & 8u) == 0u, "exact triangles use sweep_tri_ranked");
     TriCache tcache;
     tcache.yc = ~0u;
     tcache.p = -1;
-    if constexpr (MODE == MODE_COUNT) {
-        tri_x = false;
-        tri_r = tri && G.inc_hi[i];
-    }
     uint64_t cs0 = 0, cs1 = 0, ca0 = 0, ca1 = 0;  // middles before the current time group
     uint64_t ps0 = 0, ps1 = 0, pa0 = 0, pa1 = 0;  // entries of the current time group
     int64_t tg = t1;
@@ -326,8 +323,7 @@ __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t 
                 acc_add<MODE, 16>(A, 8, dj, cs0, w, a.hist, 12 + 4 * (int)d1, dlt, a.delta);
                 acc_add<MODE, 16>(A, 10, dj, cs1, w, a.hist, 14 + 4 * (int)d1, dlt, a.delta);
             }
-            if (tri_r && G.inc_hi[j]) tri_rank(G, y1, d1, t1, yj, dj, tj, hi, lo_win, a.delta, tc, tcache);
-            if (tri_x) {
+            if (tri) {
                 // middles on {y1, yj} strictly between t1 and tj; the pair and
                 // its count up to t1 are kept while entries lead to yj again
                 if (yj != tcache.yc) {
@@ -360,17 +356,34 @@ __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t 
         codes[12 + k] = 20 + 4 * (int)d1 + k;
     }
     flush<MODE, 16>(A, codes, lds, one);
-    if constexpr (MODE == MODE_COUNT) {
-        if (tri) {
+    (void)lo_win;
+}
+
+// Exact triangle counts of one anchor i of x's ranked sublist (entries
+// [i, end) of hi_nd / hi_t): every later entry j within the horizon that
+// leads to another node gives one tri_rank lookup (codes 20..27).
+__device__ inline void sweep_tri_ranked(const DevGraph &G, const SweepArgs &a, int64_t i, int64_t end, uint32_t y1,
+                                        uint32_t d1, int64_t t1, int64_t hi, int64_t lo_win,
+                                        unsigned long long *lds, OneCode *one = nullptr) {
+    uint64_t tc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    TriCache tcache;
+    tcache.yc = ~0u;
+    tcache.p = -1;
+    for (int64_t j = i + 1; j < end; ++j) {
+        int64_t tj = G.hi_t[j];
+        if (tj > hi) break;
+        if (tj == t1) continue;
+        uint32_t nd = G.hi_nd[j];
+        uint32_t yj = nd & 0x7FFFFFFFu, dj = nd >> 31;
+        if (yj != y1) tri_rank(G, y1, d1, t1, yj, dj, tj, hi, lo_win, a.delta, tc, tcache);
+    }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (!tc[k]) continue;
-                if (one) {
-                    if (one->code == 20 + k) tm_add_u128(one->cl, one->ch, tc[k], 0);
-                } else {
-                    lds_add_u128(&lds[4 * (20 + k)], &lds[4 * (20 + k) + 1], tc[k], 0);
-                }
-            }
+    for (int k = 0; k < 8; ++k) {
+        if (!tc[k]) continue;
+        if (one) {
+            if (one->code == 20 + k) tm_add_u128(one->cl, one->ch, tc[k], 0);
+        } else {
+            lds_add_u128(&lds[4 * (20 + k)], &lds[4 * (20 + k) + 1], tc[k], 0);
         }
     }
 }

@@ -296,3 +296,41 @@ def test_batched_estimates_match_per_seed(tm):
     est, kept = tm.estimate_batch(G, ti.CYCLE4, delta, c, p, [1, 2])
     for k, sd in enumerate((1, 2)):
         assert close(est[k], oracle.estimate(g.src, g.dst, g.t, ti.CYCLE4, delta, c, p, sd)["Z"])
+
+
+def _census_numpy(g, delta):
+    """Entries each sweep scans, counted on the host from the definition:
+    per node, the time-sorted incidence list of its non-self-loop edges; the
+    forward (backward) entries of an anchor are the later (earlier) entries of
+    its list within delta; the ranked sublist keeps the entries whose other
+    endpoint has a longer list (ties: larger id)."""
+    keep = g.src != g.dst
+    x = np.concatenate([g.src[keep], g.dst[keep]]).astype(np.int64)
+    y = np.concatenate([g.dst[keep], g.src[keep]]).astype(np.int64)
+    t = np.concatenate([g.t[keep], g.t[keep]]).astype(np.int64)
+    order = np.lexsort((t, x))
+    x, y, t = x[order], y[order], t[order]
+    deg = np.bincount(x, minlength=g.n)
+    fwd = bwd = 0
+    for v in np.unique(x):
+        tv = t[x == v]
+        fwd += int((np.searchsorted(tv, tv + delta, side="right") - np.arange(tv.size) - 1).sum())
+        bwd += int((np.arange(tv.size) - np.searchsorted(tv, tv - delta, side="left")).sum())
+    hi = (deg[y] > deg[x]) | ((deg[y] == deg[x]) & (y > x))
+    rf = 0
+    for v in np.unique(x[hi]):
+        tv = t[(x == v) & hi]
+        rf += int((np.searchsorted(tv, tv + delta, side="right") - np.arange(tv.size) - 1).sum())
+    return int(x.size), fwd, bwd, int(hi.sum()), rf
+
+
+@pytest.mark.gpu
+def test_sweep_census_matches_host_count(tm):
+    """The work census behind the roofline figures counts exactly the list
+    entries each sweep scans, the ranked sublists included."""
+    for g, delta in ((ti.random_small_graph(30, 4000, 20000, 5, allow_self_loops=True), 300),
+                     (ti.zipf_graph(2000, 30000, 1.8, 200000, 9), 3600)):
+        G = load(tm, g)
+        got = tm.sweep_census(G, delta)
+        want = _census_numpy(g, delta)
+        assert tuple(got) == want, (got, want)
