@@ -388,6 +388,177 @@ __device__ inline void sweep_tri_ranked(const DevGraph &G, const SweepArgs &a, i
     }
 }
 
+// Exact 2-node and star counts of one forward anchor i (codes 0..19) with
+// 32-bit running counts and per-entry work only at the entries that lead to
+// y1 ("s-entries").  For window entries j (t1 < tj <= hi, ties with t1
+// left out), with cs_k(j) / ca_k(j) the s-entries / all entries of
+// direction k in earlier time groups than j:
+//   2-node [2k + d]            sum over s-entries j with d_j = d of cs_k(j)      (= Z[d][k])
+//   star B [4 + 4 d1 + 2k + d] sum over s-entries j with d_j = d of ca_k - cs_k  (= B[d][k] - Z[d][k])
+//   star A [12 + 4 d1 + 2k + d] sum over the other entries j with d_j = d of cs_k(j)
+// The star-A sum over all entries, Y[d][k], equals sum over s-entries m of
+// direction k of the entries of direction d after m's time group, i.e.
+// S_k N_d - U[d][k] with S_k, N_d the window's totals and U[d][k] the sum,
+// taken when m's group closes, of the direction-d entries up to that group.
+__device__ inline void count_out(unsigned long long *lds, OneCode *one, int code, uint64_t v) {
+    if (!v) return;
+    if (one) {
+        if (one->code == code) tm_add_u128(one->cl, one->ch, v, 0);
+    } else {
+        lds_add_u128(&lds[4 * code], &lds[4 * code + 1], v, 0);
+    }
+}
+
+__device__ inline void sweep_fwd_count(const DevGraph &G, const SweepArgs &a, int64_t i, int64_t end, uint32_t y1,
+                                       uint32_t d1, int64_t t1, int64_t hi, unsigned long long *lds,
+                                       OneCode *one = nullptr) {
+    uint32_t as0 = 0, as1 = 0, aa0 = 0, aa1 = 0;  // s-entries / all entries so far, by direction
+    uint32_t cs0 = 0, cs1 = 0, ca0 = 0, ca1 = 0;  // the same before the current time group
+    uint32_t ps0 = 0, ps1 = 0;                    // s-entries of the current time group
+    uint64_t zt0 = 0, zt1 = 0, z10 = 0, z11 = 0;  // sums of cs_k over s-entries: all, and those with d = 1
+    uint64_t bt0 = 0, bt1 = 0, b10 = 0, b11 = 0;  // sums of ca_k over s-entries
+    uint64_t u00 = 0, u01 = 0, u10 = 0, u11 = 0;  // U[d][k]
+    int64_t tg = t1;
+    int64_t j = i + 1;
+    int64_t tn = j < end ? G.inc_t[j] : 0;
+    uint32_t nn = j < end ? G.inc_nd[j] : 0;
+    while (j < end) {
+        const int64_t tj = tn;
+        const uint32_t nd = nn;
+        if (tj > hi) break;
+        ++j;
+        if (j < end) {  // next entry's loads in flight while this one is counted
+            tn = G.inc_t[j];
+            nn = G.inc_nd[j];
+        }
+        if (tj == t1) continue;
+        if (tj != tg) {
+            u00 += (uint64_t)ps0 * aa0;
+            u01 += (uint64_t)ps1 * aa0;
+            u10 += (uint64_t)ps0 * aa1;
+            u11 += (uint64_t)ps1 * aa1;
+            ps0 = ps1 = 0;
+            cs0 = as0;
+            cs1 = as1;
+            ca0 = aa0;
+            ca1 = aa1;
+            tg = tj;
+        }
+        const uint32_t d = nd >> 31;
+        if ((nd & 0x7FFFFFFFu) == y1) {
+            zt0 += cs0;
+            zt1 += cs1;
+            bt0 += ca0;
+            bt1 += ca1;
+            if (d) {
+                z10 += cs0;
+                z11 += cs1;
+                b10 += ca0;
+                b11 += ca1;
+                ++as1;
+                ++ps1;
+            } else {
+                ++as0;
+                ++ps0;
+            }
+        }
+        aa0 += 1u - d;
+        aa1 += d;
+    }
+    u00 += (uint64_t)ps0 * aa0;
+    u01 += (uint64_t)ps1 * aa0;
+    u10 += (uint64_t)ps0 * aa1;
+    u11 += (uint64_t)ps1 * aa1;
+    // Z[d][k], B[d][k], Y[d][k]
+    const uint64_t Z00 = zt0 - z10, Z01 = zt1 - z11, Z10 = z10, Z11 = z11;
+    const uint64_t B00 = bt0 - b10, B01 = bt1 - b11, B10 = b10, B11 = b11;
+    const uint64_t Y00 = (uint64_t)as0 * aa0 - u00, Y01 = (uint64_t)as1 * aa0 - u01;
+    const uint64_t Y10 = (uint64_t)as0 * aa1 - u10, Y11 = (uint64_t)as1 * aa1 - u11;
+    const int b = 4 * (int)d1;
+    if ((a.want_fwd & 1u) && d1 == 0) {  // code 2k + d
+        count_out(lds, one, 0, Z00);
+        count_out(lds, one, 1, Z10);
+        count_out(lds, one, 2, Z01);
+        count_out(lds, one, 3, Z11);
+    }
+    if (a.want_fwd & 2u) {  // code 4 + 4 d1 + 2k + d
+        count_out(lds, one, 4 + b, B00 - Z00);
+        count_out(lds, one, 5 + b, B10 - Z10);
+        count_out(lds, one, 6 + b, B01 - Z01);
+        count_out(lds, one, 7 + b, B11 - Z11);
+    }
+    if (a.want_fwd & 4u) {  // code 12 + 4 d1 + 2k + d
+        count_out(lds, one, 12 + b, Y00 - Z00);
+        count_out(lds, one, 13 + b, Y10 - Z10);
+        count_out(lds, one, 14 + b, Y01 - Z01);
+        count_out(lds, one, 15 + b, Y11 - Z11);
+    }
+}
+
+// Exact star-C counts of one backward anchor (the last edge j, codes 28..35),
+// the same way: first edges i (lo <= ti < t3) that lead elsewhere than y3,
+// middles the s-entries (leading to y3) strictly between.  Over all i of
+// direction d1, the middles after i sum to S_k N_d1 - U[d1][k]; the s-entries'
+// own share Z[d1][k] is taken off.
+__device__ inline void sweep_bwd_count(const DevGraph &G, int64_t jj, int64_t beg, uint32_t y3, uint32_t d3,
+                                       int64_t t3, int64_t lo, unsigned long long *lds, OneCode *one = nullptr) {
+    uint32_t as0 = 0, as1 = 0, aa0 = 0, aa1 = 0;
+    uint32_t cs0 = 0, cs1 = 0, ps0 = 0, ps1 = 0;
+    uint64_t zt0 = 0, zt1 = 0, z10 = 0, z11 = 0;
+    uint64_t u00 = 0, u01 = 0, u10 = 0, u11 = 0;
+    int64_t tg = t3;
+    int64_t i = jj - 1;
+    int64_t tn = i >= beg ? G.inc_t[i] : 0;
+    uint32_t nn = i >= beg ? G.inc_nd[i] : 0;
+    while (i >= beg) {
+        const int64_t ti = tn;
+        const uint32_t nd = nn;
+        if (ti < lo) break;
+        --i;
+        if (i >= beg) {
+            tn = G.inc_t[i];
+            nn = G.inc_nd[i];
+        }
+        if (ti == t3) continue;
+        if (ti != tg) {
+            u00 += (uint64_t)ps0 * aa0;
+            u01 += (uint64_t)ps1 * aa0;
+            u10 += (uint64_t)ps0 * aa1;
+            u11 += (uint64_t)ps1 * aa1;
+            ps0 = ps1 = 0;
+            cs0 = as0;
+            cs1 = as1;
+            tg = ti;
+        }
+        const uint32_t d = nd >> 31;
+        if ((nd & 0x7FFFFFFFu) == y3) {
+            zt0 += cs0;
+            zt1 += cs1;
+            if (d) {
+                z10 += cs0;
+                z11 += cs1;
+                ++as1;
+                ++ps1;
+            } else {
+                ++as0;
+                ++ps0;
+            }
+        }
+        aa0 += 1u - d;
+        aa1 += d;
+    }
+    u00 += (uint64_t)ps0 * aa0;
+    u01 += (uint64_t)ps1 * aa0;
+    u10 += (uint64_t)ps0 * aa1;
+    u11 += (uint64_t)ps1 * aa1;
+    // code 28 + 4 d1 + 2k + d3 = Y[d1][k] - Z[d1][k]
+    const int c = 28 + (int)d3;
+    count_out(lds, one, c + 0, (uint64_t)as0 * aa0 - u00 - (zt0 - z10));
+    count_out(lds, one, c + 2, (uint64_t)as1 * aa0 - u01 - (zt1 - z11));
+    count_out(lds, one, c + 4, (uint64_t)as0 * aa1 - u10 - z10);
+    count_out(lds, one, c + 6, (uint64_t)as1 * aa1 - u11 - z11);
+}
+
 // backward sweep of one anchor (codes 28..35): star with e2 on e3's pair
 template <int MODE>
 __device__ inline void sweep_bwd(const DevGraph &G, const SweepArgs &a, int64_t jj, int64_t beg, uint32_t y3,
