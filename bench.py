@@ -306,6 +306,39 @@ def traffic_record(kernel):
     return rec.get("traffic_bytes_per_launch")
 
 
+# Algorithmic bytes per unit of the exact sweeps: 16 B per anchor edge (two
+# endpoints and a time), 12 B per scanned list entry (time and endpoint
+# word); each closing-pair lookup of the triangle sweep reads two bucket
+# bounds and the entry found, twice (tj and tj - delta): 48 B; a change of
+# closing pair also reads the hash slot (16 B), the pair's metadata (32 B)
+# and two more searches (48 B): 96 B.
+def exact_bytes(c):
+    return {
+        "sweep3_fwd_count": 16 * c["anchors"] + 12 * c["fwd_entries"],
+        "sweep3_bwd_count": 16 * c["anchors"] + 12 * c["bwd_entries"],
+        "sweep3_tri_count": 16 * c["ranked_anchors"] + 12 * c["ranked_entries"] + 48 * c["ranked_lookups"]
+        + 96 * c["ranked_pairs"],
+    }
+
+
+def exact_roofline(census, kern, steps):
+    """Roofline entry of the exact sweep kernel with the largest time, with
+    the achieved algorithmic GB/s of each exact sweep kernel beside it."""
+    eb = exact_bytes(census)
+    timed = {k: v for k, v in kern.items() if k in eb and v[1] > 0}
+    if not timed:
+        return None
+    per = {k: {"avg_launch_ms": v[0] / v[1], "algorithmic_bytes_per_launch": eb[k],
+               "achieved_GBs": eb[k] / (v[0] / v[1] / 1e3) / 1e9} for k, v in timed.items()}
+    dom = max(timed, key=lambda k: timed[k][0])
+    ach = per[dom]["achieved_GBs"]
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": traffic_record(dom), "kernel": dom, "avg_launch_ms": per[dom]["avg_launch_ms"],
+            "launches": timed[dom][1], "algorithmic_bytes_per_launch": eb[dom], "census": census,
+            "exact_kernels": per,
+            "sweep_kernels_ms_per_step": {k: v[0] / steps for k, v in kern.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -386,26 +419,7 @@ def main():
     G = tm.load_graph(src, dst, t, g.n)
     census = tm.sweep_census(G, delta)
     G.free()
-    anchors, fwd, bwd, r_anchors, r_fwd = census
-    # algorithmic bytes per launch of the exact sweeps: 12 B (time + endpoint
-    # word) per anchor and per scanned list entry
-    exact_bytes = {"sweep3_fwd_count": 12 * (anchors + fwd), "sweep3_tri_count": 12 * (r_anchors + r_fwd),
-                   "sweep3_bwd_count": 12 * (anchors + bwd)}
-    roofline = None
-    timed = {k: v for k, v in kern.items() if k in exact_bytes and v[1] > 0}
-    if timed:
-        dom = max(timed, key=lambda k: timed[k][0])
-        kms, kn = timed[dom]
-        bytes_per_launch = exact_bytes[dom]
-        avg_s = kms / kn / 1e3
-        ach = bytes_per_launch / avg_s / 1e9
-        roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": ach / HBM_PEAK_GBS, "traffic": traffic_record(dom),
-                    "kernel": dom, "avg_launch_ms": kms / kn, "launches": kn,
-                    "algorithmic_bytes_per_launch": bytes_per_launch,
-                    "census": {"anchors": anchors, "fwd_entries": fwd, "bwd_entries": bwd,
-                               "ranked_anchors": r_anchors, "ranked_entries": r_fwd},
-                    "sweep_kernels_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()}}
+    roofline = exact_roofline(census, kern, args.steps)
     out = {
         "metric": "temporal edges/s per motif query (exact & p=0.1 estimate) vs CPU",
         "value": g.m * q / dt, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

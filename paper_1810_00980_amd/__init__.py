@@ -98,7 +98,7 @@ _SIGS = {
     "tm_profile_enable": [i32],
     "tm_profile_reset": [],
     "tm_profile_read": [ctypes.c_char_p, P, P],
-    "tm_sweep_census": [P, i64, P, P, P, P, P, P],
+    "tm_sweep_census": [P, i64, P, P],
     "tm_strerror": [i32],
     "tm_version": [],
 }
@@ -308,14 +308,17 @@ def profile_read(kernel: str):
     return ms.value, n.value
 
 
-def sweep_census(g: Graph, delta: int, stream=None):
-    """(anchors, forward-scanned entries, backward-scanned entries, ranked
-    anchors, ranked-scanned entries) of the exact sweeps; the last two are
-    the exact triangle sweep's, over the ranked sublists."""
-    v = [ctypes.c_int64() for _ in range(5)]
-    _check(_lib.tm_sweep_census(g.handle, int(delta), *(ctypes.byref(x) for x in v), _stream(stream)),
-           "tm_sweep_census")
-    return tuple(x.value for x in v)
+class Census(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in
+                ("anchors", "fwd_entries", "bwd_entries", "ranked_anchors", "ranked_entries",
+                 "ranked_lookups", "ranked_pairs")]
+
+
+def sweep_census(g: Graph, delta: int, stream=None) -> dict:
+    """Work census of the exact three-edge sweeps (tm_census fields)."""
+    c = Census()
+    _check(_lib.tm_sweep_census(g.handle, int(delta), ctypes.byref(c), _stream(stream)), "tm_sweep_census")
+    return {name: getattr(c, name) for name, _ in Census._fields_}
 
 
 def batch_config(g: Graph, edges, delta: int, c: int, p: float, stream=None):

@@ -78,8 +78,7 @@ void tm_prof_collect() {
     P.pending.clear();
 }
 
-tm_status tm_sweep_census_impl(const tm_graph *g, int64_t delta, int64_t *fwd, int64_t *bwd, int64_t *ranked,
-                               hipStream_t st);
+tm_status tm_sweep_census_impl(const tm_graph *g, int64_t delta, tm_census *c, hipStream_t st);
 
 namespace {
 
@@ -771,15 +770,15 @@ extern "C" tm_status tm_profile_read(const char *kernel, double *total_ms, int64
     return TM_OK;
 }
 
-extern "C" tm_status tm_sweep_census(const tm_graph *g, int64_t delta, int64_t *anchors, int64_t *fwd_entries,
-                                     int64_t *bwd_entries, int64_t *ranked_anchors, int64_t *ranked_entries,
-                                     void *hip_stream) {
-    if (!g || delta < 0 || !anchors || !fwd_entries || !bwd_entries || !ranked_anchors || !ranked_entries)
-        return TM_EINVAL;
+extern "C" tm_status tm_sweep_census(const tm_graph *g, int64_t delta, tm_census *out, void *hip_stream) {
+    if (!g || delta < 0 || !out) return TM_EINVAL;
     hipStream_t st = (hipStream_t)hip_stream;
-    *anchors = 2 * g->m_nl;
-    *ranked_anchors = g->n_hi;
-    return finish(tm_sweep_census_impl(g, delta, fwd_entries, bwd_entries, ranked_entries, st), st);
+    tm_census c;
+    c.anchors = 2 * g->m_nl;
+    c.ranked_anchors = g->n_hi;
+    tm_status s = finish(tm_sweep_census_impl(g, delta, &c, st), st);
+    if (s == TM_OK) *out = c;
+    return s;
 }
 
 extern "C" const char *tm_strerror(tm_status s) {

@@ -214,40 +214,51 @@ __global__ void k_census(DevGraph G, int64_t delta, unsigned long long *out) {
     }
 }
 
-// entries scanned by the exact triangle sweep over the ranked sublists
+// entries scanned by the exact triangle sweep over the ranked sublists, the
+// closing-pair lookups among them and the changes of closing pair
 __global__ void k_census_ranked(DevGraph G, int64_t delta, unsigned long long *out) {
-    __shared__ unsigned long long sf[SW_TPB];
-    unsigned long long f = 0;
+    __shared__ unsigned long long sh[3][SW_TPB];
+    unsigned long long f = 0, lk = 0, pc = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < G.n_hi;
          i += (int64_t)gridDim.x * blockDim.x) {
         int64_t x = owner_of(G.hi_off, G.n, i);
         int64_t le = G.hi_off[x + 1];
         int64_t t = G.hi_t[i];
+        uint32_t y1 = G.hi_nd[i] & 0x7FFFFFFFu;
         int64_t hi = (t > LLONG_MAX - delta) ? LLONG_MAX : t + delta;
-        int64_t a0 = i + 1, a1 = le;
-        while (a0 < a1) {
-            int64_t mid = (a0 + a1) >> 1;
-            if (G.hi_t[mid] <= hi) a0 = mid + 1;
-            else a1 = mid;
+        uint32_t prev = ~0u;
+        int64_t j = i + 1;
+        for (; j < le && G.hi_t[j] <= hi; ++j) {
+            if (G.hi_t[j] == t) continue;
+            uint32_t yj = G.hi_nd[j] & 0x7FFFFFFFu;
+            if (yj == y1) continue;
+            ++lk;
+            if (yj != prev) ++pc;
+            prev = yj;
         }
-        f += (unsigned long long)(a0 - i - 1);
+        f += (unsigned long long)(j - i - 1);
     }
-    sf[threadIdx.x] = f;
+    sh[0][threadIdx.x] = f;
+    sh[1][threadIdx.x] = lk;
+    sh[2][threadIdx.x] = pc;
     __syncthreads();
     for (int s = SW_TPB / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sf[threadIdx.x] += sf[threadIdx.x + s];
+        if ((int)threadIdx.x < s) {
+            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicAdd(&out[2], sf[0]);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 3; ++q) atomicAdd(&out[2 + q], sh[q][0]);
+    }
 }
 
 }  // namespace
 
-tm_status tm_sweep_census_impl(const tm_graph *g, int64_t delta, int64_t *fwd, int64_t *bwd, int64_t *ranked,
-                               hipStream_t st) {
+tm_status tm_sweep_census_impl(const tm_graph *g, int64_t delta, tm_census *c, hipStream_t st) {
     DevBuf o;
     TM_TRY(o.alloc(64));
-    TM_HIP(hipMemsetAsync(o.p, 0, 24, st));
+    TM_HIP(hipMemsetAsync(o.p, 0, 40, st));
     if (g->m_nl > 0) {
         unsigned nb = tm_blocks(2 * g->m_nl, SW_TPB);
         if (nb > 8192) nb = 8192;
@@ -261,12 +272,14 @@ tm_status tm_sweep_census_impl(const tm_graph *g, int64_t delta, int64_t *fwd, i
                            o.as<unsigned long long>());
         TM_HIP(hipGetLastError());
     }
-    int64_t h[3];
-    TM_HIP(hipMemcpyAsync(h, o.p, 24, hipMemcpyDeviceToHost, st));
+    int64_t h[5];
+    TM_HIP(hipMemcpyAsync(h, o.p, 40, hipMemcpyDeviceToHost, st));
     TM_HIP(hipStreamSynchronize(st));
-    *fwd = h[0];
-    *bwd = h[1];
-    *ranked = h[2];
+    c->fwd_entries = h[0];
+    c->bwd_entries = h[1];
+    c->ranked_entries = h[2];
+    c->ranked_lookups = h[3];
+    c->ranked_pairs = h[4];
     return TM_OK;
 }
 

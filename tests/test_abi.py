@@ -36,6 +36,16 @@ def test_every_declared_symbol_is_exported(lib):
     assert not missing
 
 
+def test_no_library_symbol_left_undefined(lib):
+    """Every function of the library's own sources is defined in it: a
+    declaration whose definition went missing would otherwise only fail
+    when the library is loaded lazily at the first call."""
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--undefined-only", LIB], capture_output=True, text=True, check=True).stdout
+    own = [ln.split()[-1] for ln in out.splitlines() if re.search(r"tm_|sweepdev|DevGraph|tm_graph", ln)]
+    assert not own, own
+
+
 def test_python_binding_covers_the_abi():
     import paper_1810_00980_amd as tm
     assert set(declared()) == set(tm.EXPORTED)

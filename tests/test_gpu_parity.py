@@ -303,12 +303,20 @@ def _census_numpy(g, delta):
     per node, the time-sorted incidence list of its non-self-loop edges; the
     forward (backward) entries of an anchor are the later (earlier) entries of
     its list within delta; the ranked sublist keeps the entries whose other
-    endpoint has a longer list (ties: larger id)."""
+    endpoint has a longer list (ties: larger id); among an anchor's scanned
+    ranked entries (ties with its time left out), lookups are those leading to
+    another node than the anchor's, pair changes those whose node differs from
+    the previous lookup's.  The last count depends on the order of entries
+    tied in time, which in the lists is input order, the source's entry
+    first."""
     keep = g.src != g.dst
     x = np.concatenate([g.src[keep], g.dst[keep]]).astype(np.int64)
     y = np.concatenate([g.dst[keep], g.src[keep]]).astype(np.int64)
     t = np.concatenate([g.t[keep], g.t[keep]]).astype(np.int64)
-    order = np.lexsort((t, x))
+    # list order: time, then input position, then the source's entry first
+    idx = np.concatenate([np.nonzero(keep)[0], np.nonzero(keep)[0]])
+    side = np.concatenate([np.zeros(int(keep.sum()), np.int64), np.ones(int(keep.sum()), np.int64)])
+    order = np.lexsort((side, idx, t, x))
     x, y, t = x[order], y[order], t[order]
     deg = np.bincount(x, minlength=g.n)
     fwd = bwd = 0
@@ -317,20 +325,28 @@ def _census_numpy(g, delta):
         fwd += int((np.searchsorted(tv, tv + delta, side="right") - np.arange(tv.size) - 1).sum())
         bwd += int((np.arange(tv.size) - np.searchsorted(tv, tv - delta, side="left")).sum())
     hi = (deg[y] > deg[x]) | ((deg[y] == deg[x]) & (y > x))
-    rf = 0
+    rf = lk = pc = 0
     for v in np.unique(x[hi]):
-        tv = t[(x == v) & hi]
-        rf += int((np.searchsorted(tv, tv + delta, side="right") - np.arange(tv.size) - 1).sum())
-    return int(x.size), fwd, bwd, int(hi.sum()), rf
+        sel = (x == v) & hi
+        tv, yv = t[sel], y[sel]
+        ends = np.searchsorted(tv, tv + delta, side="right")
+        rf += int((ends - np.arange(tv.size) - 1).sum())
+        for a in range(tv.size):
+            ys = yv[a + 1:ends[a]][(tv[a + 1:ends[a]] != tv[a]) & (yv[a + 1:ends[a]] != yv[a])]
+            lk += int(ys.size)
+            if ys.size:
+                pc += 1 + int((ys[1:] != ys[:-1]).sum())
+    return {"anchors": int(x.size), "fwd_entries": fwd, "bwd_entries": bwd, "ranked_anchors": int(hi.sum()),
+            "ranked_entries": rf, "ranked_lookups": lk, "ranked_pairs": pc}
 
 
 @pytest.mark.gpu
 def test_sweep_census_matches_host_count(tm):
     """The work census behind the roofline figures counts exactly the list
-    entries each sweep scans, the ranked sublists included."""
+    entries each sweep scans and the triangle sweep's pair lookups."""
     for g, delta in ((ti.random_small_graph(30, 4000, 20000, 5, allow_self_loops=True), 300),
                      (ti.zipf_graph(2000, 30000, 1.8, 200000, 9), 3600)):
         G = load(tm, g)
         got = tm.sweep_census(G, delta)
         want = _census_numpy(g, delta)
-        assert tuple(got) == want, (got, want)
+        assert got == want, (got, want)
