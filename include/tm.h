@@ -206,6 +206,15 @@ tm_status tm_estimate_batch(const tm_graph *g, const tm_motif *M, int64_t delta,
 tm_status tm_batch_config(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t c, double p,
                           int32_t *tile, int32_t *blocks_per_cu, void *hip_stream);
 
+/*
+ * Releases the batched estimator's cached state of graph g: captured plans
+ * and the stored anchor values (32 B per incidence entry per (motif, delta,
+ * c)), after waiting for hip_stream.  Tuning results are kept.  The next
+ * tm_estimate_batch rebuilds what it needs.  The caller must not run a batch
+ * on g concurrently.
+ */
+tm_status tm_batch_release(const tm_graph *g, void *hip_stream);
+
 /* ------------------------------------------------------------------ serving */
 
 typedef struct tm_server tm_server;

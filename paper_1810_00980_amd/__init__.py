@@ -89,6 +89,7 @@ _SIGS = {
     "tm_estimate_multi": [P, i32, P, i64, i64, f64, u64, P, P, P],
     "tm_estimate_batch": [P, P, i64, i64, f64, i32, P, i32, P, P, P],
     "tm_batch_config": [P, P, i64, i64, f64, P, P, P],
+    "tm_batch_release": [P, P],
     "tm_server_create": [i32, i64, P],
     "tm_server_add_graph": [P, P, P],
     "tm_server_submit": [P, P, P],
@@ -327,6 +328,11 @@ def batch_config(g: Graph, edges, delta: int, c: int, p: float, stream=None):
     _check(_lib.tm_batch_config(g.handle, ctypes.byref(motif(edges)), int(delta), int(c), float(p),
                                 ctypes.byref(t), ctypes.byref(b), _stream(stream)), "tm_batch_config")
     return t.value, b.value
+
+
+def batch_release(g: Graph, stream=None):
+    """Drop the batched estimator's cached plans and stored anchor values of g."""
+    _check(_lib.tm_batch_release(g.handle, _stream(stream)), "tm_batch_release")
 
 
 class Server:

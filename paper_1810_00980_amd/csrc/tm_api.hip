@@ -657,6 +657,14 @@ extern "C" tm_status tm_estimate_batch(const tm_graph *g, const tm_motif *M, int
     return TM_OK;
 }
 
+extern "C" tm_status tm_batch_release(const tm_graph *g, void *hip_stream) {
+    if (!g) return TM_EINVAL;
+    // plans may have work in flight on the caller's stream
+    TM_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
+    tm_batch_release_plans(g);
+    return TM_OK;
+}
+
 extern "C" tm_status tm_batch_config(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t c, double p,
                                      int32_t *tile, int32_t *blocks_per_cu, void *hip_stream) {
     if (!g || !M || !tile || !blocks_per_cu) return TM_EINVAL;

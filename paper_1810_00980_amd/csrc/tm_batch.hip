@@ -565,6 +565,21 @@ void tm_batch_forget(const tm_graph *g) {
     }
 }
 
+// Drop the cached batch plans and stored anchor values of graph g, keeping
+// its tuning results (the caller reclaims device memory, or times a cold run).
+void tm_batch_release_plans(const tm_graph *g) {
+    BatchCache &C = bcache();
+    std::lock_guard<std::mutex> lk(C.mu);
+    for (auto it = C.plans.begin(); it != C.plans.end();) {
+        if (std::get<0>(it->first) == g) it = C.plans.erase(it);
+        else ++it;
+    }
+    for (auto it = C.vals.begin(); it != C.vals.end();) {
+        if (std::get<0>(it->first) == g) it = C.vals.erase(it);
+        else ++it;
+    }
+}
+
 // Autotuner: times the uncaptured batch on up to 8 seeds for each candidate
 // (tile, work-groups per CU) and keeps the fastest.
 tm_status tm_batch_tune(const tm_graph *g, int32_t code, int64_t delta, int64_t L, double p, int64_t *tile,

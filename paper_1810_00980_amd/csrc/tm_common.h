@@ -287,3 +287,4 @@ tm_status tm_batch_run(const tm_graph *g, int32_t code, int64_t delta, int64_t L
 tm_status tm_batch_tune(const tm_graph *g, int32_t code, int64_t delta, int64_t L, double p, int64_t *tile,
                         int64_t *bpc, hipStream_t st);
 void tm_batch_forget(const tm_graph *g);
+void tm_batch_release_plans(const tm_graph *g);

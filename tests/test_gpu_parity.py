@@ -292,6 +292,16 @@ def test_batched_estimates_match_per_seed(tm):
                     assert close(tm.estimate(G, M, delta, c, p, int(seeds[0])), est[0])
     t, b = tm.batch_config(G, ti.TRIANGLE, delta, c, p)
     assert t in (64, 256, 1024) and b in (8, 16)
+    # released plans and stored values are rebuilt with the same results
+    seeds = np.arange(10, dtype=np.uint64) + 7
+    before, _ = tm.estimate_batch(G, ti.TRIANGLE, delta, c, p, seeds)
+    tm.batch_release(G)
+    tm.profile_reset()
+    tm.profile_enable(True)
+    after, _ = tm.estimate_batch(G, ti.TRIANGLE, delta, c, p, seeds)
+    tm.profile_enable(False)
+    assert tm.profile_read("batch_anchor_values")[1] == 1
+    assert list(before) == list(after)
     # a four-edge motif takes the seed-by-seed path
     est, kept = tm.estimate_batch(G, ti.CYCLE4, delta, c, p, [1, 2])
     for k, sd in enumerate((1, 2)):
