@@ -114,11 +114,13 @@ struct tm_graph {
     DevBuf ph_slot;  // PairSlot[ph_cap]
     int64_t ph_cap = 0;
     // per unordered pair time buckets: bucket b of pair p covers times
-    // [t_first + b 2^shift, t_first + (b+1) 2^shift); pb_idx holds, per bucket,
-    // the index (relative to the pair's first entry) of its first entry, plus
-    // a sentinel equal to the pair's size
+    // [t_first + b 2^shift, t_first + (b+1) 2^shift), about
+    // TM_PAIR_BUCKET_DENSITY buckets per entry; pbk holds, per bucket, the
+    // index (relative to the pair's first entry) of its first entry and the
+    // a -> b edges before it, plus a sentinel bucket (size, a -> b total), so
+    // that a time in an empty bucket is answered without reading entries
     DevBuf pmeta;    // PairMeta[U]
-    DevBuf pb_idx;   // int32[sum (nb + 1)]
+    DevBuf pbk;      // PairBucket[sum (nb + 1)]
 
     // reusable per-graph workspace for queries
     DevBuf ws;
@@ -131,6 +133,13 @@ struct __attribute__((aligned(16))) PairSlot {
     int32_t pad;
 };
 
+constexpr int64_t TM_PAIR_BUCKET_DENSITY = 4;
+
+struct __attribute__((aligned(8))) PairBucket {
+    uint32_t idx;  // first entry at or after the bucket's start (relative)
+    uint32_t c0;   // a -> b edges before that entry
+};
+
 struct __attribute__((aligned(16))) PairEnt {
     int64_t t;     // time (LLONG_MAX in the sentinel)
     int64_t c0;    // a -> b edges among the pair's earlier entries
@@ -139,9 +148,9 @@ struct __attribute__((aligned(16))) PairEnt {
 struct __attribute__((aligned(32))) PairMeta {
     int64_t t0;    // time of the pair's first entry
     int64_t base;  // index of its first entry in up_ent
-    int64_t boff;  // its first bucket in pb_idx
+    int64_t boff;  // its first bucket in pbk
     int32_t shift; // bucket width 2^shift
-    int32_t nb;    // buckets (pb_idx[boff + nb] = number of entries)
+    int32_t nb;    // buckets (pbk[boff + nb] = sentinel: size, a -> b total)
 };
 
 // Plain-pointer view of a graph for kernels.
@@ -155,7 +164,7 @@ struct DevGraph {
     const int64_t *inc_off; const uint32_t *inc_nd; const int64_t *inc_t; const uint32_t *inc_twin;
     int64_t n_hi; const int64_t *hi_off; const uint32_t *hi_nd; const int64_t *hi_t;
     const PairSlot *ph_slot; int64_t ph_cap;
-    const PairMeta *pmeta; const int32_t *pb_idx;
+    const PairMeta *pmeta; const PairBucket *pbk;
     const PairEnt *up_ent;
 };
 

@@ -316,7 +316,7 @@ __global__ void k_pair_bucket_meta(const int64_t *up_beg, const PairEnt *ent, in
     if (p >= U) return;
     int64_t b = up_beg[p], e = up_beg[p + 1], k = e - b, base = b + p;
     int64_t t0 = ent[base].t, span = ent[base + k - 1].t - t0;
-    int64_t target = k / 2 > 1 ? k / 2 : 1;  // buckets wanted
+    int64_t target = k * TM_PAIR_BUCKET_DENSITY;  // buckets wanted
     int shift = 0;
     while (shift < 62 && (span >> shift) + 1 > target) ++shift;
     int64_t nb = (span >> shift) + 1;
@@ -329,7 +329,7 @@ __global__ void k_pair_bucket_meta(const int64_t *up_beg, const PairEnt *ent, in
 // entry r of pair p is the first entry of buckets (bucket(r-1), bucket(r)]
 __global__ void k_pair_bucket_fill(const uint64_t *keys, const int64_t *bscan, const int64_t *up_beg,
                                    const PairEnt *ent, int64_t m_nl, const int64_t *tfirst, const int32_t *meta,
-                                   const int64_t *boff, int32_t *bidx) {
+                                   const int64_t *boff, PairBucket *bk) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m_nl) return;
     int64_t p = bscan[j] + (upair_start(keys, j) ? 1 : 0) - 1;
@@ -338,8 +338,15 @@ __global__ void k_pair_bucket_fill(const uint64_t *keys, const int64_t *bscan, c
     int32_t nb = meta[2 * p + 1];
     int64_t bi = (ent[base + r].t - tfirst[p]) >> shift;
     int64_t bprev = r == 0 ? -1 : ((ent[base + r - 1].t - tfirst[p]) >> shift);
-    for (int64_t bb = bprev + 1; bb <= bi; ++bb) bidx[boff[p] + bb] = (int32_t)r;
-    if (r == k - 1) bidx[boff[p] + nb] = (int32_t)k;  // sentinel (bi == nb - 1 here)
+    PairBucket v;
+    v.idx = (uint32_t)r;
+    v.c0 = (uint32_t)ent[base + r].c0;
+    for (int64_t bb = bprev + 1; bb <= bi; ++bb) bk[boff[p] + bb] = v;
+    if (r == k - 1) {  // sentinel (bi == nb - 1 here)
+        v.idx = (uint32_t)k;
+        v.c0 = (uint32_t)ent[base + k].c0;
+        bk[boff[p] + nb] = v;
+    }
 }
 
 tm_status build_node_lists(tm_graph *g, const int64_t *nl_pos, bool by_src, DevBuf &off, DevBuf &nbr, DevBuf &tl,
@@ -566,11 +573,11 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
             TM_HIP(hipMemcpyAsync(&nbk_total, cnt.p, 8, hipMemcpyDeviceToHost, st));
             TM_HIP(hipStreamSynchronize(st));
         }
-        TM_TRY(g->pb_idx.alloc((size_t)(nbk_total > 0 ? nbk_total : 1) * 4));
+        TM_TRY(g->pbk.alloc((size_t)(nbk_total > 0 ? nbk_total : 1) * sizeof(PairBucket)));
         if (U > 0) {
             hipLaunchKernelGGL(k_pair_bucket_fill, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, uk.as<uint64_t>(),
                                bscan.as<int64_t>(), ubeg.as<int64_t>(), g->up_ent.as<PairEnt>(), m_nl,
-                               tfirst.as<int64_t>(), meta.as<int32_t>(), boff.as<int64_t>(), g->pb_idx.as<int32_t>());
+                               tfirst.as<int64_t>(), meta.as<int32_t>(), boff.as<int64_t>(), g->pbk.as<PairBucket>());
             TM_HIP(hipGetLastError());
             hipLaunchKernelGGL(k_pair_meta_pack, dim3(tm_blocks(U, TPB)), dim3(TPB), 0, st, ubeg.as<int64_t>(),
                                tfirst.as<int64_t>(), meta.as<int32_t>(), boff.as<int64_t>(), U,
@@ -642,7 +649,7 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
     }
     const DevBuf *all[] = {&g->es_src, &g->es_dst, &g->es_t, &g->pos_of, &g->out_off, &g->out_nbr, &g->out_t,
                            &g->in_off, &g->in_nbr, &g->in_t, &g->sp_off, &g->sp_nbr, &g->sp_beg, &g->pr_t,
-                           &g->inc_off, &g->inc_nd, &g->inc_t, &g->inc_twin, &g->hi_off, &g->hi_nd, &g->hi_t, &g->up_ent, &g->ph_slot, &g->pmeta, &g->pb_idx};
+                           &g->inc_off, &g->inc_nd, &g->inc_t, &g->inc_twin, &g->hi_off, &g->hi_nd, &g->hi_t, &g->up_ent, &g->ph_slot, &g->pmeta, &g->pbk};
     int64_t tot = 0;
     for (const DevBuf *b : all) tot += (int64_t)b->bytes;
     g->device_bytes = tot;
@@ -667,7 +674,7 @@ DevGraph dev_view(const tm_graph *g) {
     v.hi_t = g->hi_t.as<int64_t>();
     v.ph_slot = g->ph_slot.as<PairSlot>(); v.ph_cap = g->ph_cap;
     v.pmeta = g->pmeta.as<PairMeta>();
-    v.pb_idx = g->pb_idx.as<int32_t>();
+    v.pbk = g->pbk.as<PairBucket>();
     v.up_ent = g->up_ent.as<PairEnt>();
     return v;
 }

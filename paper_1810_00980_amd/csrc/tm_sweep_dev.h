@@ -66,18 +66,37 @@ __device__ inline int64_t owner_of(const int64_t *off, int64_t n, int64_t i) {
 // Unordered pair p = {a < b}: its entries are the edges of both directions,
 // time-sorted.  The counts below come as c[0] = a -> b and c[1] = b -> a.
 
-// lower bound of t in the pair described by m (entries en, n of them)
-__device__ inline int64_t pair_lower(const DevGraph &G, const PairMeta &m, const PairEnt *en, int64_t n, int64_t t) {
-    if (t <= m.t0) return 0;
+// Lower bound of t in the pair described by m (entries en, n of them): the
+// returned index, the a -> b count before it (*c0), and the end of t's
+// bucket (*be), past which no entry has time t.  A time in an empty bucket
+// is answered from the bucket array alone.
+__device__ inline int64_t pair_lower(const DevGraph &G, const PairMeta &m, const PairEnt *en, int64_t n, int64_t t,
+                                     int64_t *c0, int64_t *be) {
+    const PairBucket *bk = G.pbk + m.boff;
+    if (t <= m.t0) {
+        *c0 = 0;
+        *be = n;
+        return 0;
+    }
     int64_t b = (t - m.t0) >> m.shift;
-    if (b >= m.nb) return n;
-    const int32_t *bi = G.pb_idx + m.boff;
-    int64_t lo = bi[b], hi = bi[b + 1];
+    if (b >= m.nb) {
+        *c0 = bk[m.nb].c0;
+        *be = n;
+        return n;
+    }
+    const PairBucket b0 = bk[b], b1 = bk[b + 1];
+    *be = b1.idx;
+    if (b0.idx == b1.idx) {
+        *c0 = b0.c0;
+        return b0.idx;
+    }
+    int64_t lo = b0.idx, hi = b1.idx;
     while (lo < hi) {
         int64_t mid = (lo + hi) >> 1;
         if (en[mid].t < t) lo = mid + 1;
         else hi = mid;
     }
+    *c0 = lo == (int64_t)b1.idx ? (int64_t)b1.c0 : en[lo].c0;
     return lo;
 }
 
@@ -89,31 +108,37 @@ struct PairView {
     __device__ void load(const DevGraph &G, int32_t p) {
         m = G.pmeta[p];
         en = G.up_ent + m.base;
-        n = G.pb_idx[m.boff + m.nb];
+        n = G.pbk[m.boff + m.nb].idx;
     }
     // entries with time < t
     __device__ void lt(const DevGraph &G, int64_t t, int64_t c[2]) const {
-        int64_t lo = pair_lower(G, m, en, n, t);
-        int64_t k = en[lo].c0;
+        int64_t k, be;
+        int64_t lo = pair_lower(G, m, en, n, t, &k, &be);
         c[0] = k;
         c[1] = lo - k;
     }
     // entries with time <= t (all of them for t = LLONG_MAX)
     __device__ void le(const DevGraph &G, int64_t t, int64_t c[2]) const {
-        int64_t e = (t == LLONG_MAX) ? n : pair_lower(G, m, en, n, t + 1);
-        int64_t k = en[e].c0;
+        int64_t k, be, e;
+        if (t == LLONG_MAX) {
+            e = n;
+            k = G.pbk[m.boff + m.nb].c0;
+        } else {
+            e = pair_lower(G, m, en, n, t + 1, &k, &be);
+        }
         c[0] = k;
         c[1] = e - k;
     }
-    // both: one bucket lookup, then the entries equal to t are stepped over
+    // both: one bucket lookup, then the entries equal to t (all in t's
+    // bucket, usually none) are stepped over
     __device__ void at(const DevGraph &G, int64_t t, int64_t c_lt[2], int64_t c_le[2]) const {
-        int64_t lo = pair_lower(G, m, en, n, t);
-        int64_t e = lo;
-        while (e < n && en[e].t == t) ++e;
-        int64_t k = en[lo].c0;
+        int64_t k, be;
+        int64_t lo = pair_lower(G, m, en, n, t, &k, &be);
         c_lt[0] = k;
         c_lt[1] = lo - k;
-        k = en[e].c0;
+        int64_t e = lo;
+        while (e < be && en[e].t == t) ++e;
+        if (e != lo) k = en[e].c0;
         c_le[0] = k;
         c_le[1] = e - k;
     }
