@@ -316,7 +316,8 @@ __global__ void k_pair_bucket_meta(const int64_t *up_beg, const PairEnt *ent, in
     if (p >= U) return;
     int64_t b = up_beg[p], e = up_beg[p + 1], k = e - b, base = b + p;
     int64_t t0 = ent[base].t, span = ent[base + k - 1].t - t0;
-    int64_t target = k * TM_PAIR_BUCKET_DENSITY;  // buckets wanted
+    int64_t target = k * TM_PAIR_BUCKET_DENSITY;  // buckets wanted (nb stays below 2^31)
+    if (target > ((int64_t)1 << 30)) target = (int64_t)1 << 30;
     int shift = 0;
     while (shift < 62 && (span >> shift) + 1 > target) ++shift;
     int64_t nb = (span >> shift) + 1;

@@ -129,6 +129,36 @@ __global__ void k_weights_fx(int64_t delta, int64_t L, uint64_t *wfx) {
     wfx[d] = q;
 }
 
+// Two side streams (default priority) and fork/join events per host thread
+// and device.  They are kept until the process ends: destroying them from a
+// thread-exit or static destructor could run after the runtime's teardown.
+struct SideStreams {
+    int dev = -1;
+    hipStream_t s[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+};
+
+// nullptr when they cannot be created (the caller then stays on its stream)
+SideStreams *side_streams(int dev) {
+    thread_local SideStreams per_dev[8];
+    if (dev < 0 || dev >= 8) return nullptr;
+    SideStreams &S = per_dev[dev];
+    if (S.dev != dev) {
+        bool ok = true;
+        for (int k = 0; k < 2; ++k) {
+            ok = ok && hipStreamCreateWithFlags(&S.s[k], hipStreamNonBlocking) == hipSuccess;
+            ok = ok && hipEventCreateWithFlags(&S.join[k], hipEventDisableTiming) == hipSuccess;
+        }
+        ok = ok && hipEventCreateWithFlags(&S.fork, hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        S.dev = dev;
+    }
+    return &S;
+}
+
 template <int MODE>
 tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, hipStream_t st) {
     DevGraph G = dev_view(g);
@@ -143,31 +173,41 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, hipStr
     static const char *names[3][3] = {{"sweep3_fwd_count", "sweep3_bwd_count", "sweep3_tri_count"},
                                       {"sweep3_fwd_weight", "sweep3_bwd_weight", "sweep3_tri_weight"},
                                       {"sweep3_fwd_hist", "sweep3_bwd_hist", "sweep3_tri_hist"}};
-    // forward sweeps: 2-node and stars in one kernel, triangles in another
-    if (fwd && (a.want_fwd & 7u)) {
-        TM_HIP(hipMemsetAsync(a.counter, 0, 8, st));
-        void *tok = tm_prof_begin(names[MODE][0], st);
-        hipLaunchKernelGGL((k_sweep3<MODE, true, 7u>), dim3((unsigned)nb), dim3(SW_TPB), 0, st, G, a);
-        TM_HIP(hipGetLastError());
-        tm_prof_end(tok, st);
+    // The kernels are independent (own work counters, disjoint motif codes)
+    // and bound by different things (the 2-node/star sweeps by VALU issue,
+    // the triangle sweep by lookup latency), so they run on forked streams
+    // and share the CUs; the caller's stream waits for all of them.
+    TM_HIP(hipMemsetAsync(a.counter, 0, 3 * sizeof(int64_t), st));
+    struct Launch {
+        int kind;  // 0 fwd 2-node/stars, 1 bwd stars, 2 fwd triangles
+    } todo[3];
+    int nl = 0;
+    if (fwd && (a.want_fwd & 8u)) todo[nl++] = {2};
+    if (fwd && (a.want_fwd & 7u)) todo[nl++] = {0};
+    if (bwd) todo[nl++] = {1};
+    if (nl == 0) return TM_OK;
+    SideStreams *side = nl > 1 ? side_streams(dev) : nullptr;
+    if (side) {
+        TM_HIP(hipEventRecord(side->fork, st));
+        for (int k = 1; k < nl; ++k) TM_HIP(hipStreamWaitEvent(side->s[k - 1], side->fork, 0));
     }
-    if (fwd && (a.want_fwd & 8u)) {
-        TM_HIP(hipMemsetAsync(a.counter + 2, 0, 8, st));
+    for (int k = 0; k < nl; ++k) {
+        hipStream_t sk = (k == 0 || !side) ? st : side->s[k - 1];
         SweepArgs b = a;
-        b.counter = a.counter + 2;
-        void *tok = tm_prof_begin(names[MODE][2], st);
-        hipLaunchKernelGGL((k_sweep3<MODE, true, 8u>), dim3((unsigned)nb), dim3(SW_TPB), 0, st, G, b);
+        b.counter = a.counter + todo[k].kind;
+        void *tok = tm_prof_begin(names[MODE][todo[k].kind], sk);
+        if (todo[k].kind == 0)
+            hipLaunchKernelGGL((k_sweep3<MODE, true, 7u>), dim3((unsigned)nb), dim3(SW_TPB), 0, sk, G, b);
+        else if (todo[k].kind == 2)
+            hipLaunchKernelGGL((k_sweep3<MODE, true, 8u>), dim3((unsigned)nb), dim3(SW_TPB), 0, sk, G, b);
+        else
+            hipLaunchKernelGGL((k_sweep3<MODE, false, 0u>), dim3((unsigned)nb), dim3(SW_TPB), 0, sk, G, b);
         TM_HIP(hipGetLastError());
-        tm_prof_end(tok, st);
+        tm_prof_end(tok, sk);
     }
-    if (bwd) {
-        TM_HIP(hipMemsetAsync(a.counter + 1, 0, 8, st));
-        SweepArgs b = a;
-        b.counter = a.counter + 1;
-        void *tok = tm_prof_begin(names[MODE][1], st);
-        hipLaunchKernelGGL((k_sweep3<MODE, false, 0u>), dim3((unsigned)nb), dim3(SW_TPB), 0, st, G, b);
-        TM_HIP(hipGetLastError());
-        tm_prof_end(tok, st);
+    for (int k = 1; side && k < nl; ++k) {
+        TM_HIP(hipEventRecord(side->join[k - 1], side->s[k - 1]));
+        TM_HIP(hipStreamWaitEvent(st, side->join[k - 1], 0));
     }
     return TM_OK;
 }
