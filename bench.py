@@ -334,36 +334,51 @@ def traffic_record(kernel):
     return rec.get("traffic_bytes_per_launch")
 
 
-# Algorithmic bytes per unit of the exact sweeps: 16 B per anchor edge (two
+# Algorithmic bytes per unit of the sweeps: 16 B per anchor edge (two
 # endpoints and a time), 12 B per scanned list entry (time and endpoint
-# word); each closing-pair lookup of the triangle sweep reads two bucket
-# bounds and the entry found, twice (tj and tj - delta): 48 B; a change of
-# closing pair also reads the hash slot (16 B), the pair's metadata (32 B)
-# and two more searches (48 B): 96 B.
-def exact_bytes(c):
-    return {
-        "sweep3_fwd_count": 16 * c["anchors"] + 12 * c["fwd_entries"],
-        "sweep3_bwd_count": 16 * c["anchors"] + 12 * c["bwd_entries"],
-        "sweep3_tri_count": 16 * c["ranked_anchors"] + 12 * c["ranked_entries"] + 48 * c["ranked_lookups"]
-        + 96 * c["ranked_pairs"],
+# word), plus 8 B per scanned entry for the weighted sweeps' weight.  The
+# exact triangle sweep's closing-pair lookup reads two bucket records and
+# the entry found, at tj and at tj - delta (48 B); a change of closing pair
+# also reads the hash slot (16 B), the pair's metadata (32 B) and two more
+# searches (48 B): 96 B.  The weighted triangle sweep looks up once per
+# entry (24 B) and reads hash slot, metadata and one search on a pair change
+# (72 B).
+def sweep_bytes(exact, ests):
+    out = {
+        "sweep3_fwd_count": 16 * exact["anchors"] + 12 * exact["fwd_entries"],
+        "sweep3_bwd_count": 16 * exact["anchors"] + 12 * exact["bwd_entries"],
+        "sweep3_tri_count": 16 * exact["tri_anchors"] + 12 * exact["tri_entries"] + 48 * exact["tri_lookups"]
+        + 96 * exact["tri_pairs"],
+        "sweep3_fwd_weight": 0, "sweep3_bwd_weight": 0, "sweep3_tri_weight": 0,
     }
+    for e in ests:
+        out["sweep3_fwd_weight"] += 16 * e["anchors"] + 20 * e["fwd_entries"]
+        out["sweep3_bwd_weight"] += 16 * e["anchors"] + 20 * e["bwd_entries"]
+        out["sweep3_tri_weight"] += (16 * e["tri_anchors"] + 20 * e["tri_entries"] + 24 * e["tri_lookups"]
+                                     + 72 * e["tri_pairs"])
+    return out
 
 
-def exact_roofline(census, kern, steps):
-    """Roofline entry of the exact sweep kernel with the largest time, with
-    the achieved algorithmic GB/s of each exact sweep kernel beside it."""
-    eb = exact_bytes(census)
-    timed = {k: v for k, v in kern.items() if k in eb and v[1] > 0}
+def sweep_roofline(exact, ests, kern, steps):
+    """Roofline entry of the sweep kernel with the largest time per step,
+    with the achieved algorithmic GB/s of every sweep kernel beside it.  The
+    kernels of one pass run concurrently on forked streams, so each one's
+    duration is measured while it shares the CUs with the others."""
+    bps = sweep_bytes(exact, ests)  # algorithmic bytes per step
+    timed = {k: v for k, v in kern.items() if k in bps and v[1] > 0}
     if not timed:
         return None
-    per = {k: {"avg_launch_ms": v[0] / v[1], "algorithmic_bytes_per_launch": eb[k],
-               "achieved_GBs": eb[k] / (v[0] / v[1] / 1e3) / 1e9} for k, v in timed.items()}
+    per = {}
+    for k, (ms, n) in timed.items():
+        per[k] = {"launches_per_step": n / steps, "avg_launch_ms": ms / n,
+                  "algorithmic_bytes_per_launch": bps[k] * steps / n,
+                  "achieved_GBs": bps[k] * steps / (ms / 1e3) / 1e9}
     dom = max(timed, key=lambda k: timed[k][0])
     ach = per[dom]["achieved_GBs"]
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "traffic": traffic_record(dom), "kernel": dom, "avg_launch_ms": per[dom]["avg_launch_ms"],
-            "launches": timed[dom][1], "algorithmic_bytes_per_launch": eb[dom], "census": census,
-            "exact_kernels": per,
+            "launches": timed[dom][1], "algorithmic_bytes_per_launch": per[dom]["algorithmic_bytes_per_launch"],
+            "census": {"exact": exact, "estimates": ests}, "sweep_kernels": per,
             "sweep_kernels_ms_per_step": {k: v[0] / steps for k, v in kern.items()}}
 
 
@@ -446,8 +461,9 @@ def main():
     q = len(motifs) * (1 + len(W["est"]))
     G = tm.load_graph(src, dst, t, g.n)
     census = tm.sweep_census(G, delta)
+    ests = [tm.sweep_census_est(G, delta, c, p, 0) for c, p in W["est"]]
     G.free()
-    roofline = exact_roofline(census, kern, args.steps)
+    roofline = sweep_roofline(census, ests, kern, args.steps)
     out = {
         "metric": "temporal edges/s per motif query (exact & p=0.1 estimate) vs CPU",
         "value": g.m * q / dt, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

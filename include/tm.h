@@ -281,31 +281,38 @@ tm_status tm_profile_reset(void);
 tm_status tm_profile_read(const char *kernel, double *total_ms, int64_t *launches);
 
 /*
- * Work census of the exact three-edge sweeps over the whole graph at span
- * delta, used to express kernel time as algorithmic bytes per second:
- *   anchors          incidence entries (two per non-self-loop edge)
- *   fwd_entries      list entries the forward sweeps scan (later entries
- *                    of the anchor's list within delta)
- *   bwd_entries      list entries the backward sweep scans (earlier ones)
- *   ranked_anchors   entries of the ranked sublists (those whose other
- *                    endpoint ranks above the list's owner, rank = (list
- *                    length, node id)), the exact triangle sweep's anchors
- *   ranked_entries   ranked-sublist entries that sweep scans
- *   ranked_lookups   scanned entries that lead to another node than the
- *                    anchor's (one closing-pair lookup each)
- *   ranked_pairs     of those, the ones whose closing pair differs from the
- *                    previous lookup's (the pair's id and metadata are read)
- * Ties with the anchor's time are left out of the last two, as the sweep
- * leaves them out.  Within a list, entries tied in time follow the input
- * order of their edges (an edge's source entry before its destination
- * entry), which the last count depends on.
+ * Work census of the three-edge sweeps, used to express kernel time as
+ * algorithmic bytes per second.  tm_sweep_census covers the exact sweeps at
+ * span delta over the whole graph:
+ *   anchors       incidence entries (two per non-self-loop edge)
+ *   fwd_entries   list entries the forward sweeps scan (later entries of
+ *                 the anchor's list within delta)
+ *   bwd_entries   list entries the backward sweep scans (earlier ones)
+ *   tri_anchors   entries of the ranked sublists (those whose other endpoint
+ *                 ranks above the list's owner, rank = (list length, node
+ *                 id)): the exact triangle sweep's anchors
+ *   tri_entries   ranked-sublist entries that sweep scans
+ *   tri_lookups   scanned entries that lead to another node than the
+ *                 anchor's (one closing-pair lookup each)
+ *   tri_pairs     of those, the ones whose node differs from the previous
+ *                 lookup's (the pair's id and metadata are read)
+ * tm_sweep_census_est covers the estimate's weighted sweeps for (delta, c,
+ * p, seed): the same fields restricted to anchors in kept windows and to
+ * entries inside the anchor's window; there the triangle sweep runs over
+ * the full lists, so tri_anchors = anchors and tri_entries = fwd_entries.
+ * Ties with the anchor's time are left out of tri_lookups and tri_pairs, as
+ * the sweeps leave them out.  Within a list, entries tied in time follow the
+ * input order of their edges (an edge's source entry before its destination
+ * entry), which tri_pairs depends on.
  */
 typedef struct {
     int64_t anchors, fwd_entries, bwd_entries;
-    int64_t ranked_anchors, ranked_entries, ranked_lookups, ranked_pairs;
+    int64_t tri_anchors, tri_entries, tri_lookups, tri_pairs;
 } tm_census;
 
 tm_status tm_sweep_census(const tm_graph *g, int64_t delta, tm_census *out, void *hip_stream);
+tm_status tm_sweep_census_est(const tm_graph *g, int64_t delta, int64_t c, double p, uint64_t seed,
+                              tm_census *out, void *hip_stream);
 
 /* Human-readable name of a status code (static storage). */
 const char *tm_strerror(tm_status s);

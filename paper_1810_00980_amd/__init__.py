@@ -100,6 +100,7 @@ _SIGS = {
     "tm_profile_reset": [],
     "tm_profile_read": [ctypes.c_char_p, P, P],
     "tm_sweep_census": [P, i64, P, P],
+    "tm_sweep_census_est": [P, i64, i64, f64, u64, P, P],
     "tm_strerror": [i32],
     "tm_version": [],
 }
@@ -311,8 +312,7 @@ def profile_read(kernel: str):
 
 class Census(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in
-                ("anchors", "fwd_entries", "bwd_entries", "ranked_anchors", "ranked_entries",
-                 "ranked_lookups", "ranked_pairs")]
+                ("anchors", "fwd_entries", "bwd_entries", "tri_anchors", "tri_entries", "tri_lookups", "tri_pairs")]
 
 
 def sweep_census(g: Graph, delta: int, stream=None) -> dict:
@@ -320,6 +320,14 @@ def sweep_census(g: Graph, delta: int, stream=None) -> dict:
     c = Census()
     _check(_lib.tm_sweep_census(g.handle, int(delta), ctypes.byref(c), _stream(stream)), "tm_sweep_census")
     return {name: getattr(c, name) for name, _ in Census._fields_}
+
+
+def sweep_census_est(g: Graph, delta: int, c: int, p: float, seed: int, stream=None) -> dict:
+    """Work census of an estimate's weighted sweeps (tm_census fields)."""
+    r = Census()
+    _check(_lib.tm_sweep_census_est(g.handle, int(delta), int(c), float(p), int(seed), ctypes.byref(r),
+                                    _stream(stream)), "tm_sweep_census_est")
+    return {name: getattr(r, name) for name, _ in Census._fields_}
 
 
 def batch_config(g: Graph, edges, delta: int, c: int, p: float, stream=None):

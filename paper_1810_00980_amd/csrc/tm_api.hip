@@ -78,7 +78,8 @@ void tm_prof_collect() {
     P.pending.clear();
 }
 
-tm_status tm_sweep_census_impl(const tm_graph *g, int64_t delta, tm_census *c, hipStream_t st);
+tm_status tm_sweep_census_impl(const tm_graph *g, int64_t delta, int64_t s, int64_t L, double p, uint64_t seed,
+                               tm_census *c, hipStream_t st);
 
 namespace {
 
@@ -783,9 +784,21 @@ extern "C" tm_status tm_sweep_census(const tm_graph *g, int64_t delta, tm_census
     hipStream_t st = (hipStream_t)hip_stream;
     tm_census c;
     c.anchors = 2 * g->m_nl;
-    c.ranked_anchors = g->n_hi;
-    tm_status s = finish(tm_sweep_census_impl(g, delta, &c, st), st);
+    c.tri_anchors = g->n_hi;
+    tm_status s = finish(tm_sweep_census_impl(g, delta, 0, 0, 0.0, 0, &c, st), st);
     if (s == TM_OK) *out = c;
+    return s;
+}
+
+extern "C" tm_status tm_sweep_census_est(const tm_graph *g, int64_t delta, int64_t c, double p, uint64_t seed,
+                                         tm_census *out, void *hip_stream) {
+    if (!g || !out) return TM_EINVAL;
+    int64_t L;
+    TM_TRY(check_est_args(g, delta, c, p, &L));
+    hipStream_t st = (hipStream_t)hip_stream;
+    tm_census r;
+    tm_status s = finish(tm_sweep_census_impl(g, delta, host_shift(seed, L), L, p, seed, &r, st), st);
+    if (s == TM_OK) *out = r;
     return s;
 }
 

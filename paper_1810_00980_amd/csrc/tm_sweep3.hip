@@ -293,33 +293,108 @@ __global__ void k_census_ranked(DevGraph G, int64_t delta, unsigned long long *o
     }
 }
 
+// the estimate's weighted sweeps for window length L, shift s, seed and p:
+// kept anchors, entries scanned forward and backward inside the anchor's
+// window, and the forward triangle sweep's lookups and pair changes
+__global__ void k_census_est(DevGraph G, int64_t delta, int64_t s, int64_t L, double p, uint64_t seed,
+                             unsigned long long *out) {
+    __shared__ unsigned long long sh[5][SW_TPB];
+    unsigned long long an = 0, f = 0, b = 0, lk = 0, pc = 0;
+    int64_t nE = 2 * G.m_nl;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nE; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t t = G.inc_t[i];
+        int64_t jw = (t - s) / L + 1;
+        if (!keep_window(seed, (uint64_t)jw, p)) continue;
+        ++an;
+        int64_t wlo = s + (jw - 1) * L, whi = s + jw * L - 1;
+        int64_t x = owner_of(G.inc_off, G.n, i);
+        int64_t lb = G.inc_off[x], le = G.inc_off[x + 1];
+        uint32_t y1 = G.inc_nd[i] & 0x7FFFFFFFu;
+        int64_t hi = (t > LLONG_MAX - delta) ? LLONG_MAX : t + delta;
+        hi = hi < whi ? hi : whi;
+        int64_t lo = (t < LLONG_MIN + delta) ? LLONG_MIN : t - delta;
+        lo = lo > wlo ? lo : wlo;
+        uint32_t prev = ~0u;
+        int64_t j = i + 1;
+        for (; j < le && G.inc_t[j] <= hi; ++j) {
+            if (G.inc_t[j] == t) continue;
+            uint32_t yj = G.inc_nd[j] & 0x7FFFFFFFu;
+            if (yj == y1) continue;
+            ++lk;
+            if (yj != prev) ++pc;
+            prev = yj;
+        }
+        f += (unsigned long long)(j - i - 1);
+        int64_t c0 = lb, c1 = i;  // first entry with time >= lo
+        while (c0 < c1) {
+            int64_t mid = (c0 + c1) >> 1;
+            if (G.inc_t[mid] < lo) c0 = mid + 1;
+            else c1 = mid;
+        }
+        b += (unsigned long long)(i - c0);
+    }
+    sh[0][threadIdx.x] = an;
+    sh[1][threadIdx.x] = f;
+    sh[2][threadIdx.x] = b;
+    sh[3][threadIdx.x] = lk;
+    sh[4][threadIdx.x] = pc;
+    __syncthreads();
+    for (int w = SW_TPB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 5; ++q) atomicAdd(&out[q], sh[q][0]);
+    }
+}
+
 }  // namespace
 
-tm_status tm_sweep_census_impl(const tm_graph *g, int64_t delta, tm_census *c, hipStream_t st) {
+// L = 0: the exact sweeps (c->anchors and c->tri_anchors set by the
+// caller); L > 0: the estimate's weighted sweeps for (s, L, p, seed)
+tm_status tm_sweep_census_impl(const tm_graph *g, int64_t delta, int64_t s, int64_t L, double p, uint64_t seed,
+                               tm_census *c, hipStream_t st) {
     DevBuf o;
     TM_TRY(o.alloc(64));
     TM_HIP(hipMemsetAsync(o.p, 0, 40, st));
+    unsigned nb = g->m_nl > 0 ? tm_blocks(2 * g->m_nl, SW_TPB) : 1;
+    if (nb > 8192) nb = 8192;
+    int64_t h[5];
+    if (L > 0) {
+        if (g->m_nl > 0) {
+            hipLaunchKernelGGL(k_census_est, dim3(nb), dim3(SW_TPB), 0, st, dev_view(g), delta, s, L, p, seed,
+                               o.as<unsigned long long>());
+            TM_HIP(hipGetLastError());
+        }
+        TM_HIP(hipMemcpyAsync(h, o.p, 40, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+        c->anchors = c->tri_anchors = h[0];
+        c->fwd_entries = c->tri_entries = h[1];
+        c->bwd_entries = h[2];
+        c->tri_lookups = h[3];
+        c->tri_pairs = h[4];
+        return TM_OK;
+    }
     if (g->m_nl > 0) {
-        unsigned nb = tm_blocks(2 * g->m_nl, SW_TPB);
-        if (nb > 8192) nb = 8192;
         hipLaunchKernelGGL(k_census, dim3(nb), dim3(SW_TPB), 0, st, dev_view(g), delta, o.as<unsigned long long>());
         TM_HIP(hipGetLastError());
     }
     if (g->n_hi > 0) {
-        unsigned nb = tm_blocks(g->n_hi, SW_TPB);
-        if (nb > 8192) nb = 8192;
-        hipLaunchKernelGGL(k_census_ranked, dim3(nb), dim3(SW_TPB), 0, st, dev_view(g), delta,
+        unsigned nr = tm_blocks(g->n_hi, SW_TPB);
+        if (nr > 8192) nr = 8192;
+        hipLaunchKernelGGL(k_census_ranked, dim3(nr), dim3(SW_TPB), 0, st, dev_view(g), delta,
                            o.as<unsigned long long>());
         TM_HIP(hipGetLastError());
     }
-    int64_t h[5];
     TM_HIP(hipMemcpyAsync(h, o.p, 40, hipMemcpyDeviceToHost, st));
     TM_HIP(hipStreamSynchronize(st));
     c->fwd_entries = h[0];
     c->bwd_entries = h[1];
-    c->ranked_entries = h[2];
-    c->ranked_lookups = h[3];
-    c->ranked_pairs = h[4];
+    c->tri_entries = h[2];
+    c->tri_lookups = h[3];
+    c->tri_pairs = h[4];
     return TM_OK;
 }
 

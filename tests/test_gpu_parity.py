@@ -308,26 +308,37 @@ def test_batched_estimates_match_per_seed(tm):
         assert close(est[k], oracle.estimate(g.src, g.dst, g.t, ti.CYCLE4, delta, c, p, sd)["Z"])
 
 
-def _census_numpy(g, delta):
-    """Entries each sweep scans, counted on the host from the definition:
-    per node, the time-sorted incidence list of its non-self-loop edges; the
-    forward (backward) entries of an anchor are the later (earlier) entries of
-    its list within delta; the ranked sublist keeps the entries whose other
-    endpoint has a longer list (ties: larger id); among an anchor's scanned
-    ranked entries (ties with its time left out), lookups are those leading to
-    another node than the anchor's, pair changes those whose node differs from
-    the previous lookup's.  The last count depends on the order of entries
-    tied in time, which in the lists is input order, the source's entry
-    first."""
+def _lists(g):
+    """Per-node combined lists in the device's order: time, then input
+    position, then the source's entry first (self-loops left out)."""
     keep = g.src != g.dst
     x = np.concatenate([g.src[keep], g.dst[keep]]).astype(np.int64)
     y = np.concatenate([g.dst[keep], g.src[keep]]).astype(np.int64)
-    t = np.concatenate([g.t[keep], g.t[keep]]).astype(np.int64)
-    # list order: time, then input position, then the source's entry first
+    t = np.concatenate([g.t[keep], g.t[keep]]).astype(np.int64) - int(g.t.min())
     idx = np.concatenate([np.nonzero(keep)[0], np.nonzero(keep)[0]])
     side = np.concatenate([np.zeros(int(keep.sum()), np.int64), np.ones(int(keep.sum()), np.int64)])
     order = np.lexsort((side, idx, t, x))
-    x, y, t = x[order], y[order], t[order]
+    return x[order], y[order], t[order]
+
+
+def _scan_counts(tv, yv, a, end):
+    """Lookups and pair changes of anchor a over entries (a, end): entries
+    tied with the anchor's time and entries leading to its own node are left
+    out; a pair change is a lookup whose node differs from the previous one."""
+    ys = yv[a + 1:end][(tv[a + 1:end] != tv[a]) & (yv[a + 1:end] != yv[a])]
+    if not ys.size:
+        return 0, 0
+    return int(ys.size), 1 + int((ys[1:] != ys[:-1]).sum())
+
+
+def _census_numpy(g, delta):
+    """Entries each exact sweep scans, counted on the host from the
+    definition: per node, the time-sorted incidence list of its
+    non-self-loop edges; the forward (backward) entries of an anchor are the
+    later (earlier) entries of its list within delta; the ranked sublist
+    keeps the entries whose other endpoint has a longer list (ties: larger
+    id); lookups and pair changes as in _scan_counts, over ranked entries."""
+    x, y, t = _lists(g)
     deg = np.bincount(x, minlength=g.n)
     fwd = bwd = 0
     for v in np.unique(x):
@@ -342,21 +353,51 @@ def _census_numpy(g, delta):
         ends = np.searchsorted(tv, tv + delta, side="right")
         rf += int((ends - np.arange(tv.size) - 1).sum())
         for a in range(tv.size):
-            ys = yv[a + 1:ends[a]][(tv[a + 1:ends[a]] != tv[a]) & (yv[a + 1:ends[a]] != yv[a])]
-            lk += int(ys.size)
-            if ys.size:
-                pc += 1 + int((ys[1:] != ys[:-1]).sum())
-    return {"anchors": int(x.size), "fwd_entries": fwd, "bwd_entries": bwd, "ranked_anchors": int(hi.sum()),
-            "ranked_entries": rf, "ranked_lookups": lk, "ranked_pairs": pc}
+            l, c = _scan_counts(tv, yv, a, ends[a])
+            lk += l
+            pc += c
+    return {"anchors": int(x.size), "fwd_entries": fwd, "bwd_entries": bwd, "tri_anchors": int(hi.sum()),
+            "tri_entries": rf, "tri_lookups": lk, "tri_pairs": pc}
+
+
+def _census_est_numpy(g, delta, c, p, seed):
+    """The estimate's census: anchors in kept windows (shift and kept windows
+    from the oracle), entries inside the anchor's window within delta."""
+    o = oracle.estimate(g.src, g.dst, g.t, ti.TRIANGLE, delta, c, p, seed)
+    s, L, kept = int(o["s"]), int(o["L"]), set(int(j) for j in o["kept"])
+    x, y, t = _lists(g)
+    an = fwd = bwd = lk = pc = 0
+    for v in np.unique(x):
+        tv, yv = t[x == v], y[x == v]
+        for a in range(tv.size):
+            jw = (int(tv[a]) - s) // L + 1
+            if jw not in kept:
+                continue
+            wlo, whi = s + (jw - 1) * L, s + jw * L - 1
+            an += 1
+            end = int(np.searchsorted(tv, min(int(tv[a]) + delta, whi), side="right"))
+            beg = int(np.searchsorted(tv, max(int(tv[a]) - delta, wlo), side="left"))
+            fwd += end - a - 1
+            bwd += a - beg
+            l, cc = _scan_counts(tv, yv, a, end)
+            lk += l
+            pc += cc
+    return {"anchors": an, "fwd_entries": fwd, "bwd_entries": bwd, "tri_anchors": an, "tri_entries": fwd,
+            "tri_lookups": lk, "tri_pairs": pc}
 
 
 @pytest.mark.gpu
 def test_sweep_census_matches_host_count(tm):
     """The work census behind the roofline figures counts exactly the list
-    entries each sweep scans and the triangle sweep's pair lookups."""
+    entries each sweep scans and the triangle sweeps' pair lookups, for the
+    exact pass and for an estimate's kept windows."""
     for g, delta in ((ti.random_small_graph(30, 4000, 20000, 5, allow_self_loops=True), 300),
                      (ti.zipf_graph(2000, 30000, 1.8, 200000, 9), 3600)):
         G = load(tm, g)
         got = tm.sweep_census(G, delta)
         want = _census_numpy(g, delta)
         assert got == want, (got, want)
+        for c, p, seed in ((3, 0.5, 7), (10, 0.6, 2)):
+            got = tm.sweep_census_est(G, delta, c, p, seed)
+            want = _census_est_numpy(g, delta, c, p, seed)
+            assert got == want, (c, p, seed, got, want)
