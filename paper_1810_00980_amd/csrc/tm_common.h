@@ -110,7 +110,8 @@ struct tm_graph {
     int64_t U = 0;   // distinct unordered pairs
     DevBuf up_ent;   // PairEnt[m_nl + U]
     // unordered pair hash (open addressing, linear probing): slot = key
-    // (min << 32 | max, ~0 when empty) and the unordered pair id
+    // (min << 32 | max, ~0 when empty), the unordered pair id and a copy of
+    // the pair's metadata
     DevBuf ph_slot;  // PairSlot[ph_cap]
     int64_t ph_cap = 0;
     // per unordered pair time buckets: bucket b of pair p covers times
@@ -127,10 +128,15 @@ struct tm_graph {
     int64_t device_bytes = 0;
 };
 
-struct __attribute__((aligned(16))) PairSlot {
+// One cache line per slot: the key and, inline, what a lookup in the pair
+// needs (a copy of its PairMeta and its size), so that finding a pair and
+// reading its metadata is one access.
+struct __attribute__((aligned(64))) PairSlot {
     uint64_t key;
-    int32_t id;    // unordered pair id, -1 when empty
-    int32_t pad;
+    int64_t t0, base, boff;  // as in PairMeta
+    int32_t id;              // unordered pair id, -1 when empty
+    int32_t shift, nb;       // as in PairMeta
+    uint32_t n;              // number of entries
 };
 
 constexpr int64_t TM_PAIR_BUCKET_DENSITY = 4;

@@ -217,9 +217,13 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
 __global__ void k_slot_init(PairSlot *slots, int64_t cap) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < cap) {
-        slots[i].key = ~0ull;
-        slots[i].id = -1;
-        slots[i].pad = 0;
+        PairSlot z;
+        z.key = ~0ull;
+        z.t0 = z.base = z.boff = 0;
+        z.id = -1;
+        z.shift = z.nb = 0;
+        z.n = 0;
+        slots[i] = z;
     }
 }
 
@@ -278,6 +282,21 @@ __global__ void k_upair_place(const uint64_t *keys, const uint32_t *vals, int64_
         z.c0 = e.c0 + (es_src[k] < es_dst[k] ? 1 : 0);
         ent[j + pid + 1] = z;
     }
+}
+
+// copy each pair's metadata and size into its hash slot
+__global__ void k_slot_meta(PairSlot *slots, int64_t cap, const PairMeta *pm, const PairBucket *bk) {
+    int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= cap) return;
+    int32_t id = slots[h].id;
+    if (id < 0) return;
+    const PairMeta m = pm[id];
+    slots[h].t0 = m.t0;
+    slots[h].base = m.base;
+    slots[h].boff = m.boff;
+    slots[h].shift = m.shift;
+    slots[h].nb = m.nb;
+    slots[h].n = bk[m.boff + m.nb].idx;
 }
 
 __global__ void k_pair_hash_insert(const uint64_t *u_key, int64_t U, int64_t n, PairSlot *slots, int64_t cap) {
@@ -583,6 +602,9 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
             hipLaunchKernelGGL(k_pair_meta_pack, dim3(tm_blocks(U, TPB)), dim3(TPB), 0, st, ubeg.as<int64_t>(),
                                tfirst.as<int64_t>(), meta.as<int32_t>(), boff.as<int64_t>(), U,
                                g->pmeta.as<PairMeta>());
+            TM_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_slot_meta, dim3(tm_blocks(cap, TPB)), dim3(TPB), 0, st, g->ph_slot.as<PairSlot>(),
+                               cap, g->pmeta.as<PairMeta>(), g->pbk.as<PairBucket>());
             TM_HIP(hipGetLastError());
         }
         TM_HIP(hipStreamSynchronize(st));

@@ -144,15 +144,25 @@ struct PairView {
     }
 };
 
-// unordered pair id of {u, v}, -1 if no edge joins them
-__device__ inline int32_t pair_id(const DevGraph &G, uint32_t u, uint32_t v) {
+// The pair {u, v}: its id (-1 if no edge joins them), with its metadata
+// loaded into pv from the hash slot (one access for both).
+__device__ inline int32_t pair_find(const DevGraph &G, uint32_t u, uint32_t v, PairView &pv) {
     uint32_t a = u < v ? u : v, b = u < v ? v : u;
     uint64_t key = ((uint64_t)a << 32) | b;
     int64_t cap = G.ph_cap;
     uint64_t h = tm_pair_hash(key, cap);
     for (int64_t probe = 0; probe < cap; ++probe) {
         const PairSlot sl = G.ph_slot[h];
-        if (sl.key == key) return sl.id;
+        if (sl.key == key) {
+            pv.m.t0 = sl.t0;
+            pv.m.base = sl.base;
+            pv.m.boff = sl.boff;
+            pv.m.shift = sl.shift;
+            pv.m.nb = sl.nb;
+            pv.en = G.up_ent + sl.base;
+            pv.n = sl.n;
+            return sl.id;
+        }
         if (sl.key == ~0ull) return -1;
         h = (h + 1) & (uint64_t)(cap - 1);
     }
@@ -270,9 +280,8 @@ __device__ inline void tri_rank(const DevGraph &G, uint32_t yi, uint32_t di, int
                                 int64_t tj, int64_t hi, int64_t lo_win, int64_t delta, uint64_t *tc, TriCache &C) {
     if (yj != C.yc) {
         C.yc = yj;
-        C.p = pair_id(G, yi, yj);
+        C.p = pair_find(G, yi, yj, C.pv);
         if (C.p >= 0) {
-            C.pv.load(G, C.p);
             C.pv.at(G, ti, C.f_ti, C.f_ti1);
             C.pv.le(G, hi, C.f_hi1);
         }
@@ -353,9 +362,8 @@ __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t 
                 // its count up to t1 are kept while entries lead to yj again
                 if (yj != tcache.yc) {
                     tcache.yc = yj;
-                    tcache.p = pair_id(G, y1, yj);
+                    tcache.p = pair_find(G, y1, yj, tcache.pv);
                     if (tcache.p >= 0) {
-                        tcache.pv.load(G, tcache.p);
                         tcache.pv.le(G, t1, tcache.f_ti1);
                     }
                 }
