@@ -71,6 +71,7 @@ typedef struct {
     int64_t t_span;       /* largest normalised time t - t_min               */
     int64_t n_pairs;      /* distinct directed (u, v) pairs, u != v          */
     int64_t device_bytes; /* device memory held by the graph                 */
+    int64_t exact_table_bytes; /* of which the exact-count tables (0: none)  */
 } tm_graph_info;
 
 /* Optional diagnostics of one estimate.  Pointers are caller-owned host
@@ -100,6 +101,23 @@ typedef struct {
  */
 tm_status tm_load_graph(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t m,
                         int32_t n_nodes, int32_t on_device, void *hip_stream, tm_graph **out);
+
+/* Flags of tm_load_graph_ex. */
+enum {
+    TM_LOAD_ON_DEVICE = 1,       /* src/dst/t are device pointers                     */
+    TM_LOAD_NO_EXACT_TABLES = 2  /* skip the exact-count tables (see below)           */
+};
+
+/*
+ * tm_load_graph with flags.  Unless TM_LOAD_NO_EXACT_TABLES is set, the load
+ * also builds the exact-count tables (192 B per edge: per pair entry and
+ * endpoint, prefix sums of the counts the exact 2-node and star motif counts
+ * are range sums of), when they fit in a quarter of the free device memory;
+ * without them exact counts scan every anchor's window instead.  Results are
+ * identical either way.  Other arguments and errors as tm_load_graph.
+ */
+tm_status tm_load_graph_ex(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t m,
+                           int32_t n_nodes, uint32_t flags, void *hip_stream, tm_graph **out);
 
 /* Release a graph and its device memory.  NULL is ignored. */
 void tm_free_graph(tm_graph *g);

@@ -46,7 +46,8 @@ class Motif(ctypes.Structure):
 
 class GraphInfo(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("t_min", ctypes.c_int64),
-                ("t_span", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+                ("t_span", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("exact_table_bytes", ctypes.c_int64)]
 
 
 class EstInfo(ctypes.Structure):
@@ -78,6 +79,7 @@ i64, i32, u64, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_d
 
 _SIGS = {
     "tm_load_graph": [P, P, P, i64, i32, i32, P, P],
+    "tm_load_graph_ex": [P, P, P, i64, i32, ctypes.c_uint32, P, P],
     "tm_free_graph": [P],
     "tm_graph_info_get": [P, P],
     "tm_count_exact": [P, P, i64, P, P],
@@ -152,7 +154,7 @@ def _np(a, dtype):
 class Graph:
     """A device-resident temporal graph (freed with the object)."""
 
-    def __init__(self, src, dst, t, n_nodes: int, stream=None):
+    def __init__(self, src, dst, t, n_nodes: int, stream=None, exact_tables: bool = True):
         self._h = ctypes.c_void_p()
         self._keep = None
         on_device = 0
@@ -171,13 +173,15 @@ class Graph:
             self._keep = (s, d, tt)
             ptrs = (s.ctypes.data, d.ctypes.data, tt.ctypes.data)
             m = int(s.shape[0])
-        _check(_lib.tm_load_graph(P(ptrs[0]), P(ptrs[1]), P(ptrs[2]), m, int(n_nodes), on_device,
-                                  _stream(stream), ctypes.byref(self._h)), "tm_load_graph")
+        flags = (1 if on_device else 0) | (0 if exact_tables else 2)
+        _check(_lib.tm_load_graph_ex(P(ptrs[0]), P(ptrs[1]), P(ptrs[2]), m, int(n_nodes), flags,
+                                     _stream(stream), ctypes.byref(self._h)), "tm_load_graph_ex")
         self._keep = None
         info = GraphInfo()
         _check(_lib.tm_graph_info_get(self._h, ctypes.byref(info)), "tm_graph_info_get")
         self.m, self.n, self.t_min, self.t_span = info.m, info.n, info.t_min, info.t_span
         self.n_pairs, self.device_bytes = info.n_pairs, info.device_bytes
+        self.exact_table_bytes = info.exact_table_bytes
 
     @property
     def handle(self):
@@ -195,8 +199,8 @@ class Graph:
             pass
 
 
-def load_graph(src, dst, t, n_nodes, stream=None) -> Graph:
-    return Graph(src, dst, t, n_nodes, stream)
+def load_graph(src, dst, t, n_nodes, stream=None, exact_tables: bool = True) -> Graph:
+    return Graph(src, dst, t, n_nodes, stream, exact_tables)
 
 
 def count_exact(g: Graph, edges, delta: int, stream=None) -> int:

@@ -123,6 +123,15 @@ struct tm_graph {
     DevBuf pmeta;    // PairMeta[U]
     DevBuf pbk;      // PairBucket[sum (nb + 1)]
 
+    // exact-count tables (tm_exact.hip): per pair entry and endpoint view,
+    // global prefix sums of six counts split by the entry's direction, so
+    // that the exact 2-node and star counts of an anchor are range sums
+    int want_ex = 1;    // build them at load (TM_LOAD_NO_EXACT_TABLES clears it)
+    int has_ex = 0;
+    int64_t ex_S = 0;   // pair entry slots (m_nl + U, sentinels included)
+    DevBuf ex_c0x;      // int64[2 m_nl + 1]: direction-0 entries before each list position (global)
+    DevBuf ex_rows;     // uint64[2][ex_S][12]
+
     // reusable per-graph workspace for queries
     DevBuf ws;
     int64_t device_bytes = 0;
@@ -172,6 +181,7 @@ struct DevGraph {
     const PairSlot *ph_slot; int64_t ph_cap;
     const PairMeta *pmeta; const PairBucket *pbk;
     const PairEnt *up_ent;
+    int has_ex; int64_t ex_S; const int64_t *ex_c0x; const uint64_t *ex_rows;
 };
 
 __device__ inline uint64_t tm_pair_hash(uint64_t key, int64_t cap) {
@@ -179,6 +189,14 @@ __device__ inline uint64_t tm_pair_hash(uint64_t key, int64_t cap) {
 }
 
 DevGraph dev_view(const tm_graph *g);
+
+// Builds the exact-count tables of a loaded graph (ent_nl: edge index of
+// each pair entry slot, ~0 for sentinels; inc_pos: list position of each
+// edge's source (2k) and destination (2k + 1) entry; nl_pos: edge index ->
+// time-sorted position).  Leaves has_ex = 0 when they do not fit in a
+// quarter of the free device memory.
+tm_status tm_build_exact_tables(tm_graph *g, const uint32_t *ent_nl, const uint32_t *inc_pos, const int64_t *nl_pos,
+                                hipStream_t st);
 
 // ------------------------------------------------------------ primitives
 

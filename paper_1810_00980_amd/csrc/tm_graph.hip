@@ -266,7 +266,8 @@ __global__ void k_upair_index(const uint64_t *keys, const int64_t *bscan, int64_
 // last entry of a pair also writes the sentinel after it
 __global__ void k_upair_place(const uint64_t *keys, const uint32_t *vals, int64_t m_nl, const int64_t *nl_pos,
                               const int32_t *es_src, const int32_t *es_dst, const int64_t *es_t,
-                              const int64_t *bscan, const int64_t *g0, const int64_t *up_beg, PairEnt *ent) {
+                              const int64_t *bscan, const int64_t *g0, const int64_t *up_beg, PairEnt *ent,
+                              uint32_t *ent_nl) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m_nl) return;
     int64_t pid = bscan[j] + (upair_start(keys, j) ? 1 : 0) - 1;
@@ -276,11 +277,13 @@ __global__ void k_upair_place(const uint64_t *keys, const uint32_t *vals, int64_
     e.t = es_t[k];
     e.c0 = g0[j] - g0[b];
     ent[j + pid] = e;
+    ent_nl[j + pid] = vals[j];
     if (j + 1 == m_nl || keys[j + 1] != keys[j]) {
         PairEnt z;
         z.t = LLONG_MAX;
         z.c0 = e.c0 + (es_src[k] < es_dst[k] ? 1 : 0);
         ent[j + pid + 1] = z;
+        ent_nl[j + pid + 1] = ~0u;
     }
 }
 
@@ -402,6 +405,7 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
     g->m = m;
     g->n = n_nodes;
     DevBuf hsrc, hdst, ht;
+    DevBuf ent_nl, inc_pos;  // kept for the exact-count tables
     const int32_t *d_src = src, *d_dst = dst;
     const int64_t *d_t = t;
     if (!on_device && m > 0) {
@@ -554,6 +558,7 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
         TM_TRY(ukey.alloc((size_t)(U > 0 ? U : 1) * 8));
         TM_TRY(ubeg.alloc((size_t)(U + 1) * 8));
         TM_TRY(g->up_ent.alloc((size_t)(m_nl + U > 0 ? m_nl + U : 1) * sizeof(PairEnt)));
+        TM_TRY(ent_nl.alloc((size_t)(m_nl + U > 0 ? m_nl + U : 1) * 4));
         if (m_nl > 0) {
             hipLaunchKernelGGL(k_upair_index, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, uk.as<uint64_t>(),
                                bscan.as<int64_t>(), m_nl, ukey.as<uint64_t>(), ubeg.as<int64_t>());
@@ -565,7 +570,8 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
             hipLaunchKernelGGL(k_upair_place, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, uk.as<uint64_t>(),
                                uv.as<uint32_t>(), m_nl, nl.as<int64_t>(), g->es_src.as<int32_t>(),
                                g->es_dst.as<int32_t>(), g->es_t.as<int64_t>(), bscan.as<int64_t>(),
-                               g0.as<int64_t>(), ubeg.as<int64_t>(), g->up_ent.as<PairEnt>());
+                               g0.as<int64_t>(), ubeg.as<int64_t>(), g->up_ent.as<PairEnt>(),
+                               ent_nl.as<uint32_t>());
             TM_HIP(hipGetLastError());
         }
 
@@ -629,11 +635,10 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
                                nl.as<int64_t>(), g->es_src.as<int32_t>(), g->es_dst.as<int32_t>(),
                                g->es_t.as<int64_t>(), g->inc_nd.as<uint32_t>(), g->inc_t.as<int64_t>());
             TM_HIP(hipGetLastError());
-            DevBuf posv;
-            TM_TRY(posv.alloc((size_t)len * 4));
+            TM_TRY(inc_pos.alloc((size_t)len * 4));
             for (int pass = 0; pass < 2; ++pass) {
                 hipLaunchKernelGGL(k_inc_twin, dim3(tm_blocks(len, TPB)), dim3(TPB), 0, st, iv.as<uint32_t>(), len,
-                                   posv.as<uint32_t>(), g->inc_twin.as<uint32_t>(), pass);
+                                   inc_pos.as<uint32_t>(), g->inc_twin.as<uint32_t>(), pass);
                 TM_HIP(hipGetLastError());
             }
             TM_HIP(hipStreamSynchronize(st));
@@ -670,9 +675,13 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
         TM_HIP(hipGetLastError());
         TM_HIP(hipStreamSynchronize(st));
     }
+    if (m_nl > 0 && g->want_ex)
+        TM_TRY(tm_build_exact_tables(g, ent_nl.as<uint32_t>(), inc_pos.as<uint32_t>(), nl.as<int64_t>(), st));
+    ent_nl.release();
+    inc_pos.release();
     const DevBuf *all[] = {&g->es_src, &g->es_dst, &g->es_t, &g->pos_of, &g->out_off, &g->out_nbr, &g->out_t,
                            &g->in_off, &g->in_nbr, &g->in_t, &g->sp_off, &g->sp_nbr, &g->sp_beg, &g->pr_t,
-                           &g->inc_off, &g->inc_nd, &g->inc_t, &g->inc_twin, &g->hi_off, &g->hi_nd, &g->hi_t, &g->up_ent, &g->ph_slot, &g->pmeta, &g->pbk};
+                           &g->inc_off, &g->inc_nd, &g->inc_t, &g->inc_twin, &g->hi_off, &g->hi_nd, &g->hi_t, &g->up_ent, &g->ph_slot, &g->pmeta, &g->pbk, &g->ex_c0x, &g->ex_rows};
     int64_t tot = 0;
     for (const DevBuf *b : all) tot += (int64_t)b->bytes;
     g->device_bytes = tot;
@@ -699,16 +708,22 @@ DevGraph dev_view(const tm_graph *g) {
     v.pmeta = g->pmeta.as<PairMeta>();
     v.pbk = g->pbk.as<PairBucket>();
     v.up_ent = g->up_ent.as<PairEnt>();
+    v.has_ex = g->has_ex;
+    v.ex_S = g->ex_S;
+    v.ex_c0x = g->ex_c0x.as<int64_t>();
+    v.ex_rows = g->ex_rows.as<uint64_t>();
     return v;
 }
 
-extern "C" tm_status tm_load_graph(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t m,
-                                   int32_t n_nodes, int32_t on_device, void *hip_stream, tm_graph **out) {
+extern "C" tm_status tm_load_graph_ex(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t m,
+                                      int32_t n_nodes, uint32_t flags, void *hip_stream, tm_graph **out) {
     if (!out || m < 0 || n_nodes <= 0 || (m > 0 && (!src || !dst || !t))) return TM_EINVAL;
+    if (flags & ~(uint32_t)(TM_LOAD_ON_DEVICE | TM_LOAD_NO_EXACT_TABLES)) return TM_EINVAL;
     if (m > (int64_t)INT32_MAX) return TM_EINVAL;  // 32-bit edge indices in the sorts
     tm_graph *g = new (std::nothrow) tm_graph();
     if (!g) return TM_ENOMEM;
-    tm_status s = load_impl(src, dst, t, m, n_nodes, on_device, (hipStream_t)hip_stream, g);
+    g->want_ex = (flags & TM_LOAD_NO_EXACT_TABLES) ? 0 : 1;
+    tm_status s = load_impl(src, dst, t, m, n_nodes, (flags & TM_LOAD_ON_DEVICE) ? 1 : 0, (hipStream_t)hip_stream, g);
     if (s != TM_OK) {
         (void)hipStreamSynchronize((hipStream_t)hip_stream);
         delete g;
@@ -717,6 +732,11 @@ extern "C" tm_status tm_load_graph(const int32_t *src, const int32_t *dst, const
     }
     *out = g;
     return TM_OK;
+}
+
+extern "C" tm_status tm_load_graph(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t m,
+                                   int32_t n_nodes, int32_t on_device, void *hip_stream, tm_graph **out) {
+    return tm_load_graph_ex(src, dst, t, m, n_nodes, on_device ? (uint32_t)TM_LOAD_ON_DEVICE : 0u, hip_stream, out);
 }
 
 extern "C" void tm_free_graph(tm_graph *g) {
@@ -734,5 +754,6 @@ extern "C" tm_status tm_graph_info_get(const tm_graph *g, tm_graph_info *info) {
     info->t_span = g->t_span;
     info->n_pairs = g->S;
     info->device_bytes = g->device_bytes;
+    info->exact_table_bytes = (int64_t)(g->ex_c0x.bytes + g->ex_rows.bytes);
     return TM_OK;
 }

@@ -82,12 +82,18 @@ __global__ void __launch_bounds__(SW_TPB) k_sweep3(DevGraph G, SweepArgs a) {
                     int64_t hi = (t > LLONG_MAX - a.delta) ? LLONG_MAX : t + a.delta;
                     hi = hi < whi ? hi : whi;
                     if constexpr (RANKED) sweep_tri_ranked(G, a, i, le, y, d, t, hi, wlo, lds);
-                    else if constexpr (MODE == MODE_COUNT) sweep_fwd_count(G, a, i, le, y, d, t, hi, lds);
+                    else if constexpr (MODE == MODE_COUNT) {
+                        if (G.has_ex) sweep_fwd_prefix(G, a, i, lb, le, (uint32_t)x, y, d, t, hi, lds);
+                        else sweep_fwd_count(G, a, i, le, y, d, t, hi, lds);
+                    }
                     else sweep_fwd<MODE, CLS>(G, a, i, le, y, d, t, hi, wlo, lds);
                 } else {
                     int64_t lo = (t < LLONG_MIN + a.delta) ? LLONG_MIN : t - a.delta;
                     lo = lo > wlo ? lo : wlo;
-                    if constexpr (MODE == MODE_COUNT) sweep_bwd_count(G, i, lb, y, d, t, lo, lds);
+                    if constexpr (MODE == MODE_COUNT) {
+                        if (G.has_ex) sweep_bwd_prefix(G, i, lb, (uint32_t)x, y, d, t, lo, lds);
+                        else sweep_bwd_count(G, i, lb, y, d, t, lo, lds);
+                    }
                     else sweep_bwd<MODE>(G, a, i, lb, y, d, t, lo, lds);
                 }
             }

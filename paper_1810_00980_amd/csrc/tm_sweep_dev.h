@@ -592,6 +592,102 @@ __device__ inline void sweep_bwd_count(const DevGraph &G, int64_t jj, int64_t be
     count_out(lds, one, c + 6, (uint64_t)as1 * aa1 - u11 - z11);
 }
 
+// Exact 2-node and star counts of a forward anchor from the exact-count
+// tables (tm_exact.hip): i is the anchor's position in x's list [lb, le),
+// hi its horizon.  With R the entries of the pair P = {x, y1} in (t1, hi],
+// R_d those of direction d, and S[d_e*6 + c] the sums over R of the table's
+// values c (M_0, M_1, N_0, N_1, N+_0 - M+_0, N+_1 - M+_1):
+//   2-node [2k + d]            S[d*6 + k]     - |R_d| M+_k(t1)
+//   star B [4 + 4 d1 + 2k + d] S[d*6 + 2 + k] - |R_d| N+_k(t1) - (2-node term)
+//   star A [12 + 4 d1 + 2k + d] |R_k| (N+_d(hi) - M+_d(hi)) - S[k*6 + 4 + d]
+__device__ inline void ex_counts(const PairView &pv, const DevGraph &G, int64_t t, bool strict, int view,
+                                 int64_t *r, int64_t c[2]) {
+    int64_t ab[2];
+    if (strict) pv.lt(G, t, ab);
+    else pv.le(G, t, ab);
+    *r = ab[0] + ab[1];
+    c[0] = view ? ab[1] : ab[0];  // direction 0 as seen from x
+    c[1] = view ? ab[0] : ab[1];
+}
+
+__device__ inline void sweep_fwd_prefix(const DevGraph &G, const SweepArgs &a, int64_t i, int64_t lb, int64_t le,
+                                        uint32_t x, uint32_t y1, uint32_t d1, int64_t t1, int64_t hi,
+                                        unsigned long long *lds, OneCode *one = nullptr) {
+    PairView pv;
+    (void)pair_find(G, x, y1, pv);  // the anchor's own pair
+    const int view = x > y1 ? 1 : 0;
+    int64_t r0, r1, Mt1[2], MH[2];
+    ex_counts(pv, G, t1, false, view, &r0, Mt1);
+    ex_counts(pv, G, hi, false, view, &r1, MH);
+    const int64_t *tv = G.inc_t, *c0x = G.ex_c0x;
+    int64_t ge = i + 1;
+    while (ge < le && tv[ge] == t1) ++ge;
+    int64_t u = ge, up = le;  // first entry after hi
+    while (u < up) {
+        int64_t mid = (u + up) >> 1;
+        if (tv[mid] <= hi) u = mid + 1;
+        else up = mid;
+    }
+    const int64_t base0 = c0x[lb];
+    const int64_t Nt1[2] = {c0x[ge] - base0, (ge - lb) - (c0x[ge] - base0)};
+    const int64_t NH[2] = {c0x[u] - base0, (u - lb) - (c0x[u] - base0)};
+    const int64_t R[2] = {MH[0] - Mt1[0], MH[1] - Mt1[1]};
+    const uint64_t *row0 = G.ex_rows + ((int64_t)view * G.ex_S + pv.m.base + r0) * 12;
+    const uint64_t *row1 = G.ex_rows + ((int64_t)view * G.ex_S + pv.m.base + r1) * 12;
+    uint64_t S[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) S[c] = row1[c] - row0[c];
+    const int b = 4 * (int)d1;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            const uint64_t c2 = S[d * 6 + k] - (uint64_t)R[d] * (uint64_t)Mt1[k];
+            if ((a.want_fwd & 1u) && d1 == 0) count_out(lds, one, 2 * k + d, c2);
+            if (a.want_fwd & 2u)
+                count_out(lds, one, 4 + b + 2 * k + d, S[d * 6 + 2 + k] - (uint64_t)R[d] * (uint64_t)Nt1[k] - c2);
+            if (a.want_fwd & 4u)
+                count_out(lds, one, 12 + b + 2 * k + d,
+                          (uint64_t)R[k] * (uint64_t)(NH[d] - MH[d]) - S[k * 6 + 4 + d]);
+        }
+    }
+}
+
+// Star-C counts of a backward anchor (the last edge, time t3) from the
+// tables: R' the entries of P = {x, y3} in [lo, t3),
+//   code 28 + 4 d1 + 2k + d3 = sum over R'_k of (N_d1 - M_d1)
+//                              - |R'_k| (N_d1(lo) - M_d1(lo))
+__device__ inline void sweep_bwd_prefix(const DevGraph &G, int64_t j, int64_t lb, uint32_t x, uint32_t y3, uint32_t d3,
+                                        int64_t t3, int64_t lo, unsigned long long *lds, OneCode *one = nullptr) {
+    PairView pv;
+    (void)pair_find(G, x, y3, pv);
+    const int view = x > y3 ? 1 : 0;
+    int64_t r0, r1, Mlo[2], Mt3[2];
+    ex_counts(pv, G, lo, true, view, &r0, Mlo);
+    ex_counts(pv, G, t3, true, view, &r1, Mt3);
+    const int64_t *tv = G.inc_t, *c0x = G.ex_c0x;
+    int64_t u = lb, up = j;  // first entry with time >= lo
+    while (u < up) {
+        int64_t mid = (u + up) >> 1;
+        if (tv[mid] < lo) u = mid + 1;
+        else up = mid;
+    }
+    const int64_t base0 = c0x[lb];
+    const int64_t Nlo[2] = {c0x[u] - base0, (u - lb) - (c0x[u] - base0)};
+    const uint64_t *row0 = G.ex_rows + ((int64_t)view * G.ex_S + pv.m.base + r0) * 12;
+    const uint64_t *row1 = G.ex_rows + ((int64_t)view * G.ex_S + pv.m.base + r1) * 12;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const uint64_t Rk = (uint64_t)(Mt3[k] - Mlo[k]);
+#pragma unroll
+        for (int d1 = 0; d1 < 2; ++d1) {
+            const uint64_t sn = row1[k * 6 + 2 + d1] - row0[k * 6 + 2 + d1];
+            const uint64_t sm = row1[k * 6 + d1] - row0[k * 6 + d1];
+            count_out(lds, one, 28 + 4 * d1 + 2 * k + (int)d3, (sn - sm) - Rk * (uint64_t)(Nlo[d1] - Mlo[d1]));
+        }
+    }
+}
+
 // backward sweep of one anchor (codes 28..35): star with e2 on e3's pair
 template <int MODE>
 __device__ inline void sweep_bwd(const DevGraph &G, const SweepArgs &a, int64_t jj, int64_t beg, uint32_t y3,

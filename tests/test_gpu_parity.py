@@ -32,11 +32,11 @@ def to_dev(g):
     return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (g.src, g.dst, g.t)]
 
 
-def load(tm, g, device=True):
+def load(tm, g, device=True, exact_tables=True):
     if device:
         s, d, t = to_dev(g)
-        return tm.load_graph(s, d, t, g.n)
-    return tm.load_graph(g.src, g.dst, g.t, g.n)
+        return tm.load_graph(s, d, t, g.n, exact_tables=exact_tables)
+    return tm.load_graph(g.src, g.dst, g.t, g.n, exact_tables=exact_tables)
 
 
 def close(a, b):
@@ -203,6 +203,32 @@ def test_count_window(tm):
             for M, c in zip(THREE + [ti.CYCLE4, ti.STAR4], got):
                 want, _ = oracle.count(g.src, g.dst, g.t, M, delta, win=(lo, hi), hist=False)
                 assert c == want, (M, lo, hi, delta)
+
+
+def test_exact_with_and_without_tables(tm):
+    """Exact counts of all 36 three-edge motifs, whole-graph and windowed,
+    from the exact-count tables (range sums) and from the window scans, each
+    equal to the oracle's, on tie-heavy graphs with self-loops, repeated
+    pairs and hubs."""
+    cases = [(ti.random_small_graph(8, 1200, 2500, 71, allow_self_loops=True), (0, 9, 80)),
+             (ti.random_small_graph(40, 3000, 40000, 72, allow_self_loops=False), (0, 500, 5000)),
+             (ti.zipf_graph(300, 6000, 1.8, 50000, 73), (30, 3600))]
+    for g, deltas in cases:
+        say("tables", g.n, g.m)
+        Gt = load(tm, g, exact_tables=True)
+        Gs = load(tm, g, exact_tables=False)
+        assert Gt.exact_table_bytes > 0 and Gs.exact_table_bytes == 0
+        lo, hi = int(np.percentile(g.t, 30)), int(np.percentile(g.t, 70))
+        for delta in deltas:
+            a = tm.count_exact_multi(Gt, THREE, delta)
+            b = tm.count_exact_multi(Gs, THREE, delta)
+            wa = tm.count_window(Gt, THREE, delta, lo, hi)
+            wb = tm.count_window(Gs, THREE, delta, lo, hi)
+            for k, M in enumerate(THREE):
+                want, _ = oracle.count(g.src, g.dst, g.t, M, delta, hist=False)
+                assert a[k] == want and b[k] == want, (M, delta, a[k], b[k], want)
+                want, _ = oracle.count(g.src, g.dst, g.t, M, delta, win=(lo, hi), hist=False)
+                assert wa[k] == want and wb[k] == want, (M, delta, wa[k], wb[k], want)
 
 
 @pytest.fixture(scope="module")
