@@ -343,10 +343,17 @@ def traffic_record(kernel):
 # searches (48 B): 96 B.  The weighted triangle sweep looks up once per
 # entry (24 B) and reads hash slot, metadata and one search on a pair change
 # (72 B).
-def sweep_bytes(exact, ests):
+# With the exact-count tables, a 2-node/star count anchor instead reads its
+# pair's hash slot (64 B), two pair searches (48 B), list prefix counts
+# (24 B forward, 16 B backward) and two 96 B table rows: 344 B forward and
+# 336 B backward per anchor with its own 16 B (list-search probes not
+# counted).
+def sweep_bytes(exact, ests, tables):
     out = {
-        "sweep3_fwd_count": 16 * exact["anchors"] + 12 * exact["fwd_entries"],
-        "sweep3_bwd_count": 16 * exact["anchors"] + 12 * exact["bwd_entries"],
+        "sweep3_fwd_count": (344 * exact["anchors"] if tables
+                             else 16 * exact["anchors"] + 12 * exact["fwd_entries"]),
+        "sweep3_bwd_count": (336 * exact["anchors"] if tables
+                             else 16 * exact["anchors"] + 12 * exact["bwd_entries"]),
         "sweep3_tri_count": 16 * exact["tri_anchors"] + 12 * exact["tri_entries"] + 48 * exact["tri_lookups"]
         + 96 * exact["tri_pairs"],
         "sweep3_fwd_weight": 0, "sweep3_bwd_weight": 0, "sweep3_tri_weight": 0,
@@ -359,12 +366,12 @@ def sweep_bytes(exact, ests):
     return out
 
 
-def sweep_roofline(exact, ests, kern, steps):
+def sweep_roofline(exact, ests, kern, steps, tables):
     """Roofline entry of the sweep kernel with the largest time per step,
     with the achieved algorithmic GB/s of every sweep kernel beside it.  The
     kernels of one pass run concurrently on forked streams, so each one's
     duration is measured while it shares the CUs with the others."""
-    bps = sweep_bytes(exact, ests)  # algorithmic bytes per step
+    bps = sweep_bytes(exact, ests, tables)  # algorithmic bytes per step
     timed = {k: v for k, v in kern.items() if k in bps and v[1] > 0}
     if not timed:
         return None
@@ -462,8 +469,11 @@ def main():
     G = tm.load_graph(src, dst, t, g.n)
     census = tm.sweep_census(G, delta)
     ests = [tm.sweep_census_est(G, delta, c, p, 0) for c, p in W["est"]]
+    tables = G.exact_table_bytes > 0
     G.free()
-    roofline = sweep_roofline(census, ests, kern, args.steps)
+    roofline = sweep_roofline(census, ests, kern, args.steps, tables)
+    if roofline:
+        roofline["exact_tables"] = tables
     out = {
         "metric": "temporal edges/s per motif query (exact & p=0.1 estimate) vs CPU",
         "value": g.m * q / dt, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
