@@ -21,6 +21,15 @@ LIB_PATH = os.path.join(_HERE, "libtm.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libtm.so is not built ({LIB_PATH}); run paper_1810_00980_amd/build.py")
 
+# A process holds one HIP runtime (torch's and the system's share the soname
+# libamdhip64.so.7, and the first one loaded serves both).  Loading torch
+# first makes it the one torch is built against, so that torch keeps its
+# devices and the library shares its memory and streams.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 STATUS = {0: "TM_OK", 1: "TM_EINVAL", 2: "TM_EUNSUPPORTED", 3: "TM_ENOMEM", 4: "TM_EBUDGET",
