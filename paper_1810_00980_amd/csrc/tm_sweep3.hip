@@ -41,8 +41,18 @@ namespace {
 
 using namespace sweepdev;
 
+// resident waves per SIMD asked of the compiler: the exact triangle sweep is
+// latency-bound and two registers above five waves (192 -> 176 ms on the
+// 10M-edge graph with a 12-byte spill); the weighted one gained nothing from
+// a sixth wave
 template <int MODE, bool FWD, unsigned CLS>
-__global__ void __launch_bounds__(SW_TPB) k_sweep3(DevGraph G, SweepArgs a) {
+constexpr int sweep_waves() {
+    return (MODE == MODE_COUNT && FWD && CLS == 8u) ? 5 : 1;
+}
+
+template <int MODE, bool FWD, unsigned CLS>
+__global__ void __launch_bounds__(SW_TPB) __attribute__((amdgpu_waves_per_eu(sweep_waves<MODE, FWD, CLS>())))
+k_sweep3(DevGraph G, SweepArgs a) {
     __shared__ unsigned long long lds[36 * 4];
     for (int k = threadIdx.x; k < 36 * 4; k += SW_TPB) lds[k] = 0;
     __syncthreads();
