@@ -252,9 +252,25 @@ __device__ inline uint64_t weight_of(const SweepArgs &a, int64_t dlt) {
 }
 
 // add v to tc[4*d1 + 2*d2 + d3] (runtime index, kept in registers)
-__device__ inline void tc_add(uint64_t *tc, uint32_t idx, uint64_t v) {
+// Per-lane triangle counts of the eight codes 20 + k in 32 bits: every
+// increment is a pair count (below 2^31), so a sum wraps at most once per
+// add, and a wrap adds 2^32 to the shared total right away (rare).
+struct TriAcc {
+    uint32_t c[8];
+    unsigned long long *lds;
+    OneCode *one;
+    __device__ void add(uint32_t idx, uint32_t v);
+};
+
+__device__ inline void count_out(unsigned long long *lds, OneCode *one, int code, uint64_t v);
+
+__device__ inline void TriAcc::add(uint32_t idx, uint32_t v) {
 #pragma unroll
-    for (uint32_t k = 0; k < 8; ++k) tc[k] += (k == idx) ? v : 0;
+    for (uint32_t k = 0; k < 8; ++k) {
+        const uint32_t o = c[k];
+        c[k] = o + ((k == idx) ? v : 0u);
+        if (c[k] < o) count_out(lds, one, 20 + (int)k, 1ull << 32);
+    }
 }
 
 // Exact triangle counts at the lowest-ranked node.  Entries i (time ti) and
@@ -273,17 +289,23 @@ struct TriCache {
     uint32_t yc;
     int32_t p;
     PairView pv;
-    int64_t f_ti[2], f_ti1[2], f_hi1[2];
+    int32_t f_ti[2], f_ti1[2], f_hi1[2];  // pair counts (below 2^31)
 };
 
 __device__ inline void tri_rank(const DevGraph &G, uint32_t yi, uint32_t di, int64_t ti, uint32_t yj, uint32_t dj,
-                                int64_t tj, int64_t hi, int64_t lo_win, int64_t delta, uint64_t *tc, TriCache &C) {
+                                int64_t tj, int64_t hi, int64_t lo_win, int64_t delta, TriAcc &tc, TriCache &C) {
     if (yj != C.yc) {
         C.yc = yj;
         C.p = pair_find(G, yi, yj, C.pv);
         if (C.p >= 0) {
-            C.pv.at(G, ti, C.f_ti, C.f_ti1);
-            C.pv.le(G, hi, C.f_hi1);
+            int64_t a0[2], a1[2], h1[2];
+            C.pv.at(G, ti, a0, a1);
+            C.pv.le(G, hi, h1);
+            for (int q = 0; q < 2; ++q) {
+                C.f_ti[q] = (int32_t)a0[q];
+                C.f_ti1[q] = (int32_t)a1[q];
+                C.f_hi1[q] = (int32_t)h1[q];
+            }
         }
     }
     if (C.p < 0) return;
@@ -297,11 +319,11 @@ __device__ inline void tri_rank(const DevGraph &G, uint32_t yi, uint32_t di, int
     for (uint32_t dir = 0; dir < 2; ++dir) {  // dir 0: yi -> yj, 1: yj -> yi
         const uint32_t k = dir ^ sw;
         // v = x: d1 = di, d2 = dir, d3 = dj
-        tc_add(tc, 4 * di + 2 * dir + dj, (uint64_t)(f_tj[k] - C.f_ti1[k]));
+        tc.add(4 * di + 2 * dir + dj, (uint32_t)(f_tj[k] - C.f_ti1[k]));
         // v = y1: d1 = 1 - di, d2 = dj, d3 = dir
-        tc_add(tc, 4 * (1 - di) + 2 * dj + dir, (uint64_t)(C.f_hi1[k] - f_tj1[k]));
+        tc.add(4 * (1 - di) + 2 * dj + dir, (uint32_t)(C.f_hi1[k] - f_tj1[k]));
         // v = y3: d1 = 1 - dir, d2 = 1 - di, d3 = 1 - dj
-        tc_add(tc, 4 * (1 - dir) + 2 * (1 - di) + (1 - dj), (uint64_t)(C.f_ti[k] - f_lo3[k]));
+        tc.add(4 * (1 - dir) + 2 * (1 - di) + (1 - dj), (uint32_t)(C.f_ti[k] - f_lo3[k]));
     }
 }
 
@@ -364,7 +386,10 @@ __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t 
                     tcache.yc = yj;
                     tcache.p = pair_find(G, y1, yj, tcache.pv);
                     if (tcache.p >= 0) {
-                        tcache.pv.le(G, t1, tcache.f_ti1);
+                        int64_t a1[2];
+                        tcache.pv.le(G, t1, a1);
+                        tcache.f_ti1[0] = (int32_t)a1[0];
+                        tcache.f_ti1[1] = (int32_t)a1[1];
                     }
                 }
                 if (tcache.p >= 0) {
@@ -398,7 +423,11 @@ __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t 
 __device__ inline void sweep_tri_ranked(const DevGraph &G, const SweepArgs &a, int64_t i, int64_t end, uint32_t y1,
                                         uint32_t d1, int64_t t1, int64_t hi, int64_t lo_win,
                                         unsigned long long *lds, OneCode *one = nullptr) {
-    uint64_t tc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    TriAcc tc;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) tc.c[k] = 0;
+    tc.lds = lds;
+    tc.one = one;
     TriCache tcache;
     tcache.yc = ~0u;
     tcache.p = -1;
@@ -411,14 +440,7 @@ __device__ inline void sweep_tri_ranked(const DevGraph &G, const SweepArgs &a, i
         if (yj != y1) tri_rank(G, y1, d1, t1, yj, dj, tj, hi, lo_win, a.delta, tc, tcache);
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        if (!tc[k]) continue;
-        if (one) {
-            if (one->code == 20 + k) tm_add_u128(one->cl, one->ch, tc[k], 0);
-        } else {
-            lds_add_u128(&lds[4 * (20 + k)], &lds[4 * (20 + k) + 1], tc[k], 0);
-        }
-    }
+    for (int k = 0; k < 8; ++k) count_out(lds, one, 20 + k, tc.c[k]);
 }
 
 // Exact 2-node and star counts of one forward anchor i (codes 0..19) with
