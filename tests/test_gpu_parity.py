@@ -231,6 +231,49 @@ def test_exact_with_and_without_tables(tm):
                 assert wa[k] == want and wb[k] == want, (M, delta, wa[k], wb[k], want)
 
 
+def _wide_star_graph():
+    """Node 0 (a hub) meets 1500 distinct leaves once each in [0, 1500); node
+    1501 meets the hub every 50 s and 400 random leaves: its windows are long
+    and the hub's window holds more distinct neighbours than the weighted
+    triangle sweep's per-wave map takes."""
+    rng = np.random.default_rng(81)
+    src, dst, t = [], [], []
+    for leaf in range(1, 1501):
+        src.append(0), dst.append(leaf), t.append(leaf - 1)
+    for k in range(30):
+        src.append(1501), dst.append(0), t.append(50 * k + 7)
+    for leaf in rng.integers(1, 1501, 400):
+        if rng.random() < 0.5:
+            src.append(1501), dst.append(int(leaf)), t.append(int(rng.integers(0, 1500)))
+        else:
+            src.append(int(leaf)), dst.append(1501), t.append(int(rng.integers(0, 1500)))
+    perm = rng.permutation(len(src))
+    return ti.Graph(np.array(src, np.int32)[perm], np.array(dst, np.int32)[perm], np.array(t, np.int64)[perm], 1502)
+
+
+def test_weighted_triangles_long_windows(tm):
+    """The weighted and histogram triangle sums of anchors with long windows
+    (the wave-cooperative path, and its fallback when the window of the
+    anchor's other endpoint has too many distinct neighbours) equal the
+    oracle's, estimate by estimate and bin by bin."""
+    tri = [M for M in THREE if len({x for e in M for x in e}) == 3 and
+           not any(all(x in e for e in M) for x in range(3))]
+    cases = [(ti.zipf_graph(1000, 20000, 1.6, 20000, 83), 600, (2, 1.0, 0), (5, 0.5, 3)),
+             (_wide_star_graph(), 2000, (2, 1.0, 0), (3, 0.7, 5))]
+    for g, delta, *settings in cases:
+        say("long windows", g.n, g.m)
+        G = load(tm, g)
+        for c, p, seed in settings:
+            got, _ = tm.estimate_multi(G, tri, delta, c, p, seed)
+            for k, M in enumerate(tri):
+                o = oracle.estimate(g.src, g.dst, g.t, M, delta, c, p, seed)
+                assert close(got[k], o["Z"]), (M, c, p, seed, got[k], o["Z"])
+        counts, hlo, hhi = tm.count_exact_multi(G, tri, delta, hist=True)
+        for k, M in enumerate(tri):
+            want, h = oracle.count(g.src, g.dst, g.t, M, delta, hist=True)
+            assert counts[k] == want and (hhi[k] == 0).all() and (hlo[k] == h).all(), M
+
+
 @pytest.fixture(scope="module")
 def zipf10m():
     return ti.config_zipf10m()
