@@ -366,11 +366,13 @@ def sweep_bytes(exact, ests, tables):
     return out
 
 
-def sweep_roofline(exact, ests, kern, steps, tables):
-    """Roofline entry of the sweep kernel with the largest time per step,
-    with the achieved algorithmic GB/s of every sweep kernel beside it.  The
-    kernels of one pass run concurrently on forked streams, so each one's
-    duration is measured while it shares the CUs with the others."""
+def sweep_roofline(exact, ests, kern, crit, steps, tables):
+    """Roofline entry of the dominant sweep kernel, with the achieved
+    algorithmic GB/s of every sweep kernel beside it.  The kernels of one
+    pass run concurrently on forked streams and share the CUs, so each one's
+    duration spans most of the pass; the dominant kernel is the one with the
+    most time on the critical path, i.e. summed over the passes it was the
+    last of its pass to finish (crit)."""
     bps = sweep_bytes(exact, ests, tables)  # algorithmic bytes per step
     timed = {k: v for k, v in kern.items() if k in bps and v[1] > 0}
     if not timed:
@@ -380,13 +382,14 @@ def sweep_roofline(exact, ests, kern, steps, tables):
         per[k] = {"launches_per_step": n / steps, "avg_launch_ms": ms / n,
                   "algorithmic_bytes_per_launch": bps[k] * steps / n,
                   "achieved_GBs": bps[k] * steps / (ms / 1e3) / 1e9}
-    dom = max(timed, key=lambda k: timed[k][0])
+    dom = max(timed, key=lambda k: (crit.get(k, (0.0, 0))[0], timed[k][0]))
     ach = per[dom]["achieved_GBs"]
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "traffic": traffic_record(dom), "kernel": dom, "avg_launch_ms": per[dom]["avg_launch_ms"],
             "launches": timed[dom][1], "algorithmic_bytes_per_launch": per[dom]["algorithmic_bytes_per_launch"],
             "census": {"exact": exact, "estimates": ests}, "sweep_kernels": per,
-            "sweep_kernels_ms_per_step": {k: v[0] / steps for k, v in kern.items()}}
+            "sweep_kernels_ms_per_step": {k: v[0] / steps for k, v in kern.items()},
+            "critical_path_ms_per_step": {k: v[0] / steps for k, v in crit.items() if v[1] > 0}}
 
 
 def main():
@@ -464,6 +467,7 @@ def main():
     dt = (time.perf_counter() - t0) / args.steps
     tm.profile_enable(False)
     kern = {k: tm.profile_read(k) for k in SWEEP_KERNELS}
+    crit = {k: tm.profile_read("crit:" + k) for k in SWEEP_KERNELS}
 
     q = len(motifs) * (1 + len(W["est"]))
     G = tm.load_graph(src, dst, t, g.n)
@@ -471,7 +475,7 @@ def main():
     ests = [tm.sweep_census_est(G, delta, c, p, 0) for c, p in W["est"]]
     tables = G.exact_table_bytes > 0
     G.free()
-    roofline = sweep_roofline(census, ests, kern, args.steps, tables)
+    roofline = sweep_roofline(census, ests, kern, crit, args.steps, tables)
     if roofline:
         roofline["exact_tables"] = tables
     out = {

@@ -288,11 +288,15 @@ void tm_server_destroy(tm_server *s);
 
 /*
  * Kernel timing (off by default).  When enabled, the library brackets its
- * main kernel launches with HIP events on the caller's stream and adds the
- * elapsed times per kernel name ("sweep3_fwd_count", "sweep3_bwd_count",
- * "sweep3_fwd_weight", "sweep3_bwd_weight", "sweep3_fwd_hist",
- * "sweep3_bwd_hist", "count_generic", "count_batch").  tm_profile_read
- * returns the total milliseconds and the number of launches so far.
+ * main kernel launches with HIP events on the stream each kernel runs on and
+ * adds the elapsed times per kernel name ("sweep3_{fwd,bwd,tri}_count",
+ * "sweep3_{fwd,bwd,tri}_weight", "sweep3_{fwd,bwd,tri}_hist",
+ * "count_generic", "count_batch", "count_batch_stored",
+ * "batch_anchor_values").  The sweep kernels of one pass run concurrently;
+ * the longest of them, which the pass waits for, is also credited under
+ * "crit:<name>" (one launch per pass).  tm_profile_read returns the total
+ * milliseconds and the number of launches so far (zeros for a name never
+ * timed).
  */
 tm_status tm_profile_enable(int32_t on);
 tm_status tm_profile_reset(void);

@@ -17,12 +17,14 @@ namespace {
 struct ProfEvent {
     const char *name;
     hipEvent_t a, b;
+    uint64_t pass;
 };
 struct ProfState {
     std::mutex mu;
     bool on = false;
     std::vector<ProfEvent> pending;
     std::map<std::string, std::pair<double, int64_t>> total;
+    uint64_t next_pass = 0;
 };
 ProfState &prof() {
     static ProfState s;
@@ -30,13 +32,19 @@ ProfState &prof() {
 }
 }  // namespace
 
-void *tm_prof_begin(const char *name, hipStream_t st) {
+uint64_t tm_prof_pass() {
+    ProfState &P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    return ++P.next_pass;
+}
+
+void *tm_prof_begin(const char *name, hipStream_t st, uint64_t pass) {
     ProfState &P = prof();
     {
         std::lock_guard<std::mutex> lk(P.mu);
         if (!P.on) return nullptr;
     }
-    ProfEvent *e = new (std::nothrow) ProfEvent{name, nullptr, nullptr};
+    ProfEvent *e = new (std::nothrow) ProfEvent{name, nullptr, nullptr, pass};
     if (!e) return nullptr;
     if (hipEventCreate(&e->a) != hipSuccess || hipEventCreate(&e->b) != hipSuccess ||
         hipEventRecord(e->a, st) != hipSuccess) {
@@ -64,18 +72,29 @@ void tm_prof_end(void *token, hipStream_t st) {
 void tm_prof_collect() {
     ProfState &P = prof();
     std::lock_guard<std::mutex> lk(P.mu);
+    // longest kernel of each pass
+    std::map<uint64_t, std::pair<double, const char *>> crit;
     for (ProfEvent &e : P.pending) {
         float ms = 0.f;
         if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
             auto &t = P.total[e.name];
             t.first += ms;
             t.second += 1;
+            if (e.pass) {
+                auto &c = crit[e.pass];
+                if (!c.second || ms > c.first) c = {ms, e.name};
+            }
         }
         (void)hipGetLastError();
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
     }
     P.pending.clear();
+    for (auto &kv : crit) {
+        auto &t = P.total[std::string("crit:") + kv.second.second];
+        t.first += kv.second.first;
+        t.second += 1;
+    }
 }
 
 tm_status tm_sweep_census_impl(const tm_graph *g, int64_t delta, int64_t s, int64_t L, double p, uint64_t seed,

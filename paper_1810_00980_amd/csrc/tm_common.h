@@ -140,6 +140,8 @@ struct tm_graph {
 // One cache line per slot: the key and, inline, what a lookup in the pair
 // needs (a copy of its PairMeta and its size), so that finding a pair and
 // reading its metadata is one access.
+// Lookups read the first 48 bytes as three 16-byte vectors, so the field
+// order and offsets are fixed (static_asserts below).
 struct __attribute__((aligned(64))) PairSlot {
     uint64_t key;
     int64_t t0, base, boff;  // as in PairMeta
@@ -147,6 +149,10 @@ struct __attribute__((aligned(64))) PairSlot {
     int32_t shift, nb;       // as in PairMeta
     uint32_t n;              // number of entries
 };
+static_assert(offsetof(PairSlot, t0) == 8 && offsetof(PairSlot, base) == 16 && offsetof(PairSlot, boff) == 24 &&
+                  offsetof(PairSlot, id) == 32 && offsetof(PairSlot, shift) == 36 && offsetof(PairSlot, nb) == 40 &&
+                  offsetof(PairSlot, n) == 44 && sizeof(PairSlot) == 64,
+              "PairSlot layout is read as three 16-byte vectors");
 
 constexpr int64_t TM_PAIR_BUCKET_DENSITY = 4;
 
@@ -154,6 +160,7 @@ struct __attribute__((aligned(8))) PairBucket {
     uint32_t idx;  // first entry at or after the bucket's start (relative)
     uint32_t c0;   // a -> b edges before that entry
 };
+static_assert(sizeof(PairBucket) == 8, "two adjacent buckets are read as one 16-byte load");
 
 struct __attribute__((aligned(16))) PairEnt {
     int64_t t;     // time (LLONG_MAX in the sentinel)
@@ -304,8 +311,12 @@ tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask, int mode, int64_t del
 // Opt-in kernel timing with HIP events recorded on the launch stream.
 // tm_prof_begin returns a token (nullptr when profiling is off) that
 // tm_prof_end closes; tm_prof_collect resolves finished events into the
-// per-kernel totals (call after the stream has been synchronised).
-void *tm_prof_begin(const char *name, hipStream_t st);
+// per-kernel totals (call after the stream has been synchronised).  Kernels
+// that run concurrently as one pass share a nonzero pass id (tm_prof_pass);
+// the longest of them, the one the pass waits for, is also credited under
+// "crit:<name>".
+uint64_t tm_prof_pass();
+void *tm_prof_begin(const char *name, hipStream_t st, uint64_t pass = 0);
 void tm_prof_end(void *token, hipStream_t st);
 void tm_prof_collect();
 

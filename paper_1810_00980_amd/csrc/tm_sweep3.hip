@@ -207,11 +207,12 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, hipStr
         TM_HIP(hipEventRecord(side->fork, st));
         for (int k = 1; k < nl; ++k) TM_HIP(hipStreamWaitEvent(side->s[k - 1], side->fork, 0));
     }
+    const uint64_t pass = tm_prof_pass();
     for (int k = 0; k < nl; ++k) {
         hipStream_t sk = (k == 0 || !side) ? st : side->s[k - 1];
         SweepArgs b = a;
         b.counter = a.counter + todo[k].kind;
-        void *tok = tm_prof_begin(names[MODE][todo[k].kind], sk);
+        void *tok = tm_prof_begin(names[MODE][todo[k].kind], sk, pass);
         if (todo[k].kind == 0)
             hipLaunchKernelGGL((k_sweep3<MODE, true, 7u>), dim3((unsigned)nb), dim3(SW_TPB), 0, sk, G, b);
         else if (todo[k].kind == 2)

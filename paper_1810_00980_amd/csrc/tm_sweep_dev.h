@@ -84,19 +84,24 @@ __device__ inline int64_t pair_lower(const DevGraph &G, const PairMeta &m, const
         *be = n;
         return n;
     }
-    const PairBucket b0 = bk[b], b1 = bk[b + 1];
-    *be = b1.idx;
-    if (b0.idx == b1.idx) {
-        *c0 = b0.c0;
-        return b0.idx;
-    }
-    int64_t lo = b0.idx, hi = b1.idx;
+    // buckets b and b + 1 in one 16-byte load
+    PairBucket bb[2];
+    __builtin_memcpy(bb, bk + b, sizeof bb);
+    *be = bb[1].idx;
+    int64_t lo = bb[0].idx, hi = bb[1].idx;
+    // c: the a -> b count before entry hi, taken from the bucket or from the
+    // last entry the search stepped back to (whole entries are loaded)
+    int64_t c = lo == hi ? (int64_t)bb[0].c0 : (int64_t)bb[1].c0;
     while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (en[mid].t < t) lo = mid + 1;
-        else hi = mid;
+        // branch-free step, so that the entry's time and count arrive in one load
+        const int64_t mid = (lo + hi) >> 1;
+        const PairEnt q = en[mid];
+        const bool before = q.t < t;
+        lo = before ? mid + 1 : lo;
+        hi = before ? hi : mid;
+        c = before ? c : q.c0;
     }
-    *c0 = lo == (int64_t)b1.idx ? (int64_t)b1.c0 : en[lo].c0;
+    *c0 = c;
     return lo;
 }
 
@@ -151,22 +156,32 @@ __device__ inline int32_t pair_find(const DevGraph &G, uint32_t u, uint32_t v, P
     uint64_t key = ((uint64_t)a << 32) | b;
     int64_t cap = G.ph_cap;
     uint64_t h = tm_pair_hash(key, cap);
-    for (int64_t probe = 0; probe < cap; ++probe) {
-        const PairSlot sl = G.ph_slot[h];
-        if (sl.key == key) {
-            pv.m.t0 = sl.t0;
-            pv.m.base = sl.base;
-            pv.m.boff = sl.boff;
-            pv.m.shift = sl.shift;
-            pv.m.nb = sl.nb;
-            pv.en = G.up_ent + sl.base;
-            pv.n = sl.n;
-            return sl.id;
-        }
-        if (sl.key == ~0ull) return -1;
+    // the slot's 48 bytes of fields as three 16-byte loads issued together;
+    // the first probe's fields flow to the result, so none waits for the key
+    const uint4 *q = reinterpret_cast<const uint4 *>(G.ph_slot + h);
+    uint4 q0 = q[0], q1 = q[1], q2 = q[2];
+    // an empty statement that takes the fields as inputs keeps the compiler
+    // from sinking their loads behind the key comparison (no code emitted)
+    __asm__ volatile("" ::"v"(q1.x), "v"(q1.y), "v"(q1.z), "v"(q1.w), "v"(q2.x), "v"(q2.y), "v"(q2.z), "v"(q2.w),
+                     "v"(q0.z), "v"(q0.w));
+    uint64_t skey = ((uint64_t)q0.y << 32) | q0.x;
+    for (int64_t probe = 1; skey != key && skey != ~0ull && probe < cap; ++probe) {  // collisions (rare)
         h = (h + 1) & (uint64_t)(cap - 1);
+        q = reinterpret_cast<const uint4 *>(G.ph_slot + h);
+        q0 = q[0];
+        q1 = q[1];
+        q2 = q[2];
+        skey = ((uint64_t)q0.y << 32) | q0.x;
     }
-    return -1;
+    if (skey != key) return -1;
+    pv.m.t0 = (int64_t)(((uint64_t)q0.w << 32) | q0.z);
+    pv.m.base = (int64_t)(((uint64_t)q1.y << 32) | q1.x);
+    pv.m.boff = (int64_t)(((uint64_t)q1.w << 32) | q1.z);
+    pv.m.shift = (int32_t)q2.y;
+    pv.m.nb = (int32_t)q2.z;
+    pv.en = G.up_ent + pv.m.base;
+    pv.n = q2.w;
+    return (int32_t)q2.x;
 }
 
 // Per-lane accumulator of up to 16 motif codes.
