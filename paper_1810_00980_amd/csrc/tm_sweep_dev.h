@@ -105,6 +105,89 @@ __device__ inline int64_t pair_lower(const DevGraph &G, const PairMeta &m, const
     return lo;
 }
 
+// Two lower bounds in one pair with their search steps interleaved, so that
+// both searches' loads are in flight together.  r[s] = {index, a -> b count
+// before it, bucket end, time of the entry at the index when below the end}.
+__device__ inline void pair_lower2(const DevGraph &G, const PairMeta &m, const PairEnt *en, int64_t n, int64_t tA,
+                                   int64_t tB, int64_t r[2][4]) {
+    const PairBucket *bk = G.pbk + m.boff;
+    const int64_t t[2] = {tA, tB};
+    int64_t lo[2], hi[2], c[2], th[2], be[2];
+    bool early[2], past[2];
+    PairBucket bb[2][2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        early[s] = t[s] <= m.t0;
+        const int64_t b = early[s] ? 0 : (t[s] - m.t0) >> m.shift;
+        past[s] = !early[s] && b >= m.nb;
+        __builtin_memcpy(bb[s], bk + (past[s] ? m.nb - 1 : b), sizeof bb[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        if (early[s]) {
+            lo[s] = hi[s] = 0;
+            c[s] = 0;
+            be[s] = n;
+            th[s] = m.t0;
+        } else if (past[s]) {
+            lo[s] = hi[s] = n;
+            c[s] = bb[s][1].c0;
+            be[s] = n;
+            th[s] = 0;
+        } else {
+            lo[s] = bb[s][0].idx;
+            hi[s] = bb[s][1].idx;
+            c[s] = lo[s] == hi[s] ? (int64_t)bb[s][0].c0 : (int64_t)bb[s][1].c0;
+            be[s] = hi[s];
+            th[s] = 0;
+        }
+    }
+    while (lo[0] < hi[0] || lo[1] < hi[1]) {
+        PairEnt q[2];
+        int64_t mid[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            mid[s] = (lo[s] + hi[s]) >> 1;  // lo when done: an entry or the sentinel
+            q[s] = en[mid[s]];
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const bool act = lo[s] < hi[s];
+            const bool before = q[s].t < t[s];
+            lo[s] = (act && before) ? mid[s] + 1 : lo[s];
+            hi[s] = (act && !before) ? mid[s] : hi[s];
+            c[s] = (act && !before) ? q[s].c0 : c[s];
+            th[s] = (act && !before) ? q[s].t : th[s];
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        r[s][0] = lo[s];
+        r[s][1] = c[s];
+        r[s][2] = be[s];
+        r[s][3] = th[s];
+    }
+}
+
+// Counts of a pair's entries before t and up to t from t's lower bound r
+// (one row of pair_lower2): the entries equal to t, all in t's bucket and
+// usually none, are stepped over.
+__device__ inline void pair_at_from(const PairEnt *en, const int64_t r[4], int64_t t, int64_t c_lt[2],
+                                    int64_t c_le[2]) {
+    const int64_t lo = r[0], be = r[2];
+    int64_t k = r[1];
+    c_lt[0] = k;
+    c_lt[1] = lo - k;
+    int64_t e = lo;
+    if (e < be && r[3] == t) {  // the search read entry lo
+        ++e;
+        while (e < be && en[e].t == t) ++e;
+    }
+    if (e != lo) k = en[e].c0;
+    c_le[0] = k;
+    c_le[1] = e - k;
+}
+
 // One pair held in registers for repeated lookups.
 struct PairView {
     PairMeta m;
@@ -133,19 +216,6 @@ struct PairView {
         }
         c[0] = k;
         c[1] = e - k;
-    }
-    // both: one bucket lookup, then the entries equal to t (all in t's
-    // bucket, usually none) are stepped over
-    __device__ void at(const DevGraph &G, int64_t t, int64_t c_lt[2], int64_t c_le[2]) const {
-        int64_t k, be;
-        int64_t lo = pair_lower(G, m, en, n, t, &k, &be);
-        c_lt[0] = k;
-        c_lt[1] = lo - k;
-        int64_t e = lo;
-        while (e < be && en[e].t == t) ++e;
-        if (e != lo) k = en[e].c0;
-        c_le[0] = k;
-        c_le[1] = e - k;
     }
 };
 
@@ -313,9 +383,16 @@ __device__ inline void tri_rank(const DevGraph &G, uint32_t yi, uint32_t di, int
         C.yc = yj;
         C.p = pair_find(G, yi, yj, C.pv);
         if (C.p >= 0) {
-            int64_t a0[2], a1[2], h1[2];
-            C.pv.at(G, ti, a0, a1);
-            C.pv.le(G, hi, h1);
+            // counts at ti and up to hi, their lower bounds searched together
+            int64_t a0[2], a1[2], h1[2], r[2][4];
+            pair_lower2(G, C.pv.m, C.pv.en, C.pv.n, ti, hi == LLONG_MAX ? hi : hi + 1, r);
+            pair_at_from(C.pv.en, r[0], ti, a0, a1);
+            if (hi == LLONG_MAX) {  // every entry
+                r[1][0] = C.pv.n;
+                r[1][1] = C.pv.en[C.pv.n].c0;
+            }
+            h1[0] = r[1][1];
+            h1[1] = r[1][0] - r[1][1];
             for (int q = 0; q < 2; ++q) {
                 C.f_ti[q] = (int32_t)a0[q];
                 C.f_ti1[q] = (int32_t)a1[q];
@@ -327,8 +404,14 @@ __device__ inline void tri_rank(const DevGraph &G, uint32_t yi, uint32_t di, int
     int64_t lo3 = (tj < LLONG_MIN + delta) ? LLONG_MIN : tj - delta;
     lo3 = lo3 > lo_win ? lo3 : lo_win;
     int64_t f_tj[2], f_tj1[2], f_lo3[2];
-    C.pv.at(G, tj, f_tj, f_tj1);
-    C.pv.lt(G, lo3, f_lo3);
+    {
+        // the lower bounds of tj and lo3 searched together
+        int64_t r[2][4];
+        pair_lower2(G, C.pv.m, C.pv.en, C.pv.n, tj, lo3, r);
+        pair_at_from(C.pv.en, r[0], tj, f_tj, f_tj1);
+        f_lo3[0] = r[1][1];
+        f_lo3[1] = r[1][0] - r[1][1];
+    }
     const uint32_t sw = yi > yj ? 1u : 0u;  // index of yi -> yj in the pair's counts
 #pragma unroll
     for (uint32_t dir = 0; dir < 2; ++dir) {  // dir 0: yi -> yj, 1: yj -> yi
