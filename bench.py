@@ -366,13 +366,15 @@ def sweep_bytes(exact, ests, tables):
     return out
 
 
-def sweep_roofline(exact, ests, kern, crit, steps, tables):
+def sweep_roofline(exact, ests, kern, crit, alone, steps, tables):
     """Roofline entry of the dominant sweep kernel, with the achieved
     algorithmic GB/s of every sweep kernel beside it.  The kernels of one
     pass run concurrently on forked streams and share the CUs, so each one's
-    duration spans most of the pass; the dominant kernel is the one with the
-    most time on the critical path, i.e. summed over the passes it was the
-    last of its pass to finish (crit)."""
+    duration in the timed steps spans most of the pass.  The dominant kernel
+    is the one with the most time per step when each kernel of a pass runs
+    alone (alone: one untimed step with the library's serial timing mode);
+    its achieved rate uses its average launch duration in the timed steps.
+    crit: per kernel, the time of the passes it was the last to finish."""
     bps = sweep_bytes(exact, ests, tables)  # algorithmic bytes per step
     timed = {k: v for k, v in kern.items() if k in bps and v[1] > 0}
     if not timed:
@@ -382,14 +384,15 @@ def sweep_roofline(exact, ests, kern, crit, steps, tables):
         per[k] = {"launches_per_step": n / steps, "avg_launch_ms": ms / n,
                   "algorithmic_bytes_per_launch": bps[k] * steps / n,
                   "achieved_GBs": bps[k] * steps / (ms / 1e3) / 1e9}
-    dom = max(timed, key=lambda k: (crit.get(k, (0.0, 0))[0], timed[k][0]))
+    dom = max(timed, key=lambda k: (alone.get(k, (0.0, 0))[0], timed[k][0]))
     ach = per[dom]["achieved_GBs"]
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "traffic": traffic_record(dom), "kernel": dom, "avg_launch_ms": per[dom]["avg_launch_ms"],
             "launches": timed[dom][1], "algorithmic_bytes_per_launch": per[dom]["algorithmic_bytes_per_launch"],
             "census": {"exact": exact, "estimates": ests}, "sweep_kernels": per,
             "sweep_kernels_ms_per_step": {k: v[0] / steps for k, v in kern.items()},
-            "critical_path_ms_per_step": {k: v[0] / steps for k, v in crit.items() if v[1] > 0}}
+            "critical_path_ms_per_step": {k: v[0] / steps for k, v in crit.items() if v[1] > 0},
+            "alone_ms_per_step": {k: v[0] for k, v in alone.items() if v[1] > 0}}
 
 
 def main():
@@ -455,6 +458,15 @@ def main():
     for i in range(args.warmup):
         step(None)
         log("warmup", i)
+    # one untimed step with each pass's kernels run one after another, which
+    # gives every kernel's own duration (this decides the dominant kernel)
+    tm.profile_reset()
+    tm.profile_enable(True, serial=True)
+    step(None)
+    torch.cuda.synchronize()
+    tm.profile_enable(False)
+    alone = {k: tm.profile_read(k) for k in SWEEP_KERNELS}
+    log("serial step done")
     tm.profile_reset()
     tm.profile_enable(True)
     times = {"load": [], "exact": [], "est": []}
@@ -475,7 +487,7 @@ def main():
     ests = [tm.sweep_census_est(G, delta, c, p, 0) for c, p in W["est"]]
     tables = G.exact_table_bytes > 0
     G.free()
-    roofline = sweep_roofline(census, ests, kern, crit, args.steps, tables)
+    roofline = sweep_roofline(census, ests, kern, crit, alone, args.steps, tables)
     if roofline:
         roofline["exact_tables"] = tables
     out = {

@@ -296,7 +296,10 @@ void tm_server_destroy(tm_server *s);
  * the longest of them, which the pass waits for, is also credited under
  * "crit:<name>" (one launch per pass).  tm_profile_read returns the total
  * milliseconds and the number of launches so far (zeros for a name never
- * timed).
+ * timed).  on = 2 also runs the kernels of each pass one after another on
+ * the caller's stream (a diagnostic: each duration is then the kernel's own,
+ * and a pass takes longer); on = 1 times without changing how kernels run,
+ * 0 stops timing.  Other values: TM_EINVAL.
  */
 tm_status tm_profile_enable(int32_t on);
 tm_status tm_profile_reset(void);

@@ -308,8 +308,10 @@ def estimate_batch(g: Graph, edges, delta: int, c: int, p: float, seeds, tile: i
     return est, [kc[i].value() for i in range(k)]
 
 
-def profile_enable(on: bool = True):
-    _check(_lib.tm_profile_enable(1 if on else 0), "tm_profile_enable")
+def profile_enable(on: bool = True, serial: bool = False):
+    """Kernel timing on/off; serial=True also runs the kernels of each sweep
+    pass one after another, so that each duration is the kernel's own."""
+    _check(_lib.tm_profile_enable((2 if serial else 1) if on else 0), "tm_profile_enable")
 
 
 def profile_reset():

@@ -22,6 +22,7 @@ struct ProfEvent {
 struct ProfState {
     std::mutex mu;
     bool on = false;
+    bool serial = false;
     std::vector<ProfEvent> pending;
     std::map<std::string, std::pair<double, int64_t>> total;
     uint64_t next_pass = 0;
@@ -31,6 +32,12 @@ ProfState &prof() {
     return s;
 }
 }  // namespace
+
+bool tm_prof_serial() {
+    ProfState &P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    return P.on && P.serial;
+}
 
 uint64_t tm_prof_pass() {
     ProfState &P = prof();
@@ -770,7 +777,9 @@ extern "C" tm_status tm_count_window(const tm_graph *g, int32_t n_motifs, const 
 extern "C" tm_status tm_profile_enable(int32_t on) {
     ProfState &P = prof();
     std::lock_guard<std::mutex> lk(P.mu);
+    if (on < 0 || on > 2) return TM_EINVAL;
     P.on = on != 0;
+    P.serial = on == 2;
     return TM_OK;
 }
 

@@ -316,6 +316,10 @@ tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask, int mode, int64_t del
 // the longest of them, the one the pass waits for, is also credited under
 // "crit:<name>".
 uint64_t tm_prof_pass();
+// true while timing runs in serial mode (tm_profile_enable(2)): the kernels
+// of a pass then run one after another on the caller's stream, so that each
+// one's duration is its own
+bool tm_prof_serial();
 void *tm_prof_begin(const char *name, hipStream_t st, uint64_t pass = 0);
 void tm_prof_end(void *token, hipStream_t st);
 void tm_prof_collect();

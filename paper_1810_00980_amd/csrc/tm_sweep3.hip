@@ -202,7 +202,7 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, hipStr
     if (fwd && (a.want_fwd & 7u)) todo[nl++] = {0};
     if (bwd) todo[nl++] = {1};
     if (nl == 0) return TM_OK;
-    SideStreams *side = nl > 1 ? side_streams(dev) : nullptr;
+    SideStreams *side = (nl > 1 && !tm_prof_serial()) ? side_streams(dev) : nullptr;
     if (side) {
         TM_HIP(hipEventRecord(side->fork, st));
         for (int k = 1; k < nl; ++k) TM_HIP(hipStreamWaitEvent(side->s[k - 1], side->fork, 0));
