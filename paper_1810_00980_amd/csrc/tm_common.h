@@ -115,8 +115,8 @@ struct tm_graph {
     DevBuf ph_slot;  // PairSlot[ph_cap]
     int64_t ph_cap = 0;
     // per unordered pair time buckets: bucket b of pair p covers times
-    // [t_first + b 2^shift, t_first + (b+1) 2^shift), about
-    // TM_PAIR_BUCKET_DENSITY buckets per entry; pbk holds, per bucket, the
+    // [t_first + b 2^shift, t_first + (b+1) 2^shift), the widest buckets
+    // with at most TM_PAIR_BUCKET_DENSITY per entry; pbk holds, per bucket, the
     // index (relative to the pair's first entry) of its first entry and the
     // a -> b edges before it, plus a sentinel bucket (size, a -> b total), so
     // that a time in an empty bucket is answered without reading entries
@@ -154,7 +154,7 @@ static_assert(offsetof(PairSlot, t0) == 8 && offsetof(PairSlot, base) == 16 && o
                   offsetof(PairSlot, n) == 44 && sizeof(PairSlot) == 64,
               "PairSlot layout is read as three 16-byte vectors");
 
-constexpr int64_t TM_PAIR_BUCKET_DENSITY = 4;
+constexpr int64_t TM_PAIR_BUCKET_DENSITY = 8;
 
 struct __attribute__((aligned(8))) PairBucket {
     uint32_t idx;  // first entry at or after the bucket's start (relative)

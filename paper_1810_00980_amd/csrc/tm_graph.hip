@@ -331,7 +331,7 @@ __global__ void k_pair_meta_pack(const int64_t *up_beg, const int64_t *tfirst, c
     pm[p] = m;
 }
 
-// per pair: first time, bucket shift (about TM_PAIR_BUCKET_DENSITY buckets per entry), count
+// per pair: first time, bucket shift (at most TM_PAIR_BUCKET_DENSITY buckets per entry), count
 __global__ void k_pair_bucket_meta(const int64_t *up_beg, const PairEnt *ent, int64_t U, int64_t *tfirst,
                                    int32_t *meta, int64_t *nbk) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
