@@ -133,7 +133,11 @@ def _check(rc: int, what: str):
 
 
 def _stream(stream=None):
+    """A HIP stream handle: an integer handle, a torch stream, or (None) torch's
+    current stream when torch has a GPU, else the null stream."""
     if stream is not None:
+        if hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
         return ctypes.c_void_p(int(stream))
     try:
         import torch

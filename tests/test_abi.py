@@ -87,3 +87,17 @@ def test_product_code_does_not_use_the_oracle():
             if fn.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in txt and "tm_oracle" not in txt and "orc_" not in txt, fn
+
+
+def test_profile_modes_host_side(lib):
+    """Timing switches: 0 off, 1 on, 2 on with each pass's kernels in series;
+    anything else is rejected; a name never timed reads as zero launches."""
+    assert lib.tm_profile_enable(3) == 1  # TM_EINVAL
+    assert lib.tm_profile_enable(-1) == 1
+    for on in (2, 1, 0):
+        assert lib.tm_profile_enable(on) == 0
+    assert lib.tm_profile_reset() == 0
+    ms, n = ctypes.c_double(-1.0), ctypes.c_int64(-1)
+    assert lib.tm_profile_read(b"crit:sweep3_tri_count", ctypes.byref(ms), ctypes.byref(n)) == 0
+    assert (ms.value, n.value) == (0.0, 0)
+    assert lib.tm_profile_read(None, ctypes.byref(ms), ctypes.byref(n)) == 1

@@ -193,6 +193,36 @@ def test_sweep_estimates_all_three_edge_motifs(tm):
                 g.src, g.dst, g.t, M, delta, c, p, seed)["Z"])
 
 
+SWEEP_NAMES = ("sweep3_fwd_count", "sweep3_tri_count", "sweep3_bwd_count",
+               "sweep3_fwd_weight", "sweep3_tri_weight", "sweep3_bwd_weight")
+
+
+def test_serial_timing_mode_same_results(tm):
+    """The serial timing mode (each pass's kernels one after another) changes
+    how kernels run, never what they compute; in either mode every pass
+    credits exactly one kernel as the one it waited for."""
+    g = ti.random_small_graph(6, 1200, 6000, 47, allow_self_loops=True)
+    say("serial_timing")
+    G = load(tm, g)
+    runs = []
+    try:
+        for serial in (False, True):
+            tm.profile_reset()
+            tm.profile_enable(True, serial=serial)
+            exact = tm.count_exact_multi(G, THREE, 40)
+            est, kept = tm.estimate_multi(G, THREE, 40, 3, 0.5, 2)
+            tm.profile_enable(False)
+            crit = sum(tm.profile_read("crit:" + k)[1] for k in SWEEP_NAMES)
+            assert crit == 2, (serial, crit)  # one exact pass, one estimate pass
+            assert all(tm.profile_read(k)[1] == 1 for k in SWEEP_NAMES), serial
+            runs.append((exact, est, kept))
+    finally:
+        tm.profile_enable(False)
+    assert runs[0] == runs[1]
+    for M, c in list(zip(THREE, runs[0][0]))[::7]:
+        assert c == oracle.count(g.src, g.dst, g.t, M, 40, hist=False)[0], M
+
+
 def test_count_window(tm):
     g = ti.random_small_graph(7, 1500, 8000, 43, allow_self_loops=True)
     say("count_window")
