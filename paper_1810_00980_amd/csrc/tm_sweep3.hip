@@ -42,9 +42,9 @@ namespace {
 using namespace sweepdev;
 
 // resident waves per SIMD asked of the compiler: the exact triangle sweep is
-// latency-bound and two registers above five waves (192 -> 176 ms on the
-// 10M-edge graph with a 12-byte spill); the weighted one gained nothing from
-// a sixth wave
+// latency-bound and would otherwise settle a few registers above five waves
+// (it fits in 93 VGPRs at five); the weighted one, at five waves by itself,
+// gained nothing from a sixth
 template <int MODE, bool FWD, unsigned CLS>
 constexpr int sweep_waves() {
     return (MODE == MODE_COUNT && FWD && CLS == 8u) ? 5 : 1;
