@@ -425,6 +425,76 @@ __device__ inline void tri_rank(const DevGraph &G, uint32_t yi, uint32_t di, int
     }
 }
 
+// Window scans read U list entries at a time: their times and endpoint
+// words load together, then the duration weights of those within the
+// horizon are gathered together, so that one memory latency covers U
+// entries instead of two per entry; the entries are then visited in order.
+// Indices are clamped to the list, so no load leaves it.  (The weighted
+// triangle sweep gains too, though it drops from five resident waves to
+// four: zipf10m at c 30, p 0.1, 91 -> 84 ms.)
+constexpr int SCAN_U = 4;
+
+// forward: entries j = first, first + 1, ... < end (times tv, endpoint words
+// ndv) with time <= hi; visit(t, nd, w) with w = the weight of duration
+// t - t0 (WEIGHT mode)
+template <int MODE, int U, class F>
+__device__ inline void scan_up(const int64_t *tv, const uint32_t *ndv, const SweepArgs &a, int64_t first, int64_t end,
+                               int64_t t0, int64_t hi, F &&visit) {
+    for (int64_t j = first; j < end; j += U) {
+        int64_t tq[U];
+        uint32_t nq[U];
+        uint64_t wq[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = j + u < end ? j + u : end - 1;
+            tq[u] = j + u < end ? tv[k] : LLONG_MAX;
+            nq[u] = ndv[k];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            wq[u] = 0;
+            if constexpr (MODE == MODE_WEIGHT) {
+                if (tq[u] <= hi) wq[u] = weight_of<MODE>(a, tq[u] - t0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (tq[u] > hi) return;
+            visit(tq[u], nq[u], wq[u]);
+        }
+    }
+}
+
+// backward: entries i = last, last - 1, ... >= beg with time >= lo;
+// visit(t, nd, w) with w = the weight of duration t0 - t (WEIGHT mode)
+template <int MODE, int U, class F>
+__device__ inline void scan_down(const DevGraph &G, const SweepArgs &a, int64_t last, int64_t beg, int64_t t0,
+                                 int64_t lo, F &&visit) {
+    for (int64_t i = last; i >= beg; i -= U) {
+        int64_t tq[U];
+        uint32_t nq[U];
+        uint64_t wq[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = i - u >= beg ? i - u : beg;
+            tq[u] = i - u >= beg ? G.inc_t[k] : LLONG_MIN;
+            nq[u] = G.inc_nd[k];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            wq[u] = 0;
+            if constexpr (MODE == MODE_WEIGHT) {
+                if (tq[u] >= lo) wq[u] = weight_of<MODE>(a, t0 - tq[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (tq[u] < lo) return;
+            visit(tq[u], nq[u], wq[u]);
+        }
+    }
+}
+
 // forward sweep of one anchor (codes 0..27); CLS (1 two-node, 2 star B,
 // 4 star A, 8 triangle) fixes at compile time which classes the kernel can
 // count, so that a kernel keeps registers only for its own accumulators
@@ -448,20 +518,15 @@ __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t 
     uint64_t cs0 = 0, cs1 = 0, ca0 = 0, ca1 = 0;  // middles before the current time group
     uint64_t ps0 = 0, ps1 = 0, pa0 = 0, pa1 = 0;  // entries of the current time group
     int64_t tg = t1;
-    for (int64_t j = i + 1; j < end; ++j) {
-        int64_t tj = G.inc_t[j];
-        if (tj > hi) break;
-        if (tj == t1) continue;
+    scan_up<MODE, SCAN_U>(G.inc_t, G.inc_nd, a, i + 1, end, t1, hi, [&](int64_t tj, uint32_t nd, uint64_t w) {
+        if (tj == t1) return;
         if (tj != tg) {
             cs0 += ps0; cs1 += ps1; ca0 += pa0; ca1 += pa1;
             ps0 = ps1 = pa0 = pa1 = 0;
             tg = tj;
         }
-        uint32_t nd = G.inc_nd[j];
         uint32_t yj = nd & 0x7FFFFFFFu, dj = nd >> 31;
         int64_t dlt = tj - t1;
-        uint64_t w = 0;
-        if constexpr (MODE == MODE_WEIGHT) w = weight_of<MODE>(a, dlt);
         if (yj == y1) {
             if (two) {
                 acc_add<MODE, 16>(A, 0, dj, cs0, w, a.hist, 0, dlt, a.delta);
@@ -502,7 +567,7 @@ __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t 
             }
         }
         if (dj) ++pa1; else ++pa0;
-    }
+    });
     int codes[16];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -818,21 +883,16 @@ __device__ inline void sweep_bwd(const DevGraph &G, const SweepArgs &a, int64_t 
     A.clear();
     uint64_t cs0 = 0, cs1 = 0, ps0 = 0, ps1 = 0;
     int64_t tg = t3;
-    for (int64_t i = jj - 1; i >= beg; --i) {
-        int64_t ti = G.inc_t[i];
-        if (ti < lo) break;
-        if (ti == t3) continue;
+    scan_down<MODE, SCAN_U>(G, a, jj - 1, beg, t3, lo, [&](int64_t ti, uint32_t nd, uint64_t w) {
+        if (ti == t3) return;
         if (ti != tg) {
             cs0 += ps0; cs1 += ps1;
             ps0 = ps1 = 0;
             tg = ti;
         }
-        uint32_t nd = G.inc_nd[i];
         uint32_t yi = nd & 0x7FFFFFFFu, di = nd >> 31;
         if (yi != y3) {
             int64_t dlt = t3 - ti;
-            uint64_t w = 0;
-            if constexpr (MODE == MODE_WEIGHT) w = weight_of<MODE>(a, dlt);
             // code 28 + 4*d1 + 2*d2 + d3, kept in slot 2*d2 + d1
             if constexpr (MODE == MODE_HIST) {
                 if (cs0) {
@@ -849,7 +909,7 @@ __device__ inline void sweep_bwd(const DevGraph &G, const SweepArgs &a, int64_t 
         } else {
             if (di) ++ps1; else ++ps0;
         }
-    }
+    });
     int codes[4];
     // slot (2*d2 + d1) -> code 28 + 4*d1 + 2*d2 + d3
     codes[0] = 28 + 0 + 0 + (int)d3;  // d2=0,d1=0
