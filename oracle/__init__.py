@@ -6,9 +6,10 @@ paper_1810_00980_amd/ never does, and this package imports nothing from it.
 
 Three independent pieces:
 
-* ``count``/``count_anchors``/``estimate``/``weight`` wrap the plain C brute
-  force in ``tm_oracle.c`` (time-ordered backtracking over all later edges;
-  Algorithm 1 of Sec. 4 with one shift and q_j = p).
+* ``count``/``count_anchors``/``estimate``/``estimate_q``/``weight`` wrap the
+  plain C brute force in ``tm_oracle.c`` (time-ordered backtracking over all
+  later edges; Algorithm 1 of Sec. 4 with one shift and q_j = p, and with b
+  shifts and the edge-proportional q_j of equation heuristic_q).
 * ``brute`` is a second, structurally different brute force in pure Python:
   it tries every ordered l-tuple of distinct edges (tiny graphs only) and,
   for the window identities, every shift s in {-c delta + 1, ..., 0}.
@@ -68,6 +69,9 @@ def _load():
         lib.orc_estimate.argtypes = [i64, P, P, P, i32, P, P, i64, i64, f64, u64, i64,
                                      P, P, P, P, P, i64, P, P]
         lib.orc_estimate.restype = i32
+        lib.orc_estimate_q.argtypes = [i64, P, P, P, i32, P, P, i64, i64, f64, i32, u64, i64,
+                                       P, P, P, P, P, i64, P]
+        lib.orc_estimate_q.restype = i32
         _lib = lib
     return _lib
 
@@ -173,6 +177,30 @@ def estimate(src, dst, t, motif, delta, c, p, seed, force_shift=None, kept_cap=1
     n = min(nk.value, kept_cap)
     return {"s": s.value, "J": J.value, "n_kept": nk.value, "kept": kept[:n].copy(),
             "win_counts": wc[:n].copy(), "hist": h, "Z": z.value, "L": int(c) * int(delta)}
+
+
+def estimate_q(src, dst, t, motif, delta, c, r, b, seed, force_shift=None, cap=1 << 16):
+    """Algorithm 1 with b shifts and the edge-proportional sampling
+    probabilities of Sec. 4 (q_j = min(1, r |T_j| / |T|)).  Returns a dict
+    with the estimate Z (mean over shifts) and, per kept window in order of
+    (shift k, window j), arrays k, j, q and the weighted count y = Y_{s,j}."""
+    lib = _load()
+    src, dst, t = _edges(src, dst, t)
+    ms, md = _motif(motif)
+    nk = ctypes.c_int64()
+    wk = np.zeros(cap, dtype=np.int64)
+    wj = np.zeros(cap, dtype=np.int64)
+    wq = np.zeros(cap, dtype=np.float64)
+    wy = np.zeros(cap, dtype=np.float64)
+    z = ctypes.c_double()
+    fs = INT64_MIN if force_shift is None else int(force_shift)
+    rc = lib.orc_estimate_q(src.shape[0], _ptr(src), _ptr(dst), _ptr(t), len(motif), _ptr(ms), _ptr(md),
+                            int(delta), int(c), float(r), int(b), int(seed), fs, ctypes.byref(nk),
+                            _ptr(wk), _ptr(wj), _ptr(wq), _ptr(wy), cap, ctypes.byref(z))
+    _check(rc)
+    n = min(nk.value, cap)
+    return {"Z": z.value, "n_kept": nk.value, "k": wk[:n].copy(), "j": wj[:n].copy(), "q": wq[:n].copy(),
+            "y": wy[:n].copy(), "L": int(c) * int(delta)}
 
 
 # ---------------------------------------------------------------- tier B

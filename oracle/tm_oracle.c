@@ -375,3 +375,113 @@ int orc_estimate(int64_t m, const int32_t *src, const int32_t *dst, const int64_
     free(own);
     return rc;
 }
+
+/* ------------------------------------------------- edge-proportional q_j */
+
+/* Neumaier step: sum += x with the running compensation comp. */
+static void neu_add(double *sum, double *comp, double x) {
+    double s2 = *sum + x;
+    if (fabs(*sum) >= fabs(x)) *comp += (*sum - s2) + x;
+    else *comp += (x - s2) + *sum;
+    *sum = s2;
+}
+
+static int cmp_i64(const void *a, const void *b) {
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* number of sorted values in [lo, hi] */
+static int64_t count_in(const int64_t *v, int64_t n, int64_t lo, int64_t hi) {
+    int64_t a = 0, b = n;
+    while (a < b) { int64_t mid = a + (b - a) / 2; if (v[mid] < lo) a = mid + 1; else b = mid; }
+    int64_t first = a;
+    a = first; b = n;
+    while (a < b) { int64_t mid = a + (b - a) / 2; if (v[mid] <= hi) a = mid + 1; else b = mid; }
+    return a - first;
+}
+
+/*
+ * Algorithm 1 with b shifts and the sampling probabilities the paper uses
+ * (Sec. 4, "Choosing the sampling probabilities", equation heuristic_q):
+ * q_j proportional to the number of temporal edges in window I_j,
+ * q_j = min(1, r |T_j| / |T|), where |T| = m counts every edge of the graph
+ * and a q_j above 1 is clamped (the sum stays unbiased with the clamped
+ * value).  For shift k = 0 .. b-1: s_k from the draw (0, k, domain 0) (or
+ * force_shift), window j kept when the uniform from draw (j, k, domain 1) is
+ * below q_j; a kept window adds Y_{s,j} / q_j to Z_k, where
+ * Y_{s,j} = sum over its instances of 1 / (1 - Delta / (c delta)) (the
+ * weighted count w(I_j) of Sec. 4), taken from the window's own duration
+ * histogram in ascending Delta.  Z = (1/b) sum_k Z_k.  Sums over Delta, over
+ * kept windows (ascending j) and over shifts use Neumaier compensation.
+ *
+ * Outputs: *nkept_out (over all shifts); for the first cap kept windows, in
+ * order of (k, j): win_k, win_j (1-based), win_q, win_y (any may be NULL);
+ * *Z_out.
+ */
+int orc_estimate_q(int64_t m, const int32_t *src, const int32_t *dst, const int64_t *t,
+                   int l, const int32_t *ms, const int32_t *md, int64_t delta,
+                   int64_t cwin, double r, int32_t b, uint64_t seed, int64_t force_shift,
+                   int64_t *nkept_out, int64_t *win_k, int64_t *win_j, double *win_q,
+                   double *win_y, int64_t cap, double *Z_out) {
+    int k;
+    if (m < 0 || delta < 1 || cwin < 2 || !(r > 0.0) || b < 1 || !motif_ok(l, ms, md, &k))
+        return ORC_EINVAL;
+    if (delta > INT64_MAX / cwin) return ORC_EINVAL;
+    const int64_t L = cwin * delta;
+    int64_t *tn = (int64_t *)malloc((size_t)(m ? m : 1) * sizeof(int64_t));
+    int64_t *ts = (int64_t *)malloc((size_t)(m ? m : 1) * sizeof(int64_t));
+    uint64_t *h = (uint64_t *)calloc((size_t)delta + 1, sizeof(uint64_t));
+    if (!tn || !ts || !h) { free(tn); free(ts); free(h); return ORC_ENOMEM; }
+    int64_t tmin = 0, tmax = 0;
+    for (int64_t i = 0; i < m; ++i)
+        if (i == 0 || t[i] < tmin) tmin = t[i];
+    for (int64_t i = 0; i < m; ++i) {
+        tn[i] = t[i] - tmin;
+        if (tn[i] > tmax) tmax = tn[i];
+        ts[i] = tn[i];
+    }
+    qsort(ts, (size_t)m, sizeof(int64_t), cmp_i64);
+    if (force_shift != INT64_MIN && (force_shift > 0 || force_shift <= -L)) {
+        free(tn); free(ts); free(h);
+        return ORC_EINVAL;
+    }
+    const int64_t J = 1 + (tmax / L) + ((tmax % L) ? 1 : 0);
+    int rc = ORC_OK;
+    int64_t nkept = 0;
+    double zsum = 0.0, zcomp = 0.0;
+    for (int32_t kk = 0; kk < b; ++kk) {
+        int64_t s = force_shift;
+        if (force_shift == INT64_MIN) s = -(int64_t)(orc_draw(seed, 0, (uint32_t)kk, 0) % (uint64_t)L);
+        double zk = 0.0, zkc = 0.0;
+        for (int64_t j = 1; j <= J; ++j) {
+            const int64_t lo = s + (j - 1) * L, hi = s + j * L - 1;
+            const int64_t tj = count_in(ts, m, lo, hi);
+            double q = r * (double)tj / (double)(m ? m : 1);
+            if (q > 1.0) q = 1.0;
+            const uint64_t x = orc_draw(seed, (uint64_t)j, (uint32_t)kk, 1);
+            const double u = (double)(x >> 11) * (1.0 / 9007199254740992.0);
+            if (!(u < q)) continue;
+            memset(h, 0, ((size_t)delta + 1) * sizeof(uint64_t));
+            uint64_t cl, ch;
+            int rr = orc_count(m, src, dst, tn, l, ms, md, delta, lo, hi, h, &cl, &ch);
+            if (rr != ORC_OK) rc = rr;
+            const double y = orc_weight(h, NULL, delta, L, 1.0);
+            neu_add(&zk, &zkc, y / q);
+            if (nkept < cap) {
+                if (win_k) win_k[nkept] = kk;
+                if (win_j) win_j[nkept] = j;
+                if (win_q) win_q[nkept] = q;
+                if (win_y) win_y[nkept] = y;
+            }
+            ++nkept;
+        }
+        neu_add(&zsum, &zcomp, zk + zkc);
+    }
+    *nkept_out = nkept;
+    *Z_out = (zsum + zcomp) / (double)b;
+    free(tn);
+    free(ts);
+    free(h);
+    return rc;
+}

@@ -379,3 +379,107 @@ def test_estimator_unbiased_over_1000_seeds():
                    for seed in range(1000)])
     se = zs.std(ddof=1) / math.sqrt(len(zs))
     assert abs(zs.mean() - CM) < 3 * se
+
+
+# ------------------------------------------- edge-proportional q_j (Sec. 4)
+
+def _window_edge_counts(t, shift, L):
+    tn = np.asarray(t, dtype=np.int64) - int(np.min(t))
+    J = 1 + -(-int(tn.max()) // L)
+    return [int(((tn >= shift + (j - 1) * L) & (tn <= shift + j * L - 1)).sum()) for j in range(1, J + 1)]
+
+
+def test_q_all_windows_kept_equals_p1():
+    """With r so large that every non-empty window has q_j = 1, the
+    edge-proportional estimate of one shift is ||Y_s||_1, the p = 1
+    estimate of the same shift."""
+    g = ti.config_small_dense(3)
+    for seed in (0, 5):
+        zq = oracle.estimate_q(g.src, g.dst, g.t, ti.TRIANGLE, 3600, 30, 1e12, 1, seed)
+        zp = oracle.estimate(g.src, g.dst, g.t, ti.TRIANGLE, 3600, 30, 1.0, seed)
+        assert np.all(zq["q"] == 1.0)
+        assert abs(zq["Z"] - zp["Z"]) <= 1e-12 * zp["Z"]
+        assert abs(zq["y"].sum() - zp["Z"]) <= 1e-12 * zp["Z"]
+
+
+def test_q_window_weights_equal_tuple_brute_force():
+    """Each kept window's Y_{s,j} equals the weighted count w(I_j) of Sec. 4
+    computed exactly from the tier-B brute force restricted to the window."""
+    g = ti.random_small_graph(5, 40, 300, 31)
+    edges = list(zip(g.src.tolist(), g.dst.tolist(), g.t.tolist()))
+    s_, d_, t_ = arr(edges)
+    delta, c, shift = 20, 3, -17
+    L = c * delta
+    tmin = min(e[2] for e in edges)
+    en = [(u, v, tt - tmin) for (u, v, tt) in edges]
+    for motif in (ti.TRIANGLE, ti.TWO_NODE_ALT, ((0, 1), (0, 2), (0, 1))):
+        r = oracle.estimate_q(s_, d_, t_, motif, delta, c, 1e12, 1, 0, force_shift=shift)
+        assert r["n_kept"] > 0
+        for j, y in zip(r["j"], r["y"]):
+            h = oracle.brute(en, motif, delta, win=(shift + (j - 1) * L, shift + j * L - 1))
+            exact = sum((Fraction(n * L, L - dd) for dd, n in h.items()), Fraction(0))
+            assert abs(Fraction(y) - exact) <= Fraction(1, 10 ** 12) * max(exact, Fraction(1))
+
+
+def test_q_probabilities_follow_window_edge_counts():
+    """q_j = min(1, r |T_j| / |T|) with |T_j| counted from the times alone."""
+    g = ti.config_small_dense(4)
+    delta, c, r = 3600, 30, 1.5
+    L = c * delta
+    shift = -12345
+    counts = _window_edge_counts(g.t, shift, L)
+    res = oracle.estimate_q(g.src, g.dst, g.t, ti.TRIANGLE, delta, c, r, 1, 7, force_shift=shift)
+    assert res["n_kept"] > 0
+    for j, q in zip(res["j"], res["q"]):
+        assert q == min(1.0, r * counts[j - 1] / g.m)
+
+
+def test_q_conditional_mean_and_variance():
+    """Lemma var_Zs with unequal q_j: with the shift fixed, E[Z | s] =
+    ||Y_s||_1 and Var[Z | s] = sum_j Y_{s,j}^2 (1/q_j - 1); per-window
+    weights from the counting oracle, q_j from the window edge counts,
+    against 3000 seeds."""
+    g = ti.random_small_graph(4, 70, 400, 9)
+    s_, d_, t_ = g.src, g.dst, g.t
+    delta, c, r, shift = 15, 2, 6.0, -7
+    L = c * delta
+    tn = t_ - int(t_.min())
+    counts = _window_edge_counts(t_, shift, L)
+    ys, qs = [], []
+    for j in range(1, len(counts) + 1):
+        _, h = oracle.count(s_, d_, tn, ti.TWO_NODE_ALT, delta, win=(shift + (j - 1) * L, shift + j * L - 1))
+        ys.append(float(sum(Fraction(int(n) * L, L - dd) for dd, n in enumerate(h) if n)))
+        qs.append(min(1.0, r * counts[j - 1] / g.m))
+    ynorm = sum(ys)
+    var_cf = sum(y * y * (1 / q - 1) for y, q in zip(ys, qs) if q > 0)
+    assert var_cf > 0 and len(set(qs)) > 2
+    zs = np.array([oracle.estimate_q(s_, d_, t_, ti.TWO_NODE_ALT, delta, c, r, 1, seed, force_shift=shift)["Z"]
+                   for seed in range(3000)])
+    assert abs(zs.mean() - ynorm) < 4 * math.sqrt(var_cf / len(zs))
+    assert abs(zs.var() / var_cf - 1) < 0.12
+
+
+def test_q_several_shifts_average():
+    """Algorithm 1 returns the mean of the b per-shift sums; each shift k
+    draws its own s and its own window uniforms."""
+    g = ti.config_small_dense(1)
+    res = oracle.estimate_q(g.src, g.dst, g.t, ti.TRIANGLE, 3600, 30, 2.0, 4, 11)
+    per_k = [float(sum(y / q for k, y, q in zip(res["k"], res["y"], res["q"]) if k == kk)) for kk in range(4)]
+    assert abs(res["Z"] - sum(per_k) / 4) <= 1e-12 * res["Z"]
+    # the shifts differ: the kept window sets of the four shifts are not all equal
+    sets = [tuple(res["j"][res["k"] == kk]) for kk in range(4)]
+    assert len(set(sets)) > 1
+
+
+@pytest.mark.slow
+def test_q_estimator_unbiased_over_seeds():
+    """Mean over 600 seeds of the b = 2, r = 2 estimate lies within 3
+    standard errors of the exact count (unbiasedness of Sec. 4 with
+    arbitrary q_j)."""
+    g = ti.config_small_dense()
+    delta, c = 3600, 30
+    CM, _ = oracle.count(g.src, g.dst, g.t, ti.TRIANGLE, delta, hist=False)
+    zs = np.array([oracle.estimate_q(g.src, g.dst, g.t, ti.TRIANGLE, delta, c, 2.0, 2, seed)["Z"]
+                   for seed in range(600)])
+    se = zs.std(ddof=1) / math.sqrt(len(zs))
+    assert abs(zs.mean() - CM) < 3 * se
