@@ -197,6 +197,38 @@ tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, const tm_motif 
                             tm_u128 *kept_counts, void *hip_stream);
 
 /*
+ * Algorithm 1 of Sec. 4 with b shifts and the window probabilities the paper
+ * uses (equation heuristic_q): window j of shift k is kept with probability
+ * q_j = min(1, r |T_j| / |T|), where |T_j| counts the edges (self-loops
+ * included) whose normalised time lies in I_j and |T| = m; a q_j above 1 is
+ * clamped, which keeps the estimate unbiased.  A kept window adds
+ * Y_{s,j} / q_j, Y_{s,j} being its weighted count w(I_j) (the sum over its
+ * instances of 1 / (1 - Delta / (c delta))), and the estimate is the mean
+ * over the b shifts.  Shift k takes its shift from draw (0, k, domain 0)
+ * and its window uniforms from draws (j, k, domain 1) of the seed's
+ * Philox4x32-10 stream, so shift 0 is tm_estimate's shift.
+ * Motifs: three-edge motifs only (TM_EUNSUPPORTED otherwise), n_motifs >= 1.
+ * delta >= 1, c >= 2, r > 0 and finite, b >= 1.  estimates: host array of
+ * n_motifs.  info (nullable, host memory, caller-owned): n_kept (out) = the
+ * kept windows over all shifts; with cap > 0 the first cap of them, in order
+ * of (k, j), are described in win_k[cap], win_j[cap] (1-based), win_q[cap]
+ * and win_y[cap * n_motifs] (one row per window: Y_{s,j} of each motif).
+ * Errors: TM_EINVAL (bad arguments, or null info arrays with cap > 0),
+ * TM_EUNSUPPORTED (a motif without three edges, more than 2^30 windows),
+ * TM_ENOMEM, TM_EDEVICE.  Outputs are written only on TM_OK.
+ */
+typedef struct {
+    int64_t n_kept;
+    int64_t cap;
+    int64_t *win_k;
+    int64_t *win_j;
+    double *win_q;
+    double *win_y;
+} tm_q_info;
+tm_status tm_estimate_q(const tm_graph *g, int32_t n_motifs, const tm_motif *motifs, int64_t delta, int64_t c,
+                        double r, int32_t b, uint64_t seed, double *estimates, tm_q_info *info, void *hip_stream);
+
+/*
  * Batched estimator: n_seeds independent estimates of one motif (each seed
  * draws its own shift and window samples, Algorithm 1's loop over shifts run
  * as separate estimators); estimates[k] equals tm_estimate with seeds[k].

@@ -65,6 +65,11 @@ class EstInfo(ctypes.Structure):
                 ("win_counts", ctypes.c_void_p), ("hist_lo", ctypes.c_void_p), ("hist_hi", ctypes.c_void_p)]
 
 
+class QInfo(ctypes.Structure):
+    _fields_ = [("n_kept", ctypes.c_int64), ("cap", ctypes.c_int64), ("win_k", ctypes.c_void_p),
+                ("win_j", ctypes.c_void_p), ("win_q", ctypes.c_void_p), ("win_y", ctypes.c_void_p)]
+
+
 class Query(ctypes.Structure):
     _fields_ = [("graph", ctypes.c_int32), ("kind", ctypes.c_int32), ("motif", Motif), ("delta", ctypes.c_int64),
                 ("c", ctypes.c_int64), ("p", ctypes.c_double), ("seed", ctypes.c_uint64)]
@@ -98,6 +103,7 @@ _SIGS = {
     "tm_count_window": [P, i32, P, i64, i64, i64, P, P],
     "tm_estimate": [P, P, i64, i64, f64, u64, P, P, P],
     "tm_estimate_multi": [P, i32, P, i64, i64, f64, u64, P, P, P],
+    "tm_estimate_q": [P, i32, P, i64, i64, f64, i32, u64, P, P, P],
     "tm_estimate_batch": [P, P, i64, i64, f64, i32, P, i32, P, P, P],
     "tm_batch_config": [P, P, i64, i64, f64, P, P, P],
     "tm_batch_release": [P, P],
@@ -299,6 +305,26 @@ def estimate_multi(g: Graph, motifs, delta: int, c: int, p: float, seed: int, st
     _check(_lib.tm_estimate_multi(g.handle, k, arr, int(delta), int(c), float(p), int(seed), est, kc,
                                   _stream(stream)), "tm_estimate_multi")
     return [est[i] for i in range(k)], [kc[i].value() for i in range(k)]
+
+
+def estimate_q(g: Graph, motifs, delta: int, c: int, r: float, b: int, seed: int, cap: int = 4096, stream=None):
+    """Algorithm 1 with b shifts and window probabilities q_j = min(1, r |T_j| / |T|)
+    (three-edge motifs).  Returns (estimates, windows): windows holds, for the
+    first `cap` kept windows in order of (shift, window), arrays k, j, q and
+    y (Y_{s,j} per motif, shape [windows, motifs]), and n_kept over all shifts."""
+    k = len(motifs)
+    arr = (Motif * max(k, 1))(*[motif(m) for m in motifs])
+    est = (ctypes.c_double * max(k, 1))()
+    wk = np.zeros(max(cap, 1), dtype=np.int64)
+    wj = np.zeros(max(cap, 1), dtype=np.int64)
+    wq = np.zeros(max(cap, 1), dtype=np.float64)
+    wy = np.zeros((max(cap, 1), max(k, 1)), dtype=np.float64)
+    info = QInfo(0, int(cap), wk.ctypes.data, wj.ctypes.data, wq.ctypes.data, wy.ctypes.data)
+    _check(_lib.tm_estimate_q(g.handle, k, arr, int(delta), int(c), float(r), int(b), int(seed), est,
+                              ctypes.byref(info), _stream(stream)), "tm_estimate_q")
+    n = min(info.n_kept, cap)
+    return [est[i] for i in range(k)], {"n_kept": info.n_kept, "k": wk[:n].copy(), "j": wj[:n].copy(),
+                                        "q": wq[:n].copy(), "y": wy[:n, :k].copy()}
 
 
 def estimate_batch(g: Graph, edges, delta: int, c: int, p: float, seeds, tile: int = 0, stream=None):

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <new>
@@ -293,6 +294,45 @@ tm_status select_kept(const tm_graph *g, int64_t L, uint64_t seed, double p, hip
     return TM_OK;
 }
 
+// Edge-proportional window probabilities (Sec. 4, equation heuristic_q) for
+// shift s of estimator k: window j = 1 .. J gets its edge count from two
+// searches of the sorted times, q_j = min(1, r count / m) (a q_j above 1 is
+// clamped), and is kept when the uniform of draw (j, k, domain 1) is below
+// q_j.  flag[j-1], q[j-1].
+__global__ void k_q_windows(const int64_t *es_t, int64_t m, int64_t J, int64_t s, int64_t L, double r,
+                            uint64_t seed, uint32_t k, int64_t *flag, double *q) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (j > J) return;
+    const int64_t lo = s + (j - 1) * L, hi = s + j * L - 1;
+    int64_t a = 0, b = m;
+    while (a < b) {
+        const int64_t mid = (a + b) >> 1;
+        if (es_t[mid] < lo) a = mid + 1;
+        else b = mid;
+    }
+    const int64_t first = a;
+    b = m;
+    while (a < b) {
+        const int64_t mid = (a + b) >> 1;
+        if (es_t[mid] <= hi) a = mid + 1;
+        else b = mid;
+    }
+    double qj = r * (double)(a - first) / (double)m;
+    if (qj > 1.0) qj = 1.0;
+    const uint64_t x = tm_draw(seed, (uint64_t)j, k, 1);
+    const double u = (double)(x >> 11) * (1.0 / 9007199254740992.0);
+    flag[j - 1] = u < qj ? 1 : 0;
+    q[j - 1] = qj;
+}
+
+// kidx[j] = rank of window j among the kept ones (scan: exclusive sums of
+// the flags), -1 when not kept; kidx[0] is unused
+__global__ void k_q_kidx(const int64_t *flag, const int64_t *scan, int64_t J, int32_t *kidx) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (j == 1) kidx[0] = -1;
+    if (j <= J) kidx[j] = flag[j - 1] ? (int32_t)scan[j - 1] : -1;
+}
+
 tm_status check_est_args(const tm_graph *g, int64_t delta, int64_t c, double p, int64_t *L) {
     if (!g || delta < 1 || c < 2 || !(p > 0.0 && p <= 1.0)) return TM_EINVAL;
     if (delta > INT64_MAX / c) return TM_EINVAL;
@@ -422,14 +462,15 @@ thread_local SweepWs t_ws;
 
 tm_status run_sweep(const tm_graph *g, uint64_t mask, int mode, int64_t delta, int windowed, int64_t s, int64_t L,
                     uint64_t seed, double p, SweepOut *out, const std::vector<int> &hist_codes,
-                    std::vector<uint64_t> *hist_host, hipStream_t st) {
+                    std::vector<uint64_t> *hist_host, hipStream_t st, const int32_t *kidx = nullptr,
+                    uint64_t *win = nullptr) {
     DevBuf &o = t_ws.o, &h = t_ws.h, &w = t_ws.w, &ctr = t_ws.ctr;
     TM_TRY(o.reserve(36 * 4 * 8));
     TM_TRY(ctr.reserve(64));
     if (mode == 2) TM_TRY(h.reserve((size_t)36 * (delta + 1) * 16));
     if (mode == 1) TM_TRY(w.reserve((size_t)(delta + 1) * 8));
     TM_TRY(tm_sweep3(g, mask, mode, delta, windowed, s, L, seed, p, o.as<uint64_t>(), h.as<uint64_t>(),
-                     w.as<uint64_t>(), ctr.as<int64_t>(), st));
+                     w.as<uint64_t>(), ctr.as<int64_t>(), st, kidx, win));
     TM_HIP(hipMemcpyAsync(out->v, o.p, sizeof out->v, hipMemcpyDeviceToHost, st));
     if (mode == 2 && hist_host) {
         hist_host->assign(hist_codes.size() * (size_t)(delta + 1) * 2, 0);
@@ -477,6 +518,106 @@ tm_status sweep_estimates(const tm_graph *g, int32_t n, const tm_motif *motifs, 
         if (kept) {
             kept[i].lo = v[0];
             kept[i].hi = v[1];
+        }
+    }
+    return TM_OK;
+}
+
+static void neumaier_add(double &sum, double &comp, double x) {
+    const double t = sum + x;
+    if (std::fabs(sum) >= std::fabs(x)) comp += (sum - t) + x;
+    else comp += (x - t) + sum;
+    sum = t;
+}
+
+// Algorithm 1 (Sec. 4) with b shifts and edge-proportional window
+// probabilities, for 3-edge motifs through the sweep.  Per shift: window
+// flags and q_j on the device, one sweep whose anchors add their exact
+// fixed-point sums into their kept window's slot, then on the host
+// Z_k = sum over kept windows (ascending j) of Y_{s,j} / q_j with
+// Y_{s,j} = weight sum / 2^52; the estimate is the mean of the Z_k.
+tm_status estimate_q_impl(const tm_graph *g, int32_t n, const tm_motif *motifs, int64_t delta, int64_t c, double r,
+                          int32_t b, uint64_t seed, double *est, tm_q_info *info, hipStream_t st) {
+    if (!g || n < 1 || !motifs || !est || !(r > 0.0) || !std::isfinite(r) || b < 1) return TM_EINVAL;
+    if (info && info->cap > 0 && (!info->win_k || !info->win_j || !info->win_q || !info->win_y)) return TM_EINVAL;
+    int64_t L;
+    TM_TRY(check_est_args(g, delta, c, 1.0, &L));
+    std::vector<int> codes;
+    uint64_t mask;
+    if (!all_sweep_codes(n, motifs, &codes, &mask)) return TM_EUNSUPPORTED;
+    const int64_t J = 1 + (g->t_span + L - 1) / L;
+    if (J > ((int64_t)1 << 30)) return TM_EUNSUPPORTED;
+    std::vector<double> zs(n, 0.0), zc(n, 0.0);
+    int64_t n_kept = 0;
+    const int64_t cap = info ? info->cap : 0;
+    std::vector<int64_t> rk, rj;  // window records, copied to info only on success
+    std::vector<double> rq, ry;
+    if (g->m > 0) {
+        DevBuf flag, scan, qd, kidx, tot, win;
+        TM_TRY(flag.alloc((size_t)J * 8));
+        TM_TRY(scan.alloc((size_t)J * 8));
+        TM_TRY(qd.alloc((size_t)J * 8));
+        TM_TRY(kidx.alloc((size_t)(J + 1) * 4));
+        TM_TRY(tot.alloc(8));
+        std::vector<int64_t> flag_h((size_t)J);
+        std::vector<double> q_h((size_t)J);
+        std::vector<uint64_t> win_h;
+        for (int32_t k = 0; k < b; ++k) {
+            const int64_t s = -(int64_t)(tm_draw(seed, 0, (uint32_t)k, 0) % (uint64_t)L);
+            hipLaunchKernelGGL(k_q_windows, dim3(tm_blocks(J, TPB)), dim3(TPB), 0, st, g->es_t.as<int64_t>(), g->m,
+                               J, s, L, r, seed, (uint32_t)k, flag.as<int64_t>(), qd.as<double>());
+            TM_HIP(hipGetLastError());
+            TM_HIP(hipMemcpyAsync(scan.p, flag.p, (size_t)J * 8, hipMemcpyDeviceToDevice, st));
+            TM_TRY(tm_scan_i64(scan.as<int64_t>(), J, tot.as<int64_t>(), st));
+            hipLaunchKernelGGL(k_q_kidx, dim3(tm_blocks(J, TPB)), dim3(TPB), 0, st, flag.as<int64_t>(),
+                               scan.as<int64_t>(), J, kidx.as<int32_t>());
+            TM_HIP(hipGetLastError());
+            int64_t K = 0;
+            TM_HIP(hipMemcpyAsync(&K, tot.p, 8, hipMemcpyDeviceToHost, st));
+            TM_HIP(hipMemcpyAsync(flag_h.data(), flag.p, (size_t)J * 8, hipMemcpyDeviceToHost, st));
+            TM_HIP(hipMemcpyAsync(q_h.data(), qd.p, (size_t)J * 8, hipMemcpyDeviceToHost, st));
+            TM_HIP(hipStreamSynchronize(st));
+            std::vector<double> zk(n, 0.0), zkc(n, 0.0);
+            if (K > 0) {
+                TM_TRY(win.reserve((size_t)K * 144 * 8));
+                TM_HIP(hipMemsetAsync(win.p, 0, (size_t)K * 144 * 8, st));
+                SweepOut so;
+                TM_TRY(run_sweep(g, mask, 1, delta, 3, s, L, seed, 1.0, &so, {}, nullptr, st, kidx.as<int32_t>(),
+                                 win.as<uint64_t>()));
+                win_h.resize((size_t)K * 144);
+                TM_HIP(hipMemcpyAsync(win_h.data(), win.p, (size_t)K * 144 * 8, hipMemcpyDeviceToHost, st));
+                TM_HIP(hipStreamSynchronize(st));
+                int64_t kk = 0;
+                for (int64_t j = 1; j <= J; ++j) {
+                    if (!flag_h[(size_t)j - 1]) continue;
+                    const double q = q_h[(size_t)j - 1];
+                    const bool rec = n_kept < cap;
+                    for (int32_t i = 0; i < n; ++i) {
+                        const uint64_t *v = win_h.data() + (size_t)kk * 144 + 4 * (size_t)codes[(size_t)i];
+                        const double y = u128_scaled(v[2], v[3], 1.0 / 4503599627370496.0);
+                        neumaier_add(zk[(size_t)i], zkc[(size_t)i], y / q);
+                        if (rec) ry.push_back(y);
+                    }
+                    if (rec) {
+                        rk.push_back(k);
+                        rj.push_back(j);
+                        rq.push_back(q);
+                    }
+                    ++kk;
+                    ++n_kept;
+                }
+            }
+            for (int32_t i = 0; i < n; ++i) neumaier_add(zs[(size_t)i], zc[(size_t)i], zk[(size_t)i] + zkc[(size_t)i]);
+        }
+    }
+    for (int32_t i = 0; i < n; ++i) est[i] = (zs[(size_t)i] + zc[(size_t)i]) / (double)b;
+    if (info) {
+        info->n_kept = n_kept;
+        for (size_t w = 0; w < rk.size(); ++w) {
+            info->win_k[w] = rk[w];
+            info->win_j[w] = rj[w];
+            info->win_q[w] = rq[w];
+            for (int32_t i = 0; i < n; ++i) info->win_y[w * (size_t)n + i] = ry[w * (size_t)n + i];
         }
     }
     return TM_OK;
@@ -632,6 +773,13 @@ extern "C" tm_status tm_estimate(const tm_graph *g, const tm_motif *M, int64_t d
         return finish(sweep_estimates(g, 1, M, delta, c, p, seed, estimate, nullptr, st), st);
     }
     return finish(estimate_impl(g, M, delta, c, p, seed, estimate, info, st), st);
+}
+
+extern "C" tm_status tm_estimate_q(const tm_graph *g, int32_t n_motifs, const tm_motif *motifs, int64_t delta,
+                                   int64_t c, double r, int32_t b, uint64_t seed, double *estimates, tm_q_info *info,
+                                   void *hip_stream) {
+    hipStream_t st = (hipStream_t)hip_stream;
+    return finish(estimate_q_impl(g, n_motifs, motifs, delta, c, r, b, seed, estimates, info, st), st);
 }
 
 extern "C" tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, const tm_motif *motifs, int64_t delta,

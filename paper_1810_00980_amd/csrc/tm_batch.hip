@@ -165,6 +165,8 @@ __global__ void __launch_bounds__(BT_TPB) k_batch_sweep(DevGraph G, BatchArgs a)
             sa.counter = nullptr;
             sa.want_fwd = a.want_fwd;
             sa.n_entries = 0;
+            sa.kidx = nullptr;
+            sa.win = nullptr;
             OneCode one{a.code, 0, 0, 0, 0};
             for (int64_t i = e0 + lane; i < e1; i += TM_WAVE) {
                 uint32_t nd = G.inc_nd[i];
@@ -227,6 +229,8 @@ __global__ void __launch_bounds__(BT_TPB) k_anchor_vals(DevGraph G, BatchArgs a,
     sa.counter = nullptr;
     sa.want_fwd = a.want_fwd;
     sa.n_entries = 0;
+    sa.kidx = nullptr;
+    sa.win = nullptr;
     while (true) {
         int64_t base = 0;
         if (lane == 0) base = (int64_t)atomicAdd(counter, (unsigned long long)TM_WAVE);

@@ -296,12 +296,16 @@ int tm_sweep_code_of(const tm_motif *M);  // -1 when M is not one of them
 // Sweep counter.  mode 0: counts; 1: counts and fixed-point weighted sums
 // (weights round(2^52 L / (L - Delta)) written to wfx_dev); 2: counts and
 // duration histograms (hist_dev: 36 x (delta+1) x {lo, hi}).  out_dev:
-// 36 x {count lo, count hi, weight lo, weight hi}.  windowed: only anchors in
-// windows kept by (seed, p) under shift s and window length L.
-// counter_dev: 2 int64 work-queue heads.
+// 36 x {count lo, count hi, weight lo, weight hi}.  windowed: 0 every anchor;
+// 1 anchors in windows kept by (seed, p) under shift s and window length L;
+// 2 anchors in the one window [s, L]; 3 anchors in windows j (shift s,
+// length L) with kidx_dev[j] >= 0, whose sums go to the window's own slot
+// win_dev + 144 kidx_dev[j] (same layout as out_dev) instead of out_dev.
+// counter_dev: 8 int64 work-queue heads.
 tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask, int mode, int64_t delta, int windowed, int64_t s,
                     int64_t L, uint64_t seed, double p, uint64_t *out_dev, uint64_t *hist_dev, uint64_t *wfx_dev,
-                    int64_t *counter_dev, hipStream_t st);
+                    int64_t *counter_dev, hipStream_t st, const int32_t *kidx_dev = nullptr,
+                    uint64_t *win_dev = nullptr);
 
 // Largest delta for the sweep counter's histogram mode (36 histograms).
 #define TM_MAX_SWEEP_HIST_DELTA ((int64_t)1 << 20)

@@ -77,6 +77,7 @@ k_sweep3(DevGraph G, SweepArgs a) {
             int64_t t = tv[i];
             bool go = true;
             int64_t wlo = LLONG_MIN, whi = LLONG_MAX;
+            unsigned long long *acc = lds;  // where this anchor's sums go
             if (a.windowed == 1) {
                 int64_t j = (t - a.s) / a.L + 1;
                 go = keep_window(a.seed, (uint64_t)j, a.p);
@@ -86,25 +87,32 @@ k_sweep3(DevGraph G, SweepArgs a) {
                 wlo = a.s;
                 whi = a.L;
                 go = t >= wlo && t <= whi;
+            } else if (a.windowed == 3) {
+                int64_t j = (t - a.s) / a.L + 1;
+                const int32_t kk = a.kidx[j];
+                go = kk >= 0;
+                wlo = a.s + (j - 1) * a.L;
+                whi = a.s + j * a.L - 1;
+                if (go) acc = (unsigned long long *)(a.win + (int64_t)kk * 36 * 4);
             }
             if (go) {
                 if (FWD) {
                     int64_t hi = (t > LLONG_MAX - a.delta) ? LLONG_MAX : t + a.delta;
                     hi = hi < whi ? hi : whi;
-                    if constexpr (RANKED) sweep_tri_ranked(G, a, i, le, y, d, t, hi, wlo, lds);
+                    if constexpr (RANKED) sweep_tri_ranked(G, a, i, le, y, d, t, hi, wlo, acc);
                     else if constexpr (MODE == MODE_COUNT) {
-                        if (G.has_ex) sweep_fwd_prefix(G, a, i, lb, le, (uint32_t)x, y, d, t, hi, lds);
-                        else sweep_fwd_count(G, a, i, le, y, d, t, hi, lds);
+                        if (G.has_ex) sweep_fwd_prefix(G, a, i, lb, le, (uint32_t)x, y, d, t, hi, acc);
+                        else sweep_fwd_count(G, a, i, le, y, d, t, hi, acc);
                     }
-                    else sweep_fwd<MODE, CLS>(G, a, i, le, y, d, t, hi, wlo, lds);
+                    else sweep_fwd<MODE, CLS>(G, a, i, le, y, d, t, hi, wlo, acc);
                 } else {
                     int64_t lo = (t < LLONG_MIN + a.delta) ? LLONG_MIN : t - a.delta;
                     lo = lo > wlo ? lo : wlo;
                     if constexpr (MODE == MODE_COUNT) {
-                        if (G.has_ex) sweep_bwd_prefix(G, i, lb, (uint32_t)x, y, d, t, lo, lds);
-                        else sweep_bwd_count(G, i, lb, y, d, t, lo, lds);
+                        if (G.has_ex) sweep_bwd_prefix(G, i, lb, (uint32_t)x, y, d, t, lo, acc);
+                        else sweep_bwd_count(G, i, lb, y, d, t, lo, acc);
                     }
-                    else sweep_bwd<MODE>(G, a, i, lb, y, d, t, lo, lds);
+                    else sweep_bwd<MODE>(G, a, i, lb, y, d, t, lo, acc);
                 }
             }
         }
@@ -464,8 +472,11 @@ int tm_sweep_code_of(const tm_motif *M) {
 // hist_dev: 36 x (delta+1) x 2 u64 (mode 2), zeroed here.
 tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask_lo, int mode, int64_t delta, int windowed, int64_t s,
                     int64_t L, uint64_t seed, double p, uint64_t *out_dev, uint64_t *hist_dev, uint64_t *wfx_dev,
-                    int64_t *counter_dev, hipStream_t st) {
+                    int64_t *counter_dev, hipStream_t st, const int32_t *kidx_dev, uint64_t *win_dev) {
+    if (windowed == 3 && (!kidx_dev || !win_dev)) return TM_EINVAL;
     SweepArgs a;
+    a.kidx = kidx_dev;
+    a.win = win_dev;
     a.delta = delta;
     a.windowed = windowed;
     a.s = s;

@@ -17,7 +17,8 @@ enum : int { MODE_COUNT = 0, MODE_WEIGHT = 1, MODE_HIST = 2 };
 struct SweepArgs {
     int64_t delta;
     // windows (estimate): anchor kept when its window's draw is below p
-    int32_t windowed;      // 0 none, 1 kept windows of (s, L, seed, p), 2 one window [s, L]
+    int32_t windowed;      // 0 none, 1 kept windows of (s, L, seed, p), 2 one window [s, L],
+                           // 3 windows with kidx[j] >= 0, summed per window into win
     int64_t s, L;
     uint64_t seed;
     double p;
@@ -27,6 +28,8 @@ struct SweepArgs {
     int64_t *counter;      // work queue head
     uint32_t want_fwd;     // bit mask: 1 two-node, 2 star B, 4 star A, 8 triangle
     int64_t n_entries;
+    const int32_t *kidx;   // windowed 3: kept index of window j (j = 1 .. J), -1 when not kept
+    uint64_t *win;         // windowed 3: per kept window, 36 x {count lo, hi, weight lo, hi}
 };
 
 __device__ inline void philox10_d(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3, uint32_t k0, uint32_t k1) {

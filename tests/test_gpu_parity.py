@@ -193,6 +193,58 @@ def test_sweep_estimates_all_three_edge_motifs(tm):
                 g.src, g.dst, g.t, M, delta, c, p, seed)["Z"])
 
 
+def test_estimate_q_matches_oracle(tm):
+    """Algorithm 1 with b shifts and edge-proportional window probabilities
+    (equation heuristic_q): the kept windows (shift, window, q_j) are the
+    oracle's exactly; each window's weighted count Y_{s,j} and every motif's
+    estimate agree within 1e-12."""
+    cases = [
+        (ti.random_small_graph(6, 1200, 6000, 51, allow_self_loops=True), 40, 3, 4.0, 3, 5, THREE),
+        (ti.config_small_dense(2), 3600, 10, 8.0, 2, 9, THREE[::6]),
+        (ti.random_small_graph(8, 3000, 20000, 52), 60, 2, 1e12, 1, 1, THREE[::5]),
+    ]
+    for g, delta, c, r, b, seed, motifs in cases:
+        say("estimate_q", g.m, delta, c, r, b, seed)
+        G = load(tm, g)
+        est, win = tm.estimate_q(G, motifs, delta, c, r, b, seed)
+        assert win["n_kept"] > 0
+        for i, M in enumerate(motifs):
+            o = oracle.estimate_q(g.src, g.dst, g.t, M, delta, c, r, b, seed)
+            assert close(est[i], o["Z"]), (M, est[i], o["Z"])
+            assert win["n_kept"] == o["n_kept"]
+            assert np.array_equal(win["k"], o["k"]) and np.array_equal(win["j"], o["j"])
+            assert np.array_equal(win["q"], o["q"])
+            for y, yo in zip(win["y"][:, i], o["y"]):
+                assert close(y, yo), (M, y, yo)
+    # every non-empty window kept (r huge) with one shift: the p = 1 estimate
+    g = ti.random_small_graph(7, 900, 4000, 53)
+    G = load(tm, g)
+    est, _ = tm.estimate_q(G, THREE, 30, 3, 1e12, 1, 4)
+    est1, _ = tm.estimate_multi(G, THREE, 30, 3, 1.0, 4)
+    for a, b_ in zip(est, est1):
+        assert close(a, b_)
+
+
+def test_estimate_q_edge_cases(tm):
+    g = ti.random_small_graph(5, 200, 1000, 54)
+    G = load(tm, g)
+    est, win = tm.estimate_q(G, THREE[:3], 20, 3, 2.0, 2, 0, cap=0)
+    assert win["n_kept"] >= 0 and len(win["k"]) == 0
+    est2, _ = tm.estimate_q(G, THREE[:3], 20, 3, 2.0, 2, 0)
+    assert est == est2
+    e = ti.Graph(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int64), 4)
+    E = load(tm, e, device=False)
+    z, w = tm.estimate_q(E, THREE[:2], 10, 2, 5.0, 3, 1)
+    assert z == [0.0, 0.0] and w["n_kept"] == 0
+    for bad in (dict(r=0.0), dict(r=-1.0), dict(r=float("inf")), dict(b=0), dict(c=1), dict(delta=0)):
+        args = dict(delta=20, c=3, r=2.0, b=1)
+        args.update(bad)
+        with pytest.raises(tm.TMError):
+            tm.estimate_q(G, THREE[:1], args["delta"], args["c"], args["r"], args["b"], 0)
+    with pytest.raises(tm.TMError):
+        tm.estimate_q(G, [ti.CYCLE4], 20, 3, 2.0, 1, 0)
+
+
 SWEEP_NAMES = ("sweep3_fwd_count", "sweep3_tri_count", "sweep3_bwd_count",
                "sweep3_fwd_weight", "sweep3_tri_weight", "sweep3_bwd_weight")
 
