@@ -419,6 +419,37 @@ def sweep_roofline(exact, ests, kern, crit, alone, steps, tables):
             "alone_ms_per_step": {k: v[0] for k, v in alone.items() if v[1] > 0}}
 
 
+def edge_proportional(tm, torch, g, src, dst, t, motifs, delta, c=30):
+    """Algorithm 1 with the paper's window probabilities q_j = min(1, r |T_j| / |T|)
+    (equation heuristic_q) and b shifts, for all the step's motifs: r = 0.1 J
+    keeps about as many windows as p = 0.1.  Also the paper's diagnostic of
+    how well q follows the weighted counts: with every window of one shift
+    kept, the correlation of each window's edge count with the triangle's
+    weighted count Y_{s,j}."""
+    G = tm.load_graph(src, dst, t, g.n)
+    L = c * delta
+    tn = np.sort(g.t - g.t.min())
+    J = 1 + -(-int(tn[-1]) // L)
+    r = 0.1 * J
+    out = {"c": c, "r": r, "windows": J}
+    for b in (1, 4):
+        tm.estimate_q(G, motifs, delta, c, r, b, 0, cap=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, w = tm.estimate_q(G, motifs, delta, c, r, b, 1, cap=0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"b{b}"] = {"ms": dt * 1e3, "edges_per_s_per_query": g.m * len(motifs) / dt, "kept_windows": w["n_kept"]}
+    s0 = tm.estimate(G, ti.TRIANGLE, delta, c, 1e-300, 0, info=True)["s"]
+    _, w = tm.estimate_q(G, [ti.TRIANGLE], delta, c, 1e15, 1, 0, cap=J + 1)
+    lo = s0 + (w["j"] - 1) * L
+    cnt = np.searchsorted(tn, lo + L - 1, side="right") - np.searchsorted(tn, lo, side="left")
+    out["all_windows_kept"] = int(w["n_kept"])
+    out["corr_window_edges_vs_triangle_Y"] = float(np.corrcoef(cnt, w["y"][:, 0])[0, 1])
+    G.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -536,6 +567,8 @@ def main():
     torch.cuda.synchronize()
     dtc = (time.perf_counter() - tc0) / args.steps
     log("concurrent steps done", f"{dtc * 1e3:.1f} ms per step")
+    edge_prop = edge_proportional(tm, torch, g, src, dst, t, motifs, delta)
+    log("edge-proportional estimates done")
     kern = {k: tm.profile_read(k) for k in SWEEP_KERNELS}
     crit = {k: tm.profile_read("crit:" + k) for k in SWEEP_KERNELS}
 
@@ -559,6 +592,7 @@ def main():
         "roofline": roofline,
         "concurrent_queries": {"ms_per_step": dtc * 1e3, "value": g.m * len(motifs) * (1 + len(W["est"])) / dtc,
                                "threads": len(streams), "same_results": same},
+        "edge_proportional": edge_prop,
     }
     if not args.no_cpu:
         log("cpu baseline (oracle)")
