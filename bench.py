@@ -304,6 +304,63 @@ def run_perf23(args):
     }
 
 
+# The paper's timings for the bi-fan at delta 3600 (its bifan table; 16-core
+# Xeon, C++ backtracking): datasets by temporal-edge count, exact and with
+# parallel sampling, in seconds.
+BIFAN_PAPER = {
+    "CollegeMsg": (59_835, 0.081, 0.069),
+    "Email-Eu": (332_334, 0.353, 0.120),
+    "MathOverflow": (390_441, 0.528, 0.041),
+    "AskUbuntu": (726_639, 1.408, 0.078),
+    "SuperUser": (1_108_739, 2.486, 0.164),
+}
+
+
+def run_bifan(args):
+    """Synthetic analogue of the paper's bifan table: the bi-fan
+    (0,1),(0,2),(3,1),(3,2) at delta 3600 on bursty Zipf(1.8) graphs with the
+    temporal-edge counts of its five datasets, counted exactly and estimated
+    (c 30, p 0.1), one timed run each after a warm-up on the smallest.  The
+    paper's backtracking seconds on the dataset of the same size are quoted
+    beside (other data, other hardware: context only)."""
+    import torch
+    import paper_1810_00980_amd as tm
+    delta, c, p = 3600, 30, 0.1
+    rows = []
+    for idx, (name, (m, bt_s, btps_s)) in enumerate(BIFAN_PAPER.items()):
+        g = ti.zipf_graph(max(1000, m // 30), m, 1.8, 30_000_000, 23)
+        s_, d_, t_ = (torch.from_numpy(a).cuda() for a in (g.src, g.dst, g.t))
+        G = tm.load_graph(s_, d_, t_, g.n)
+        if idx == 0:
+            tm.count_exact(G, ti.BIFAN, delta)
+            tm.estimate(G, ti.BIFAN, delta, c, p, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        exact = tm.count_exact(G, ti.BIFAN, delta)
+        torch.cuda.synchronize()
+        ex = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        z = tm.estimate(G, ti.BIFAN, delta, c, p, 1)
+        torch.cuda.synchronize()
+        es = time.perf_counter() - t0
+        G.free()
+        rows.append({"like": name, "m": g.m, "n": g.n, "exact_count": exact, "exact_s": ex,
+                     "exact_edges_per_s": g.m / ex, "estimate_s": es, "estimate_edges_per_s": g.m / es,
+                     "estimate_rel_error": (z - exact) / exact if exact else None,
+                     "paper_bt_s": bt_s, "paper_bt_ps_s": btps_s})
+        log("bifan", name, g.m, f"exact {ex * 1e3:.1f} ms, estimate {es * 1e3:.1f} ms")
+    big = rows[-1]
+    return {
+        "metric": "temporal edges/s, bi-fan (0,1),(0,2),(3,1),(3,2), delta 3600 (exact count)",
+        "value": big["exact_edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": big["exact_s"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "bursty Zipf(1.8) graphs with the edge counts of the paper's five bi-fan datasets "
+                               "(times over [0,3e7) s, n = m/30); estimates at c 30, p 0.1"},
+        "sizes": rows,
+    }
+
+
 def run_serve(args):
     """Poisson streams of count/estimate queries over 6 resident graphs of
     1e4 .. 7.2e6 edges at several arrival rates, served by the
@@ -515,7 +572,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="zipf10m", choices=sorted(WORKLOADS) + ["batch50m", "serve", "perf23"])
+    ap.add_argument("--workload", default="zipf10m", choices=sorted(WORKLOADS) + ["batch50m", "serve", "perf23", "bifan"])
     ap.add_argument("--qps-list", type=float, nargs="+", default=[50.0, 400.0], help="serve: arrival rates")
     ap.add_argument("--queries", type=int, default=400, help="serve: queries per arrival rate")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
@@ -534,8 +591,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    if args.workload in ("batch50m", "serve", "perf23"):
-        out = {"batch50m": run_batch, "serve": run_serve, "perf23": run_perf23}[args.workload](args)
+    if args.workload in ("batch50m", "serve", "perf23", "bifan"):
+        out = {"batch50m": run_batch, "serve": run_serve, "perf23": run_perf23, "bifan": run_bifan}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     W = WORKLOADS[args.workload]

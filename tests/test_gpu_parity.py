@@ -43,7 +43,7 @@ def close(a, b):
     return abs(a - b) <= REL * max(1.0, abs(b))
 
 
-MOTIFS = ti.three_edge_motifs() + [ti.CYCLE4, ti.STAR4, ti.OUTSTAR5, ((0, 1),), ((0, 1), (1, 0)),
+MOTIFS = ti.three_edge_motifs() + [ti.CYCLE4, ti.STAR4, ti.OUTSTAR5, ti.BIFAN, ((0, 1),), ((0, 1), (1, 0)),
                                     ((0, 1), (2, 0)), ((0, 1), (0, 1)), ((0, 1), (1, 2), (2, 3)),
                                     ((0, 1), (1, 2), (2, 0), (0, 1))]
 
@@ -243,6 +243,24 @@ def test_estimate_q_edge_cases(tm):
             tm.estimate_q(G, THREE[:1], args["delta"], args["c"], args["r"], args["b"], 0)
     with pytest.raises(tm.TMError):
         tm.estimate_q(G, [ti.CYCLE4], 20, 3, 2.0, 1, 0)
+
+
+def test_bifan_zipf(tm):
+    """The bi-fan on a bursty Zipf graph (hubs, ties): exact counts with
+    their duration histograms, and seed-matched estimates, against the
+    oracle."""
+    g = ti.zipf_graph(2000, 30000, 1.8, 200_000, 71)
+    say("bifan_zipf", g.m)
+    G = load(tm, g)
+    for delta in (60, 600):
+        got, hlo, hhi = tm.count_exact_multi(G, [ti.BIFAN], delta, hist=True)
+        want, h = oracle.count(g.src, g.dst, g.t, ti.BIFAN, delta)
+        assert got[0] == want, delta
+        assert np.array_equal(hlo[0], h) and not hhi.any()
+    for (c, p, seed) in ((10, 0.3, 1), (30, 1.0, 2)):
+        z = tm.estimate(G, ti.BIFAN, 600, c, p, seed)
+        o = oracle.estimate(g.src, g.dst, g.t, ti.BIFAN, 600, c, p, seed)
+        assert close(z, o["Z"]), (c, p, seed, z, o["Z"])
 
 
 SWEEP_NAMES = ("sweep3_fwd_count", "sweep3_tri_count", "sweep3_bwd_count",

@@ -168,7 +168,7 @@ def test_h9_window_boundaries_every_shift():
 
 # ------------------------------------------------- second brute force (tier B)
 
-MOTIFS = ti.three_edge_motifs() + [ti.CYCLE4, ti.STAR4, ti.OUTSTAR5, ((0, 1),), ((0, 1), (1, 0)),
+MOTIFS = ti.three_edge_motifs() + [ti.CYCLE4, ti.STAR4, ti.OUTSTAR5, ti.BIFAN, ((0, 1),), ((0, 1), (1, 0)),
                                     ((0, 1), (2, 0)), ((0, 1), (1, 2), (2, 3))]
 
 
@@ -483,3 +483,24 @@ def test_q_estimator_unbiased_over_seeds():
                    for seed in range(600)])
     se = zs.std(ddof=1) / math.sqrt(len(zs))
     assert abs(zs.mean() - CM) < 3 * se
+
+
+def test_bifan_is_canonical():
+    assert ti.canonical(ti.BIFAN) == ti.BIFAN
+
+
+def test_bifan_hand_example():
+    """The bi-fan (0,1),(0,2),(3,1),(3,2): sources a, b and targets c, d
+    with one edge per pair in motif order is one instance when its span fits
+    delta; the same edges in another order, or a shared source, are none."""
+    a, b, c, d = 0, 1, 2, 3
+    one = [(a, c, 1), (a, d, 2), (b, c, 3), (b, d, 4)]
+    assert ocount(one, ti.BIFAN, 3)[0] == 1
+    assert ocount(one, ti.BIFAN, 2)[0] == 0
+    swapped = [(a, c, 1), (b, c, 2), (a, d, 3), (b, d, 4)]
+    assert ocount(swapped, ti.BIFAN, 10)[0] == 0
+    same_source = [(a, c, 1), (a, d, 2), (a, c, 3), (a, d, 4)]
+    assert ocount(same_source, ti.BIFAN, 10)[0] == 0
+    # two parallel edges on every pair, all in motif order by blocks: 2^4 instances
+    blocks = [(a, c, 1), (a, c, 2), (a, d, 3), (a, d, 4), (b, c, 5), (b, c, 6), (b, d, 7), (b, d, 8)]
+    assert ocount(blocks, ti.BIFAN, 10)[0] == 16

@@ -219,3 +219,9 @@ TWO_NODE_ALT = ((0, 1), (1, 0), (0, 1))
 CYCLE4 = ((0, 1), (1, 2), (2, 3), (3, 0))
 STAR4 = ((0, 1), (0, 1), (0, 2), (0, 3))
 OUTSTAR5 = ((0, 1), (0, 2), (0, 3), (0, 4))
+# The bi-fan of the paper's second experiment (Sec. 5): two sources each
+# linked to the same two targets.  The figure that fixed its edge order is
+# lost, so this order (both edges of the first source, then both of the
+# second, targets in the same order) is a reading; labels are canonical
+# (numbered by first appearance): sources 0 and 3, targets 1 and 2.
+BIFAN = ((0, 1), (0, 2), (3, 1), (3, 2))
