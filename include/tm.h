@@ -217,6 +217,35 @@ tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, const tm_motif 
  * TM_EUNSUPPORTED (a motif without three edges, more than 2^30 windows),
  * TM_ENOMEM, TM_EDEVICE.  Outputs are written only on TM_OK.
  */
+/*
+ * Algorithm 1 (Sec. 4, one shift, q_j = p) with the windows visited in time
+ * order and only one kept window's edges on the device at a time: the
+ * streaming, memory-bounded use the paper describes after choosing the
+ * sampling probabilities.  The edges are host arrays (src, dst, t, m; node
+ * ids below n_nodes) sorted by non-decreasing time; the library checks the
+ * order on the device in bounded chunks (TM_EINVAL when unsorted) and
+ * validates the ids of every window it reads.  Per kept window it uploads
+ * that window's edges, builds a graph of them and sweeps it, so the device
+ * holds one window at a time.  Results are those of tm_estimate_multi on the
+ * whole graph with the same seed, to the last bit (both sum the same exact
+ * fixed-point integers).  Motifs: three-edge motifs only
+ * (TM_EUNSUPPORTED otherwise).  estimates[n_motifs], kept_counts[n_motifs]
+ * (nullable): host.  info (nullable, host): the shift, J, the kept windows,
+ * the edges of the largest kept window (what is resident at once) and the
+ * device bytes of its graph.  Errors as tm_estimate_multi and tm_load_graph.
+ */
+typedef struct {
+    int64_t shift;
+    int64_t n_windows;
+    int64_t n_kept;
+    int64_t max_window_edges;
+    int64_t peak_graph_bytes;
+} tm_stream_info;
+tm_status tm_estimate_stream(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t m, int32_t n_nodes,
+                             int32_t n_motifs, const tm_motif *motifs, int64_t delta, int64_t c, double p,
+                             uint64_t seed, double *estimates, tm_u128 *kept_counts, tm_stream_info *info,
+                             void *hip_stream);
+
 typedef struct {
     int64_t n_kept;
     int64_t cap;

@@ -70,6 +70,11 @@ class QInfo(ctypes.Structure):
                 ("win_j", ctypes.c_void_p), ("win_q", ctypes.c_void_p), ("win_y", ctypes.c_void_p)]
 
 
+class StreamInfo(ctypes.Structure):
+    _fields_ = [("shift", ctypes.c_int64), ("n_windows", ctypes.c_int64), ("n_kept", ctypes.c_int64),
+                ("max_window_edges", ctypes.c_int64), ("peak_graph_bytes", ctypes.c_int64)]
+
+
 class Query(ctypes.Structure):
     _fields_ = [("graph", ctypes.c_int32), ("kind", ctypes.c_int32), ("motif", Motif), ("delta", ctypes.c_int64),
                 ("c", ctypes.c_int64), ("p", ctypes.c_double), ("seed", ctypes.c_uint64)]
@@ -104,6 +109,7 @@ _SIGS = {
     "tm_estimate": [P, P, i64, i64, f64, u64, P, P, P],
     "tm_estimate_multi": [P, i32, P, i64, i64, f64, u64, P, P, P],
     "tm_estimate_q": [P, i32, P, i64, i64, f64, i32, u64, P, P, P],
+    "tm_estimate_stream": [P, P, P, i64, i32, i32, P, i64, i64, f64, u64, P, P, P, P],
     "tm_estimate_batch": [P, P, i64, i64, f64, i32, P, i32, P, P, P],
     "tm_batch_config": [P, P, i64, i64, f64, P, P, P],
     "tm_batch_release": [P, P],
@@ -325,6 +331,29 @@ def estimate_q(g: Graph, motifs, delta: int, c: int, r: float, b: int, seed: int
     n = min(info.n_kept, cap)
     return [est[i] for i in range(k)], {"n_kept": info.n_kept, "k": wk[:n].copy(), "j": wj[:n].copy(),
                                         "q": wq[:n].copy(), "y": wy[:n, :k].copy()}
+
+
+def estimate_stream(src, dst, t, n_nodes: int, motifs, delta: int, c: int, p: float, seed: int, stream=None):
+    """Algorithm 1 over host arrays sorted by time, one kept window on the
+    device at a time (three-edge motifs).  Returns (estimates, kept counts,
+    info dict)."""
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    t = np.ascontiguousarray(t, dtype=np.int64)
+    m = int(t.shape[0])
+    if src.shape[0] != m or dst.shape[0] != m:
+        raise ValueError("src, dst and t differ in length")
+    k = len(motifs)
+    arr = (Motif * max(k, 1))(*[motif(x) for x in motifs])
+    est = (ctypes.c_double * max(k, 1))()
+    kc = (U128 * max(k, 1))()
+    info = StreamInfo()
+    _check(_lib.tm_estimate_stream(P(src.ctypes.data), P(dst.ctypes.data), P(t.ctypes.data), m, int(n_nodes), k,
+                                   arr, int(delta), int(c), float(p), int(seed), est, kc, ctypes.byref(info),
+                                   _stream(stream)), "tm_estimate_stream")
+    return ([est[i] for i in range(k)], [kc[i].value() for i in range(k)],
+            {"shift": info.shift, "n_windows": info.n_windows, "n_kept": info.n_kept,
+             "max_window_edges": info.max_window_edges, "peak_graph_bytes": info.peak_graph_bytes})
 
 
 def estimate_batch(g: Graph, edges, delta: int, c: int, p: float, seeds, tile: int = 0, stream=None):

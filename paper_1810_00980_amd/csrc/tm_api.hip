@@ -333,6 +333,15 @@ __global__ void k_q_kidx(const int64_t *flag, const int64_t *scan, int64_t J, in
     if (j <= J) kidx[j] = flag[j - 1] ? (int32_t)scan[j - 1] : -1;
 }
 
+// Time order of one chunk of a host edge stream: bad[0] = 1 when a time is
+// below its predecessor (prev: the last time of the previous chunk).
+__global__ void k_sorted_chunk(const int64_t *t, int64_t n, int64_t prev, int32_t *bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t before = i == 0 ? prev : t[i - 1];
+    if (t[i] < before) bad[0] = 1;
+}
+
 tm_status check_est_args(const tm_graph *g, int64_t delta, int64_t c, double p, int64_t *L) {
     if (!g || delta < 1 || c < 2 || !(p > 0.0 && p <= 1.0)) return TM_EINVAL;
     if (delta > INT64_MAX / c) return TM_EINVAL;
@@ -623,6 +632,113 @@ tm_status estimate_q_impl(const tm_graph *g, int32_t n, const tm_motif *motifs, 
     return TM_OK;
 }
 
+// Algorithm 1 with the windows visited in time order and only one kept
+// window's edges on the device at a time (the streaming use of Sec. 4): the
+// edges come as host arrays sorted by time; per kept window, its edges are
+// loaded as a graph of their own and swept with every anchor (instances of
+// that graph are exactly the instances inside the window); the windows'
+// exact fixed-point sums add up to the same integers as one in-memory sweep.
+tm_status estimate_stream_impl(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t m, int32_t n_nodes,
+                               int32_t n, const tm_motif *motifs, int64_t delta, int64_t c, double p, uint64_t seed,
+                               double *est, tm_u128 *kept, tm_stream_info *info, hipStream_t st) {
+    if (m < 0 || n_nodes <= 0 || (m > 0 && (!src || !dst || !t)) || n < 1 || !motifs || !est) return TM_EINVAL;
+    if (delta < 1 || c < 2 || !(p > 0.0 && p <= 1.0) || delta > INT64_MAX / c) return TM_EINVAL;
+    const int64_t L = c * delta;
+    if (L > INT64_MAX / 4) return TM_EINVAL;
+    std::vector<int> codes;
+    uint64_t mask;
+    if (!all_sweep_codes(n, motifs, &codes, &mask)) return TM_EUNSUPPORTED;
+    unsigned __int128 wsum[36] = {}, csum[36] = {};
+    int64_t J = 0, nk = 0, maxw = 0, peak = 0, s = 0;
+    if (m > 0) {
+        // time order, checked on the device in bounded chunks
+        const int64_t CH = (int64_t)1 << 24;
+        DevBuf tc, bad;
+        TM_TRY(tc.alloc((size_t)std::min(m, CH) * 8));
+        TM_TRY(bad.alloc(4));
+        TM_HIP(hipMemsetAsync(bad.p, 0, 4, st));
+        int64_t prev = t[0];
+        for (int64_t off = 0; off < m; off += CH) {
+            const int64_t len = std::min(CH, m - off);
+            TM_HIP(hipMemcpyAsync(tc.p, t + off, (size_t)len * 8, hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(k_sorted_chunk, dim3(tm_blocks(len, TPB)), dim3(TPB), 0, st, tc.as<int64_t>(), len,
+                               prev, bad.as<int32_t>());
+            TM_HIP(hipGetLastError());
+            TM_HIP(hipStreamSynchronize(st));  // the chunk buffer is reused
+            prev = t[off + len - 1];
+        }
+        int32_t bad_h = 0;
+        TM_HIP(hipMemcpyAsync(&bad_h, bad.p, 4, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+        if (bad_h) return TM_EINVAL;
+        const int64_t tmin = t[0], tmax = t[m - 1];
+        if (tmin < 0 && tmax > INT64_MAX + tmin) return TM_EINVAL;
+        const int64_t span = tmax - tmin;
+        if (span > INT64_MAX - 2 * L) return TM_EINVAL;
+        J = 1 + span / L + ((span % L) ? 1 : 0);
+        if (J > ((int64_t)1 << 30)) return TM_EUNSUPPORTED;
+        s = host_shift(seed, L);
+        // kept windows, on the device
+        std::vector<int64_t> ids;
+        {
+            DevBuf f, sc, di, tot;
+            TM_TRY(f.alloc((size_t)J * 8));
+            TM_TRY(sc.alloc((size_t)J * 8));
+            TM_TRY(di.alloc((size_t)J * 8));
+            TM_TRY(tot.alloc(8));
+            hipLaunchKernelGGL(k_all_windows, dim3(tm_blocks(J, TPB)), dim3(TPB), 0, st, seed, J, p, f.as<int64_t>());
+            TM_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_copy_i64, dim3(tm_blocks(J, TPB)), dim3(TPB), 0, st, f.as<int64_t>(),
+                               sc.as<int64_t>(), J);
+            TM_HIP(hipGetLastError());
+            TM_TRY(tm_scan_i64(sc.as<int64_t>(), J, tot.as<int64_t>(), st));
+            hipLaunchKernelGGL(k_list_windows, dim3(tm_blocks(J, TPB)), dim3(TPB), 0, st, f.as<int64_t>(),
+                               sc.as<int64_t>(), J, J, di.as<int64_t>());
+            TM_HIP(hipGetLastError());
+            TM_HIP(hipMemcpyAsync(&nk, tot.p, 8, hipMemcpyDeviceToHost, st));
+            TM_HIP(hipStreamSynchronize(st));
+            ids.resize((size_t)(nk > 0 ? nk : 1));
+            if (nk > 0) TM_HIP(hipMemcpyAsync(ids.data(), di.p, (size_t)nk * 8, hipMemcpyDeviceToHost, st));
+            TM_HIP(hipStreamSynchronize(st));
+        }
+        for (int64_t w = 0; w < nk; ++w) {
+            const int64_t j = ids[(size_t)w];
+            const int64_t lo = tmin + s + (j - 1) * L, hi = tmin + s + j * L - 1;
+            const int64_t a = std::lower_bound(t, t + m, lo) - t;
+            const int64_t b = std::upper_bound(t, t + m, hi) - t;
+            if (b <= a) continue;  // an empty window holds no instance
+            maxw = std::max(maxw, b - a);
+            tm_graph *gw = nullptr;
+            TM_TRY(tm_load_graph_ex(src + a, dst + a, t + a, b - a, n_nodes, TM_LOAD_NO_EXACT_TABLES, st, &gw));
+            SweepOut so;
+            const tm_status r = run_sweep(gw, mask, 1, delta, 0, 0, L, seed, 1.0, &so, {}, nullptr, st);
+            peak = std::max(peak, gw->device_bytes);
+            tm_free_graph(gw);
+            if (r != TM_OK) return r;
+            for (int k = 0; k < 36; ++k) {
+                csum[k] += ((unsigned __int128)so.v[4 * k + 1] << 64) | so.v[4 * k];
+                wsum[k] += ((unsigned __int128)so.v[4 * k + 3] << 64) | so.v[4 * k + 2];
+            }
+        }
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        const int k = codes[(size_t)i];
+        est[i] = u128_scaled((uint64_t)wsum[k], (uint64_t)(wsum[k] >> 64), 1.0 / 4503599627370496.0) / p;
+        if (kept) {
+            kept[i].lo = (uint64_t)csum[k];
+            kept[i].hi = (uint64_t)(csum[k] >> 64);
+        }
+    }
+    if (info) {
+        info->shift = s;
+        info->n_windows = J;
+        info->n_kept = nk;
+        info->max_window_edges = maxw;
+        info->peak_graph_bytes = peak;
+    }
+    return TM_OK;
+}
+
 tm_status count_exact_impl(const tm_graph *g, const tm_motif *M, int64_t delta, uint64_t *hist_lo_host,
                            uint64_t *hist_hi_host, tm_u128 *out, hipStream_t st) {
     MotifPlan P;
@@ -780,6 +896,16 @@ extern "C" tm_status tm_estimate_q(const tm_graph *g, int32_t n_motifs, const tm
                                    void *hip_stream) {
     hipStream_t st = (hipStream_t)hip_stream;
     return finish(estimate_q_impl(g, n_motifs, motifs, delta, c, r, b, seed, estimates, info, st), st);
+}
+
+extern "C" tm_status tm_estimate_stream(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t m,
+                                        int32_t n_nodes, int32_t n_motifs, const tm_motif *motifs, int64_t delta,
+                                        int64_t c, double p, uint64_t seed, double *estimates, tm_u128 *kept_counts,
+                                        tm_stream_info *info, void *hip_stream) {
+    hipStream_t st = (hipStream_t)hip_stream;
+    return finish(estimate_stream_impl(src, dst, t, m, n_nodes, n_motifs, motifs, delta, c, p, seed, estimates,
+                                       kept_counts, info, st),
+                  st);
 }
 
 extern "C" tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, const tm_motif *motifs, int64_t delta,

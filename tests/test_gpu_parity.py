@@ -263,6 +263,38 @@ def test_bifan_zipf(tm):
         assert close(z, o["Z"]), (c, p, seed, z, o["Z"])
 
 
+def test_estimate_stream_equals_in_memory(tm):
+    """Streaming (kept windows in time order, one window's edges on the
+    device at a time) gives the in-memory estimates and kept counts to the
+    last bit, and the oracle's estimates within 1e-12; unsorted streams are
+    refused."""
+    cases = [
+        (ti.random_small_graph(6, 1500, 8000, 81, allow_self_loops=True), 40, 3, 0.5, 2, True),
+        (ti.config_small_dense(5), 3600, 10, 0.3, 1, True),
+        (ti.zipf_graph(3000, 60000, 1.8, 2_000_000, 82), 3600, 5, 0.2, 3, False),
+    ]
+    for g, delta, c, p, seed, with_oracle in cases:
+        say("estimate_stream", g.m, delta, c, p, seed)
+        o = np.argsort(g.t, kind="stable")
+        est, kc, info = tm.estimate_stream(g.src[o], g.dst[o], g.t[o], g.n, THREE, delta, c, p, seed)
+        G = load(tm, g)
+        e2, k2 = tm.estimate_multi(G, THREE, delta, c, p, seed)
+        assert est == e2 and kc == k2
+        assert info["n_kept"] > 0 and 0 < info["max_window_edges"] < g.m
+        if with_oracle:
+            for M, z in list(zip(THREE, est))[::9]:
+                assert close(z, oracle.estimate(g.src, g.dst, g.t, M, delta, c, p, seed)["Z"]), M
+    g = ti.random_small_graph(5, 300, 1000, 83)
+    assert not np.all(np.diff(g.t) >= 0)
+    with pytest.raises(tm.TMError):
+        tm.estimate_stream(g.src, g.dst, g.t, g.n, THREE[:1], 20, 3, 0.5, 0)
+    z, k, info = tm.estimate_stream(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int64), 4,
+                                    THREE[:2], 10, 2, 0.5, 0)
+    assert z == [0.0, 0.0] and k == [0, 0] and info["n_kept"] == 0
+    with pytest.raises(tm.TMError):
+        tm.estimate_stream(g.src[:1], g.dst[:1], g.t[:1], g.n, [ti.CYCLE4], 20, 3, 0.5, 0)
+
+
 SWEEP_NAMES = ("sweep3_fwd_count", "sweep3_tri_count", "sweep3_bwd_count",
                "sweep3_fwd_weight", "sweep3_tri_weight", "sweep3_bwd_weight")
 
