@@ -536,6 +536,31 @@ def sweep_roofline(exact, ests, kern, crit, alone, steps, tables):
             "alone_ms_per_step": {k: v[0] for k, v in alone.items() if v[1] > 0}}
 
 
+def stream_estimates(tm, torch, g, motifs, delta, c=30, p=0.1):
+    """The p = 0.1 estimates of all the step's motifs from the time-sorted
+    edges in host memory, one kept window on the device at a time: time per
+    call (uploads included), the largest resident window and its graph's
+    device bytes, beside the in-memory graph's; results are checked equal to
+    the in-memory call."""
+    o = np.argsort(g.t, kind="stable")
+    hs, hd, ht = g.src[o], g.dst[o], g.t[o]
+    tm.estimate_stream(hs, hd, ht, g.n, motifs, delta, c, p, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    est, _, info = tm.estimate_stream(hs, hd, ht, g.n, motifs, delta, c, p, 0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s_, d_, t_ = (torch.from_numpy(a).cuda() for a in (g.src, g.dst, g.t))
+    G = tm.load_graph(s_, d_, t_, g.n)
+    same = est == tm.estimate_multi(G, motifs, delta, c, p, 0)[0]
+    full = G.device_bytes
+    G.free()
+    return {"c": c, "p": p, "ms": dt * 1e3, "edges_per_s_per_query": g.m * len(motifs) / dt,
+            "kept_windows": info["n_kept"], "max_window_edges": info["max_window_edges"],
+            "peak_window_graph_bytes": info["peak_graph_bytes"], "in_memory_graph_bytes": full,
+            "same_results": same}
+
+
 def edge_proportional(tm, torch, g, src, dst, t, motifs, delta, c=30):
     """Algorithm 1 with the paper's window probabilities q_j = min(1, r |T_j| / |T|)
     (equation heuristic_q) and b shifts, for all the step's motifs: r = 0.1 J
@@ -686,6 +711,8 @@ def main():
     log("concurrent steps done", f"{dtc * 1e3:.1f} ms per step")
     edge_prop = edge_proportional(tm, torch, g, src, dst, t, motifs, delta)
     log("edge-proportional estimates done")
+    streaming = stream_estimates(tm, torch, g, motifs, delta)
+    log("streaming estimates done")
     kern = {k: tm.profile_read(k) for k in SWEEP_KERNELS}
     crit = {k: tm.profile_read("crit:" + k) for k in SWEEP_KERNELS}
 
@@ -710,6 +737,7 @@ def main():
         "concurrent_queries": {"ms_per_step": dtc * 1e3, "value": g.m * len(motifs) * (1 + len(W["est"])) / dtc,
                                "threads": len(streams), "same_results": same},
         "edge_proportional": edge_prop,
+        "streaming": streaming,
     }
     if not args.no_cpu:
         log("cpu baseline (oracle)")
