@@ -222,7 +222,8 @@ tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, const tm_motif 
  * order and only one kept window's edges on the device at a time: the
  * streaming, memory-bounded use the paper describes after choosing the
  * sampling probabilities.  The edges are host arrays (src, dst, t, m; node
- * ids below n_nodes) sorted by non-decreasing time; the library checks the
+ * ids below n_nodes; device arrays: TM_EINVAL) sorted by non-decreasing
+ * time; the library checks the
  * order on the device in bounded chunks (TM_EINVAL when unsorted) and
  * validates the ids of every window it reads.  Per kept window it uploads
  * that window's edges, builds a graph of them and sweeps it, so the device

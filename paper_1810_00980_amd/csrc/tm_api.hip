@@ -648,6 +648,14 @@ tm_status estimate_stream_impl(const int32_t *src, const int32_t *dst, const int
     std::vector<int> codes;
     uint64_t mask;
     if (!all_sweep_codes(n, motifs, &codes, &mask)) return TM_EUNSUPPORTED;
+    // the stream is read on the host: device arrays are refused
+    for (const void *ptr : {(const void *)src, (const void *)dst, (const void *)t}) {
+        if (!ptr) continue;
+        hipPointerAttribute_t attr;
+        const hipError_t e = hipPointerGetAttributes(&attr, ptr);
+        (void)hipGetLastError();  // plain host memory is unknown to HIP: not an error here
+        if (e == hipSuccess && attr.type == hipMemoryTypeDevice) return TM_EINVAL;
+    }
     unsigned __int128 wsum[36] = {}, csum[36] = {};
     int64_t J = 0, nk = 0, maxw = 0, peak = 0, s = 0;
     if (m > 0) {

@@ -293,6 +293,16 @@ def test_estimate_stream_equals_in_memory(tm):
     assert z == [0.0, 0.0] and k == [0, 0] and info["n_kept"] == 0
     with pytest.raises(tm.TMError):
         tm.estimate_stream(g.src[:1], g.dst[:1], g.t[:1], g.n, [ti.CYCLE4], 20, 3, 0.5, 0)
+    # device arrays are refused (the stream is read on the host)
+    import ctypes
+    s_dev, d_dev, t_dev = to_dev(ti.random_small_graph(5, 50, 1000, 84))
+    m_ = int(t_dev.shape[0])
+    arr = (tm.Motif * 1)(tm.motif(THREE[0]))
+    est_ = (ctypes.c_double * 1)()
+    rc = tm._lib.tm_estimate_stream(ctypes.c_void_p(s_dev.data_ptr()), ctypes.c_void_p(d_dev.data_ptr()),
+                                    ctypes.c_void_p(t_dev.data_ptr()), m_, 5, 1, arr, 20, 3, 0.5, 0, est_, None,
+                                    None, None)
+    assert rc == 1  # TM_EINVAL
 
 
 SWEEP_NAMES = ("sweep3_fwd_count", "sweep3_tri_count", "sweep3_bwd_count",
