@@ -12,7 +12,11 @@
 // with the start found by binary search on time.  The last level is not
 // enumerated for totals: a pair list contributes its range length and a node
 // list the number of admissible entries.  With a duration histogram the last
-// level is enumerated and each instance adds one to bin t_l - t_1.
+// level is enumerated and each instance adds one to bin t_l - t_1: in a
+// block-local u64 histogram in LDS when delta + 1 bins fit (flushed into the
+// u128 global bins once per block), else straight into the global bins.  A
+// block's LDS bin cannot reach 2^64: that many increments would take
+// centuries at the CU's LDS atomic rate.
 #include "tm_common.h"
 
 #include <limits.h>
@@ -20,6 +24,18 @@
 namespace {
 
 constexpr int CG_TPB = 256;
+constexpr int64_t CG_LDS_BINS = 8192;  // 64 KB of u64 bins per block
+
+// histogram modes
+constexpr int HM_NONE = 0, HM_GLOBAL = 1, HM_LDS = 2;
+
+extern __shared__ uint64_t cg_bins[];
+
+template <int HM>
+__device__ inline void hist_add(uint64_t *hlo, uint64_t *hhi, int64_t d) {
+    if constexpr (HM == HM_LDS) atomicAdd((unsigned long long *)&cg_bins[d], 1ull);
+    else if constexpr (HM == HM_GLOBAL) tm_atomic_add_u128(hlo + d, hhi + d, 1, 0);
+}
 
 struct Binding {
     int32_t f0, f1, f2, f3, f4;
@@ -109,7 +125,7 @@ struct Acc {
     }
 };
 
-template <bool HIST>
+template <int HIST>
 __device__ inline void count_last(const Range &R, const Binding &f, int64_t t1, Acc &acc, uint64_t *hlo,
                                   uint64_t *hhi) {
     if (R.nbr == nullptr) {
@@ -117,8 +133,7 @@ __device__ inline void count_last(const Range &R, const Binding &f, int64_t t1, 
             acc.add((uint64_t)(R.end - R.cur));
         } else {
             for (int64_t i = R.cur; i < R.end; ++i) {
-                int64_t d = R.t[i] - t1;
-                tm_atomic_add_u128(hlo + d, hhi + d, 1, 0);
+                hist_add<HIST>(hlo, hhi, R.t[i] - t1);
             }
             acc.add((uint64_t)(R.end - R.cur));
         }
@@ -128,17 +143,14 @@ __device__ inline void count_last(const Range &R, const Binding &f, int64_t t1, 
     for (int64_t i = R.cur; i < R.end; ++i) {
         if (!f.used(R.nbr[i])) {
             ++c;
-            if (HIST) {
-                int64_t d = R.t[i] - t1;
-                tm_atomic_add_u128(hlo + d, hhi + d, 1, 0);
-            }
+            if (HIST) hist_add<HIST>(hlo, hhi, R.t[i] - t1);
         }
     }
     acc.add(c);
 }
 
 // Levels R .. LEN-1 below the current binding.
-template <int R, int LEN, bool HIST>
+template <int R, int LEN, int HIST>
 __device__ inline void levels(const DevGraph &G, const MotifPlan &P, Binding &f, int64_t tprev, int64_t t1,
                               int64_t hi, Acc &acc, uint64_t *hlo, uint64_t *hhi) {
     Range rg = open_level(G, P, R, f, tprev, hi);
@@ -160,7 +172,7 @@ __device__ inline void levels(const DevGraph &G, const MotifPlan &P, Binding &f,
     }
 }
 
-template <int LEN, bool HIST>
+template <int LEN, int HIST>
 __device__ inline void count_anchor(const DevGraph &G, const MotifPlan &P, int64_t pos, int64_t win_end,
                                     int64_t delta, Acc &acc, uint64_t *hlo, uint64_t *hhi) {
     int32_t a = G.es_src[pos], b = G.es_dst[pos];
@@ -170,7 +182,7 @@ __device__ inline void count_anchor(const DevGraph &G, const MotifPlan &P, int64
     hi = hi < win_end ? hi : win_end;
     if constexpr (LEN == 1) {
         acc.add(1);
-        if (HIST) tm_atomic_add_u128(hlo, hhi, 1, 0);
+        if (HIST) hist_add<HIST>(hlo, hhi, 0);
     } else {
         Binding f{-1, -1, -1, -1, -1};
         f.set(0, a);
@@ -188,13 +200,28 @@ __device__ inline void wave_reduce_u128(uint64_t &lo, uint64_t &hi) {
     }
 }
 
-template <int LEN, bool HIST>
+// Persistent waves take 64 consecutive anchors at a time from a global
+// counter: per-anchor work is heavy-tailed (hub anchors), so a wave that
+// drew light anchors moves on instead of waiting for a static share.
+template <int LEN, int HIST>
 __global__ void __launch_bounds__(CG_TPB) k_count_generic(DevGraph G, MotifPlan P, int64_t delta, AnchorSet A,
                                                          uint64_t *total, uint64_t *slot_tot, uint64_t *hlo,
-                                                         uint64_t *hhi, uint64_t *per_anchor, int32_t *flag) {
-    int64_t nA = A.dev_n ? *A.dev_n : A.n;
+                                                         uint64_t *hhi, uint64_t *per_anchor, int32_t *flag,
+                                                         unsigned long long *counter) {
+    const int64_t nA = A.dev_n ? *A.dev_n : A.n;
+    const int lane = threadIdx.x & (TM_WAVE - 1);
+    if constexpr (HIST == HM_LDS) {
+        for (int64_t k = threadIdx.x; k <= delta; k += blockDim.x) cg_bins[k] = 0;
+        __syncthreads();
+    }
     uint64_t lo = 0, hi = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nA; i += (int64_t)gridDim.x * blockDim.x) {
+    while (true) {
+        int64_t base = 0;
+        if (lane == 0) base = (int64_t)atomicAdd(counter, (unsigned long long)TM_WAVE);
+        base = __shfl(base, 0, TM_WAVE);
+        if (base >= nA) break;
+        const int64_t i = base + lane;
+        if (i >= nA) continue;
         int64_t pos = A.pos ? A.pos[i] : i;
         int64_t we = A.win_end ? A.win_end[i] : LLONG_MAX;
         Acc acc{0, 0};
@@ -211,19 +238,36 @@ __global__ void __launch_bounds__(CG_TPB) k_count_generic(DevGraph G, MotifPlan 
     }
     wave_reduce_u128(lo, hi);
     if ((threadIdx.x & (TM_WAVE - 1)) == 0 && total) tm_atomic_add_u128(total, total + 1, lo, hi);
+    if constexpr (HIST == HM_LDS) {
+        __syncthreads();
+        for (int64_t k = threadIdx.x; k <= delta; k += blockDim.x) {
+            uint64_t v = cg_bins[k];
+            if (v) tm_atomic_add_u128(hlo + k, hhi + k, v, 0);
+        }
+    }
 }
 
-template <int LEN, bool HIST>
-tm_status launch_len(const DevGraph &G, const MotifPlan &P, int64_t delta, const AnchorSet &A, uint64_t *total,
-                     uint64_t *slot_tot, uint64_t *hlo, uint64_t *hhi, uint64_t *per_anchor, int32_t *flag,
-                     hipStream_t st) {
+// work-queue head of the calls made from this host thread (each call
+// finishes on its stream before returning)
+thread_local DevBuf t_cg_counter;
+
+template <int LEN, int HIST>
+tm_status launch_len(int device, const DevGraph &G, const MotifPlan &P, int64_t delta, const AnchorSet &A,
+                     uint64_t *total, uint64_t *slot_tot, uint64_t *hlo, uint64_t *hhi, uint64_t *per_anchor,
+                     int32_t *flag, hipStream_t st) {
     int64_t n = A.n;
     if (n <= 0) return TM_OK;
-    unsigned nb = tm_blocks(n, CG_TPB);
-    if (nb > 65535u * 4) nb = 65535u * 4;
+    TM_TRY(t_cg_counter.reserve(8));
+    TM_HIP(hipMemsetAsync(t_cg_counter.p, 0, 8, st));
+    int ncu = 0;
+    TM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
+    if (ncu <= 0) ncu = 256;
+    int64_t nb = tm_blocks(n, CG_TPB);
+    if (nb > (int64_t)ncu * 8) nb = (int64_t)ncu * 8;
     void *tok = tm_prof_begin("count_generic", st);
-    hipLaunchKernelGGL((k_count_generic<LEN, HIST>), dim3(nb), dim3(CG_TPB), 0, st, G, P, delta, A, total,
-                       slot_tot, hlo, hhi, per_anchor, flag);
+    size_t lds = HIST == HM_LDS ? (size_t)(delta + 1) * 8 : 0;
+    hipLaunchKernelGGL((k_count_generic<LEN, HIST>), dim3((unsigned)nb), dim3(CG_TPB), lds, st, G, P, delta, A, total,
+                       slot_tot, hlo, hhi, per_anchor, flag, t_cg_counter.as<unsigned long long>());
     tm_status s = tm_hip_status(hipGetLastError());
     tm_prof_end(tok, st);
     return s;
@@ -296,10 +340,14 @@ tm_status tm_count_generic(const tm_graph *g, const MotifPlan &P, int64_t delta,
     bool hist = hist_lo != nullptr;
 #define TM_LEN_CASE(LN)                                                                                          \
     case LN:                                                                                                     \
-        return hist ? launch_len<LN, true>(G, P, delta, A, total, slot_tot, hist_lo, hist_hi, per_anchor, flag,  \
-                                           st)                                                                   \
-                    : launch_len<LN, false>(G, P, delta, A, total, slot_tot, nullptr, nullptr, per_anchor, flag, \
-                                            st);
+        if (!hist)                                                                                               \
+            return launch_len<LN, HM_NONE>(g->device, G, P, delta, A, total, slot_tot, nullptr, nullptr,        \
+                                           per_anchor, flag, st);                                                \
+        if (delta < CG_LDS_BINS)                                                                                 \
+            return launch_len<LN, HM_LDS>(g->device, G, P, delta, A, total, slot_tot, hist_lo, hist_hi,         \
+                                          per_anchor, flag, st);                                                 \
+        return launch_len<LN, HM_GLOBAL>(g->device, G, P, delta, A, total, slot_tot, hist_lo, hist_hi,          \
+                                         per_anchor, flag, st);
     switch (P.l) {
         TM_LEN_CASE(1)
         TM_LEN_CASE(2)

@@ -416,6 +416,24 @@ def test_weighted_triangles_long_windows(tm):
             assert counts[k] == want and (hhi[k] == 0).all() and (hlo[k] == h).all(), M
 
 
+@pytest.mark.gpu
+def test_generic_hist_both_bin_stores(tm):
+    """Four-edge duration histograms on either side of the largest delta
+    whose bins a block keeps in LDS (8192 bins): exact histograms and
+    seed-matched estimates against the oracle."""
+    g = ti.zipf_graph(500, 4000, 1.5, 2_000_000, 73)
+    say("generic hist", g.m)
+    G = load(tm, g)
+    for delta in (8191, 8192, 20000):
+        got, hlo, hhi = tm.count_exact_multi(G, [ti.BIFAN, ti.CYCLE4], delta, hist=True)
+        for k, M in enumerate((ti.BIFAN, ti.CYCLE4)):
+            want, h = oracle.count(g.src, g.dst, g.t, M, delta)
+            assert got[k] == want and np.array_equal(hlo[k], h) and not hhi[k].any(), (M, delta)
+        z = tm.estimate(G, ti.BIFAN, delta, 10, 0.5, 3)
+        o = oracle.estimate(g.src, g.dst, g.t, ti.BIFAN, delta, 10, 0.5, 3)
+        assert close(z, o["Z"]), (delta, z, o["Z"])
+
+
 @pytest.fixture(scope="module")
 def zipf10m():
     return ti.config_zipf10m()
