@@ -172,14 +172,19 @@ __device__ inline void levels(const DevGraph &G, const MotifPlan &P, Binding &f,
     }
 }
 
+// last time a later motif edge may take: min(t1 + delta, window end)
+__device__ inline int64_t anchor_hi(int64_t t1, int64_t delta, int64_t win_end) {
+    int64_t hi = (t1 > LLONG_MAX - delta) ? LLONG_MAX : t1 + delta;
+    return hi < win_end ? hi : win_end;
+}
+
 template <int LEN, int HIST>
 __device__ inline void count_anchor(const DevGraph &G, const MotifPlan &P, int64_t pos, int64_t win_end,
                                     int64_t delta, Acc &acc, uint64_t *hlo, uint64_t *hhi) {
     int32_t a = G.es_src[pos], b = G.es_dst[pos];
     if (a == b) return;
     int64_t t1 = G.es_t[pos];
-    int64_t hi = (t1 > LLONG_MAX - delta) ? LLONG_MAX : t1 + delta;
-    hi = hi < win_end ? hi : win_end;
+    int64_t hi = anchor_hi(t1, delta, win_end);
     if constexpr (LEN == 1) {
         acc.add(1);
         if (HIST) hist_add<HIST>(hlo, hhi, 0);
@@ -247,9 +252,121 @@ __global__ void __launch_bounds__(CG_TPB) k_count_generic(DevGraph G, MotifPlan 
     }
 }
 
-// work-queue head of the calls made from this host thread (each call
-// finishes on its stream before returning)
+// Motifs of three or four edges: the work under one anchor grows with the
+// product of its hub degrees, and on hub-heavy graphs a single anchor can
+// outweigh a lane's fair share of the whole count many times over.  The
+// counter therefore splits each anchor into one work item per entry of its
+// level-1 range (the motif's second edge): k_level1_ranges stores each
+// anchor's range start and length, an exclusive scan turns the lengths into
+// item offsets, and k_count_split's persistent waves claim 64 items at a
+// time, find each item's anchor by binary search over the offsets and run
+// levels 2 .. LEN-1 under it.  Per-slot and per-anchor outputs are atomic
+// adds of the items' counts (their sums equal the per-anchor totals).
+
+struct Level1 {
+    const int32_t *nbr;  // nullptr for a pair list
+    const int64_t *t;
+    int32_t newnode;
+};
+
+__device__ inline Level1 level1_list(const DevGraph &G, const MotifPlan &P) {
+    if (P.kind[1] == LV_PAIR) return Level1{nullptr, G.pr_t, -1};
+    if (P.kind[1] == LV_OUT) return Level1{G.out_nbr, G.out_t, P.v[1]};
+    return Level1{G.in_nbr, G.in_t, P.u[1]};
+}
+
+__global__ void __launch_bounds__(CG_TPB) k_level1_ranges(DevGraph G, MotifPlan P, int64_t delta, AnchorSet A,
+                                                         int64_t *beg, int64_t *len) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    int64_t pos = A.pos ? A.pos[i] : i;
+    int32_t a = G.es_src[pos], b = G.es_dst[pos];
+    int64_t s = 0, c = 0;
+    if (a != b) {
+        int64_t t1 = G.es_t[pos];
+        int64_t hi = anchor_hi(t1, delta, A.win_end ? A.win_end[i] : LLONG_MAX);
+        Binding f{-1, -1, -1, -1, -1};
+        f.set(0, a);
+        f.set(1, b);
+        Range rg = open_level(G, P, 1, f, t1, hi);
+        s = rg.cur;
+        c = rg.end - rg.cur;
+    }
+    beg[i] = s;
+    len[i] = c;
+}
+
+template <int LEN, int HIST>
+__global__ void __launch_bounds__(CG_TPB)
+    k_count_split(DevGraph G, MotifPlan P, int64_t delta, AnchorSet A, const int64_t *beg, const int64_t *off,
+                  const int64_t *n_items, uint64_t *total, uint64_t *slot_tot, uint64_t *hlo, uint64_t *hhi,
+                  uint64_t *per_anchor, int32_t *flag, unsigned long long *counter) {
+    static_assert(LEN >= 3, "split counting needs levels below level 1");
+    const int64_t T = *n_items, nA = A.n;
+    const int lane = threadIdx.x & (TM_WAVE - 1);
+    if constexpr (HIST == HM_LDS) {
+        for (int64_t k = threadIdx.x; k <= delta; k += blockDim.x) cg_bins[k] = 0;
+        __syncthreads();
+    }
+    const Level1 L1 = level1_list(G, P);
+    uint64_t lo = 0, hi = 0;
+    while (true) {
+        int64_t base = 0;
+        if (lane == 0) base = (int64_t)atomicAdd(counter, (unsigned long long)TM_WAVE);
+        base = __shfl(base, 0, TM_WAVE);
+        if (base >= T) break;
+        const int64_t k = base + lane;
+        if (k >= T) continue;
+        // the item's anchor: the last i with off[i] <= k (anchors with empty
+        // ranges share their successor's offset and are never the last)
+        int64_t l = 0, h = nA;
+        while (h - l > 1) {
+            int64_t mid = (l + h) >> 1;
+            if (off[mid] <= k) l = mid;
+            else h = mid;
+        }
+        const int64_t i = l;
+        const int64_t pos = A.pos ? A.pos[i] : i;
+        const int64_t t1 = G.es_t[pos];
+        const int64_t thi = anchor_hi(t1, delta, A.win_end ? A.win_end[i] : LLONG_MAX);
+        const int64_t j = beg[i] + (k - off[i]);
+        Binding f{-1, -1, -1, -1, -1};
+        f.set(0, G.es_src[pos]);
+        f.set(1, G.es_dst[pos]);
+        Acc acc{0, 0};
+        bool ok = true;
+        if (L1.nbr != nullptr) {
+            int32_t w = L1.nbr[j];
+            ok = !f.used(w);
+            f.set(L1.newnode, w);
+        }
+        if (ok) levels<2, LEN, HIST>(G, P, f, L1.t[j], t1, thi, acc, hlo, hhi);
+        if ((acc.lo | acc.hi) == 0) continue;
+        tm_add_u128(lo, hi, acc.lo, acc.hi);
+        if (per_anchor) {
+            unsigned long long old = atomicAdd((unsigned long long *)(per_anchor + i), (unsigned long long)acc.lo);
+            if (acc.hi || old + acc.lo < old) atomicOr(flag, 1);
+        }
+        if (slot_tot) {
+            int32_t s = A.slot[i];
+            tm_atomic_add_u128(slot_tot + 2 * (int64_t)s, slot_tot + 2 * (int64_t)s + 1, acc.lo, acc.hi);
+        }
+    }
+    wave_reduce_u128(lo, hi);
+    if (lane == 0 && total) tm_atomic_add_u128(total, total + 1, lo, hi);
+    if constexpr (HIST == HM_LDS) {
+        __syncthreads();
+        for (int64_t k = threadIdx.x; k <= delta; k += blockDim.x) {
+            uint64_t v = cg_bins[k];
+            if (v) tm_atomic_add_u128(hlo + k, hhi + k, v, 0);
+        }
+    }
+}
+
+// Per host thread (each call finishes on its stream before returning): the
+// work-queue head, and the level-1 range starts, item offsets and item count.
 thread_local DevBuf t_cg_counter;
+thread_local DevBuf t_cg_items;
 
 template <int LEN, int HIST>
 tm_status launch_len(int device, const DevGraph &G, const MotifPlan &P, int64_t delta, const AnchorSet &A,
@@ -262,15 +379,35 @@ tm_status launch_len(int device, const DevGraph &G, const MotifPlan &P, int64_t 
     int ncu = 0;
     TM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
     if (ncu <= 0) ncu = 256;
-    int64_t nb = tm_blocks(n, CG_TPB);
+    int64_t nb = tm_blocks(n, CG_TPB);  // persistent: at most 8 blocks per CU
     if (nb > (int64_t)ncu * 8) nb = (int64_t)ncu * 8;
-    void *tok = tm_prof_begin("count_generic", st);
     size_t lds = HIST == HM_LDS ? (size_t)(delta + 1) * 8 : 0;
-    hipLaunchKernelGGL((k_count_generic<LEN, HIST>), dim3((unsigned)nb), dim3(CG_TPB), lds, st, G, P, delta, A, total,
-                       slot_tot, hlo, hhi, per_anchor, flag, t_cg_counter.as<unsigned long long>());
-    tm_status s = tm_hip_status(hipGetLastError());
-    tm_prof_end(tok, st);
-    return s;
+    if constexpr (LEN >= 3) {
+        TM_TRY(t_cg_items.reserve((size_t)n * 16 + 64));
+        int64_t *beg = t_cg_items.as<int64_t>(), *off = beg + n, *n_items = off + n;
+        void *tok1 = tm_prof_begin("count_generic_ranges", st);
+        hipLaunchKernelGGL(k_level1_ranges, dim3(tm_blocks(n, CG_TPB)), dim3(CG_TPB), 0, st, G, P, delta, A, beg,
+                           off);
+        tm_status s1 = tm_hip_status(hipGetLastError());
+        tm_prof_end(tok1, st);
+        TM_TRY(s1);
+        TM_TRY(tm_scan_i64(off, n, n_items, st));
+        if (per_anchor) TM_HIP(hipMemsetAsync(per_anchor, 0, (size_t)n * 8, st));
+        void *tok = tm_prof_begin("count_generic", st);
+        hipLaunchKernelGGL((k_count_split<LEN, HIST>), dim3((unsigned)((int64_t)ncu * 8)), dim3(CG_TPB), lds, st, G,
+                           P, delta, A, beg, off, n_items, total, slot_tot, hlo, hhi, per_anchor, flag,
+                           t_cg_counter.as<unsigned long long>());
+        tm_status s = tm_hip_status(hipGetLastError());
+        tm_prof_end(tok, st);
+        return s;
+    } else {
+        void *tok = tm_prof_begin("count_generic", st);
+        hipLaunchKernelGGL((k_count_generic<LEN, HIST>), dim3((unsigned)nb), dim3(CG_TPB), lds, st, G, P, delta, A,
+                           total, slot_tot, hlo, hhi, per_anchor, flag, t_cg_counter.as<unsigned long long>());
+        tm_status s = tm_hip_status(hipGetLastError());
+        tm_prof_end(tok, st);
+        return s;
+    }
 }
 
 __global__ void k_weight(const uint64_t *hlo, const uint64_t *hhi, int64_t delta, int64_t L, double p, double *out) {

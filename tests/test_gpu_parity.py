@@ -167,7 +167,7 @@ def test_per_anchor_counts(tm):
     rng = np.random.default_rng(0)
     anchors = rng.choice(g.m, size=100, replace=False)
     win = rng.integers(0, 2500, size=100)
-    for M in (ti.TRIANGLE, ti.STAR4, ((0, 1), (1, 0), (0, 1))):
+    for M in (ti.TRIANGLE, ti.STAR4, ti.BIFAN, ((0, 1), (1, 0), (0, 1))):
         got = tm.count_anchors(G, M, 50, anchors, win_end=win)
         want = oracle.count_anchors(g.src, g.dst, g.t - g.t.min(), M, 50, anchors, win_hi=win)
         assert (got == want).all()
