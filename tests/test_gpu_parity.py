@@ -45,7 +45,10 @@ def close(a, b):
 
 MOTIFS = ti.three_edge_motifs() + [ti.CYCLE4, ti.STAR4, ti.OUTSTAR5, ti.BIFAN, ((0, 1),), ((0, 1), (1, 0)),
                                     ((0, 1), (2, 0)), ((0, 1), (0, 1)), ((0, 1), (1, 2), (2, 3)),
-                                    ((0, 1), (1, 2), (2, 0), (0, 1))]
+                                    ((0, 1), (1, 2), (2, 0), (0, 1)),
+                                    # second edge from an in-list; a repeated pair at level 2
+                                    ((0, 1), (2, 1), (1, 3), (3, 2)), ((0, 1), (1, 2), (0, 1), (2, 0))]
+FOUR = [M for M in MOTIFS if len(M) == 4]
 
 
 @pytest.mark.parametrize("seed", range(4))
@@ -60,10 +63,11 @@ def test_small_random_all_motifs(tm, seed):
             got = tm.count_exact(G, M, delta)
             want, _ = oracle.count(g.src, g.dst, g.t, M, delta, hist=False)
             assert got == want, (M, delta, got, want)
-    cnt, hlo, hhi = tm.count_exact_multi(G, MOTIFS[:8], 60, hist=True)
-    for i, M in enumerate(MOTIFS[:8]):
-        want, h = oracle.count(g.src, g.dst, g.t, M, 60)
-        assert cnt[i] == want and (hlo[i] == h).all() and not hhi[i].any()
+    for ms in (MOTIFS[:8], FOUR):
+        cnt, hlo, hhi = tm.count_exact_multi(G, ms, 60, hist=True)
+        for i, M in enumerate(ms):
+            want, h = oracle.count(g.src, g.dst, g.t, M, 60)
+            assert cnt[i] == want and (hlo[i] == h).all() and not hhi[i].any(), M
 
 
 @pytest.mark.parametrize("motif", [ti.TRIANGLE, ti.TWO_NODE_ALT, ((0, 1), (0, 2), (2, 0)), ti.CYCLE4])
