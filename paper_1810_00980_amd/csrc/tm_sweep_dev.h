@@ -73,6 +73,11 @@ __device__ inline int64_t owner_of(const int64_t *off, int64_t n, int64_t i) {
 // returned index, the a -> b count before it (*c0), and the end of t's
 // bucket (*be), past which no entry has time t.  A time in an empty bucket
 // is answered from the bucket array alone.
+constexpr int PAIR_SCAN = 2;  // entries a search reads together once that few are left
+
+// SCAN: finish with one load of the last PAIR_SCAN entries instead of
+// binary steps (shorter dependent chain, more registers)
+template <bool SCAN = false>
 __device__ inline int64_t pair_lower(const DevGraph &G, const PairMeta &m, const PairEnt *en, int64_t n, int64_t t,
                                      int64_t *c0, int64_t *be) {
     const PairBucket *bk = G.pbk + m.boff;
@@ -95,7 +100,7 @@ __device__ inline int64_t pair_lower(const DevGraph &G, const PairMeta &m, const
     // c: the a -> b count before entry hi, taken from the bucket or from the
     // last entry the search stepped back to (whole entries are loaded)
     int64_t c = lo == hi ? (int64_t)bb[0].c0 : (int64_t)bb[1].c0;
-    while (lo < hi) {
+    while (hi - lo > (SCAN ? PAIR_SCAN : 0)) {
         // branch-free step, so that the entry's time and count arrive in one load
         const int64_t mid = (lo + hi) >> 1;
         const PairEnt q = en[mid];
@@ -103,6 +108,21 @@ __device__ inline int64_t pair_lower(const DevGraph &G, const PairMeta &m, const
         lo = before ? mid + 1 : lo;
         hi = before ? hi : mid;
         c = before ? c : q.c0;
+    }
+    if (SCAN && lo < hi) {
+        // the last few entries are loaded together (index hi is an entry or the
+        // pair's sentinel) and the first one not before t is picked
+        PairEnt q[PAIR_SCAN];
+#pragma unroll
+        for (int k = 0; k < PAIR_SCAN; ++k) q[k] = en[lo + k < hi ? lo + k : hi];
+        int64_t r = hi;
+#pragma unroll
+        for (int k = PAIR_SCAN - 1; k >= 0; --k) {
+            const bool at = lo + k < hi && !(q[k].t < t);
+            r = at ? lo + k : r;
+            c = at ? q[k].c0 : c;
+        }
+        lo = r;
     }
     *c0 = c;
     return lo;
@@ -202,20 +222,22 @@ struct PairView {
         n = G.pbk[m.boff + m.nb].idx;
     }
     // entries with time < t
+    template <bool SCAN = false>
     __device__ void lt(const DevGraph &G, int64_t t, int64_t c[2]) const {
         int64_t k, be;
-        int64_t lo = pair_lower(G, m, en, n, t, &k, &be);
+        int64_t lo = pair_lower<SCAN>(G, m, en, n, t, &k, &be);
         c[0] = k;
         c[1] = lo - k;
     }
     // entries with time <= t (all of them for t = LLONG_MAX)
+    template <bool SCAN = false>
     __device__ void le(const DevGraph &G, int64_t t, int64_t c[2]) const {
         int64_t k, be, e;
         if (t == LLONG_MAX) {
             e = n;
             k = G.pbk[m.boff + m.nb].c0;
         } else {
-            e = pair_lower(G, m, en, n, t + 1, &k, &be);
+            e = pair_lower<SCAN>(G, m, en, n, t + 1, &k, &be);
         }
         c[0] = k;
         c[1] = e - k;
@@ -553,14 +575,14 @@ __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t 
                     tcache.p = pair_find(G, y1, yj, tcache.pv);
                     if (tcache.p >= 0) {
                         int64_t a1[2];
-                        tcache.pv.le(G, t1, a1);
+                        tcache.pv.template le<true>(G, t1, a1);
                         tcache.f_ti1[0] = (int32_t)a1[0];
                         tcache.f_ti1[1] = (int32_t)a1[1];
                     }
                 }
                 if (tcache.p >= 0) {
                     int64_t up[2];
-                    tcache.pv.lt(G, tj, up);
+                    tcache.pv.template lt<true>(G, tj, up);
                     const uint32_t sw = y1 > yj ? 1u : 0u;
                     uint64_t c01 = (uint64_t)(up[sw] - tcache.f_ti1[sw]);
                     uint64_t c10 = (uint64_t)(up[sw ^ 1u] - tcache.f_ti1[sw ^ 1u]);
