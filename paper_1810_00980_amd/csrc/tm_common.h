@@ -208,7 +208,8 @@ tm_status tm_build_exact_tables(tm_graph *g, const uint32_t *ent_nl, const uint3
 // ------------------------------------------------------------ primitives
 
 // Exclusive prefix sum of n int64 values, in place; *total (nullable, device)
-// receives the sum.  Uses tmp workspace it allocates itself.
+// receives the sum.  Asynchronous on st; its block sums live in a per-thread
+// workspace that grows on demand (a host thread scans on one stream at a time).
 tm_status tm_scan_i64(int64_t *d, int64_t n, int64_t *d_total, hipStream_t st);
 
 // Stable LSD radix sort of (key, val) pairs by the low `bits` bits of key.

@@ -148,27 +148,55 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t *kin, 
 
 }  // namespace
 
+namespace {
+
+// Block sums of every level of the scan hierarchy, per host thread, grown on
+// demand: a scan then neither allocates nor waits, so a chain of scans and
+// kernels on one stream runs without host round trips.  A host thread issues
+// its scans on one stream at a time (every library call finishes its work
+// before returning), so the next scan's writes come after this one's reads.
+thread_local DevBuf t_scan_ws;
+
+int64_t scan_ws_elems(int64_t n) {
+    int64_t tot = 0;
+    while (true) {
+        const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+        tot += nb;
+        if (nb <= 1) return tot;
+        n = nb;
+    }
+}
+
+tm_status scan_levels(int64_t *d, int64_t n, int64_t *d_total, int64_t *ws, hipStream_t st) {
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    int64_t *bsum = ws;
+    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, d, n, bsum);
+    TM_HIP(hipGetLastError());
+    if (nb > 1) {
+        TM_TRY(scan_levels(bsum, nb, d_total, ws + nb, st));
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, d, n, bsum);
+        TM_HIP(hipGetLastError());
+    } else if (d_total) {
+        hipLaunchKernelGGL(k_copy1, dim3(1), dim3(1), 0, st, d_total, bsum);
+        TM_HIP(hipGetLastError());
+    }
+    return TM_OK;
+}
+
+}  // namespace
+
 tm_status tm_scan_i64(int64_t *d, int64_t n, int64_t *d_total, hipStream_t st) {
     if (n <= 0) {
         if (d_total) TM_HIP(hipMemsetAsync(d_total, 0, sizeof(int64_t), st));
         return TM_OK;
     }
-    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
-    DevBuf bsum;
-    TM_TRY(bsum.alloc((size_t)nb * sizeof(int64_t)));
-    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, d, n, bsum.as<int64_t>());
-    TM_HIP(hipGetLastError());
-    if (nb > 1) {
-        TM_TRY(tm_scan_i64(bsum.as<int64_t>(), nb, d_total, st));
-        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, d, n, bsum.as<int64_t>());
-        TM_HIP(hipGetLastError());
-    } else if (d_total) {
-        hipLaunchKernelGGL(k_copy1, dim3(1), dim3(1), 0, st, d_total, bsum.as<int64_t>());
-        TM_HIP(hipGetLastError());
+    const size_t need = (size_t)scan_ws_elems(n) * sizeof(int64_t);
+    if (t_scan_ws.bytes < need) {
+        // earlier scans of this thread may still read the old buffer
+        TM_HIP(hipStreamSynchronize(st));
+        TM_TRY(t_scan_ws.reserve(need));
     }
-    // bsum must outlive the kernels that read it
-    TM_HIP(hipStreamSynchronize(st));
-    return TM_OK;
+    return scan_levels(d, n, d_total, t_scan_ws.as<int64_t>(), st);
 }
 
 tm_status tm_radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st) {
