@@ -115,15 +115,22 @@ __global__ void k_ex_values(DevGraph G, const uint32_t *ent_nl, const uint32_t *
     }
 }
 
-// column-major exclusive prefix sums -> rows[(view * S + slot) * 12 + c]
-__global__ void k_ex_rows(const uint64_t *cols, int64_t S, uint64_t *rows) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
+// column-major exclusive prefix sums -> rows[(view * S + slot) * 12 + c].
+// A block moves EX_T slots of one view through LDS: it reads the 12 column
+// runs coalesced and writes the 12 * EX_T row words as one contiguous run.
+constexpr int EX_T = 256;
+__global__ void __launch_bounds__(EX_T) k_ex_rows(const uint64_t *cols, int64_t S, uint64_t *rows) {
+    __shared__ uint64_t tile[EX_T * 13];  // rows padded to 13 words against bank conflicts
+    const int w = (int)blockIdx.y;
+    const int64_t s0 = (int64_t)blockIdx.x * EX_T;
+    const int64_t ns = (S - s0) < EX_T ? (S - s0) : EX_T;
 #pragma unroll
-    for (int w = 0; w < 2; ++w) {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) rows[((int64_t)w * S + s) * 12 + c] = cols[(int64_t)(w * 12 + c) * S + s];
+    for (int c = 0; c < 12; ++c) {
+        if (threadIdx.x < ns) tile[threadIdx.x * 13 + c] = cols[(int64_t)(w * 12 + c) * S + s0 + threadIdx.x];
     }
+    __syncthreads();
+    uint64_t *out = rows + ((int64_t)w * S + s0) * 12;
+    for (int k = threadIdx.x; k < (int)ns * 12; k += EX_T) out[k] = tile[(k / 12) * 13 + k % 12];
 }
 
 }  // namespace
@@ -151,7 +158,7 @@ tm_status tm_build_exact_tables(tm_graph *g, const uint32_t *ent_nl, const uint3
     TM_HIP(hipGetLastError());
     for (int c = 0; c < 24; ++c) TM_TRY(tm_scan_i64(cols.as<int64_t>() + (int64_t)c * S, S, nullptr, st));
     TM_TRY(g->ex_rows.alloc((size_t)S * 24 * 8));
-    hipLaunchKernelGGL(k_ex_rows, dim3(tm_blocks(S, TPB)), dim3(TPB), 0, st, cols.as<uint64_t>(), S,
+    hipLaunchKernelGGL(k_ex_rows, dim3((unsigned)((S + EX_T - 1) / EX_T), 2), dim3(EX_T), 0, st, cols.as<uint64_t>(), S,
                        g->ex_rows.as<uint64_t>());
     TM_HIP(hipGetLastError());
     TM_HIP(hipStreamSynchronize(st));
