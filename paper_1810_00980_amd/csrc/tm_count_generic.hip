@@ -1,5 +1,7 @@
-// Generic per-window exact counter: one anchor edge (the motif's first
-// edge) per lane, backtracking over time-bounded incidence lists.
+// Generic per-window exact counter: backtracking from each anchor edge (the
+// motif's first edge) over time-bounded incidence lists.  Motifs of one or
+// two edges take one anchor per lane (k_count_generic); longer ones take one
+// (anchor, level-1 entry) pair per lane (k_count_split).
 //
 // For an anchor e1 = (a, b, t1) in a window ending at time W, every later
 // motif edge r must have a time in (t_{r-1}, min(t1 + delta, W)] (strictly
