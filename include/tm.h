@@ -207,14 +207,19 @@ tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, const tm_motif 
  * over the b shifts.  Shift k takes its shift from draw (0, k, domain 0)
  * and its window uniforms from draws (j, k, domain 1) of the seed's
  * Philox4x32-10 stream, so shift 0 is tm_estimate's shift.
- * Motifs: three-edge motifs only (TM_EUNSUPPORTED otherwise), n_motifs >= 1.
+ * Motifs: up to four edges, prefix-connected (TM_EUNSUPPORTED otherwise),
+ * n_motifs >= 1.  When every motif has three edges, one windowed sweep per
+ * shift gives each kept window's exact fixed-point Y_{s,j}; otherwise each
+ * kept window and motif is counted by the generic counter with its duration
+ * histogram, weighted in FP64 in ascending Delta (delta up to 2^26).
  * delta >= 1, c >= 2, r > 0 and finite, b >= 1.  estimates: host array of
  * n_motifs.  info (nullable, host memory, caller-owned): n_kept (out) = the
  * kept windows over all shifts; with cap > 0 the first cap of them, in order
  * of (k, j), are described in win_k[cap], win_j[cap] (1-based), win_q[cap]
  * and win_y[cap * n_motifs] (one row per window: Y_{s,j} of each motif).
  * Errors: TM_EINVAL (bad arguments, or null info arrays with cap > 0),
- * TM_EUNSUPPORTED (a motif without three edges, more than 2^30 windows),
+ * TM_EUNSUPPORTED (a motif over four edges or not prefix-connected, more
+ * than 2^30 windows, delta above 2^26 with a motif of other than three edges),
  * TM_ENOMEM, TM_EDEVICE.  Outputs are written only on TM_OK.
  */
 /*

@@ -315,7 +315,7 @@ def estimate_multi(g: Graph, motifs, delta: int, c: int, p: float, seed: int, st
 
 def estimate_q(g: Graph, motifs, delta: int, c: int, r: float, b: int, seed: int, cap: int = 4096, stream=None):
     """Algorithm 1 with b shifts and window probabilities q_j = min(1, r |T_j| / |T|)
-    (three-edge motifs).  Returns (estimates, windows): windows holds, for the
+    (motifs of up to four edges).  Returns (estimates, windows): windows holds, for the
     first `cap` kept windows in order of (shift, window), arrays k, j, q and
     y (Y_{s,j} per motif, shape [windows, motifs]), and n_kept over all shifts."""
     k = len(motifs)

@@ -553,7 +553,16 @@ tm_status estimate_q_impl(const tm_graph *g, int32_t n, const tm_motif *motifs, 
     TM_TRY(check_est_args(g, delta, c, 1.0, &L));
     std::vector<int> codes;
     uint64_t mask;
-    if (!all_sweep_codes(n, motifs, &codes, &mask)) return TM_EUNSUPPORTED;
+    // three-edge motifs: one windowed sweep per shift (exact fixed-point
+    // sums); otherwise the generic counter per kept window and motif, with
+    // its duration histogram weighted in FP64
+    const bool sweep = all_sweep_codes(n, motifs, &codes, &mask);
+    std::vector<MotifPlan> plans;
+    if (!sweep) {
+        plans.resize((size_t)n);
+        for (int32_t i = 0; i < n; ++i) TM_TRY(check_graph_motif(g, &motifs[i], delta, &plans[(size_t)i]));
+        if (delta > TM_MAX_HIST_DELTA) return TM_EUNSUPPORTED;
+    }
     const int64_t J = 1 + (g->t_span + L - 1) / L;
     if (J > ((int64_t)1 << 30)) return TM_EUNSUPPORTED;
     std::vector<double> zs(n, 0.0), zc(n, 0.0);
@@ -571,6 +580,15 @@ tm_status estimate_q_impl(const tm_graph *g, int32_t n, const tm_motif *motifs, 
         std::vector<int64_t> flag_h((size_t)J);
         std::vector<double> q_h((size_t)J);
         std::vector<uint64_t> win_h;
+        std::vector<double> y_h;  // Y_{s,j} of each kept window (rows) and motif
+        std::vector<int64_t> tt;  // generic path: the sorted normalised times
+        DevBuf hist, ydev, ap, we;
+        if (!sweep) {
+            tt.resize((size_t)g->m);
+            TM_HIP(hipMemcpyAsync(tt.data(), g->es_t.p, (size_t)g->m * 8, hipMemcpyDeviceToHost, st));
+            TM_TRY(hist.alloc((size_t)(delta + 1) * 16));
+            TM_TRY(ydev.alloc((size_t)n * 8));
+        }
         for (int32_t k = 0; k < b; ++k) {
             const int64_t s = -(int64_t)(tm_draw(seed, 0, (uint32_t)k, 0) % (uint64_t)L);
             hipLaunchKernelGGL(k_q_windows, dim3(tm_blocks(J, TPB)), dim3(TPB), 0, st, g->es_t.as<int64_t>(), g->m,
@@ -588,22 +606,62 @@ tm_status estimate_q_impl(const tm_graph *g, int32_t n, const tm_motif *motifs, 
             TM_HIP(hipStreamSynchronize(st));
             std::vector<double> zk(n, 0.0), zkc(n, 0.0);
             if (K > 0) {
-                TM_TRY(win.reserve((size_t)K * 144 * 8));
-                TM_HIP(hipMemsetAsync(win.p, 0, (size_t)K * 144 * 8, st));
-                SweepOut so;
-                TM_TRY(run_sweep(g, mask, 1, delta, 3, s, L, seed, 1.0, &so, {}, nullptr, st, kidx.as<int32_t>(),
-                                 win.as<uint64_t>()));
-                win_h.resize((size_t)K * 144);
-                TM_HIP(hipMemcpyAsync(win_h.data(), win.p, (size_t)K * 144 * 8, hipMemcpyDeviceToHost, st));
-                TM_HIP(hipStreamSynchronize(st));
+                y_h.assign((size_t)K * n, 0.0);
+                if (sweep) {
+                    TM_TRY(win.reserve((size_t)K * 144 * 8));
+                    TM_HIP(hipMemsetAsync(win.p, 0, (size_t)K * 144 * 8, st));
+                    SweepOut so;
+                    TM_TRY(run_sweep(g, mask, 1, delta, 3, s, L, seed, 1.0, &so, {}, nullptr, st,
+                                     kidx.as<int32_t>(), win.as<uint64_t>()));
+                    win_h.resize((size_t)K * 144);
+                    TM_HIP(hipMemcpyAsync(win_h.data(), win.p, (size_t)K * 144 * 8, hipMemcpyDeviceToHost, st));
+                    TM_HIP(hipStreamSynchronize(st));
+                    for (int64_t kk = 0; kk < K; ++kk) {
+                        for (int32_t i = 0; i < n; ++i) {
+                            const uint64_t *v = win_h.data() + (size_t)kk * 144 + 4 * (size_t)codes[(size_t)i];
+                            y_h[(size_t)kk * n + i] = u128_scaled(v[2], v[3], 1.0 / 4503599627370496.0);
+                        }
+                    }
+                } else {
+                    // anchors of window j: edges with normalised time in
+                    // [s + (j-1) L, s + j L - 1], every later edge up to that end
+                    int64_t kk = 0;
+                    for (int64_t j = 1; j <= J; ++j) {
+                        if (!flag_h[(size_t)j - 1]) continue;
+                        const int64_t lo = s + (j - 1) * L, hi = s + j * L - 1;
+                        const int64_t a0 = std::lower_bound(tt.begin(), tt.end(), lo) - tt.begin();
+                        const int64_t a1 = std::upper_bound(tt.begin(), tt.end(), hi) - tt.begin();
+                        const int64_t nA = a1 - a0;
+                        if (nA > 0) {
+                            std::vector<int64_t> pos((size_t)nA), wend((size_t)nA, hi);
+                            for (int64_t x = 0; x < nA; ++x) pos[(size_t)x] = a0 + x;
+                            TM_TRY(ap.reserve((size_t)nA * 8));
+                            TM_TRY(we.reserve((size_t)nA * 8));
+                            TM_HIP(hipMemcpyAsync(ap.p, pos.data(), (size_t)nA * 8, hipMemcpyHostToDevice, st));
+                            TM_HIP(hipMemcpyAsync(we.p, wend.data(), (size_t)nA * 8, hipMemcpyHostToDevice, st));
+                            const AnchorSet A{nA, ap.as<int64_t>(), we.as<int64_t>(), nullptr, nullptr};
+                            uint64_t *hlo = hist.as<uint64_t>(), *hhi = hlo + (delta + 1);
+                            for (int32_t i = 0; i < n; ++i) {
+                                TM_HIP(hipMemsetAsync(hist.p, 0, (size_t)(delta + 1) * 16, st));
+                                TM_TRY(tm_count_generic(g, plans[(size_t)i], delta, A, nullptr, nullptr, hlo, hhi,
+                                                        nullptr, nullptr, st));
+                                TM_TRY(tm_weight(hlo, hhi, delta, L, 1.0, ydev.as<double>() + i, st));
+                            }
+                            TM_HIP(hipMemcpyAsync(y_h.data() + (size_t)kk * n, ydev.p, (size_t)n * 8,
+                                                  hipMemcpyDeviceToHost, st));
+                            // pos and wend are read by the copies above
+                            TM_HIP(hipStreamSynchronize(st));
+                        }
+                        ++kk;
+                    }
+                }
                 int64_t kk = 0;
                 for (int64_t j = 1; j <= J; ++j) {
                     if (!flag_h[(size_t)j - 1]) continue;
                     const double q = q_h[(size_t)j - 1];
                     const bool rec = n_kept < cap;
                     for (int32_t i = 0; i < n; ++i) {
-                        const uint64_t *v = win_h.data() + (size_t)kk * 144 + 4 * (size_t)codes[(size_t)i];
-                        const double y = u128_scaled(v[2], v[3], 1.0 / 4503599627370496.0);
+                        const double y = y_h[(size_t)kk * n + i];
                         neumaier_add(zk[(size_t)i], zkc[(size_t)i], y / q);
                         if (rec) ry.push_back(y);
                     }

@@ -229,6 +229,31 @@ def test_estimate_q_matches_oracle(tm):
         assert close(a, b_)
 
 
+def test_estimate_q_four_edge_motifs(tm):
+    """Edge-proportional estimates of four-edge motifs (generic counter per
+    kept window, FP64 weighting of its duration histogram), alone and mixed
+    with a three-edge motif: kept windows exactly the oracle's, Y_{s,j} and
+    estimates within 1e-12."""
+    cases = [
+        (ti.zipf_graph(300, 4000, 1.5, 400_000, 61), 600, 4, 3.0, 3, 2, [ti.BIFAN, ti.CYCLE4, ti.STAR4]),
+        (ti.random_small_graph(7, 1500, 5000, 62, allow_self_loops=True), 50, 3, 5.0, 2, 7,
+         [ti.TRIANGLE, ti.CYCLE4]),
+    ]
+    for g, delta, c, r, b, seed, motifs in cases:
+        say("estimate_q four-edge", g.m, delta, c, r, b, seed)
+        G = load(tm, g)
+        est, win = tm.estimate_q(G, motifs, delta, c, r, b, seed)
+        assert win["n_kept"] > 0
+        for i, M in enumerate(motifs):
+            o = oracle.estimate_q(g.src, g.dst, g.t, M, delta, c, r, b, seed)
+            assert close(est[i], o["Z"]), (M, est[i], o["Z"])
+            assert win["n_kept"] == o["n_kept"]
+            assert np.array_equal(win["k"], o["k"]) and np.array_equal(win["j"], o["j"])
+            assert np.array_equal(win["q"], o["q"])
+            for y, yo in zip(win["y"][:, i], o["y"]):
+                assert close(y, yo), (M, y, yo)
+
+
 def test_estimate_q_edge_cases(tm):
     g = ti.random_small_graph(5, 200, 1000, 54)
     G = load(tm, g)
@@ -245,8 +270,8 @@ def test_estimate_q_edge_cases(tm):
         args.update(bad)
         with pytest.raises(tm.TMError):
             tm.estimate_q(G, THREE[:1], args["delta"], args["c"], args["r"], args["b"], 0)
-    with pytest.raises(tm.TMError):
-        tm.estimate_q(G, [ti.CYCLE4], 20, 3, 2.0, 1, 0)
+    with pytest.raises(tm.TMError):  # the second edge touches no earlier node
+        tm.estimate_q(G, [((0, 1), (2, 3), (0, 2), (1, 3))], 20, 3, 2.0, 1, 0)
 
 
 def test_bifan_zipf(tm):
