@@ -232,10 +232,12 @@ tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, const tm_motif 
  * order on the device in bounded chunks (TM_EINVAL when unsorted) and
  * validates the ids of every window it reads.  Per kept window it uploads
  * that window's edges, builds a graph of them and sweeps it, so the device
- * holds one window at a time.  Results are those of tm_estimate_multi on the
- * whole graph with the same seed, to the last bit (both sum the same exact
- * fixed-point integers).  Motifs: three-edge motifs only
- * (TM_EUNSUPPORTED otherwise).  estimates[n_motifs], kept_counts[n_motifs]
+ * holds one window at a time.  Each motif's result is tm_estimate's on the
+ * whole graph with the same seed, to the last bit: three-edge motifs sum the
+ * same exact fixed-point integers over the window sweeps; other motifs (up
+ * to four edges, prefix-connected; delta up to 2^26) add the windows'
+ * integer duration histograms on the device and weight the total once, as
+ * tm_estimate does.  Kept counts are exact.  estimates[n_motifs], kept_counts[n_motifs]
  * (nullable): host.  info (nullable, host): the shift, J, the kept windows,
  * the edges of the largest kept window (what is resident at once) and the
  * device bytes of its graph.  Errors as tm_estimate_multi and tm_load_graph.

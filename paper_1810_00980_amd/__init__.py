@@ -335,8 +335,8 @@ def estimate_q(g: Graph, motifs, delta: int, c: int, r: float, b: int, seed: int
 
 def estimate_stream(src, dst, t, n_nodes: int, motifs, delta: int, c: int, p: float, seed: int, stream=None):
     """Algorithm 1 over host arrays sorted by time, one kept window on the
-    device at a time (three-edge motifs).  Returns (estimates, kept counts,
-    info dict)."""
+    device at a time (motifs of up to four edges).  Returns (estimates, kept
+    counts, info dict)."""
     src = np.ascontiguousarray(src, dtype=np.int32)
     dst = np.ascontiguousarray(dst, dtype=np.int32)
     t = np.ascontiguousarray(t, dtype=np.int64)

@@ -703,9 +703,33 @@ tm_status estimate_stream_impl(const int32_t *src, const int32_t *dst, const int
     if (delta < 1 || c < 2 || !(p > 0.0 && p <= 1.0) || delta > INT64_MAX / c) return TM_EINVAL;
     const int64_t L = c * delta;
     if (L > INT64_MAX / 4) return TM_EINVAL;
-    std::vector<int> codes;
-    uint64_t mask;
-    if (!all_sweep_codes(n, motifs, &codes, &mask)) return TM_EUNSUPPORTED;
+    // three-edge motifs go through the sweep of each window graph; the others
+    // through the generic counter, whose duration histograms add up over the
+    // windows on the device and are weighted once at the end
+    std::vector<int> codes((size_t)n, -1);
+    std::vector<MotifPlan> plans((size_t)n);
+    std::vector<int32_t> gen;
+    uint64_t mask = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        TM_TRY(tm_make_plan(&motifs[i], &plans[(size_t)i]));
+        const int code = tm_sweep_code_of(&motifs[i]);
+        if (code >= 0) {
+            codes[(size_t)i] = code;
+            mask |= 1ull << code;
+        } else {
+            gen.push_back(i);
+        }
+    }
+    if (!gen.empty() && delta > TM_MAX_HIST_DELTA) return TM_EUNSUPPORTED;
+    const size_t ng = gen.size(), nbins = (size_t)delta + 1;
+    DevBuf ghist, gtot, gz;
+    if (ng > 0) {
+        TM_TRY(ghist.alloc(ng * nbins * 16));
+        TM_TRY(gtot.alloc(ng * 16));
+        TM_TRY(gz.alloc(ng * 8));
+        TM_HIP(hipMemsetAsync(ghist.p, 0, ghist.bytes, st));
+        TM_HIP(hipMemsetAsync(gtot.p, 0, gtot.bytes, st));
+    }
     // the stream is read on the host: device arrays are refused
     for (const void *ptr : {(const void *)src, (const void *)dst, (const void *)t}) {
         if (!ptr) continue;
@@ -777,18 +801,51 @@ tm_status estimate_stream_impl(const int32_t *src, const int32_t *dst, const int
             tm_graph *gw = nullptr;
             TM_TRY(tm_load_graph_ex(src + a, dst + a, t + a, b - a, n_nodes, TM_LOAD_NO_EXACT_TABLES, st, &gw));
             SweepOut so;
-            const tm_status r = run_sweep(gw, mask, 1, delta, 0, 0, L, seed, 1.0, &so, {}, nullptr, st);
+            tm_status r = TM_OK;
+            if (mask) r = run_sweep(gw, mask, 1, delta, 0, 0, L, seed, 1.0, &so, {}, nullptr, st);
+            // every anchor of the window graph: its instances are the window's
+            const AnchorSet A{gw->m, nullptr, nullptr, nullptr, nullptr};
+            for (size_t x = 0; x < ng && r == TM_OK; ++x) {
+                uint64_t *hlo = ghist.as<uint64_t>() + x * nbins * 2, *hhi = hlo + nbins;
+                r = tm_count_generic(gw, plans[(size_t)gen[x]], delta, A, gtot.as<uint64_t>() + 2 * x, nullptr, hlo,
+                                     hhi, nullptr, nullptr, st);
+            }
+            // the counts read the window graph until they finish
+            const hipError_t e = hipStreamSynchronize(st);
             peak = std::max(peak, gw->device_bytes);
             tm_free_graph(gw);
             if (r != TM_OK) return r;
-            for (int k = 0; k < 36; ++k) {
-                csum[k] += ((unsigned __int128)so.v[4 * k + 1] << 64) | so.v[4 * k];
-                wsum[k] += ((unsigned __int128)so.v[4 * k + 3] << 64) | so.v[4 * k + 2];
+            if (e != hipSuccess) return tm_hip_status(e);
+            if (mask) {
+                for (int k = 0; k < 36; ++k) {
+                    csum[k] += ((unsigned __int128)so.v[4 * k + 1] << 64) | so.v[4 * k];
+                    wsum[k] += ((unsigned __int128)so.v[4 * k + 3] << 64) | so.v[4 * k + 2];
+                }
             }
+        }
+    }
+    std::vector<double> gz_h(ng);
+    std::vector<uint64_t> gtot_h(2 * ng);
+    if (ng > 0) {
+        for (size_t x = 0; x < ng; ++x) {
+            uint64_t *hlo = ghist.as<uint64_t>() + x * nbins * 2, *hhi = hlo + nbins;
+            TM_TRY(tm_weight(hlo, hhi, delta, L, p, gz.as<double>() + x, st));
+        }
+        TM_HIP(hipMemcpyAsync(gz_h.data(), gz.p, ng * 8, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipMemcpyAsync(gtot_h.data(), gtot.p, ng * 16, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+    }
+    for (size_t x = 0; x < ng; ++x) {
+        const int32_t i = gen[x];
+        est[i] = gz_h[x];
+        if (kept) {
+            kept[i].lo = gtot_h[2 * x];
+            kept[i].hi = gtot_h[2 * x + 1];
         }
     }
     for (int32_t i = 0; i < n; ++i) {
         const int k = codes[(size_t)i];
+        if (k < 0) continue;
         est[i] = u128_scaled((uint64_t)wsum[k], (uint64_t)(wsum[k] >> 64), 1.0 / 4503599627370496.0) / p;
         if (kept) {
             kept[i].lo = (uint64_t)csum[k];

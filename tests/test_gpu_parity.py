@@ -295,8 +295,8 @@ def test_bifan_zipf(tm):
 def test_estimate_stream_equals_in_memory(tm):
     """Streaming (kept windows in time order, one window's edges on the
     device at a time) gives the in-memory estimates and kept counts to the
-    last bit, and the oracle's estimates within 1e-12; unsorted streams are
-    refused."""
+    last bit, and the oracle's estimates within 1e-12, for three- and
+    four-edge motifs; unsorted streams are refused."""
     cases = [
         (ti.random_small_graph(6, 1500, 8000, 81, allow_self_loops=True), 40, 3, 0.5, 2, True),
         (ti.config_small_dense(5), 3600, 10, 0.3, 1, True),
@@ -320,8 +320,24 @@ def test_estimate_stream_equals_in_memory(tm):
     z, k, info = tm.estimate_stream(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int64), 4,
                                     THREE[:2], 10, 2, 0.5, 0)
     assert z == [0.0, 0.0] and k == [0, 0] and info["n_kept"] == 0
-    with pytest.raises(tm.TMError):
-        tm.estimate_stream(g.src[:1], g.dst[:1], g.t[:1], g.n, [ti.CYCLE4], 20, 3, 0.5, 0)
+    with pytest.raises(tm.TMError):  # the second edge touches no earlier node
+        tm.estimate_stream(g.src[:1], g.dst[:1], g.t[:1], g.n, [((0, 1), (2, 3), (0, 2), (1, 3))], 20, 3, 0.5, 0)
+    # four-edge motifs, alone and mixed with three-edge ones: tm_estimate's
+    # value of each motif to the last bit, its kept count, and the oracle's
+    for g, delta, c, p, seed, motifs in (
+            (ti.zipf_graph(400, 6000, 1.5, 600_000, 85), 600, 4, 0.4, 3, [ti.BIFAN, ti.CYCLE4, ti.STAR4]),
+            (ti.random_small_graph(7, 1500, 6000, 86, allow_self_loops=True), 50, 3, 0.5, 1,
+             [ti.TRIANGLE, ti.CYCLE4, THREE[3]])):
+        say("estimate_stream four-edge", g.m, delta, c, p, seed)
+        o = np.argsort(g.t, kind="stable")
+        est, kc, info = tm.estimate_stream(g.src[o], g.dst[o], g.t[o], g.n, motifs, delta, c, p, seed)
+        assert info["n_kept"] > 0
+        G = load(tm, g)
+        _, k2 = tm.estimate_multi(G, motifs, delta, c, p, seed)
+        assert kc == k2
+        for M, z in zip(motifs, est):
+            assert z == tm.estimate(G, M, delta, c, p, seed), M
+            assert close(z, oracle.estimate(g.src, g.dst, g.t, M, delta, c, p, seed)["Z"]), M
     # device arrays are refused (the stream is read on the host)
     import ctypes
     s_dev, d_dev, t_dev = to_dev(ti.random_small_graph(5, 50, 1000, 84))
