@@ -300,7 +300,7 @@ tm_status select_kept(const tm_graph *g, int64_t L, uint64_t seed, double p, hip
 // clamped), and is kept when the uniform of draw (j, k, domain 1) is below
 // q_j.  flag[j-1], q[j-1].
 __global__ void k_q_windows(const int64_t *es_t, int64_t m, int64_t J, int64_t s, int64_t L, double r,
-                            uint64_t seed, uint32_t k, int64_t *flag, double *q) {
+                            uint64_t seed, uint32_t k, int64_t *flag, double *q, int64_t *range) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
     if (j > J) return;
     const int64_t lo = s + (j - 1) * L, hi = s + j * L - 1;
@@ -323,6 +323,10 @@ __global__ void k_q_windows(const int64_t *es_t, int64_t m, int64_t J, int64_t s
     const double u = (double)(x >> 11) * (1.0 / 9007199254740992.0);
     flag[j - 1] = u < qj ? 1 : 0;
     q[j - 1] = qj;
+    if (range) {  // the window's edges: sorted positions [first, a)
+        range[2 * (j - 1)] = first;
+        range[2 * (j - 1) + 1] = a;
+    }
 }
 
 // kidx[j] = rank of window j among the kept ones (scan: exclusive sums of
@@ -581,18 +585,19 @@ tm_status estimate_q_impl(const tm_graph *g, int32_t n, const tm_motif *motifs, 
         std::vector<double> q_h((size_t)J);
         std::vector<uint64_t> win_h;
         std::vector<double> y_h;  // Y_{s,j} of each kept window (rows) and motif
-        std::vector<int64_t> tt;  // generic path: the sorted normalised times
-        DevBuf hist, ydev, ap, we;
+        std::vector<int64_t> rng_h;  // generic path: each window's sorted edge range
+        DevBuf hist, ydev, ap, we, rng;
         if (!sweep) {
-            tt.resize((size_t)g->m);
-            TM_HIP(hipMemcpyAsync(tt.data(), g->es_t.p, (size_t)g->m * 8, hipMemcpyDeviceToHost, st));
+            rng_h.resize((size_t)J * 2);
+            TM_TRY(rng.alloc((size_t)J * 16));
             TM_TRY(hist.alloc((size_t)(delta + 1) * 16));
             TM_TRY(ydev.alloc((size_t)n * 8));
         }
         for (int32_t k = 0; k < b; ++k) {
             const int64_t s = -(int64_t)(tm_draw(seed, 0, (uint32_t)k, 0) % (uint64_t)L);
             hipLaunchKernelGGL(k_q_windows, dim3(tm_blocks(J, TPB)), dim3(TPB), 0, st, g->es_t.as<int64_t>(), g->m,
-                               J, s, L, r, seed, (uint32_t)k, flag.as<int64_t>(), qd.as<double>());
+                               J, s, L, r, seed, (uint32_t)k, flag.as<int64_t>(), qd.as<double>(),
+                               sweep ? nullptr : rng.as<int64_t>());
             TM_HIP(hipGetLastError());
             TM_HIP(hipMemcpyAsync(scan.p, flag.p, (size_t)J * 8, hipMemcpyDeviceToDevice, st));
             TM_TRY(tm_scan_i64(scan.as<int64_t>(), J, tot.as<int64_t>(), st));
@@ -603,6 +608,7 @@ tm_status estimate_q_impl(const tm_graph *g, int32_t n, const tm_motif *motifs, 
             TM_HIP(hipMemcpyAsync(&K, tot.p, 8, hipMemcpyDeviceToHost, st));
             TM_HIP(hipMemcpyAsync(flag_h.data(), flag.p, (size_t)J * 8, hipMemcpyDeviceToHost, st));
             TM_HIP(hipMemcpyAsync(q_h.data(), qd.p, (size_t)J * 8, hipMemcpyDeviceToHost, st));
+            if (!sweep) TM_HIP(hipMemcpyAsync(rng_h.data(), rng.p, (size_t)J * 16, hipMemcpyDeviceToHost, st));
             TM_HIP(hipStreamSynchronize(st));
             std::vector<double> zk(n, 0.0), zkc(n, 0.0);
             if (K > 0) {
@@ -628,9 +634,8 @@ tm_status estimate_q_impl(const tm_graph *g, int32_t n, const tm_motif *motifs, 
                     int64_t kk = 0;
                     for (int64_t j = 1; j <= J; ++j) {
                         if (!flag_h[(size_t)j - 1]) continue;
-                        const int64_t lo = s + (j - 1) * L, hi = s + j * L - 1;
-                        const int64_t a0 = std::lower_bound(tt.begin(), tt.end(), lo) - tt.begin();
-                        const int64_t a1 = std::upper_bound(tt.begin(), tt.end(), hi) - tt.begin();
+                        const int64_t hi = s + j * L - 1;
+                        const int64_t a0 = rng_h[2 * ((size_t)j - 1)], a1 = rng_h[2 * ((size_t)j - 1) + 1];
                         const int64_t nA = a1 - a0;
                         if (nA > 0) {
                             std::vector<int64_t> pos((size_t)nA), wend((size_t)nA, hi);
