@@ -183,6 +183,118 @@ SideStreams *side_streams(int dev) {
     return &S;
 }
 
+// The four 2-node motifs alone, weighted: grouped by static edge.  Their
+// instances lie on one unordered pair, so each anchor (an entry of the
+// pair's time-sorted list, i.e. an edge) scans only the later entries of its
+// own pair instead of its endpoint's whole list (8x fewer entries on the
+// bursty Zipf graphs at delta = 86400).  An entry's direction is the step of
+// the a -> b counts at it.  Codes and counters follow the forward sweep:
+// e1 = the anchor, x its source; a later entry j (t1 < t_j <= hi) is e3 with
+// d3 = 0 when it has e1's direction, and the middles are the entries of
+// earlier time groups after t1, split the same way (code 2 d2 + d3).
+template <int MODE>
+__global__ void __launch_bounds__(SW_TPB) k_pair2(DevGraph G, SweepArgs a) {
+    static_assert(MODE == MODE_WEIGHT, "2-node pair sweep is for the weighted pass");
+    __shared__ unsigned long long lds[36 * 4];
+    for (int k = threadIdx.x; k < 36 * 4; k += SW_TPB) lds[k] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & (TM_WAVE - 1);
+    const int64_t nE = a.n_entries;  // pair entries, sentinels included
+    const PairEnt *E = G.up_ent;
+    while (true) {
+        int64_t base = 0;
+        if (lane == 0) base = (int64_t)atomicAdd((unsigned long long *)a.counter, (unsigned long long)TM_WAVE);
+        base = __shfl(base, 0, TM_WAVE);
+        if (base >= nE) break;
+        const int64_t i = base + lane;
+        if (i >= nE) continue;
+        const PairEnt e1 = E[i];
+        if (e1.t == LLONG_MAX) continue;  // a pair's sentinel
+        const int64_t t1 = e1.t;
+        bool go = true;
+        int64_t whi = LLONG_MAX;
+        unsigned long long *acc = lds;
+        if (a.windowed == 1) {
+            const int64_t jw = (t1 - a.s) / a.L + 1;
+            go = keep_window(a.seed, (uint64_t)jw, a.p);
+            whi = a.s + jw * a.L - 1;
+        } else if (a.windowed == 2) {
+            go = t1 >= a.s && t1 <= a.L;
+            whi = a.L;
+        } else if (a.windowed == 3) {
+            const int64_t jw = (t1 - a.s) / a.L + 1;
+            const int32_t kk = a.kidx[jw];
+            go = kk >= 0;
+            whi = a.s + jw * a.L - 1;
+            if (go) acc = (unsigned long long *)(a.win + (int64_t)kk * 36 * 4);
+        }
+        if (!go) continue;
+        int64_t hi = (t1 > LLONG_MAX - a.delta) ? LLONG_MAX : t1 + a.delta;
+        hi = hi < whi ? hi : whi;
+        // the entry after the anchor exists (at worst the sentinel)
+        int64_t cprev = E[i + 1].c0;
+        const int64_t dir1 = cprev - e1.c0;  // 1: a -> b
+        Acc<MODE, 4> A;
+        A.clear();
+        uint64_t cs0 = 0, cs1 = 0, ps0 = 0, ps1 = 0;
+        int64_t tg = t1;
+        for (int64_t j = i + 1;; j += 4) {
+            // four entries and the count after each, loaded together; the
+            // sentinel ends every pair, so no load leaves the pair's list + 1
+            PairEnt q[4];
+            int64_t cn[4];  // the a -> b count after each entry
+            bool stop[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = E[j + u < nE ? j + u : nE - 1];
+            const int64_t c4 = E[j + 4 < nE ? j + 4 : nE - 1].c0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) cn[u] = u < 3 ? q[u + 1].c0 : c4;
+            bool done = false;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                stop[u] = done || j + u >= nE || q[u].t == LLONG_MAX || q[u].t > hi;
+                done = stop[u];
+            }
+            uint64_t wq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) wq[u] = stop[u] ? 0 : weight_of<MODE>(a, q[u].t - t1);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (stop[u]) break;
+                const int64_t cj = u == 0 ? cprev : cn[u - 1];
+                const uint32_t d3 = ((cn[u] - cj) == dir1) ? 0u : 1u;
+                const int64_t tj = q[u].t;
+                if (tj == t1) continue;
+                if (tj != tg) {
+                    cs0 += ps0;
+                    cs1 += ps1;
+                    ps0 = ps1 = 0;
+                    tg = tj;
+                }
+                acc_add<MODE, 4>(A, 0, d3, cs0, wq[u], nullptr, 0, tj - t1, a.delta);
+                acc_add<MODE, 4>(A, 2, d3, cs1, wq[u], nullptr, 2, tj - t1, a.delta);
+                if (d3) ++ps1;
+                else ++ps0;
+            }
+            if (done) break;
+            cprev = cn[3];
+        }
+        const int codes[4] = {0, 1, 2, 3};
+        flush<MODE, 4>(A, codes, acc, nullptr);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 36 * 4; k += SW_TPB) {
+        uint64_t v = lds[k];
+        if (!v) continue;
+        int part = k & 3;
+        uint64_t *o = a.out + (k & ~3);
+        if (part == 0) tm_atomic_add_u128(o, o + 1, v, 0);
+        else if (part == 1) atomicAdd((unsigned long long *)(o + 1), (unsigned long long)v);
+        else if (part == 2) tm_atomic_add_u128(o + 2, o + 3, v, 0);
+        else atomicAdd((unsigned long long *)(o + 3), (unsigned long long)v);
+    }
+}
+
 template <int MODE>
 tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, hipStream_t st) {
     DevGraph G = dev_view(g);
@@ -202,6 +314,20 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, hipStr
     // the triangle sweep by lookup latency), so they run on forked streams
     // and share the CUs; the caller's stream waits for all of them.
     TM_HIP(hipMemsetAsync(a.counter, 0, 3 * sizeof(int64_t), st));
+    if (MODE == MODE_WEIGHT && fwd && a.want_fwd == 1u && !bwd) {
+        // the 2-node motifs alone: one anchor per pair entry
+        SweepArgs b = a;
+        b.n_entries = g->m_nl + g->U;
+        int64_t nbp = (b.n_entries + SW_TPB - 1) / SW_TPB;
+        if (nbp > (int64_t)ncu * 8) nbp = (int64_t)ncu * 8;
+        if (nbp < 1) nbp = 1;
+        void *tok = tm_prof_begin("pair2_weight", st, tm_prof_pass());
+        if constexpr (MODE == MODE_WEIGHT)
+            hipLaunchKernelGGL((k_pair2<MODE_WEIGHT>), dim3((unsigned)nbp), dim3(SW_TPB), 0, st, G, b);
+        TM_HIP(hipGetLastError());
+        tm_prof_end(tok, st);
+        return TM_OK;
+    }
     struct Launch {
         int kind;  // 0 fwd 2-node/stars, 1 bwd stars, 2 fwd triangles
     } todo[3];

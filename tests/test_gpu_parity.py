@@ -350,6 +350,37 @@ def test_estimate_stream_equals_in_memory(tm):
     assert rc == 1  # TM_EINVAL
 
 
+def test_two_node_pair_sweep(tm):
+    """Weighted estimates of the four 2-node motifs alone take the sweep
+    grouped by static edge; with a star motif added, the same motifs go
+    through the per-node sweep.  Both sum exact fixed-point integers, so the
+    estimates, kept counts and per-window Y_{s,j} agree to the last bit (one
+    window per kept anchor, edge-proportional windows, streamed windows), and
+    the oracle's estimates within 1e-12."""
+    TWO = [M for M in THREE if len(set(sum(M, ()))) == 2]
+    star = ((0, 1), (0, 1), (0, 2))
+    cases = [
+        (ti.random_small_graph(5, 1500, 6000, 91, allow_self_loops=True), 40, 3, 0.5, 2, True),
+        (ti.zipf_graph(2000, 40000, 1.8, 2_000_000, 92), 86400, 3, 0.3, 1, False),
+    ]
+    for g, delta, c, p, seed, with_oracle in cases:
+        say("two-node pair sweep", g.m, delta, c, p, seed)
+        G = load(tm, g)
+        e2, k2 = tm.estimate_multi(G, TWO, delta, c, p, seed)
+        e3, k3 = tm.estimate_multi(G, TWO + [star], delta, c, p, seed)
+        assert e2 == e3[:4] and k2 == k3[:4]
+        assert any(k > 0 for k in k2)
+        q2, w2 = tm.estimate_q(G, TWO, delta, c, 4.0, 2, seed)
+        q3, w3 = tm.estimate_q(G, TWO + [star], delta, c, 4.0, 2, seed)
+        assert q2 == q3[:4] and np.array_equal(w2["y"], w3["y"][:, :4])
+        o = np.argsort(g.t, kind="stable")
+        s2, ks2, _ = tm.estimate_stream(g.src[o], g.dst[o], g.t[o], g.n, TWO, delta, c, p, seed)
+        assert s2 == e2 and ks2 == k2
+        if with_oracle:
+            for M, z in zip(TWO, e2):
+                assert close(z, oracle.estimate(g.src, g.dst, g.t, M, delta, c, p, seed)["Z"]), M
+
+
 SWEEP_NAMES = ("sweep3_fwd_count", "sweep3_tri_count", "sweep3_bwd_count",
                "sweep3_fwd_weight", "sweep3_tri_weight", "sweep3_bwd_weight")
 
