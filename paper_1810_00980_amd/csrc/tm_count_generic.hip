@@ -23,6 +23,8 @@
 
 #include <limits.h>
 
+#include "tm_sweep_dev.h"
+
 namespace {
 
 constexpr int CG_TPB = 256;
@@ -64,29 +66,48 @@ __device__ inline int64_t ub_time(const int64_t *t, int64_t lo, int64_t hi, int6
     return lo;
 }
 
-// entries of pair (x -> y): [*b, *e) in pr_t
-__device__ inline void pair_range(const DevGraph &G, int32_t x, int32_t y, int64_t *b, int64_t *e) {
-    int64_t lo = G.sp_off[x], hi = G.sp_off[x + 1];
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (G.sp_nbr[mid] < y) lo = mid + 1;
-        else hi = mid;
+struct Range {
+    const int32_t *nbr;  // nullptr for pair levels
+    const int64_t *t;    // node lists: entry times
+    int64_t cur, end;    // node lists: [cur, end) of the list; pairs: of up_ent
+    int32_t newnode;     // motif node bound by an entry (-1 for pair levels)
+    // pair levels: the unordered pair's entries (both directions, time
+    // sorted); an entry runs a -> b (a < b) when the a -> b count steps at it,
+    // want = 1 for a -> b, 0 for b -> a; ab = a -> b entries in [cur, end)
+    uint32_t want;
+    int64_t ab;
+};
+
+// Pair level (x -> y) within (tprev, hi]: the unordered pair {x, y} from the
+// pair hash, its entries with times in the interval found by two interleaved
+// bucket searches, whose a -> b counts also give the directed count.
+__device__ inline void open_pair(const DevGraph &G, uint32_t x, uint32_t y, int64_t tprev, int64_t hi, Range &R) {
+    R.nbr = nullptr;
+    R.t = nullptr;
+    R.newnode = -1;
+    R.want = x < y ? 1u : 0u;
+    R.cur = R.end = 0;
+    R.ab = 0;
+    sweepdev::PairView pv;
+    if (tprev >= hi || G.ph_cap == 0 || sweepdev::pair_find(G, x, y, pv) < 0) return;
+    int64_t r[2][4];
+    const bool all = hi == LLONG_MAX;  // every entry after tprev
+    sweepdev::pair_lower2(G, pv.m, pv.en, pv.n, tprev + 1, all ? tprev + 1 : hi + 1, r);
+    const int64_t base = pv.m.base;
+    int64_t e = r[1][0], ce = r[1][1];
+    if (all) {
+        e = pv.n;
+        ce = pv.en[pv.n].c0;
     }
-    if (lo < G.sp_off[x + 1] && G.sp_nbr[lo] == y) {
-        *b = G.sp_beg[lo];
-        *e = G.sp_beg[lo + 1];
-    } else {
-        *b = 0;
-        *e = 0;
-    }
+    R.cur = base + r[0][0];
+    R.end = base + e;
+    R.ab = ce - r[0][1];
 }
 
-struct Range {
-    const int32_t *nbr;  // nullptr for pair lists
-    const int64_t *t;
-    int64_t cur, end;
-    int32_t newnode;     // motif node bound by an entry (-1 for pair lists)
-};
+// direction of up_ent entry k: 1 for a -> b
+__device__ inline uint32_t pair_dir(const DevGraph &G, int64_t k) {
+    return (uint32_t)(G.up_ent[k + 1].c0 - G.up_ent[k].c0);
+}
 
 __device__ inline Range open_level(const DevGraph &G, const MotifPlan &P, int r, const Binding &f, int64_t tprev,
                                    int64_t hi) {
@@ -94,10 +115,8 @@ __device__ inline Range open_level(const DevGraph &G, const MotifPlan &P, int r,
     int kind = P.kind[r];
     int64_t lo, up;
     if (kind == LV_PAIR) {
-        pair_range(G, f.get(P.u[r]), f.get(P.v[r]), &lo, &up);
-        R.nbr = nullptr;
-        R.t = G.pr_t;
-        R.newnode = -1;
+        open_pair(G, (uint32_t)f.get(P.u[r]), (uint32_t)f.get(P.v[r]), tprev, hi, R);
+        return R;
     } else if (kind == LV_OUT) {
         int32_t x = f.get(P.u[r]);
         lo = G.out_off[x];
@@ -113,6 +132,8 @@ __device__ inline Range open_level(const DevGraph &G, const MotifPlan &P, int r,
         R.t = G.in_t;
         R.newnode = P.u[r];
     }
+    R.want = 0;
+    R.ab = 0;
     R.cur = ub_time(R.t, lo, up, tprev);
     R.end = ub_time(R.t, R.cur, up, hi);
     return R;
@@ -128,17 +149,16 @@ struct Acc {
 };
 
 template <int HIST>
-__device__ inline void count_last(const Range &R, const Binding &f, int64_t t1, Acc &acc, uint64_t *hlo,
-                                  uint64_t *hhi) {
+__device__ inline void count_last(const DevGraph &G, const Range &R, const Binding &f, int64_t t1, Acc &acc,
+                                  uint64_t *hlo, uint64_t *hhi) {
     if (R.nbr == nullptr) {
-        if (!HIST) {
-            acc.add((uint64_t)(R.end - R.cur));
-        } else {
+        const int64_t n = R.want ? R.ab : (R.end - R.cur) - R.ab;
+        if (HIST) {
             for (int64_t i = R.cur; i < R.end; ++i) {
-                hist_add<HIST>(hlo, hhi, R.t[i] - t1);
+                if (pair_dir(G, i) == R.want) hist_add<HIST>(hlo, hhi, G.up_ent[i].t - t1);
             }
-            acc.add((uint64_t)(R.end - R.cur));
         }
+        acc.add((uint64_t)n);
         return;
     }
     uint64_t c = 0;
@@ -157,13 +177,14 @@ __device__ inline void levels(const DevGraph &G, const MotifPlan &P, Binding &f,
                               int64_t hi, Acc &acc, uint64_t *hlo, uint64_t *hhi) {
     Range rg = open_level(G, P, R, f, tprev, hi);
     if constexpr (R == LEN - 1) {
-        count_last<HIST>(rg, f, t1, acc, hlo, hhi);
+        count_last<HIST>(G, rg, f, t1, acc, hlo, hhi);
     } else {
         for (int64_t i = rg.cur; i < rg.end; ++i) {
-            int64_t ti = rg.t[i];
             if (rg.nbr == nullptr) {
-                levels<R + 1, LEN, HIST>(G, P, f, ti, t1, hi, acc, hlo, hhi);
+                if (pair_dir(G, i) != rg.want) continue;
+                levels<R + 1, LEN, HIST>(G, P, f, G.up_ent[i].t, t1, hi, acc, hlo, hhi);
             } else {
+                int64_t ti = rg.t[i];
                 int32_t w = rg.nbr[i];
                 if (f.used(w)) continue;
                 f.set(rg.newnode, w);
@@ -266,13 +287,13 @@ __global__ void __launch_bounds__(CG_TPB) k_count_generic(DevGraph G, MotifPlan 
 // adds of the items' counts (their sums equal the per-anchor totals).
 
 struct Level1 {
-    const int32_t *nbr;  // nullptr for a pair list
+    const int32_t *nbr;  // nullptr for a pair level (entries of up_ent)
     const int64_t *t;
     int32_t newnode;
 };
 
 __device__ inline Level1 level1_list(const DevGraph &G, const MotifPlan &P) {
-    if (P.kind[1] == LV_PAIR) return Level1{nullptr, G.pr_t, -1};
+    if (P.kind[1] == LV_PAIR) return Level1{nullptr, nullptr, -1};
     if (P.kind[1] == LV_OUT) return Level1{G.out_nbr, G.out_t, P.v[1]};
     return Level1{G.in_nbr, G.in_t, P.u[1]};
 }
@@ -337,12 +358,19 @@ __global__ void __launch_bounds__(CG_TPB)
         f.set(1, G.es_dst[pos]);
         Acc acc{0, 0};
         bool ok = true;
+        int64_t tj;
         if (L1.nbr != nullptr) {
             int32_t w = L1.nbr[j];
             ok = !f.used(w);
             f.set(L1.newnode, w);
+            tj = L1.t[j];
+        } else {
+            // an entry of the pair {x, y} of motif edge 1: only those running x -> y
+            const uint32_t x = (uint32_t)f.get(P.u[1]), y = (uint32_t)f.get(P.v[1]);
+            ok = pair_dir(G, j) == (x < y ? 1u : 0u);
+            tj = G.up_ent[j].t;
         }
-        if (ok) levels<2, LEN, HIST>(G, P, f, L1.t[j], t1, thi, acc, hlo, hhi);
+        if (ok) levels<2, LEN, HIST>(G, P, f, tj, t1, thi, acc, hlo, hhi);
         if ((acc.lo | acc.hi) == 0) continue;
         tm_add_u128(lo, hi, acc.lo, acc.hi);
         if (per_anchor) {
