@@ -82,12 +82,6 @@ struct tm_graph {
     DevBuf out_off, out_nbr, out_t;  // int64[n+1], int32[m_nl], int64[m_nl]
     DevBuf in_off, in_nbr, in_t;
 
-    // directed pairs: entries sorted by (src, dst, t)
-    DevBuf sp_off;   // int64[n+1]: first pair of each source node
-    DevBuf sp_nbr;   // int32[S]: destination of each pair
-    DevBuf sp_beg;   // int64[S+1]: first entry of each pair in pr_t
-    DevBuf pr_t;     // int64[m_nl]
-
     // combined incidence lists: every non-self-loop edge appears in the list
     // of its source (direction bit 0) and of its destination (bit 1), times
     // ascending within a list
@@ -182,7 +176,6 @@ struct DevGraph {
     const int64_t *es_t;
     const int64_t *out_off; const int32_t *out_nbr; const int64_t *out_t;
     const int64_t *in_off; const int32_t *in_nbr; const int64_t *in_t;
-    const int64_t *sp_off; const int32_t *sp_nbr; const int64_t *sp_beg; const int64_t *pr_t;
     const int64_t *inc_off; const uint32_t *inc_nd; const int64_t *inc_t; const uint32_t *inc_twin;
     int64_t n_hi; const int64_t *hi_off; const uint32_t *hi_nd; const int64_t *hi_t;
     const PairSlot *ph_slot; int64_t ph_cap;

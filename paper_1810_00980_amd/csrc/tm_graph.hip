@@ -103,34 +103,14 @@ __global__ void k_lower_bound(const uint64_t *keys, int64_t len, int64_t n, uint
     }
 }
 
-__global__ void k_pair_keys(const int64_t *nl_pos, int64_t m_nl, const int32_t *es_src, const int32_t *es_dst,
-                            int64_t n, uint64_t *keys, uint32_t *vals) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m_nl) {
-        int64_t k = nl_pos[i];
-        keys[i] = (uint64_t)es_src[k] * (uint64_t)n + (uint64_t)es_dst[k];
-        vals[i] = (uint32_t)i;
-    }
-}
-
-__global__ void k_pair_fill(const uint64_t *keys, const uint32_t *vals, int64_t m_nl, const int64_t *nl_pos,
-                            const int64_t *es_t, int64_t *pr_t, int64_t *bflag) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < m_nl) {
-        pr_t[j] = es_t[nl_pos[vals[j]]];
-        bflag[j] = (j == 0 || keys[j] != keys[j - 1]) ? 1 : 0;
-    }
-}
-
-__global__ void k_pair_index(const uint64_t *keys, const int64_t *bscan, int64_t m_nl, int64_t n,
-                             uint64_t *sp_key, int32_t *sp_nbr, int64_t *sp_beg) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < m_nl && (j == 0 || keys[j] != keys[j - 1])) {
-        int64_t p = bscan[j];
-        sp_key[p] = keys[j];
-        sp_nbr[p] = (int32_t)(keys[j] % (uint64_t)n);
-        sp_beg[p] = j;
-    }
+// distinct directed pairs: each unordered pair adds one per direction that
+// has an edge (its sentinel entry holds the a -> b total)
+__global__ void k_dir_pairs(const int64_t *ubeg, const PairEnt *ent, int64_t U, unsigned long long *out) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= U) return;
+    const int64_t n = ubeg[p + 1] - ubeg[p];
+    const int64_t ab = ent[ubeg[p] + p + n].c0;
+    atomicAdd(out, (unsigned long long)((ab > 0 ? 1 : 0) + (n - ab > 0 ? 1 : 0)));
 }
 
 __global__ void k_set1(int64_t *p, int64_t v) { p[0] = v; }
@@ -463,8 +443,8 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
         TM_HIP(hipGetLastError());
     }
     // non-self-loop positions
-    DevBuf cnt;
-    TM_TRY(cnt.alloc(8));
+    DevBuf cnt;  // device scalars read back: [0] a scan total, [1] the directed pair count
+    TM_TRY(cnt.alloc(16));
     TM_TRY(tm_scan_i64(flag.as<int64_t>(), m, cnt.as<int64_t>(), st));
     int64_t m_nl = 0;
     TM_HIP(hipMemcpyAsync(&m_nl, cnt.p, 8, hipMemcpyDeviceToHost, st));
@@ -485,49 +465,6 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
     // out- and in-lists
     TM_TRY(build_node_lists(g, nl.as<int64_t>(), true, g->out_off, g->out_nbr, g->out_t, st));
     TM_TRY(build_node_lists(g, nl.as<int64_t>(), false, g->in_off, g->in_nbr, g->in_t, st));
-
-    // directed pairs sorted by (src, dst, t)
-    {
-        int64_t n = g->n;
-        DevBuf pk, pv, bflag, spk;
-        TM_TRY(pk.alloc((size_t)m_nl * 8));
-        TM_TRY(pv.alloc((size_t)m_nl * 4));
-        TM_TRY(bflag.alloc((size_t)(m_nl + 1) * 8));
-        TM_TRY(g->pr_t.alloc((size_t)m_nl * 8));
-        int64_t S = 0;
-        if (m_nl > 0) {
-            hipLaunchKernelGGL(k_pair_keys, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, nl.as<int64_t>(), m_nl,
-                               g->es_src.as<int32_t>(), g->es_dst.as<int32_t>(), n, pk.as<uint64_t>(),
-                               pv.as<uint32_t>());
-            TM_HIP(hipGetLastError());
-            TM_TRY(tm_radix_sort(pk.as<uint64_t>(), pv.as<uint32_t>(), m_nl,
-                                 tm_bitlen((uint64_t)n * (uint64_t)n - 1), st));
-            hipLaunchKernelGGL(k_pair_fill, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, pk.as<uint64_t>(),
-                               pv.as<uint32_t>(), m_nl, nl.as<int64_t>(), g->es_t.as<int64_t>(), g->pr_t.as<int64_t>(),
-                               bflag.as<int64_t>());
-            TM_HIP(hipGetLastError());
-            TM_TRY(tm_scan_i64(bflag.as<int64_t>(), m_nl, cnt.as<int64_t>(), st));
-            TM_HIP(hipMemcpyAsync(&S, cnt.p, 8, hipMemcpyDeviceToHost, st));
-            TM_HIP(hipStreamSynchronize(st));
-        }
-        g->S = S;
-        TM_TRY(spk.alloc((size_t)S * 8));
-        TM_TRY(g->sp_nbr.alloc((size_t)S * 4));
-        TM_TRY(g->sp_beg.alloc((size_t)(S + 1) * 8));
-        TM_TRY(g->sp_off.alloc((size_t)(n + 1) * 8));
-        if (m_nl > 0) {
-            hipLaunchKernelGGL(k_pair_index, dim3(tm_blocks(m_nl, TPB)), dim3(TPB), 0, st, pk.as<uint64_t>(),
-                               bflag.as<int64_t>(), m_nl, n, spk.as<uint64_t>(), g->sp_nbr.as<int32_t>(),
-                               g->sp_beg.as<int64_t>());
-            TM_HIP(hipGetLastError());
-        }
-        hipLaunchKernelGGL(k_set1, dim3(1), dim3(1), 0, st, g->sp_beg.as<int64_t>() + S, m_nl);
-        TM_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_lower_bound, dim3(tm_blocks(n + 1, TPB)), dim3(TPB), 0, st, spk.as<uint64_t>(), S, n,
-                           (uint64_t)n, g->sp_off.as<int64_t>());
-        TM_HIP(hipGetLastError());
-        TM_HIP(hipStreamSynchronize(st));
-    }
 
     // unordered pair timelines, pair hash and per-pair time buckets
     {
@@ -596,8 +533,15 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
                                boff.as<int64_t>());
             TM_HIP(hipGetLastError());
             TM_TRY(tm_scan_i64(boff.as<int64_t>(), U, cnt.as<int64_t>(), st));
-            TM_HIP(hipMemcpyAsync(&nbk_total, cnt.p, 8, hipMemcpyDeviceToHost, st));
+            TM_HIP(hipMemsetAsync(cnt.as<int64_t>() + 1, 0, 8, st));
+            hipLaunchKernelGGL(k_dir_pairs, dim3(tm_blocks(U, TPB)), dim3(TPB), 0, st, ubeg.as<int64_t>(),
+                               g->up_ent.as<PairEnt>(), U, (unsigned long long *)(cnt.as<int64_t>() + 1));
+            TM_HIP(hipGetLastError());
+            int64_t two[2] = {0, 0};
+            TM_HIP(hipMemcpyAsync(two, cnt.p, 16, hipMemcpyDeviceToHost, st));
             TM_HIP(hipStreamSynchronize(st));
+            nbk_total = two[0];
+            g->S = two[1];
         }
         TM_TRY(g->pbk.alloc((size_t)(nbk_total > 0 ? nbk_total : 1) * sizeof(PairBucket)));
         if (U > 0) {
@@ -680,7 +624,7 @@ tm_status load_impl(const int32_t *src, const int32_t *dst, const int64_t *t, in
     ent_nl.release();
     inc_pos.release();
     const DevBuf *all[] = {&g->es_src, &g->es_dst, &g->es_t, &g->pos_of, &g->out_off, &g->out_nbr, &g->out_t,
-                           &g->in_off, &g->in_nbr, &g->in_t, &g->sp_off, &g->sp_nbr, &g->sp_beg, &g->pr_t,
+                           &g->in_off, &g->in_nbr, &g->in_t,
                            &g->inc_off, &g->inc_nd, &g->inc_t, &g->inc_twin, &g->hi_off, &g->hi_nd, &g->hi_t, &g->up_ent, &g->ph_slot, &g->pmeta, &g->pbk, &g->ex_c0x, &g->ex_rows};
     int64_t tot = 0;
     for (const DevBuf *b : all) tot += (int64_t)b->bytes;
@@ -696,8 +640,6 @@ DevGraph dev_view(const tm_graph *g) {
     v.es_src = g->es_src.as<int32_t>(); v.es_dst = g->es_dst.as<int32_t>(); v.es_t = g->es_t.as<int64_t>();
     v.out_off = g->out_off.as<int64_t>(); v.out_nbr = g->out_nbr.as<int32_t>(); v.out_t = g->out_t.as<int64_t>();
     v.in_off = g->in_off.as<int64_t>(); v.in_nbr = g->in_nbr.as<int32_t>(); v.in_t = g->in_t.as<int64_t>();
-    v.sp_off = g->sp_off.as<int64_t>(); v.sp_nbr = g->sp_nbr.as<int32_t>(); v.sp_beg = g->sp_beg.as<int64_t>();
-    v.pr_t = g->pr_t.as<int64_t>();
     v.inc_off = g->inc_off.as<int64_t>(); v.inc_nd = g->inc_nd.as<uint32_t>(); v.inc_t = g->inc_t.as<int64_t>();
     v.inc_twin = g->inc_twin.as<uint32_t>();
     v.n_hi = g->n_hi;

@@ -58,6 +58,8 @@ def test_small_random_all_motifs(tm, seed):
     g = ti.random_small_graph(6 + seed, 700 + 37 * seed, 3000, 900 + seed, allow_self_loops=True)
     say("small_random", seed, g.m)
     G = load(tm, g, device=(seed % 2 == 0))
+    nl = g.src != g.dst
+    assert G.n_pairs == len(set(zip(g.src[nl].tolist(), g.dst[nl].tolist())))
     for M in MOTIFS:
         for delta in (0, 7, 60):
             got = tm.count_exact(G, M, delta)
