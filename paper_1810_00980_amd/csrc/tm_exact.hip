@@ -56,6 +56,41 @@ __device__ inline int64_t list_upper(const int64_t *tv, int64_t lo, int64_t hi, 
     return lo;
 }
 
+// The bounds of the tie group of entry q (time t = tv[q]) in a list,
+// found by galloping outward from q: one or two loads when t has no ties,
+// instead of a binary search over the whole list.
+// first index in [lo, q] with tv >= t
+__device__ inline int64_t tie_lower(const int64_t *tv, int64_t lo, int64_t q, int64_t t) {
+    int64_t hi = q, step = 1, l = lo;  // tv[hi] >= t
+    while (true) {
+        const int64_t c = hi - step;
+        if (c < lo) break;
+        if (tv[c] < t) {
+            l = c + 1;
+            break;
+        }
+        hi = c;
+        step <<= 1;
+    }
+    return list_lower(tv, l, hi, t);
+}
+
+// first index in [q, end) with tv > t (end if none)
+__device__ inline int64_t tie_upper(const int64_t *tv, int64_t q, int64_t end, int64_t t) {
+    int64_t lo = q, step = 1, h = end;  // tv[lo] <= t
+    while (true) {
+        const int64_t c = lo + step;
+        if (c >= end) break;
+        if (tv[c] > t) {
+            h = c;
+            break;
+        }
+        lo = c;
+        step <<= 1;
+    }
+    return list_upper(tv, lo + 1, h, t);
+}
+
 // values of one pair entry slot in both views, column-major:
 // cols[(view * 12 + d_e * 6 + c) * S + slot], c = M_0, M_1, N_0, N_1,
 // N+_0 - M+_0, N+_1 - M+_1 (directions as seen from the view's endpoint)
@@ -98,8 +133,8 @@ __global__ void k_ex_values(DevGraph G, const uint32_t *ent_nl, const uint32_t *
                 // the edge's entry in x's list: side 0 when x is its source
                 int64_t q = inc_pos[2 * (int64_t)nlk + ((xs[w] == src) ? 0 : 1)];
                 int64_t ls = G.inc_off[xs[w]], lend = G.inc_off[xs[w] + 1];
-                int64_t lgs = list_lower(G.inc_t, ls, q + 1, t);
-                int64_t lge = list_upper(G.inc_t, q, lend, t);
+                int64_t lgs = tie_lower(G.inc_t, ls, q, t);
+                int64_t lge = tie_upper(G.inc_t, q, lend, t);
                 int64_t n0 = c0x[lgs] - c0x[ls], n1 = (lgs - ls) - n0;
                 int64_t n0p = c0x[lge] - c0x[ls], n1p = (lge - ls) - n0p;
                 const int64_t val[6] = {M[w][0], M[w][1], n0, n1, n0p - Mp[w][0], n1p - Mp[w][1]};
