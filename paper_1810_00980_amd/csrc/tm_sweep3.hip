@@ -43,8 +43,9 @@ using namespace sweepdev;
 
 // resident waves per SIMD asked of the compiler: the exact triangle sweep is
 // latency-bound and would otherwise settle a few registers above five waves
-// (it fits in 93 VGPRs at five); the weighted one, at five waves by itself,
-// gained nothing from a sixth
+// (at five it takes 95 VGPRs and keeps one 8-byte value per anchor in
+// scratch, outside the entry loop); the weighted ones gained nothing from a
+// forced count
 template <int MODE, bool FWD, unsigned CLS>
 constexpr int sweep_waves() {
     return (MODE == MODE_COUNT && FWD && CLS == 8u) ? 5 : 1;
