@@ -383,6 +383,27 @@ def test_two_node_pair_sweep(tm):
                 assert close(z, oracle.estimate(g.src, g.dst, g.t, M, delta, c, p, seed)["Z"]), M
 
 
+def test_self_loop_only_graph(tm):
+    """A graph whose edges are all self-loops holds no instance of any motif:
+    every counter, estimator and the per-anchor counts give zero (the pair
+    structures are empty)."""
+    n, m = 6, 400
+    rng = np.random.default_rng(95)
+    u = rng.integers(0, n, m).astype(np.int32)
+    g = ti.Graph(u, u.copy(), np.sort(rng.integers(0, 5000, m)).astype(np.int64), n)
+    say("self-loop only", g.m)
+    G = load(tm, g)
+    assert G.n_pairs == 0
+    ms = [ti.TRIANGLE, ((0, 1), (1, 0), (0, 1)), ti.BIFAN, ti.CYCLE4, ti.STAR4]
+    got, hlo, hhi = tm.count_exact_multi(G, ms, 600, hist=True)
+    assert all(c == 0 for c in got) and not hlo.any() and not hhi.any()
+    est, kept = tm.estimate_multi(G, ms, 600, 3, 1.0, 0)
+    assert est == [0.0] * len(ms) and kept == [0] * len(ms)
+    q, w = tm.estimate_q(G, ms, 600, 3, 2.0, 2, 0)
+    assert q == [0.0] * len(ms) and not np.any(w["y"])
+    assert not np.any(tm.count_anchors(G, ti.CYCLE4, 600, np.arange(m)))
+
+
 SWEEP_NAMES = ("sweep3_fwd_count", "sweep3_tri_count", "sweep3_bwd_count",
                "sweep3_fwd_weight", "sweep3_tri_weight", "sweep3_bwd_weight")
 
