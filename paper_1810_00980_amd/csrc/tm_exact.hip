@@ -150,7 +150,9 @@ __global__ void k_ex_values(DevGraph G, const uint32_t *ent_nl, const uint32_t *
     }
 }
 
-// column-major exclusive prefix sums -> rows[(view * S + slot) * 12 + c].
+// column-major prefix sums -> rows[(view * S + slot) * 12 + c].  The columns
+// were scanned as one array, so each value less its column's first one is
+// the column's own exclusive prefix.
 // A block moves EX_T slots of one view through LDS: it reads the 12 column
 // runs coalesced and writes the 12 * EX_T row words as one contiguous run.
 constexpr int EX_T = 256;
@@ -161,7 +163,8 @@ __global__ void __launch_bounds__(EX_T) k_ex_rows(const uint64_t *cols, int64_t 
     const int64_t ns = (S - s0) < EX_T ? (S - s0) : EX_T;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-        if (threadIdx.x < ns) tile[threadIdx.x * 13 + c] = cols[(int64_t)(w * 12 + c) * S + s0 + threadIdx.x];
+        const uint64_t *col = cols + (int64_t)(w * 12 + c) * S;
+        if (threadIdx.x < ns) tile[threadIdx.x * 13 + c] = col[s0 + threadIdx.x] - col[0];
     }
     __syncthreads();
     uint64_t *out = rows + ((int64_t)w * S + s0) * 12;
@@ -191,7 +194,9 @@ tm_status tm_build_exact_tables(tm_graph *g, const uint32_t *ent_nl, const uint3
     hipLaunchKernelGGL(k_ex_values, dim3(tm_blocks(S, TPB)), dim3(TPB), 0, st, dev_view(g), ent_nl, inc_pos, nl_pos,
                        g->ex_c0x.as<int64_t>(), S, cols.as<uint64_t>());
     TM_HIP(hipGetLastError());
-    for (int c = 0; c < 24; ++c) TM_TRY(tm_scan_i64(cols.as<int64_t>() + (int64_t)c * S, S, nullptr, st));
+    // one exclusive scan over the 24 columns back to back: column c's prefix
+    // plus the total of the columns before it, which k_ex_rows subtracts
+    TM_TRY(tm_scan_i64(cols.as<int64_t>(), 24 * S, nullptr, st));
     TM_TRY(g->ex_rows.alloc((size_t)S * 24 * 8));
     hipLaunchKernelGGL(k_ex_rows, dim3((unsigned)((S + EX_T - 1) / EX_T), 2), dim3(EX_T), 0, st, cols.as<uint64_t>(), S,
                        g->ex_rows.as<uint64_t>());
