@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <map>
 #include <vector>
 
 #include "tm.h"
@@ -28,29 +29,92 @@ static inline tm_status tm_hip_status(hipError_t e) {
 
 #define TM_HIP(expr) TM_TRY(tm_hip_status(expr))
 
-// Owned device allocation (freed on destruction).
+// Device blocks that graph loads on this host thread freed, kept for the
+// next load: hipMalloc and hipFree cost 0.1-0.2 ms each and a load makes
+// about forty of each for its temporaries.  Only allocations and frees made
+// while a load runs (LoadCacheScope) go through the cache, which keeps at
+// most TM_LOAD_CACHE_BYTES and gives its blocks back to the device when an
+// allocation runs out of memory.
+constexpr size_t TM_LOAD_CACHE_BYTES = (size_t)2 << 30;
+struct LoadCache {
+    std::multimap<size_t, void *> blocks;  // block size -> block
+    size_t bytes = 0;
+    bool active = false;
+    void clear() {
+        for (auto &kv : blocks) (void)hipFree(kv.second);
+        blocks.clear();
+        bytes = 0;
+    }
+    ~LoadCache() { clear(); }
+};
+inline thread_local LoadCache t_load_cache;
+
+struct LoadCacheScope {
+    bool prev;
+    LoadCacheScope() : prev(t_load_cache.active) { t_load_cache.active = true; }
+    LoadCacheScope(const LoadCacheScope &) = delete;
+    LoadCacheScope &operator=(const LoadCacheScope &) = delete;
+    ~LoadCacheScope() { t_load_cache.active = prev; }
+};
+
+// Owned device allocation (freed on destruction).  bytes is the size asked
+// for; a block taken from the load cache can be larger (cap).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    size_t cap = 0;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            LoadCache &C = t_load_cache;
+            bool kept = false;
+            if (C.active && C.bytes + cap <= TM_LOAD_CACHE_BYTES) {
+                try {
+                    C.blocks.emplace(cap, p);
+                    C.bytes += cap;
+                    kept = true;
+                } catch (...) {
+                }
+            }
+            if (!kept) (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
+        cap = 0;
     }
     tm_status alloc(size_t nbytes) {
         release();
         if (nbytes == 0) nbytes = 256;
+        LoadCache &C = t_load_cache;
+        if (C.active) {
+            // a cached block of at least the size and at most a quarter more
+            // (graph buffers come from here too; a reload asks the same sizes)
+            auto it = C.blocks.lower_bound(nbytes);
+            if (it != C.blocks.end() && it->first <= nbytes + nbytes / 4) {
+                p = it->second;
+                cap = it->first;
+                bytes = nbytes;
+                C.bytes -= it->first;
+                C.blocks.erase(it);
+                return TM_OK;
+            }
+        }
         hipError_t e = hipMalloc(&p, nbytes);
+        if (e == hipErrorOutOfMemory && !C.blocks.empty()) {
+            (void)hipGetLastError();
+            C.clear();
+            e = hipMalloc(&p, nbytes);
+        }
         if (e != hipSuccess) {
             p = nullptr;
             (void)hipGetLastError();
             return e == hipErrorOutOfMemory ? TM_ENOMEM : TM_EDEVICE;
         }
         bytes = nbytes;
+        cap = nbytes;
         return TM_OK;
     }
     // grow-only reuse

@@ -662,6 +662,7 @@ extern "C" tm_status tm_load_graph_ex(const int32_t *src, const int32_t *dst, co
     if (!out || m < 0 || n_nodes <= 0 || (m > 0 && (!src || !dst || !t))) return TM_EINVAL;
     if (flags & ~(uint32_t)(TM_LOAD_ON_DEVICE | TM_LOAD_NO_EXACT_TABLES)) return TM_EINVAL;
     if (m > (int64_t)INT32_MAX) return TM_EINVAL;  // 32-bit edge indices in the sorts
+    LoadCacheScope cache;  // the load's temporaries are kept for the next load on this thread
     tm_graph *g = new (std::nothrow) tm_graph();
     if (!g) return TM_ENOMEM;
     g->want_ex = (flags & TM_LOAD_NO_EXACT_TABLES) ? 0 : 1;
