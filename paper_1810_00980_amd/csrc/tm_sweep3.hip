@@ -66,9 +66,18 @@ k_sweep3(DevGraph G, SweepArgs a) {
     const int64_t nE = RANKED ? G.n_hi : a.n_entries;
     while (true) {
         int64_t base = 0;
-        if (lane == 0) base = (int64_t)atomicAdd((unsigned long long *)a.counter, (unsigned long long)TM_WAVE);
-        base = __shfl(base, 0, TM_WAVE);
-        if (base >= nE) break;
+        if (RANKED && a.order) {
+            // the next batch in the claim order (heaviest first)
+            int64_t b = 0;
+            if (lane == 0) b = (int64_t)atomicAdd((unsigned long long *)a.counter, 1ull);
+            b = __shfl(b, 0, TM_WAVE);
+            if (b >= a.n_batches) break;
+            base = (int64_t)a.order[b] * TM_WAVE;
+        } else {
+            if (lane == 0) base = (int64_t)atomicAdd((unsigned long long *)a.counter, (unsigned long long)TM_WAVE);
+            base = __shfl(base, 0, TM_WAVE);
+            if (base >= nE) break;
+        }
         int64_t i = base + lane;
         if (i < nE) {
             int64_t x = owner_of(off, G.n, i);
@@ -296,6 +305,58 @@ __global__ void __launch_bounds__(SW_TPB) k_pair2(DevGraph G, SweepArgs a) {
     }
 }
 
+// Claim order of the exact triangle sweep's 64-anchor batches.  Their work
+// is heavy-tailed (the longest windows of the ranked sublists: the heaviest
+// batch is about three quarters of a wave's fair share of the whole pass),
+// so claimed in index order the last heavy batches ran alone at the end.  A
+// batch's cost is its first anchor's window length (its lanes' windows are
+// nearly equal); keys sort descending.
+__global__ void k_tri_batch_cost(DevGraph G, SweepArgs a, int64_t nbt, uint64_t *keys, uint32_t *vals) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbt) return;
+    const int64_t i = b * TM_WAVE;
+    const int64_t x = owner_of(G.hi_off, G.n, i);
+    const int64_t end = G.hi_off[x + 1];
+    const int64_t t = G.hi_t[i];
+    int64_t hi = (t > LLONG_MAX - a.delta) ? LLONG_MAX : t + a.delta;
+    int64_t len = 0;
+    if (a.windowed == 2) {
+        if (t < a.s || t > a.L) hi = LLONG_MIN;
+        else hi = hi < a.L ? hi : a.L;
+    }
+    if (hi != LLONG_MIN) {
+        int64_t lo = i + 1, up = end;  // first entry with time > hi
+        while (lo < up) {
+            const int64_t mid = (lo + up) >> 1;
+            if (G.hi_t[mid] <= hi) lo = mid + 1;
+            else up = mid;
+        }
+        len = lo - (i + 1);
+    }
+    const uint64_t c = len < 0xFFFFFFFFll ? (uint64_t)len : 0xFFFFFFFFull;
+    keys[b] = 0xFFFFFFFFull - c;
+    vals[b] = (uint32_t)b;
+}
+
+// per host thread: keys and batch ids of the claim order
+thread_local DevBuf t_order_k, t_order_v;
+
+tm_status tri_claim_order(const tm_graph *g, SweepArgs &a, hipStream_t st) {
+    const DevGraph G = dev_view(g);
+    const int64_t nbt = (G.n_hi + TM_WAVE - 1) / TM_WAVE;
+    if (nbt <= 1 || nbt > (int64_t)UINT32_MAX) return TM_OK;  // index order
+    LoadCacheScope cache;  // the sort's buffers are reused from call to call
+    TM_TRY(t_order_k.reserve((size_t)nbt * 8));
+    TM_TRY(t_order_v.reserve((size_t)nbt * 4));
+    hipLaunchKernelGGL(k_tri_batch_cost, dim3(tm_blocks(nbt, 256)), dim3(256), 0, st, G, a, nbt,
+                       t_order_k.as<uint64_t>(), t_order_v.as<uint32_t>());
+    TM_HIP(hipGetLastError());
+    TM_TRY(tm_radix_sort(t_order_k.as<uint64_t>(), t_order_v.as<uint32_t>(), nbt, 32, st));
+    a.order = t_order_v.as<uint32_t>();
+    a.n_batches = nbt;
+    return TM_OK;
+}
+
 template <int MODE>
 tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, hipStream_t st) {
     DevGraph G = dev_view(g);
@@ -315,6 +376,7 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, hipStr
     // the triangle sweep by lookup latency), so they run on forked streams
     // and share the CUs; the caller's stream waits for all of them.
     TM_HIP(hipMemsetAsync(a.counter, 0, 3 * sizeof(int64_t), st));
+    if (MODE == MODE_COUNT && fwd && (a.want_fwd & 8u) && a.windowed != 3) TM_TRY(tri_claim_order(g, a, st));
     if (MODE == MODE_WEIGHT && fwd && a.want_fwd == 1u && !bwd) {
         // the 2-node motifs alone: one anchor per pair entry
         SweepArgs b = a;

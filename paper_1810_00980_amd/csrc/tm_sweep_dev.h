@@ -30,6 +30,10 @@ struct SweepArgs {
     int64_t n_entries;
     const int32_t *kidx;   // windowed 3: kept index of window j (j = 1 .. J), -1 when not kept
     uint64_t *win;         // windowed 3: per kept window, 36 x {count lo, hi, weight lo, hi}
+    // exact triangles: the 64-anchor batches of the ranked sublists in the
+    // order they are claimed (heaviest window first), or nullptr for index order
+    const uint32_t *order = nullptr;
+    int64_t n_batches = 0;
 };
 
 __device__ inline void philox10_d(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3, uint32_t k0, uint32_t k1) {
