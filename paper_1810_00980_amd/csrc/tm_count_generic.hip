@@ -153,9 +153,13 @@ __device__ inline void count_last(const DevGraph &G, const Range &R, const Bindi
                                   uint64_t *hlo, uint64_t *hhi) {
     if (R.nbr == nullptr) {
         const int64_t n = R.want ? R.ab : (R.end - R.cur) - R.ab;
-        if (HIST) {
+        if (HIST && R.cur < R.end) {
+            // one 16-byte load per entry: the next entry's count gives this one's direction
+            PairEnt e = G.up_ent[R.cur];
             for (int64_t i = R.cur; i < R.end; ++i) {
-                if (pair_dir(G, i) == R.want) hist_add<HIST>(hlo, hhi, G.up_ent[i].t - t1);
+                const PairEnt nx = G.up_ent[i + 1];
+                if ((uint32_t)(nx.c0 - e.c0) == R.want) hist_add<HIST>(hlo, hhi, e.t - t1);
+                e = nx;
             }
         }
         acc.add((uint64_t)n);
@@ -181,8 +185,9 @@ __device__ inline void levels(const DevGraph &G, const MotifPlan &P, Binding &f,
     } else {
         for (int64_t i = rg.cur; i < rg.end; ++i) {
             if (rg.nbr == nullptr) {
-                if (pair_dir(G, i) != rg.want) continue;
-                levels<R + 1, LEN, HIST>(G, P, f, G.up_ent[i].t, t1, hi, acc, hlo, hhi);
+                const PairEnt e = G.up_ent[i];
+                if ((uint32_t)(G.up_ent[i + 1].c0 - e.c0) != rg.want) continue;
+                levels<R + 1, LEN, HIST>(G, P, f, e.t, t1, hi, acc, hlo, hhi);
             } else {
                 int64_t ti = rg.t[i];
                 int32_t w = rg.nbr[i];
