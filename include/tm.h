@@ -95,9 +95,10 @@ typedef struct {
  * (on_device = 0) or device memory (on_device = 1).  They are copied; the
  * library keeps no caller pointer.  The graph is stored time-sorted with
  * per-node time-sorted incidence lists (device radix sort + CSR build).
- * The device memory a load frees (its temporaries) is kept, up to 2 GiB per
- * host thread, for the next load on the same thread; it goes back to the
- * device when an allocation of a load runs out of memory or the thread ends.
+ * The device memory that loads and exact triangle counts free (their
+ * temporaries) is kept, up to 2 GiB per host thread, for the next such call
+ * on the same thread; it goes back to the device when one of their
+ * allocations runs out of memory or the thread ends.
  * Errors: TM_EINVAL (m < 0, n_nodes <= 0, an id outside [0, n_nodes), NULL
  * array with m > 0), TM_ENOMEM, TM_EDEVICE.  *out is owned by the caller
  * until tm_free_graph.
