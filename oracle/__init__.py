@@ -13,6 +13,12 @@ Three independent pieces:
 * ``brute`` is a second, structurally different brute force in pure Python:
   it tries every ordered l-tuple of distinct edges (tiny graphs only) and,
   for the window identities, every shift s in {-c delta + 1, ..., 0}.
+* ``count3_indexed``/``estimate3_indexed`` wrap tier C (``tm_oracle_c.c``):
+  exact counts and duration histograms of up to 64 three-edge motifs at once
+  for graphs of millions of edges, from every (first, last) edge pair that
+  shares a node within delta and range counts of the middles between them,
+  multithreaded with OpenMP; and Algorithm 1 with one shift and q_j = p over
+  those counts (the same draws as ``estimate``).
 * ``ex23`` is Algorithm 2 of Sec. 5.1 (exact count of the two-node motif
   (0,1),(1,0),(0,1) per node pair, fixing first and last edge and counting the
   middles in between), with its inner loop starting right after the first
@@ -31,6 +37,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tm_oracle.c")
+_SRC_C = os.path.join(_HERE, "tm_oracle_c.c")
 _LIB = os.path.join(_HERE, "libtm_oracle.so")
 
 INT64_MIN = -(1 << 63)
@@ -40,11 +47,13 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile the C oracle with gcc (no fast-math, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile the C oracle with gcc (no fast-math, no FMA contraction; OpenMP
+    for tier C)."""
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_C))
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-fopenmp",
+                               "-o", tmp, _SRC, _SRC_C, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -72,6 +81,11 @@ def _load():
         lib.orc_estimate_q.argtypes = [i64, P, P, P, i32, P, P, i64, i64, f64, i32, u64, i64,
                                        P, P, P, P, P, i64, P]
         lib.orc_estimate_q.restype = i32
+        lib.orc_count3_indexed.argtypes = [i64, P, P, P, i32, P, P, i64, i64, i64, P, P, i32]
+        lib.orc_count3_indexed.restype = i32
+        lib.orc_estimate3_indexed.argtypes = [i64, P, P, P, i32, P, P, i64, i64, f64, u64, P, P, P, P, i64, P, P,
+                                              i32]
+        lib.orc_estimate3_indexed.restype = i32
         _lib = lib
     return _lib
 
@@ -203,6 +217,57 @@ def estimate_q(src, dst, t, motif, delta, c, r, b, seed, force_shift=None, cap=1
             "y": wy[:n].copy(), "L": int(c) * int(delta)}
 
 
+# ---------------------------------------------------------------- tier C
+
+def _motifs3(motifs):
+    ms = np.ascontiguousarray([[e[0] for e in M] for M in motifs], dtype=np.int32).reshape(-1)
+    md = np.ascontiguousarray([[e[1] for e in M] for M in motifs], dtype=np.int32).reshape(-1)
+    if any(len(M) != 3 for M in motifs):
+        raise OracleError("tier C takes three-edge motifs")
+    return ms, md
+
+
+def count3_indexed(src, dst, t, motifs, delta, win=None, hist=False, threads=0):
+    """Tier C: exact counts (Python ints) of up to 64 distinct canonical
+    three-edge motifs in one pass, and optionally their duration histograms
+    (uint64[len(motifs), delta+1]).  win=(lo, hi) restricts every edge of an
+    instance to times in [lo, hi].  threads=0: all host cores."""
+    lib = _load()
+    src, dst, t = _edges(src, dst, t)
+    ms, md = _motifs3(motifs)
+    k = len(motifs)
+    lo, hi = win if win is not None else (INT64_MIN, INT64_MAX)
+    tot = np.zeros(2 * k, dtype=np.uint64)
+    h = np.zeros((k, delta + 1), dtype=np.uint64) if hist else None
+    rc = lib.orc_count3_indexed(src.shape[0], _ptr(src), _ptr(dst), _ptr(t), k, _ptr(ms), _ptr(md), int(delta),
+                                int(lo), int(hi), _ptr(tot), _ptr(h) if h is not None else None, int(threads))
+    _check(rc)
+    counts = [(int(tot[2 * i + 1]) << 64) | int(tot[2 * i]) for i in range(k)]
+    return (counts, h) if hist else counts
+
+
+def estimate3_indexed(src, dst, t, motifs, delta, c, p, seed, threads=0, kept_cap=1 << 16):
+    """Algorithm 1 with one shift and q_j = p for up to 64 three-edge motifs,
+    kept windows counted by tier C.  Returns a dict with s, J, kept window ids,
+    per-motif kept counts and estimates Z."""
+    lib = _load()
+    src, dst, t = _edges(src, dst, t)
+    ms, md = _motifs3(motifs)
+    k = len(motifs)
+    s, J, nk = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    kept = np.zeros(kept_cap, dtype=np.int64)
+    kt = np.zeros(2 * k, dtype=np.uint64)
+    z = np.zeros(k, dtype=np.float64)
+    rc = lib.orc_estimate3_indexed(src.shape[0], _ptr(src), _ptr(dst), _ptr(t), k, _ptr(ms), _ptr(md), int(delta),
+                                   int(c), float(p), int(seed), ctypes.byref(s), ctypes.byref(J), ctypes.byref(nk),
+                                   _ptr(kept), kept_cap, _ptr(kt), _ptr(z), int(threads))
+    _check(rc)
+    n = min(nk.value, kept_cap)
+    return {"s": s.value, "J": J.value, "n_kept": nk.value, "kept": kept[:n].copy(),
+            "kept_counts": [(int(kt[2 * i + 1]) << 64) | int(kt[2 * i]) for i in range(k)],
+            "Z": [float(x) for x in z], "L": int(c) * int(delta)}
+
+
 # ---------------------------------------------------------------- tier B
 
 def brute(edges, motif, delta, win=None):
@@ -229,6 +294,31 @@ def brute(edges, motif, delta, win=None):
                 break
         if ok and len(set(f.values())) == len(f):
             out[es[-1][2] - es[0][2]] += 1
+    return out
+
+
+def brute_per_first(edges, motif, delta, win_hi=None):
+    """Per first edge: the number of instances (same enumeration as
+    ``brute``) whose first edge has index i, with every edge at time
+    <= win_hi[i] when win_hi is given.  Returns {i: count}."""
+    l = len(motif)
+    out = Counter()
+    for tup in itertools.permutations(range(len(edges)), l):
+        es = [edges[i] for i in tup]
+        if not all(es[r][2] < es[r + 1][2] for r in range(l - 1)):
+            continue
+        if es[-1][2] - es[0][2] > delta:
+            continue
+        if win_hi is not None and any(e[2] > win_hi[tup[0]] for e in es):
+            continue
+        f = {}
+        ok = True
+        for (mu, mv), (gu, gv, _) in zip(motif, es):
+            if f.setdefault(mu, gu) != gu or f.setdefault(mv, gv) != gv:
+                ok = False
+                break
+        if ok and len(set(f.values())) == len(f):
+            out[tup[0]] += 1
     return out
 
 

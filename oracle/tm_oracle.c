@@ -157,6 +157,7 @@ static void anchor_count(ctx_t *c, int64_t q) {
     int64_t e = c->ord[q];
     int64_t te = c->t[e];
     int nu, nv;
+    if (te > c->win_hi) return; /* every edge of an instance, the first one too, lies in the window */
     for (int x = 0; x < c->k; ++x) c->f[x] = -1;
     if (!bind(c, c->ms[0], c->src[e], &nu)) return;
     if (!bind(c, c->md[0], c->dst[e], &nv)) return;

@@ -1,0 +1,592 @@
+/*
+ * Tier C of the CPU oracle: indexed exact counts of three-edge motifs, for
+ * graphs too large for the brute force of tm_oracle.c.
+ *
+ * TEST INFRASTRUCTURE ONLY, under the same rules as tm_oracle.c: nothing in
+ * the library under paper_1810_00980_amd/ links, loads or calls this file;
+ * only tests/, __graft_entry__.smoke() and the CPU-baseline leg of bench.py
+ * use it.  It shares no code, header, table or helper with the HIP path, and
+ * none with tm_oracle.c either except the exported draw and weighting
+ * functions that the estimate below calls.
+ *
+ * What it computes is orc_count's set (Sec. 2, Definitions "temporal motif",
+ * "motif delta-instance" and "motif duration") for motifs of three edges on
+ * at most three nodes, restated so that graphs of millions of edges finish:
+ *
+ *  - two edges that together with a third span at most three nodes share a
+ *    node, so the first edge e1 and the last edge e3 of an instance do.  The
+ *    candidates e3 of one e1 are the edges of the time-sorted incidence lists
+ *    of e1's two endpoints with time in (t1, min(t1 + delta, win_hi)]; an
+ *    edge that touches both endpoints is taken from the first endpoint's list
+ *    only;
+ *  - for one (e1, e3) the middles are the edges e2 with t1 < t2 < t3 (times
+ *    increase strictly) whose endpoints keep (e1, e2, e3) on at most three
+ *    nodes.  When e1 and e3 span three nodes, e2 joins two of them (six
+ *    directed pairs).  When they lie on one node pair {a, b}, e2 is a -> b,
+ *    b -> a, or joins a or b to a third node: a node's out- (in-) edges minus
+ *    those to (from) the pair's other node, self-loops left out, so that the
+ *    node map stays injective.  Each kind of middle is a count of the times
+ *    of one sorted list strictly between t1 and t3: a binary search for the
+ *    first time above t1, once per anchor and list, and a cursor that walks
+ *    to the first time at or above t3 as the anchor's later edges come in
+ *    time order;
+ *  - all instances with first edge e1 and last edge e3 have the duration
+ *    t3 - t1, so each kind of middle adds its count to one histogram bin of
+ *    the motif that (e1, e2, e3) is an instance of (its canonical form: nodes
+ *    numbered by first appearance).
+ *
+ * Anchors e1 are shared out between OpenMP threads; each thread sums into
+ * its own histograms and totals, which are added up at the end, so results
+ * do not depend on the thread count.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef unsigned __int128 u128;
+
+#define ORC_OK 0
+#define ORC_EINVAL 1
+#define ORC_ENOMEM 3
+#define ORC_EOVERFLOW 5
+
+/* from tm_oracle.c */
+uint64_t orc_draw(uint64_t seed, uint64_t j, uint32_t k, uint32_t domain);
+double orc_weight(const uint64_t *hist_lo, const uint64_t *hist_hi, int64_t delta, int64_t L, double p);
+
+/* ------------------------------------------------------------ sorted lists */
+
+/* first index in a[0..n) with a[i] >= x */
+static int64_t lower(const int64_t *a, int64_t n, int64_t x) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+/* first index in a[0..n) with a[i] > x */
+static int64_t upper(const int64_t *a, int64_t n, int64_t x) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (a[mid] <= x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+/* number of times in a[0..n) strictly between lo and hi */
+static int64_t between(const int64_t *a, int64_t n, int64_t lo, int64_t hi) {
+    int64_t b = lower(a, n, hi), a0 = upper(a, n, lo);
+    return b > a0 ? b - a0 : 0;
+}
+
+/* A family of sorted time lists: list k is t[off[k] .. off[k+1]). */
+typedef struct {
+    int64_t *off;
+    int64_t *t;
+} lists_t;
+
+static int64_t list_between(const lists_t *L, int64_t k, int64_t lo, int64_t hi) {
+    return between(L->t + L->off[k], L->off[k + 1] - L->off[k], lo, hi);
+}
+
+static int cmp_i64(const void *a, const void *b) {
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* lists by integer key: key[i] in [0, nkeys) for the items i with key >= 0;
+   times sorted within each list.  item_of (nullable) receives, per list
+   position, the item index, in time order. */
+static int build_lists(int64_t nitems, const int64_t *key, const int64_t *t, int64_t nkeys, lists_t *L,
+                       int64_t **item_of) {
+    L->off = (int64_t *)calloc((size_t)nkeys + 1, sizeof(int64_t));
+    L->t = (int64_t *)malloc((size_t)(nitems ? nitems : 1) * sizeof(int64_t));
+    int64_t *items = item_of ? (int64_t *)malloc((size_t)(nitems ? nitems : 1) * sizeof(int64_t)) : NULL;
+    int64_t *fill = (int64_t *)malloc((size_t)(nkeys + 1) * sizeof(int64_t));
+    if (!L->off || !L->t || !fill || (item_of && !items)) {
+        free(L->off); free(L->t); free(items); free(fill);
+        return ORC_ENOMEM;
+    }
+    for (int64_t i = 0; i < nitems; ++i)
+        if (key[i] >= 0) L->off[key[i] + 1] += 1;
+    for (int64_t k = 0; k < nkeys; ++k) L->off[k + 1] += L->off[k];
+    memcpy(fill, L->off, (size_t)(nkeys + 1) * sizeof(int64_t));
+    if (item_of) {
+        /* items in time order: sort (time, item) pairs per list */
+        for (int64_t i = 0; i < nitems; ++i)
+            if (key[i] >= 0) items[fill[key[i]]++] = i;
+        for (int64_t k = 0; k < nkeys; ++k) {
+            int64_t a = L->off[k], n = L->off[k + 1] - a;
+            /* sort (time, item) pairs by time; tied times may come out in any
+               order, which no count depends on (tied edges never share an
+               instance) */
+            if (n > 1) {
+                int64_t *pair = (int64_t *)malloc((size_t)n * 2 * sizeof(int64_t));
+                if (!pair) { free(L->off); free(L->t); free(items); free(fill); return ORC_ENOMEM; }
+                for (int64_t q = 0; q < n; ++q) {
+                    pair[2 * q] = t[items[a + q]];
+                    pair[2 * q + 1] = items[a + q];
+                }
+                qsort(pair, (size_t)n, 2 * sizeof(int64_t), cmp_i64);
+                for (int64_t q = 0; q < n; ++q) items[a + q] = pair[2 * q + 1];
+                free(pair);
+            }
+            for (int64_t q = 0; q < n; ++q) L->t[a + q] = t[items[a + q]];
+        }
+        *item_of = items;
+    } else {
+        for (int64_t i = 0; i < nitems; ++i)
+            if (key[i] >= 0) L->t[fill[key[i]]++] = t[i];
+        for (int64_t k = 0; k < nkeys; ++k)
+            qsort(L->t + L->off[k], (size_t)(L->off[k + 1] - L->off[k]), sizeof(int64_t), cmp_i64);
+    }
+    free(fill);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------ pair index */
+
+/* directed pair (a, b) -> list number, open addressing over 64-bit keys */
+typedef struct {
+    uint64_t *key;
+    int64_t *val;
+    uint64_t cap;
+} pmap_t;
+
+static uint64_t mix64(uint64_t x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return x;
+}
+
+static int64_t pmap_get(const pmap_t *P, int64_t a, int64_t b) {
+    uint64_t k = ((uint64_t)a << 32) | (uint64_t)b;
+    uint64_t h = mix64(k) & (P->cap - 1);
+    while (P->key[h] != ~0ull) {
+        if (P->key[h] == k) return P->val[h];
+        h = (h + 1) & (P->cap - 1);
+    }
+    return -1;
+}
+
+/* ------------------------------------------------------------ motifs */
+
+/* canonical code of three directed edges given by node ids: nodes numbered
+   0, 1, 2 by first appearance, code = sum of label_k 3^k over the six
+   endpoints; -1 when more than three nodes appear */
+static int canon3(int64_t a1, int64_t b1, int64_t a2, int64_t b2, int64_t a3, int64_t b3) {
+    int64_t seen[3];
+    int ns = 0, code = 0, mul = 1;
+    int64_t v[6] = {a1, b1, a2, b2, a3, b3};
+    for (int k = 0; k < 6; ++k) {
+        int lab = -1;
+        for (int q = 0; q < ns; ++q)
+            if (seen[q] == v[k]) lab = q;
+        if (lab < 0) {
+            if (ns == 3) return -1;
+            seen[ns] = v[k];
+            lab = ns++;
+        }
+        code += lab * mul;
+        mul *= 3;
+    }
+    return code;
+}
+
+/* ------------------------------------------------------------ counting */
+
+typedef struct {
+    int64_t n;              /* node ids are < n */
+    int64_t m;
+    const int32_t *src, *dst;
+    const int64_t *t;
+    lists_t inc;            /* per node: times of its incidence entries */
+    int64_t *inc_e;         /* per incidence position: edge index */
+    lists_t out, in;        /* per node: times of out- / in-edges */
+    lists_t pair;           /* per directed pair: times */
+    pmap_t pm;
+} cgraph_t;
+
+static void cgraph_free(cgraph_t *G) {
+    free(G->inc.off); free(G->inc.t); free(G->inc_e);
+    free(G->out.off); free(G->out.t);
+    free(G->in.off); free(G->in.t);
+    free(G->pair.off); free(G->pair.t);
+    free(G->pm.key); free(G->pm.val);
+    memset(G, 0, sizeof *G);
+}
+
+static int cgraph_build(cgraph_t *G, int64_t m, const int32_t *src, const int32_t *dst, const int64_t *t) {
+    memset(G, 0, sizeof *G);
+    G->m = m; G->src = src; G->dst = dst; G->t = t;
+    int64_t n = 1;
+    for (int64_t i = 0; i < m; ++i) {
+        if (src[i] < 0 || dst[i] < 0) return ORC_EINVAL;
+        if (src[i] + 1 > n) n = src[i] + 1;
+        if (dst[i] + 1 > n) n = dst[i] + 1;
+    }
+    G->n = n;
+    int rc = ORC_ENOMEM;
+    int64_t *key = (int64_t *)malloc((size_t)(2 * m + 1) * sizeof(int64_t));
+    int64_t *tt = (int64_t *)malloc((size_t)(2 * m + 1) * sizeof(int64_t));
+    int64_t *pk = (int64_t *)malloc((size_t)(m + 1) * sizeof(int64_t));
+    uint64_t *pkeys = (uint64_t *)malloc((size_t)(m + 1) * sizeof(uint64_t));
+    if (!key || !tt || !pk || !pkeys) goto done;
+    /* incidence lists: entry 2i in src's list, 2i + 1 in dst's list */
+    for (int64_t i = 0; i < m; ++i) {
+        int loop = src[i] == dst[i];
+        key[2 * i] = loop ? -1 : src[i];
+        key[2 * i + 1] = loop ? -1 : dst[i];
+        tt[2 * i] = tt[2 * i + 1] = t[i];
+    }
+    {
+        int64_t *ent = NULL;
+        if (build_lists(2 * m, key, tt, n, &G->inc, &ent) != ORC_OK) goto done;
+        for (int64_t q = 0; q < G->inc.off[n]; ++q) ent[q] >>= 1; /* entry -> edge index */
+        G->inc_e = ent;
+    }
+    for (int64_t i = 0; i < m; ++i) key[i] = src[i] == dst[i] ? -1 : src[i];
+    if (build_lists(m, key, t, n, &G->out, NULL) != ORC_OK) goto done;
+    for (int64_t i = 0; i < m; ++i) key[i] = src[i] == dst[i] ? -1 : dst[i];
+    if (build_lists(m, key, t, n, &G->in, NULL) != ORC_OK) goto done;
+    /* directed pairs: distinct (src, dst) keys numbered in sorted order */
+    {
+        int64_t np = 0;
+        for (int64_t i = 0; i < m; ++i)
+            if (src[i] != dst[i]) pkeys[np++] = ((uint64_t)src[i] << 32) | (uint64_t)dst[i];
+        qsort(pkeys, (size_t)np, sizeof(uint64_t), cmp_i64); /* keys < 2^63: signed order is fine */
+        int64_t S = 0;
+        for (int64_t q = 0; q < np; ++q)
+            if (q == 0 || pkeys[q] != pkeys[q - 1]) pkeys[S++] = pkeys[q];
+        uint64_t cap = 16;
+        while (cap < (uint64_t)(2 * S + 2)) cap <<= 1;
+        G->pm.cap = cap;
+        G->pm.key = (uint64_t *)malloc(cap * sizeof(uint64_t));
+        G->pm.val = (int64_t *)malloc(cap * sizeof(int64_t));
+        if (!G->pm.key || !G->pm.val) goto done;
+        for (uint64_t h = 0; h < cap; ++h) G->pm.key[h] = ~0ull;
+        for (int64_t q = 0; q < S; ++q) {
+            uint64_t h = mix64(pkeys[q]) & (cap - 1);
+            while (G->pm.key[h] != ~0ull) h = (h + 1) & (cap - 1);
+            G->pm.key[h] = pkeys[q];
+            G->pm.val[h] = q;
+        }
+        for (int64_t i = 0; i < m; ++i)
+            pk[i] = src[i] == dst[i] ? -1 : pmap_get(&G->pm, src[i], dst[i]);
+        if (build_lists(m, pk, t, S, &G->pair, NULL) != ORC_OK) goto done;
+    }
+    rc = ORC_OK;
+done:
+    free(key); free(tt); free(pk); free(pkeys);
+    if (rc != ORC_OK) cgraph_free(G);
+    return rc;
+}
+
+static int64_t pair_between(const cgraph_t *G, int64_t a, int64_t b, int64_t lo, int64_t hi) {
+    int64_t k = pmap_get(&G->pm, a, b);
+    return k < 0 ? 0 : list_between(&G->pair, k, lo, hi);
+}
+
+/* per-thread sums */
+typedef struct {
+    u128 *total;      /* per motif */
+    uint64_t *hist;   /* per motif, delta + 1 bins (nullable) */
+    int overflow;
+} sums_t;
+
+/* cnt instances of the k-th motif (k < 0: not asked for) of duration d */
+static void add_inst(sums_t *S, int k, int64_t cnt, int64_t d, int64_t delta) {
+    if (cnt <= 0 || k < 0) return;
+    S->total[k] += (u128)cnt;
+    if (S->hist) {
+        uint64_t *b = &S->hist[(size_t)k * (size_t)(delta + 1) + (size_t)d];
+        if (*b > UINT64_MAX - (uint64_t)cnt) S->overflow = 1;
+        *b += (uint64_t)cnt;
+    }
+}
+
+/* Count of the times of one sorted list that lie strictly between t1 and
+   a later time t3, for a sequence of non-decreasing t3 (the later edges of
+   one anchor in time order): lo = first entry above t1 (one binary search),
+   and a cursor walks forward to the first entry at or above t3. */
+typedef struct {
+    const int64_t *a;
+    int64_t n, lo, cur;
+} range_t;
+
+static void range_init(range_t *r, const lists_t *L, int64_t k, int64_t t1) {
+    if (k < 0) {
+        r->a = NULL;
+        r->n = r->lo = r->cur = 0;
+        return;
+    }
+    r->a = L->t + L->off[k];
+    r->n = L->off[k + 1] - L->off[k];
+    r->lo = upper(r->a, r->n, t1);
+    r->cur = r->lo;
+}
+
+static int64_t range_count(range_t *r, int64_t t3) {
+    while (r->cur < r->n && r->a[r->cur] < t3) ++r->cur;
+    return r->cur - r->lo;
+}
+
+/* the four directed pairs between a third node y and the two endpoints of
+   the anchor, remembered for the anchor's later edges that lead to y again */
+#define YCACHE 16
+typedef struct {
+    int64_t y;
+    range_t xy, yx, oy, yo;  /* x -> y, y -> x, o -> y, y -> o */
+} yslot_t;
+
+/* instances with first edge e1 (an edge that is not a self-loop) */
+static void anchor3(const cgraph_t *G, const int *table, int64_t e1, int64_t delta, int64_t win_hi, sums_t *S) {
+    const int64_t u1 = G->src[e1], v1 = G->dst[e1], t1 = G->t[e1];
+    int64_t tlim = t1 > INT64_MAX - delta ? INT64_MAX : t1 + delta;
+    if (tlim > win_hi) tlim = win_hi;
+    const int64_t Z = -1, Y = -2; /* stand-ins for a third node, other than u1 and v1 */
+    const int64_t k_uv = pmap_get(&G->pm, u1, v1), k_vu = pmap_get(&G->pm, v1, u1);
+    yslot_t yc[YCACHE];
+    for (int side = 0; side < 2; ++side) {
+        const int64_t x = side == 0 ? u1 : v1, o = side == 0 ? v1 : u1;
+        /* motif of (e1, e2, e3) by the kind of middle, for both directions of
+           e3 (r = 0: e3 leaves x); canon3 depends only on which endpoints are
+           equal, so stand-ins for the third node give the same motif */
+        int mot2[2][6], mot3[2][6];
+        for (int r = 0; r < 2; ++r) {
+            const int64_t a3 = r == 0 ? x : o, b3 = r == 0 ? o : x;    /* e3 on {u1, v1} */
+            const int64_t c3 = r == 0 ? x : Y, d3 = r == 0 ? Y : x;    /* e3 = x - third node */
+            const int64_t m2[6][2] = {{u1, v1}, {v1, u1}, {u1, Z}, {Z, u1}, {v1, Z}, {Z, v1}};
+            const int64_t m3[6][2] = {{u1, v1}, {v1, u1}, {x, Y}, {Y, x}, {o, Y}, {Y, o}};
+            for (int k = 0; k < 6; ++k) {
+                int c = canon3(u1, v1, m2[k][0], m2[k][1], a3, b3);
+                mot2[r][k] = c < 0 ? -1 : table[c];
+                c = canon3(u1, v1, m3[k][0], m3[k][1], c3, d3);
+                mot3[r][k] = c < 0 ? -1 : table[c];
+            }
+        }
+        /* lists whose nodes the anchor fixes: u1 -> v1, v1 -> u1, and the
+           out- and in-lists of u1 and v1 */
+        range_t r_uv, r_vu, r_out[2], r_in[2];
+        range_init(&r_uv, &G->pair, k_uv, t1);
+        range_init(&r_vu, &G->pair, k_vu, t1);
+        range_init(&r_out[0], &G->out, u1, t1);
+        range_init(&r_out[1], &G->out, v1, t1);
+        range_init(&r_in[0], &G->in, u1, t1);
+        range_init(&r_in[1], &G->in, v1, t1);
+        for (int c = 0; c < YCACHE; ++c) yc[c].y = -1;
+        const int64_t a = G->inc.off[x], b = G->inc.off[x + 1];
+        for (int64_t q = a + upper(G->inc.t + a, b - a, t1); q < b && G->inc.t[q] <= tlim; ++q) {
+            const int64_t e3 = G->inc_e[q];
+            const int64_t u3 = G->src[e3], v3 = G->dst[e3], t3 = G->t[e3];
+            if (side == 1 && (u3 == u1 || v3 == u1)) continue; /* already taken from u1's list */
+            const int64_t y3 = u3 == x ? v3 : u3;
+            const int r = u3 == x ? 0 : 1;
+            const int64_t d = t3 - t1;
+            /* the counts of the fixed lists in (t1, t3) */
+            const int64_t n_uv = range_count(&r_uv, t3), n_vu = range_count(&r_vu, t3);
+            if (y3 == o) {
+                /* e1 and e3 on one node pair {u1, v1}: e2 is u1 -> v1 or
+                   v1 -> u1, or joins u1 or v1 to a third node */
+                const int *K = mot2[r];
+                add_inst(S, K[0], n_uv, d, delta);
+                add_inst(S, K[1], n_vu, d, delta);
+                if (K[2] >= 0) add_inst(S, K[2], range_count(&r_out[0], t3) - n_uv, d, delta); /* u1 -> third */
+                if (K[3] >= 0) add_inst(S, K[3], range_count(&r_in[0], t3) - n_vu, d, delta);  /* third -> u1 */
+                if (K[4] >= 0) add_inst(S, K[4], range_count(&r_out[1], t3) - n_vu, d, delta); /* v1 -> third */
+                if (K[5] >= 0) add_inst(S, K[5], range_count(&r_in[1], t3) - n_uv, d, delta);  /* third -> v1 */
+            } else {
+                /* three nodes u1, v1, y3: e2 joins two of them */
+                const int *K = mot3[r];
+                yslot_t *W = &yc[(uint64_t)y3 % YCACHE];
+                if (W->y != y3) {
+                    W->y = y3;
+                    range_init(&W->xy, &G->pair, pmap_get(&G->pm, x, y3), t1);
+                    range_init(&W->yx, &G->pair, pmap_get(&G->pm, y3, x), t1);
+                    range_init(&W->oy, &G->pair, pmap_get(&G->pm, o, y3), t1);
+                    range_init(&W->yo, &G->pair, pmap_get(&G->pm, y3, o), t1);
+                }
+                add_inst(S, K[0], n_uv, d, delta);
+                add_inst(S, K[1], n_vu, d, delta);
+                if (K[2] >= 0) add_inst(S, K[2], range_count(&W->xy, t3), d, delta);
+                if (K[3] >= 0) add_inst(S, K[3], range_count(&W->yx, t3), d, delta);
+                if (K[4] >= 0) add_inst(S, K[4], range_count(&W->oy, t3), d, delta);
+                if (K[5] >= 0) add_inst(S, K[5], range_count(&W->yo, t3), d, delta);
+            }
+        }
+    }
+}
+
+/* motif table: canonical code -> position in the caller's list */
+static int motif_table(int n_mot, const int32_t *ms, const int32_t *md, int table[729]) {
+    if (n_mot < 1 || n_mot > 64) return ORC_EINVAL;
+    for (int k = 0; k < 729; ++k) table[k] = -1;
+    for (int i = 0; i < n_mot; ++i) {
+        const int32_t *a = ms + 3 * i, *b = md + 3 * i;
+        for (int k = 0; k < 3; ++k)
+            if (a[k] < 0 || b[k] < 0 || a[k] > 2 || b[k] > 2 || a[k] == b[k]) return ORC_EINVAL;
+        int code = canon3(a[0], b[0], a[1], b[1], a[2], b[2]);
+        /* canonical: the code of the labels as given equals that of their relabelling */
+        int direct = a[0] + 3 * b[0] + 9 * a[1] + 27 * b[1] + 81 * a[2] + 243 * b[2];
+        if (code < 0 || code != direct || table[code] >= 0) return ORC_EINVAL;
+        table[code] = i;
+    }
+    return ORC_OK;
+}
+
+/* counts of every anchor with time in [win_lo, win_hi] of a built graph */
+static int count3_run(const cgraph_t *G, const int *table, int n_mot, int64_t delta, int64_t win_lo,
+                      int64_t win_hi, uint64_t *totals, uint64_t *hist, int nthreads) {
+    const size_t hb = hist ? (size_t)n_mot * (size_t)(delta + 1) : 0;
+    if (hist) memset(hist, 0, hb * sizeof(uint64_t));
+    u128 tot[64];
+    memset(tot, 0, sizeof tot);
+    int overflow = 0, fail = 0;
+    const int64_t m = G->m;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#else
+    nthreads = 1;
+#endif
+#pragma omp parallel num_threads(nthreads)
+    {
+        sums_t S;
+        S.overflow = 0;
+        S.total = (u128 *)calloc((size_t)n_mot, sizeof(u128));
+        S.hist = hist ? (uint64_t *)calloc(hb ? hb : 1, sizeof(uint64_t)) : NULL;
+        if (!S.total || (hist && !S.hist)) {
+#pragma omp atomic write
+            fail = 1;
+        }
+        /* every thread takes part in the loop (the work split needs all of them) */
+#pragma omp for schedule(dynamic, 512)
+        for (int64_t e = 0; e < m; ++e) {
+            if (!S.total || (hist && !S.hist)) continue;
+            if (G->src[e] == G->dst[e] || G->t[e] < win_lo || G->t[e] > win_hi) continue;
+            anchor3(G, table, e, delta, win_hi, &S);
+        }
+        if (S.total && (!hist || S.hist)) {
+#pragma omp critical
+            {
+                for (int k = 0; k < n_mot; ++k) tot[k] += S.total[k];
+                if (hist)
+                    for (size_t q = 0; q < hb; ++q) {
+                        if (hist[q] > UINT64_MAX - S.hist[q]) overflow = 1;
+                        hist[q] += S.hist[q];
+                    }
+                overflow |= S.overflow;
+            }
+        }
+        free(S.total);
+        free(S.hist);
+    }
+    if (fail) return ORC_ENOMEM;
+    for (int k = 0; k < n_mot; ++k) {
+        totals[2 * k] = (uint64_t)tot[k];
+        totals[2 * k + 1] = (uint64_t)(tot[k] >> 64);
+    }
+    return overflow ? ORC_EOVERFLOW : ORC_OK;
+}
+
+/*
+ * Exact counts of n_mot three-edge motifs (ms/md: 3 n_mot node labels,
+ * motif-major, canonical, pairwise distinct, n_mot <= 64) among the edges
+ * with times in [win_lo, win_hi]: totals (2 n_mot words, lo/hi per motif)
+ * and, when hist is not NULL, duration histograms (n_mot (delta + 1) bins,
+ * motif-major, cleared here).  nthreads <= 0: all available.
+ */
+int orc_count3_indexed(int64_t m, const int32_t *src, const int32_t *dst, const int64_t *t, int n_mot,
+                       const int32_t *ms, const int32_t *md, int64_t delta, int64_t win_lo, int64_t win_hi,
+                       uint64_t *totals, uint64_t *hist, int nthreads) {
+    if (m < 0 || delta < 0) return ORC_EINVAL;
+    int table[729];
+    int rc = motif_table(n_mot, ms, md, table);
+    if (rc != ORC_OK) return rc;
+    cgraph_t G;
+    rc = cgraph_build(&G, m, src, dst, t);
+    if (rc != ORC_OK) return rc;
+    rc = count3_run(&G, table, n_mot, delta, win_lo, win_hi, totals, hist, nthreads);
+    cgraph_free(&G);
+    return rc;
+}
+
+/*
+ * Algorithm 1 (Sec. 4) with one shift and q_j = p for n_mot three-edge
+ * motifs at once, the windows counted by orc_count3_indexed: times
+ * normalised to start at 0, J = 1 + ceil(t_max / (c delta)), the shift from
+ * draw (0, 0, domain 0), window j kept when the uniform of draw (j, 0,
+ * domain 1) is below p (the same draws as orc_estimate), each kept window
+ * counted with its duration histograms, which add up over kept windows, and
+ * each motif's sum weighted by orc_weight.
+ * Outputs: *s_out, *J_out, *nkept_out; kept ids (first kept_cap); kept
+ * totals (2 n_mot words); Z[n_mot].
+ */
+int orc_estimate3_indexed(int64_t m, const int32_t *src, const int32_t *dst, const int64_t *t, int n_mot,
+                          const int32_t *ms, const int32_t *md, int64_t delta, int64_t cwin, double p,
+                          uint64_t seed, int64_t *s_out, int64_t *J_out, int64_t *nkept_out, int64_t *kept_ids,
+                          int64_t kept_cap, uint64_t *kept_totals, double *Z, int nthreads) {
+    if (m < 0 || delta < 1 || cwin < 2 || !(p > 0.0 && p <= 1.0)) return ORC_EINVAL;
+    if (delta > INT64_MAX / cwin) return ORC_EINVAL;
+    int table[729];
+    int rc = motif_table(n_mot, ms, md, table);
+    if (rc != ORC_OK) return rc;
+    const int64_t L = cwin * delta;
+    const size_t hb = (size_t)n_mot * (size_t)(delta + 1);
+    int64_t *tn = (int64_t *)malloc((size_t)(m ? m : 1) * sizeof(int64_t));
+    uint64_t *h = (uint64_t *)calloc(hb, sizeof(uint64_t));
+    uint64_t *hw = (uint64_t *)malloc(hb * sizeof(uint64_t));
+    uint64_t *tw = (uint64_t *)malloc((size_t)n_mot * 2 * sizeof(uint64_t));
+    if (!tn || !h || !hw || !tw) { free(tn); free(h); free(hw); free(tw); return ORC_ENOMEM; }
+    int64_t tmin = 0, tmax = 0;
+    for (int64_t i = 0; i < m; ++i)
+        if (i == 0 || t[i] < tmin) tmin = t[i];
+    for (int64_t i = 0; i < m; ++i) {
+        tn[i] = t[i] - tmin;
+        if (tn[i] > tmax) tmax = tn[i];
+    }
+    const int64_t J = 1 + (tmax / L) + ((tmax % L) ? 1 : 0);
+    const int64_t s = -(int64_t)(orc_draw(seed, 0, 0, 0) % (uint64_t)L);
+    u128 kt[64];
+    memset(kt, 0, sizeof kt);
+    int64_t nkept = 0;
+    cgraph_t G;
+    rc = cgraph_build(&G, m, src, dst, tn);
+    if (rc != ORC_OK) { free(tn); free(h); free(hw); free(tw); return rc; }
+    for (int64_t j = 1; j <= J && rc == ORC_OK; ++j) {
+        const uint64_t x = orc_draw(seed, (uint64_t)j, 0, 1);
+        const double u = (double)(x >> 11) * (1.0 / 9007199254740992.0);
+        if (!(u < p)) continue;
+        const int64_t lo = s + (j - 1) * L, hi = s + j * L - 1;
+        rc = count3_run(&G, table, n_mot, delta, lo, hi, tw, hw, nthreads);
+        for (size_t q = 0; q < hb; ++q) {
+            if (h[q] > UINT64_MAX - hw[q]) rc = ORC_EOVERFLOW;
+            h[q] += hw[q];
+        }
+        for (int k = 0; k < n_mot; ++k) kt[k] += ((u128)tw[2 * k + 1] << 64) | tw[2 * k];
+        if (nkept < kept_cap && kept_ids) kept_ids[nkept] = j;
+        ++nkept;
+    }
+    *s_out = s;
+    *J_out = J;
+    *nkept_out = nkept;
+    for (int k = 0; k < n_mot; ++k) {
+        kept_totals[2 * k] = (uint64_t)kt[k];
+        kept_totals[2 * k + 1] = (uint64_t)(kt[k] >> 64);
+        Z[k] = orc_weight(h + (size_t)k * (size_t)(delta + 1), NULL, delta, L, p);
+    }
+    cgraph_free(&G);
+    free(tn); free(h); free(hw); free(tw);
+    return rc;
+}

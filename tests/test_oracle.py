@@ -504,3 +504,118 @@ def test_bifan_hand_example():
     # two parallel edges on every pair, all in motif order by blocks: 2^4 instances
     blocks = [(a, c, 1), (a, c, 2), (a, d, 3), (a, d, 4), (b, c, 5), (b, c, 6), (b, d, 7), (b, d, 8)]
     assert ocount(blocks, ti.BIFAN, 10)[0] == 16
+
+
+# ------------------------------------------------------- per-anchor counts
+
+@pytest.mark.parametrize("seed", range(4))
+def test_per_anchor_counts_sum_to_total(seed):
+    """orc_count_anchors over every edge adds up to orc_count's total and
+    histogram (each instance has exactly one first edge)."""
+    g = ti.random_small_graph(5 + seed, 160, 300, 40 + seed, allow_self_loops=True)
+    allidx = np.arange(g.m)
+    for M in (ti.TRIANGLE, ((0, 1), (0, 2), (0, 1)), ti.TWO_NODE_ALT, ti.CYCLE4, ti.STAR4, ((0, 1),),
+              ((0, 1), (1, 0))):
+        for delta in (0, 9, 60):
+            per, h = oracle.count_anchors(g.src, g.dst, g.t, M, delta, allidx, hist=True)
+            n, hw = oracle.count(g.src, g.dst, g.t, M, delta)
+            assert int(per.sum(dtype=np.uint64)) == n, (M, delta)
+            assert np.array_equal(h, hw), (M, delta)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_per_anchor_counts_equal_tuple_brute_force(seed):
+    """Per first edge, with and without a window end per anchor, against the
+    tuple brute force filtered by first edge; the window bounds the first
+    edge as well as the later ones."""
+    g = ti.random_small_graph(4 + seed % 2, 12, 12, 300 + seed, allow_self_loops=(seed % 2 == 0))
+    edges = list(zip(g.src.tolist(), g.dst.tolist(), g.t.tolist()))
+    rng = np.random.default_rng(seed)
+    win = rng.integers(-1, 14, g.m)
+    allidx = np.arange(g.m)
+    for M in (ti.TRIANGLE, ((0, 1), (0, 2), (0, 1)), ti.TWO_NODE_ALT, ti.CYCLE4, ((0, 1),), ((0, 1), (1, 2))):
+        for delta in (0, 3, 8):
+            b = oracle.brute_per_first(edges, M, delta)
+            per = oracle.count_anchors(g.src, g.dst, g.t, M, delta, allidx)
+            assert [int(x) for x in per] == [b[i] for i in range(g.m)], (M, delta)
+            bw = oracle.brute_per_first(edges, M, delta, win_hi=win.tolist())
+            perw = oracle.count_anchors(g.src, g.dst, g.t, M, delta, allidx, win_hi=win)
+            assert [int(x) for x in perw] == [bw[i] for i in range(g.m)], (M, delta)
+
+
+# ----------------------------------------------------------------- tier C
+
+THREE = ti.three_edge_motifs()
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_tier_c_equals_tier_a(seed):
+    """Tier C (every first/last pair sharing a node, middles by range counts)
+    equals the brute force for all 36 motifs: counts and histograms, whole
+    graph and windowed, on graphs with ties, repeated pairs and self-loops."""
+    g = ti.random_small_graph(4 + seed % 5, 150 + 9 * seed, 400, 700 + seed, allow_self_loops=(seed % 2 == 0))
+    for delta in (0, 5, 40, 1000):
+        cnt, h = oracle.count3_indexed(g.src, g.dst, g.t, THREE, delta, hist=True, threads=2)
+        for k, M in enumerate(THREE):
+            want, hw = oracle.count(g.src, g.dst, g.t, M, delta)
+            assert cnt[k] == want and np.array_equal(h[k], hw), (M, delta)
+    for win in ((100, 250), (-5, 3), (390, 1000)):
+        sub = THREE[3::4]
+        cnt = oracle.count3_indexed(g.src, g.dst, g.t, sub, 40, win=win)
+        for k, M in enumerate(sub):
+            assert cnt[k] == oracle.count(g.src, g.dst, g.t, M, 40, win=win, hist=False)[0], (M, win)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_tier_c_equals_tuple_brute_force(seed):
+    g = ti.random_small_graph(4, 14, 9, 80 + seed, allow_self_loops=(seed % 2 == 1))
+    edges = list(zip(g.src.tolist(), g.dst.tolist(), g.t.tolist()))
+    for delta in (0, 2, 7):
+        cnt, h = oracle.count3_indexed(g.src, g.dst, g.t, THREE, delta, hist=True)
+        for k, M in enumerate(THREE):
+            b = oracle.brute(edges, M, delta)
+            assert cnt[k] == sum(b.values()) and np.array_equal(h[k], hist_of(b, delta)), (M, delta)
+
+
+def test_tier_c_closed_forms():
+    """Blocks n_ab n_bc n_ca of the cyclic triangle (H3) and C(L, 3) with the
+    duration histogram (d - 1)(L - d) on one pair (H4), through tier C."""
+    e, t = [], 0
+    for (u, v, k) in ((0, 1, 7), (1, 2, 5), (2, 0, 9)):
+        for _ in range(k):
+            t += 1
+            e.append((u, v, t))
+    s, d, tt = arr(e)
+    assert oracle.count3_indexed(s, d, tt, [TRI], t)[0] == 7 * 5 * 9
+    Lc = 40
+    s, d, tt = arr([(0, 1, x) for x in range(1, Lc + 1)])
+    m3 = ((0, 1), (0, 1), (0, 1))
+    cnt, h = oracle.count3_indexed(s, d, tt, [m3], Lc, hist=True)
+    assert cnt[0] == math.comb(Lc, 3)
+    assert [int(x) for x in h[0]] == [max(x - 1, 0) * (Lc - x) if x >= 2 else 0 for x in range(Lc + 1)]
+
+
+def test_tier_c_thread_count_and_motif_order_do_not_matter():
+    g = ti.zipf_graph(200, 5000, 1.5, 100_000, 5)
+    a = oracle.count3_indexed(g.src, g.dst, g.t, THREE, 900, threads=1)
+    b = oracle.count3_indexed(g.src, g.dst, g.t, THREE, 900, threads=5)
+    c = oracle.count3_indexed(g.src, g.dst, g.t, THREE[::-1], 900, threads=3)
+    assert a == b == c[::-1]
+    with pytest.raises(oracle.OracleError):  # a repeated motif
+        oracle.count3_indexed(g.src, g.dst, g.t, [TRI, TRI], 900)
+    with pytest.raises(oracle.OracleError):  # not canonical
+        oracle.count3_indexed(g.src, g.dst, g.t, [((1, 0), (0, 2), (2, 1))], 900)
+
+
+def test_tier_c_estimate_equals_brute_force_estimate():
+    """Algorithm 1 over tier C counts: the same shift, kept windows and, per
+    motif, the same kept count and estimate (to the last bit: the same
+    histogram weighted by the same routine) as the brute-force estimate."""
+    g = ti.random_small_graph(6, 900, 5000, 31, allow_self_loops=True)
+    for (delta, c, p, seed) in ((40, 2, 0.5, 1), (40, 3, 1.0, 2), (25, 10, 0.3, 3)):
+        r = oracle.estimate3_indexed(g.src, g.dst, g.t, THREE, delta, c, p, seed, threads=2)
+        for k, M in enumerate(THREE):
+            o = oracle.estimate(g.src, g.dst, g.t, M, delta, c, p, seed)
+            assert r["s"] == o["s"] and r["J"] == o["J"] and list(r["kept"]) == list(o["kept"])
+            assert r["kept_counts"][k] == int(o["win_counts"].sum()), M
+            assert r["Z"][k] == o["Z"], (M, r["Z"][k], o["Z"])
