@@ -306,6 +306,34 @@ tm_status tm_batch_config(const tm_graph *g, const tm_motif *M, int64_t delta, i
  */
 tm_status tm_batch_release(const tm_graph *g, void *hip_stream);
 
+/*
+ * Allocation-free variant of tm_estimate_multi, for callers that cannot
+ * allocate device memory: code under hipGraph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The estimates are those of
+ * tm_estimate_multi for the same arguments, to the last bit (the same
+ * kernels and the same exact fixed-point sums).
+ *
+ *  - Motifs: the 36 three-edge motifs on two or three nodes only
+ *    (TM_EUNSUPPORTED otherwise); n_motifs >= 1.  delta <= TM_NOALLOC_MAX_DELTA
+ *    (TM_EUNSUPPORTED above it); other argument errors as tm_estimate.
+ *  - Outputs are caller-owned DEVICE arrays: estimates_dev[n_motifs]
+ *    (double) and kept_dev[n_motifs] (nullable; exact kept-window counts).
+ *  - Work space: a library-owned static device array of
+ *    8 (152 + TM_NOALLOC_MAX_DELTA + 1) bytes (about 8 MiB) per GPU, held
+ *    until the process ends; no hipMalloc, hipFree or other allocation is
+ *    made.  Every call on one GPU shares that array: calls that overlap on one
+ *    GPU (different streams or host threads without ordering) race and give
+ *    wrong results.  Each call clears what it reads.
+ *  - The pass runs its kernels one after another on hip_stream and the call
+ *    returns once they are enqueued, without waiting: results are valid when
+ *    the stream reaches that point (synchronize it, or capture the call).
+ *    Errors of kernels that have not run yet surface in later HIP calls.
+ */
+#define TM_NOALLOC_MAX_DELTA ((int64_t)1048575)
+tm_status tm_estimate_multi_noalloc(const tm_graph *g, int32_t n_motifs, const tm_motif *motifs, int64_t delta,
+                                    int64_t c, double p, uint64_t seed, double *estimates_dev,
+                                    tm_u128 *kept_dev, void *hip_stream);
+
 /* ------------------------------------------------------------------ serving */
 
 typedef struct tm_server tm_server;

@@ -108,6 +108,7 @@ _SIGS = {
     "tm_count_window": [P, i32, P, i64, i64, i64, P, P],
     "tm_estimate": [P, P, i64, i64, f64, u64, P, P, P],
     "tm_estimate_multi": [P, i32, P, i64, i64, f64, u64, P, P, P],
+    "tm_estimate_multi_noalloc": [P, i32, P, i64, i64, f64, u64, P, P, P],
     "tm_estimate_q": [P, i32, P, i64, i64, f64, i32, u64, P, P, P],
     "tm_estimate_stream": [P, P, P, i64, i32, i32, P, i64, i64, f64, u64, P, P, P, P],
     "tm_estimate_batch": [P, P, i64, i64, f64, i32, P, i32, P, P, P],
@@ -311,6 +312,23 @@ def estimate_multi(g: Graph, motifs, delta: int, c: int, p: float, seed: int, st
     _check(_lib.tm_estimate_multi(g.handle, k, arr, int(delta), int(c), float(p), int(seed), est, kc,
                                   _stream(stream)), "tm_estimate_multi")
     return [est[i] for i in range(k)], [kc[i].value() for i in range(k)]
+
+
+NOALLOC_MAX_DELTA = 1048575
+
+
+def estimate_multi_noalloc(g: Graph, motifs, delta: int, c: int, p: float, seed: int, est_dev, kept_dev=None,
+                           stream=None):
+    """tm_estimate_multi_noalloc: the estimates of tm_estimate_multi written
+    into caller-owned device buffers (est_dev: float64 tensor of len(motifs);
+    kept_dev: nullable uint64 tensor of 2 len(motifs) words, lo/hi per motif)
+    without any device allocation.  Returns once the work is enqueued on the
+    stream; synchronize before reading the buffers."""
+    k = len(motifs)
+    arr = (Motif * max(k, 1))(*[motif(m) for m in motifs])
+    _check(_lib.tm_estimate_multi_noalloc(g.handle, k, arr, int(delta), int(c), float(p), int(seed),
+                                          P(est_dev.data_ptr()), P(kept_dev.data_ptr()) if kept_dev is not None
+                                          else None, _stream(stream)), "tm_estimate_multi_noalloc")
 
 
 def estimate_q(g: Graph, motifs, delta: int, c: int, r: float, b: int, seed: int, cap: int = 4096, stream=None):

@@ -1058,6 +1058,100 @@ extern "C" tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, cons
     return TM_OK;
 }
 
+// ------------------------------------------------ allocation-free estimates
+
+// Device scratch of tm_estimate_multi_noalloc, one copy per GPU, held until
+// the process ends: the sweep's 36 x 4 accumulators (144 words), its work
+// counters (8 words) and the delta + 1 fixed-point weights.  Host code never
+// passes the symbol itself to a kernel or a copy: it takes the device
+// address of this GPU's copy from hipGetSymbolAddress (noalloc_scratch).
+#define TM_NOALLOC_HEAD_WORDS 152
+#define TM_NOALLOC_WORDS ((int64_t)TM_NOALLOC_HEAD_WORDS + TM_NOALLOC_MAX_DELTA + 1)
+static __device__ __align__(256) uint64_t scratch[TM_NOALLOC_WORDS];
+
+namespace {
+
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[64];
+
+// This device's copy of the scratch array, looked up once per device with
+// the device current.
+tm_status noalloc_scratch(int dev, uint64_t **out) {
+    if (dev < 0 || dev >= 64) return TM_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        int cur = -1;
+        TM_HIP(hipGetDevice(&cur));
+        if (cur != dev) TM_HIP(hipSetDevice(dev));
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return TM_EDEVICE;
+        }
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *out = static_cast<uint64_t *>(g_noalloc_ptr[dev]);
+    return TM_OK;
+}
+
+// Up to 64 motifs per launch: est[i] = weight sum of code[i] / 2^52 / p and
+// kept[i] = its count, the same operations in the same order as the host
+// side of tm_estimate_multi (u128 to double, scale by 2^-52, divide by p).
+struct NoallocCodes {
+    int8_t code[64];
+};
+
+__global__ void k_noalloc_final(const uint64_t *out, NoallocCodes c, int32_t n, double p, double *est,
+                                tm_u128 *kept) {
+    const int i = (int)threadIdx.x;
+    if (i >= n) return;
+    const uint64_t *v = out + 4 * (int)c.code[i];
+    double x = (double)v[3] * 18446744073709551616.0;
+    x = x + (double)v[2];
+    x = x * (1.0 / 4503599627370496.0);
+    est[i] = x / p;
+    if (kept) {
+        kept[i].lo = v[0];
+        kept[i].hi = v[1];
+    }
+}
+
+}  // namespace
+
+extern "C" tm_status tm_estimate_multi_noalloc(const tm_graph *g, int32_t n_motifs, const tm_motif *motifs,
+                                               int64_t delta, int64_t c, double p, uint64_t seed,
+                                               double *estimates_dev, tm_u128 *kept_dev, void *hip_stream) {
+    if (!g || n_motifs < 1 || !motifs || !estimates_dev) return TM_EINVAL;
+    MotifPlan P;
+    for (int32_t i = 0; i < n_motifs; ++i) TM_TRY(tm_make_plan(&motifs[i], &P));
+    std::vector<int> codes;
+    uint64_t mask;
+    if (!all_sweep_codes(n_motifs, motifs, &codes, &mask)) return TM_EUNSUPPORTED;
+    int64_t L;
+    TM_TRY(check_est_args(g, delta, c, p, &L));
+    if (delta > TM_NOALLOC_MAX_DELTA) return TM_EUNSUPPORTED;
+    uint64_t *base = nullptr;
+    TM_TRY(noalloc_scratch(g->device, &base));
+    hipStream_t st = (hipStream_t)hip_stream;
+    uint64_t *out = base;
+    int64_t *ctr = reinterpret_cast<int64_t *>(base + 144);
+    uint64_t *wfx = base + TM_NOALLOC_HEAD_WORDS;
+    tm_status s = tm_sweep3(g, mask, 1, delta, 1, host_shift(seed, L), L, seed, p, out, nullptr, wfx, ctr, st,
+                            nullptr, nullptr, true);
+    for (int32_t b = 0; s == TM_OK && b < n_motifs; b += 64) {
+        NoallocCodes nc;
+        const int32_t k = std::min<int32_t>(64, n_motifs - b);
+        for (int32_t i = 0; i < k; ++i) nc.code[i] = (int8_t)codes[(size_t)(b + i)];
+        hipLaunchKernelGGL(k_noalloc_final, dim3(1), dim3(64), 0, st, (const uint64_t *)out, nc, k, p,
+                           estimates_dev + b, kept_dev ? kept_dev + b : nullptr);
+        s = tm_hip_status(hipGetLastError());
+    }
+    if (s != TM_OK) (void)hipGetLastError();
+    return s;
+}
+
 extern "C" tm_status tm_estimate_batch(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t c, double p,
                                        int32_t n_seeds, const uint64_t *seeds, int32_t tile, double *estimates,
                                        tm_u128 *kept_counts, void *hip_stream) {

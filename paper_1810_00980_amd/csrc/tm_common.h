@@ -359,11 +359,16 @@ int tm_sweep_code_of(const tm_motif *M);  // -1 when M is not one of them
 // 2 anchors in the one window [s, L]; 3 anchors in windows j (shift s,
 // length L) with kidx_dev[j] >= 0, whose sums go to the window's own slot
 // win_dev + 144 kidx_dev[j] (same layout as out_dev) instead of out_dev.
-// counter_dev: 8 int64 work-queue heads.
+// counter_dev: 8 int64 work-queue heads.  single_stream: run the pass's
+// kernels one after another on st instead of forking them onto the calling
+// thread's side streams (which are created on first use).  Accumulators and
+// counters are cleared by a kernel, not a memset.  Allocates nothing in
+// modes 1 and 2; the exact triangle sweep of mode 0 sorts its claim order in
+// a per-thread workspace.
 tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask, int mode, int64_t delta, int windowed, int64_t s,
                     int64_t L, uint64_t seed, double p, uint64_t *out_dev, uint64_t *hist_dev, uint64_t *wfx_dev,
                     int64_t *counter_dev, hipStream_t st, const int32_t *kidx_dev = nullptr,
-                    uint64_t *win_dev = nullptr);
+                    uint64_t *win_dev = nullptr, bool single_stream = false);
 
 // Largest delta for the sweep counter's histogram mode (36 histograms).
 #define TM_MAX_SWEEP_HIST_DELTA ((int64_t)1 << 20)

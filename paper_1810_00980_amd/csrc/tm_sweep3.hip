@@ -141,6 +141,22 @@ k_sweep3(DevGraph G, SweepArgs a) {
     }
 }
 
+// p[0 .. n) = 0.  The sweep clears its accumulators and work counters with
+// this kernel rather than a memset node, so that a caller may capture the
+// whole sequence in a hipGraph and replay it.
+__global__ void k_zero_u64(uint64_t *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+tm_status zero_u64(uint64_t *p, int64_t n, hipStream_t st) {
+    if (n <= 0) return TM_OK;
+    unsigned nb = tm_blocks(n, 256);
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_zero_u64, dim3(nb), dim3(256), 0, st, p, n);
+    return tm_hip_status(hipGetLastError());
+}
+
 // wfx[d] = round(2^52 L / (L - d)), d = 0..delta: the estimator's weight
 // 1 / (1 - d / L) in 52-bit fixed point (at most 2^53 for L >= 2 delta),
 // computed exactly by restoring long division of the 116-bit numerator.
@@ -358,7 +374,7 @@ tm_status tri_claim_order(const tm_graph *g, SweepArgs &a, hipStream_t st) {
 }
 
 template <int MODE>
-tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, hipStream_t st) {
+tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, bool single_stream, hipStream_t st) {
     DevGraph G = dev_view(g);
     int dev = g->device, ncu = 0;
     TM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -375,7 +391,7 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, hipStr
     // and bound by different things (the 2-node/star sweeps by VALU issue,
     // the triangle sweep by lookup latency), so they run on forked streams
     // and share the CUs; the caller's stream waits for all of them.
-    TM_HIP(hipMemsetAsync(a.counter, 0, 3 * sizeof(int64_t), st));
+    TM_TRY(zero_u64((uint64_t *)a.counter, 3, st));
     if (MODE == MODE_COUNT && fwd && (a.want_fwd & 8u) && a.windowed != 3) TM_TRY(tri_claim_order(g, a, st));
     if (MODE == MODE_WEIGHT && fwd && a.want_fwd == 1u && !bwd) {
         // the 2-node motifs alone: one anchor per pair entry
@@ -399,7 +415,7 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, hipStr
     if (fwd && (a.want_fwd & 7u)) todo[nl++] = {0};
     if (bwd) todo[nl++] = {1};
     if (nl == 0) return TM_OK;
-    SideStreams *side = (nl > 1 && !tm_prof_serial()) ? side_streams(dev) : nullptr;
+    SideStreams *side = (nl > 1 && !tm_prof_serial() && !single_stream) ? side_streams(dev) : nullptr;
     if (side) {
         TM_HIP(hipEventRecord(side->fork, st));
         for (int k = 1; k < nl; ++k) TM_HIP(hipStreamWaitEvent(side->s[k - 1], side->fork, 0));
@@ -661,7 +677,8 @@ int tm_sweep_code_of(const tm_motif *M) {
 // hist_dev: 36 x (delta+1) x 2 u64 (mode 2), zeroed here.
 tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask_lo, int mode, int64_t delta, int windowed, int64_t s,
                     int64_t L, uint64_t seed, double p, uint64_t *out_dev, uint64_t *hist_dev, uint64_t *wfx_dev,
-                    int64_t *counter_dev, hipStream_t st, const int32_t *kidx_dev, uint64_t *win_dev) {
+                    int64_t *counter_dev, hipStream_t st, const int32_t *kidx_dev, uint64_t *win_dev,
+                    bool single_stream) {
     if (windowed == 3 && (!kidx_dev || !win_dev)) return TM_EINVAL;
     SweepArgs a;
     a.kidx = kidx_dev;
@@ -684,16 +701,16 @@ tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask_lo, int mode, int64_t 
     if (code_mask_lo & 0xFF00000ull) wf |= 8;
     bool bwd = (code_mask_lo >> 28) & 0xFFull;
     a.want_fwd = wf;
-    TM_HIP(hipMemsetAsync(out_dev, 0, 36 * 4 * 8, st));
-    if (mode == MODE_HIST) TM_HIP(hipMemsetAsync(hist_dev, 0, (size_t)36 * (delta + 1) * 16, st));
+    TM_TRY(zero_u64(out_dev, 36 * 4, st));
+    if (mode == MODE_HIST) TM_TRY(zero_u64(hist_dev, (int64_t)36 * (delta + 1) * 2, st));
     if (mode == MODE_WEIGHT) {
         hipLaunchKernelGGL(k_weights_fx, dim3(tm_blocks(delta + 1, 256)), dim3(256), 0, st, delta, L, wfx_dev);
         TM_HIP(hipGetLastError());
     }
     if (a.n_entries == 0) return TM_OK;
     switch (mode) {
-        case MODE_COUNT: return launch_pair<MODE_COUNT>(g, a, wf != 0, bwd, st);
-        case MODE_WEIGHT: return launch_pair<MODE_WEIGHT>(g, a, wf != 0, bwd, st);
-        default: return launch_pair<MODE_HIST>(g, a, wf != 0, bwd, st);
+        case MODE_COUNT: return launch_pair<MODE_COUNT>(g, a, wf != 0, bwd, single_stream, st);
+        case MODE_WEIGHT: return launch_pair<MODE_WEIGHT>(g, a, wf != 0, bwd, single_stream, st);
+        default: return launch_pair<MODE_HIST>(g, a, wf != 0, bwd, single_stream, st);
     }
 }
