@@ -214,8 +214,11 @@ __device__ inline void count_anchor(const DevGraph &G, const MotifPlan &P, int64
     int64_t t1 = G.es_t[pos];
     int64_t hi = anchor_hi(t1, delta, win_end);
     if constexpr (LEN == 1) {
-        acc.add(1);
-        if (HIST) hist_add<HIST>(hlo, hhi, 0);
+        // every edge of an instance lies in the window, the first one too
+        if (t1 <= win_end) {
+            acc.add(1);
+            if (HIST) hist_add<HIST>(hlo, hhi, 0);
+        }
     } else {
         Binding f{-1, -1, -1, -1, -1};
         f.set(0, a);

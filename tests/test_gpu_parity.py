@@ -2,7 +2,9 @@
 inputs.  Counts and histograms must be bit-exact; estimates for the same seed
 within 1e-12 relative (the weighting is the same fixed-order FP64 sum, so in
 practice they are identical)."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -173,7 +175,7 @@ def test_per_anchor_counts(tm):
     rng = np.random.default_rng(0)
     anchors = rng.choice(g.m, size=100, replace=False)
     win = rng.integers(0, 2500, size=100)
-    for M in (ti.TRIANGLE, ti.STAR4, ti.BIFAN, ((0, 1), (1, 0), (0, 1))):
+    for M in (ti.TRIANGLE, ti.STAR4, ti.BIFAN, ((0, 1), (1, 0), (0, 1)), ((0, 1),), ((0, 1), (1, 2))):
         got = tm.count_anchors(G, M, 50, anchors, win_end=win)
         want = oracle.count_anchors(g.src, g.dst, g.t - g.t.min(), M, 50, anchors, win_hi=win)
         assert (got == want).all()
@@ -315,6 +317,11 @@ def test_estimate_stream_equals_in_memory(tm):
         if with_oracle:
             for M, z in list(zip(THREE, est))[::9]:
                 assert close(z, oracle.estimate(g.src, g.dst, g.t, M, delta, c, p, seed)["Z"]), M
+        else:  # the Zipf graph: tier C, every motif at once
+            o = oracle.estimate3_indexed(g.src, g.dst, g.t, THREE, delta, c, p, seed)
+            assert o["n_kept"] == info["n_kept"] and o["s"] == info["shift"] and kc == o["kept_counts"]
+            for M, z, zo in zip(THREE, est, o["Z"]):
+                assert close(z, zo), (M, z, zo)
     g = ti.random_small_graph(5, 300, 1000, 83)
     assert not np.all(np.diff(g.t) >= 0)
     with pytest.raises(tm.TMError):
@@ -381,6 +388,11 @@ def test_two_node_pair_sweep(tm):
         if with_oracle:
             for M, z in zip(TWO, e2):
                 assert close(z, oracle.estimate(g.src, g.dst, g.t, M, delta, c, p, seed)["Z"]), M
+        else:  # the Zipf graph at delta 86400: tier C
+            o = oracle.estimate3_indexed(g.src, g.dst, g.t, TWO + [star], delta, c, p, seed)
+            assert k3 == o["kept_counts"]
+            for M, z, zo in zip(TWO + [star], e3, o["Z"]):
+                assert close(z, zo), (M, z, zo)
 
 
 def test_self_loop_only_graph(tm):
@@ -538,33 +550,106 @@ def zipf10m():
     return ti.config_zipf10m()
 
 
-def test_zipf10m_sampled_windows(tm, zipf10m):
+def test_zipf10m_heavy_windows(tm, zipf10m):
     """Full-size 10M-edge Zipf(1.8) graph: exact counts of the 36 three-edge
-    motifs inside sampled windows (the per-window counting step) against the
-    oracle on the same window sub-graphs."""
+    motifs inside windows of two hours where the busiest node holds most
+    edges (the per-window counting step), 2,000-3,000 edges and 20,000-40,000
+    edges, against the oracle (tier C) on the same window sub-graphs."""
     g = zipf10m
     say("zipf10m windows: load")
     G = load(tm, g)
     delta = 3600
     tsort = np.sort(g.t)
+    deg = np.bincount(g.src, minlength=g.n) + np.bincount(g.dst, minlength=g.n)
+    hub = int(np.argmax(deg))
+    on_hub = np.sort(g.t[(g.src == hub) | (g.dst == hub)])
     rng = np.random.default_rng(7)
-    wins = []
-    for _ in range(4000):
+    wins = {0: [], 1: []}
+    for _ in range(20000):
         lo = int(rng.integers(0, 30_000_000 - 7200))
         hi = lo + 7199
         k = np.searchsorted(tsort, hi, side="right") - np.searchsorted(tsort, lo, side="left")
-        if 150 <= k <= 450:
-            wins.append((lo, hi))
-        if len(wins) == 3:
+        kh = np.searchsorted(on_hub, hi, side="right") - np.searchsorted(on_hub, lo, side="left")
+        if 2 * kh < k:
+            continue
+        if 2000 <= k <= 3000 and len(wins[0]) < 3:
+            wins[0].append((lo, hi))
+        if 20000 <= k <= 40000 and len(wins[1]) < 2:
+            wins[1].append((lo, hi))
+        if len(wins[0]) == 3 and len(wins[1]) == 2:
             break
-    assert len(wins) == 3
-    for (lo, hi) in wins:
-        say("zipf10m window", lo, hi)
-        got = tm.count_window(G, THREE, delta, lo, hi)
+    assert len(wins[0]) == 3 and len(wins[1]) == 2
+    for (lo, hi) in wins[0] + wins[1]:
         sel = (g.t >= lo) & (g.t <= hi)
-        for M, c in zip(THREE, got):
-            want, _ = oracle.count(g.src[sel], g.dst[sel], g.t[sel], M, delta, hist=False)
-            assert c == want, (M, lo, hi)
+        say("zipf10m window", lo, hi, int(sel.sum()))
+        got = tm.count_window(G, THREE, delta, lo, hi)
+        want = oracle.count3_indexed(g.src[sel], g.dst[sel], g.t[sel], THREE, delta)
+        assert got == want, (lo, hi)
+        # the same window on its own: its exact counts, and the weighted sweep
+        # with every edge in one kept window (p = 1), seed-matched
+        sub = ti.Graph(g.src[sel], g.dst[sel], g.t[sel], g.n)
+        Gw = load(tm, sub)
+        assert tm.count_exact_multi(Gw, THREE, delta) == want
+        c = 16  # the sub-graph spans at most 7,200 s: L = 57,600 holds it for most shifts
+        seed = next(sd for sd in range(64) if oracle.draw(sd, 0, 0, 0) % (c * delta) <= c * delta - 7200)
+        est, kept = tm.estimate_multi(Gw, THREE, delta, c, 1.0, seed)
+        o = oracle.estimate3_indexed(sub.src, sub.dst, sub.t, THREE, delta, c, 1.0, seed)
+        assert kept == o["kept_counts"] == want
+        for M, z, zo in zip(THREE, est, o["Z"]):
+            assert close(z, zo), (M, z, zo)
+        Gw.free()
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _check_golden(tm, G, ref):
+    motifs = [tuple(tuple(e) for e in M) for M in ref["motifs"]]
+    assert motifs == THREE
+    delta = ref["delta"]
+    got = tm.count_exact_multi(G, motifs, delta)
+    assert got == [int(x) for x in ref["exact"]]
+    for e in ref["estimates"]:
+        say("golden estimate", e["c"], e["p"], e["seed"])
+        est, kept = tm.estimate_multi(G, motifs, delta, e["c"], e["p"], e["seed"])
+        assert kept == [int(x) for x in e["kept_counts"]], (e["c"], e["p"], e["seed"])
+        for M, z, zo in zip(motifs, est, e["Z"]):
+            assert close(z, zo), (M, e["c"], e["p"], e["seed"], z, zo)
+
+
+def test_zipf_mid_config2_parameters(tm):
+    """A 300k-edge graph drawn with the 10M-edge workload's recipe (Zipf 1.8,
+    bursty, same edge density): exact counts of all 36 motifs and the
+    estimates at c in {10, 30}, p in {0.01, 0.1}, seeds 0..7, against the
+    oracle's stored values (tests/golden/make_zipf_mid_oracle.py)."""
+    ref = _golden("zipf_mid_oracle.json")
+    g = ti.zipf_graph(3000, 300_000, 1.8, 900_000, 12)
+    say("zipf mid", g.m)
+    G = load(tm, g)
+    _check_golden(tm, G, ref)
+    # kept windows and shift of one motif's diagnostics, seed by seed
+    for e in ref["estimates"][::5]:
+        r = tm.estimate(G, ti.TRIANGLE, ref["delta"], e["c"], e["p"], e["seed"], info=True)
+        assert r["s"] == e["s"] and r["J"] == e["J"] and list(r["kept"]) == e["kept"]
+
+
+def test_zipf10m_golden(tm, zipf10m):
+    """Full size, the benchmark's workload and launch configuration: the 36
+    exact whole-graph counts and the seed-0 estimates at the four benchmark
+    settings (every kept window, hub windows of up to 1.6e5 edges) against
+    the oracle's stored values (tests/golden/make_zipf10m_oracle.py)."""
+    path = os.path.join(GOLDEN, "zipf10m_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle values of the 10M-edge workload not generated")
+    ref = _golden("zipf10m_oracle.json")
+    say("zipf10m golden: load")
+    G = load(tm, zipf10m)
+    _check_golden(tm, G, ref)
 
 
 def test_zipf10m_sampled_anchors(tm, zipf10m):
