@@ -14,15 +14,27 @@ then the graph is freed.  Prints one JSON line on stdout.
 
 value = temporal edges x motif queries answered per step / seconds per step
 (a motif query is one motif's exact count or one motif's estimate at one
-(c, p)).  The roofline object reports the forward sweep kernel of the exact
-pass (the dominant kernel): algorithmic bytes per launch (12 bytes per
-incidence entry read: the anchor's own entry plus every entry its forward
-sweep scans, from the work census) over its average launch time, measured
-with HIP events on the launch stream inside the library.
+(c, p)).  The roofline object reports the dominant sweep kernel (the one
+with the most time per step when each kernel of a pass runs alone): its HBM
+traffic per launch, from the committed rocprofv3 FETCH_SIZE + WRITE_SIZE
+record of the current kernel source (calibrated by a plain copy), over its
+average launch time measured with HIP events on the launch stream inside the
+library, against 8 TB/s; and beside it the algorithmic bytes per launch of
+the work census with the per-unit figures of the method (16 B per anchor,
+12 B per scanned list entry, 8 B per binary-search probe, 8 B per weight
+read).
+
+Profiling helpers (rocprofv3 -f csv output directories):
+  --profile-run                 only the serial-timing step and one timed
+                                step (for rocprofv3 runs)
+  --pmc-summary FETCH WRITE     write profiles/<kernel>_zipf10m_traffic.json
+  --kt-summary DIR              write profiles/sweep3_zipf10m_kernel_trace.txt
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
 import hashlib
 import json
 import os
@@ -65,37 +77,42 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(g, motifs, delta, budget_s=15.0, seed=123, max_edges=3000):
-    """The oracle (single-threaded C brute force) on sampled windows of the
-    same graph: windows of length 2*delta around edges drawn uniformly (so
-    busy periods are sampled in proportion to their edges), skipping windows
-    above max_edges edges, every motif counted on each window, until the time
-    budget is spent.  Rate = window edges x motifs / seconds."""
+def _host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(g, motifs, delta, frac=0.05):
+    """The oracle's indexed tier (every first/last edge pair sharing a node
+    within delta, middles by range counts; OpenMP over anchors) timed on the
+    host cores, single-threaded and with every core, on a bounded sample of
+    the same workload: the exact counts of all the step's motifs on the
+    sub-graph of the edges in the first `frac` of the time span (a contiguous
+    slice at the workload's own density and burstiness).  Rate = slice edges
+    x motifs / seconds, the unit of the GPU's value."""
     import oracle
-    rng = np.random.default_rng(seed)
-    tsort = np.sort(g.t)
-    order = np.argsort(g.t, kind="stable")
-    edges_done, secs, nwin, skipped = 0, 0.0, 0, 0
-    while secs < budget_s and nwin < 10000:
-        e = int(rng.integers(0, g.m))
-        lo = int(g.t[e]) - delta
-        hi = lo + 2 * delta - 1
-        a, b = np.searchsorted(tsort, lo), np.searchsorted(tsort, hi, side="right")
-        if b - a > max_edges or b - a == 0:
-            skipped += 1
-            continue
-        sel = order[a:b]
-        s, d, t = g.src[sel], g.dst[sel], g.t[sel]
+    hi = int(g.t.min() + frac * (int(g.t.max()) - int(g.t.min())))
+    sel = g.t < hi
+    s, d, t = g.src[sel], g.dst[sel], g.t[sel]
+    oracle.count3_indexed(s[:1000], d[:1000], t[:1000], motifs, delta, threads=1)  # load, build
+    cores = os.cpu_count() or 1
+    out = {}
+    for threads in (1, cores):
         t0 = time.perf_counter()
-        for M in motifs:
-            oracle.count(s, d, t, M, delta, hist=False)
-        secs += time.perf_counter() - t0
-        edges_done += b - a
-        nwin += 1
-    return {"value": edges_done * len(motifs) / secs, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nwin} windows of 2*delta around uniformly drawn edges ({edges_done} edges, windows over "
-                      f"{max_edges} edges skipped: {skipped}), {len(motifs)} motifs each, single-threaded C brute "
-                      f"force, {secs:.1f} s"}
+        oracle.count3_indexed(s, d, t, motifs, delta, threads=threads)
+        out[threads] = time.perf_counter() - t0
+    m = int(sel.sum())
+    return {"value": m * len(motifs) / out[cores], "unit": "edges/s", "cores": cores, "kind": "oracle",
+            "single_thread_value": m * len(motifs) / out[1], "single_thread_s": out[1], "all_cores_s": out[cores],
+            "host_cpu": _host_cpu_model(),
+            "sample": f"exact counts of all {len(motifs)} motifs on the {m} edges of the first {frac:.0%} of the "
+                      f"time span (a contiguous slice of the same graph), oracle tier C (indexed: first/last "
+                      f"edge pairs sharing a node, middles by range counts), {cores} host threads and 1 thread"}
 
 
 def run_batch(args):
@@ -475,48 +492,42 @@ def traffic_record(kernel):
     return rec.get("traffic_bytes_per_launch")
 
 
-# Algorithmic bytes per unit of the sweeps: 16 B per anchor edge (two
-# endpoints and a time), 12 B per scanned list entry (time and endpoint
-# word), plus 8 B per scanned entry for the weighted sweeps' weight.  The
-# exact triangle sweep's closing-pair lookup reads two bucket records and
-# the entry found, at tj and at tj - delta (48 B); a change of closing pair
-# also reads the hash slot (16 B), the pair's metadata (32 B) and two more
-# searches (48 B): 96 B.  The weighted triangle sweep looks up once per
-# entry (24 B) and reads hash slot, metadata and one search on a pair change
-# (72 B).
-# With the exact-count tables, a 2-node/star count anchor instead reads its
-# pair's hash slot (64 B), two pair searches (48 B), list prefix counts
-# (24 B forward, 16 B backward) and two 96 B table rows: 344 B forward and
-# 336 B backward per anchor with its own 16 B (list-search probes not
-# counted).
-def sweep_bytes(exact, ests, tables):
+# Algorithmic bytes per unit of the sweeps, the method's own work in the
+# plain model (every anchor reads its edge: 16 B; every list entry in (t1, hi]
+# it scans: 12 B, time and endpoint word; a weighted sweep also reads the
+# entry's duration weight: 8 B; every binary-search probe of a closing-pair
+# lookup: 8 B, counted by the census as ceil(log2(n + 1)) per search of a
+# pair timeline of n entries, plus one probe to find the pair on a change).
+# The exact-count tables let the 2-node and star counts skip their scans;
+# their algorithmic bytes are still the scans they replace.
+def sweep_bytes(exact, ests):
     out = {
-        "sweep3_fwd_count": (344 * exact["anchors"] if tables
-                             else 16 * exact["anchors"] + 12 * exact["fwd_entries"]),
-        "sweep3_bwd_count": (336 * exact["anchors"] if tables
-                             else 16 * exact["anchors"] + 12 * exact["bwd_entries"]),
-        "sweep3_tri_count": 16 * exact["tri_anchors"] + 12 * exact["tri_entries"] + 48 * exact["tri_lookups"]
-        + 96 * exact["tri_pairs"],
+        "sweep3_fwd_count": 16 * exact["anchors"] + 12 * exact["fwd_entries"],
+        "sweep3_bwd_count": 16 * exact["anchors"] + 12 * exact["bwd_entries"],
+        "sweep3_tri_count": 16 * exact["tri_anchors"] + 12 * exact["tri_entries"] + 8 * exact["tri_probes"],
         "sweep3_fwd_weight": 0, "sweep3_bwd_weight": 0, "sweep3_tri_weight": 0,
     }
     for e in ests:
         out["sweep3_fwd_weight"] += 16 * e["anchors"] + 20 * e["fwd_entries"]
         out["sweep3_bwd_weight"] += 16 * e["anchors"] + 20 * e["bwd_entries"]
-        out["sweep3_tri_weight"] += (16 * e["tri_anchors"] + 20 * e["tri_entries"] + 24 * e["tri_lookups"]
-                                     + 72 * e["tri_pairs"])
+        out["sweep3_tri_weight"] += 16 * e["tri_anchors"] + 20 * e["tri_entries"] + 8 * e["tri_probes"]
     return out
 
 
-def sweep_roofline(exact, ests, kern, crit, alone, steps, tables):
-    """Roofline entry of the dominant sweep kernel, with the achieved
-    algorithmic GB/s of every sweep kernel beside it.  The kernels of one
-    pass run concurrently on forked streams and share the CUs, so each one's
-    duration in the timed steps spans most of the pass.  The dominant kernel
+def sweep_roofline(exact, ests, kern, crit, alone, steps):
+    """Roofline entry of the dominant sweep kernel.  The kernels of one pass
+    run concurrently on forked streams and share the CUs, so each one's
+    duration in the timed steps spans most of the pass; the dominant kernel
     is the one with the most time per step when each kernel of a pass runs
-    alone (alone: one untimed step with the library's serial timing mode);
-    its achieved rate uses its average launch duration in the timed steps.
-    crit: per kernel, the time of the passes it was the last to finish."""
-    bps = sweep_bytes(exact, ests, tables)  # algorithmic bytes per step
+    alone (alone: one untimed step with the library's serial timing mode).
+    achieved = its HBM bytes per launch (FETCH_SIZE + WRITE_SIZE from the
+    committed rocprofv3 record of the current kernel source, calibrated by a
+    plain copy) / its average launch duration in the timed steps; the
+    algorithmic figure (census x per-unit bytes) is reported beside it.  When
+    the record is stale (kernel source changed since the counters were
+    taken) traffic is null and frac falls back to the algorithmic figure,
+    with frac_basis saying so."""
+    bps = sweep_bytes(exact, ests)  # algorithmic bytes per step
     timed = {k: v for k, v in kern.items() if k in bps and v[1] > 0}
     if not timed:
         return None
@@ -524,16 +535,156 @@ def sweep_roofline(exact, ests, kern, crit, alone, steps, tables):
     for k, (ms, n) in timed.items():
         per[k] = {"launches_per_step": n / steps, "avg_launch_ms": ms / n,
                   "algorithmic_bytes_per_launch": bps[k] * steps / n,
-                  "achieved_GBs": bps[k] * steps / (ms / 1e3) / 1e9}
+                  "algorithmic_GBs": bps[k] * steps / (ms / 1e3) / 1e9}
+        tr = traffic_record(k)
+        if tr is not None:
+            per[k]["traffic_bytes_per_launch"] = tr
+            per[k]["hbm_GBs"] = tr / (ms / n / 1e3) / 1e9
     dom = max(timed, key=lambda k: (alone.get(k, (0.0, 0))[0], timed[k][0]))
-    ach = per[dom]["achieved_GBs"]
+    d = per[dom]
+    traffic = d.get("traffic_bytes_per_launch")
+    if traffic is not None:
+        ach, basis = d["hbm_GBs"], "rocprofv3 FETCH_SIZE + WRITE_SIZE per launch / launch time"
+    else:
+        ach, basis = d["algorithmic_GBs"], "algorithmic bytes per launch / launch time (counter record stale)"
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-            "traffic": traffic_record(dom), "kernel": dom, "avg_launch_ms": per[dom]["avg_launch_ms"],
-            "launches": timed[dom][1], "algorithmic_bytes_per_launch": per[dom]["algorithmic_bytes_per_launch"],
+            "traffic": traffic, "frac_basis": basis, "kernel": dom, "avg_launch_ms": d["avg_launch_ms"],
+            "launches": timed[dom][1],
+            "algorithmic": {"bytes_per_launch": d["algorithmic_bytes_per_launch"], "GBs": d["algorithmic_GBs"],
+                            "frac": d["algorithmic_GBs"] / HBM_PEAK_GBS,
+                            "per_unit": "16 B per anchor, 12 B per scanned entry, 8 B per weight read, "
+                                        "8 B per binary-search probe"},
             "census": {"exact": exact, "estimates": ests}, "sweep_kernels": per,
             "sweep_kernels_ms_per_step": {k: v[0] / steps for k, v in kern.items()},
             "critical_path_ms_per_step": {k: v[0] / steps for k, v in crit.items() if v[1] > 0},
             "alone_ms_per_step": {k: v[0] for k, v in alone.items() if v[1] > 0}}
+
+
+# rocprofv3 names of the sweep kernels (template arguments: mode, forward,
+# class mask) and the library's timing names
+TEMPLATE_NAMES = {"k_sweep3<0, true, 7u>": "sweep3_fwd_count", "k_sweep3<0, true, 8u>": "sweep3_tri_count",
+                  "k_sweep3<0, false, 0u>": "sweep3_bwd_count", "k_sweep3<1, true, 7u>": "sweep3_fwd_weight",
+                  "k_sweep3<1, true, 8u>": "sweep3_tri_weight", "k_sweep3<1, false, 0u>": "sweep3_bwd_weight"}
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def _csv_rows(folder, suffix):
+    rows = []
+    for f in sorted(glob.glob(os.path.join(folder, "**", f"*{suffix}"), recursive=True)):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no *{suffix} under {folder} (run rocprofv3 with -f csv)")
+    return rows
+
+
+def _short_name(kernel_name):
+    """A rocprofv3 kernel name without return type, namespaces and arguments."""
+    k = kernel_name.strip()
+    if k.startswith("void "):
+        k = k[5:]
+    k = k.replace("(anonymous namespace)::", "").replace("sweepdev::", "")
+    return k.split("(")[0].strip()
+
+
+def _timing_name(kernel_name):
+    return TEMPLATE_NAMES.get(_short_name(kernel_name))
+
+
+def pmc_summary(fetch_dir, write_dir):
+    """Per sweep kernel: mean FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
+    over its dispatches, each scaled by what the counter reads for the 1 GiB
+    copy of --copy-calib (1 GiB read, 1 GiB written), written with the
+    kernel source hash to profiles/<kernel>_zipf10m_traffic.json."""
+    vals = {}
+    for folder, counter in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        per = {}
+        copy = 0.0
+        for r in _csv_rows(folder, "counter_collection.csv"):
+            if r.get("Counter_Name") != counter:
+                continue
+            v = float(r["Counter_Value"])
+            k = r["Kernel_Name"]
+            if _short_name(k) == COPY_KERNEL:
+                copy = max(copy, v)
+            name = _timing_name(k)
+            if name:
+                per.setdefault(name, []).append(v)
+        if copy <= 0:
+            raise SystemExit(f"no {COPY_KERNEL} dispatch in {folder}: run bench.py with --copy-calib")
+        vals[counter] = (per, copy)
+    sha = kernel_src_sha()
+    fper, fcopy = vals["FETCH_SIZE"]
+    wper, wcopy = vals["WRITE_SIZE"]
+    ff, wf = (1 << 20) / fcopy, (1 << 20) / wcopy  # KiB of 1 GiB over what each counter read
+    for name in sorted(set(fper) & set(wper)):
+        fk, wk = sum(fper[name]) / len(fper[name]), sum(wper[name]) / len(wper[name])
+        rec = {"kernel": f"{[t for t, n in TEMPLATE_NAMES.items() if n == name][0]} ({name})",
+               "workload": "zipf10m bench step (100k nodes, 10M edges, 36 three-edge motifs, delta 3600)",
+               "kernel_src_sha256": sha,
+               "commands": [f"rocprofv3 --pmc FETCH_SIZE -f csv -d REPO/{fetch_dir} -o run -- python3 REPO/bench.py "
+                            "--profile-run --copy-calib",
+                            f"rocprofv3 --pmc WRITE_SIZE -f csv -d REPO/{write_dir} -o run -- python3 REPO/bench.py "
+                            "--profile-run --copy-calib",
+                            f"python3 bench.py --pmc-summary {fetch_dir} {write_dir}"],
+               "dispatches_averaged": len(fper[name]),
+               "fetch_size_kib_per_dispatch": fk, "write_size_kib_per_dispatch": wk,
+               "calibration": {"copy": "1 GiB device-to-device copy (1 GiB read + 1 GiB written)",
+                               "copy_fetch_kib": fcopy, "copy_write_kib": wcopy,
+                               "fetch_factor": ff, "write_factor": wf},
+               "traffic_bytes_per_launch": (fk * ff + wk * wf) * 1024}
+        with open(traffic_file(name), "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(name, f"{rec['traffic_bytes_per_launch'] / 1e9:.2f} GB per launch", file=sys.stderr)
+
+
+def kt_summary(folder):
+    """Kernel-trace summary of a --profile-run: per kernel, calls, total and
+    average duration; for the sweep kernels only the timed step's dispatches
+    (the second half of each one's dispatches: the serial-timing step runs
+    the same launches first)."""
+    rows = _csv_rows(folder, "kernel_trace.csv")
+    per = {}
+    for r in rows:
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        name = _short_name(r["Kernel_Name"])
+        per.setdefault(name, []).append(dur)
+    for name in list(per):
+        if name in TEMPLATE_NAMES:
+            d = per[name]
+            per[name] = d[len(d) // 2:]
+    tot = sum(sum(v) for v in per.values())
+    lines = ["rocprofv3 kernel trace: one timed bench step on the 10M-edge Zipf(1.8) workload", "",
+             "commands (REPO = repository root; run from /tmp with TMPDIR=/tmp):",
+             f"  rocprofv3 --kernel-trace --stats -f csv -d REPO/{folder} -o run -- python3 REPO/bench.py --profile-run",
+             f"  python3 bench.py --kt-summary {folder}", "",
+             "workload: 100k nodes, 10M edges, Zipf(1.8) endpoints, bursty times over [0,3e7) s, 36 three-edge "
+             "motifs, delta 3600;", "one step = load + exact counts + estimates at c in {10,30} x p in {0.01,0.1}; "
+             "durations in microseconds;", "sweep kernels: the timed step's dispatches only (they run "
+             "concurrently on forked streams, so each spans most of its pass)", "",
+             f"{'kernel':<60} {'calls':>7} {'total_us':>14} {'avg_us':>14} {'pct':>7}"]
+    for name, d in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:40]:
+        label = name + (f" ({TEMPLATE_NAMES[name]})" if name in TEMPLATE_NAMES else "")
+        lines.append(f"{label[:60]:<60} {len(d):>7} {sum(d):>14.1f} {sum(d) / len(d):>14.1f} "
+                     f"{100 * sum(d) / tot:>7.2f}")
+    out = os.path.join(ROOT, "profiles", "sweep3_zipf10m_kernel_trace.txt")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines[-12:]), file=sys.stderr)
+
+
+def latency(fn, repeats):
+    """p50 / p99 (nearest rank) and mean of `repeats` timed calls, in ms."""
+    import torch
+    ts = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    ts.sort()
+    pct = lambda f: ts[max(0, int(np.ceil(f * len(ts))) - 1)]
+    return {"repeats": repeats, "p50_ms": pct(0.5), "p99_ms": pct(0.99), "mean_ms": float(np.mean(ts))}
 
 
 def stream_estimates(tm, torch, g, motifs, delta, c=30, p=0.1):
@@ -603,7 +754,21 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only the serial-timing step and one timed step (for rocprofv3 runs)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the traffic records from two rocprofv3 --pmc -f csv runs and exit")
+    ap.add_argument("--kt-summary", metavar="DIR", help="write the kernel-trace summary of a --profile-run and exit")
+    ap.add_argument("--latency-repeats", type=int, default=50)
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
+    if args.kt_summary:
+        kt_summary(args.kt_summary)
+        return
+    if args.profile_run:
+        args.steps, args.warmup, args.no_cpu = 1, 0, True
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU sharding of "
               "windows is described, not implemented)", file=sys.stderr)
@@ -675,6 +840,11 @@ def main():
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     tm.profile_enable(False)
+    kern = {k: tm.profile_read(k) for k in SWEEP_KERNELS}
+    crit = {k: tm.profile_read("crit:" + k) for k in SWEEP_KERNELS}
+    if args.profile_run:
+        log("profile run done", {k: v for k, v in kern.items()})
+        return
 
     # The same step with its queries issued together from one host thread
     # each, on streams of their own (the library keeps per-thread workspaces
@@ -713,16 +883,32 @@ def main():
     log("edge-proportional estimates done")
     streaming = stream_estimates(tm, torch, g, motifs, delta)
     log("streaming estimates done")
-    kern = {k: tm.profile_read(k) for k in SWEEP_KERNELS}
-    crit = {k: tm.profile_read("crit:" + k) for k in SWEEP_KERNELS}
 
     q = len(motifs) * (1 + len(W["est"]))
     G = tm.load_graph(src, dst, t, g.n)
     census = tm.sweep_census(G, delta)
     ests = [tm.sweep_census_est(G, delta, c, p, 0) for c, p in W["est"]]
     tables = G.exact_table_bytes > 0
+    # latency over repeated single queries on the resident graph: the exact
+    # pass of every motif, the p = 0.1 estimate pass (largest c), and one
+    # motif (the triangle) alone
+    cl, pl = max(W["est"], key=lambda e: (e[1], e[0]))
+    R = args.latency_repeats
+    lat = {"exact_all_motifs": latency(lambda: tm.count_exact_multi(G, motifs, delta), R),
+           f"estimate_all_motifs_c{cl}_p{pl}": latency(lambda: tm.estimate_multi(G, motifs, delta, cl, pl, 0), R),
+           "exact_triangle": latency(lambda: tm.count_exact(G, ti.TRIANGLE, delta), R),
+           f"estimate_triangle_c{cl}_p{pl}": latency(lambda: tm.estimate(G, ti.TRIANGLE, delta, cl, pl, 0), R)}
+    for v in lat.values():
+        v["edges_per_s_per_query_at_p50"] = None
+    lat["exact_all_motifs"]["edges_per_s_per_query_at_p50"] = g.m * len(motifs) / (lat["exact_all_motifs"]["p50_ms"] / 1e3)
+    k_est = f"estimate_all_motifs_c{cl}_p{pl}"
+    lat[k_est]["edges_per_s_per_query_at_p50"] = g.m * len(motifs) / (lat[k_est]["p50_ms"] / 1e3)
+    lat["exact_triangle"]["edges_per_s_per_query_at_p50"] = g.m / (lat["exact_triangle"]["p50_ms"] / 1e3)
+    k_tri = f"estimate_triangle_c{cl}_p{pl}"
+    lat[k_tri]["edges_per_s_per_query_at_p50"] = g.m / (lat[k_tri]["p50_ms"] / 1e3)
+    log("latency repeats done")
     G.free()
-    roofline = sweep_roofline(census, ests, kern, crit, alone, args.steps, tables)
+    roofline = sweep_roofline(census, ests, kern, crit, alone, args.steps)
     if roofline:
         roofline["exact_tables"] = tables
     out = {
@@ -733,6 +919,8 @@ def main():
         "config": {"workload": W["desc"], "m": g.m, "n": g.n, "motif_queries_per_step": q},
         "phases_ms": {k: 1e3 * float(np.mean(v)) for k, v in times.items()},
         "exact_edges_per_s_per_query": g.m * len(motifs) / float(np.mean(times["exact"])),
+        "estimate_p0.1_edges_per_s_per_query": g.m * len(motifs) / (lat[k_est]["mean_ms"] / 1e3),
+        "latency": lat,
         "roofline": roofline,
         "concurrent_queries": {"ms_per_step": dtc * 1e3, "value": g.m * len(motifs) * (1 + len(W["est"])) / dtc,
                                "threads": len(streams), "same_results": same},
@@ -742,7 +930,6 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(g, motifs, delta)
-        out["cpu_baseline"]["host_cpus"] = os.cpu_count()
     print(json.dumps(out), flush=True)
 
 

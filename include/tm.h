@@ -283,10 +283,34 @@ tm_status tm_estimate_q(const tm_graph *g, int32_t n_motifs, const tm_motif *mot
  * work-groups per CU.  Other motifs run seed by seed.
  * kept_counts (nullable) receives each seed's exact count over its kept
  * windows.  Plans are cached with the graph and released by tm_free_graph.
+ * Calls with the same (motif, delta, c, p, n_seeds, tile) share one plan:
+ * concurrent ones (other threads, other streams) run it one after another.
  */
 tm_status tm_estimate_batch(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t c,
                             double p, int32_t n_seeds, const uint64_t *seeds, int32_t tile,
                             double *estimates, tm_u128 *kept_counts, void *hip_stream);
+
+/*
+ * Estimates of n queries on one graph, each with its own motif, delta, c, p
+ * and seed (Algorithm 1 once per query).  The queries with three-edge motifs
+ * run together in one persistent, work-stealing launch replayed from a
+ * captured hipGraph: node-aligned tiles of 256 anchors are queued per
+ * (tile, query) that meets a window the query keeps, one kernel per sweep
+ * class (the classes as parallel branches of the graph).  Other motifs (up to
+ * four edges) run one after another through the generic counter.
+ * estimates[i] and kept_counts[i] (nullable: exact counts over the kept
+ * windows) are each query's tm_estimate result, to the last bit.  Host
+ * arrays of n entries.  Errors: as tm_estimate for any query.
+ */
+typedef struct {
+    tm_motif motif;
+    int64_t delta;
+    int64_t c;
+    double p;
+    uint64_t seed;
+} tm_est_query;
+tm_status tm_estimate_mixed(const tm_graph *g, int32_t n, const tm_est_query *q, double *estimates,
+                            tm_u128 *kept_counts, void *hip_stream);
 
 /*
  * Autotuner of the batched estimator: times candidate tile sizes
@@ -301,8 +325,8 @@ tm_status tm_batch_config(const tm_graph *g, const tm_motif *M, int64_t delta, i
  * Releases the batched estimator's cached state of graph g: captured plans
  * and the stored anchor values (32 B per incidence entry per (motif, delta,
  * c)), after waiting for hip_stream.  Tuning results are kept.  The next
- * tm_estimate_batch rebuilds what it needs.  The caller must not run a batch
- * on g concurrently.
+ * tm_estimate_batch rebuilds what it needs.  A plan that a concurrent
+ * tm_estimate_batch is running stays alive until that run ends.
  */
 tm_status tm_batch_release(const tm_graph *g, void *hip_stream);
 
@@ -356,6 +380,8 @@ typedef struct {
     double queue_ms;     /* submit to start on a slot                         */
     int32_t batch_size;  /* queries answered by the same device pass          */
     int32_t slot;
+    int64_t ws_charged;  /* device bytes the batch was charged against the budget */
+    int64_t ws_measured; /* device bytes the batch held at its peak (measured)  */
 } tm_result;
 
 typedef struct {
@@ -364,20 +390,31 @@ typedef struct {
     double wall_s;                    /* first submit to last completion     */
     double edges_per_s;               /* graph edges of completed queries / wall_s */
     int64_t budget_bytes, peak_bytes; /* admitted workspace, high-water mark */
+    int64_t measured_max_bytes;       /* largest measured batch workspace    */
+    int64_t over_charge;              /* batches that held more than charged */
+    int64_t uncollected;              /* results ready but not yet waited for */
 } tm_server_stats;
 
 /*
  * Query server with continuous batching.  `slots` worker threads, each with
  * its own HIP stream, run batches concurrently; a dispatcher admits the
  * oldest queued query whose device workspace fits what is left of
- * budget_bytes, merges every queued query that can share its device pass
- * (exact counts of three-edge motifs on the same graph and delta; estimates
- * of three-edge motifs with the same graph, delta, c, p and seed), and
- * starts it on a free slot.  Queries that arrive while others run are
+ * budget_bytes, merges every queued query that can share its device work
+ * (exact counts of three-edge motifs on the same graph and delta share one
+ * sweep; estimates of three-edge motifs on the same graph share one
+ * tm_estimate_mixed launch, whatever their motifs, deltas, c, p and seeds),
+ * up to 256 per batch, and starts it on a free slot.  A batch is charged the
+ * device bytes its path allocates, and the bytes it really allocated are
+ * measured and reported beside the charge (tm_result, tm_server_stats); the
+ * grow-only workspaces a slot thread keeps between batches are measured
+ * after each batch and counted against the budget too (an idle slot frees
+ * them when the oldest query would not fit otherwise), so budget_bytes
+ * bounds the device memory the server's threads hold beyond the graphs.  Queries that arrive while others run are
  * admitted as slots and memory free up.  A result is the same whether its
  * query ran alone or in a batch.  Graphs must stay loaded while the server
  * uses them.  tm_server_wait blocks until the ticket's result is ready
- * (TM_EINVAL for an unknown or already collected ticket); tm_server_destroy
+ * (TM_EINVAL for an unknown or already collected ticket; a collected result
+ * is dropped from the server, one byte per ticket stays); tm_server_destroy
  * completes queued queries with TM_EDEVICE and joins the threads.
  */
 tm_status tm_server_create(int32_t slots, int64_t budget_bytes, tm_server **out);
@@ -426,6 +463,13 @@ tm_status tm_profile_read(const char *kernel, double *total_ms, int64_t *launche
  * p, seed): the same fields restricted to anchors in kept windows and to
  * entries inside the anchor's window; there the triangle sweep runs over
  * the full lists, so tri_anchors = anchors and tri_entries = fwd_entries.
+ *   tri_probes    binary-search probes of a plain lookup of the closing
+ *                 pair's middle count, ceil(log2(n + 1)) per search of a pair
+ *                 timeline of n entries: the exact sweep searches at t_j and
+ *                 t_j - delta per lookup and, per change of pair, probes once
+ *                 to find it and searches at t_i and at the window end; the
+ *                 weighted sweep searches at t_j per lookup and, per change,
+ *                 probes once and searches at t_i
  * Ties with the anchor's time are left out of tri_lookups and tri_pairs, as
  * the sweeps leave them out.  Within a list, entries tied in time follow the
  * input order of their edges (an edge's source entry before its destination
@@ -434,6 +478,7 @@ tm_status tm_profile_read(const char *kernel, double *total_ms, int64_t *launche
 typedef struct {
     int64_t anchors, fwd_entries, bwd_entries;
     int64_t tri_anchors, tri_entries, tri_lookups, tri_pairs;
+    int64_t tri_probes;
 } tm_census;
 
 tm_status tm_sweep_census(const tm_graph *g, int64_t delta, tm_census *out, void *hip_stream);

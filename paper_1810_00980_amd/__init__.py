@@ -83,14 +83,16 @@ class Query(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("count", U128), ("estimate", ctypes.c_double),
                 ("latency_ms", ctypes.c_double), ("queue_ms", ctypes.c_double), ("batch_size", ctypes.c_int32),
-                ("slot", ctypes.c_int32)]
+                ("slot", ctypes.c_int32), ("ws_charged", ctypes.c_int64), ("ws_measured", ctypes.c_int64)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
                 ("batches", ctypes.c_int64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
                 ("mean_ms", ctypes.c_double), ("wall_s", ctypes.c_double), ("edges_per_s", ctypes.c_double),
-                ("budget_bytes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64)]
+                ("budget_bytes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
+                ("measured_max_bytes", ctypes.c_int64), ("over_charge", ctypes.c_int64),
+                ("uncollected", ctypes.c_int64)]
 
 
 P = ctypes.c_void_p
@@ -113,6 +115,7 @@ _SIGS = {
     "tm_estimate_stream": [P, P, P, i64, i32, i32, P, i64, i64, f64, u64, P, P, P, P],
     "tm_estimate_batch": [P, P, i64, i64, f64, i32, P, i32, P, P, P],
     "tm_batch_config": [P, P, i64, i64, f64, P, P, P],
+    "tm_estimate_mixed": [P, i32, P, P, P, P],
     "tm_batch_release": [P, P],
     "tm_server_create": [i32, i64, P],
     "tm_server_add_graph": [P, P, P],
@@ -385,6 +388,23 @@ def estimate_batch(g: Graph, edges, delta: int, c: int, p: float, seeds, tile: i
     return est, [kc[i].value() for i in range(k)]
 
 
+class EstQuery(ctypes.Structure):
+    _fields_ = [("motif", Motif), ("delta", ctypes.c_int64), ("c", ctypes.c_int64), ("p", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+def estimate_mixed(g: Graph, queries, stream=None):
+    """Estimates of queries [(motif edges, delta, c, p, seed)] on one graph,
+    the three-edge ones in one launch.  Returns (estimates, kept counts)."""
+    k = len(queries)
+    arr = (EstQuery * max(k, 1))(*[EstQuery(motif(M), int(d), int(c), float(p), int(s))
+                                   for (M, d, c, p, s) in queries])
+    est = (ctypes.c_double * max(k, 1))()
+    kc = (U128 * max(k, 1))()
+    _check(_lib.tm_estimate_mixed(g.handle, k, arr, est, kc, _stream(stream)), "tm_estimate_mixed")
+    return [est[i] for i in range(k)], [kc[i].value() for i in range(k)]
+
+
 def profile_enable(on: bool = True, serial: bool = False):
     """Kernel timing on/off; serial=True also runs the kernels of each sweep
     pass one after another, so that each duration is the kernel's own."""
@@ -404,7 +424,8 @@ def profile_read(kernel: str):
 
 class Census(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in
-                ("anchors", "fwd_entries", "bwd_entries", "tri_anchors", "tri_entries", "tri_lookups", "tri_pairs")]
+                ("anchors", "fwd_entries", "bwd_entries", "tri_anchors", "tri_entries", "tri_lookups", "tri_pairs",
+                 "tri_probes")]
 
 
 def sweep_census(g: Graph, delta: int, stream=None) -> dict:
@@ -459,7 +480,8 @@ class Server:
         r = Result()
         _check(_lib.tm_server_wait(self._h, int(ticket), ctypes.byref(r)), "tm_server_wait")
         return {"status": r.status, "count": r.count.value(), "estimate": r.estimate, "latency_ms": r.latency_ms,
-                "queue_ms": r.queue_ms, "batch_size": r.batch_size, "slot": r.slot}
+                "queue_ms": r.queue_ms, "batch_size": r.batch_size, "slot": r.slot, "ws_charged": r.ws_charged,
+                "ws_measured": r.ws_measured}
 
     def stats(self) -> dict:
         s = ServerStats()

@@ -473,6 +473,17 @@ struct SweepWs {
 };
 thread_local SweepWs t_ws;
 
+}  // namespace
+
+void tm_api_release_thread_ws() {
+    t_ws.o.release();
+    t_ws.h.release();
+    t_ws.w.release();
+    t_ws.ctr.release();
+}
+
+namespace {
+
 tm_status run_sweep(const tm_graph *g, uint64_t mask, int mode, int64_t delta, int windowed, int64_t s, int64_t L,
                     uint64_t seed, double p, SweepOut *out, const std::vector<int> &hist_codes,
                     std::vector<uint64_t> *hist_host, hipStream_t st, const int32_t *kidx = nullptr,
@@ -1178,6 +1189,52 @@ extern "C" tm_status tm_estimate_batch(const tm_graph *g, const tm_motif *M, int
         if (kept_counts) kept_counts[i] = info.kept_count;
     }
     return TM_OK;
+}
+
+extern "C" tm_status tm_estimate_mixed(const tm_graph *g, int32_t n, const tm_est_query *q, double *estimates,
+                                       tm_u128 *kept_counts, void *hip_stream) {
+    if (!g || n < 0 || (n > 0 && (!q || !estimates))) return TM_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<int32_t> code;
+    std::vector<int64_t> delta, L, idx;
+    std::vector<double> p;
+    std::vector<uint64_t> seed;
+    for (int32_t i = 0; i < n; ++i) {
+        MotifPlan P;
+        TM_TRY(tm_make_plan(&q[i].motif, &P));
+        int64_t Li;
+        TM_TRY(check_est_args(g, q[i].delta, q[i].c, q[i].p, &Li));
+        const int c = tm_sweep_code_of(&q[i].motif);
+        if (c < 0) continue;
+        code.push_back(c);
+        delta.push_back(q[i].delta);
+        L.push_back(Li);
+        p.push_back(q[i].p);
+        seed.push_back(q[i].seed);
+        idx.push_back(i);
+    }
+    // three-edge motifs: one launch for all of them
+    const int64_t k = (int64_t)idx.size();
+    std::vector<double> est((size_t)(k > 0 ? k : 1));
+    std::vector<tm_u128> kept((size_t)(k > 0 ? k : 1));
+    tm_status s = tm_batch_mixed(g, k, code.data(), delta.data(), L.data(), p.data(), seed.data(), est.data(),
+                                 kept.data(), st);
+    if (s != TM_OK) return finish(s, st);
+    for (int64_t j = 0; j < k; ++j) {
+        estimates[idx[(size_t)j]] = est[(size_t)j];
+        if (kept_counts) kept_counts[idx[(size_t)j]] = kept[(size_t)j];
+    }
+    // the others, one after another through the generic counter
+    for (int32_t i = 0; i < n; ++i) {
+        if (tm_sweep_code_of(&q[i].motif) >= 0) continue;
+        tm_est_info info;
+        memset(&info, 0, sizeof info);
+        s = finish(estimate_impl(g, &q[i].motif, q[i].delta, q[i].c, q[i].p, q[i].seed, &estimates[i],
+                                 kept_counts ? &info : nullptr, st), st);
+        if (s != TM_OK) return s;
+        if (kept_counts) kept_counts[i] = info.kept_count;
+    }
+    return finish(TM_OK, st);
 }
 
 extern "C" tm_status tm_batch_release(const tm_graph *g, void *hip_stream) {

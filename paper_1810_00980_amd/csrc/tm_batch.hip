@@ -305,11 +305,17 @@ struct BatchPlan {
     int64_t tile = 0, bpc = 0, n_seeds = 0, delta = 0, L = 0, J = 0, n_tiles = 0;
     int32_t code = -1;
     double p = 0;
-    const uint64_t *vals = nullptr;  // stored anchor values (owned by the cache), or null
+    const uint64_t *vals = nullptr;  // stored anchor values, or null
+    std::shared_ptr<DevBuf> vals_buf; // keeps them alive while the plan lives
     DevBuf tiles, tnode, seeds, shifts, kp, qctl, out, wfx, z;
+    // One run at a time: a run writes the plan's seeds, queue counters and
+    // outputs and replays its one hipGraphExec.  Concurrent callers with the
+    // same key (other threads, other streams) wait here.
+    std::mutex run_mu;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap_stream = nullptr;
     ~BatchPlan() {
+        std::shared_lock<std::shared_mutex> lk(tm_capture_lock());  // may synchronise
         if (exec) (void)hipGraphExecDestroy(exec);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
@@ -319,11 +325,14 @@ using PlanKey = std::tuple<const tm_graph *, int32_t, int64_t, int64_t, double, 
 using TuneKey = std::tuple<const tm_graph *, int32_t, int64_t, int64_t, double>;
 using ValKey = std::tuple<const tm_graph *, int32_t, int64_t, int64_t>;
 
+// Plans and stored values are shared: dropping them from the cache (release,
+// tuning clean-up) leaves a plan that another thread is running alive until
+// that run ends.
 struct BatchCache {
     std::mutex mu;
-    std::map<PlanKey, std::unique_ptr<BatchPlan>> plans;
+    std::map<PlanKey, std::shared_ptr<BatchPlan>> plans;
     std::map<TuneKey, std::pair<int64_t, int64_t>> tuned;
-    std::map<ValKey, std::unique_ptr<DevBuf>> vals;  // stored anchor values per (graph, code, delta, L)
+    std::map<ValKey, std::shared_ptr<DevBuf>> vals;  // stored anchor values per (graph, code, delta, L)
 };
 BatchCache &bcache() {
     static BatchCache c;
@@ -425,9 +434,16 @@ tm_status build_plan(const tm_graph *g, BatchPlan &B, hipStream_t st) {
 tm_status capture(const tm_graph *g, BatchPlan &B) {
     TM_HIP(hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
-    TM_HIP(hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal));
-    tm_status s = enqueue(g, B, B.cap_stream);
-    hipError_t e = hipStreamEndCapture(B.cap_stream, &graph);
+    tm_status s;
+    hipError_t e;
+    {
+        // no library free (an implicit device synchronisation) during the capture
+        std::unique_lock<std::shared_mutex> lk(tm_capture_lock());
+        e = hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return tm_hip_status(e);
+        s = enqueue(g, B, B.cap_stream);
+        e = hipStreamEndCapture(B.cap_stream, &graph);
+    }
     if (s != TM_OK) {
         if (graph) (void)hipGraphDestroy(graph);
         return s;
@@ -468,24 +484,24 @@ tm_status run_plan(const tm_graph *g, BatchPlan &B, const uint64_t *seeds, doubl
 // Stored anchor values of (graph, code, delta, L) for plan B, computed on
 // first use with B's weights; *vals stays null when they do not fit in a
 // quarter of the free device memory.
-tm_status anchor_vals(const tm_graph *g, BatchPlan &B, const uint64_t **vals, hipStream_t st) {
+tm_status anchor_vals(const tm_graph *g, BatchPlan &B, std::shared_ptr<DevBuf> *vals, hipStream_t st) {
     BatchCache &C = bcache();
     ValKey key{g, B.code, B.delta, B.L};
     {
         std::lock_guard<std::mutex> lk(C.mu);
         auto it = C.vals.find(key);
         if (it != C.vals.end()) {
-            *vals = it->second->as<uint64_t>();
+            *vals = it->second;
             return TM_OK;
         }
     }
-    *vals = nullptr;
+    vals->reset();
     int64_t ne = 2 * g->m_nl;
     size_t bytes = (size_t)ne * 32;
     size_t fr = 0, tot = 0;
     TM_HIP(hipMemGetInfo(&fr, &tot));
     if (bytes > fr / 4) return TM_OK;
-    std::unique_ptr<DevBuf> V(new (std::nothrow) DevBuf());
+    std::shared_ptr<DevBuf> V(new (std::nothrow) DevBuf());
     if (!V) return TM_ENOMEM;
     TM_TRY(V->alloc(bytes));
     DevBuf ctr;
@@ -511,25 +527,24 @@ tm_status anchor_vals(const tm_graph *g, BatchPlan &B, const uint64_t **vals, hi
     tm_prof_end(tok, st);
     TM_HIP(hipStreamSynchronize(st));
     std::lock_guard<std::mutex> lk(C.mu);
-    auto it = C.vals.find(key);
-    if (it == C.vals.end()) it = C.vals.emplace(key, std::move(V)).first;
-    *vals = it->second->as<uint64_t>();
+    // a thread that computed the same values first wins; ours are dropped
+    *vals = C.vals.try_emplace(key, std::move(V)).first->second;
     return TM_OK;
 }
 
 tm_status get_plan(const tm_graph *g, int32_t code, int64_t delta, int64_t L, double p, int64_t n_seeds, int64_t tile,
-                   int64_t bpc, bool want_graph, BatchPlan **out, hipStream_t st) {
+                   int64_t bpc, bool want_graph, std::shared_ptr<BatchPlan> *out, hipStream_t st) {
     BatchCache &C = bcache();
     PlanKey key{g, code, delta, L, p, n_seeds, tile, bpc};
     {
         std::lock_guard<std::mutex> lk(C.mu);
         auto it = C.plans.find(key);
         if (it != C.plans.end()) {
-            *out = it->second.get();
+            *out = it->second;
             return TM_OK;
         }
     }
-    std::unique_ptr<BatchPlan> B(new (std::nothrow) BatchPlan());
+    std::shared_ptr<BatchPlan> B(new (std::nothrow) BatchPlan());
     if (!B) return TM_ENOMEM;
     B->tile = tile;
     B->bpc = bpc;
@@ -540,12 +555,14 @@ tm_status get_plan(const tm_graph *g, int32_t code, int64_t delta, int64_t L, do
     B->code = code;
     B->J = 1 + g->t_span / L + ((g->t_span % L) ? 1 : 0);
     TM_TRY(build_plan(g, *B, st));
-    if ((double)n_seeds * p >= 1.0) TM_TRY(anchor_vals(g, *B, &B->vals, st));
+    if ((double)n_seeds * p >= 1.0) {
+        TM_TRY(anchor_vals(g, *B, &B->vals_buf, st));
+        B->vals = B->vals_buf ? B->vals_buf->as<uint64_t>() : nullptr;
+    }
     if (want_graph) TM_TRY(capture(g, *B));
     std::lock_guard<std::mutex> lk(C.mu);
-    BatchPlan *raw = B.get();
-    C.plans[key] = std::move(B);
-    *out = raw;
+    // a thread that built the same plan first wins; ours is dropped unused
+    *out = C.plans.try_emplace(key, std::move(B)).first->second;
     return TM_OK;
 }
 
@@ -611,13 +628,14 @@ tm_status tm_batch_tune(const tm_graph *g, int32_t code, int64_t delta, int64_t 
     TM_HIP(hipEventCreate(&e1));
     for (int64_t t : tiles) {
         for (int64_t b : bpcs) {
-            BatchPlan *B = nullptr;
+            std::shared_ptr<BatchPlan> B;
             tm_status s = get_plan(g, code, delta, L, p, NS, t, b, false, &B, st);
             if (s != TM_OK) {
                 (void)hipEventDestroy(e0);
                 (void)hipEventDestroy(e1);
                 return s;
             }
+            std::lock_guard<std::mutex> run(B->run_mu);
             (void)hipMemcpyAsync(B->seeds.p, seeds, sizeof seeds, hipMemcpyHostToDevice, st);
             (void)hipEventRecord(e0, st);
             (void)enqueue(g, *B, st);
@@ -635,7 +653,8 @@ tm_status tm_batch_tune(const tm_graph *g, int32_t code, int64_t delta, int64_t 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     {
-        // tuning plans (8 seeds, uncaptured) are not needed any more
+        // tuning plans (2 seeds, uncaptured) are not needed any more; one
+        // that another thread is running stays alive until its run ends
         std::lock_guard<std::mutex> lk(C.mu);
         for (auto it = C.plans.begin(); it != C.plans.end();) {
             if (std::get<0>(it->first) == g && std::get<5>(it->first) == 2 && !it->second->exec)
@@ -661,7 +680,471 @@ tm_status tm_batch_run(const tm_graph *g, int32_t code, int64_t delta, int64_t L
         }
         return TM_OK;
     }
-    BatchPlan *B = nullptr;
+    std::shared_ptr<BatchPlan> B;
     TM_TRY(get_plan(g, code, delta, L, p, n_seeds, tile, bpc, true, &B, st));
+    std::lock_guard<std::mutex> run(B->run_mu);
     return run_plan(g, *B, seeds, est, kept, true, st);
+}
+
+// ---------------------------------------------------------- mixed batches
+//
+// Estimates of many queries on one graph in one captured launch: each
+// estimator has its own three-edge motif, delta, window length c delta,
+// sampling probability and seed (Algorithm 1 run once per query, the loop
+// over its windows in parallel, all queries' windows together).  The
+// candidate tasks are (tile, estimator) pairs, tile-major, so that waves
+// working on one region of the graph serve every estimator that keeps it.
+// Each sweep class has a kernel of its own, holding only that class's
+// accumulators, over the estimators of that class; the kernels run as
+// parallel branches of one hipGraph and steal work from their own queues.
+// Sums are exact integers, so every estimate equals what a single call gives.
+
+namespace {
+
+// one estimator of a mixed batch
+struct MixEst {
+    int64_t delta, L, J;
+    int64_t s;       // shift (k_mix_flags)
+    int64_t kp_off;  // its kept-window prefix: kp[kp_off .. kp_off + J]
+    int64_t w_off;   // its weights: wfx[w_off .. w_off + delta]
+    double p;
+    uint64_t seed;
+    int32_t code;
+    uint32_t want_fwd;  // 1, 2, 4, 8: forward class; 0: backward stars
+};
+
+struct MixArgs {
+    const MixEst *est;       // [n_est]
+    const int32_t *cls_est;  // estimators of this kernel's class
+    int64_t n_cls;
+    int32_t *kp;
+    const uint64_t *wfx;
+    const int64_t *tiles;
+    const int32_t *tile_node;
+    int64_t n_tiles;
+    unsigned long long *qctl;  // this class's candidate counter
+    uint64_t *out;             // [n_est][4]
+};
+
+// one work-group per estimator: its shift and the prefix count of its kept windows
+__global__ void __launch_bounds__(BT_TPB) k_mix_flags(MixEst *E, int32_t *kp) {
+    __shared__ int32_t carry;
+    __shared__ int32_t wsum[BT_TPB / TM_WAVE];
+    MixEst &e = E[blockIdx.x];
+    const uint64_t seed = e.seed;
+    const int64_t J = e.J;
+    int32_t *pre = kp + e.kp_off;
+    if (threadIdx.x == 0) {
+        uint32_t x0 = 0, x1 = 0, x2 = 0, x3 = 0;
+        philox10_d(x0, x1, x2, x3, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const uint64_t x = ((uint64_t)x1 << 32) | (uint64_t)x0;
+        e.s = -(int64_t)(x % (uint64_t)e.L);
+        carry = 0;
+        pre[0] = 0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & (TM_WAVE - 1), w = threadIdx.x / TM_WAVE;
+    for (int64_t base = 1; base <= J; base += BT_TPB) {
+        const int64_t j = base + threadIdx.x;
+        const int32_t f = (j <= J && keep_window(seed, (uint64_t)j, e.p)) ? 1 : 0;
+        int32_t v = f;
+#pragma unroll
+        for (int o = 1; o < TM_WAVE; o <<= 1) {
+            const int32_t y = __shfl_up(v, o, TM_WAVE);
+            if (lane >= o) v += y;
+        }
+        if (lane == TM_WAVE - 1) wsum[w] = v;
+        __syncthreads();
+        int32_t add = carry;
+        for (int i = 0; i < w; ++i) add += wsum[i];
+        if (j <= J) pre[j] = add + v;
+        __syncthreads();
+        if (threadIdx.x == BT_TPB - 1) carry = add + v;
+        __syncthreads();
+    }
+}
+
+// weights round(2^52 L / (L - d)) of every estimator (grid y = estimator)
+__global__ void k_mix_weights(const MixEst *E, uint64_t *wfx) {
+    const MixEst &e = E[blockIdx.y];
+    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d <= e.delta; d += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t den = (uint64_t)(e.L - d);
+        const uint64_t nhi = (uint64_t)e.L >> 12, nlo = (uint64_t)e.L << 52;
+        uint64_t rem = nhi, q = 0;
+        for (int b = 63; b >= 0; --b) {
+            const uint64_t top = rem >> 63;
+            rem = (rem << 1) | ((nlo >> b) & 1ull);
+            q <<= 1;
+            if (top || rem >= den) {
+                rem -= den;
+                q |= 1ull;
+            }
+        }
+        if (rem >= den - rem) q += 1;
+        wfx[e.w_off + d] = q;
+    }
+}
+
+// persistent waves of one sweep class: claim (tile, estimator) candidates,
+// keep those whose tile meets a window the estimator keeps (one ballot), and
+// sweep each kept task's anchors in kept windows with that estimator's delta,
+// windows and weights
+template <unsigned CLS>
+__global__ void __launch_bounds__(BT_TPB) k_mix_sweep(DevGraph G, MixArgs a) {
+    const int lane = threadIdx.x & (TM_WAVE - 1);
+    const int64_t total = a.n_tiles * a.n_cls;
+    const int64_t claim = a.n_cls < TM_WAVE ? a.n_cls : TM_WAVE;
+    while (true) {
+        int64_t base = 0;
+        if (lane == 0) base = (int64_t)atomicAdd(a.qctl, (unsigned long long)claim);
+        base = __shfl(base, 0, TM_WAVE);
+        if (base >= total) break;
+        const int64_t cand = base + lane;
+        bool kept = false;
+        if (lane < claim && cand < total) {
+            const int64_t t = cand / a.n_cls, k = a.cls_est[cand - t * a.n_cls];
+            const MixEst &e = a.est[k];
+            const int64_t e0 = a.tiles[t], e1 = a.tiles[t + 1];
+            const int64_t j0 = (G.inc_t[e0] - e.s) / e.L + 1;
+            int64_t j1 = (G.inc_t[e1 - 1] - e.s) / e.L + 1;
+            if (j1 > e.J) j1 = e.J;
+            const int32_t *kp = a.kp + e.kp_off;
+            kept = kp[j1] - kp[j0 - 1] > 0;
+        }
+        unsigned long long todo = __ballot(kept);
+        while (todo) {
+            const int b = __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
+            const int64_t id = base + b;
+            const int64_t t = id / a.n_cls, k = a.cls_est[id - t * a.n_cls];
+            const MixEst e = a.est[k];
+            const int64_t e0 = a.tiles[t], e1 = a.tiles[t + 1];
+            const int64_t x = a.tile_node[t];
+            const int64_t lb = G.inc_off[x], le = G.inc_off[x + 1];
+            SweepArgs sa;
+            sa.delta = e.delta;
+            sa.windowed = 1;
+            sa.s = e.s;
+            sa.L = e.L;
+            sa.seed = e.seed;
+            sa.p = e.p;
+            sa.wfx = a.wfx + e.w_off;
+            sa.hist = nullptr;
+            sa.out = nullptr;
+            sa.counter = nullptr;
+            sa.want_fwd = CLS;
+            sa.n_entries = 0;
+            sa.kidx = nullptr;
+            sa.win = nullptr;
+            OneCode one{e.code, 0, 0, 0, 0};
+            for (int64_t i = e0 + lane; i < e1; i += TM_WAVE) {
+                const uint32_t nd = G.inc_nd[i];
+                const uint32_t y = nd & 0x7FFFFFFFu, d = nd >> 31;
+                const int64_t tt = G.inc_t[i];
+                const int64_t j = (tt - sa.s) / sa.L + 1;
+                if (!keep_window(sa.seed, (uint64_t)j, sa.p)) continue;
+                const int64_t wlo = sa.s + (j - 1) * sa.L, whi = sa.s + j * sa.L - 1;
+                if (CLS != 0u) {
+                    int64_t hi = (tt > LLONG_MAX - e.delta) ? LLONG_MAX : tt + e.delta;
+                    hi = hi < whi ? hi : whi;
+                    sweep_fwd<MODE_WEIGHT, CLS>(G, sa, i, le, y, d, tt, hi, wlo, nullptr, &one);
+                } else {
+                    int64_t lo = (tt < LLONG_MIN + e.delta) ? LLONG_MIN : tt - e.delta;
+                    lo = lo > wlo ? lo : wlo;
+                    sweep_bwd<MODE_WEIGHT>(G, sa, i, lb, y, d, tt, lo, nullptr, &one);
+                }
+            }
+            wave_sum_u128(one.cl, one.ch);
+            wave_sum_u128(one.wl, one.wh);
+            if (lane == 0) {
+                uint64_t *o = a.out + 4 * k;
+                if (one.cl | one.ch) tm_atomic_add_u128(o, o + 1, one.cl, one.ch);
+                if (one.wl | one.wh) tm_atomic_add_u128(o + 2, o + 3, one.wl, one.wh);
+            }
+        }
+    }
+}
+
+__global__ void k_mix_final(const MixEst *E, const uint64_t *out, int64_t n, double *z) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const uint64_t *o = out + 4 * k;
+    double x = (double)o[3] * 18446744073709551616.0;
+    x = x + (double)o[2];
+    z[k] = x * (1.0 / 4503599627370496.0) / E[k].p;
+}
+
+constexpr int MIX_CLASSES = 5;
+const uint32_t kMixClass[MIX_CLASSES] = {1u, 2u, 4u, 8u, 0u};
+
+int mix_class_index(int code) {
+    if (code < 4) return 0;
+    if (code < 12) return 1;
+    if (code < 20) return 2;
+    if (code < 28) return 3;
+    return 4;
+}
+
+// A mixed batch's device buffers, per host thread and grow-only (a free is a
+// device-wide synchronisation, which would stall the other threads' work),
+// their sizes bounded by mix_bytes.
+struct MixBufs {
+    DevBuf est, cls_est, kp, wfx, tiles, tnode, qctl, out, z, cnt, tot;
+};
+thread_local MixBufs t_mix;
+
+struct MixPlan {
+    int64_t n = 0, tile = 0, bpc = 0, n_tiles = 0, kp_words = 0, w_words = 0;
+    int64_t n_cls[MIX_CLASSES] = {0, 0, 0, 0, 0}, cls_off[MIX_CLASSES] = {0, 0, 0, 0, 0};
+    MixBufs &b = t_mix;
+    DevBuf &est = b.est, &cls_est = b.cls_est, &kp = b.kp, &wfx = b.wfx, &tiles = b.tiles, &tnode = b.tnode,
+           &qctl = b.qctl, &out = b.out, &z = b.z, &cnt = b.cnt, &tot = b.tot;
+    hipStream_t *side = nullptr;
+    hipEvent_t fork = nullptr, *join = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~MixPlan() {
+        if (exec) {
+            std::shared_lock<std::shared_mutex> lk(tm_capture_lock());  // may synchronise
+            (void)hipGraphExecDestroy(exec);
+        }
+    }
+};
+
+// Per host thread: the capture stream, the class branches' streams (default
+// priority) and their fork/join events, created on first use and kept until
+// the process ends (destroying them at thread exit could run after the
+// runtime's teardown).
+struct MixStreams {
+    bool ok = false;
+    hipStream_t cap = nullptr, side[MIX_CLASSES] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[MIX_CLASSES] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+
+MixStreams *mix_streams() {
+    thread_local MixStreams S;
+    if (!S.ok) {
+        bool ok = hipStreamCreateWithFlags(&S.cap, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&S.fork, hipEventDisableTiming) == hipSuccess;
+        for (int c = 0; c < MIX_CLASSES; ++c) {
+            ok = ok && hipStreamCreateWithFlags(&S.side[c], hipStreamNonBlocking) == hipSuccess;
+            ok = ok && hipEventCreateWithFlags(&S.join[c], hipEventDisableTiming) == hipSuccess;
+        }
+        if (!ok) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        S.ok = true;
+    }
+    return &S;
+}
+
+// device bytes of every buffer a mixed batch allocates (DevBuf sizes)
+int64_t mix_bytes(const tm_graph *g, int64_t n, const int64_t *delta, const int64_t *L, int64_t tile,
+                  int64_t *n_tiles_ub, int64_t *kp_words, int64_t *w_words) {
+    int64_t kw = 0, ww = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t J = 1 + g->t_span / L[k] + ((g->t_span % L[k]) ? 1 : 0);
+        kw += J + 1;
+        ww += delta[k] + 1;
+    }
+    // node-aligned tiles: at most one partial tile per node plus full ones
+    const int64_t nt = (2 * g->m_nl) / tile + g->n + 1;
+    if (n_tiles_ub) *n_tiles_ub = nt;
+    if (kp_words) *kp_words = kw;
+    if (w_words) *w_words = ww;
+    const int64_t n1 = n > 0 ? n : 1;
+    return (int64_t)sizeof(MixEst) * n1 + 4 * n1 + 4 * kw + 8 * ww + 8 * (nt + 1) + 4 * nt + 64 + 32 * n1 +
+           8 * n1 + 8 * (g->n + 1) + 8;
+}
+
+tm_status mix_enqueue(const tm_graph *g, MixPlan &B, hipStream_t st, bool fork_streams) {
+    DevGraph G = dev_view(g);
+    MixEst *E = B.est.as<MixEst>();
+    hipLaunchKernelGGL(k_fill_u64, dim3(tm_blocks(4 * B.n, 256)), dim3(256), 0, st, (unsigned long long *)B.out.p,
+                       4 * B.n, 0ull);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, B.qctl.as<unsigned long long>(), (int64_t)8, 0ull);
+    hipLaunchKernelGGL(k_mix_flags, dim3((unsigned)B.n), dim3(BT_TPB), 0, st, E, B.kp.as<int32_t>());
+    TM_HIP(hipGetLastError());
+    int dev = g->device, ncu = 0;
+    TM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (ncu <= 0) ncu = 256;
+    int used = 0;
+    for (int c = 0; c < MIX_CLASSES; ++c) used += B.n_cls[c] > 0;
+    if (fork_streams && used > 1) TM_HIP(hipEventRecord(B.fork, st));
+    int branch = 0;
+    for (int c = 0; c < MIX_CLASSES; ++c) {
+        if (!B.n_cls[c]) continue;
+        hipStream_t sk = st;
+        if (fork_streams && used > 1 && branch++ > 0) {
+            sk = B.side[c];
+            TM_HIP(hipStreamWaitEvent(sk, B.fork, 0));
+        }
+        MixArgs a;
+        a.est = E;
+        a.cls_est = B.cls_est.as<int32_t>() + B.cls_off[c];
+        a.n_cls = B.n_cls[c];
+        a.kp = B.kp.as<int32_t>();
+        a.wfx = B.wfx.as<uint64_t>();
+        a.tiles = B.tiles.as<int64_t>();
+        a.tile_node = B.tnode.as<int32_t>();
+        a.n_tiles = B.n_tiles;
+        a.qctl = B.qctl.as<unsigned long long>() + c;
+        a.out = B.out.as<uint64_t>();
+        const unsigned nb = (unsigned)(ncu * B.bpc);
+        switch (kMixClass[c]) {
+            case 1u: hipLaunchKernelGGL((k_mix_sweep<1u>), dim3(nb), dim3(BT_TPB), 0, sk, G, a); break;
+            case 2u: hipLaunchKernelGGL((k_mix_sweep<2u>), dim3(nb), dim3(BT_TPB), 0, sk, G, a); break;
+            case 4u: hipLaunchKernelGGL((k_mix_sweep<4u>), dim3(nb), dim3(BT_TPB), 0, sk, G, a); break;
+            case 8u: hipLaunchKernelGGL((k_mix_sweep<8u>), dim3(nb), dim3(BT_TPB), 0, sk, G, a); break;
+            default: hipLaunchKernelGGL((k_mix_sweep<0u>), dim3(nb), dim3(BT_TPB), 0, sk, G, a); break;
+        }
+        TM_HIP(hipGetLastError());
+        if (sk != st) {
+            TM_HIP(hipEventRecord(B.join[c], sk));
+            TM_HIP(hipStreamWaitEvent(st, B.join[c], 0));
+        }
+    }
+    hipLaunchKernelGGL(k_mix_final, dim3(tm_blocks(B.n, 64)), dim3(64), 0, st, (const MixEst *)E,
+                       (const uint64_t *)B.out.p, B.n, B.z.as<double>());
+    return tm_hip_status(hipGetLastError());
+}
+
+}  // namespace
+
+// Estimates of n three-edge-motif queries (sweep codes) on graph g in one
+// captured launch; each query has its own delta, window length L, p and
+// seed.  ws_bytes (nullable) receives the device bytes the batch allocated.
+tm_status tm_batch_mixed(const tm_graph *g, int64_t n, const int32_t *code, const int64_t *delta, const int64_t *L,
+                         const double *p, const uint64_t *seeds, double *est, tm_u128 *kept, hipStream_t st) {
+    if (n <= 0) return TM_OK;
+    if (g->m_nl == 0) {
+        for (int64_t k = 0; k < n; ++k) {
+            est[k] = 0.0;
+            if (kept) kept[k].lo = kept[k].hi = 0;
+        }
+        return TM_OK;
+    }
+    MixPlan B;
+    B.n = n;
+    B.tile = 256;
+    B.bpc = 8;
+    int64_t nt_ub = 0;
+    mix_bytes(g, n, delta, L, B.tile, &nt_ub, &B.kp_words, &B.w_words);
+    // estimators, grouped by sweep class
+    std::vector<MixEst> E((size_t)n);
+    std::vector<int32_t> order;
+    order.reserve((size_t)n);
+    int64_t kw = 0, ww = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        MixEst &e = E[(size_t)k];
+        e.delta = delta[k];
+        e.L = L[k];
+        e.J = 1 + g->t_span / L[k] + ((g->t_span % L[k]) ? 1 : 0);
+        e.s = 0;
+        e.kp_off = kw;
+        e.w_off = ww;
+        e.p = p[k];
+        e.seed = seeds[k];
+        e.code = code[k];
+        const int c = mix_class_index(code[k]);
+        e.want_fwd = kMixClass[c];
+        kw += e.J + 1;
+        ww += e.delta + 1;
+        B.n_cls[c] += 1;
+    }
+    for (int c = 0, off = 0; c < MIX_CLASSES; ++c) {
+        B.cls_off[c] = off;
+        off += (int)B.n_cls[c];
+        for (int64_t k = 0; k < n; ++k)
+            if (mix_class_index(code[k]) == c) order.push_back((int32_t)k);
+    }
+    TM_TRY(B.est.reserve((size_t)n * sizeof(MixEst)));
+    TM_TRY(B.cls_est.reserve((size_t)n * 4));
+    TM_TRY(B.kp.reserve((size_t)kw * 4));
+    TM_TRY(B.wfx.reserve((size_t)ww * 8));
+    TM_TRY(B.qctl.reserve(64));
+    TM_TRY(B.out.reserve((size_t)n * 32));
+    TM_TRY(B.z.reserve((size_t)n * 8));
+    TM_HIP(hipMemcpyAsync(B.est.p, E.data(), (size_t)n * sizeof(MixEst), hipMemcpyHostToDevice, st));
+    TM_HIP(hipMemcpyAsync(B.cls_est.p, order.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
+    // node-aligned tiles of at most B.tile entries
+    const int64_t nn = g->n;
+    TM_TRY(B.cnt.reserve((size_t)(nn + 1) * 8));
+    TM_TRY(B.tot.reserve(8));
+    hipLaunchKernelGGL(k_tile_count, dim3(tm_blocks(nn, 256)), dim3(256), 0, st, g->inc_off.as<int64_t>(), nn, B.tile,
+                       B.cnt.as<int64_t>());
+    TM_HIP(hipGetLastError());
+    TM_TRY(tm_scan_i64(B.cnt.as<int64_t>(), nn, B.tot.as<int64_t>(), st));
+    int64_t ntile = 0;
+    TM_HIP(hipMemcpyAsync(&ntile, B.tot.p, 8, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipStreamSynchronize(st));
+    if (ntile > nt_ub) return TM_EDEVICE;  // the bound mix_bytes charges
+    B.n_tiles = ntile;
+    TM_TRY(B.tiles.reserve((size_t)(nt_ub + 1) * 8));
+    TM_TRY(B.tnode.reserve((size_t)nt_ub * 4));
+    hipLaunchKernelGGL(k_tile_fill, dim3(tm_blocks(nn, 256)), dim3(256), 0, st, g->inc_off.as<int64_t>(), nn, B.tile,
+                       B.cnt.as<int64_t>(), B.tiles.as<int64_t>(), B.tnode.as<int32_t>());
+    hipLaunchKernelGGL(k_set_last, dim3(1), dim3(1), 0, st, B.tiles.as<int64_t>(), ntile, 2 * g->m_nl);
+    int64_t maxd = 0;
+    for (int64_t k = 0; k < n; ++k) maxd = std::max<int64_t>(maxd, delta[k]);
+    unsigned gx = tm_blocks(maxd + 1, 256);
+    if (gx > 1024) gx = 1024;
+    hipLaunchKernelGGL(k_mix_weights, dim3(gx, (unsigned)n), dim3(256), 0, st, (const MixEst *)B.est.as<MixEst>(),
+                       B.wfx.as<uint64_t>());
+    TM_HIP(hipGetLastError());
+    // capture the launch sequence (the class kernels as parallel branches)
+    // on this thread's capture stream, then replay it on the caller's stream
+    MixStreams *MS = mix_streams();
+    if (!MS) return TM_EDEVICE;
+    hipStream_t cap = MS->cap;
+    B.side = MS->side;
+    B.fork = MS->fork;
+    B.join = MS->join;
+    TM_HIP(hipStreamSynchronize(st));
+    hipGraph_t graph = nullptr;
+    tm_status s;
+    hipError_t e;
+    {
+        // no library free (an implicit device synchronisation) during the capture
+        std::unique_lock<std::shared_mutex> lk(tm_capture_lock());
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return tm_hip_status(e);
+        s = mix_enqueue(g, B, cap, true);
+        e = hipStreamEndCapture(cap, &graph);
+    }
+    if (s != TM_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    TM_HIP(e);
+    e = hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    TM_HIP(e);
+    void *tok = tm_prof_begin("count_batch_mixed", st);
+    TM_HIP(hipGraphLaunch(B.exec, st));
+    tm_prof_end(tok, st);
+    std::vector<double> z((size_t)n);
+    std::vector<uint64_t> o((size_t)n * 4);
+    TM_HIP(hipMemcpyAsync(z.data(), B.z.p, (size_t)n * 8, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipMemcpyAsync(o.data(), B.out.p, (size_t)n * 32, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipStreamSynchronize(st));
+    for (int64_t k = 0; k < n; ++k) {
+        est[k] = z[(size_t)k];
+        if (kept) {
+            kept[k].lo = o[(size_t)(4 * k)];
+            kept[k].hi = o[(size_t)(4 * k + 1)];
+        }
+    }
+    return TM_OK;
+}
+
+// device bytes tm_batch_mixed allocates for these queries
+int64_t tm_batch_mixed_bytes(const tm_graph *g, int64_t n, const int64_t *delta, const int64_t *L) {
+    return mix_bytes(g, n, delta, L, 256, nullptr, nullptr, nullptr) + tm_scan_ws_bytes(g->n);
+}
+
+void tm_batch_release_thread_ws() {
+    MixBufs &b = t_mix;
+    for (DevBuf *d : {&b.est, &b.cls_est, &b.kp, &b.wfx, &b.tiles, &b.tnode, &b.qctl, &b.out, &b.z, &b.cnt, &b.tot})
+        d->release();
 }

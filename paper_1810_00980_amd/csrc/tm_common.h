@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <stddef.h>
 #include <map>
+#include <shared_mutex>
 #include <vector>
 
 #include "tm.h"
@@ -36,12 +37,43 @@ static inline tm_status tm_hip_status(hipError_t e) {
 // most TM_LOAD_CACHE_BYTES and gives its blocks back to the device when an
 // allocation runs out of memory.
 constexpr size_t TM_LOAD_CACHE_BYTES = (size_t)2 << 30;
+
+// hipFree performs an implicit device-wide synchronisation, which a stream
+// that another thread is capturing into a hipGraph does not allow.  The
+// library's frees and device synchronisations therefore hold this lock
+// shared, and its captures (BeginCapture .. EndCapture) hold it exclusively,
+// so that none of its frees overlaps one of its captures.
+inline std::shared_mutex &tm_capture_lock() {
+    static std::shared_mutex m;
+    return m;
+}
+
+// Device bytes held by the calling host thread: what its DevBufs allocated
+// minus what they freed (blocks kept by the load cache count as held), and
+// the high-water mark since the caller last set peak = live.  The query
+// server charges each batch's workspace against its budget and checks the
+// charge against this measurement.
+struct DevTally {
+    int64_t live = 0, peak = 0;
+    void add(int64_t b) {
+        live += b;
+        if (live > peak) peak = live;
+    }
+};
+inline thread_local DevTally t_dev_tally;
+
 struct LoadCache {
     std::multimap<size_t, void *> blocks;  // block size -> block
     size_t bytes = 0;
+    size_t limit = TM_LOAD_CACHE_BYTES;    // 0: keep nothing (server slot threads)
     bool active = false;
     void clear() {
-        for (auto &kv : blocks) (void)hipFree(kv.second);
+        if (blocks.empty()) return;
+        std::shared_lock<std::shared_mutex> lk(tm_capture_lock());
+        for (auto &kv : blocks) {
+            (void)hipFree(kv.second);
+            t_dev_tally.add(-(int64_t)kv.first);
+        }
         blocks.clear();
         bytes = 0;
     }
@@ -71,7 +103,7 @@ struct DevBuf {
         if (p) {
             LoadCache &C = t_load_cache;
             bool kept = false;
-            if (C.active && C.bytes + cap <= TM_LOAD_CACHE_BYTES) {
+            if (C.active && C.bytes + cap <= C.limit) {
                 try {
                     C.blocks.emplace(cap, p);
                     C.bytes += cap;
@@ -79,7 +111,11 @@ struct DevBuf {
                 } catch (...) {
                 }
             }
-            if (!kept) (void)hipFree(p);
+            if (!kept) {
+                std::shared_lock<std::shared_mutex> lk(tm_capture_lock());
+                (void)hipFree(p);
+                t_dev_tally.add(-(int64_t)cap);
+            }
         }
         p = nullptr;
         bytes = 0;
@@ -115,6 +151,7 @@ struct DevBuf {
         }
         bytes = nbytes;
         cap = nbytes;
+        t_dev_tally.add((int64_t)nbytes);
         return TM_OK;
     }
     // grow-only reuse
@@ -264,6 +301,28 @@ tm_status tm_build_exact_tables(tm_graph *g, const uint32_t *ent_nl, const uint3
 
 // ------------------------------------------------------------ primitives
 
+// Grow-only device workspaces the query paths keep per host thread (sweep
+// accumulators, claim orders, scan block sums, generic-counter items), and
+// the sizes they reach: the query server frees them after every batch, so
+// that a batch's device memory is exactly what it was charged.
+void tm_api_release_thread_ws();
+void tm_sweep_release_thread_ws();
+void tm_prims_release_thread_ws();
+void tm_generic_release_thread_ws();
+void tm_batch_release_thread_ws();
+inline void tm_release_thread_ws() {
+    tm_api_release_thread_ws();
+    tm_sweep_release_thread_ws();
+    tm_prims_release_thread_ws();
+    tm_generic_release_thread_ws();
+    tm_batch_release_thread_ws();
+    t_load_cache.clear();
+}
+int64_t tm_scan_ws_bytes(int64_t n);           // block sums of a scan of n values
+int64_t tm_radix_sort_bytes(int64_t n);        // temporaries of a radix sort of n pairs
+int64_t tm_tri_order_bytes(const tm_graph *g); // the exact triangle sweep's claim order
+int64_t tm_generic_bytes(int64_t n_anchors, int len);  // the generic counter's items
+
 // Exclusive prefix sum of n int64 values, in place; *total (nullable, device)
 // receives the sum.  Asynchronous on st; its block sums live in a per-thread
 // workspace that grows on demand (a host thread scans on one stream at a time).
@@ -403,3 +462,9 @@ tm_status tm_batch_tune(const tm_graph *g, int32_t code, int64_t delta, int64_t 
                         int64_t *bpc, hipStream_t st);
 void tm_batch_forget(const tm_graph *g);
 void tm_batch_release_plans(const tm_graph *g);
+// Estimates of n three-edge-motif queries (sweep codes, each with its own
+// delta, window length L, p and seed) in one captured launch, and the device
+// bytes that takes.
+tm_status tm_batch_mixed(const tm_graph *g, int64_t n, const int32_t *code, const int64_t *delta, const int64_t *L,
+                         const double *p, const uint64_t *seeds, double *est, tm_u128 *kept, hipStream_t st);
+int64_t tm_batch_mixed_bytes(const tm_graph *g, int64_t n, const int64_t *delta, const int64_t *L);

@@ -469,6 +469,17 @@ __global__ void k_weight(const uint64_t *hlo, const uint64_t *hhi, int64_t delta
 
 }  // namespace
 
+void tm_generic_release_thread_ws() {
+    t_cg_counter.release();
+    t_cg_items.release();
+}
+
+int64_t tm_generic_bytes(int64_t n_anchors, int len) {
+    int64_t b = 8;  // the work-queue head
+    if (len >= 3 && n_anchors > 0) b += n_anchors * 16 + 64 + tm_scan_ws_bytes(n_anchors);
+    return b;
+}
+
 tm_status tm_make_plan(const tm_motif *M, MotifPlan *P) {
     if (!M || !P) return TM_EINVAL;
     int l = M->l;

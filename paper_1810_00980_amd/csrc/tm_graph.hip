@@ -684,7 +684,10 @@ extern "C" tm_status tm_load_graph(const int32_t *src, const int32_t *dst, const
 
 extern "C" void tm_free_graph(tm_graph *g) {
     if (!g) return;
-    (void)hipDeviceSynchronize();
+    {
+        std::shared_lock<std::shared_mutex> lk(tm_capture_lock());
+        (void)hipDeviceSynchronize();
+    }
     tm_batch_forget(g);
     delete g;
 }

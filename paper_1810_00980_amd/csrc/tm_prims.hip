@@ -228,3 +228,14 @@ tm_status tm_radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hip
     TM_HIP(hipStreamSynchronize(st));
     return TM_OK;
 }
+
+void tm_prims_release_thread_ws() { t_scan_ws.release(); }
+
+int64_t tm_scan_ws_bytes(int64_t n) { return n > 0 ? scan_ws_elems(n) * (int64_t)sizeof(int64_t) : 0; }
+
+int64_t tm_radix_sort_bytes(int64_t n) {
+    if (n <= 1) return 0;
+    const int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
+    return n * (int64_t)(sizeof(uint64_t) + sizeof(uint32_t)) + ntiles * 256 * (int64_t)sizeof(int64_t) +
+           tm_scan_ws_bytes(ntiles * 256);
+}

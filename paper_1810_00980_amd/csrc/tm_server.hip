@@ -2,19 +2,29 @@
 // device-resident graphs, admitted against a device-memory budget.
 //
 // A dispatcher thread keeps a FIFO of submitted queries.  Whenever a worker
-// slot is free it takes the oldest query, merges every pending query that
-// can share its device pass (exact counts of three-edge motifs on the same
-// graph and delta share one sweep; estimates of three-edge motifs with the
-// same graph, delta, c, p and seed share one windowed sweep, because the
-// shift and kept windows depend only on those), reserves the batch's
-// workspace from the budget, and hands the batch to the slot.  Each slot is a
-// host thread with its own HIP stream (default priority), so batches on
-// different slots overlap on the device; finishing a batch returns its
-// workspace to the budget and wakes the dispatcher, which admits waiting
-// queries as memory and slots free up.  A query whose workspace alone exceeds
-// the budget is completed with TM_EBUDGET.  Results do not depend on how
-// queries were batched: every count is an exact integer and every estimate
-// is computed from exact integer sums.
+// slot is free it takes the oldest query that fits the memory budget and
+// merges every pending query that can share its device work: exact counts of
+// three-edge motifs on the same graph and delta share one sweep; estimates of
+// three-edge motifs on the same graph share one persistent launch, whatever
+// their motifs, deltas, c, p and seeds (each is its own estimator in the
+// mixed batch).  It reserves the batch's device workspace from the budget
+// and hands the batch to the slot.  Each slot is a host thread with its own
+// HIP stream (default priority), so batches on different slots overlap on the
+// device; finishing a batch returns its workspace to the budget and wakes the
+// dispatcher, which admits waiting queries as memory and slots free up.
+//
+// A batch is charged the device bytes its path allocates (every buffer of
+// that path, at the sizes the graph and queries fix, with upper bounds where
+// a size is only known on the device); the bytes it really allocated are
+// measured (DevTally) and reported beside the charge.  A slot thread keeps
+// its grow-only workspaces between batches (a free is a device-wide
+// synchronisation that would stall the other slots), and what it holds is
+// measured after each batch and counted against the budget as well; when the
+// oldest query does not fit, an idle slot is asked to free what it holds.  A
+// query whose workspace alone exceeds the budget is completed with
+// TM_EBUDGET.  Results do
+// not depend on how queries were batched: every count is an exact integer and
+// every estimate is computed from exact integer sums.
 #include "tm_common.h"
 
 #include <string.h>
@@ -41,24 +51,60 @@ struct Pending {
     Clock::time_point submit;
 };
 
-struct Done {
-    tm_result r;
-    bool ready = false;
-    bool claimed = false;
-};
+constexpr size_t TM_SERVER_MAX_BATCH = 256;
 
-int64_t query_ws_bytes(const tm_graph *g, const tm_query &q) {
-    bool three = tm_sweep_code_of(&q.motif) >= 0;
-    if (three) return 36 * 4 * 8 + 64 + (q.kind == 1 ? (q.delta + 1) * 8 : 0);
-    // generic path: kept-anchor lists (8 arrays of m words) and a histogram
-    return 8 * 8 * g->m + 16 * (q.delta + 1) + 4096;
+int64_t buf(int64_t b) { return b > 0 ? b : 256; }  // DevBuf's size for a request of b bytes
+
+// Device bytes of the path a batch takes (the DevBufs it allocates, alive
+// together).  All queries of a batch share graph and kind; a batch of more
+// than one query holds three-edge motifs only.
+int64_t batch_ws_bytes(const tm_graph *g, const std::vector<tm_query> &b) {
+    const tm_query &q0 = b[0];
+    const bool three = tm_sweep_code_of(&q0.motif) >= 0;
+    const int64_t m1 = g->m > 0 ? g->m : 1;
+    if (q0.kind == 0) {
+        if (three) {
+            // the sweep's accumulators and work counters, and the exact
+            // triangle sweep's claim order when a triangle motif is asked for
+            int64_t bytes = buf(36 * 4 * 8) + buf(64);
+            for (const tm_query &q : b) {
+                const int c = tm_sweep_code_of(&q.motif);
+                if (c >= 20 && c < 28) {
+                    bytes += tm_tri_order_bytes(g);
+                    break;
+                }
+            }
+            return bytes;
+        }
+        // the generic counter over every edge
+        return buf(64) + tm_generic_bytes(g->m, q0.motif.l);
+    }
+    if (three) {
+        std::vector<int64_t> delta, L;
+        for (const tm_query &q : b) {
+            delta.push_back(q.delta);
+            L.push_back(q.c * q.delta);
+        }
+        return tm_batch_mixed_bytes(g, (int64_t)b.size(), delta.data(), L.data());
+    }
+    // the generic estimate with diagnostics: kept-anchor lists (the kept
+    // anchors are at most m), the duration histogram, per-window totals, the
+    // generic counter's items, the window list and the scan workspace
+    const int64_t L = q0.c * q0.delta;
+    const int64_t J = 1 + g->t_span / L + ((g->t_span % L) ? 1 : 0);
+    int64_t bytes = buf(64) + 3 * buf(8 * m1) + 6 * buf(8 * m1) + buf(4 * m1);
+    bytes += buf(16 * (q0.delta + 1)) + buf((2 + 2 * m1) * 8 + 64);
+    bytes += tm_generic_bytes(m1, q0.motif.l);
+    if (J <= ((int64_t)1 << 24)) bytes += 2 * buf(8 * J) + buf(8) + buf(8);
+    bytes += tm_scan_ws_bytes(m1 > J ? m1 : J);
+    return bytes;
 }
 
 bool shareable(const tm_query &a, const tm_query &b) {
-    if (a.graph != b.graph || a.kind != b.kind || a.delta != b.delta) return false;
+    if (a.graph != b.graph || a.kind != b.kind) return false;
     if (tm_sweep_code_of(&a.motif) < 0 || tm_sweep_code_of(&b.motif) < 0) return false;
-    if (a.kind == 0) return true;
-    return a.c == b.c && a.p == b.p && a.seed == b.seed;
+    if (a.kind == 0) return a.delta == b.delta;
+    return true;  // estimates: one estimator each in the mixed batch
 }
 
 }  // namespace
@@ -67,17 +113,21 @@ struct tm_server {
     std::mutex mu;
     std::condition_variable cv_disp, cv_done;
     std::deque<Pending> queue;
-    std::map<int64_t, Done> done;
+    std::map<int64_t, tm_result> done;  // finished, not yet collected
+    std::vector<uint8_t> state;         // per ticket: 0 pending, 1 ready, 2 collected
     std::vector<const tm_graph *> graphs;
     std::vector<std::thread> workers;
     std::thread dispatcher;
     std::vector<std::vector<Pending>> slot_work;
-    std::vector<int64_t> slot_bytes;
+    std::vector<int64_t> slot_bytes;   // charge of the running batch
+    std::vector<int64_t> slot_held;    // device bytes the slot thread holds between batches
+    std::vector<bool> release_req;     // asked to free what it holds
     std::vector<hipStream_t> streams;
     std::vector<bool> slot_busy;
     std::condition_variable cv_slot;
     int64_t budget = 0, in_use = 0, peak = 0, next_ticket = 1;
     int64_t submitted = 0, completed = 0, rejected = 0, batches = 0;
+    int64_t measured_max = 0, over_charge = 0;
     bool stop = false, have_first = false;
     Clock::time_point first_submit, last_done;
     std::vector<double> lat_ms;
@@ -85,10 +135,8 @@ struct tm_server {
     int device = 0;
 
     void finish_query(const Pending &pq, const tm_result &r) {
-        Done &d = done[pq.ticket];
-        d.r = r;
-        d.ready = true;
-        d.claimed = false;
+        done[pq.ticket] = r;
+        state[(size_t)pq.ticket] = 1;
         ++completed;
         if (r.status == TM_OK) {
             lat_ms.push_back(r.latency_ms);
@@ -134,7 +182,7 @@ struct tm_server {
             for (size_t qi = 0; qi < queue.size(); ++qi) {
                 const Pending &head = queue[qi];
                 const tm_graph *g = graphs[(size_t)head.q.graph];
-                int64_t need = query_ws_bytes(g, head.q);
+                int64_t need = batch_ws_bytes(g, {head.q});
                 if (need > budget) {
                     tm_result r;
                     memset(&r, 0, sizeof r);
@@ -145,12 +193,34 @@ struct tm_server {
                     admitted = true;  // re-evaluate
                     break;
                 }
-                if (in_use + need > budget) continue;
+                if (in_use + need > budget) {
+                    // ask idle slots that hold workspaces to free them
+                    for (size_t k = 0; k < slot_busy.size(); ++k)
+                        if (!slot_busy[k] && slot_held[k] > 0 && !release_req[k]) {
+                            release_req[k] = true;
+                            cv_slot.notify_all();
+                        }
+                    continue;
+                }
                 std::vector<Pending> batch;
+                std::vector<tm_query> bq;
                 batch.push_back(head);
+                bq.push_back(head.q);
                 queue.erase(queue.begin() + (long)qi);
                 for (size_t k = 0; k < queue.size();) {
-                    if (batch.size() < 36 && shareable(batch[0].q, queue[k].q)) {
+                    bool take = batch.size() < TM_SERVER_MAX_BATCH && shareable(batch[0].q, queue[k].q);
+                    if (take) {
+                        // a merged query must keep the batch within what is left
+                        bq.push_back(queue[k].q);
+                        const int64_t more = batch_ws_bytes(g, bq);
+                        if (in_use + more > budget) {
+                            bq.pop_back();
+                            take = false;
+                        } else {
+                            need = more;
+                        }
+                    }
+                    if (take) {
                         batch.push_back(queue[k]);
                         queue.erase(queue.begin() + (long)k);
                     } else {
@@ -174,8 +244,10 @@ struct tm_server {
         }
     }
 
-    void run_batch(int slot, std::vector<Pending> &batch) {
+    void run_batch(int slot, std::vector<Pending> &batch, int64_t charged) {
         hipStream_t st = streams[(size_t)slot];
+        const int64_t base = t_dev_tally.live;
+        t_dev_tally.peak = base;
         const tm_query &q0 = batch[0].q;
         const tm_graph *g = graphs[(size_t)q0.graph];
         Clock::time_point start = Clock::now();
@@ -195,17 +267,12 @@ struct tm_server {
         } else {
             std::vector<double> est((size_t)n);
             std::vector<tm_u128> kc((size_t)n);
-            tm_status s;
-            if (n > 1) {
-                s = tm_estimate_multi(g, n, ms.data(), q0.delta, q0.c, q0.p, q0.seed, est.data(), kc.data(), st);
-            } else {
-                tm_est_info info;
-                memset(&info, 0, sizeof info);
-                bool three = tm_sweep_code_of(&ms[0]) >= 0;
-                s = three ? tm_estimate_multi(g, 1, ms.data(), q0.delta, q0.c, q0.p, q0.seed, est.data(), kc.data(), st)
-                          : tm_estimate(g, &ms[0], q0.delta, q0.c, q0.p, q0.seed, &est[0], &info, st);
-                if (!three) kc[0] = info.kept_count;
+            std::vector<tm_est_query> eq((size_t)n);
+            for (int i = 0; i < n; ++i) {
+                const tm_query &q = batch[(size_t)i].q;
+                eq[(size_t)i] = tm_est_query{q.motif, q.delta, q.c, q.p, q.seed};
             }
+            tm_status s = tm_estimate_mixed(g, n, eq.data(), est.data(), kc.data(), st);
             for (int i = 0; i < n; ++i) {
                 res[(size_t)i].status = s;
                 res[(size_t)i].estimate = est[(size_t)i];
@@ -213,9 +280,14 @@ struct tm_server {
             }
         }
         Clock::time_point end = Clock::now();
+        const int64_t measured = t_dev_tally.peak - base;
         std::lock_guard<std::mutex> lk(mu);
+        measured_max = std::max(measured_max, measured);
+        if (measured > charged) ++over_charge;
         for (int i = 0; i < n; ++i) {
             tm_result &r = res[(size_t)i];
+            r.ws_charged = charged;
+            r.ws_measured = measured;
             r.latency_ms = std::chrono::duration<double, std::milli>(end - batch[(size_t)i].submit).count();
             r.queue_ms = std::chrono::duration<double, std::milli>(start - batch[(size_t)i].submit).count();
             r.batch_size = n;
@@ -225,22 +297,45 @@ struct tm_server {
         cv_done.notify_all();
     }
 
+    // what this slot thread holds now replaces what it held (lock held)
+    void set_held(int slot) {
+        const int64_t h = std::max<int64_t>(0, t_dev_tally.live);
+        in_use += h - slot_held[(size_t)slot];
+        slot_held[(size_t)slot] = h;
+        peak = std::max(peak, in_use);
+    }
+
     void worker_loop(int slot) {
         (void)hipSetDevice(device);
+        t_dev_tally.live = t_dev_tally.peak = 0;  // this thread's own allocations only
         while (true) {
             std::vector<Pending> batch;
+            int64_t charged = 0;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv_slot.wait(lk, [&] { return stop || !slot_work[(size_t)slot].empty(); });
+                cv_slot.wait(lk, [&] {
+                    return stop || !slot_work[(size_t)slot].empty() || release_req[(size_t)slot];
+                });
+                if (release_req[(size_t)slot] && slot_work[(size_t)slot].empty()) {
+                    lk.unlock();
+                    tm_release_thread_ws();
+                    lk.lock();
+                    release_req[(size_t)slot] = false;
+                    set_held(slot);
+                    cv_disp.notify_all();
+                    continue;
+                }
                 if (slot_work[(size_t)slot].empty()) return;  // stop requested, no work
                 batch = std::move(slot_work[(size_t)slot]);
                 slot_work[(size_t)slot].clear();
+                charged = slot_bytes[(size_t)slot];
             }
-            run_batch(slot, batch);
+            run_batch(slot, batch, charged);
             {
                 std::lock_guard<std::mutex> lk(mu);
                 in_use -= slot_bytes[(size_t)slot];
                 slot_bytes[(size_t)slot] = 0;
+                set_held(slot);
                 slot_busy[(size_t)slot] = false;
             }
             cv_disp.notify_all();
@@ -259,6 +354,8 @@ extern "C" tm_status tm_server_create(int32_t slots, int64_t budget_bytes, tm_se
     S->budget = budget_bytes;
     S->slot_work.resize((size_t)slots);
     S->slot_bytes.assign((size_t)slots, 0);
+    S->slot_held.assign((size_t)slots, 0);
+    S->release_req.assign((size_t)slots, false);
     S->slot_busy.assign((size_t)slots, false);
     for (int i = 0; i < slots; ++i) {
         hipStream_t st;
@@ -294,6 +391,7 @@ extern "C" tm_status tm_server_submit(tm_server *S, const tm_query *q, int64_t *
     if (q->graph < 0 || (size_t)q->graph >= S->graphs.size()) return TM_EINVAL;
     Pending pq;
     pq.ticket = S->next_ticket++;
+    S->state.resize((size_t)S->next_ticket, 0);
     pq.q = *q;
     pq.submit = Clock::now();
     if (!S->have_first) {
@@ -311,15 +409,13 @@ extern "C" tm_status tm_server_wait(tm_server *S, int64_t ticket, tm_result *res
     if (!S || !res) return TM_EINVAL;
     std::unique_lock<std::mutex> lk(S->mu);
     if (ticket <= 0 || ticket >= S->next_ticket) return TM_EINVAL;
-    auto it0 = S->done.find(ticket);
-    if (it0 != S->done.end() && it0->second.claimed) return TM_EINVAL;  // already collected
-    S->cv_done.wait(lk, [&] {
-        auto it = S->done.find(ticket);
-        return it != S->done.end() && it->second.ready;
-    });
-    Done &d = S->done[ticket];
-    d.claimed = true;
-    *res = d.r;
+    if (S->state[(size_t)ticket] == 2) return TM_EINVAL;  // already collected
+    S->cv_done.wait(lk, [&] { return S->state[(size_t)ticket] != 0; });
+    if (S->state[(size_t)ticket] == 2) return TM_EINVAL;  // collected by another waiter
+    auto it = S->done.find(ticket);
+    *res = it->second;
+    S->done.erase(it);
+    S->state[(size_t)ticket] = 2;
     return TM_OK;
 }
 
@@ -333,6 +429,9 @@ extern "C" tm_status tm_server_stats_get(tm_server *S, tm_server_stats *out) {
     out->batches = S->batches;
     out->budget_bytes = S->budget;
     out->peak_bytes = S->peak;
+    out->measured_max_bytes = S->measured_max;
+    out->over_charge = S->over_charge;
+    out->uncollected = (int64_t)S->done.size();
     std::vector<double> v = S->lat_ms;
     if (!v.empty()) {
         std::sort(v.begin(), v.end());

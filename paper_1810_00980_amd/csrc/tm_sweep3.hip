@@ -357,6 +357,21 @@ __global__ void k_tri_batch_cost(DevGraph G, SweepArgs a, int64_t nbt, uint64_t 
 // per host thread: keys and batch ids of the claim order
 thread_local DevBuf t_order_k, t_order_v;
 
+}  // namespace
+
+void tm_sweep_release_thread_ws() {
+    t_order_k.release();
+    t_order_v.release();
+}
+
+int64_t tm_tri_order_bytes(const tm_graph *g) {
+    const int64_t nbt = (g->n_hi + TM_WAVE - 1) / TM_WAVE;
+    if (nbt <= 1 || nbt > (int64_t)UINT32_MAX) return 0;
+    return nbt * 12 + tm_radix_sort_bytes(nbt);
+}
+
+namespace {
+
 tm_status tri_claim_order(const tm_graph *g, SweepArgs &a, hipStream_t st) {
     const DevGraph G = dev_view(g);
     const int64_t nbt = (G.n_hi + TM_WAVE - 1) / TM_WAVE;
@@ -484,11 +499,19 @@ __global__ void k_census(DevGraph G, int64_t delta, unsigned long long *out) {
     }
 }
 
+// binary-search probes of one search over a pair timeline of n entries
+__device__ inline unsigned long long search_probes(int64_t n) {
+    return n > 0 ? (unsigned long long)(64 - __clzll((unsigned long long)n)) : 0ull;
+}
+
 // entries scanned by the exact triangle sweep over the ranked sublists, the
-// closing-pair lookups among them and the changes of closing pair
+// closing-pair lookups among them, the changes of closing pair and the
+// binary-search probes of a plain lookup: per lookup, searches at t_j and
+// t_j - delta; per change of pair, one probe to find it and searches at t_i
+// and at the window end
 __global__ void k_census_ranked(DevGraph G, int64_t delta, unsigned long long *out) {
-    __shared__ unsigned long long sh[3][SW_TPB];
-    unsigned long long f = 0, lk = 0, pc = 0;
+    __shared__ unsigned long long sh[4][SW_TPB];
+    unsigned long long f = 0, lk = 0, pc = 0, pr = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < G.n_hi;
          i += (int64_t)gridDim.x * blockDim.x) {
         int64_t x = owner_of(G.hi_off, G.n, i);
@@ -497,13 +520,20 @@ __global__ void k_census_ranked(DevGraph G, int64_t delta, unsigned long long *o
         uint32_t y1 = G.hi_nd[i] & 0x7FFFFFFFu;
         int64_t hi = (t > LLONG_MAX - delta) ? LLONG_MAX : t + delta;
         uint32_t prev = ~0u;
+        unsigned long long lp = 0;  // probes of one search in the current pair
         int64_t j = i + 1;
         for (; j < le && G.hi_t[j] <= hi; ++j) {
             if (G.hi_t[j] == t) continue;
             uint32_t yj = G.hi_nd[j] & 0x7FFFFFFFu;
             if (yj == y1) continue;
             ++lk;
-            if (yj != prev) ++pc;
+            if (yj != prev) {
+                ++pc;
+                PairView pv;
+                lp = pair_find(G, y1, yj, pv) >= 0 ? search_probes(pv.n) : 0ull;
+                pr += 1 + 2 * lp;
+            }
+            pr += 2 * lp;
             prev = yj;
         }
         f += (unsigned long long)(j - i - 1);
@@ -511,25 +541,29 @@ __global__ void k_census_ranked(DevGraph G, int64_t delta, unsigned long long *o
     sh[0][threadIdx.x] = f;
     sh[1][threadIdx.x] = lk;
     sh[2][threadIdx.x] = pc;
+    sh[3][threadIdx.x] = pr;
     __syncthreads();
     for (int s = SW_TPB / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) {
-            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+            for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         for (int q = 0; q < 3; ++q) atomicAdd(&out[2 + q], sh[q][0]);
+        atomicAdd(&out[5], sh[3][0]);
     }
 }
 
 // the estimate's weighted sweeps for window length L, shift s, seed and p:
 // kept anchors, entries scanned forward and backward inside the anchor's
-// window, and the forward triangle sweep's lookups and pair changes
+// window, the forward triangle sweep's lookups and pair changes, and the
+// binary-search probes of a plain lookup: per lookup, one search at t_j; per
+// change of pair, one probe to find it and a search at t_i
 __global__ void k_census_est(DevGraph G, int64_t delta, int64_t s, int64_t L, double p, uint64_t seed,
                              unsigned long long *out) {
-    __shared__ unsigned long long sh[5][SW_TPB];
-    unsigned long long an = 0, f = 0, b = 0, lk = 0, pc = 0;
+    __shared__ unsigned long long sh[6][SW_TPB];
+    unsigned long long an = 0, f = 0, b = 0, lk = 0, pc = 0, pr = 0;
     int64_t nE = 2 * G.m_nl;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nE; i += (int64_t)gridDim.x * blockDim.x) {
         int64_t t = G.inc_t[i];
@@ -545,13 +579,20 @@ __global__ void k_census_est(DevGraph G, int64_t delta, int64_t s, int64_t L, do
         int64_t lo = (t < LLONG_MIN + delta) ? LLONG_MIN : t - delta;
         lo = lo > wlo ? lo : wlo;
         uint32_t prev = ~0u;
+        unsigned long long lp = 0;
         int64_t j = i + 1;
         for (; j < le && G.inc_t[j] <= hi; ++j) {
             if (G.inc_t[j] == t) continue;
             uint32_t yj = G.inc_nd[j] & 0x7FFFFFFFu;
             if (yj == y1) continue;
             ++lk;
-            if (yj != prev) ++pc;
+            if (yj != prev) {
+                ++pc;
+                PairView pv;
+                lp = pair_find(G, y1, yj, pv) >= 0 ? search_probes(pv.n) : 0ull;
+                pr += 1 + lp;
+            }
+            pr += lp;
             prev = yj;
         }
         f += (unsigned long long)(j - i - 1);
@@ -568,15 +609,16 @@ __global__ void k_census_est(DevGraph G, int64_t delta, int64_t s, int64_t L, do
     sh[2][threadIdx.x] = b;
     sh[3][threadIdx.x] = lk;
     sh[4][threadIdx.x] = pc;
+    sh[5][threadIdx.x] = pr;
     __syncthreads();
     for (int w = SW_TPB / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
-            for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+            for (int q = 0; q < 6; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        for (int q = 0; q < 5; ++q) atomicAdd(&out[q], sh[q][0]);
+        for (int q = 0; q < 6; ++q) atomicAdd(&out[q], sh[q][0]);
     }
 }
 
@@ -588,23 +630,24 @@ tm_status tm_sweep_census_impl(const tm_graph *g, int64_t delta, int64_t s, int6
                                tm_census *c, hipStream_t st) {
     DevBuf o;
     TM_TRY(o.alloc(64));
-    TM_HIP(hipMemsetAsync(o.p, 0, 40, st));
+    TM_TRY(zero_u64(o.as<uint64_t>(), 6, st));
     unsigned nb = g->m_nl > 0 ? tm_blocks(2 * g->m_nl, SW_TPB) : 1;
     if (nb > 8192) nb = 8192;
-    int64_t h[5];
+    int64_t h[6];
     if (L > 0) {
         if (g->m_nl > 0) {
             hipLaunchKernelGGL(k_census_est, dim3(nb), dim3(SW_TPB), 0, st, dev_view(g), delta, s, L, p, seed,
                                o.as<unsigned long long>());
             TM_HIP(hipGetLastError());
         }
-        TM_HIP(hipMemcpyAsync(h, o.p, 40, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipMemcpyAsync(h, o.p, 48, hipMemcpyDeviceToHost, st));
         TM_HIP(hipStreamSynchronize(st));
         c->anchors = c->tri_anchors = h[0];
         c->fwd_entries = c->tri_entries = h[1];
         c->bwd_entries = h[2];
         c->tri_lookups = h[3];
         c->tri_pairs = h[4];
+        c->tri_probes = h[5];
         return TM_OK;
     }
     if (g->m_nl > 0) {
@@ -618,13 +661,14 @@ tm_status tm_sweep_census_impl(const tm_graph *g, int64_t delta, int64_t s, int6
                            o.as<unsigned long long>());
         TM_HIP(hipGetLastError());
     }
-    TM_HIP(hipMemcpyAsync(h, o.p, 40, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipMemcpyAsync(h, o.p, 48, hipMemcpyDeviceToHost, st));
     TM_HIP(hipStreamSynchronize(st));
     c->fwd_entries = h[0];
     c->bwd_entries = h[1];
     c->tri_entries = h[2];
     c->tri_lookups = h[3];
     c->tri_pairs = h[4];
+    c->tri_probes = h[5];
     return TM_OK;
 }
 

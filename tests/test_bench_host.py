@@ -25,31 +25,69 @@ def test_code_only_drops_comments_keeps_literals(bench):
 
 
 CENSUS = {"anchors": 10, "fwd_entries": 100, "bwd_entries": 90, "tri_anchors": 5, "tri_entries": 50,
-          "tri_lookups": 20, "tri_pairs": 7}
+          "tri_lookups": 20, "tri_pairs": 7, "tri_probes": 33}
 
 
 def test_sweep_bytes_model(bench):
-    b = bench.sweep_bytes(CENSUS, [CENSUS, CENSUS], tables=False)
+    """16 B per anchor, 12 B per scanned entry (20 with the weight), 8 B per
+    probe; the tables of the exact 2-node/star counts do not change the
+    algorithmic bytes (the scans they replace)."""
+    b = bench.sweep_bytes(CENSUS, [CENSUS, CENSUS])
     assert b["sweep3_fwd_count"] == 16 * 10 + 12 * 100
     assert b["sweep3_bwd_count"] == 16 * 10 + 12 * 90
-    assert b["sweep3_tri_count"] == 16 * 5 + 12 * 50 + 48 * 20 + 96 * 7
-    assert b["sweep3_tri_weight"] == 2 * (16 * 5 + 20 * 50 + 24 * 20 + 72 * 7)
-    t = bench.sweep_bytes(CENSUS, [], tables=True)
-    assert t["sweep3_fwd_count"] == 344 * 10 and t["sweep3_bwd_count"] == 336 * 10
+    assert b["sweep3_tri_count"] == 16 * 5 + 12 * 50 + 8 * 33
+    assert b["sweep3_tri_weight"] == 2 * (16 * 5 + 20 * 50 + 8 * 33)
+    assert b["sweep3_fwd_weight"] == 2 * (16 * 10 + 20 * 100)
 
 
-def test_dominant_kernel_is_the_one_with_most_time_alone(bench):
+def test_dominant_kernel_and_counter_based_fraction(bench, monkeypatch):
     # in the timed (concurrent) steps the forward kernel looks longest, but
     # alone the triangle kernel takes the most time: it is the dominant one
     kern = {"sweep3_fwd_weight": (240.0, 4), "sweep3_tri_weight": (200.0, 4), "sweep3_tri_count": (140.0, 1)}
     alone = {"sweep3_fwd_weight": (70.0, 4), "sweep3_tri_weight": (190.0, 4), "sweep3_tri_count": (135.0, 1)}
     crit = {"sweep3_fwd_weight": (190.0, 3)}
-    r = bench.sweep_roofline(CENSUS, [CENSUS] * 4, kern, crit, alone, 1, tables=True)
+    # with a valid counter record, frac is its bytes per launch over the launch time
+    monkeypatch.setattr(bench, "traffic_record", lambda k: 4.0e9 if k == "sweep3_tri_weight" else None)
+    r = bench.sweep_roofline(CENSUS, [CENSUS] * 4, kern, crit, alone, 1)
     assert r["kernel"] == "sweep3_tri_weight"
     per = r["sweep_kernels"]["sweep3_tri_weight"]
     assert per["avg_launch_ms"] == pytest.approx(50.0)
-    assert r["achieved"] == pytest.approx(per["algorithmic_bytes_per_launch"] / 0.050 / 1e9)
+    assert r["traffic"] == 4.0e9
+    assert r["achieved"] == pytest.approx(4.0e9 / 0.050 / 1e9)
     assert r["frac"] == pytest.approx(r["achieved"] / 8000.0)
+    assert r["algorithmic"]["bytes_per_launch"] == pytest.approx(per["algorithmic_bytes_per_launch"])
+    assert r["algorithmic"]["GBs"] == pytest.approx(per["algorithmic_bytes_per_launch"] / 0.050 / 1e9)
+    # a stale record: traffic null, frac from the algorithmic bytes, and said so
+    monkeypatch.setattr(bench, "traffic_record", lambda k: None)
+    r = bench.sweep_roofline(CENSUS, [CENSUS] * 4, kern, crit, alone, 1)
+    assert r["traffic"] is None and "stale" in r["frac_basis"]
+    assert r["achieved"] == pytest.approx(per["algorithmic_bytes_per_launch"] / 0.050 / 1e9)
+
+
+def test_pmc_and_trace_summaries(bench, tmp_path, monkeypatch):
+    """The traffic record and the kernel-trace summary are computed from
+    rocprofv3's csv files: counters scaled by the copy calibration, the
+    sweep kernels' timed-step dispatches only."""
+    def write(folder, name, header, rows):
+        d = tmp_path / folder / "host" / "123"
+        d.mkdir(parents=True, exist_ok=True)
+        with open(d / f"run_{name}", "w") as f:
+            f.write(",".join(header) + "\n")
+            for r in rows:
+                f.write(",".join(str(x) for x in r) + "\n")
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    tri = '"void (anonymous namespace)::k_sweep3<1, true, 8u>(DevGraph, sweepdev::SweepArgs)"'
+    write("f", "counter_collection.csv", hdr, [[1, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 524288.0],
+                                              [2, tri, "FETCH_SIZE", 100.0], [3, tri, "FETCH_SIZE", 300.0]])
+    write("w", "counter_collection.csv", hdr, [[1, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 1048576.0],
+                                              [2, tri, "WRITE_SIZE", 10.0], [3, tri, "WRITE_SIZE", 30.0]])
+    monkeypatch.setattr(bench, "traffic_file", lambda k: str(tmp_path / f"{k}.json"))
+    bench.pmc_summary(str(tmp_path / "f"), str(tmp_path / "w"))
+    import json
+    rec = json.load(open(tmp_path / "sweep3_tri_weight.json"))
+    assert rec["dispatches_averaged"] == 2
+    assert rec["traffic_bytes_per_launch"] == pytest.approx((200.0 * 2 + 20.0) * 1024)
+    assert rec["kernel_src_sha256"] == bench.kernel_src_sha()
 
 
 def test_more_than_one_gpu_is_refused():

@@ -721,6 +721,83 @@ def test_batched_estimates_match_per_seed(tm):
         assert close(est[k], oracle.estimate(g.src, g.dst, g.t, ti.CYCLE4, delta, c, p, sd)["Z"])
 
 
+def test_mixed_queries_share_one_launch(tm):
+    """Queries with different motifs, deltas, c, p and seeds on one graph:
+    the three-edge ones run as estimators of one captured persistent launch,
+    the four-edge ones through the generic counter; every estimate and kept
+    count equals that query's single-call result to the last bit, and the
+    oracle's within 1e-12."""
+    rng = np.random.default_rng(17)
+    for g, deltas in ((ti.random_small_graph(7, 2500, 9000, 65, allow_self_loops=True), (20, 40, 90)),
+                      (ti.zipf_graph(1500, 30000, 1.8, 600_000, 66), (600, 3600))):
+        say("mixed", g.m)
+        G = load(tm, g)
+        qs = []
+        for _ in range(48):
+            M = THREE[int(rng.integers(0, len(THREE)))] if rng.random() < 0.9 else ti.CYCLE4
+            qs.append((M, int(rng.choice(deltas)), int(rng.choice([2, 3, 10, 30])), float(rng.choice([0.2, 0.5, 1.0])),
+                       int(rng.integers(0, 1 << 40))))
+        tm.profile_reset()
+        tm.profile_enable(True)
+        est, kept = tm.estimate_mixed(G, qs)
+        tm.profile_enable(False)
+        assert tm.profile_read("count_batch_mixed")[1] == 1
+        for (M, d, c, p, sd), z, k in zip(qs, est, kept):
+            if len(M) == 3:
+                z1, k1 = tm.estimate_multi(G, [M], d, c, p, sd)
+                assert z == z1[0] and k == k1[0], (M, d, c, p, sd)
+            else:
+                r = tm.estimate(G, M, d, c, p, sd, info=True)
+                assert z == r["Z"] and k == r["kept_count"]
+        for (M, d, c, p, sd), z in list(zip(qs, est))[:6]:
+            o = oracle.estimate(g.src, g.dst, g.t, M, d, c, p, sd)
+            assert close(z, o["Z"]), (M, d, c, p, sd, z, o["Z"])
+
+
+def test_batched_estimates_concurrent_same_plan(tm):
+    """Two host threads run tm_estimate_batch with the same key (graph,
+    motif, delta, c, p, seeds count, tile) on streams of their own, and a
+    third releases the cached plans meanwhile: every call returns its own
+    seeds' estimates, equal to the single-call ones."""
+    import threading
+    import torch
+    g = ti.random_small_graph(7, 3000, 20000, 64, allow_self_loops=True)
+    say("batch concurrent")
+    G = load(tm, g)
+    delta, c, p, M = 40, 3, 0.4, ti.TRIANGLE
+    sets = [np.arange(16, dtype=np.uint64) + 1000 * (k + 1) for k in range(6)]
+    want = [[tm.estimate(G, M, delta, c, p, int(sd)) for sd in S] for S in sets]
+    out = [None] * len(sets)
+    err = []
+
+    def run(k, st):
+        try:
+            with torch.cuda.stream(st):
+                for _ in range(3):
+                    e, _ = tm.estimate_batch(G, M, delta, c, p, sets[k], tile=64, stream=st)
+                    out[k] = list(e)
+        except Exception as x:  # reported below
+            err.append(x)
+
+    def release():
+        try:
+            for _ in range(5):
+                tm.batch_release(G)
+        except Exception as x:
+            err.append(x)
+
+    streams = [torch.cuda.Stream() for _ in sets]
+    th = [threading.Thread(target=run, args=(k, streams[k])) for k in range(len(sets))]
+    th.append(threading.Thread(target=release))
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    assert not err, err
+    for k in range(len(sets)):
+        assert out[k] == want[k], k
+
+
 def _lists(g):
     """Per-node combined lists in the device's order: time, then input
     position, then the source's entry first (self-loops left out)."""
@@ -734,14 +811,39 @@ def _lists(g):
     return x[order], y[order], t[order]
 
 
-def _scan_counts(tv, yv, a, end):
-    """Lookups and pair changes of anchor a over entries (a, end): entries
-    tied with the anchor's time and entries leading to its own node are left
-    out; a pair change is a lookup whose node differs from the previous one."""
+def _pair_sizes(g):
+    """Edges per unordered node pair (self-loops left out)."""
+    keep = g.src != g.dst
+    a = np.minimum(g.src[keep], g.dst[keep]).astype(np.int64)
+    b = np.maximum(g.src[keep], g.dst[keep]).astype(np.int64)
+    k, c = np.unique(a * (1 << 32) + b, return_counts=True)
+    return dict(zip(k.tolist(), c.tolist()))
+
+
+def _probes(n):
+    """Probes of one binary search over n sorted entries: ceil(log2(n + 1))."""
+    return int(n).bit_length()
+
+
+def _scan_counts(tv, yv, a, end, x, sizes, per_lookup, per_change):
+    """Lookups, pair changes and probes of anchor a (at node x) over entries
+    (a, end): entries tied with the anchor's time and entries leading to its
+    own node are left out; a pair change is a lookup whose node differs from
+    the previous one.  A lookup costs per_lookup searches of the pair {y1, yj}
+    and a change one probe plus per_change searches."""
     ys = yv[a + 1:end][(tv[a + 1:end] != tv[a]) & (yv[a + 1:end] != yv[a])]
     if not ys.size:
-        return 0, 0
-    return int(ys.size), 1 + int((ys[1:] != ys[:-1]).sum())
+        return 0, 0, 0
+    y1 = int(yv[a])
+    probes = 0
+    prev = None
+    for yj in ys.tolist():
+        n = sizes.get(min(y1, yj) * (1 << 32) + max(y1, yj), 0)
+        if yj != prev:
+            probes += 1 + per_change * _probes(n)
+        probes += per_lookup * _probes(n)
+        prev = yj
+    return int(ys.size), 1 + int((ys[1:] != ys[:-1]).sum()), probes
 
 
 def _census_numpy(g, delta):
@@ -752,6 +854,7 @@ def _census_numpy(g, delta):
     keeps the entries whose other endpoint has a longer list (ties: larger
     id); lookups and pair changes as in _scan_counts, over ranked entries."""
     x, y, t = _lists(g)
+    sizes = _pair_sizes(g)
     deg = np.bincount(x, minlength=g.n)
     fwd = bwd = 0
     for v in np.unique(x):
@@ -759,18 +862,19 @@ def _census_numpy(g, delta):
         fwd += int((np.searchsorted(tv, tv + delta, side="right") - np.arange(tv.size) - 1).sum())
         bwd += int((np.arange(tv.size) - np.searchsorted(tv, tv - delta, side="left")).sum())
     hi = (deg[y] > deg[x]) | ((deg[y] == deg[x]) & (y > x))
-    rf = lk = pc = 0
+    rf = lk = pc = pr = 0
     for v in np.unique(x[hi]):
         sel = (x == v) & hi
         tv, yv = t[sel], y[sel]
         ends = np.searchsorted(tv, tv + delta, side="right")
         rf += int((ends - np.arange(tv.size) - 1).sum())
         for a in range(tv.size):
-            l, c = _scan_counts(tv, yv, a, ends[a])
+            l, c, q = _scan_counts(tv, yv, a, ends[a], v, sizes, 2, 2)
             lk += l
             pc += c
+            pr += q
     return {"anchors": int(x.size), "fwd_entries": fwd, "bwd_entries": bwd, "tri_anchors": int(hi.sum()),
-            "tri_entries": rf, "tri_lookups": lk, "tri_pairs": pc}
+            "tri_entries": rf, "tri_lookups": lk, "tri_pairs": pc, "tri_probes": pr}
 
 
 def _census_est_numpy(g, delta, c, p, seed):
@@ -779,7 +883,8 @@ def _census_est_numpy(g, delta, c, p, seed):
     o = oracle.estimate(g.src, g.dst, g.t, ti.TRIANGLE, delta, c, p, seed)
     s, L, kept = int(o["s"]), int(o["L"]), set(int(j) for j in o["kept"])
     x, y, t = _lists(g)
-    an = fwd = bwd = lk = pc = 0
+    sizes = _pair_sizes(g)
+    an = fwd = bwd = lk = pc = pr = 0
     for v in np.unique(x):
         tv, yv = t[x == v], y[x == v]
         for a in range(tv.size):
@@ -792,11 +897,12 @@ def _census_est_numpy(g, delta, c, p, seed):
             beg = int(np.searchsorted(tv, max(int(tv[a]) - delta, wlo), side="left"))
             fwd += end - a - 1
             bwd += a - beg
-            l, cc = _scan_counts(tv, yv, a, end)
+            l, cc, q = _scan_counts(tv, yv, a, end, v, sizes, 1, 1)
             lk += l
             pc += cc
+            pr += q
     return {"anchors": an, "fwd_entries": fwd, "bwd_entries": bwd, "tri_anchors": an, "tri_entries": fwd,
-            "tri_lookups": lk, "tri_pairs": pc}
+            "tri_lookups": lk, "tri_pairs": pc, "tri_probes": pr}
 
 
 @pytest.mark.gpu

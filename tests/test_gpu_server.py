@@ -32,8 +32,8 @@ def make_queries(rng, n_graphs, k):
         if rng.random() < 0.3:
             qs.append(dict(graph=gi, edges=M, delta=delta, kind=0))
         else:
-            qs.append(dict(graph=gi, edges=M, delta=delta, kind=1, c=3, p=float(rng.choice([0.3, 1.0])),
-                           seed=int(rng.integers(0, 3))))
+            qs.append(dict(graph=gi, edges=M, delta=delta, kind=1, c=int(rng.choice([3, 10])),
+                           p=float(rng.choice([0.3, 1.0])), seed=int(rng.integers(0, 1 << 30))))
     return qs
 
 
@@ -84,14 +84,33 @@ def test_server_mix_invariance(tm):
 
 
 def test_server_budget(tm):
+    """Each batch is charged the device bytes its path allocates and
+    allocates no more (measured per slot thread); what the slots keep between
+    batches counts against the budget too, so with a budget of one batch's
+    charge the admitted and held workspace never exceeds it; a query whose
+    path alone needs more is completed with TM_EBUDGET."""
     g = ti.random_small_graph(6, 2000, 4000, 77)
     G = tm.load_graph(g.src, g.dst, g.t, g.n)
     say("server budget")
-    # 4 KiB: three-edge queries fit one at a time, the generic four-edge path does not
-    S = tm.Server(slots=3, budget_bytes=4096)
+    rng = np.random.default_rng(9)
+    qs = make_queries(rng, 1, 60)
+    S = tm.Server(slots=3, budget_bytes=1 << 30)
+    gid = S.add_graph(G)
+    res = [S.wait(S.submit(gid, q["edges"], q["delta"], q["kind"], q.get("c", 0), q.get("p", 0.0),
+                           q.get("seed", 0))) for q in qs]
+    # a batch that reuses a slot's grow-only workspaces allocates nothing new
+    assert all(r["status"] == 0 and 0 <= r["ws_measured"] <= r["ws_charged"] for r in res)
+    st = S.stats()
+    assert st["over_charge"] == 0 and 0 < st["measured_max_bytes"] <= st["peak_bytes"] <= 1 << 30
+    assert st["uncollected"] == 0
+    S.close()
+    # a budget of the largest three-edge charge: one such batch at a time; the
+    # four-edge estimate's path (kept-anchor lists of m words) does not fit
+    big = max(r["ws_charged"] for q, r in zip(qs, res) if len(q["edges"]) == 3)
+    S = tm.Server(slots=3, budget_bytes=big)
     gid = S.add_graph(G)
     tks = [S.submit(gid, ti.TRIANGLE, 30) for _ in range(6)]
-    tks.append(S.submit(gid, ti.CYCLE4, 30))
+    tks.append(S.submit(gid, ti.CYCLE4, 30, kind=1, c=3, p=0.5, seed=4))
     tks.append(S.submit(gid, ti.TWO_NODE_ALT, 30, kind=1, c=3, p=0.5, seed=4))
     res = [S.wait(t) for t in tks]
     want = tm.count_exact(G, ti.TRIANGLE, 30)
@@ -99,5 +118,5 @@ def test_server_budget(tm):
     assert res[6]["status"] == 4  # TM_EBUDGET
     assert res[7]["status"] == 0 and res[7]["estimate"] == tm.estimate(G, ti.TWO_NODE_ALT, 30, 3, 0.5, 4)
     st = S.stats()
-    assert st["peak_bytes"] <= 4096 and st["rejected"] == 1
+    assert st["peak_bytes"] <= big and st["rejected"] == 1 and st["over_charge"] == 0
     S.close()
