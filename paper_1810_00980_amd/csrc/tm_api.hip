@@ -229,6 +229,27 @@ __global__ void k_map_anchors(const int64_t *pos_of, const int64_t *anchor, int6
     }
 }
 
+// r[0] = first sorted edge with time >= lo, r[1] = first with time > hi
+__global__ void k_time_range(const int64_t *t, int64_t m, int64_t lo, int64_t hi, int64_t *r) {
+    if (blockIdx.x != 0 || threadIdx.x > 1) return;
+    const int64_t key = threadIdx.x == 0 ? lo : hi;
+    int64_t a = 0, b = m;
+    while (a < b) {
+        const int64_t mid = a + (b - a) / 2;
+        if (threadIdx.x == 0 ? t[mid] < key : t[mid] <= key) a = mid + 1;
+        else b = mid;
+    }
+    r[threadIdx.x] = a;
+}
+
+// anchors a0 .. a0 + n - 1 with window end hi
+__global__ void k_anchor_range(int64_t a0, int64_t n, int64_t hi, int64_t *pos, int64_t *wend) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    pos[k] = a0 + k;
+    wend[k] = hi;
+}
+
 tm_status check_graph_motif(const tm_graph *g, const tm_motif *M, int64_t delta, MotifPlan *P) {
     if (!g || !M || delta < 0) return TM_EINVAL;
     return tm_make_plan(M, P);
@@ -545,6 +566,27 @@ tm_status sweep_estimates(const tm_graph *g, int32_t n, const tm_motif *motifs, 
         }
     }
     return TM_OK;
+}
+
+// estimates of a four-edge star (tm_star4_shape) through its own counter:
+// Z = weight / 2^52 / p, and its exact count over the kept windows
+tm_status star_estimate(const tm_graph *g, const tm_motif *M, int64_t delta, int64_t c, double p, uint64_t seed,
+                        double *est, tm_u128 *kept, hipStream_t st) {
+    int64_t L;
+    TM_TRY(check_est_args(g, delta, c, p, &L));
+    uint64_t o[4];
+    TM_TRY(tm_star4_run(g, M, 1, delta, 1, host_shift(seed, L), L, seed, p, o, nullptr, st));
+    *est = u128_scaled(o[2], o[3], 1.0 / 4503599627370496.0) / p;
+    if (kept) {
+        kept->lo = o[0];
+        kept->hi = o[1];
+    }
+    return TM_OK;
+}
+
+bool is_star4(const tm_motif *M) {
+    uint32_t d[4];
+    return tm_star4_shape(M, d);
 }
 
 static void neumaier_add(double &sum, double &comp, double x) {
@@ -890,6 +932,13 @@ tm_status count_exact_impl(const tm_graph *g, const tm_motif *M, int64_t delta, 
         out->hi = so.v[4 * code + 1];
         return TM_OK;
     }
+    if (!hist_lo_host && is_star4(M)) {
+        uint64_t o[4];
+        TM_TRY(tm_star4_run(g, M, 0, delta, 0, 0, 1, 0, 1.0, o, nullptr, st));
+        out->lo = o[0];
+        out->hi = o[1];
+        return TM_OK;
+    }
     DevBuf acc, hist;
     TM_TRY(acc.alloc(64));
     TM_HIP(hipMemsetAsync(acc.p, 0, 64, st));
@@ -1027,6 +1076,11 @@ extern "C" tm_status tm_estimate(const tm_graph *g, const tm_motif *M, int64_t d
         TM_TRY(check_graph_motif(g, M, delta, &P));
         return finish(sweep_estimates(g, 1, M, delta, c, p, seed, estimate, nullptr, st), st);
     }
+    if (!info && g && M && estimate && is_star4(M)) {
+        MotifPlan P;
+        TM_TRY(check_graph_motif(g, M, delta, &P));
+        return finish(star_estimate(g, M, delta, c, p, seed, estimate, nullptr, st), st);
+    }
     return finish(estimate_impl(g, M, delta, c, p, seed, estimate, info, st), st);
 }
 
@@ -1060,6 +1114,12 @@ extern "C" tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, cons
         return finish(sweep_estimates(g, n_motifs, motifs, delta, c, p, seed, estimates, kept_counts, st), st);
     }
     for (int32_t i = 0; i < n_motifs; ++i) {
+        if (is_star4(&motifs[i])) {
+            hipStream_t st = (hipStream_t)hip_stream;
+            TM_TRY(finish(star_estimate(g, &motifs[i], delta, c, p, seed, &estimates[i],
+                                        kept_counts ? &kept_counts[i] : nullptr, st), st));
+            continue;
+        }
         tm_est_info info;
         memset(&info, 0, sizeof info);
         TM_TRY(tm_estimate(g, &motifs[i], delta, c, p, seed, &estimates[i], kept_counts ? &info : nullptr,
@@ -1224,9 +1284,16 @@ extern "C" tm_status tm_estimate_mixed(const tm_graph *g, int32_t n, const tm_es
         estimates[idx[(size_t)j]] = est[(size_t)j];
         if (kept_counts) kept_counts[idx[(size_t)j]] = kept[(size_t)j];
     }
-    // the others, one after another through the generic counter
+    // the others one after another: four-edge stars through their counter,
+    // the rest through the generic counter
     for (int32_t i = 0; i < n; ++i) {
         if (tm_sweep_code_of(&q[i].motif) >= 0) continue;
+        if (is_star4(&q[i].motif)) {
+            s = finish(star_estimate(g, &q[i].motif, q[i].delta, q[i].c, q[i].p, q[i].seed, &estimates[i],
+                                     kept_counts ? &kept_counts[i] : nullptr, st), st);
+            if (s != TM_OK) return s;
+            continue;
+        }
         tm_est_info info;
         memset(&info, 0, sizeof info);
         s = finish(estimate_impl(g, &q[i].motif, q[i].delta, q[i].c, q[i].p, q[i].seed, &estimates[i],
@@ -1291,27 +1358,41 @@ extern "C" tm_status tm_count_window(const tm_graph *g, int32_t n_motifs, const 
         };
         return finish(run(), st);
     }
-    // other motifs: generic counter over the window's anchors
+    // other motifs: generic counter over the window's anchors, the window's
+    // range of the sorted times found on the device
     auto run = [&]() -> tm_status {
-        int64_t m = g->m;
-        std::vector<int64_t> tt((size_t)(m > 0 ? m : 1));
-        if (m > 0) TM_HIP(hipMemcpyAsync(tt.data(), g->es_t.p, (size_t)m * 8, hipMemcpyDeviceToHost, st));
-        TM_HIP(hipStreamSynchronize(st));
-        int64_t a0 = std::lower_bound(tt.begin(), tt.begin() + m, lo) - tt.begin();
-        int64_t a1 = std::upper_bound(tt.begin(), tt.begin() + m, hi) - tt.begin();
-        int64_t nA = a1 - a0;
+        int64_t a[2] = {0, 0};
+        if (g->m > 0) {
+            DevBuf r;
+            TM_TRY(r.alloc(16));
+            hipLaunchKernelGGL(k_time_range, dim3(1), dim3(64), 0, st, g->es_t.as<int64_t>(), g->m, lo, hi,
+                               r.as<int64_t>());
+            TM_HIP(hipGetLastError());
+            TM_HIP(hipMemcpyAsync(a, r.p, 16, hipMemcpyDeviceToHost, st));
+            TM_HIP(hipStreamSynchronize(st));
+        }
+        const int64_t a0 = a[0], nA = a[1] > a[0] ? a[1] - a[0] : 0;
+        DevBuf ap, we;
+        if (nA > 0) {
+            TM_TRY(ap.alloc((size_t)nA * 8));
+            TM_TRY(we.alloc((size_t)nA * 8));
+            hipLaunchKernelGGL(k_anchor_range, dim3(tm_blocks(nA, TPB)), dim3(TPB), 0, st, a0, nA, hi,
+                               ap.as<int64_t>(), we.as<int64_t>());
+            TM_HIP(hipGetLastError());
+        }
         for (int32_t i = 0; i < n_motifs; ++i) {
             TM_TRY(tm_make_plan(&motifs[i], &P));
-            DevBuf acc, ap, we;
+            if (is_star4(&motifs[i])) {
+                uint64_t o[4];
+                TM_TRY(tm_star4_run(g, &motifs[i], 0, delta, 2, lo, hi, 0, 1.0, o, nullptr, st));
+                counts[i].lo = o[0];
+                counts[i].hi = o[1];
+                continue;
+            }
+            DevBuf acc;
             TM_TRY(acc.alloc(64));
             TM_HIP(hipMemsetAsync(acc.p, 0, 64, st));
             if (nA > 0) {
-                std::vector<int64_t> pos((size_t)nA), wend((size_t)nA, hi);
-                for (int64_t k = 0; k < nA; ++k) pos[(size_t)k] = a0 + k;
-                TM_TRY(ap.alloc((size_t)nA * 8));
-                TM_TRY(we.alloc((size_t)nA * 8));
-                TM_HIP(hipMemcpyAsync(ap.p, pos.data(), (size_t)nA * 8, hipMemcpyHostToDevice, st));
-                TM_HIP(hipMemcpyAsync(we.p, wend.data(), (size_t)nA * 8, hipMemcpyHostToDevice, st));
                 AnchorSet A{nA, ap.as<int64_t>(), we.as<int64_t>(), nullptr, nullptr};
                 TM_TRY(tm_count_generic(g, P, delta, A, acc.as<uint64_t>(), nullptr, nullptr, nullptr, nullptr, nullptr,
                                         st));

@@ -227,6 +227,10 @@ struct tm_graph {
     DevBuf ex_c0x;      // int64[2 m_nl + 1]: direction-0 entries before each list position (global)
     DevBuf ex_rows;     // uint64[2][ex_S][12]
 
+    // four-edge stars (tm_star4.hip): per incidence entry, the rank of its
+    // other endpoint among the owner's heaviest neighbours, built on first use
+    DevBuf s4_rank;   // uint8[2 m_nl]
+
     // reusable per-graph workspace for queries
     DevBuf ws;
     int64_t device_bytes = 0;
@@ -310,12 +314,14 @@ void tm_sweep_release_thread_ws();
 void tm_prims_release_thread_ws();
 void tm_generic_release_thread_ws();
 void tm_batch_release_thread_ws();
+void tm_star4_release_thread_ws();
 inline void tm_release_thread_ws() {
     tm_api_release_thread_ws();
     tm_sweep_release_thread_ws();
     tm_prims_release_thread_ws();
     tm_generic_release_thread_ws();
     tm_batch_release_thread_ws();
+    tm_star4_release_thread_ws();
     t_load_cache.clear();
 }
 int64_t tm_scan_ws_bytes(int64_t n);           // block sums of a scan of n values
@@ -468,3 +474,21 @@ void tm_batch_release_plans(const tm_graph *g);
 tm_status tm_batch_mixed(const tm_graph *g, int64_t n, const int32_t *code, const int64_t *delta, const int64_t *L,
                          const double *p, const uint64_t *seeds, double *est, tm_u128 *kept, hipStream_t st);
 int64_t tm_batch_mixed_bytes(const tm_graph *g, int64_t n, const int64_t *delta, const int64_t *L);
+
+// ------------------------------------------------------------ 4-edge stars
+
+// Whether M is a four-edge star whose first two edges join the center to
+// the same leaf, (x,a),(x,a),(x,b),(x,c) with a, b, c distinct; d[k] is the
+// direction of edge k at the center (0: it leaves the center, 1: it enters).
+bool tm_star4_shape(const tm_motif *M, uint32_t d[4]);
+// Its counts (mode 0), counts and 52-bit fixed-point weighted sums (mode 1,
+// window length L), or counts and the duration histogram (mode 2, hist_dev:
+// delta + 1 bins {lo, hi}, zeroed here); windowed 0: all anchors, 1: anchors
+// in windows kept by (s, L, seed, p), 2: every edge in [s, L].  out: count
+// lo/hi, weight lo/hi.
+tm_status tm_star4_run(const tm_graph *g, const tm_motif *M, int mode, int64_t delta, int windowed, int64_t s, int64_t L,
+                       uint64_t seed, double p, uint64_t out[4], uint64_t *hist_dev, hipStream_t st);
+// Device bytes of one query (workspace; the first query on a graph also
+// builds its ranks: tm_star4_build_bytes).
+int64_t tm_star4_bytes(const tm_graph *g, int64_t delta);
+int64_t tm_star4_build_bytes(const tm_graph *g);

@@ -76,6 +76,8 @@ int64_t batch_ws_bytes(const tm_graph *g, const std::vector<tm_query> &b) {
             }
             return bytes;
         }
+        uint32_t d[4];
+        if (tm_star4_shape(&q0.motif, d)) return tm_star4_bytes(g, 0) + tm_star4_build_bytes(g);
         // the generic counter over every edge
         return buf(64) + tm_generic_bytes(g->m, q0.motif.l);
     }
@@ -87,6 +89,8 @@ int64_t batch_ws_bytes(const tm_graph *g, const std::vector<tm_query> &b) {
         }
         return tm_batch_mixed_bytes(g, (int64_t)b.size(), delta.data(), L.data());
     }
+    uint32_t d[4];
+    if (tm_star4_shape(&q0.motif, d)) return tm_star4_bytes(g, q0.delta) + tm_star4_build_bytes(g);
     // the generic estimate with diagnostics: kept-anchor lists (the kept
     // anchors are at most m), the duration histogram, per-window totals, the
     // generic counter's items, the window list and the scan workspace

@@ -296,6 +296,38 @@ def test_bifan_zipf(tm):
         assert close(z, o["Z"]), (c, p, seed, z, o["Z"])
 
 
+STARS4 = [ti.STAR4, ((0, 1), (1, 0), (0, 2), (3, 0)), ((0, 1), (0, 1), (2, 1), (3, 1)), ((0, 1), (1, 0), (2, 1), (1, 3))]
+
+
+def test_star4_counter(tm):
+    """Four-edge stars whose first two edges share a leaf, through their own
+    counter (running sums over the center's list, the heaviest 32 leaves of a
+    node in LDS, the others from the pair timelines): exact counts,
+    seed-matched estimates and their kept counts, and windowed counts against
+    the oracle, on Zipf graphs whose hubs have hundreds of distinct leaves."""
+    for g, delta, wins in ((ti.zipf_graph(300, 4000, 1.5, 400_000, 61), 600, ((50_000, 150_000),)),
+                           (ti.zipf_graph(2000, 30000, 1.8, 200_000, 71), 300, ((20_000, 60_000),)),
+                           (ti.random_small_graph(6, 900, 3000, 74, allow_self_loops=True), 80, ((500, 2000),))):
+        say("star4", g.m, delta)
+        G = load(tm, g)
+        nl = g.src != g.dst
+        nbrs = np.unique(np.concatenate([g.src[nl] * g.n + g.dst[nl], g.dst[nl] * g.n + g.src[nl]]))
+        most = int(np.bincount(nbrs // g.n, minlength=g.n).max())  # distinct neighbours of the busiest node
+        for M in STARS4:
+            want, _ = oracle.count(g.src, g.dst, g.t, M, delta, hist=False)
+            assert tm.count_exact(G, M, delta) == want, (M, delta)
+            for (c, p, seed) in ((10, 0.5, 3), (3, 1.0, 1)):
+                o = oracle.estimate(g.src, g.dst, g.t, M, delta, c, p, seed)
+                z = tm.estimate(G, M, delta, c, p, seed)
+                assert close(z, o["Z"]), (M, c, p, seed, z, o["Z"])
+                zs, ks = tm.estimate_multi(G, [M, ti.TRIANGLE], delta, c, p, seed)
+                assert zs[0] == z and ks[0] == int(o["win_counts"].sum())
+            for (lo, hi) in wins:
+                wc = tm.count_window(G, [M], delta, lo, hi)[0]
+                assert wc == oracle.count(g.src, g.dst, g.t, M, delta, win=(lo, hi), hist=False)[0], (M, lo, hi)
+        assert most > 32 or g.n <= 32  # the Zipf hubs take the light-leaf path
+
+
 def test_estimate_stream_equals_in_memory(tm):
     """Streaming (kept windows in time order, one window's edges on the
     device at a time) gives the in-memory estimates and kept counts to the
