@@ -378,6 +378,89 @@ def run_bifan(args):
     }
 
 
+def run_four_edge(args):
+    """The four-edge workload at full size: 20M nodes, 500M edges, Zipf(2.0)
+    endpoints, bursty times over [0, 3e8) s, drawn on the device; the 4-star
+    (0,1),(0,1),(0,2),(0,3) (its own counter) at delta 86400, c 30,
+    p 0.05.  The star's exact count runs when the estimate predicts it fits
+    in the run (about 1/p of the estimate's time).  The 4-cycle
+    (0,1),(1,2),(2,3),(3,0) goes through the generic backtracking counter,
+    whose work on this graph (two-edge prefixes through the top node) is out
+    of reach, so it is timed on the same recipe with 1% of the edges over
+    the same span (200k nodes, 5M edges)."""
+    import torch
+    import paper_1810_00980_amd as tm
+    delta, c, p = 86400, 30, 0.05
+    out = {"metric": "temporal edges/s per motif query (4-star p=0.05 estimate)", "unit": "edges/s", "n_gpus": 1,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic"}
+    t0 = time.perf_counter()
+    sc = args.scale
+    n, m_want, t_hi = int(20_000_000 * sc), int(500_000_000 * sc), int(300_000_000 * sc)
+    if sc == 1.0:
+        src, dst, t = ti.config_star_cycle()
+    else:  # the same recipe and density on a fraction of the span (calibration)
+        src, dst, t = ti.zipf_graph_device(n, m_want, 2.0, t_hi, 3)
+    torch.cuda.synchronize()
+    m = int(src.numel())
+    log("generated", m, "edges", f"{time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    G = tm.load_graph(src, dst, t, n, exact_tables=False)
+    torch.cuda.synchronize()
+    t_load = time.perf_counter() - t0
+    log("loaded", f"{t_load:.1f}s", "device GB", G.device_bytes / 1e9)
+    del src, dst, t
+    torch.cuda.empty_cache()
+    star = ti.STAR4
+    runs = []
+    for seed in range(args.steps + 1):
+        t0 = time.perf_counter()
+        z = tm.estimate(G, star, delta, c, p, seed)
+        dt = time.perf_counter() - t0
+        runs.append({"seed": seed, "estimate": z, "s": dt})
+        log("star estimate seed", seed, f"{dt:.2f}s", f"{z:.4e}")
+    timed = runs[1:] if len(runs) > 1 else runs
+    dt = float(np.mean([r["s"] for r in timed]))
+    out.update({"value": m / dt, "steps": len(timed), "warmup": 1, "ms_per_step": dt * 1e3,
+                "config": {"workload": f"{n / 1e6:g}M nodes, {m / 1e6:g}M edges, Zipf(2.0) endpoints, bursty times "
+                                       f"over [0,{t_hi:.0e}) s (drawn on the device); 4-star (0,1),(0,1),(0,2),(0,3), "
+                                       "delta 86400, c 30, p 0.05", "m": m, "n": n, "scale": sc},
+                "load_s": t_load, "graph_device_bytes": G.device_bytes, "star_estimates": runs})
+    pred = dt / p * 1.2
+    if pred < args.max_exact_s:
+        t0 = time.perf_counter()
+        exact = tm.count_exact(G, star, delta)
+        te = time.perf_counter() - t0
+        out["star_exact"] = {"count": str(exact), "s": te, "edges_per_s": m / te,
+                             "mean_estimate_rel_error": (float(np.mean([r["estimate"] for r in runs])) - exact) / exact
+                             if exact else None}
+        log("star exact", exact, f"{te:.1f}s")
+    else:
+        out["star_exact"] = {"skipped": f"predicted {pred:.0f} s (1.2 x estimate time / p) > {args.max_exact_s} s"}
+    G.free()
+    torch.cuda.empty_cache()
+    if args.no_cycle:
+        return out
+    # the 4-cycle on the same recipe with 1% of the edges
+    src, dst, t = ti.zipf_graph_device(200_000, 5_000_000, 2.0, 300_000_000, 5)
+    Gs = tm.load_graph(src, dst, t, 200_000)
+    del src, dst, t
+    small = {"workload": "200k nodes, 5M edges, Zipf(2.0), bursty times over [0,3e8) s (graph seed 5)"}
+    for M, name in ((ti.CYCLE4, "cycle4"), (star, "star4")):
+        tm.estimate(Gs, M, delta, c, p, 0)
+        t0 = time.perf_counter()
+        z = tm.estimate(Gs, M, delta, c, p, 1)
+        dz = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ex = tm.count_exact(Gs, M, delta)
+        de = time.perf_counter() - t0
+        small[name] = {"estimate_s": dz, "estimate": z, "exact_s": de, "exact": str(ex),
+                       "estimate_edges_per_s": 5_000_000 / dz, "exact_edges_per_s": 5_000_000 / de}
+        log(name, "5M-edge variant", f"estimate {dz:.2f}s exact {de:.2f}s", ex)
+    Gs.free()
+    out["one_percent_variant"] = small
+    return out
+
+
 def run_serve(args):
     """Poisson streams of count/estimate queries over 6 resident graphs of
     1e4 .. 7.2e6 edges at several arrival rates, served by the
@@ -748,7 +831,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="zipf10m", choices=sorted(WORKLOADS) + ["batch50m", "serve", "perf23", "bifan"])
+    ap.add_argument("--workload", default="zipf10m",
+                    choices=sorted(WORKLOADS) + ["batch50m", "serve", "perf23", "bifan", "zipf500m_star_cycle"])
+    ap.add_argument("--max-exact-s", type=float, default=120.0,
+                    help="zipf500m_star_cycle: run the star's exact count when predicted below this")
+    ap.add_argument("--no-cycle", action="store_true",
+                    help="zipf500m_star_cycle: leave out the 4-cycle on the 1%% variant")
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="zipf500m_star_cycle: fraction of the nodes, edges and time span (same density)")
     ap.add_argument("--qps-list", type=float, nargs="+", default=[50.0, 400.0], help="serve: arrival rates")
     ap.add_argument("--queries", type=int, default=400, help="serve: queries per arrival rate")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
@@ -781,8 +871,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    if args.workload in ("batch50m", "serve", "perf23", "bifan"):
-        out = {"batch50m": run_batch, "serve": run_serve, "perf23": run_perf23, "bifan": run_bifan}[args.workload](args)
+    if args.workload in ("batch50m", "serve", "perf23", "bifan", "zipf500m_star_cycle"):
+        out = {"batch50m": run_batch, "serve": run_serve, "perf23": run_perf23, "bifan": run_bifan,
+               "zipf500m_star_cycle": run_four_edge}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     W = WORKLOADS[args.workload]

@@ -86,6 +86,8 @@ def _load():
         lib.orc_estimate3_indexed.argtypes = [i64, P, P, P, i32, P, P, i64, i64, f64, u64, P, P, P, P, i64, P, P,
                                               i32]
         lib.orc_estimate3_indexed.restype = i32
+        lib.orc_star4_indexed.argtypes = [i64, P, P, P, P, i64, i64, i64, P, P, i32]
+        lib.orc_star4_indexed.restype = i32
         _lib = lib
     return _lib
 
@@ -266,6 +268,46 @@ def estimate3_indexed(src, dst, t, motifs, delta, c, p, seed, threads=0, kept_ca
     return {"s": s.value, "J": J.value, "n_kept": nk.value, "kept": kept[:n].copy(),
             "kept_counts": [(int(kt[2 * i + 1]) << 64) | int(kt[2 * i]) for i in range(k)],
             "Z": [float(x) for x in z], "L": int(c) * int(delta)}
+
+
+def star4_directions(motif):
+    """(d0, d1, d2, d3) of a four-edge star (x,a),(x,a),(x,b),(x,c) with a, b,
+    c distinct (d_k = 0 when the center is edge k's source), or None."""
+    if len(motif) != 4:
+        return None
+    for x in (0, 1):
+        d, leaf = [], []
+        for (u, v) in motif:
+            if u == x:
+                d.append(0)
+                leaf.append(v)
+            elif v == x:
+                d.append(1)
+                leaf.append(u)
+            else:
+                break
+        else:
+            if leaf[0] == leaf[1] and len({leaf[0], leaf[2], leaf[3]}) == 3:
+                return tuple(d)
+    return None
+
+
+def star4_indexed(src, dst, t, motif, delta, win=None, threads=0):
+    """Tier C for four-edge stars (x,a),(x,a),(x,b),(x,c): exact count from
+    every (first, second, third) edge with the fourth edges counted by range
+    counts.  win=(lo, hi) restricts every edge to times in [lo, hi]."""
+    lib = _load()
+    d = star4_directions(motif)
+    if d is None:
+        raise OracleError("not a four-edge star of that shape")
+    src, dst, t = _edges(src, dst, t)
+    dd = np.ascontiguousarray(d, dtype=np.uint32)
+    lo, hi = win if win is not None else (INT64_MIN, INT64_MAX)
+    tl, th = ctypes.c_uint64(), ctypes.c_uint64()
+    rc = lib.orc_star4_indexed(src.shape[0], _ptr(src), _ptr(dst), _ptr(t), _ptr(dd), int(delta), int(lo), int(hi),
+                               ctypes.byref(tl), ctypes.byref(th), int(threads))
+    _check(rc)
+    return (th.value << 64) | tl.value
 
 
 # ---------------------------------------------------------------- tier B

@@ -590,3 +590,75 @@ int orc_estimate3_indexed(int64_t m, const int32_t *src, const int32_t *dst, con
     free(tn); free(h); free(hw); free(tw);
     return rc;
 }
+
+/* ---------------------------------------------------- tier C, 4-edge stars */
+
+/* edges of the center's list per direction: out (0) or in (1) */
+static const lists_t *dir_lists(const cgraph_t *G, uint32_t d) { return d == 0 ? &G->out : &G->in; }
+
+/* edges between x and y with direction d at x (0: x -> y, 1: y -> x) in (lo, hi) */
+static int64_t pair_dir_between(const cgraph_t *G, int64_t x, int64_t y, uint32_t d, int64_t lo, int64_t hi) {
+    return d == 0 ? pair_between(G, x, y, lo, hi) : pair_between(G, y, x, lo, hi);
+}
+
+/*
+ * Exact count of a four-edge star whose first two edges join the center to
+ * the same leaf: edges (x, a), (x, a), (x, b), (x, c), a, b, c distinct, the
+ * direction of edge k at the center x given by d[k] (0: x is its source),
+ * among edges with times in [win_lo, win_hi] (Sec. 2, Definition "motif
+ * delta-instance").  For every first edge e1 (center x, leaf a, time t1),
+ * every second edge e2 on x's pair with a after t1, and every third edge e3
+ * of x's list to a leaf b other than a after t2, the fourth edges are the
+ * edges of x's list with direction d[3] and time in (t3, min(t1 + delta,
+ * win_hi)], less those to a and those to b: three range counts.  Both
+ * possible centers of the first edge are tried, as the motif's direction
+ * d[0] picks one.  nthreads <= 0: all available.
+ */
+int orc_star4_indexed(int64_t m, const int32_t *src, const int32_t *dst, const int64_t *t, const uint32_t *d,
+                      int64_t delta, int64_t win_lo, int64_t win_hi, uint64_t *total_lo, uint64_t *total_hi,
+                      int nthreads) {
+    if (m < 0 || delta < 0) return ORC_EINVAL;
+    for (int k = 0; k < 4; ++k)
+        if (d[k] > 1) return ORC_EINVAL;
+    cgraph_t G;
+    int rc = cgraph_build(&G, m, src, dst, t);
+    if (rc != ORC_OK) return rc;
+    u128 tot = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#else
+    nthreads = 1;
+#endif
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads) reduction(+ : tot)
+    for (int64_t e1 = 0; e1 < m; ++e1) {
+        if (src[e1] == dst[e1] || t[e1] < win_lo || t[e1] > win_hi) continue;
+        const int64_t t1 = t[e1];
+        const int64_t x = d[0] == 0 ? src[e1] : dst[e1], a = d[0] == 0 ? dst[e1] : src[e1];
+        int64_t hi = t1 > INT64_MAX - delta ? INT64_MAX : t1 + delta;
+        if (hi > win_hi) hi = win_hi;
+        const int64_t b0 = G.inc.off[x], b1 = G.inc.off[x + 1];
+        /* second edges: x's list entries on the pair {x, a} with direction d[1] */
+        for (int64_t q2 = b0 + upper(G.inc.t + b0, b1 - b0, t1); q2 < b1 && G.inc.t[q2] <= hi; ++q2) {
+            const int64_t e2 = G.inc_e[q2];
+            const int64_t x2 = d[1] == 0 ? src[e2] : dst[e2], y2 = d[1] == 0 ? dst[e2] : src[e2];
+            if (x2 != x || y2 != a) continue;
+            const int64_t t2 = t[e2];
+            for (int64_t q3 = b0 + upper(G.inc.t + b0, b1 - b0, t2); q3 < b1 && G.inc.t[q3] <= hi; ++q3) {
+                const int64_t e3 = G.inc_e[q3];
+                const int64_t x3 = d[2] == 0 ? src[e3] : dst[e3], b = d[2] == 0 ? dst[e3] : src[e3];
+                if (x3 != x || b == a) continue;
+                const int64_t t3 = t[e3];
+                /* fourth edges in (t3, hi]: times strictly between t3 and hi + 1 */
+                const int64_t hi1 = hi == INT64_MAX ? INT64_MAX : hi + 1;
+                int64_t n4 = list_between(dir_lists(&G, d[3]), x, t3, hi1);
+                n4 -= pair_dir_between(&G, x, a, d[3], t3, hi1);
+                n4 -= pair_dir_between(&G, x, b, d[3], t3, hi1);
+                tot += (u128)n4;
+            }
+        }
+    }
+    cgraph_free(&G);
+    *total_lo = (uint64_t)tot;
+    *total_hi = (uint64_t)(tot >> 64);
+    return ORC_OK;
+}

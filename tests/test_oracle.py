@@ -619,3 +619,34 @@ def test_tier_c_estimate_equals_brute_force_estimate():
             assert r["s"] == o["s"] and r["J"] == o["J"] and list(r["kept"]) == list(o["kept"])
             assert r["kept_counts"][k] == int(o["win_counts"].sum()), M
             assert r["Z"][k] == o["Z"], (M, r["Z"][k], o["Z"])
+
+
+STARS4 = [ti.STAR4, ((0, 1), (1, 0), (0, 2), (3, 0)), ((0, 1), (0, 1), (2, 1), (3, 1)), ((0, 1), (1, 0), (2, 1), (1, 3))]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_tier_c_stars_equal_tier_a(seed):
+    """Tier C's four-edge stars (first three edges enumerated, the fourth by
+    range counts) equal the brute force, whole graph and windowed, on graphs
+    with ties, repeated pairs and self-loops."""
+    g = ti.random_small_graph(5 + seed % 4, 160 + 10 * seed, 220, 900 + seed, allow_self_loops=(seed % 2 == 0))
+    for M in STARS4:
+        assert oracle.star4_directions(M) is not None
+        for delta in (0, 12, 70, 1000):
+            assert oracle.star4_indexed(g.src, g.dst, g.t, M, delta, threads=2) == \
+                oracle.count(g.src, g.dst, g.t, M, delta, hist=False)[0], (M, delta)
+        assert oracle.star4_indexed(g.src, g.dst, g.t, M, 40, win=(30, 160)) == \
+            oracle.count(g.src, g.dst, g.t, M, 40, win=(30, 160), hist=False)[0], M
+
+
+def test_tier_c_star_closed_form():
+    """A center with n1 edges to leaf a at time 1, n2 more to a at time 2,
+    n3 edges to each of k3 leaves at time 3 and n4 to each of k4 others at
+    time 4: n1 n2 (n3 k3) (n4 k4) out-stars (0,1),(0,1),(0,2),(0,3)."""
+    n1, n2, n3, k3, n4, k4 = 3, 4, 2, 3, 5, 2
+    e = [(0, 1, 1)] * n1 + [(0, 1, 2)] * n2
+    e += [(0, 2 + j, 3) for j in range(k3) for _ in range(n3)]
+    e += [(0, 2 + k3 + j, 4) for j in range(k4) for _ in range(n4)]
+    s, d, tt = arr(e)
+    want = n1 * n2 * (n3 * k3) * (n4 * k4)
+    assert oracle.star4_indexed(s, d, tt, ti.STAR4, 10) == want == oracle.count(s, d, tt, ti.STAR4, 10)[0]

@@ -125,6 +125,66 @@ def zipf_graph(n: int, m: int, alpha: float, t_hi: int, seed: int, sigma: float 
     return Graph(src.astype(np.int32), dst.astype(np.int32), t, n)
 
 
+def zipf_graph_device(n: int, m: int, alpha: float, t_hi: int, seed: int, sigma: float = 1.5, phi: float = 0.95,
+                      device: str = "cuda", chunk: int = 1 << 26):
+    """The recipe of zipf_graph drawn on the GPU with torch's generator (for
+    graphs of hundreds of millions of edges): returns device tensors src,
+    dst (int32) and t (int64).  Endpoints: Zipf(alpha) ranks by inverse CDF
+    through a seeded permutation of the ids, dst redrawn until it differs
+    from src.  Times: the hourly rates of bursty_times (daily sinusoid times
+    a log-normal AR(1) factor, drawn on the host from the same seed), each
+    edge's hour drawn from them independently (the multinomial counts of
+    bursty_times, without conditioning on m) and its offset uniform in the
+    hour.  Edges come out in draw order, not time order."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    r = torch.arange(1, n + 1, dtype=torch.float64, device=device)
+    cdf = torch.cumsum(r.pow(-alpha), 0)
+    cdf /= cdf[-1].clone()
+    del r
+    perm = torch.randperm(n, generator=gen, device=device).to(torch.int32)
+
+    def ids(size):
+        out = torch.empty(size, dtype=torch.int32, device=device)
+        for a in range(0, size, chunk):
+            b = min(size, a + chunk)
+            u = torch.rand(b - a, dtype=torch.float64, generator=gen, device=device)
+            k = torch.searchsorted(cdf, u, right=True).clamp_(max=n - 1)
+            out[a:b] = perm[k]
+        return out
+
+    src = ids(m)
+    dst = ids(m)
+    while True:
+        bad = torch.nonzero(dst == src).flatten()
+        if bad.numel() == 0:
+            break
+        dst[bad] = ids(bad.numel())
+    # hourly rates from the host generator of the same seed
+    rng = _rng(seed)
+    nb = (t_hi + HOUR - 1) // HOUR
+    g = np.empty(nb)
+    eps = rng.standard_normal(nb)
+    g[0] = eps[0]
+    c = np.sqrt(1.0 - phi * phi)
+    for b in range(1, nb):
+        g[b] = phi * g[b - 1] + c * eps[b]
+    b_idx = np.arange(nb)
+    width = np.minimum(HOUR, t_hi - b_idx * HOUR)
+    lam = (1.0 + 0.5 * np.sin(2.0 * np.pi * b_idx / 24.0)) * np.exp(sigma * g - 0.5 * sigma * sigma) * (width / HOUR)
+    bcdf = torch.from_numpy(np.cumsum(lam) / lam.sum()).to(device)
+    wid = torch.from_numpy(width).to(device)
+    t = torch.empty(m, dtype=torch.int64, device=device)
+    for a in range(0, m, chunk):
+        b = min(m, a + chunk)
+        u = torch.rand(b - a, dtype=torch.float64, generator=gen, device=device)
+        k = torch.searchsorted(bcdf, u, right=True).clamp_(max=nb - 1)
+        off = (torch.rand(b - a, dtype=torch.float64, generator=gen, device=device) * wid[k]).to(torch.int64)
+        t[a:b] = k * HOUR + off
+    return src, dst, t
+
+
 def random_small_graph(n: int, m: int, t_span: int, seed: int, allow_self_loops: bool = False) -> Graph:
     """Tiny dense graphs with many repeated pairs and tied times (property tests)."""
     rng = _rng(seed)
@@ -163,6 +223,12 @@ def config_batch50m(seed: int = 4) -> Graph:
 
 def config_zipf(m: int, n: int, alpha: float, t_hi: int, seed: int, **kw) -> Graph:
     return zipf_graph(n, m, alpha, t_hi, seed, **kw)
+
+
+def config_star_cycle(device: str = "cuda"):
+    """The four-edge workload: 20M nodes, 500M edges, Zipf(2.0) endpoints,
+    bursty times over [0, 3e8) s (graph seed 3), drawn on the device."""
+    return zipf_graph_device(20_000_000, 500_000_000, 2.0, 300_000_000, 3, device=device)
 
 
 def serving_graph(i: int) -> Graph:
