@@ -87,7 +87,7 @@ def _host_cpu_model():
     return "unknown"
 
 
-def cpu_baseline(g, motifs, delta, frac=0.05):
+def cpu_baseline(g, motifs, delta, frac=0.03):
     """The oracle's indexed tier (every first/last edge pair sharing a node
     within delta, middles by range counts; OpenMP over anchors) timed on the
     host cores, single-threaded and with every core, on a bounded sample of
@@ -217,19 +217,20 @@ def run_batch(args):
     }
 
 
-def serving_queries(rng, graphs, n, qps):
-    """Poisson arrivals; 25% exact / 75% estimate; motif uniform over the 36
-    three-edge motifs and the 4-cycle, delta in {600, 3600, 86400}, p in
-    {0.01, 0.1, 1}, c 30, seed from a pool of 4.  The 4-cycle (with delta at
-    most 3600) and delta 86400 are drawn only on graphs of at most 4e4 edges:
-    on the larger serving graphs, whose times are packed into 1e6 s, those
-    queries cost seconds to minutes each."""
+def serving_queries(rng, sizes, n, qps):
+    """Poisson arrivals at rate qps over graphs of the given edge counts;
+    graph uniform; 25% exact / 75% estimate; motif uniform over the 36
+    three-edge motifs and the 4-cycle; delta in {600, 3600, 86400}; p in
+    {0.01, 0.1, 1}; c 30; a fresh 62-bit seed per request.  The 4-cycle (with
+    delta at most 3600) and delta 86400 are drawn only on graphs of at most
+    4e4 edges: on the larger graphs those queries cost seconds to minutes
+    each."""
     motifs = THREE + [ti.CYCLE4]
     qs, t = [], 0.0
     for _ in range(n):
         t += rng.exponential(1.0 / qps)
-        gi = int(rng.integers(0, len(graphs)))
-        small = graphs[gi].m <= 40_000
+        gi = int(rng.integers(0, len(sizes)))
+        small = sizes[gi] <= 40_000
         M = motifs[int(rng.integers(0, len(motifs) - (0 if small else 1)))]
         deltas = [600, 3600, 86400] if (small and M != ti.CYCLE4) else [600, 3600]
         delta = int(rng.choice(deltas))
@@ -237,28 +238,41 @@ def serving_queries(rng, graphs, n, qps):
             qs.append(dict(at=t, graph=gi, edges=M, delta=delta, kind=0))
         else:
             qs.append(dict(at=t, graph=gi, edges=M, delta=delta, kind=1, c=30, p=float(rng.choice([0.01, 0.1, 1.0])),
-                           seed=int(rng.integers(0, 4))))
+                           seed=int(rng.integers(0, 1 << 62))))
     return qs
 
 
-def serve_once(tm, Gs, graphs, qs, slots, budget):
-    """Submit qs at their arrival times to a server; returns its statistics."""
+def _pct(a, f):
+    """The f-quantile of a sorted array by the nearest-rank rule."""
+    return float(a[max(0, int(np.ceil(f * len(a))) - 1)]) if len(a) else float("nan")
+
+
+def serve_once(tm, Gs, sizes, qs, slots, budget):
+    """Submit qs at their arrival times to a server; returns its statistics
+    and the results in submission order."""
     S = tm.Server(slots=slots, budget_bytes=budget)
     ids = [S.add_graph(G) for G in Gs]
     tickets, t0 = [], time.perf_counter()
-    for q in qs:
+    for qi, q in enumerate(qs):
         now = time.perf_counter() - t0
         if now < q["at"]:
             time.sleep(q["at"] - now)
         tickets.append(S.submit(ids[q["graph"]], q["edges"], q["delta"], q["kind"], q.get("c", 0),
                                 q.get("p", 0.0), q.get("seed", 0)))
+        if qi % 250 == 249:
+            log("  submitted", qi + 1, f"{time.perf_counter() - t0:.1f}s")
     res = [S.wait(tk) for tk in tickets]
     st = S.stats()
     S.close()
+    lat = np.sort(np.array([r["latency_ms"] for r in res]))
+    big = np.sort(np.array([r["latency_ms"] for r, q in zip(res, qs) if sizes[q["graph"]] >= 10_000_000]))
     return {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "wall_s": st["wall_s"],
             "edges_per_s": st["edges_per_s"], "batches": st["batches"], "queries": st["completed"],
             "rejected": st["rejected"], "peak_workspace_bytes": st["peak_bytes"],
-            "max_batch": max(r["batch_size"] for r in res)}, res
+            "measured_max_bytes": st["measured_max_bytes"], "over_charge": st["over_charge"],
+            "max_batch": max(r["batch_size"] for r in res),
+            "p50_ms_check": _pct(lat, 0.5), "p99_ms_check": _pct(lat, 0.99),
+            "p99_ms_graphs_from_1e7": _pct(big, 0.99)}, res
 
 
 # The paper's timings for the 2-node motif (0,1),(1,0),(0,1) at delta 86400
@@ -462,18 +476,23 @@ def run_four_edge(args):
 
 
 def run_serve(args):
-    """Poisson streams of count/estimate queries over 6 resident graphs of
-    1e4 .. 7.2e6 edges at several arrival rates, served by the
-    continuous-batching server (4 slots, 4 GiB budget) and, for comparison,
-    one query at a time on the GPU in arrival order."""
+    """Poisson streams of count/estimate queries over the 8 resident graphs of
+    1e4 .. 1e8 edges at several arrival rates, served by the
+    continuous-batching server (4 slots, a device-memory budget on the
+    workspace it measures) and, for comparison, one query at a time on the
+    GPU in arrival order.  The value is the server's throughput at the
+    highest rate whose p99 latency meets the stated target."""
     import torch
     import paper_1810_00980_amd as tm
-    graphs = [ti.serving_graph(i) for i in range(6)]
-    Gs = []
-    for g in graphs:
-        s, d, t = (torch.from_numpy(a).cuda() for a in (g.src, g.dst, g.t))
-        Gs.append(tm.load_graph(s, d, t, g.n))
-    log("graphs", [g.m for g in graphs])
+    Gs, sizes = [], []
+    for i in range(8):
+        s_, d_, t_, n = ti.serving_graph_device(i)
+        Gs.append(tm.load_graph(s_, d_, t_, n))
+        sizes.append(int(s_.numel()))
+        del s_, d_, t_
+    torch.cuda.empty_cache()
+    log("graphs", sizes, "device GB", sum(G.device_bytes for G in Gs) / 1e9)
+    slots, budget = 4, args.serve_budget_gib << 30
 
     def direct(q):
         G = Gs[q["graph"]]
@@ -481,47 +500,57 @@ def run_serve(args):
             return tm.count_exact(G, q["edges"], q["delta"])
         return tm.estimate(G, q["edges"], q["delta"], q["c"], q["p"], q["seed"], info=(q["edges"] == ti.CYCLE4))
 
-    warm = serving_queries(np.random.default_rng(1), graphs, 40, 1000.0)
+    warm = serving_queries(np.random.default_rng(1), sizes, 60, 1000.0)
     for q in warm:
         direct(q)
-    serve_once(tm, Gs, graphs, warm, 4, 4 << 30)
+    serve_once(tm, Gs, sizes, warm, slots, budget)
     torch.cuda.synchronize()
+    log("warm")
     sweeps = []
     for qps in args.qps_list:
-        qs = serving_queries(np.random.default_rng(2024), graphs, args.queries, qps)
-        edges = sum(graphs[q["graph"]].m for q in qs)
+        qs = serving_queries(np.random.default_rng(2024), sizes, args.queries, qps)
+        edges = sum(sizes[q["graph"]] for q in qs)
+        log("qps", qps, "server")
+        srv, res = serve_once(tm, Gs, sizes, qs, slots, budget)
         log("qps", qps, "one at a time")
-        lat, t0 = [], time.perf_counter()
+        lat, mismatched, t0 = [], 0, time.perf_counter()
         for qi, q in enumerate(qs):
             now = time.perf_counter() - t0
             if now < q["at"]:
                 time.sleep(q["at"] - now)
-            direct(q)
+            r = direct(q)
             lat.append(time.perf_counter() - t0 - q["at"])
-            if qi % 100 == 99:
+            got = res[qi]["count"] if q["kind"] == 0 else res[qi]["estimate"]
+            want = r if q["kind"] == 0 else (r["Z"] if isinstance(r, dict) else r)
+            mismatched += int(got != want if q["kind"] == 0 else abs(got - want) > 1e-12 * abs(want))
+            if qi % 250 == 249:
                 log("  done", qi + 1, f"{time.perf_counter() - t0:.1f}s")
         seq_wall = time.perf_counter() - t0
-        log("qps", qps, "server")
-        srv, res = serve_once(tm, Gs, graphs, qs, 4, 4 << 30)
         lat_ms = np.sort(np.array(lat) * 1e3)
-        pct = lambda a, f: float(a[max(0, int(np.ceil(f * len(a))) - 1)])
-        sweeps.append({"qps": qps, "queries": len(qs), "server": srv,
-                       "one_at_a_time": {"p50_ms": pct(lat_ms, 0.5), "p99_ms": pct(lat_ms, 0.99),
-                                         "wall_s": seq_wall, "edges_per_s": edges / seq_wall}})
-        log("qps", qps, "server edges/s", f"{srv['edges_per_s']:.3e}", "p99", f"{srv['p99_ms']:.1f}",
-            "| one at a time", f"{edges / seq_wall:.3e}", "p99", f"{pct(lat_ms, 0.99):.1f}")
-    top = sweeps[-1]
+        one = {"p50_ms": _pct(lat_ms, 0.5), "p99_ms": _pct(lat_ms, 0.99), "wall_s": seq_wall,
+               "edges_per_s": edges / seq_wall}
+        sweeps.append({"qps": qps, "queries": len(qs), "server": srv, "one_at_a_time": one,
+                       "results_differing_from_one_at_a_time": mismatched,
+                       "server_meets_p99_target": srv["p99_ms"] <= args.p99_target_ms,
+                       "one_at_a_time_meets_p99_target": one["p99_ms"] <= args.p99_target_ms})
+        log("qps", qps, "server edges/s", f"{srv['edges_per_s']:.3e}", "p50", f"{srv['p50_ms']:.1f}", "p99",
+            f"{srv['p99_ms']:.1f}", "| one at a time", f"{one['edges_per_s']:.3e}", "p50", f"{one['p50_ms']:.1f}",
+            "p99", f"{one['p99_ms']:.1f}")
+    ok = [sw for sw in sweeps if sw["server_meets_p99_target"]]
+    top = max(ok, key=lambda sw: sw["qps"]) if ok else sweeps[0]
     out = {
         "metric": "temporal edges/s per motif query (served stream); p50/p99 latency",
         "value": top["server"]["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": top["server"]["wall_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-        "config": {"workload": f"{args.queries} Poisson queries per arrival rate over 6 graphs of 1e4..7.2e6 edges "
-                               "(Zipf 1.8, bursty); 25% exact / 75% estimate; motif uniform over 36 three-edge "
+        "config": {"workload": f"{args.queries} Poisson queries per arrival rate over 8 graphs of 1e4..1e8 edges "
+                               "(log-spaced, 100 edges per node, Zipf 1.8 endpoints, bursty times over "
+                               "[0, max(1e6, 3m)) s); 25% exact / 75% estimate; motif uniform over 36 three-edge "
                                "motifs + 4-cycle (4-cycle, with delta <= 3600, and delta 86400 on graphs up to 4e4 "
-                               "edges); delta in "
-                               "{600,3600,86400}; p in {0.01,0.1,1}; c 30; seeds from a pool of 4; value at the "
-                               "highest rate", "slots": 4, "budget_bytes": 4 << 30, "qps": args.qps_list},
+                               "edges); delta in {600,3600,86400}; p in {0.01,0.1,1}; c 30; a fresh seed per "
+                               "request", "graph_edges": sizes, "slots": slots, "budget_bytes": budget,
+                   "qps": args.qps_list, "p99_target_ms": args.p99_target_ms,
+                   "value_at_qps": top["qps"]},
         "sweep": sweeps,
     }
     for G in Gs:
@@ -839,8 +868,10 @@ def main():
                     help="zipf500m_star_cycle: leave out the 4-cycle on the 1%% variant")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="zipf500m_star_cycle: fraction of the nodes, edges and time span (same density)")
-    ap.add_argument("--qps-list", type=float, nargs="+", default=[50.0, 400.0], help="serve: arrival rates")
-    ap.add_argument("--queries", type=int, default=400, help="serve: queries per arrival rate")
+    ap.add_argument("--qps-list", type=float, nargs="+", default=[2.0, 4.0, 8.0], help="serve: arrival rates")
+    ap.add_argument("--queries", type=int, default=1000, help="serve: queries per arrival rate")
+    ap.add_argument("--p99-target-ms", type=float, default=5000.0, help="serve: the stated p99 latency target")
+    ap.add_argument("--serve-budget-gib", type=int, default=16, help="serve: the server's device-memory budget")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")

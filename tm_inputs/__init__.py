@@ -231,11 +231,25 @@ def config_star_cycle(device: str = "cuda"):
     return zipf_graph_device(20_000_000, 500_000_000, 2.0, 300_000_000, 3, device=device)
 
 
-def serving_graph(i: int) -> Graph:
-    """Graph i (0..7) of the serving mix: 1e4 .. 1e8 edges, log-spaced."""
+def serving_spec(i: int):
+    """(n, m, t_hi, seed) of graph i (0..7) of the serving mix: 1e4 .. 1e8
+    edges, log-spaced, 100 edges per node, Zipf(1.8) endpoints, bursty times
+    over [0, max(1e6, 3m)) s."""
     m = int(round(10 ** (4 + 4 * i / 7)))
-    n = max(100, m // 100)
-    return zipf_graph(n, m, 1.8, max(1_000_000, 3 * m), 50 + i)
+    return max(100, m // 100), m, max(1_000_000, 3 * m), 50 + i
+
+
+def serving_graph(i: int) -> Graph:
+    """Graph i (0..7) of the serving mix, drawn on the host."""
+    n, m, t_hi, seed = serving_spec(i)
+    return zipf_graph(n, m, 1.8, t_hi, seed)
+
+
+def serving_graph_device(i: int, device: str = "cuda"):
+    """Graph i of the serving mix drawn on the device (same recipe, torch's
+    generator): src, dst, t tensors and n."""
+    n, m, t_hi, seed = serving_spec(i)
+    return (*zipf_graph_device(n, m, 1.8, t_hi, seed, device=device), n)
 
 
 # ---------------------------------------------------------------- motifs
