@@ -54,8 +54,8 @@ void *tm_prof_begin(const char *name, hipStream_t st, uint64_t pass) {
     }
     ProfEvent *e = new (std::nothrow) ProfEvent{name, nullptr, nullptr, pass};
     if (!e) return nullptr;
-    if (hipEventCreate(&e->a) != hipSuccess || hipEventCreate(&e->b) != hipSuccess ||
-        hipEventRecord(e->a, st) != hipSuccess) {
+    if (tm_locked_call([&] { return hipEventCreate(&e->a); }) != hipSuccess ||
+        tm_locked_call([&] { return hipEventCreate(&e->b); }) != hipSuccess || hipEventRecord(e->a, st) != hipSuccess) {
         (void)hipGetLastError();
         delete e;
         return nullptr;
@@ -94,8 +94,8 @@ void tm_prof_collect() {
             }
         }
         (void)hipGetLastError();
-        (void)hipEventDestroy(e.a);
-        (void)hipEventDestroy(e.b);
+        (void)tm_locked_call([&] { return hipEventDestroy(e.a); });
+        (void)tm_locked_call([&] { return hipEventDestroy(e.b); });
     }
     P.pending.clear();
     for (auto &kv : crit) {

@@ -432,7 +432,7 @@ tm_status build_plan(const tm_graph *g, BatchPlan &B, hipStream_t st) {
 }
 
 tm_status capture(const tm_graph *g, BatchPlan &B) {
-    TM_HIP(hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking));
+    TM_HIP(tm_locked_call([&] { return hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking); }));
     hipGraph_t graph = nullptr;
     tm_status s;
     hipError_t e;
@@ -449,7 +449,7 @@ tm_status capture(const tm_graph *g, BatchPlan &B) {
         return s;
     }
     TM_HIP(e);
-    e = hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0);
+    e = tm_locked_call([&] { return hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0); });
     (void)hipGraphDestroy(graph);
     TM_HIP(e);
     return TM_OK;
@@ -624,15 +624,15 @@ tm_status tm_batch_tune(const tm_graph *g, int32_t code, int64_t delta, int64_t 
     double best = 1e300;
     int64_t bt = 1024, bb = 4;
     hipEvent_t e0, e1;
-    TM_HIP(hipEventCreate(&e0));
-    TM_HIP(hipEventCreate(&e1));
+    TM_HIP(tm_locked_call([&] { return hipEventCreate(&e0); }));
+    TM_HIP(tm_locked_call([&] { return hipEventCreate(&e1); }));
     for (int64_t t : tiles) {
         for (int64_t b : bpcs) {
             std::shared_ptr<BatchPlan> B;
             tm_status s = get_plan(g, code, delta, L, p, NS, t, b, false, &B, st);
             if (s != TM_OK) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
+                (void)tm_locked_call([&] { return hipEventDestroy(e0); });
+                (void)tm_locked_call([&] { return hipEventDestroy(e1); });
                 return s;
             }
             std::lock_guard<std::mutex> run(B->run_mu);
@@ -650,8 +650,8 @@ tm_status tm_batch_tune(const tm_graph *g, int32_t code, int64_t delta, int64_t 
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    (void)tm_locked_call([&] { return hipEventDestroy(e0); });
+    (void)tm_locked_call([&] { return hipEventDestroy(e1); });
     {
         // tuning plans (2 seeds, uncaptured) are not needed any more; one
         // that another thread is running stays alive until its run ends
@@ -923,6 +923,7 @@ struct MixStreams {
 MixStreams *mix_streams() {
     thread_local MixStreams S;
     if (!S.ok) {
+        std::shared_lock<std::shared_mutex> lk(tm_capture_lock());
         bool ok = hipStreamCreateWithFlags(&S.cap, hipStreamNonBlocking) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&S.fork, hipEventDisableTiming) == hipSuccess;
         for (int c = 0; c < MIX_CLASSES; ++c) {
@@ -1117,7 +1118,7 @@ tm_status tm_batch_mixed(const tm_graph *g, int64_t n, const int32_t *code, cons
         return s;
     }
     TM_HIP(e);
-    e = hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0);
+    e = tm_locked_call([&] { return hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0); });
     (void)hipGraphDestroy(graph);
     TM_HIP(e);
     void *tok = tm_prof_begin("count_batch_mixed", st);

@@ -48,6 +48,18 @@ inline std::shared_mutex &tm_capture_lock() {
     return m;
 }
 
+// The other runtime calls that may synchronise or take the device's
+// allocator (device allocation, graph instantiation, stream and event
+// creation) hold the lock shared too: on this runtime a free made by one
+// thread while another captures broke the process, and an allocation is the
+// same kind of call.  Never called while the thread holds the lock
+// exclusively (captures only enqueue kernels, copies and event waits).
+template <class F>
+inline hipError_t tm_locked_call(F &&f) {
+    std::shared_lock<std::shared_mutex> lk(tm_capture_lock());
+    return f();
+}
+
 // Device bytes held by the calling host thread: what its DevBufs allocated
 // minus what they freed (blocks kept by the load cache count as held), and
 // the high-water mark since the caller last set peak = live.  The query
@@ -138,11 +150,11 @@ struct DevBuf {
                 return TM_OK;
             }
         }
-        hipError_t e = hipMalloc(&p, nbytes);
+        hipError_t e = tm_locked_call([&] { return hipMalloc(&p, nbytes); });
         if (e == hipErrorOutOfMemory && !C.blocks.empty()) {
             (void)hipGetLastError();
             C.clear();
-            e = hipMalloc(&p, nbytes);
+            e = tm_locked_call([&] { return hipMalloc(&p, nbytes); });
         }
         if (e != hipSuccess) {
             p = nullptr;

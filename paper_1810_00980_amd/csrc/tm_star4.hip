@@ -141,46 +141,94 @@ __global__ void __launch_bounds__(S4_TPB) k_star4(DevGraph G, Star4Args a) {
         const int64_t le = G.inc_off[x + 1];
         int64_t j = i + 1;
         while (j < le && G.inc_t[j] == t1) ++j;  // ties with the anchor
+        // The last-edge role of an entry e4 (direction d3, leaf c != a) adds
+        // S - T_c, then its second-edge (leaf a, direction d2: A += 1) or
+        // third-edge role (leaf != a, direction d3: S += A, T_c += A) joins
+        // the sums.  An entry whose time no neighbour shares does both at
+        // once; a group of entries tied in time takes the last-edge roles of
+        // all its entries first and their other roles after (star_group), so
+        // that tied edges never share an instance.  Entries are read four at
+        // a time, with the next chunk's first time for the tie test.
+        auto last_edge = [&](int64_t tq, uint32_t nd, uint8_t r, uint64_t w) {
+            const uint32_t c = nd & 0x7FFFFFFFu;
+            if ((nd >> 31) != a.d[3] || c == y1) return;
+            const uint64_t tc = r != S4_LIGHT ? (uint64_t)T[r][tid]
+                                               : light_sum(G, x, c, a.d[2], t1, tq, pa, sel2, base2);
+            const uint64_t cnt = S - tc;
+            if (!cnt) return;
+            tm_add_u128(cl, ch, cnt, 0);
+            if constexpr (MODE == MODE_WEIGHT) tm_add_u128(wl, wh, cnt * w, __umul64hi(cnt, w));
+            if constexpr (MODE == MODE_HIST) {
+                uint64_t *h = a.hist + 2 * (tq - t1);
+                tm_atomic_add_u128(h, h + 1, cnt, 0);
+            }
+        };
         while (j < le) {
-            const int64_t tg = G.inc_t[j];
-            if (tg > hi) break;
-            int64_t ge = j + 1;
-            while (ge < le && G.inc_t[ge] == tg) ++ge;
-            // the group's last edges, over the sums of earlier groups
-            if (S) {
-                const uint64_t w = MODE == MODE_WEIGHT ? a.wfx[tg - t1] : 0;
-                for (int64_t q = j; q < ge; ++q) {
-                    const uint32_t nd = G.inc_nd[q];
-                    const uint32_t c = nd & 0x7FFFFFFFu;
-                    if ((nd >> 31) != a.d[3] || c == y1) continue;
-                    const uint8_t r = a.rank[q];
-                    const uint64_t tc = r != S4_LIGHT ? (uint64_t)T[r][tid]
-                                                       : light_sum(G, x, c, a.d[2], t1, tg, pa, sel2, base2);
-                    const uint64_t cnt = S - tc;
-                    if (!cnt) continue;
-                    tm_add_u128(cl, ch, cnt, 0);
-                    if constexpr (MODE == MODE_WEIGHT) tm_add_u128(wl, wh, cnt * w, __umul64hi(cnt, w));
-                    if constexpr (MODE == MODE_HIST) {
-                        uint64_t *h = a.hist + 2 * (tg - t1);
-                        tm_atomic_add_u128(h, h + 1, cnt, 0);
-                    }
+            int64_t tq[4];
+            uint32_t nq[4];
+            uint8_t rq[4];
+            uint64_t wq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t k = j + u < le ? j + u : le - 1;
+                tq[u] = j + u < le ? G.inc_t[k] : LLONG_MAX;
+                nq[u] = G.inc_nd[k];
+                rq[u] = a.rank[k];
+            }
+            const int64_t tn = j + 4 < le ? G.inc_t[j + 4] : LLONG_MAX;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                wq[u] = 0;
+                if constexpr (MODE == MODE_WEIGHT) {
+                    if (tq[u] <= hi) wq[u] = a.wfx[tq[u] - t1];
                 }
             }
-            // then the group's second and third edges join the sums
-            uint64_t addA = 0;
-            for (int64_t q = j; q < ge; ++q) {
-                const uint32_t nd = G.inc_nd[q];
-                const uint32_t y = nd & 0x7FFFFFFFu, dq = nd >> 31;
+            int64_t jn = j + 4;
+            bool stop = false;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (stop) continue;
+                if (j + u >= le || tq[u] > hi) {
+                    stop = true;
+                    jn = le;
+                    continue;
+                }
+                const int64_t tnext = u < 3 ? tq[u + 1] : tn;
+                if (tq[u] == tnext) {
+                    // a group of tied entries from j + u
+                    const int64_t tg = tq[u];
+                    int64_t ge = j + u + 1;
+                    while (ge < le && G.inc_t[ge] == tg) ++ge;
+                    if (S) {
+                        for (int64_t q = j + u; q < ge; ++q) last_edge(tg, G.inc_nd[q], a.rank[q], wq[u]);
+                    }
+                    uint64_t addA = 0;
+                    for (int64_t q = j + u; q < ge; ++q) {
+                        const uint32_t nd = G.inc_nd[q];
+                        const uint32_t y = nd & 0x7FFFFFFFu, dq = nd >> 31;
+                        if (y == y1) {
+                            addA += dq == a.d[1];
+                        } else if (dq == a.d[2] && A) {
+                            S += A;
+                            const uint8_t r = a.rank[q];
+                            if (r != S4_LIGHT) T[r][tid] += A;
+                        }
+                    }
+                    A += addA;
+                    jn = ge;
+                    stop = true;
+                    continue;
+                }
+                if (S) last_edge(tq[u], nq[u], rq[u], wq[u]);
+                const uint32_t y = nq[u] & 0x7FFFFFFFu, dq = nq[u] >> 31;
                 if (y == y1) {
-                    addA += dq == a.d[1];
+                    A += dq == a.d[1];
                 } else if (dq == a.d[2] && A) {
                     S += A;
-                    const uint8_t r = a.rank[q];
-                    if (r != S4_LIGHT) T[r][tid] += A;
+                    if (rq[u] != S4_LIGHT) T[rq[u]][tid] += A;
                 }
             }
-            A += addA;
-            j = ge;
+            j = jn;
         }
     }
     wave_add_u128(cl, ch);

@@ -194,6 +194,7 @@ SideStreams *side_streams(int dev) {
     if (dev < 0 || dev >= 8) return nullptr;
     SideStreams &S = per_dev[dev];
     if (S.dev != dev) {
+        std::shared_lock<std::shared_mutex> lk(tm_capture_lock());
         bool ok = true;
         for (int k = 0; k < 2; ++k) {
             ok = ok && hipStreamCreateWithFlags(&S.s[k], hipStreamNonBlocking) == hipSuccess;
