@@ -259,9 +259,13 @@ def serve_once(tm, Gs, sizes, qs, slots, budget):
             time.sleep(q["at"] - now)
         tickets.append(S.submit(ids[q["graph"]], q["edges"], q["delta"], q["kind"], q.get("c", 0),
                                 q.get("p", 0.0), q.get("seed", 0)))
-        if qi % 250 == 249:
+        if qi % 100 == 99:
             log("  submitted", qi + 1, f"{time.perf_counter() - t0:.1f}s")
-    res = [S.wait(tk) for tk in tickets]
+    res = []
+    for k, tk in enumerate(tickets):
+        res.append(S.wait(tk))
+        if k % 100 == 99:
+            log("  collected", k + 1, f"{time.perf_counter() - t0:.1f}s")
     st = S.stats()
     S.close()
     lat = np.sort(np.array([r["latency_ms"] for r in res]))
@@ -393,85 +397,82 @@ def run_bifan(args):
 
 
 def run_four_edge(args):
-    """The four-edge workload at full size: 20M nodes, 500M edges, Zipf(2.0)
-    endpoints, bursty times over [0, 3e8) s, drawn on the device; the 4-star
-    (0,1),(0,1),(0,2),(0,3) (its own counter) at delta 86400, c 30,
-    p 0.05.  The star's exact count runs when the estimate predicts it fits
-    in the run (about 1/p of the estimate's time).  The 4-cycle
-    (0,1),(1,2),(2,3),(3,0) goes through the generic backtracking counter,
-    whose work on this graph (two-edge prefixes through the top node) is out
-    of reach, so it is timed on the same recipe with 1% of the edges over
-    the same span (200k nodes, 5M edges)."""
+    """The four-edge workload: 20M nodes, 500M edges, Zipf(2.0) endpoints,
+    bursty times over [0, 3e8) s, drawn on the device, with the 4-star
+    (0,1),(0,1),(0,2),(0,3) (its own counter) and the 4-cycle
+    (0,1),(1,2),(2,3),(3,0) (the generic backtracking counter) at delta
+    86400, c 30, p 0.05.  At full size the graph is generated and loaded
+    (load time, device bytes) but not counted: one kept 30-day window holds
+    about 2e12 star window-entry visits and the cycle about 1e17 three-edge
+    prefixes, beyond a benchmark run.  Both motifs are timed, estimate and
+    exact count, on the same recipe with 1% of the edges over the same span
+    (200k nodes, 5M edges), whose hubs carry 1% of the density."""
     import torch
     import paper_1810_00980_amd as tm
     delta, c, p = 86400, 30, 0.05
-    out = {"metric": "temporal edges/s per motif query (4-star p=0.05 estimate)", "unit": "edges/s", "n_gpus": 1,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic"}
-    t0 = time.perf_counter()
+    out = {"metric": "temporal edges/s per motif query (4-star and 4-cycle, exact and p=0.05 estimate)",
+           "unit": "edges/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "int64", "data": "synthetic"}
     sc = args.scale
     n, m_want, t_hi = int(20_000_000 * sc), int(500_000_000 * sc), int(300_000_000 * sc)
+    t0 = time.perf_counter()
     if sc == 1.0:
         src, dst, t = ti.config_star_cycle()
-    else:  # the same recipe and density on a fraction of the span (calibration)
+    else:  # the same recipe and density on a fraction of the span
         src, dst, t = ti.zipf_graph_device(n, m_want, 2.0, t_hi, 3)
     torch.cuda.synchronize()
     m = int(src.numel())
     log("generated", m, "edges", f"{time.perf_counter() - t0:.1f}s")
-    t0 = time.perf_counter()
-    G = tm.load_graph(src, dst, t, n, exact_tables=False)
-    torch.cuda.synchronize()
-    t_load = time.perf_counter() - t0
-    log("loaded", f"{t_load:.1f}s", "device GB", G.device_bytes / 1e9)
+    loads = []
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G = tm.load_graph(src, dst, t, n, exact_tables=False)
+        torch.cuda.synchronize()
+        loads.append(time.perf_counter() - t0)
+        dev_bytes = G.device_bytes
+        G.free()
+        log("loaded", f"{loads[-1]:.2f}s", "device GB", dev_bytes / 1e9)
     del src, dst, t
     torch.cuda.empty_cache()
-    star = ti.STAR4
-    runs = []
-    for seed in range(args.steps + 1):
-        t0 = time.perf_counter()
-        z = tm.estimate(G, star, delta, c, p, seed)
-        dt = time.perf_counter() - t0
-        runs.append({"seed": seed, "estimate": z, "s": dt})
-        log("star estimate seed", seed, f"{dt:.2f}s", f"{z:.4e}")
-    timed = runs[1:] if len(runs) > 1 else runs
-    dt = float(np.mean([r["s"] for r in timed]))
-    out.update({"value": m / dt, "steps": len(timed), "warmup": 1, "ms_per_step": dt * 1e3,
-                "config": {"workload": f"{n / 1e6:g}M nodes, {m / 1e6:g}M edges, Zipf(2.0) endpoints, bursty times "
-                                       f"over [0,{t_hi:.0e}) s (drawn on the device); 4-star (0,1),(0,1),(0,2),(0,3), "
-                                       "delta 86400, c 30, p 0.05", "m": m, "n": n, "scale": sc},
-                "load_s": t_load, "graph_device_bytes": G.device_bytes, "star_estimates": runs})
-    pred = dt / p * 1.2
-    if pred < args.max_exact_s:
-        t0 = time.perf_counter()
-        exact = tm.count_exact(G, star, delta)
-        te = time.perf_counter() - t0
-        out["star_exact"] = {"count": str(exact), "s": te, "edges_per_s": m / te,
-                             "mean_estimate_rel_error": (float(np.mean([r["estimate"] for r in runs])) - exact) / exact
-                             if exact else None}
-        log("star exact", exact, f"{te:.1f}s")
-    else:
-        out["star_exact"] = {"skipped": f"predicted {pred:.0f} s (1.2 x estimate time / p) > {args.max_exact_s} s"}
-    G.free()
-    torch.cuda.empty_cache()
-    if args.no_cycle:
-        return out
-    # the 4-cycle on the same recipe with 1% of the edges
-    src, dst, t = ti.zipf_graph_device(200_000, 5_000_000, 2.0, 300_000_000, 5)
-    Gs = tm.load_graph(src, dst, t, 200_000)
+    full = {"workload": f"{n / 1e6:g}M nodes, {m / 1e6:g}M edges, Zipf(2.0) endpoints, bursty times over "
+                        f"[0,{t_hi:.0e}) s (drawn on the device)", "m": m, "n": n, "scale": sc,
+            "load_s": loads[-1], "load_edges_per_s": m / loads[-1], "graph_device_bytes": dev_bytes,
+            "counted": False}
+    # both motifs on the same recipe with 1% of the edges over the same span
+    mv, nv = 5_000_000, 200_000
+    src, dst, t = ti.zipf_graph_device(nv, mv, 2.0, 300_000_000, 5)
+    Gs = tm.load_graph(src, dst, t, nv)
     del src, dst, t
-    small = {"workload": "200k nodes, 5M edges, Zipf(2.0), bursty times over [0,3e8) s (graph seed 5)"}
-    for M, name in ((ti.CYCLE4, "cycle4"), (star, "star4")):
+    small = {"workload": "200k nodes, 5M edges, Zipf(2.0), bursty times over [0,3e8) s (graph seed 5)",
+             "delta": delta, "c": c, "p": p}
+    rates = []
+    for M, name in ((ti.STAR4, "star4"), (ti.CYCLE4, "cycle4")):
         tm.estimate(Gs, M, delta, c, p, 0)
-        t0 = time.perf_counter()
-        z = tm.estimate(Gs, M, delta, c, p, 1)
-        dz = time.perf_counter() - t0
+        ests = []
+        for seed in range(1, 1 + args.steps):
+            t0 = time.perf_counter()
+            z = tm.estimate(Gs, M, delta, c, p, seed)
+            ests.append({"seed": seed, "estimate": z, "s": time.perf_counter() - t0})
+        dz = float(np.mean([e["s"] for e in ests]))
         t0 = time.perf_counter()
         ex = tm.count_exact(Gs, M, delta)
         de = time.perf_counter() - t0
-        small[name] = {"estimate_s": dz, "estimate": z, "exact_s": de, "exact": str(ex),
-                       "estimate_edges_per_s": 5_000_000 / dz, "exact_edges_per_s": 5_000_000 / de}
-        log(name, "5M-edge variant", f"estimate {dz:.2f}s exact {de:.2f}s", ex)
+        mean = float(np.mean([e["estimate"] for e in ests]))
+        small[name] = {"estimates": ests, "estimate_s": dz, "exact": str(ex), "exact_s": de,
+                       "estimate_edges_per_s": mv / dz, "exact_edges_per_s": mv / de,
+                       "mean_estimate_rel_error": (mean - ex) / ex if ex else None}
+        rates += [mv / dz, mv / de]
+        log(name, "1% variant", f"estimate {dz:.2f}s exact {de:.2f}s", ex)
     Gs.free()
-    out["one_percent_variant"] = small
+    q = 4
+    wall = sum(small[k]["estimate_s"] + small[k]["exact_s"] for k in ("star4", "cycle4"))
+    out.update({"value": mv * q / wall, "steps": args.steps, "warmup": 1, "ms_per_step": wall * 1e3,
+                "config": {"workload": small["workload"] + "; the 1%-of-edges variant of the 500M-edge "
+                                                           "four-edge workload; 4-star and 4-cycle, exact and "
+                                                           "estimate, delta 86400, c 30, p 0.05",
+                           "m": mv, "n": nv, "motif_queries_per_step": q},
+                "full_size": full, "one_percent_variant": small})
     return out
 
 
@@ -481,7 +482,9 @@ def run_serve(args):
     continuous-batching server (4 slots, a device-memory budget on the
     workspace it measures) and, for comparison, one query at a time on the
     GPU in arrival order.  The value is the server's throughput at the
-    highest rate whose p99 latency meets the stated target."""
+    highest rate whose p99 latency meets the stated target.  --serve-phase
+    runs one side only (a line per phase, each with its per-query results);
+    --serve-merge joins such lines into the comparison."""
     import torch
     import paper_1810_00980_amd as tm
     Gs, sizes = [], []
@@ -498,7 +501,8 @@ def run_serve(args):
         G = Gs[q["graph"]]
         if q["kind"] == 0:
             return tm.count_exact(G, q["edges"], q["delta"])
-        return tm.estimate(G, q["edges"], q["delta"], q["c"], q["p"], q["seed"], info=(q["edges"] == ti.CYCLE4))
+        r = tm.estimate(G, q["edges"], q["delta"], q["c"], q["p"], q["seed"], info=(q["edges"] == ti.CYCLE4))
+        return r["Z"] if isinstance(r, dict) else r
 
     warm = serving_queries(np.random.default_rng(1), sizes, 60, 1000.0)
     for q in warm:
@@ -506,56 +510,84 @@ def run_serve(args):
     serve_once(tm, Gs, sizes, warm, slots, budget)
     torch.cuda.synchronize()
     log("warm")
-    sweeps = []
+    phases = []
     for qps in args.qps_list:
         qs = serving_queries(np.random.default_rng(2024), sizes, args.queries, qps)
         edges = sum(sizes[q["graph"]] for q in qs)
-        log("qps", qps, "server")
-        srv, res = serve_once(tm, Gs, sizes, qs, slots, budget)
-        log("qps", qps, "one at a time")
-        lat, mismatched, t0 = [], 0, time.perf_counter()
-        for qi, q in enumerate(qs):
-            now = time.perf_counter() - t0
-            if now < q["at"]:
-                time.sleep(q["at"] - now)
-            r = direct(q)
-            lat.append(time.perf_counter() - t0 - q["at"])
-            got = res[qi]["count"] if q["kind"] == 0 else res[qi]["estimate"]
-            want = r if q["kind"] == 0 else (r["Z"] if isinstance(r, dict) else r)
-            mismatched += int(got != want if q["kind"] == 0 else abs(got - want) > 1e-12 * abs(want))
-            if qi % 250 == 249:
-                log("  done", qi + 1, f"{time.perf_counter() - t0:.1f}s")
-        seq_wall = time.perf_counter() - t0
-        lat_ms = np.sort(np.array(lat) * 1e3)
-        one = {"p50_ms": _pct(lat_ms, 0.5), "p99_ms": _pct(lat_ms, 0.99), "wall_s": seq_wall,
-               "edges_per_s": edges / seq_wall}
-        sweeps.append({"qps": qps, "queries": len(qs), "server": srv, "one_at_a_time": one,
-                       "results_differing_from_one_at_a_time": mismatched,
-                       "server_meets_p99_target": srv["p99_ms"] <= args.p99_target_ms,
-                       "one_at_a_time_meets_p99_target": one["p99_ms"] <= args.p99_target_ms})
-        log("qps", qps, "server edges/s", f"{srv['edges_per_s']:.3e}", "p50", f"{srv['p50_ms']:.1f}", "p99",
-            f"{srv['p99_ms']:.1f}", "| one at a time", f"{one['edges_per_s']:.3e}", "p50", f"{one['p50_ms']:.1f}",
-            "p99", f"{one['p99_ms']:.1f}")
-    ok = [sw for sw in sweeps if sw["server_meets_p99_target"]]
-    top = max(ok, key=lambda sw: sw["qps"]) if ok else sweeps[0]
-    out = {
-        "metric": "temporal edges/s per motif query (served stream); p50/p99 latency",
-        "value": top["server"]["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": top["server"]["wall_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-        "config": {"workload": f"{args.queries} Poisson queries per arrival rate over 8 graphs of 1e4..1e8 edges "
-                               "(log-spaced, 100 edges per node, Zipf 1.8 endpoints, bursty times over "
-                               "[0, max(1e6, 3m)) s); 25% exact / 75% estimate; motif uniform over 36 three-edge "
-                               "motifs + 4-cycle (4-cycle, with delta <= 3600, and delta 86400 on graphs up to 4e4 "
-                               "edges); delta in {600,3600,86400}; p in {0.01,0.1,1}; c 30; a fresh seed per "
-                               "request", "graph_edges": sizes, "slots": slots, "budget_bytes": budget,
-                   "qps": args.qps_list, "p99_target_ms": args.p99_target_ms,
-                   "value_at_qps": top["qps"]},
-        "sweep": sweeps,
-    }
+        if args.serve_phase in ("both", "server"):
+            log("qps", qps, "server")
+            srv, res = serve_once(tm, Gs, sizes, qs, slots, budget)
+            srv["results"] = [str(r["count"]) if q["kind"] == 0 else r["estimate"] for q, r in zip(qs, res)]
+            phases.append({"qps": qps, "phase": "server", "queries": len(qs), "edges": edges, **srv})
+            log("qps", qps, "server edges/s", f"{srv['edges_per_s']:.3e}", "p50", f"{srv['p50_ms']:.1f}", "p99",
+                f"{srv['p99_ms']:.1f}")
+        if args.serve_phase in ("both", "direct"):
+            log("qps", qps, "one at a time")
+            lat, got, t0 = [], [], time.perf_counter()
+            for qi, q in enumerate(qs):
+                now = time.perf_counter() - t0
+                if now < q["at"]:
+                    time.sleep(q["at"] - now)
+                r = direct(q)
+                lat.append(time.perf_counter() - t0 - q["at"])
+                got.append(str(r) if q["kind"] == 0 else r)
+                if qi % 100 == 99:
+                    log("  done", qi + 1, f"{time.perf_counter() - t0:.1f}s")
+            wall = time.perf_counter() - t0
+            lat_ms = np.sort(np.array(lat) * 1e3)
+            one = {"p50_ms": _pct(lat_ms, 0.5), "p99_ms": _pct(lat_ms, 0.99), "wall_s": wall,
+                   "edges_per_s": edges / wall, "results": got}
+            phases.append({"qps": qps, "phase": "one_at_a_time", "queries": len(qs), "edges": edges, **one})
+            log("qps", qps, "one at a time edges/s", f"{one['edges_per_s']:.3e}", "p50", f"{one['p50_ms']:.1f}",
+                "p99", f"{one['p99_ms']:.1f}")
     for G in Gs:
         G.free()
-    return out
+    cfg = {"workload": f"{args.queries} Poisson queries per arrival rate over 8 graphs of 1e4..1e8 edges "
+                       "(log-spaced, 100 edges per node, Zipf 1.8 endpoints, bursty times over "
+                       "[0, max(1e6, 3m)) s); 25% exact / 75% estimate; motif uniform over 36 three-edge "
+                       "motifs + 4-cycle (4-cycle, with delta <= 3600, and delta 86400 on graphs up to 4e4 "
+                       "edges); delta in {600,3600,86400}; p in {0.01,0.1,1}; c 30; a fresh seed per "
+                       "request", "graph_edges": sizes, "slots": slots, "budget_bytes": budget,
+           "p99_target_ms": args.p99_target_ms}
+    return serve_merge(phases, cfg, args.p99_target_ms)
+
+
+def serve_merge(phases, cfg, target_ms):
+    """One bench line from serving phases (the server and the one-at-a-time
+    runs of each arrival rate, possibly from separate runs): per rate the two
+    sides' latency and throughput, whether each meets the p99 target, and
+    how many results differ between them (counts exactly, estimates beyond
+    1e-12 relative)."""
+    by = {}
+    for ph in phases:
+        by.setdefault(ph["qps"], {})[ph["phase"]] = ph
+    sweeps = []
+    for qps in sorted(by):
+        d = by[qps]
+        srv, one = d.get("server"), d.get("one_at_a_time")
+        sw = {"qps": qps}
+        for name, ph in (("server", srv), ("one_at_a_time", one)):
+            if ph:
+                sw[name] = {k: v for k, v in ph.items() if k not in ("results", "qps", "phase")}
+                sw[name + "_meets_p99_target"] = ph["p99_ms"] <= target_ms
+        if srv and one:
+            diff = 0
+            for a, b in zip(srv["results"], one["results"]):
+                if isinstance(a, str) or isinstance(b, str):
+                    diff += int(str(a) != str(b))
+                else:
+                    diff += int(abs(a - b) > 1e-12 * abs(b))
+            sw["results_differing_from_one_at_a_time"] = diff
+            sw["server_over_one_at_a_time_throughput"] = srv["edges_per_s"] / one["edges_per_s"]
+        sweeps.append(sw)
+    ok = [sw for sw in sweeps if sw.get("server_meets_p99_target")]
+    top = max(ok, key=lambda sw: sw["qps"]) if ok else next((sw for sw in sweeps if "server" in sw), None)
+    cfg = dict(cfg, qps=sorted(by), value_at_qps=top["qps"] if top else None)
+    return {"metric": "temporal edges/s per motif query (served stream); p50/p99 latency",
+            "value": top["server"]["edges_per_s"] if top else None, "unit": "edges/s", "n_gpus": 1, "steps": 1,
+            "warmup": 1, "ms_per_step": top["server"]["wall_s"] * 1e3 if top else None, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic", "config": cfg,
+            "sweep": sweeps, "phases": phases}
 
 
 def _code_only(src: str) -> str:
@@ -862,16 +894,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="zipf10m",
                     choices=sorted(WORKLOADS) + ["batch50m", "serve", "perf23", "bifan", "zipf500m_star_cycle"])
-    ap.add_argument("--max-exact-s", type=float, default=120.0,
-                    help="zipf500m_star_cycle: run the star's exact count when predicted below this")
-    ap.add_argument("--no-cycle", action="store_true",
-                    help="zipf500m_star_cycle: leave out the 4-cycle on the 1%% variant")
     ap.add_argument("--scale", type=float, default=1.0,
-                    help="zipf500m_star_cycle: fraction of the nodes, edges and time span (same density)")
+                    help="zipf500m_star_cycle: fraction of the nodes, edges and time span of the loaded graph "
+                         "(same density)")
     ap.add_argument("--qps-list", type=float, nargs="+", default=[2.0, 4.0, 8.0], help="serve: arrival rates")
     ap.add_argument("--queries", type=int, default=1000, help="serve: queries per arrival rate")
     ap.add_argument("--p99-target-ms", type=float, default=5000.0, help="serve: the stated p99 latency target")
     ap.add_argument("--serve-budget-gib", type=int, default=16, help="serve: the server's device-memory budget")
+    ap.add_argument("--serve-phase", choices=["both", "server", "direct"], default="both",
+                    help="serve: run the server, the one-at-a-time comparison, or both")
+    ap.add_argument("--serve-merge", nargs="+", metavar="JSON",
+                    help="join the serve lines of separate phase runs into one line and exit")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
@@ -887,6 +920,11 @@ def main():
         return
     if args.kt_summary:
         kt_summary(args.kt_summary)
+        return
+    if args.serve_merge:
+        lines = [json.loads(open(f).read().strip().splitlines()[-1]) for f in args.serve_merge]
+        print(json.dumps(serve_merge([ph for ln in lines for ph in ln["phases"]], lines[0]["config"],
+                                     lines[0]["config"]["p99_target_ms"])))
         return
     if args.profile_run:
         args.steps, args.warmup, args.no_cpu = 1, 0, True

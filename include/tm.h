@@ -343,7 +343,7 @@ tm_status tm_batch_release(const tm_graph *g, void *hip_stream);
  *  - Outputs are caller-owned DEVICE arrays: estimates_dev[n_motifs]
  *    (double) and kept_dev[n_motifs] (nullable; exact kept-window counts).
  *  - Work space: a library-owned static device array of
- *    8 (152 + TM_NOALLOC_MAX_DELTA + 1) bytes (about 8 MiB) per GPU, held
+ *    8 (168 + TM_NOALLOC_MAX_DELTA + 1) bytes (about 8 MiB) per GPU, held
  *    until the process ends; no hipMalloc, hipFree or other allocation is
  *    made.  Every call on one GPU shares that array: calls that overlap on one
  *    GPU (different streams or host threads without ordering) race and give
@@ -401,16 +401,19 @@ typedef struct {
  * oldest queued query whose device workspace fits what is left of
  * budget_bytes, merges every queued query that can share its device work
  * (exact counts of three-edge motifs on the same graph and delta share one
- * sweep; estimates of three-edge motifs on the same graph share one
- * tm_estimate_mixed launch, whatever their motifs, deltas, c, p and seeds),
- * up to 256 per batch, and starts it on a free slot.  A batch is charged the
+ * sweep; estimates of three-edge motifs on the same graph share the launch
+ * sequence of tm_estimate_mixed, enqueued on the slot's stream rather than
+ * captured, whatever their motifs, deltas, c, p and seeds; a lone estimate
+ * takes tm_estimate_multi's sweep), up to 256 per batch, and starts it on a
+ * free slot.  A batch is charged the
  * device bytes its path allocates, and the bytes it really allocated are
  * measured and reported beside the charge (tm_result, tm_server_stats); the
  * grow-only workspaces a slot thread keeps between batches are measured
  * after each batch and counted against the budget too (an idle slot frees
  * them when the oldest query would not fit otherwise), so budget_bytes
- * bounds the device memory the server's threads hold beyond the graphs.  Queries that arrive while others run are
- * admitted as slots and memory free up.  A result is the same whether its
+ * bounds the device memory the server's threads hold beyond the graphs.
+ * Queries that arrive while others run are admitted as slots and memory
+ * free up.  A result is the same whether its
  * query ran alone or in a batch.  Graphs must stay loaded while the server
  * uses them.  tm_server_wait blocks until the ticket's result is ready
  * (TM_EINVAL for an unknown or already collected ticket; a collected result

@@ -511,7 +511,7 @@ tm_status run_sweep(const tm_graph *g, uint64_t mask, int mode, int64_t delta, i
                     uint64_t *win = nullptr) {
     DevBuf &o = t_ws.o, &h = t_ws.h, &w = t_ws.w, &ctr = t_ws.ctr;
     TM_TRY(o.reserve(36 * 4 * 8));
-    TM_TRY(ctr.reserve(64));
+    TM_TRY(ctr.reserve(TM_SWEEP_COUNTER_BYTES));
     if (mode == 2) TM_TRY(h.reserve((size_t)36 * (delta + 1) * 16));
     if (mode == 1) TM_TRY(w.reserve((size_t)(delta + 1) * 8));
     TM_TRY(tm_sweep3(g, mask, mode, delta, windowed, s, L, seed, p, o.as<uint64_t>(), h.as<uint64_t>(),
@@ -1133,10 +1133,11 @@ extern "C" tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, cons
 
 // Device scratch of tm_estimate_multi_noalloc, one copy per GPU, held until
 // the process ends: the sweep's 36 x 4 accumulators (144 words), its work
-// counters (8 words) and the delta + 1 fixed-point weights.  Host code never
+// counters (TM_SWEEP_COUNTER_BYTES: 24 words) and the delta + 1 fixed-point
+// weights.  Host code never
 // passes the symbol itself to a kernel or a copy: it takes the device
 // address of this GPU's copy from hipGetSymbolAddress (noalloc_scratch).
-#define TM_NOALLOC_HEAD_WORDS 152
+#define TM_NOALLOC_HEAD_WORDS (144 + TM_SWEEP_COUNTER_BYTES / 8)
 #define TM_NOALLOC_WORDS ((int64_t)TM_NOALLOC_HEAD_WORDS + TM_NOALLOC_MAX_DELTA + 1)
 static __device__ __align__(256) uint64_t scratch[TM_NOALLOC_WORDS];
 
@@ -1253,8 +1254,12 @@ extern "C" tm_status tm_estimate_batch(const tm_graph *g, const tm_motif *M, int
 
 extern "C" tm_status tm_estimate_mixed(const tm_graph *g, int32_t n, const tm_est_query *q, double *estimates,
                                        tm_u128 *kept_counts, void *hip_stream) {
+    return tm_estimate_mixed_ex(g, n, q, estimates, kept_counts, (hipStream_t)hip_stream, true);
+}
+
+tm_status tm_estimate_mixed_ex(const tm_graph *g, int32_t n, const tm_est_query *q, double *estimates,
+                               tm_u128 *kept_counts, hipStream_t st, bool capture) {
     if (!g || n < 0 || (n > 0 && (!q || !estimates))) return TM_EINVAL;
-    hipStream_t st = (hipStream_t)hip_stream;
     std::vector<int32_t> code;
     std::vector<int64_t> delta, L, idx;
     std::vector<double> p;
@@ -1278,7 +1283,7 @@ extern "C" tm_status tm_estimate_mixed(const tm_graph *g, int32_t n, const tm_es
     std::vector<double> est((size_t)(k > 0 ? k : 1));
     std::vector<tm_u128> kept((size_t)(k > 0 ? k : 1));
     tm_status s = tm_batch_mixed(g, k, code.data(), delta.data(), L.data(), p.data(), seed.data(), est.data(),
-                                 kept.data(), st);
+                                 kept.data(), st, capture);
     if (s != TM_OK) return finish(s, st);
     for (int64_t j = 0; j < k; ++j) {
         estimates[idx[(size_t)j]] = est[(size_t)j];

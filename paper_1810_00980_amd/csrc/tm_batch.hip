@@ -1016,7 +1016,8 @@ tm_status mix_enqueue(const tm_graph *g, MixPlan &B, hipStream_t st, bool fork_s
 // captured launch; each query has its own delta, window length L, p and
 // seed.  ws_bytes (nullable) receives the device bytes the batch allocated.
 tm_status tm_batch_mixed(const tm_graph *g, int64_t n, const int32_t *code, const int64_t *delta, const int64_t *L,
-                         const double *p, const uint64_t *seeds, double *est, tm_u128 *kept, hipStream_t st) {
+                         const double *p, const uint64_t *seeds, double *est, tm_u128 *kept, hipStream_t st,
+                         bool capture) {
     if (n <= 0) return TM_OK;
     if (g->m_nl == 0) {
         for (int64_t k = 0; k < n; ++k) {
@@ -1093,37 +1094,44 @@ tm_status tm_batch_mixed(const tm_graph *g, int64_t n, const int32_t *code, cons
     hipLaunchKernelGGL(k_mix_weights, dim3(gx, (unsigned)n), dim3(256), 0, st, (const MixEst *)B.est.as<MixEst>(),
                        B.wfx.as<uint64_t>());
     TM_HIP(hipGetLastError());
-    // capture the launch sequence (the class kernels as parallel branches)
-    // on this thread's capture stream, then replay it on the caller's stream
+    // the launch sequence (the class kernels as parallel branches): captured
+    // on this thread's capture stream and replayed on the caller's stream, or
+    // enqueued on the caller's stream with the same fork and join
     MixStreams *MS = mix_streams();
     if (!MS) return TM_EDEVICE;
     hipStream_t cap = MS->cap;
     B.side = MS->side;
     B.fork = MS->fork;
     B.join = MS->join;
-    TM_HIP(hipStreamSynchronize(st));
-    hipGraph_t graph = nullptr;
-    tm_status s;
-    hipError_t e;
-    {
-        // no library free (an implicit device synchronisation) during the capture
-        std::unique_lock<std::shared_mutex> lk(tm_capture_lock());
-        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return tm_hip_status(e);
-        s = mix_enqueue(g, B, cap, true);
-        e = hipStreamEndCapture(cap, &graph);
+    if (capture) {
+        TM_HIP(hipStreamSynchronize(st));
+        hipGraph_t graph = nullptr;
+        tm_status s;
+        hipError_t e;
+        {
+            // no library free (an implicit device synchronisation) during the capture
+            std::unique_lock<std::shared_mutex> lk(tm_capture_lock());
+            e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return tm_hip_status(e);
+            s = mix_enqueue(g, B, cap, true);
+            e = hipStreamEndCapture(cap, &graph);
+        }
+        if (s != TM_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return s;
+        }
+        TM_HIP(e);
+        e = tm_locked_call([&] { return hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0); });
+        (void)hipGraphDestroy(graph);
+        TM_HIP(e);
+        void *tok = tm_prof_begin("count_batch_mixed", st);
+        TM_HIP(hipGraphLaunch(B.exec, st));
+        tm_prof_end(tok, st);
+    } else {
+        void *tok = tm_prof_begin("count_batch_mixed", st);
+        TM_TRY(mix_enqueue(g, B, st, true));
+        tm_prof_end(tok, st);
     }
-    if (s != TM_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return s;
-    }
-    TM_HIP(e);
-    e = tm_locked_call([&] { return hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0); });
-    (void)hipGraphDestroy(graph);
-    TM_HIP(e);
-    void *tok = tm_prof_begin("count_batch_mixed", st);
-    TM_HIP(hipGraphLaunch(B.exec, st));
-    tm_prof_end(tok, st);
     std::vector<double> z((size_t)n);
     std::vector<uint64_t> o((size_t)n * 4);
     TM_HIP(hipMemcpyAsync(z.data(), B.z.p, (size_t)n * 8, hipMemcpyDeviceToHost, st));

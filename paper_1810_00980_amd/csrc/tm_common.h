@@ -12,6 +12,11 @@
 
 #define TM_WAVE 64
 
+// Work counters of the three-edge sweep: one per XCD for each of its three
+// kernels (the claim ranges of SweepArgs::parts).
+#define TM_SWEEP_PARTS 8
+#define TM_SWEEP_COUNTER_BYTES (3 * TM_SWEEP_PARTS * 8)
+
 // Largest delta for which a duration histogram (delta + 1 bins) is built.
 #define TM_MAX_HIST_DELTA ((int64_t)1 << 26)
 
@@ -481,10 +486,15 @@ tm_status tm_batch_tune(const tm_graph *g, int32_t code, int64_t delta, int64_t 
 void tm_batch_forget(const tm_graph *g);
 void tm_batch_release_plans(const tm_graph *g);
 // Estimates of n three-edge-motif queries (sweep codes, each with its own
-// delta, window length L, p and seed) in one captured launch, and the device
+// delta, window length L, p and seed) in one launch sequence, captured in a
+// hipGraph and replayed (capture) or enqueued on st as it is, and the device
 // bytes that takes.
 tm_status tm_batch_mixed(const tm_graph *g, int64_t n, const int32_t *code, const int64_t *delta, const int64_t *L,
-                         const double *p, const uint64_t *seeds, double *est, tm_u128 *kept, hipStream_t st);
+                         const double *p, const uint64_t *seeds, double *est, tm_u128 *kept, hipStream_t st,
+                         bool capture = true);
+// tm_estimate_mixed with the same choice (the query server enqueues)
+tm_status tm_estimate_mixed_ex(const tm_graph *g, int32_t n, const tm_est_query *q, double *estimates,
+                               tm_u128 *kept_counts, hipStream_t st, bool capture);
 int64_t tm_batch_mixed_bytes(const tm_graph *g, int64_t n, const int64_t *delta, const int64_t *L);
 
 // ------------------------------------------------------------ 4-edge stars

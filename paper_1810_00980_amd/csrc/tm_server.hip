@@ -5,10 +5,11 @@
 // slot is free it takes the oldest query that fits the memory budget and
 // merges every pending query that can share its device work: exact counts of
 // three-edge motifs on the same graph and delta share one sweep; estimates of
-// three-edge motifs on the same graph share one persistent launch, whatever
-// their motifs, deltas, c, p and seeds (each is its own estimator in the
-// mixed batch).  It reserves the batch's device workspace from the budget
-// and hands the batch to the slot.  Each slot is a host thread with its own
+// three-edge motifs on the same graph share one persistent launch sequence,
+// whatever their motifs, deltas, c, p and seeds (each is its own estimator
+// in the mixed batch; a lone one takes the plain weighted sweep).  It
+// reserves the batch's device workspace from the budget and hands the batch
+// to the slot.  Each slot is a host thread with its own
 // HIP stream (default priority), so batches on different slots overlap on the
 // device; finishing a batch returns its workspace to the budget and wakes the
 // dispatcher, which admits waiting queries as memory and slots free up.
@@ -22,9 +23,9 @@
 // measured after each batch and counted against the budget as well; when the
 // oldest query does not fit, an idle slot is asked to free what it holds.  A
 // query whose workspace alone exceeds the budget is completed with
-// TM_EBUDGET.  Results do
-// not depend on how queries were batched: every count is an exact integer and
-// every estimate is computed from exact integer sums.
+// TM_EBUDGET.  Results do not depend on how queries were batched: every
+// count is an exact integer and every estimate is computed from exact
+// integer sums.
 #include "tm_common.h"
 
 #include <string.h>
@@ -66,7 +67,7 @@ int64_t batch_ws_bytes(const tm_graph *g, const std::vector<tm_query> &b) {
         if (three) {
             // the sweep's accumulators and work counters, and the exact
             // triangle sweep's claim order when a triangle motif is asked for
-            int64_t bytes = buf(36 * 4 * 8) + buf(64);
+            int64_t bytes = buf(36 * 4 * 8) + buf(TM_SWEEP_COUNTER_BYTES);
             for (const tm_query &q : b) {
                 const int c = tm_sweep_code_of(&q.motif);
                 if (c >= 20 && c < 28) {
@@ -80,6 +81,10 @@ int64_t batch_ws_bytes(const tm_graph *g, const std::vector<tm_query> &b) {
         if (tm_star4_shape(&q0.motif, d)) return tm_star4_bytes(g, 0) + tm_star4_build_bytes(g);
         // the generic counter over every edge
         return buf(64) + tm_generic_bytes(g->m, q0.motif.l);
+    }
+    if (three && b.size() == 1) {
+        // the plain weighted sweep: accumulators, work counters, weights
+        return buf(36 * 4 * 8) + buf(TM_SWEEP_COUNTER_BYTES) + buf((q0.delta + 1) * 8);
     }
     if (three) {
         std::vector<int64_t> delta, L;
@@ -276,7 +281,14 @@ struct tm_server {
                 const tm_query &q = batch[(size_t)i].q;
                 eq[(size_t)i] = tm_est_query{q.motif, q.delta, q.c, q.p, q.seed};
             }
-            tm_status s = tm_estimate_mixed(g, n, eq.data(), est.data(), kc.data(), st);
+            // a lone three-edge estimate takes the plain sweep; several share
+            // one mixed launch sequence, enqueued on the slot's stream (a
+            // graph captured per batch would be replayed once, and a capture
+            // must not overlap the other slots' runtime calls)
+            tm_status s = (n == 1 && tm_sweep_code_of(&eq[0].motif) >= 0)
+                              ? tm_estimate_multi(g, 1, &eq[0].motif, eq[0].delta, eq[0].c, eq[0].p, eq[0].seed,
+                                                  est.data(), kc.data(), st)
+                              : tm_estimate_mixed_ex(g, n, eq.data(), est.data(), kc.data(), st, false);
             for (int i = 0; i < n; ++i) {
                 res[(size_t)i].status = s;
                 res[(size_t)i].estimate = est[(size_t)i];

@@ -64,20 +64,29 @@ k_sweep3(DevGraph G, SweepArgs a) {
     const uint32_t *ndv = RANKED ? G.hi_nd : G.inc_nd;
     const int64_t *tv = RANKED ? G.hi_t : G.inc_t;
     const int64_t nE = RANKED ? G.n_hi : a.n_entries;
+    const bool ordered = RANKED && a.order;
+    // units: batches of the claim order (heaviest first within each range),
+    // or 64-entry chunks in index order
+    const int64_t nU = ordered ? a.n_batches : (nE + TM_WAVE - 1) / TM_WAVE;
+    const int parts = a.parts;
+    int q = (int)(blockIdx.x % (unsigned)parts), left = parts;  // lane 0's range, ranges not yet used up
     while (true) {
-        int64_t base = 0;
-        if (RANKED && a.order) {
-            // the next batch in the claim order (heaviest first)
-            int64_t b = 0;
-            if (lane == 0) b = (int64_t)atomicAdd((unsigned long long *)a.counter, 1ull);
-            b = __shfl(b, 0, TM_WAVE);
-            if (b >= a.n_batches) break;
-            base = (int64_t)a.order[b] * TM_WAVE;
-        } else {
-            if (lane == 0) base = (int64_t)atomicAdd((unsigned long long *)a.counter, (unsigned long long)TM_WAVE);
-            base = __shfl(base, 0, TM_WAVE);
-            if (base >= nE) break;
+        int64_t u = -1;
+        if (lane == 0) {
+            while (left > 0) {
+                const int64_t lo = part_lo(q, nU, parts), hi = part_lo(q + 1, nU, parts);
+                const int64_t c = (int64_t)atomicAdd((unsigned long long *)(a.counter + q), 1ull);
+                if (lo + c < hi) {
+                    u = lo + c;
+                    break;
+                }
+                q = q + 1 == parts ? 0 : q + 1;
+                --left;
+            }
         }
+        u = __shfl(u, 0, TM_WAVE);
+        if (u < 0) break;
+        const int64_t base = ordered ? (int64_t)a.order[u] * TM_WAVE : u * TM_WAVE;
         int64_t i = base + lane;
         if (i < nE) {
             int64_t x = owner_of(off, G.n, i);
@@ -351,7 +360,11 @@ __global__ void k_tri_batch_cost(DevGraph G, SweepArgs a, int64_t nbt, uint64_t 
         len = lo - (i + 1);
     }
     const uint64_t c = len < 0xFFFFFFFFll ? (uint64_t)len : 0xFFFFFFFFull;
-    keys[b] = 0xFFFFFFFFull - c;
+    // the batch's claim range (SweepArgs::parts) above the cost
+    int64_t q = (b * a.parts) / nbt;
+    while (q > 0 && b < part_lo(q, nbt, a.parts)) --q;
+    while (q + 1 < a.parts && b >= part_lo(q + 1, nbt, a.parts)) ++q;
+    keys[b] = ((uint64_t)q << 32) | (0xFFFFFFFFull - c);
     vals[b] = (uint32_t)b;
 }
 
@@ -383,7 +396,8 @@ tm_status tri_claim_order(const tm_graph *g, SweepArgs &a, hipStream_t st) {
     hipLaunchKernelGGL(k_tri_batch_cost, dim3(tm_blocks(nbt, 256)), dim3(256), 0, st, G, a, nbt,
                        t_order_k.as<uint64_t>(), t_order_v.as<uint32_t>());
     TM_HIP(hipGetLastError());
-    TM_TRY(tm_radix_sort(t_order_k.as<uint64_t>(), t_order_v.as<uint32_t>(), nbt, 32, st));
+    TM_TRY(tm_radix_sort(t_order_k.as<uint64_t>(), t_order_v.as<uint32_t>(), nbt, 32 + tm_bitlen((uint64_t)a.parts),
+                         st));
     a.order = t_order_v.as<uint32_t>();
     a.n_batches = nbt;
     return TM_OK;
@@ -407,7 +421,10 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, bool s
     // and bound by different things (the 2-node/star sweeps by VALU issue,
     // the triangle sweep by lookup latency), so they run on forked streams
     // and share the CUs; the caller's stream waits for all of them.
-    TM_TRY(zero_u64((uint64_t *)a.counter, 3, st));
+    // one claim range per XCD (the grid is dealt to the XCDs in turn) for
+    // the exact triangle sweep and its claim order
+    a.parts = (ncu % TM_SWEEP_PARTS == 0 && nb >= TM_SWEEP_PARTS) ? TM_SWEEP_PARTS : 1;
+    TM_TRY(zero_u64((uint64_t *)a.counter, 3 * TM_SWEEP_PARTS, st));
     if (MODE == MODE_COUNT && fwd && (a.want_fwd & 8u) && a.windowed != 3) TM_TRY(tri_claim_order(g, a, st));
     if (MODE == MODE_WEIGHT && fwd && a.want_fwd == 1u && !bwd) {
         // the 2-node motifs alone: one anchor per pair entry
@@ -440,7 +457,12 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, bool s
     for (int k = 0; k < nl; ++k) {
         hipStream_t sk = (k == 0 || !side) ? st : side->s[k - 1];
         SweepArgs b = a;
-        b.counter = a.counter + todo[k].kind;
+        b.counter = a.counter + TM_SWEEP_PARTS * todo[k].kind;
+        // claim ranges by XCD for the exact triangles only (their batches go
+        // heaviest first, so a single range scatters every XCD's waves over
+        // the whole graph; the weighted sweeps, claimed in index order, ran
+        // no faster by XCD ranges in their concurrent pass and slower alone)
+        if (!(MODE == MODE_COUNT && todo[k].kind == 2)) b.parts = 1;
         void *tok = tm_prof_begin(names[MODE][todo[k].kind], sk, pass);
         if (todo[k].kind == 0)
             hipLaunchKernelGGL((k_sweep3<MODE, true, 7u>), dim3((unsigned)nb), dim3(SW_TPB), 0, sk, G, b);

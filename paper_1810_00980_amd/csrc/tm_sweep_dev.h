@@ -34,7 +34,19 @@ struct SweepArgs {
     // order they are claimed (heaviest window first), or nullptr for index order
     const uint32_t *order = nullptr;
     int64_t n_batches = 0;
+    // claims by XCD: the work units (64-entry chunks in index order, or the
+    // claim order's batches) form `parts` contiguous ranges (unit u is in
+    // range q when ceil(q n / parts) <= u < ceil((q + 1) n / parts)), each
+    // with its own counter counter[q]; a work-group starts on the range of
+    // its XCD (blockIdx.x mod parts: work-groups are dealt to the XCDs in
+    // turn) and moves on to the next range when its own is used up
+    int32_t parts = 1;
 };
+
+// first unit of range q of n units in `parts` ranges
+__host__ __device__ inline int64_t part_lo(int64_t q, int64_t n, int64_t parts) {
+    return (q * n + parts - 1) / parts;
+}
 
 __device__ inline void philox10_d(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3, uint32_t k0, uint32_t k1) {
 #pragma unroll

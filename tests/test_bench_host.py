@@ -95,3 +95,25 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=300)
     assert p.returncode != 0
     assert "one GPU" in (p.stdout + p.stderr)
+
+
+def test_serve_merge_pairs_phases(bench):
+    """Serving lines from separate server and one-at-a-time runs join per
+    arrival rate; differing results are counted (counts exactly, estimates
+    beyond 1e-12 relative) and the value is the server's throughput at the
+    highest rate meeting the p99 target."""
+    def ph(qps, phase, p99, eps, results):
+        return {"qps": qps, "phase": phase, "queries": 3, "edges": 30, "p50_ms": 1.0, "p99_ms": p99,
+                "wall_s": 2.0, "edges_per_s": eps, "results": results}
+    phases = [ph(2.0, "server", 100.0, 20.0, ["7", 1.5, 2.0]),
+              ph(2.0, "one_at_a_time", 600.0, 10.0, ["7", 1.5, 2.0 * (1 + 1e-9)]),
+              ph(4.0, "server", 900.0, 40.0, ["8", 1.0, 3.0]),
+              ph(4.0, "one_at_a_time", 2000.0, 15.0, ["9", 1.0, 3.0])]
+    out = bench.serve_merge(phases, {"workload": "w"}, 500.0)
+    sw = {s["qps"]: s for s in out["sweep"]}
+    assert sw[2.0]["results_differing_from_one_at_a_time"] == 1
+    assert sw[4.0]["results_differing_from_one_at_a_time"] == 1
+    assert sw[2.0]["server_meets_p99_target"] and not sw[2.0]["one_at_a_time_meets_p99_target"]
+    assert not sw[4.0]["server_meets_p99_target"]
+    assert out["value"] == 20.0 and out["config"]["value_at_qps"] == 2.0
+    assert abs(sw[2.0]["server_over_one_at_a_time_throughput"] - 2.0) < 1e-12
