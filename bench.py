@@ -29,6 +29,7 @@ Profiling helpers (rocprofv3 -f csv output directories):
                                 step (for rocprofv3 runs)
   --pmc-summary FETCH WRITE     write profiles/<kernel>_zipf10m_traffic.json
   --kt-summary DIR              write profiles/sweep3_zipf10m_kernel_trace.txt
+  --pmc-counters DIR            write profiles/sweep3_zipf10m_counters.json
 """
 from __future__ import annotations
 
@@ -782,6 +783,52 @@ def pmc_summary(fetch_dir, write_dir):
         print(name, f"{rec['traffic_bytes_per_launch'] / 1e9:.2f} GB per launch", file=sys.stderr)
 
 
+PMC_COUNTERS = ("TCC_HIT_sum", "TCC_MISS_sum", "SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_BUSY_CYCLES",
+                "TA_BUSY_avr", "GRBM_GUI_ACTIVE")
+N_XCD = 8  # MI355X: GRBM_GUI_ACTIVE sums one instance per XCD
+
+
+def pmc_counters(folder):
+    """Per sweep kernel: the mean over its dispatches of the counters of one
+    rocprofv3 --pmc pass (PMC_COUNTERS), with the L2 hit rate (TCC hits over
+    hits and misses), the shares of wave cycles spent waiting for anything
+    (SQ_WAIT_ANY: memory and dependencies) and waiting to issue
+    (SQ_WAIT_INST_ANY), both over SQ_WAVE_CYCLES (all in quad-cycles), and
+    the texture-address units' busy share (TA_BUSY_avr, the mean over the
+    units, over the busy cycles of one XCD: GRBM_GUI_ACTIVE / N_XCD),
+    written to profiles/sweep3_zipf10m_counters.json."""
+    per = {}
+    for r in _csv_rows(folder, "counter_collection.csv"):
+        name = _timing_name(r["Kernel_Name"])
+        if not name or r.get("Counter_Name") not in PMC_COUNTERS:
+            continue
+        per.setdefault(name, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    out = {"workload": "zipf10m bench step (100k nodes, 10M edges, 36 three-edge motifs, delta 3600)",
+           "kernel_src_sha256": kernel_src_sha(),
+           "commands": [f"rocprofv3 --pmc {' '.join(PMC_COUNTERS)} -f csv -d REPO/{folder} -o run -- "
+                        "python3 REPO/bench.py --profile-run",
+                        f"python3 bench.py --pmc-counters {folder}"],
+           "kernels": {}}
+    for name, cs in sorted(per.items()):
+        mean = {c: sum(v) / len(v) for c, v in cs.items()}
+        rec = {"dispatches_averaged": max(len(v) for v in cs.values()), "mean_per_dispatch": mean}
+        h, mi = mean.get("TCC_HIT_sum"), mean.get("TCC_MISS_sum")
+        if h is not None and mi is not None and h + mi > 0:
+            rec["l2_hit_rate"] = h / (h + mi)
+        wc = mean.get("SQ_WAVE_CYCLES")
+        for c, key in (("SQ_WAIT_ANY", "wave_cycles_waiting_share"),
+                       ("SQ_WAIT_INST_ANY", "wave_cycles_waiting_issue_share")):
+            if mean.get(c) is not None and wc:
+                rec[key] = mean[c] / wc
+        ta, g = mean.get("TA_BUSY_avr"), mean.get("GRBM_GUI_ACTIVE")
+        if ta is not None and g:
+            rec["ta_busy_share"] = ta / (g / N_XCD)
+        out["kernels"][name] = rec
+        print(name, {k: round(v, 3) for k, v in rec.items() if isinstance(v, float)}, file=sys.stderr)
+    with open(os.path.join(ROOT, "profiles", "sweep3_zipf10m_counters.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+
+
 def kt_summary(folder):
     """Kernel-trace summary of a --profile-run: per kernel, calls, total and
     average duration; for the sweep kernels only the timed step's dispatches
@@ -913,6 +960,8 @@ def main():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic records from two rocprofv3 --pmc -f csv runs and exit")
     ap.add_argument("--kt-summary", metavar="DIR", help="write the kernel-trace summary of a --profile-run and exit")
+    ap.add_argument("--pmc-counters", metavar="DIR",
+                    help="write the L2, wait and TA counter summary of a rocprofv3 --pmc pass and exit")
     ap.add_argument("--latency-repeats", type=int, default=50)
     args = ap.parse_args()
     if args.pmc_summary:
@@ -920,6 +969,9 @@ def main():
         return
     if args.kt_summary:
         kt_summary(args.kt_summary)
+        return
+    if args.pmc_counters:
+        pmc_counters(args.pmc_counters)
         return
     if args.serve_merge:
         lines = [json.loads(open(f).read().strip().splitlines()[-1]) for f in args.serve_merge]
