@@ -659,7 +659,7 @@ def sweep_bytes(exact, ests):
     return out
 
 
-def sweep_roofline(exact, ests, kern, crit, alone, steps):
+def sweep_roofline(exact, ests, kern, crit, alone, steps, traffic_records=True):
     """Roofline entry of the dominant sweep kernel.  The kernels of one pass
     run concurrently on forked streams and share the CUs, so each one's
     duration in the timed steps spans most of the pass; the dominant kernel
@@ -670,8 +670,9 @@ def sweep_roofline(exact, ests, kern, crit, alone, steps):
     plain copy) / its average launch duration in the timed steps; the
     algorithmic figure (census x per-unit bytes) is reported beside it.  When
     the record is stale (kernel source changed since the counters were
-    taken) traffic is null and frac falls back to the algorithmic figure,
-    with frac_basis saying so."""
+    taken), or when the step is not the workload the records were taken on
+    (traffic_records false), traffic is null and frac falls back to the
+    algorithmic figure, with frac_basis saying so."""
     bps = sweep_bytes(exact, ests)  # algorithmic bytes per step
     timed = {k: v for k, v in kern.items() if k in bps and v[1] > 0}
     if not timed:
@@ -681,7 +682,7 @@ def sweep_roofline(exact, ests, kern, crit, alone, steps):
         per[k] = {"launches_per_step": n / steps, "avg_launch_ms": ms / n,
                   "algorithmic_bytes_per_launch": bps[k] * steps / n,
                   "algorithmic_GBs": bps[k] * steps / (ms / 1e3) / 1e9}
-        tr = traffic_record(k)
+        tr = traffic_record(k) if traffic_records else None
         if tr is not None:
             per[k]["traffic_bytes_per_launch"] = tr
             per[k]["hbm_GBs"] = tr / (ms / n / 1e3) / 1e9
@@ -691,7 +692,10 @@ def sweep_roofline(exact, ests, kern, crit, alone, steps):
     if traffic is not None:
         ach, basis = d["hbm_GBs"], "rocprofv3 FETCH_SIZE + WRITE_SIZE per launch / launch time"
     else:
-        ach, basis = d["algorithmic_GBs"], "algorithmic bytes per launch / launch time (counter record stale)"
+        ach, basis = d["algorithmic_GBs"], ("algorithmic bytes per launch / launch time (counter record stale)"
+                                            if traffic_records else
+                                            "algorithmic bytes per launch / launch time (no counter record of "
+                                            "this workload)")
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "traffic": traffic, "frac_basis": basis, "kernel": dom, "avg_launch_ms": d["avg_launch_ms"],
             "launches": timed[dom][1],
@@ -1120,7 +1124,8 @@ def main():
     lat[k_tri]["edges_per_s_per_query_at_p50"] = g.m / (lat[k_tri]["p50_ms"] / 1e3)
     log("latency repeats done")
     G.free()
-    roofline = sweep_roofline(census, ests, kern, crit, alone, args.steps)
+    roofline = sweep_roofline(census, ests, kern, crit, alone, args.steps,
+                              traffic_records=args.workload == "zipf10m")
     if roofline:
         roofline["exact_tables"] = tables
     out = {
