@@ -403,9 +403,12 @@ typedef struct {
  * (exact counts of three-edge motifs on the same graph and delta share one
  * sweep; estimates of three-edge motifs on the same graph share the launch
  * sequence of tm_estimate_mixed, enqueued on the slot's stream rather than
- * captured, whatever their motifs, deltas, c, p and seeds; a lone estimate
- * takes tm_estimate_multi's sweep), up to 256 per batch, and starts it on a
- * free slot.  A batch is charged the
+ * captured, whatever their motifs, deltas, c, p and seeds; a lone estimate,
+ * or one on a heavy graph, takes tm_estimate_multi's sweep), up to 256 per
+ * batch, and starts it on a
+ * free slot; batches on graphs with at least an eighth of the largest
+ * graph's edges take at most half the slots while lighter graphs are
+ * resident.  A batch is charged the
  * device bytes its path allocates, and the bytes it really allocated are
  * measured and reported beside the charge (tm_result, tm_server_stats); the
  * grow-only workspaces a slot thread keeps between batches are measured

@@ -445,6 +445,29 @@ tm_status estimate_impl(const tm_graph *g, const tm_motif *M, int64_t delta, int
     if (!estimate) return TM_EINVAL;
     KeptAnchors K;
     TM_TRY(select_kept(g, L, seed, p, st, K));
+    if (delta > TM_GENERIC_LDS_DELTA && !(info && (info->hist_lo || info->hist_hi))) {
+        // no histogram asked for and none that fits in LDS: the kept
+        // instances' fixed-point weights are summed instead
+        DevBuf wfx, acc;
+        TM_TRY(wfx.alloc((size_t)(delta + 1) * 8));
+        const int64_t ns = K.nslots;
+        TM_TRY(acc.alloc((size_t)(4 + 2 * (ns > 0 ? ns : 1)) * 8));
+        TM_HIP(hipMemsetAsync(acc.p, 0, acc.bytes, st));
+        TM_TRY(tm_fx_weights(delta, L, wfx.as<uint64_t>(), st));
+        uint64_t *total = acc.as<uint64_t>(), *wsum = total + 2, *slot_tot = total + 4;
+        if (K.nA > 0) {
+            AnchorSet A{K.nA, K.apos.as<int64_t>(), K.win_end.as<int64_t>(), K.slot.as<int32_t>(), nullptr};
+            TM_TRY(tm_count_generic_weighted(g, P, delta, A, total, slot_tot, wfx.as<uint64_t>(), wsum, st));
+        }
+        uint64_t tw[4];
+        std::vector<uint64_t> stot((size_t)(2 * (ns > 0 ? ns : 1)));
+        TM_HIP(hipMemcpyAsync(tw, total, 32, hipMemcpyDeviceToHost, st));
+        if (ns > 0) TM_HIP(hipMemcpyAsync(stot.data(), slot_tot, (size_t)ns * 16, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+        if (info) TM_TRY(fill_info(g, L, seed, p, K, stot, nullptr, nullptr, delta, tw, info, st));
+        *estimate = tm_fx_estimate(tw[2], tw[3], p);
+        return TM_OK;
+    }
     DevBuf hist, acc;
     TM_TRY(hist.alloc((size_t)(delta + 1) * 16));
     int64_t ns = K.nslots;
@@ -779,14 +802,22 @@ tm_status estimate_stream_impl(const int32_t *src, const int32_t *dst, const int
         }
     }
     if (!gen.empty() && delta > TM_MAX_HIST_DELTA) return TM_EUNSUPPORTED;
-    const size_t ng = gen.size(), nbins = (size_t)delta + 1;
-    DevBuf ghist, gtot, gz;
+    // generic motifs: duration histograms summed over the windows and weighted
+    // at the end, or, above the LDS histogram size, fixed-point weight sums
+    // (as tm_estimate does for the same delta)
+    const bool wsums = delta > TM_GENERIC_LDS_DELTA;
+    const size_t ng = gen.size(), nbins = wsums ? 1 : (size_t)delta + 1;
+    DevBuf ghist, gtot, gz, gwfx;
     if (ng > 0) {
         TM_TRY(ghist.alloc(ng * nbins * 16));
         TM_TRY(gtot.alloc(ng * 16));
         TM_TRY(gz.alloc(ng * 8));
         TM_HIP(hipMemsetAsync(ghist.p, 0, ghist.bytes, st));
         TM_HIP(hipMemsetAsync(gtot.p, 0, gtot.bytes, st));
+        if (wsums) {
+            TM_TRY(gwfx.alloc(((size_t)delta + 1) * 8));
+            TM_TRY(tm_fx_weights(delta, L, gwfx.as<uint64_t>(), st));
+        }
     }
     // the stream is read on the host: device arrays are refused
     for (const void *ptr : {(const void *)src, (const void *)dst, (const void *)t}) {
@@ -865,8 +896,11 @@ tm_status estimate_stream_impl(const int32_t *src, const int32_t *dst, const int
             const AnchorSet A{gw->m, nullptr, nullptr, nullptr, nullptr};
             for (size_t x = 0; x < ng && r == TM_OK; ++x) {
                 uint64_t *hlo = ghist.as<uint64_t>() + x * nbins * 2, *hhi = hlo + nbins;
-                r = tm_count_generic(gw, plans[(size_t)gen[x]], delta, A, gtot.as<uint64_t>() + 2 * x, nullptr, hlo,
-                                     hhi, nullptr, nullptr, st);
+                r = wsums ? tm_count_generic_weighted(gw, plans[(size_t)gen[x]], delta, A,
+                                                      gtot.as<uint64_t>() + 2 * x, nullptr, gwfx.as<uint64_t>(), hlo,
+                                                      st)
+                          : tm_count_generic(gw, plans[(size_t)gen[x]], delta, A, gtot.as<uint64_t>() + 2 * x,
+                                             nullptr, hlo, hhi, nullptr, nullptr, st);
             }
             // the counts read the window graph until they finish
             const hipError_t e = hipStreamSynchronize(st);
@@ -883,15 +917,24 @@ tm_status estimate_stream_impl(const int32_t *src, const int32_t *dst, const int
         }
     }
     std::vector<double> gz_h(ng);
-    std::vector<uint64_t> gtot_h(2 * ng);
+    std::vector<uint64_t> gtot_h(2 * ng), gw_h(2 * ng);
     if (ng > 0) {
-        for (size_t x = 0; x < ng; ++x) {
-            uint64_t *hlo = ghist.as<uint64_t>() + x * nbins * 2, *hhi = hlo + nbins;
-            TM_TRY(tm_weight(hlo, hhi, delta, L, p, gz.as<double>() + x, st));
+        if (wsums) {
+            // per motif, its weight sum is the first two words of its slot
+            for (size_t x = 0; x < ng; ++x)
+                TM_HIP(hipMemcpyAsync(&gw_h[2 * x], ghist.as<uint64_t>() + x * nbins * 2, 16,
+                                      hipMemcpyDeviceToHost, st));
+        } else {
+            for (size_t x = 0; x < ng; ++x) {
+                uint64_t *hlo = ghist.as<uint64_t>() + x * nbins * 2, *hhi = hlo + nbins;
+                TM_TRY(tm_weight(hlo, hhi, delta, L, p, gz.as<double>() + x, st));
+            }
+            TM_HIP(hipMemcpyAsync(gz_h.data(), gz.p, ng * 8, hipMemcpyDeviceToHost, st));
         }
-        TM_HIP(hipMemcpyAsync(gz_h.data(), gz.p, ng * 8, hipMemcpyDeviceToHost, st));
         TM_HIP(hipMemcpyAsync(gtot_h.data(), gtot.p, ng * 16, hipMemcpyDeviceToHost, st));
         TM_HIP(hipStreamSynchronize(st));
+        if (wsums)
+            for (size_t x = 0; x < ng; ++x) gz_h[x] = tm_fx_estimate(gw_h[2 * x], gw_h[2 * x + 1], p);
     }
     for (size_t x = 0; x < ng; ++x) {
         const int32_t i = gen[x];

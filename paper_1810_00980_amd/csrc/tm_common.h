@@ -426,6 +426,33 @@ tm_status tm_count_generic(const tm_graph *g, const MotifPlan &P, int64_t delta,
 tm_status tm_weight(const uint64_t *hist_lo, const uint64_t *hist_hi, int64_t delta, int64_t L,
                     double p, double *out, hipStream_t st);
 
+// Largest delta whose duration histogram the generic counter keeps in LDS;
+// above it the estimate paths sum fixed-point weights instead
+// (tm_count_generic_weighted) rather than building a histogram in global
+// memory with one atomic add per instance.
+constexpr int64_t TM_GENERIC_LDS_DELTA = 8191;
+
+// The generic counter's totals (as tm_count_generic, no histogram) and the
+// sum of the instances' fixed-point weights wfx[t_l - t_1] (delta + 1 of
+// them, tm_fx_weights) added to wsum[0] (low word) and wsum[1] (high word).
+tm_status tm_count_generic_weighted(const tm_graph *g, const MotifPlan &P, int64_t delta, const AnchorSet &A,
+                                    uint64_t *total, uint64_t *slot_tot, const uint64_t *wfx, uint64_t *wsum,
+                                    hipStream_t st);
+
+// wfx[d] = round(2^52 L / (L - d)) for d = 0 .. delta (L >= 2 delta): the
+// estimator's weight 1 / (1 - d / L) in 52-bit fixed point, the same table as
+// the sweeps'.
+tm_status tm_fx_weights(int64_t delta, int64_t L, uint64_t *wfx, hipStream_t st);
+
+// An estimate from a 128-bit sum of fixed-point weights: (hi 2^64 + lo) 2^-52 / p,
+// in the same operation order as the sweep paths.
+inline double tm_fx_estimate(uint64_t lo, uint64_t hi, double p) {
+    double x = (double)hi * 18446744073709551616.0;
+    x = x + (double)lo;
+    x = x * (1.0 / 4503599627370496.0);
+    return x / p;
+}
+
 // ------------------------------------------------------------ 3-edge sweep
 
 // The 36 motifs with three edges on two or three nodes, indexed 0..35 by the

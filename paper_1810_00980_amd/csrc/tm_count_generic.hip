@@ -28,17 +28,36 @@
 namespace {
 
 constexpr int CG_TPB = 256;
-constexpr int64_t CG_LDS_BINS = 8192;  // 64 KB of u64 bins per block
+constexpr int64_t CG_LDS_BINS = TM_GENERIC_LDS_DELTA + 1;  // 64 KB of u64 bins per block
 
-// histogram modes
-constexpr int HM_NONE = 0, HM_GLOBAL = 1, HM_LDS = 2;
+// histogram modes; HM_WEIGHT: no histogram, each instance adds the
+// fixed-point weight of its duration (hlo: the delta + 1 weights) to a
+// 128-bit per-lane sum, added at the end to hhi[0..1]
+constexpr int HM_NONE = 0, HM_GLOBAL = 1, HM_LDS = 2, HM_WEIGHT = 3;
 
 extern __shared__ uint64_t cg_bins[];
 
+struct Acc {
+    uint64_t lo, hi;    // instances
+    uint64_t wlo, whi;  // HM_WEIGHT: their fixed-point weights
+    __device__ void add(uint64_t v) {
+        uint64_t s = lo + v;
+        hi += (s < lo) ? 1 : 0;
+        lo = s;
+    }
+    __device__ void addw(uint64_t w) {
+        uint64_t s = wlo + w;
+        whi += (s < wlo) ? 1 : 0;
+        wlo = s;
+    }
+};
+
+// one instance of duration d
 template <int HM>
-__device__ inline void hist_add(uint64_t *hlo, uint64_t *hhi, int64_t d) {
+__device__ inline void hist_add(uint64_t *hlo, uint64_t *hhi, int64_t d, Acc &acc) {
     if constexpr (HM == HM_LDS) atomicAdd((unsigned long long *)&cg_bins[d], 1ull);
     else if constexpr (HM == HM_GLOBAL) tm_atomic_add_u128(hlo + d, hhi + d, 1, 0);
+    else if constexpr (HM == HM_WEIGHT) acc.addw(hlo[d]);
 }
 
 struct Binding {
@@ -139,15 +158,6 @@ __device__ inline Range open_level(const DevGraph &G, const MotifPlan &P, int r,
     return R;
 }
 
-struct Acc {
-    uint64_t lo, hi;
-    __device__ void add(uint64_t v) {
-        uint64_t s = lo + v;
-        hi += (s < lo) ? 1 : 0;
-        lo = s;
-    }
-};
-
 template <int HIST>
 __device__ inline void count_last(const DevGraph &G, const Range &R, const Binding &f, int64_t t1, Acc &acc,
                                   uint64_t *hlo, uint64_t *hhi) {
@@ -158,7 +168,7 @@ __device__ inline void count_last(const DevGraph &G, const Range &R, const Bindi
             PairEnt e = G.up_ent[R.cur];
             for (int64_t i = R.cur; i < R.end; ++i) {
                 const PairEnt nx = G.up_ent[i + 1];
-                if ((uint32_t)(nx.c0 - e.c0) == R.want) hist_add<HIST>(hlo, hhi, e.t - t1);
+                if ((uint32_t)(nx.c0 - e.c0) == R.want) hist_add<HIST>(hlo, hhi, e.t - t1, acc);
                 e = nx;
             }
         }
@@ -169,7 +179,7 @@ __device__ inline void count_last(const DevGraph &G, const Range &R, const Bindi
     for (int64_t i = R.cur; i < R.end; ++i) {
         if (!f.used(R.nbr[i])) {
             ++c;
-            if (HIST) hist_add<HIST>(hlo, hhi, R.t[i] - t1);
+            if (HIST) hist_add<HIST>(hlo, hhi, R.t[i] - t1, acc);
         }
     }
     acc.add(c);
@@ -217,7 +227,7 @@ __device__ inline void count_anchor(const DevGraph &G, const MotifPlan &P, int64
         // every edge of an instance lies in the window, the first one too
         if (t1 <= win_end) {
             acc.add(1);
-            if (HIST) hist_add<HIST>(hlo, hhi, 0);
+            if (HIST) hist_add<HIST>(hlo, hhi, 0, acc);
         }
     } else {
         Binding f{-1, -1, -1, -1, -1};
@@ -250,7 +260,7 @@ __global__ void __launch_bounds__(CG_TPB) k_count_generic(DevGraph G, MotifPlan 
         for (int64_t k = threadIdx.x; k <= delta; k += blockDim.x) cg_bins[k] = 0;
         __syncthreads();
     }
-    uint64_t lo = 0, hi = 0;
+    uint64_t lo = 0, hi = 0, wlo = 0, whi = 0;
     while (true) {
         int64_t base = 0;
         if (lane == 0) base = (int64_t)atomicAdd(counter, (unsigned long long)TM_WAVE);
@@ -260,9 +270,10 @@ __global__ void __launch_bounds__(CG_TPB) k_count_generic(DevGraph G, MotifPlan 
         if (i >= nA) continue;
         int64_t pos = A.pos ? A.pos[i] : i;
         int64_t we = A.win_end ? A.win_end[i] : LLONG_MAX;
-        Acc acc{0, 0};
+        Acc acc{0, 0, 0, 0};
         count_anchor<LEN, HIST>(G, P, pos, we, delta, acc, hlo, hhi);
         tm_add_u128(lo, hi, acc.lo, acc.hi);
+        if constexpr (HIST == HM_WEIGHT) tm_add_u128(wlo, whi, acc.wlo, acc.whi);
         if (per_anchor) {
             per_anchor[i] = acc.lo;
             if (acc.hi) atomicOr(flag, 1);
@@ -274,6 +285,10 @@ __global__ void __launch_bounds__(CG_TPB) k_count_generic(DevGraph G, MotifPlan 
     }
     wave_reduce_u128(lo, hi);
     if ((threadIdx.x & (TM_WAVE - 1)) == 0 && total) tm_atomic_add_u128(total, total + 1, lo, hi);
+    if constexpr (HIST == HM_WEIGHT) {
+        wave_reduce_u128(wlo, whi);
+        if ((threadIdx.x & (TM_WAVE - 1)) == 0) tm_atomic_add_u128(hhi, hhi + 1, wlo, whi);
+    }
     if constexpr (HIST == HM_LDS) {
         __syncthreads();
         for (int64_t k = threadIdx.x; k <= delta; k += blockDim.x) {
@@ -340,7 +355,7 @@ __global__ void __launch_bounds__(CG_TPB)
         __syncthreads();
     }
     const Level1 L1 = level1_list(G, P);
-    uint64_t lo = 0, hi = 0;
+    uint64_t lo = 0, hi = 0, wlo = 0, whi = 0;
     while (true) {
         int64_t base = 0;
         if (lane == 0) base = (int64_t)atomicAdd(counter, (unsigned long long)TM_WAVE);
@@ -364,7 +379,7 @@ __global__ void __launch_bounds__(CG_TPB)
         Binding f{-1, -1, -1, -1, -1};
         f.set(0, G.es_src[pos]);
         f.set(1, G.es_dst[pos]);
-        Acc acc{0, 0};
+        Acc acc{0, 0, 0, 0};
         bool ok = true;
         int64_t tj;
         if (L1.nbr != nullptr) {
@@ -381,6 +396,7 @@ __global__ void __launch_bounds__(CG_TPB)
         if (ok) levels<2, LEN, HIST>(G, P, f, tj, t1, thi, acc, hlo, hhi);
         if ((acc.lo | acc.hi) == 0) continue;
         tm_add_u128(lo, hi, acc.lo, acc.hi);
+        if constexpr (HIST == HM_WEIGHT) tm_add_u128(wlo, whi, acc.wlo, acc.whi);
         if (per_anchor) {
             unsigned long long old = atomicAdd((unsigned long long *)(per_anchor + i), (unsigned long long)acc.lo);
             if (acc.hi || old + acc.lo < old) atomicOr(flag, 1);
@@ -392,6 +408,10 @@ __global__ void __launch_bounds__(CG_TPB)
     }
     wave_reduce_u128(lo, hi);
     if (lane == 0 && total) tm_atomic_add_u128(total, total + 1, lo, hi);
+    if constexpr (HIST == HM_WEIGHT) {
+        wave_reduce_u128(wlo, whi);
+        if (lane == 0) tm_atomic_add_u128(hhi, hhi + 1, wlo, whi);
+    }
     if constexpr (HIST == HM_LDS) {
         __syncthreads();
         for (int64_t k = threadIdx.x; k <= delta; k += blockDim.x) {
@@ -543,6 +563,20 @@ tm_status tm_count_generic(const tm_graph *g, const MotifPlan &P, int64_t delta,
             return TM_EUNSUPPORTED;
     }
 #undef TM_LEN_CASE
+}
+
+tm_status tm_count_generic_weighted(const tm_graph *g, const MotifPlan &P, int64_t delta, const AnchorSet &A,
+                                    uint64_t *total, uint64_t *slot_tot, const uint64_t *wfx, uint64_t *wsum,
+                                    hipStream_t st) {
+    DevGraph G = dev_view(g);
+    uint64_t *w = const_cast<uint64_t *>(wfx);  // read only (the kernels' histogram argument)
+    switch (P.l) {
+        case 1: return launch_len<1, HM_WEIGHT>(g->device, G, P, delta, A, total, slot_tot, w, wsum, nullptr, nullptr, st);
+        case 2: return launch_len<2, HM_WEIGHT>(g->device, G, P, delta, A, total, slot_tot, w, wsum, nullptr, nullptr, st);
+        case 3: return launch_len<3, HM_WEIGHT>(g->device, G, P, delta, A, total, slot_tot, w, wsum, nullptr, nullptr, st);
+        case 4: return launch_len<4, HM_WEIGHT>(g->device, G, P, delta, A, total, slot_tot, w, wsum, nullptr, nullptr, st);
+        default: return TM_EUNSUPPORTED;
+    }
 }
 
 tm_status tm_weight(const uint64_t *hist_lo, const uint64_t *hist_hi, int64_t delta, int64_t L, double p, double *out,

@@ -7,12 +7,18 @@
 // three-edge motifs on the same graph and delta share one sweep; estimates of
 // three-edge motifs on the same graph share one persistent launch sequence,
 // whatever their motifs, deltas, c, p and seeds (each is its own estimator
-// in the mixed batch; a lone one takes the plain weighted sweep).  It
+// in the mixed batch; a lone one, or one on a heavy graph, takes the plain
+// weighted sweep).  It
 // reserves the batch's device workspace from the budget and hands the batch
 // to the slot.  Each slot is a host thread with its own
 // HIP stream (default priority), so batches on different slots overlap on the
 // device; finishing a batch returns its workspace to the budget and wakes the
 // dispatcher, which admits waiting queries as memory and slots free up.
+// Batches on the heavy graphs (an eighth or more of the largest graph's
+// edges, when lighter graphs are resident too) take at most half the slots:
+// a heavy query fills the device by itself, so more of them at once only
+// stretch each other, while the queries on small graphs would wait behind
+// them.
 //
 // A batch is charged the device bytes its path allocates (every buffer of
 // that path, at the sizes the graph and queries fix, with upper bounds where
@@ -109,11 +115,15 @@ int64_t batch_ws_bytes(const tm_graph *g, const std::vector<tm_query> &b) {
     return bytes;
 }
 
-bool shareable(const tm_query &a, const tm_query &b) {
+// heavy: the graph of the query is heavy (see tm_server::is_heavy)
+bool shareable(const tm_query &a, const tm_query &b, bool heavy) {
     if (a.graph != b.graph || a.kind != b.kind) return false;
     if (tm_sweep_code_of(&a.motif) < 0 || tm_sweep_code_of(&b.motif) < 0) return false;
-    if (a.kind == 0) return a.delta == b.delta;
-    return true;  // estimates: one estimator each in the mixed batch
+    if (a.kind == 0) return a.delta == b.delta;  // one sweep counts all
+    // estimates: one estimator each in the mixed batch, which saves launches
+    // and host round trips; on a heavy graph each estimator's own work
+    // dominates, and the plain sweep of each serves them as well
+    return !heavy;
 }
 
 }  // namespace
@@ -133,6 +143,16 @@ struct tm_server {
     std::vector<bool> release_req;     // asked to free what it holds
     std::vector<hipStream_t> streams;
     std::vector<bool> slot_busy;
+    std::vector<bool> slot_heavy;      // the running batch is on a heavy graph
+    // heavy: at least an eighth of the edges of the largest graph added,
+    // when some graph is lighter than that (one size class: none is heavy)
+    bool is_heavy(const tm_graph *g) const {
+        int64_t mx = 0;
+        for (const tm_graph *h : graphs) mx = std::max<int64_t>(mx, h->m);
+        bool any_light = false;
+        for (const tm_graph *h : graphs) any_light = any_light || 8 * h->m < mx;
+        return any_light && 8 * g->m >= mx;
+    }
     std::condition_variable cv_slot;
     int64_t budget = 0, in_use = 0, peak = 0, next_ticket = 1;
     int64_t submitted = 0, completed = 0, rejected = 0, batches = 0;
@@ -186,11 +206,18 @@ struct tm_server {
                     slot = (int)i;
                     break;
                 }
-            // oldest admissible query: first in FIFO whose workspace fits
+            // oldest admissible query: first in FIFO whose workspace fits;
+            // a query on a heavy graph waits while half the slots run heavy
+            // batches, so that queries on the small graphs keep slots
+            int heavy_running = 0;
+            for (size_t k = 0; k < slot_busy.size(); ++k) heavy_running += slot_busy[k] && slot_heavy[k];
+            const int heavy_cap = std::max<int>(1, (int)slot_busy.size() / 2);
             bool admitted = false;
             for (size_t qi = 0; qi < queue.size(); ++qi) {
                 const Pending &head = queue[qi];
                 const tm_graph *g = graphs[(size_t)head.q.graph];
+                const bool heavy = is_heavy(g);
+                if (heavy && heavy_running >= heavy_cap) continue;
                 int64_t need = batch_ws_bytes(g, {head.q});
                 if (need > budget) {
                     tm_result r;
@@ -217,7 +244,7 @@ struct tm_server {
                 bq.push_back(head.q);
                 queue.erase(queue.begin() + (long)qi);
                 for (size_t k = 0; k < queue.size();) {
-                    bool take = batch.size() < TM_SERVER_MAX_BATCH && shareable(batch[0].q, queue[k].q);
+                    bool take = batch.size() < TM_SERVER_MAX_BATCH && shareable(batch[0].q, queue[k].q, heavy);
                     if (take) {
                         // a merged query must keep the batch within what is left
                         bq.push_back(queue[k].q);
@@ -239,6 +266,7 @@ struct tm_server {
                 in_use += need;
                 peak = std::max(peak, in_use);
                 slot_busy[(size_t)slot] = true;
+                slot_heavy[(size_t)slot] = heavy;
                 slot_bytes[(size_t)slot] = need;
                 slot_work[(size_t)slot] = std::move(batch);
                 ++batches;
@@ -373,6 +401,7 @@ extern "C" tm_status tm_server_create(int32_t slots, int64_t budget_bytes, tm_se
     S->slot_held.assign((size_t)slots, 0);
     S->release_req.assign((size_t)slots, false);
     S->slot_busy.assign((size_t)slots, false);
+    S->slot_heavy.assign((size_t)slots, false);
     for (int i = 0; i < slots; ++i) {
         hipStream_t st;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {

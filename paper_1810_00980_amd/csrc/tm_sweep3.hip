@@ -739,6 +739,11 @@ int tm_sweep_code_of(const tm_motif *M) {
     return -1;
 }
 
+tm_status tm_fx_weights(int64_t delta, int64_t L, uint64_t *wfx, hipStream_t st) {
+    hipLaunchKernelGGL(k_weights_fx, dim3(tm_blocks(delta + 1, 256)), dim3(256), 0, st, delta, L, wfx);
+    return tm_hip_status(hipGetLastError());
+}
+
 // mode: 0 counts, 1 counts + weights (needs L), 2 counts + histograms.
 // out_dev: 36 x 4 u64 (count lo/hi, weight lo/hi), zeroed here.
 // hist_dev: 36 x (delta+1) x 2 u64 (mode 2), zeroed here.

@@ -575,6 +575,20 @@ def test_generic_hist_both_bin_stores(tm):
         z = tm.estimate(G, ti.BIFAN, delta, 10, 0.5, 3)
         o = oracle.estimate(g.src, g.dst, g.t, ti.BIFAN, delta, 10, 0.5, 3)
         assert close(z, o["Z"]), (delta, z, o["Z"])
+    # above the LDS bins an estimate without a histogram sums fixed-point
+    # weights: the oracle's value, the histogram path's within 1e-12 and the
+    # same kept count, and the streamed estimate to the last bit
+    o_ = np.argsort(g.t, kind="stable")
+    for delta in (8192, 20000):
+        say("generic weighted sums", delta)
+        est, kc, _ = tm.estimate_stream(g.src[o_], g.dst[o_], g.t[o_], g.n, [ti.CYCLE4, ti.BIFAN], delta, 10, 0.5, 3)
+        for k, M in enumerate((ti.CYCLE4, ti.BIFAN)):
+            z = tm.estimate(G, M, delta, 10, 0.5, 3)
+            r = tm.estimate(G, M, delta, 10, 0.5, 3, info=True)
+            o = oracle.estimate(g.src, g.dst, g.t, M, delta, 10, 0.5, 3)
+            assert close(z, o["Z"]) and close(r["Z"], z), (M, delta, z, r["Z"], o["Z"])
+            assert r["kept_count"] == int(o["win_counts"].sum()) == kc[k], (M, delta)
+            assert est[k] == z, (M, delta, est[k], z)
 
 
 @pytest.fixture(scope="module")
