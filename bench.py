@@ -479,7 +479,8 @@ def run_four_edge(args):
 
 def run_serve(args):
     """Poisson streams of count/estimate queries over the 8 resident graphs of
-    1e4 .. 1e8 edges at several arrival rates, served by the
+    1e4 .. 1e8 edges (or the first --serve-graphs of them) at several arrival
+    rates, served by the
     continuous-batching server (4 slots, a device-memory budget on the
     workspace it measures) and, for comparison, one query at a time on the
     GPU in arrival order.  The value is the server's throughput at the
@@ -489,7 +490,7 @@ def run_serve(args):
     import torch
     import paper_1810_00980_amd as tm
     Gs, sizes = [], []
-    for i in range(8):
+    for i in range(args.serve_graphs):
         s_, d_, t_, n = ti.serving_graph_device(i)
         Gs.append(tm.load_graph(s_, d_, t_, n))
         sizes.append(int(s_.numel()))
@@ -519,6 +520,9 @@ def run_serve(args):
             log("qps", qps, "server")
             srv, res = serve_once(tm, Gs, sizes, qs, slots, budget)
             srv["results"] = [str(r["count"]) if q["kind"] == 0 else r["estimate"] for q, r in zip(qs, res)]
+            srv["latency_ms"] = [round(r["latency_ms"], 3) for r in res]
+            srv["batch_size"] = [r["batch_size"] for r in res]
+            srv["graph_edges"] = [sizes[q["graph"]] for q in qs]
             phases.append({"qps": qps, "phase": "server", "queries": len(qs), "edges": edges, **srv})
             log("qps", qps, "server edges/s", f"{srv['edges_per_s']:.3e}", "p50", f"{srv['p50_ms']:.1f}", "p99",
                 f"{srv['p99_ms']:.1f}")
@@ -537,13 +541,15 @@ def run_serve(args):
             wall = time.perf_counter() - t0
             lat_ms = np.sort(np.array(lat) * 1e3)
             one = {"p50_ms": _pct(lat_ms, 0.5), "p99_ms": _pct(lat_ms, 0.99), "wall_s": wall,
-                   "edges_per_s": edges / wall, "results": got}
+                   "edges_per_s": edges / wall, "results": got, "latency_ms": [round(x * 1e3, 3) for x in lat],
+                   "graph_edges": [sizes[q["graph"]] for q in qs]}
             phases.append({"qps": qps, "phase": "one_at_a_time", "queries": len(qs), "edges": edges, **one})
             log("qps", qps, "one at a time edges/s", f"{one['edges_per_s']:.3e}", "p50", f"{one['p50_ms']:.1f}",
                 "p99", f"{one['p99_ms']:.1f}")
     for G in Gs:
         G.free()
-    cfg = {"workload": f"{args.queries} Poisson queries per arrival rate over 8 graphs of 1e4..1e8 edges "
+    cfg = {"workload": f"{args.queries} Poisson queries per arrival rate over the {args.serve_graphs} graphs of "
+                       f"1e4..{sizes[-1]:.2g} edges of the serving mix "
                        "(log-spaced, 100 edges per node, Zipf 1.8 endpoints, bursty times over "
                        "[0, max(1e6, 3m)) s); 25% exact / 75% estimate; motif uniform over 36 three-edge "
                        "motifs + 4-cycle (4-cycle, with delta <= 3600, and delta 86400 on graphs up to 4e4 "
@@ -569,8 +575,19 @@ def serve_merge(phases, cfg, target_ms):
         sw = {"qps": qps}
         for name, ph in (("server", srv), ("one_at_a_time", one)):
             if ph:
-                sw[name] = {k: v for k, v in ph.items() if k not in ("results", "qps", "phase")}
+                sw[name] = {k: v for k, v in ph.items() if k not in ("results", "latency_ms", "batch_size", "qps",
+                                                                      "phase", "graph_edges")}
                 sw[name + "_meets_p99_target"] = ph["p99_ms"] <= target_ms
+                if ph.get("latency_ms") and ph.get("graph_edges"):
+                    # queries on the graphs below an eighth of the largest one's
+                    # edges (the ones that need not wait for the large graphs)
+                    big = max(ph["graph_edges"])
+                    small = np.sort([l for l, e in zip(ph["latency_ms"], ph["graph_edges"]) if 8 * e < big])
+                    large = np.sort([l for l, e in zip(ph["latency_ms"], ph["graph_edges"]) if 8 * e >= big])
+                    sw[name]["small_graphs"] = {"queries": len(small), "p50_ms": _pct(small, 0.5),
+                                                "p99_ms": _pct(small, 0.99)}
+                    sw[name]["large_graphs"] = {"queries": len(large), "p50_ms": _pct(large, 0.5),
+                                                "p99_ms": _pct(large, 0.99)}
         if srv and one:
             diff = 0
             for a, b in zip(srv["results"], one["results"]):
@@ -952,6 +969,8 @@ def main():
     ap.add_argument("--queries", type=int, default=1000, help="serve: queries per arrival rate")
     ap.add_argument("--p99-target-ms", type=float, default=5000.0, help="serve: the stated p99 latency target")
     ap.add_argument("--serve-budget-gib", type=int, default=16, help="serve: the server's device-memory budget")
+    ap.add_argument("--serve-graphs", type=int, default=8, choices=range(1, 9),
+                    help="serve: the first K of the 8 graphs of 1e4..1e8 edges")
     ap.add_argument("--serve-phase", choices=["both", "server", "direct"], default="both",
                     help="serve: run the server, the one-at-a-time comparison, or both")
     ap.add_argument("--serve-merge", nargs="+", metavar="JSON",

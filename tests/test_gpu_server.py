@@ -120,3 +120,32 @@ def test_server_budget(tm):
     st = S.stats()
     assert st["peak_bytes"] <= big and st["rejected"] == 1 and st["over_charge"] == 0
     S.close()
+
+
+def test_server_heavy_graph_cap(tm):
+    """With a large graph resident beside small ones, batches on the large
+    graph take at most half the slots and its estimates run one per batch
+    through the plain sweep; every result is still the query's alone result
+    and every query completes."""
+    graphs = [ti.random_small_graph(6, m, 4000, 400 + m, allow_self_loops=True) for m in (500, 900)]
+    graphs.append(ti.zipf_graph(300, 20_000, 1.5, 400_000, 91))
+    Gs = [tm.load_graph(g.src, g.dst, g.t, g.n) for g in graphs]
+    rng = np.random.default_rng(11)
+    qs = make_queries(rng, len(Gs), 60)
+    # half of the queries on the large graph
+    for k, q in enumerate(qs):
+        if k % 2 == 0:
+            q["graph"] = 2
+    say("server heavy cap")
+    want = [alone(tm, Gs, q) for q in qs]
+    S = tm.Server(slots=4, budget_bytes=1 << 30)
+    ids = [S.add_graph(G) for G in Gs]
+    res = [S.wait(t) for t in [S.submit(ids[q["graph"]], q["edges"], q["delta"], q["kind"], q.get("c", 0),
+                                        q.get("p", 0.0), q.get("seed", 0)) for q in qs]]
+    for q, r, w in zip(qs, res, want):
+        assert r["status"] == 0
+        assert (r["count"] if q["kind"] == 0 else r["estimate"]) == w, q
+        if q["graph"] == 2 and q["kind"] == 1:
+            assert r["batch_size"] == 1, q
+    assert S.stats()["completed"] == len(qs)
+    S.close()
