@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtm.so")
-SOURCES = ["tm_prims.hip", "tm_graph.hip", "tm_exact.hip", "tm_count_generic.hip", "tm_sweep3.hip", "tm_star4.hip", "tm_batch.hip", "tm_server.hip", "tm_api.hip"]
+SOURCES = ["tm_prims.hip", "tm_graph.hip", "tm_exact.hip", "tm_count_generic.hip", "tm_sweep3.hip", "tm_tri_static.hip", "tm_star4.hip", "tm_batch.hip", "tm_server.hip", "tm_api.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

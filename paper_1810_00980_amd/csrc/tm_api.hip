@@ -538,7 +538,7 @@ tm_status run_sweep(const tm_graph *g, uint64_t mask, int mode, int64_t delta, i
     if (mode == 2) TM_TRY(h.reserve((size_t)36 * (delta + 1) * 16));
     if (mode == 1) TM_TRY(w.reserve((size_t)(delta + 1) * 8));
     TM_TRY(tm_sweep3(g, mask, mode, delta, windowed, s, L, seed, p, o.as<uint64_t>(), h.as<uint64_t>(),
-                     w.as<uint64_t>(), ctr.as<int64_t>(), st, kidx, win));
+                     w.as<uint64_t>(), ctr.as<int64_t>(), st, kidx, win, false, true));
     TM_HIP(hipMemcpyAsync(out->v, o.p, sizeof out->v, hipMemcpyDeviceToHost, st));
     if (mode == 2 && hist_host) {
         hist_host->assign(hist_codes.size() * (size_t)(delta + 1) * 2, 0);

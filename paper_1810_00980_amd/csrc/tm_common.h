@@ -248,6 +248,12 @@ struct tm_graph {
     // other endpoint among the owner's heaviest neighbours, built on first use
     DevBuf s4_rank;   // uint8[2 m_nl]
 
+    // static triangles (tm_tri_static.hip), built on first use by a weighted
+    // triangle estimate: nodes ascending and the pair opposite each
+    int st_state = 0;   // 0 not built, 1 built, 2 not kept (too many)
+    int64_t st_ntri = 0;
+    DevBuf st_tri;      // {uint32 u[3]; int32 q[3]}[st_ntri]
+
     // reusable per-graph workspace for queries
     DevBuf ws;
     int64_t device_bytes = 0;
@@ -332,6 +338,7 @@ void tm_prims_release_thread_ws();
 void tm_generic_release_thread_ws();
 void tm_batch_release_thread_ws();
 void tm_star4_release_thread_ws();
+void tm_tri_static_release_thread_ws();
 inline void tm_release_thread_ws() {
     tm_api_release_thread_ws();
     tm_sweep_release_thread_ws();
@@ -339,6 +346,7 @@ inline void tm_release_thread_ws() {
     tm_generic_release_thread_ws();
     tm_batch_release_thread_ws();
     tm_star4_release_thread_ws();
+    tm_tri_static_release_thread_ws();
     t_load_cache.clear();
 }
 int64_t tm_scan_ws_bytes(int64_t n);           // block sums of a scan of n values
@@ -471,13 +479,28 @@ int tm_sweep_code_of(const tm_motif *M);  // -1 when M is not one of them
 // counter_dev: 8 int64 work-queue heads.  single_stream: run the pass's
 // kernels one after another on st instead of forking them onto the calling
 // thread's side streams (which are created on first use).  Accumulators and
-// counters are cleared by a kernel, not a memset.  Allocates nothing in
-// modes 1 and 2; the exact triangle sweep of mode 0 sorts its claim order in
+// counters are cleared by a kernel, not a memset.  static_tri: in mode 1
+// over kept windows, count the triangle codes over the static triangles
+// (tm_tri_static_weight, which allocates and synchronises st) instead of the
+// incidence lists.  Allocates nothing in modes 1 and 2 without static_tri;
+// the exact triangle sweep of mode 0 sorts its claim order in
 // a per-thread workspace.
 tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask, int mode, int64_t delta, int windowed, int64_t s,
                     int64_t L, uint64_t seed, double p, uint64_t *out_dev, uint64_t *hist_dev, uint64_t *wfx_dev,
                     int64_t *counter_dev, hipStream_t st, const int32_t *kidx_dev = nullptr,
-                    uint64_t *win_dev = nullptr, bool single_stream = false);
+                    uint64_t *win_dev = nullptr, bool single_stream = false, bool static_tri = false);
+
+// Weighted triangle sums (codes 20..27 of out, added to) of the kept windows
+// of (s, L, seed, p) over the graph's static triangles, built on first use.
+// *used = false (nothing enqueued) when the graph keeps no static triangles
+// or the calling thread has switched the path off; then the incidence-list
+// sweep must count them.  Allocates per-thread workspace and reads two sizes
+// back to the host (the stream is synchronised).
+tm_status tm_tri_static_weight(const tm_graph *g, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,
+                               const uint64_t *wfx, uint64_t *out, hipStream_t st, uint64_t pass, bool *used);
+// Off for the calling thread: the query server charges its batches the
+// incidence-list sweep's bytes.
+void tm_tri_static_enable(bool on);
 
 // Largest delta for the sweep counter's histogram mode (36 histograms).
 #define TM_MAX_SWEEP_HIST_DELTA ((int64_t)1 << 20)

@@ -352,6 +352,7 @@ struct tm_server {
     void worker_loop(int slot) {
         (void)hipSetDevice(device);
         t_dev_tally.live = t_dev_tally.peak = 0;  // this thread's own allocations only
+        tm_tri_static_enable(false);              // batches are charged the list sweep's bytes
         while (true) {
             std::vector<Pending> batch;
             int64_t charged = 0;

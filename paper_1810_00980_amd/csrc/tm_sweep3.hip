@@ -454,8 +454,12 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, bool s
         for (int k = 1; k < nl; ++k) TM_HIP(hipStreamWaitEvent(side->s[k - 1], side->fork, 0));
     }
     const uint64_t pass = tm_prof_pass();
+    // weighted triangles of kept windows over the static triangles, after the
+    // other kernels are on their side streams (its set-up reads sizes back)
+    const bool defer_tri = MODE == MODE_WEIGHT && a.static_tri && todo[0].kind == 2;
     for (int k = 0; k < nl; ++k) {
         hipStream_t sk = (k == 0 || !side) ? st : side->s[k - 1];
+        if (k == 0 && defer_tri) continue;
         SweepArgs b = a;
         b.counter = a.counter + TM_SWEEP_PARTS * todo[k].kind;
         // claim ranges by XCD for the exact triangles only (their batches go
@@ -472,6 +476,19 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, bool s
             hipLaunchKernelGGL((k_sweep3<MODE, false, 0u>), dim3((unsigned)nb), dim3(SW_TPB), 0, sk, G, b);
         TM_HIP(hipGetLastError());
         tm_prof_end(tok, sk);
+    }
+    if (defer_tri) {
+        bool used = false;
+        TM_TRY(tm_tri_static_weight(g, a.delta, a.s, a.L, a.seed, a.p, a.wfx, a.out, st, pass, &used));
+        if (!used) {
+            SweepArgs b = a;
+            b.counter = a.counter + TM_SWEEP_PARTS * 2;
+            b.parts = 1;
+            void *tok = tm_prof_begin(names[MODE][2], st, pass);
+            hipLaunchKernelGGL((k_sweep3<MODE, true, 8u>), dim3((unsigned)nb), dim3(SW_TPB), 0, st, G, b);
+            TM_HIP(hipGetLastError());
+            tm_prof_end(tok, st);
+        }
     }
     for (int k = 1; side && k < nl; ++k) {
         TM_HIP(hipEventRecord(side->join[k - 1], side->s[k - 1]));
@@ -750,7 +767,7 @@ tm_status tm_fx_weights(int64_t delta, int64_t L, uint64_t *wfx, hipStream_t st)
 tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask_lo, int mode, int64_t delta, int windowed, int64_t s,
                     int64_t L, uint64_t seed, double p, uint64_t *out_dev, uint64_t *hist_dev, uint64_t *wfx_dev,
                     int64_t *counter_dev, hipStream_t st, const int32_t *kidx_dev, uint64_t *win_dev,
-                    bool single_stream) {
+                    bool single_stream, bool static_tri) {
     if (windowed == 3 && (!kidx_dev || !win_dev)) return TM_EINVAL;
     SweepArgs a;
     a.kidx = kidx_dev;
@@ -766,6 +783,7 @@ tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask_lo, int mode, int64_t 
     a.out = out_dev;
     a.counter = counter_dev;
     a.n_entries = 2 * g->m_nl;
+    a.static_tri = static_tri && mode == MODE_WEIGHT && windowed == 1;
     uint32_t wf = 0;
     if (code_mask_lo & 0xFull) wf |= 1;
     if (code_mask_lo & 0xFF0ull) wf |= 2;

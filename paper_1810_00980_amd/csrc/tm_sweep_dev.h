@@ -41,6 +41,8 @@ struct SweepArgs {
     // its XCD (blockIdx.x mod parts: work-groups are dealt to the XCDs in
     // turn) and moves on to the next range when its own is used up
     int32_t parts = 1;
+    // host side: weighted triangles of kept windows over the static triangles
+    bool static_tri = false;
 };
 
 // first unit of range q of n units in `parts` ranges

@@ -201,6 +201,53 @@ def test_sweep_estimates_all_three_edge_motifs(tm):
                 g.src, g.dst, g.t, M, delta, c, p, seed)["Z"])
 
 
+def _one_triangle_graph(seed):
+    """Nodes 0, 1, 2 only: many parallel edges of both directions on each of
+    the three pairs, with tied times, so every role and direction of every
+    triangle code occurs, plus a pendant pair without triangles."""
+    rng = np.random.default_rng(seed)
+    m = 900
+    pairs = np.array([(0, 1), (1, 2), (0, 2), (2, 3)])
+    k = rng.integers(0, 4, m)
+    flip = rng.integers(0, 2, m).astype(bool)
+    src = np.where(flip, pairs[k, 1], pairs[k, 0]).astype(np.int32)
+    dst = np.where(flip, pairs[k, 0], pairs[k, 1]).astype(np.int32)
+    t = (rng.integers(0, 300, m) * 3).astype(np.int64)  # ties
+    return ti.Graph(src, dst, t, 4)
+
+
+def test_static_triangles_equal_list_sweep(tm, monkeypatch):
+    """The weighted triangle sums over the static triangles (the three pair
+    timelines of each static triangle inside each kept window) and over the
+    incidence lists are the same integers: every estimate and kept count of
+    the 36 motifs is equal bit for bit, on bursty Zipf graphs with heavy
+    pairs, a small multigraph and a one-triangle graph with tied times; the
+    oracle checks the one-triangle case."""
+    cases = [
+        (ti.config_zipf(200_000, 2_000, 1.8, 2_000_000, 7), 3600, 30, 0.1, 0),
+        (ti.config_zipf(200_000, 2_000, 1.8, 2_000_000, 7), 3600, 10, 0.5, 3),
+        (ti.config_zipf(100_000, 500, 1.5, 300_000, 8), 500, 3, 1.0, 1),
+        (ti.random_small_graph(6, 1200, 6000, 41, allow_self_loops=True), 40, 2, 0.5, 3),
+        (_one_triangle_graph(5), 40, 3, 0.7, 2),
+        (_one_triangle_graph(6), 90, 2, 1.0, 4),
+    ]
+    for g, delta, c, p, seed in cases:
+        say("static_triangles", g.m, g.n, delta, c, p, seed)
+        G = load(tm, g)
+        monkeypatch.setenv("TM_TRI_STATIC", "0")
+        z0, k0 = tm.estimate_multi(G, THREE, delta, c, p, seed)
+        monkeypatch.delenv("TM_TRI_STATIC")
+        z1, k1 = tm.estimate_multi(G, THREE, delta, c, p, seed)
+        assert k1 == k0
+        assert z1 == z0
+        if g.n == 4:
+            assert sum(k1[i] for i, M in enumerate(THREE) if len({x for e in M for x in e}) == 3) > 0
+            for M, z, k in zip(THREE, z1, k1):
+                o = oracle.estimate(g.src, g.dst, g.t, M, delta, c, p, seed)
+                assert close(z, o["Z"]), (M, z, o["Z"])
+                assert k == int(o["win_counts"].sum()), M
+
+
 def test_estimate_q_matches_oracle(tm):
     """Algorithm 1 with b shifts and edge-proportional window probabilities
     (equation heuristic_q): the kept windows (shift, window, q_j) are the
