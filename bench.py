@@ -54,9 +54,10 @@ THREE = ti.three_edge_motifs()
 HBM_PEAK_GBS = 8000.0
 # library timing names of the three-edge sweep kernels (exact, then weighted)
 SWEEP_KERNELS = ("sweep3_fwd_count", "sweep3_tri_count", "sweep3_bwd_count",
-                 "sweep3_fwd_weight", "sweep3_tri_weight", "sweep3_bwd_weight")
+                 "sweep3_fwd_weight", "sweep3_tri_weight", "sweep3_bwd_weight",
+                 "tri_static_weight", "tri_static_prep")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1810_00980_amd", "csrc", f)
-               for f in ("tm_sweep3.hip", "tm_sweep_dev.h", "tm_common.h")]
+               for f in ("tm_sweep3.hip", "tm_sweep_dev.h", "tm_common.h", "tm_tri_static.hip")]
 
 WORKLOADS = {
     "zipf10m": dict(
@@ -662,6 +663,18 @@ def traffic_record(kernel):
 # pair timeline of n entries, plus one probe to find the pair on a change).
 # The exact-count tables let the 2-node and star counts skip their scans;
 # their algorithmic bytes are still the scans they replace.
+# The weighted triangles over static triangles (tm_tri_static_census): per
+# (triangle, kept window) unit, the window bounds of its three pair
+# timelines (six searches, 8 B each); per driver entry, its 16 B pair entry
+# and the two 16 B entries where its middle and inner ranges start; per
+# (first, last) pair visited, the inner 16 B pair entry and its 8 B weight.
+PER_UNIT = {
+    "sweep3": "16 B per anchor, 12 B per scanned entry, 8 B per weight read, 8 B per binary-search probe",
+    "tri_static_weight": "48 B per (static triangle, kept window) unit, 48 B per driver entry, "
+                         "24 B per (first, last) edge pair visited",
+}
+
+
 def sweep_bytes(exact, ests):
     out = {
         "sweep3_fwd_count": 16 * exact["anchors"] + 12 * exact["fwd_entries"],
@@ -669,6 +682,9 @@ def sweep_bytes(exact, ests):
         "sweep3_tri_count": 16 * exact["tri_anchors"] + 12 * exact["tri_entries"] + 8 * exact["tri_probes"],
         "sweep3_fwd_weight": 0, "sweep3_bwd_weight": 0, "sweep3_tri_weight": 0,
     }
+    static = [e.get("static") for e in ests]
+    if static and all(s is not None for s in static):
+        out["tri_static_weight"] = sum(48 * s["units"] + 48 * s["drivers"] + 24 * s["combos"] for s in static)
     for e in ests:
         out["sweep3_fwd_weight"] += 16 * e["anchors"] + 20 * e["fwd_entries"]
         out["sweep3_bwd_weight"] += 16 * e["anchors"] + 20 * e["bwd_entries"]
@@ -718,8 +734,7 @@ def sweep_roofline(exact, ests, kern, crit, alone, steps, traffic_records=True):
             "launches": timed[dom][1],
             "algorithmic": {"bytes_per_launch": d["algorithmic_bytes_per_launch"], "GBs": d["algorithmic_GBs"],
                             "frac": d["algorithmic_GBs"] / HBM_PEAK_GBS,
-                            "per_unit": "16 B per anchor, 12 B per scanned entry, 8 B per weight read, "
-                                        "8 B per binary-search probe"},
+                            "per_unit": PER_UNIT.get(dom, PER_UNIT["sweep3"])},
             "census": {"exact": exact, "estimates": ests}, "sweep_kernels": per,
             "sweep_kernels_ms_per_step": {k: v[0] / steps for k, v in kern.items()},
             "critical_path_ms_per_step": {k: v[0] / steps for k, v in crit.items() if v[1] > 0},
@@ -730,7 +745,8 @@ def sweep_roofline(exact, ests, kern, crit, alone, steps, traffic_records=True):
 # class mask) and the library's timing names
 TEMPLATE_NAMES = {"k_sweep3<0, true, 7u>": "sweep3_fwd_count", "k_sweep3<0, true, 8u>": "sweep3_tri_count",
                   "k_sweep3<0, false, 0u>": "sweep3_bwd_count", "k_sweep3<1, true, 7u>": "sweep3_fwd_weight",
-                  "k_sweep3<1, true, 8u>": "sweep3_tri_weight", "k_sweep3<1, false, 0u>": "sweep3_bwd_weight"}
+                  "k_sweep3<1, true, 8u>": "sweep3_tri_weight", "k_sweep3<1, false, 0u>": "sweep3_bwd_weight",
+                  "k_st_weight<false>": "tri_static_weight"}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
@@ -1123,6 +1139,11 @@ def main():
     G = tm.load_graph(src, dst, t, g.n)
     census = tm.sweep_census(G, delta)
     ests = [tm.sweep_census_est(G, delta, c, p, 0) for c, p in W["est"]]
+    for e, (c, p) in zip(ests, W["est"]):
+        try:
+            e["static"] = tm.tri_static_census(G, delta, c, p, 0)
+        except tm.TMError:
+            e["static"] = None  # no static triangles kept: the list sweep counts them
     tables = G.exact_table_bytes > 0
     # latency over repeated single queries on the resident graph: the exact
     # pass of every motif, the p = 0.1 estimate pass (largest c), and one

@@ -491,6 +491,34 @@ tm_status tm_sweep_census(const tm_graph *g, int64_t delta, tm_census *out, void
 tm_status tm_sweep_census_est(const tm_graph *g, int64_t delta, int64_t c, double p, uint64_t seed,
                               tm_census *out, void *hip_stream);
 
+/*
+ * Work census of the weighted triangle sums of an estimate for (delta, c,
+ * p, seed) as tm_estimate_multi computes them for triangle motifs: over the
+ * static triangles {u0, u1, u2} (three node pairs joined by edges; Sec. 2,
+ * the three edges of a triangle instance lie on the three pairs), inside
+ * each kept window (Sec. 4, Algorithm 1).
+ *   triangles  static triangles of the graph
+ *   units      (static triangle, kept window) with edges on all three pairs
+ *              inside the window
+ *   tasks      work items: per unit, six roles (the pair of the middle edge,
+ *              and which other pair holds the first edge), each cut into
+ *              chunks of 16 entries of the lighter of the first- and
+ *              last-edge pairs (the driver)
+ *   drivers    driver entries whose window range holds a middle edge and a
+ *              candidate edge on the third pair
+ *   steps      64-entry steps over those candidates
+ *   combos     (first, last) edge pairs visited (candidates in the steps)
+ * TM_EUNSUPPORTED when the graph keeps no static triangles (too many
+ * candidates to enumerate, or a pair with 2^28 edges or more); estimates
+ * then count triangles over the incidence lists.  Synchronises the stream.
+ */
+typedef struct {
+    int64_t triangles, units, tasks, drivers, steps, combos;
+} tm_tri_census;
+
+tm_status tm_tri_static_census(const tm_graph *g, int64_t delta, int64_t c, double p, uint64_t seed,
+                               tm_tri_census *out, void *hip_stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *tm_strerror(tm_status s);
 

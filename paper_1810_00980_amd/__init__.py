@@ -128,6 +128,7 @@ _SIGS = {
     "tm_profile_read": [ctypes.c_char_p, P, P],
     "tm_sweep_census": [P, i64, P, P],
     "tm_sweep_census_est": [P, i64, i64, f64, u64, P, P],
+    "tm_tri_static_census": [P, i64, i64, f64, u64, P, P],
     "tm_strerror": [i32],
     "tm_version": [],
 }
@@ -441,6 +442,19 @@ def sweep_census_est(g: Graph, delta: int, c: int, p: float, seed: int, stream=N
     _check(_lib.tm_sweep_census_est(g.handle, int(delta), int(c), float(p), int(seed), ctypes.byref(r),
                                     _stream(stream)), "tm_sweep_census_est")
     return {name: getattr(r, name) for name, _ in Census._fields_}
+
+
+class TriCensus(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in ("triangles", "units", "tasks", "drivers", "steps", "combos")]
+
+
+def tri_static_census(g: Graph, delta: int, c: int, p: float, seed: int, stream=None) -> dict:
+    """Work census of an estimate's weighted triangle sums over the static
+    triangles (tm_tri_census fields)."""
+    r = TriCensus()
+    _check(_lib.tm_tri_static_census(g.handle, int(delta), int(c), float(p), int(seed), ctypes.byref(r),
+                                     _stream(stream)), "tm_tri_static_census")
+    return {name: getattr(r, name) for name, _ in TriCensus._fields_}
 
 
 def batch_config(g: Graph, edges, delta: int, c: int, p: float, stream=None):

@@ -1512,6 +1512,18 @@ extern "C" tm_status tm_sweep_census_est(const tm_graph *g, int64_t delta, int64
     return s;
 }
 
+extern "C" tm_status tm_tri_static_census(const tm_graph *g, int64_t delta, int64_t c, double p, uint64_t seed,
+                                          tm_tri_census *out, void *hip_stream) {
+    if (!g || !out) return TM_EINVAL;
+    int64_t L;
+    TM_TRY(check_est_args(g, delta, c, p, &L));
+    hipStream_t st = (hipStream_t)hip_stream;
+    tm_tri_census r;
+    tm_status s = finish(tm_tri_static_census_impl(g, delta, host_shift(seed, L), L, seed, p, &r, st), st);
+    if (s == TM_OK) *out = r;
+    return s;
+}
+
 extern "C" const char *tm_strerror(tm_status s) {
     switch (s) {
         case TM_OK: return "ok";

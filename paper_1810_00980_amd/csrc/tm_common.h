@@ -501,6 +501,10 @@ tm_status tm_tri_static_weight(const tm_graph *g, int64_t delta, int64_t s, int6
 // Off for the calling thread: the query server charges its batches the
 // incidence-list sweep's bytes.
 void tm_tri_static_enable(bool on);
+// Work counts of that path (tm_tri_static_census); TM_EUNSUPPORTED when the
+// graph keeps no static triangles.
+tm_status tm_tri_static_census_impl(const tm_graph *g, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,
+                                    tm_tri_census *c, hipStream_t st);
 
 // Largest delta for the sweep counter's histogram mode (36 histograms).
 #define TM_MAX_SWEEP_HIST_DELTA ((int64_t)1 << 20)

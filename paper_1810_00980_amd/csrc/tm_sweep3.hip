@@ -454,9 +454,24 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, bool s
         for (int k = 1; k < nl; ++k) TM_HIP(hipStreamWaitEvent(side->s[k - 1], side->fork, 0));
     }
     const uint64_t pass = tm_prof_pass();
-    // weighted triangles of kept windows over the static triangles, after the
-    // other kernels are on their side streams (its set-up reads sizes back)
+    // weighted triangles of kept windows over the static triangles first: its
+    // set-up (short kernels that read two sizes back) runs before the
+    // persistent kernels of the other classes hold the CUs, and its sums then
+    // run beside them
     const bool defer_tri = MODE == MODE_WEIGHT && a.static_tri && todo[0].kind == 2;
+    if (defer_tri) {
+        bool used = false;
+        TM_TRY(tm_tri_static_weight(g, a.delta, a.s, a.L, a.seed, a.p, a.wfx, a.out, st, pass, &used));
+        if (!used) {
+            SweepArgs b = a;
+            b.counter = a.counter + TM_SWEEP_PARTS * 2;
+            b.parts = 1;
+            void *tok = tm_prof_begin(names[MODE][2], st, pass);
+            hipLaunchKernelGGL((k_sweep3<MODE, true, 8u>), dim3((unsigned)nb), dim3(SW_TPB), 0, st, G, b);
+            TM_HIP(hipGetLastError());
+            tm_prof_end(tok, st);
+        }
+    }
     for (int k = 0; k < nl; ++k) {
         hipStream_t sk = (k == 0 || !side) ? st : side->s[k - 1];
         if (k == 0 && defer_tri) continue;
@@ -476,19 +491,6 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, bool s
             hipLaunchKernelGGL((k_sweep3<MODE, false, 0u>), dim3((unsigned)nb), dim3(SW_TPB), 0, sk, G, b);
         TM_HIP(hipGetLastError());
         tm_prof_end(tok, sk);
-    }
-    if (defer_tri) {
-        bool used = false;
-        TM_TRY(tm_tri_static_weight(g, a.delta, a.s, a.L, a.seed, a.p, a.wfx, a.out, st, pass, &used));
-        if (!used) {
-            SweepArgs b = a;
-            b.counter = a.counter + TM_SWEEP_PARTS * 2;
-            b.parts = 1;
-            void *tok = tm_prof_begin(names[MODE][2], st, pass);
-            hipLaunchKernelGGL((k_sweep3<MODE, true, 8u>), dim3((unsigned)nb), dim3(SW_TPB), 0, st, G, b);
-            TM_HIP(hipGetLastError());
-            tm_prof_end(tok, st);
-        }
     }
     for (int k = 1; side && k < nl; ++k) {
         TM_HIP(hipEventRecord(side->join[k - 1], side->s[k - 1]));

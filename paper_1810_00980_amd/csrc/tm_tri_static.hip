@@ -369,9 +369,11 @@ using StAcc = Acc<MODE_WEIGHT, 4>;
 // index not before the step's first time, shared by the wave, unless a
 // middle falls inside the step's span (then the lane seeks its own).  Slots:
 // 2 dm + d3 (dm: middle direction, 0 for y1 -> z).
+// CENSUS: count the steps and the valid lanes instead (cnt[1], cnt[2]).
+template <bool CENSUS>
 __device__ inline void st_fwd_entry(const PairEnt *E, int lane, int64_t t1, int64_t hi, int64_t j0, int64_t hiC,
                                     int64_t b1, int64_t hiB, int64_t cb1, bool s_min_c, bool y1_min,
-                                    const uint64_t *wfx, StAcc &A) {
+                                    const uint64_t *wfx, StAcc &A, uint64_t *cnt) {
     int64_t pbase = b1;
     for (int64_t js = j0;; js += TM_WAVE) {
         const int64_t j = js + lane;
@@ -382,6 +384,12 @@ __device__ inline void st_fwd_entry(const PairEnt *E, int lane, int64_t t1, int6
         const bool valid = j < hiC && ec.t <= hi;
         const unsigned long long vm = __ballot(valid);
         if (vm == 0ull) break;  // valid lanes form a prefix
+        if constexpr (CENSUS) {
+            cnt[1] += 1;
+            cnt[2] += (uint64_t)__popcll(vm);
+            if (!(vm >> (TM_WAVE - 1))) break;
+            continue;
+        }
         int64_t nc0 = __shfl_down(ec.c0, 1, TM_WAVE);
         if (lane == TM_WAVE - 1 && valid) nc0 = E[j + 1].c0;
         const int64_t t3 = ec.t;
@@ -409,9 +417,10 @@ __device__ inline void st_fwd_entry(const PairEnt *E, int lane, int64_t t1, int6
 // 2], ... with times from lo on, 64 per step.  The first middle after t1 is
 // shared by the wave from the step's latest first edge unless a middle falls
 // inside the step's span.  Slots: 2 dm + d1.
+template <bool CENSUS>
 __device__ inline void st_bwd_entry(const PairEnt *E, int lane, int64_t t3, int64_t lo, int64_t i0, int64_t loA,
                                     int64_t pb, int64_t loB, int64_t cbt, bool s_min_a, bool y1_min,
-                                    const uint64_t *wfx, StAcc &A) {
+                                    const uint64_t *wfx, StAcc &A, uint64_t *cnt) {
     int64_t qbase = pb;
     for (int64_t is = i0 - 1;; is -= TM_WAVE) {
         const int64_t i = is - lane;
@@ -422,6 +431,12 @@ __device__ inline void st_bwd_entry(const PairEnt *E, int lane, int64_t t3, int6
         const bool valid = i >= loA && ea.t >= lo;
         const unsigned long long vm = __ballot(valid);
         if (vm == 0ull) break;
+        if constexpr (CENSUS) {
+            cnt[1] += 1;
+            cnt[2] += (uint64_t)__popcll(vm);
+            if (!(vm >> (TM_WAVE - 1))) break;
+            continue;
+        }
         int64_t nc0 = __shfl_up(ea.c0, 1, TM_WAVE);  // lane - 1 holds entry i + 1
         if (lane == 0) nc0 = E[i + 1].c0;             // i + 1 <= i0 <= hiA
         const int64_t t1 = ea.t;
@@ -459,7 +474,9 @@ __device__ inline void st_flush(const StAcc &A, const int codes[4], unsigned lon
 // lane computes the same pointers), the inner ranges 64 entries at a time.
 // Sums go to two accumulator sets chosen by the driver entry's direction
 // (the same for every lane), flushed once per task.
-__device__ void st_task(const DevGraph &G, const StArgs &a, uint64_t tw, int lane, unsigned long long *lds) {
+template <bool CENSUS>
+__device__ void st_task(const DevGraph &G, const StArgs &a, uint64_t tw, int lane, unsigned long long *lds,
+                        uint64_t *cnt) {
     const StUnit u = a.units[(uint32_t)tw];
     const int role = (int)((tw >> 32) & 7u);
     const int64_t chunk = (int64_t)(tw >> 35);
@@ -491,9 +508,11 @@ __device__ void st_task(const DevGraph &G, const StArgs &a, uint64_t tw, int lan
             j0 = st_seek<false>(E, j0, hiC, eb1.t);  // first last edge after it
             if (j0 == hiC) break;
             const uint32_t d1 = st_dir(ea, E[i + 1], s_min_a);
-            if (d1) st_fwd_entry(E, lane, t1, hi, j0, hiC, b1, hiB, eb1.c0, s_min_c, y1_min, a.wfx, A1);
-            else st_fwd_entry(E, lane, t1, hi, j0, hiC, b1, hiB, eb1.c0, s_min_c, y1_min, a.wfx, A0);
+            cnt[0] += 1;
+            if (d1) st_fwd_entry<CENSUS>(E, lane, t1, hi, j0, hiC, b1, hiB, eb1.c0, s_min_c, y1_min, a.wfx, A1, cnt);
+            else st_fwd_entry<CENSUS>(E, lane, t1, hi, j0, hiC, b1, hiB, eb1.c0, s_min_c, y1_min, a.wfx, A0, cnt);
         }
+        if constexpr (CENSUS) return;
         // set d1, slot 2 dm + d3 -> code 20 + 4 d1 + 2 dm + d3
         const int c0[4] = {20, 21, 22, 23}, c1[4] = {24, 25, 26, 27};
         st_flush(A0, c0, lds);
@@ -514,9 +533,11 @@ __device__ void st_task(const DevGraph &G, const StArgs &a, uint64_t tw, int lan
             if (i0 == loA) continue;
             const uint32_t d3 = st_dir(ec, E[jj + 1], s_min_c);
             const int64_t cbt = E[pb].c0;
-            if (d3) st_bwd_entry(E, lane, t3, lo, i0, loA, pb, loB, cbt, s_min_a, y1_min, a.wfx, A1);
-            else st_bwd_entry(E, lane, t3, lo, i0, loA, pb, loB, cbt, s_min_a, y1_min, a.wfx, A0);
+            cnt[0] += 1;
+            if (d3) st_bwd_entry<CENSUS>(E, lane, t3, lo, i0, loA, pb, loB, cbt, s_min_a, y1_min, a.wfx, A1, cnt);
+            else st_bwd_entry<CENSUS>(E, lane, t3, lo, i0, loA, pb, loB, cbt, s_min_a, y1_min, a.wfx, A0, cnt);
         }
+        if constexpr (CENSUS) return;
         // set d3, slot 2 dm + d1 -> code 20 + 4 d1 + 2 dm + d3
         const int c0[4] = {20, 24, 22, 26}, c1[4] = {21, 25, 23, 27};
         st_flush(A0, c0, lds);
@@ -524,17 +545,25 @@ __device__ void st_task(const DevGraph &G, const StArgs &a, uint64_t tw, int lan
     }
 }
 
+// CENSUS: out[0..2] += driver entries walked, 64-entry steps, valid lanes.
+template <bool CENSUS>
 __global__ void __launch_bounds__(ST_TPB) k_st_weight(DevGraph G, StArgs a) {
     __shared__ unsigned long long lds[36 * 4];
     for (int k = threadIdx.x; k < 36 * 4; k += ST_TPB) lds[k] = 0;
     __syncthreads();
     const int lane = threadIdx.x & (TM_WAVE - 1);
+    uint64_t cnt[3] = {0, 0, 0};
     while (true) {
         int64_t b = 0;
         if (lane == 0) b = (int64_t)atomicAdd(a.counter, 1ull);
         b = __shfl(b, 0, TM_WAVE);
         if (b >= a.ntask) break;
-        st_task(G, a, a.tasks[a.order[b]], lane, lds);
+        st_task<CENSUS>(G, a, a.tasks[a.order[b]], lane, lds, cnt);
+    }
+    if constexpr (CENSUS) {
+        if (lane == 0)
+            for (int k = 0; k < 3; ++k) atomicAdd((unsigned long long *)&a.out[k], (unsigned long long)cnt[k]);
+        return;
     }
     __syncthreads();
     for (int k = 20 * 4 + threadIdx.x; k < 28 * 4; k += ST_TPB) {
@@ -655,11 +684,18 @@ void tm_tri_static_release_thread_ws() {
     t_st.ctr.release();
 }
 
-tm_status tm_tri_static_weight(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,
-                               const uint64_t *wfx, uint64_t *out, hipStream_t st, uint64_t pass, bool *used) {
+namespace {
+
+// The per-call set-up (units, tasks in claim order) and the launch: sums of
+// codes 20..27 into out, or with census the work counts into out[0..2].
+// *used = false when the path is off or the graph keeps no static triangles;
+// nu, nt: units and tasks.
+tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,
+                 const uint64_t *wfx, uint64_t *out, hipStream_t st, uint64_t pass, bool census, bool *used,
+                 int64_t *nu_out, int64_t *nt_out) {
     *used = false;
-    if (!t_st_enabled || L <= 0) return TM_OK;
-    if (const char *e = getenv("TM_TRI_STATIC"); e && e[0] == '0') return TM_OK;
+    *nu_out = *nt_out = 0;
+    if (L <= 0) return TM_OK;
     tm_graph *g = const_cast<tm_graph *>(gc);  // the index is a cache of the immutable graph
     bool ok = false;
     TM_TRY(st_index(g, st, &ok));
@@ -670,7 +706,7 @@ tm_status tm_tri_static_weight(const tm_graph *gc, int64_t delta, int64_t s, int
     const DevGraph G = dev_view(g);
     const StTri *tris = g->st_tri.as<StTri>();
     StWs &W = t_st;
-    void *tok = tm_prof_begin("tri_static_prep", st, pass);
+    void *tok = census ? nullptr : tm_prof_begin("tri_static_prep", st, pass);
     TM_TRY(W.cnt.reserve((size_t)(ntri + 1) * 8));
     hipLaunchKernelGGL((k_st_units<false>), dim3(tm_blocks(ntri, 256)), dim3(256), 0, st, G, tris, ntri, s, L, seed,
                        p, W.cnt.as<int64_t>(), (StUnit *)nullptr, (int64_t *)nullptr);
@@ -692,6 +728,8 @@ tm_status tm_tri_static_weight(const tm_graph *gc, int64_t delta, int64_t s, int
     int64_t nt = 0;
     TM_TRY(read_i64(W.tcnt.as<int64_t>() + nu, &nt, st));
     if (nt > UINT32_MAX) return TM_ENOMEM;
+    *nu_out = nu;
+    *nt_out = nt;
     TM_TRY(W.tasks.reserve((size_t)nt * 8));
     TM_TRY(W.keys.reserve((size_t)nt * 8));
     TM_TRY(W.vals.reserve((size_t)nt * 4));
@@ -721,9 +759,46 @@ tm_status tm_tri_static_weight(const tm_graph *gc, int64_t delta, int64_t s, int
     int64_t nb = (nt + ST_TPB / TM_WAVE - 1) / (ST_TPB / TM_WAVE);  // one task per wave
     if (nb > (int64_t)ncu * 8) nb = (int64_t)ncu * 8;
     if (nb < 1) nb = 1;
+    if (census) {
+        hipLaunchKernelGGL((k_st_weight<true>), dim3((unsigned)nb), dim3(ST_TPB), 0, st, G, a);
+        return tm_hip_status(hipGetLastError());
+    }
     void *tk = tm_prof_begin("tri_static_weight", st, pass);
-    hipLaunchKernelGGL(k_st_weight, dim3((unsigned)nb), dim3(ST_TPB), 0, st, G, a);
+    hipLaunchKernelGGL((k_st_weight<false>), dim3((unsigned)nb), dim3(ST_TPB), 0, st, G, a);
     TM_HIP(hipGetLastError());
     tm_prof_end(tk, st);
+    return TM_OK;
+}
+
+}  // namespace
+
+tm_status tm_tri_static_weight(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,
+                               const uint64_t *wfx, uint64_t *out, hipStream_t st, uint64_t pass, bool *used) {
+    *used = false;
+    if (!t_st_enabled) return TM_OK;
+    if (const char *e = getenv("TM_TRI_STATIC"); e && e[0] == '0') return TM_OK;
+    int64_t nu, nt;
+    return st_run(gc, delta, s, L, seed, p, wfx, out, st, pass, false, used, &nu, &nt);
+}
+
+tm_status tm_tri_static_census_impl(const tm_graph *g, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,
+                                    tm_tri_census *c, hipStream_t st) {
+    DevBuf o;
+    TM_TRY(o.alloc(32));
+    hipLaunchKernelGGL(k_st_zero, dim3(1), dim3(64), 0, st, o.as<uint64_t>(), (int64_t)4);
+    TM_HIP(hipGetLastError());
+    bool used = false;
+    int64_t nu = 0, nt = 0;
+    TM_TRY(st_run(g, delta, s, L, seed, p, nullptr, o.as<uint64_t>(), st, 0, true, &used, &nu, &nt));
+    if (!used) return TM_EUNSUPPORTED;
+    uint64_t h[4];
+    TM_HIP(hipMemcpyAsync(h, o.p, 32, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipStreamSynchronize(st));
+    c->triangles = g->st_ntri;
+    c->units = nu;
+    c->tasks = nt;
+    c->drivers = (int64_t)h[0];
+    c->steps = (int64_t)h[1];
+    c->combos = (int64_t)h[2];
     return TM_OK;
 }

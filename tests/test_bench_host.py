@@ -38,6 +38,19 @@ def test_sweep_bytes_model(bench):
     assert b["sweep3_tri_count"] == 16 * 5 + 12 * 50 + 8 * 33
     assert b["sweep3_tri_weight"] == 2 * (16 * 5 + 20 * 50 + 8 * 33)
     assert b["sweep3_fwd_weight"] == 2 * (16 * 10 + 20 * 100)
+    assert "tri_static_weight" not in b
+
+
+def test_static_triangle_bytes_model(bench):
+    """Weighted triangles over static triangles: 48 B per unit, 48 B per
+    driver entry, 24 B per (first, last) pair, summed over the estimate
+    settings; absent when a setting has no static census."""
+    st = {"triangles": 9, "units": 3, "tasks": 40, "drivers": 11, "steps": 5, "combos": 70}
+    ests = [dict(CENSUS, static=st), dict(CENSUS, static=dict(st, units=1, drivers=2, combos=4))]
+    b = bench.sweep_bytes(CENSUS, ests)
+    assert b["tri_static_weight"] == (48 * 3 + 48 * 11 + 24 * 70) + (48 * 1 + 48 * 2 + 24 * 4)
+    b = bench.sweep_bytes(CENSUS, [dict(CENSUS, static=st), dict(CENSUS, static=None)])
+    assert "tri_static_weight" not in b
 
 
 def test_dominant_kernel_and_counter_based_fraction(bench, monkeypatch):

@@ -248,6 +248,54 @@ def test_static_triangles_equal_list_sweep(tm, monkeypatch):
                 assert k == int(o["win_counts"].sum()), M
 
 
+def test_tri_static_census(tm):
+    """The census of the static-triangle path counts, by brute force over the
+    oracle's shift and kept windows: the (static triangle, kept window) units
+    with edges on all three pairs in the window, and the (first, last) edge
+    pairs on two pairs of a static triangle, in one kept window, within delta,
+    with an edge of the third pair strictly between (the pairs the path
+    visits); at least six tasks per unit (one per role)."""
+    g = ti.random_small_graph(7, 400, 3000, 77)
+    delta, c, p, seed = 60, 3, 0.6, 5
+    say("tri_static_census", g.m, delta, c, p, seed)
+    G = load(tm, g)
+    o = oracle.estimate(g.src, g.dst, g.t, ti.TRIANGLE, delta, c, p, seed)
+    s, L = int(o["s"]), c * delta
+    kept = {int(j) for j in o["kept"]}
+    t = (g.t - g.t.min()).astype(np.int64)
+    win = (t - s) // L + 1
+    pairs = {}
+    for k, (u, v) in enumerate(zip(g.src.tolist(), g.dst.tolist())):
+        if u != v:
+            pairs.setdefault((min(u, v), max(u, v)), []).append(k)
+    units = combos = 0
+    for x in range(g.n):
+        for y in range(x + 1, g.n):
+            for z in range(y + 1, g.n):
+                if (y, z) not in pairs or (x, z) not in pairs or (x, y) not in pairs:
+                    continue
+                P = [pairs[(y, z)], pairs[(x, z)], pairs[(x, y)]]
+                common = set(win[P[0]]) & set(win[P[1]]) & set(win[P[2]]) & kept
+                units += len(common)
+                for r in range(3):
+                    for i in range(3):
+                        for j in range(3):
+                            if len({i, j, r}) < 3:
+                                continue
+                            for a in P[i]:
+                                if win[a] not in kept:
+                                    continue
+                                for e in P[j]:
+                                    if win[e] != win[a] or not (t[a] < t[e] <= t[a] + delta):
+                                        continue
+                                    if any(t[a] < t[b] < t[e] for b in P[r]):
+                                        combos += 1
+    cen = tm.tri_static_census(G, delta, c, p, seed)
+    assert units > 0 and combos > 0
+    assert cen["units"] == units and cen["combos"] == combos, (cen, units, combos)
+    assert cen["tasks"] >= 6 * units and cen["steps"] >= 1 and cen["triangles"] > 0
+
+
 def test_estimate_q_matches_oracle(tm):
     """Algorithm 1 with b shifts and edge-proportional window probabilities
     (equation heuristic_q): the kept windows (shift, window, q_j) are the
@@ -495,8 +543,12 @@ def test_self_loop_only_graph(tm):
     assert not np.any(tm.count_anchors(G, ti.CYCLE4, 600, np.arange(m)))
 
 
+# kernels of an exact pass and of an estimate pass (its triangles over the
+# static triangles: a set-up step, then the sums), and the incidence-list
+# triangle kernel the estimate pass leaves out when the static path runs
 SWEEP_NAMES = ("sweep3_fwd_count", "sweep3_tri_count", "sweep3_bwd_count",
-               "sweep3_fwd_weight", "sweep3_tri_weight", "sweep3_bwd_weight")
+               "sweep3_fwd_weight", "sweep3_bwd_weight", "tri_static_prep", "tri_static_weight")
+UNUSED_NAMES = ("sweep3_tri_weight",)
 
 
 def test_serial_timing_mode_same_results(tm):
@@ -514,9 +566,10 @@ def test_serial_timing_mode_same_results(tm):
             exact = tm.count_exact_multi(G, THREE, 40)
             est, kept = tm.estimate_multi(G, THREE, 40, 3, 0.5, 2)
             tm.profile_enable(False)
-            crit = sum(tm.profile_read("crit:" + k)[1] for k in SWEEP_NAMES)
+            crit = sum(tm.profile_read("crit:" + k)[1] for k in SWEEP_NAMES + UNUSED_NAMES)
             assert crit == 2, (serial, crit)  # one exact pass, one estimate pass
             assert all(tm.profile_read(k)[1] == 1 for k in SWEEP_NAMES), serial
+            assert all(tm.profile_read(k)[1] == 0 for k in UNUSED_NAMES), serial
             runs.append((exact, est, kept))
     finally:
         tm.profile_enable(False)
