@@ -492,9 +492,10 @@ tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask, int mode, int64_t del
 
 // Weighted triangle sums (codes 20..27 of out, added to) of the kept windows
 // of (s, L, seed, p) over the graph's static triangles, built on first use.
-// *used = false (nothing enqueued) when the graph keeps no static triangles
-// or the calling thread has switched the path off; then the incidence-list
-// sweep must count them.  Allocates per-thread workspace and reads two sizes
+// *used = false (nothing enqueued) when the graph keeps no static triangles,
+// has fewer than 2^20 non-self-loop edges (unless TM_TRI_STATIC=1; =0 turns
+// the path off), or the calling thread has switched the path off; then the
+// incidence-list sweep must count them.  Allocates per-thread workspace and reads two sizes
 // back to the host (the stream is synchronised).
 tm_status tm_tri_static_weight(const tm_graph *g, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,
                                const uint64_t *wfx, uint64_t *out, hipStream_t st, uint64_t pass, bool *used);

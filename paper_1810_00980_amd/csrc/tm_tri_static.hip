@@ -54,6 +54,13 @@ constexpr int ST_TPB = 256;
 constexpr int64_t ST_K = 16;  // driver entries per task
 // candidate out-neighbour pairs the enumeration may check (about a second)
 constexpr uint64_t ST_MAX_BUILD_CHECKS = 1ull << 33;
+// smallest graph (non-self-loop edges) that takes this path by default: the
+// set-up costs about fifteen launches and two reads back to the host, about
+// a millisecond, which a list sweep of a smaller graph does not
+constexpr int64_t ST_MIN_EDGES = (int64_t)1 << 20;
+// most windows whose kept ids are listed per call (8 B each); beyond that a
+// triangle's walk draws each window it touches instead
+constexpr int64_t ST_MAX_WINDOW_LIST = (int64_t)1 << 24;
 
 struct StTri {
     uint32_t u[3];  // nodes, ascending
@@ -197,12 +204,26 @@ __device__ inline int64_t st_lower(const DevGraph &G, const StPairs &P, int r, i
     return pair_lower<false>(G, P.m[r], P.en[r], P.n[r], t, &c0, &be);
 }
 
+// kept window ids of the call, ascending: flags, then a scan, then the ids
+__global__ void k_st_kept_flags(int64_t J, uint64_t seed, double p, int64_t *flag) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (j <= J) flag[j - 1] = keep_window(seed, (uint64_t)j, p) ? 1 : 0;
+}
+
+__global__ void k_st_kept_fill(int64_t J, uint64_t seed, double p, const int64_t *pos, int64_t *kept) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (j <= J && keep_window(seed, (uint64_t)j, p)) kept[pos[j - 1]] = j;
+}
+
 // The kept windows in which all three pairs of triangle i have entries:
-// walked along the lightest pair's entries, one window at a time.  FILL
-// writes each as a unit at units[uoff[i]...] with its task count.
+// walked along the lightest pair's entries, from one kept window it touches
+// to the next (kept: the call's kept window ids ascending, *nkept of them;
+// nullptr: every window it touches, with its draw).  FILL writes each as a
+// unit at units[uoff[i]...] with its task count.
 template <bool FILL>
 __global__ void k_st_units(DevGraph G, const StTri *tris, int64_t ntri, int64_t s, int64_t L, uint64_t seed,
-                           double p, int64_t *ucnt, StUnit *units, int64_t *tcnt) {
+                           double p, const int64_t *kept, const int64_t *nkept, int64_t *ucnt, StUnit *units,
+                           int64_t *tcnt) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ntri) return;
     const StTri T = tris[i];
@@ -210,13 +231,28 @@ __global__ void k_st_units(DevGraph G, const StTri *tris, int64_t ntri, int64_t 
     st_pairs(G, T, P);
     const int li = (P.n[0] <= P.n[1] && P.n[0] <= P.n[2]) ? 0 : (P.n[1] <= P.n[2] ? 1 : 2);
     int64_t c = 0, at = FILL ? ucnt[i] : 0;
+    const int64_t nk = kept ? *nkept : 0;
     int64_t k = 0;
     while (k < P.n[li]) {
         const int64_t t = P.en[li][k].t;
         const int64_t jw = (t - s) / L + 1;
+        if (kept) {
+            // the first kept window at or after jw; entries before it are skipped
+            int64_t a = 0, b = nk;
+            while (a < b) {
+                const int64_t mid = (a + b) >> 1;
+                if (kept[mid] < jw) a = mid + 1;
+                else b = mid;
+            }
+            if (a == nk) break;
+            if (kept[a] != jw) {
+                k = st_lower(G, P, li, s + (kept[a] - 1) * L);
+                continue;
+            }
+        }
         const int64_t wlo = s + (jw - 1) * L, whi = wlo > LLONG_MAX - L ? LLONG_MAX - 1 : wlo + L - 1;
         const int64_t kn = st_lower(G, P, li, whi + 1);
-        if (keep_window(seed, (uint64_t)jw, p)) {
+        if (kept || keep_window(seed, (uint64_t)jw, p)) {
             int64_t lo[3], hi[3];
             bool all = true;
 #pragma unroll
@@ -580,7 +616,7 @@ __global__ void __launch_bounds__(ST_TPB) k_st_weight(DevGraph G, StArgs a) {
 
 // Per host thread, grow-only workspace of the per-call steps.
 struct StWs {
-    DevBuf cnt, units, tcnt, tasks, keys, vals, ctr;
+    DevBuf cnt, units, tcnt, tasks, keys, vals, ctr, kflag, kept;
 };
 thread_local StWs t_st;
 
@@ -682,6 +718,8 @@ void tm_tri_static_release_thread_ws() {
     t_st.keys.release();
     t_st.vals.release();
     t_st.ctr.release();
+    t_st.kflag.release();
+    t_st.kept.release();
 }
 
 namespace {
@@ -708,8 +746,24 @@ tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64
     StWs &W = t_st;
     void *tok = census ? nullptr : tm_prof_begin("tri_static_prep", st, pass);
     TM_TRY(W.cnt.reserve((size_t)(ntri + 1) * 8));
+    // the kept window ids, when their list is small enough to build per call
+    const int64_t J = (g->t_span - s) / L + 1;
+    const int64_t *kept = nullptr, *nkept = nullptr;
+    if (J <= ST_MAX_WINDOW_LIST) {
+        TM_TRY(W.kflag.reserve((size_t)(J + 1) * 8));
+        TM_TRY(W.kept.reserve((size_t)J * 8));
+        hipLaunchKernelGGL(k_st_kept_flags, dim3(tm_blocks(J, 256)), dim3(256), 0, st, J, seed, p,
+                           W.kflag.as<int64_t>());
+        TM_HIP(hipGetLastError());
+        TM_TRY(tm_scan_i64(W.kflag.as<int64_t>(), J, W.kflag.as<int64_t>() + J, st));
+        hipLaunchKernelGGL(k_st_kept_fill, dim3(tm_blocks(J, 256)), dim3(256), 0, st, J, seed, p,
+                           W.kflag.as<int64_t>(), W.kept.as<int64_t>());
+        TM_HIP(hipGetLastError());
+        kept = W.kept.as<int64_t>();
+        nkept = W.kflag.as<int64_t>() + J;
+    }
     hipLaunchKernelGGL((k_st_units<false>), dim3(tm_blocks(ntri, 256)), dim3(256), 0, st, G, tris, ntri, s, L, seed,
-                       p, W.cnt.as<int64_t>(), (StUnit *)nullptr, (int64_t *)nullptr);
+                       p, kept, nkept, W.cnt.as<int64_t>(), (StUnit *)nullptr, (int64_t *)nullptr);
     TM_HIP(hipGetLastError());
     TM_TRY(tm_scan_i64(W.cnt.as<int64_t>(), ntri, W.cnt.as<int64_t>() + ntri, st));
     int64_t nu = 0;
@@ -722,7 +776,7 @@ tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64
     TM_TRY(W.units.reserve((size_t)nu * sizeof(StUnit)));
     TM_TRY(W.tcnt.reserve((size_t)(nu + 1) * 8));
     hipLaunchKernelGGL((k_st_units<true>), dim3(tm_blocks(ntri, 256)), dim3(256), 0, st, G, tris, ntri, s, L, seed,
-                       p, W.cnt.as<int64_t>(), W.units.as<StUnit>(), W.tcnt.as<int64_t>());
+                       p, kept, nkept, W.cnt.as<int64_t>(), W.units.as<StUnit>(), W.tcnt.as<int64_t>());
     TM_HIP(hipGetLastError());
     TM_TRY(tm_scan_i64(W.tcnt.as<int64_t>(), nu, W.tcnt.as<int64_t>() + nu, st));
     int64_t nt = 0;
@@ -776,7 +830,12 @@ tm_status tm_tri_static_weight(const tm_graph *gc, int64_t delta, int64_t s, int
                                const uint64_t *wfx, uint64_t *out, hipStream_t st, uint64_t pass, bool *used) {
     *used = false;
     if (!t_st_enabled) return TM_OK;
-    if (const char *e = getenv("TM_TRI_STATIC"); e && e[0] == '0') return TM_OK;
+    // TM_TRI_STATIC=0 keeps the incidence-list sweep, =1 takes this path on
+    // any graph; otherwise graphs below ST_MIN_EDGES keep the list sweep,
+    // whose whole pass there is shorter than this path's set-up
+    const char *e = getenv("TM_TRI_STATIC");
+    if (e && e[0] == '0') return TM_OK;
+    if (!(e && e[0] == '1') && gc->m_nl < ST_MIN_EDGES) return TM_OK;
     int64_t nu, nt;
     return st_run(gc, delta, s, L, seed, p, wfx, out, st, pass, false, used, &nu, &nt);
 }

@@ -236,8 +236,15 @@ def test_static_triangles_equal_list_sweep(tm, monkeypatch):
         G = load(tm, g)
         monkeypatch.setenv("TM_TRI_STATIC", "0")
         z0, k0 = tm.estimate_multi(G, THREE, delta, c, p, seed)
-        monkeypatch.delenv("TM_TRI_STATIC")
+        monkeypatch.setenv("TM_TRI_STATIC", "1")  # also below the default size threshold
         z1, k1 = tm.estimate_multi(G, THREE, delta, c, p, seed)
+        tm.profile_reset()
+        tm.profile_enable(True)
+        tm.estimate_multi(G, THREE, delta, c, p, seed)
+        tm.profile_enable(False)
+        assert tm.profile_read("tri_static_weight")[1] + tm.profile_read("tri_static_prep")[1] >= 1
+        assert tm.profile_read("sweep3_tri_weight")[1] == 0
+        monkeypatch.delenv("TM_TRI_STATIC")
         assert k1 == k0
         assert z1 == z0
         if g.n == 4:
@@ -551,10 +558,13 @@ SWEEP_NAMES = ("sweep3_fwd_count", "sweep3_tri_count", "sweep3_bwd_count",
 UNUSED_NAMES = ("sweep3_tri_weight",)
 
 
-def test_serial_timing_mode_same_results(tm):
+def test_serial_timing_mode_same_results(tm, monkeypatch):
     """The serial timing mode (each pass's kernels one after another) changes
     how kernels run, never what they compute; in either mode every pass
-    credits exactly one kernel as the one it waited for."""
+    credits exactly one kernel as the one it waited for (the estimate pass
+    with its triangles over the static triangles, forced on this small
+    graph)."""
+    monkeypatch.setenv("TM_TRI_STATIC", "1")
     g = ti.random_small_graph(6, 1200, 6000, 47, allow_self_loops=True)
     say("serial_timing")
     G = load(tm, g)
