@@ -502,7 +502,7 @@ tm_status tm_sweep_census_est(const tm_graph *g, int64_t delta, int64_t c, doubl
  *              inside the window
  *   tasks      work items: per unit, six roles (the pair of the middle edge,
  *              and which other pair holds the first edge), each cut into
- *              chunks of 16 entries of the lighter of the first- and
+ *              chunks of 32 entries of the lighter of the first- and
  *              last-edge pairs (the driver)
  *   drivers    driver entries whose window range holds a middle edge and a
  *              candidate edge on the third pair

@@ -51,7 +51,7 @@ namespace {
 using namespace sweepdev;
 
 constexpr int ST_TPB = 256;
-constexpr int64_t ST_K = 16;  // driver entries per task
+constexpr int64_t ST_K = 32;  // driver entries per task (16: 3% slower on zipf10m, 64: 25%)
 // candidate out-neighbour pairs the enumeration may check (about a second)
 constexpr uint64_t ST_MAX_BUILD_CHECKS = 1ull << 33;
 // smallest graph (non-self-loop edges) that takes this path by default: the
