@@ -496,9 +496,11 @@ tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask, int mode, int64_t del
 // has fewer than 2^20 non-self-loop edges (unless TM_TRI_STATIC=1; =0 turns
 // the path off), or the calling thread has switched the path off; then the
 // incidence-list sweep must count them.  Allocates per-thread workspace and reads two sizes
-// back to the host (the stream is synchronised).
+// back to the host (the stream is synchronised).  shared: other kernels of
+// the pass run beside it on other streams (it then takes a smaller grid).
 tm_status tm_tri_static_weight(const tm_graph *g, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,
-                               const uint64_t *wfx, uint64_t *out, hipStream_t st, uint64_t pass, bool *used);
+                               const uint64_t *wfx, uint64_t *out, hipStream_t st, uint64_t pass, bool shared,
+                               bool *used);
 // Off for the calling thread: the query server charges its batches the
 // incidence-list sweep's bytes.
 void tm_tri_static_enable(bool on);

@@ -461,7 +461,8 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, bool s
     const bool defer_tri = MODE == MODE_WEIGHT && a.static_tri && todo[0].kind == 2;
     if (defer_tri) {
         bool used = false;
-        TM_TRY(tm_tri_static_weight(g, a.delta, a.s, a.L, a.seed, a.p, a.wfx, a.out, st, pass, &used));
+        TM_TRY(tm_tri_static_weight(g, a.delta, a.s, a.L, a.seed, a.p, a.wfx, a.out, st, pass, side != nullptr,
+                                    &used));
         if (!used) {
             SweepArgs b = a;
             b.counter = a.counter + TM_SWEEP_PARTS * 2;

@@ -729,8 +729,8 @@ namespace {
 // *used = false when the path is off or the graph keeps no static triangles;
 // nu, nt: units and tasks.
 tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,
-                 const uint64_t *wfx, uint64_t *out, hipStream_t st, uint64_t pass, bool census, bool *used,
-                 int64_t *nu_out, int64_t *nt_out) {
+                 const uint64_t *wfx, uint64_t *out, hipStream_t st, uint64_t pass, int groups_per_cu, bool census,
+                 bool *used, int64_t *nu_out, int64_t *nt_out) {
     *used = false;
     *nu_out = *nt_out = 0;
     if (L <= 0) return TM_OK;
@@ -811,7 +811,7 @@ tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64
     TM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     if (ncu <= 0) ncu = 256;
     int64_t nb = (nt + ST_TPB / TM_WAVE - 1) / (ST_TPB / TM_WAVE);  // one task per wave
-    if (nb > (int64_t)ncu * 8) nb = (int64_t)ncu * 8;
+    if (nb > (int64_t)ncu * groups_per_cu) nb = (int64_t)ncu * groups_per_cu;
     if (nb < 1) nb = 1;
     if (census) {
         hipLaunchKernelGGL((k_st_weight<true>), dim3((unsigned)nb), dim3(ST_TPB), 0, st, G, a);
@@ -827,7 +827,8 @@ tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64
 }  // namespace
 
 tm_status tm_tri_static_weight(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,
-                               const uint64_t *wfx, uint64_t *out, hipStream_t st, uint64_t pass, bool *used) {
+                               const uint64_t *wfx, uint64_t *out, hipStream_t st, uint64_t pass, bool shared,
+                               bool *used) {
     *used = false;
     if (!t_st_enabled) return TM_OK;
     // TM_TRI_STATIC=0 keeps the incidence-list sweep, =1 takes this path on
@@ -836,8 +837,14 @@ tm_status tm_tri_static_weight(const tm_graph *gc, int64_t delta, int64_t s, int
     const char *e = getenv("TM_TRI_STATIC");
     if (e && e[0] == '0') return TM_OK;
     if (!(e && e[0] == '1') && gc->m_nl < ST_MIN_EDGES) return TM_OK;
+    // Beside the pass's other kernels two work-groups per CU (eight waves,
+    // two per SIMD at 122 VGPRs) leave each SIMD room for one wave of the
+    // 2-node/star sweep and one of the backward star sweep: on zipf10m the four
+    // estimate passes took 109 ms against 136 ms with three work-groups per CU
+    // and 141 ms with eight.  Alone, eight fill the CUs (c 30, p 0.1: 26 ms
+    // against 38 ms with two).
     int64_t nu, nt;
-    return st_run(gc, delta, s, L, seed, p, wfx, out, st, pass, false, used, &nu, &nt);
+    return st_run(gc, delta, s, L, seed, p, wfx, out, st, pass, shared ? 2 : 8, false, used, &nu, &nt);
 }
 
 tm_status tm_tri_static_census_impl(const tm_graph *g, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,
@@ -848,7 +855,7 @@ tm_status tm_tri_static_census_impl(const tm_graph *g, int64_t delta, int64_t s,
     TM_HIP(hipGetLastError());
     bool used = false;
     int64_t nu = 0, nt = 0;
-    TM_TRY(st_run(g, delta, s, L, seed, p, nullptr, o.as<uint64_t>(), st, 0, true, &used, &nu, &nt));
+    TM_TRY(st_run(g, delta, s, L, seed, p, nullptr, o.as<uint64_t>(), st, 0, 8, true, &used, &nu, &nt));
     if (!used) return TM_EUNSUPPORTED;
     uint64_t h[4];
     TM_HIP(hipMemcpyAsync(h, o.p, 32, hipMemcpyDeviceToHost, st));
