@@ -255,6 +255,39 @@ def test_static_triangles_equal_list_sweep(tm, monkeypatch):
                 assert k == int(o["win_counts"].sum()), M
 
 
+def test_static_triangles_huge_span(tm, monkeypatch):
+    """Bursts of edges on four nodes at times up to 2^62: about 10^15 windows,
+    far more than the per-call list of kept window ids holds, so each static
+    triangle's walk draws every window its lightest pair touches.  Estimates
+    and kept counts equal the incidence-list sweep's bit for bit."""
+    rng = np.random.default_rng(9)
+    pairs = np.array([(0, 1), (1, 2), (0, 2), (2, 3), (1, 3)])
+    src, dst, t = [], [], []
+    for base in (0, 1 << 40, 1 << 60, (1 << 62) - 5000):
+        k = 300
+        sel = rng.integers(0, len(pairs), k)
+        flip = rng.integers(0, 2, k).astype(bool)
+        src.append(np.where(flip, pairs[sel, 1], pairs[sel, 0]))
+        dst.append(np.where(flip, pairs[sel, 0], pairs[sel, 1]))
+        t.append(base + rng.integers(0, 4000, k))
+    g = ti.Graph(np.concatenate(src).astype(np.int32), np.concatenate(dst).astype(np.int32),
+                 np.concatenate(t).astype(np.int64), 4)
+    G = load(tm, g)
+    tri_codes = [i for i, M in enumerate(THREE) if len({x for e in M for x in e}) == 3
+                 and len({frozenset(e) for e in M}) == 3]
+    kept_tri = 0
+    for (delta, c, p, seed) in ((1000, 3, 0.6, 1), (500, 2, 1.0, 2), (2000, 5, 0.3, 3)):
+        say("static_huge_span", delta, c, p, seed)
+        monkeypatch.setenv("TM_TRI_STATIC", "0")
+        z0, k0 = tm.estimate_multi(G, THREE, delta, c, p, seed)
+        monkeypatch.setenv("TM_TRI_STATIC", "1")
+        z1, k1 = tm.estimate_multi(G, THREE, delta, c, p, seed)
+        monkeypatch.delenv("TM_TRI_STATIC")
+        assert k1 == k0 and z1 == z0
+        kept_tri += sum(k1[i] for i in tri_codes)
+    assert kept_tri > 0
+
+
 def test_tri_static_census(tm):
     """The census of the static-triangle path counts, by brute force over the
     oracle's shift and kept windows: the (static triangle, kept window) units
