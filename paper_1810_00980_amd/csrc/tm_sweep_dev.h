@@ -474,7 +474,7 @@ __device__ inline void tri_rank(const DevGraph &G, uint32_t yi, uint32_t di, int
 // entries instead of two per entry; the entries are then visited in order.
 // Indices are clamped to the list, so no load leaves it.  (The weighted
 // triangle sweep gains too, though it drops from five resident waves to
-// four: zipf10m at c 30, p 0.1, 91 -> 84 ms.)
+// four: on a 10M-edge Zipf graph at c 30, p 0.1, 91 -> 84 ms.)
 constexpr int SCAN_U = 4;
 
 // forward: entries j = first, first + 1, ... < end (times tv, endpoint words

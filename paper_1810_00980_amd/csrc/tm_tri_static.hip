@@ -51,7 +51,7 @@ namespace {
 using namespace sweepdev;
 
 constexpr int ST_TPB = 256;
-constexpr int64_t ST_K = 32;  // driver entries per task (16: 3% slower on zipf10m, 64: 25%)
+constexpr int64_t ST_K = 32;  // driver entries per task (on a 10M-edge Zipf graph 16 ran 3% slower, 64 25%)
 // candidate out-neighbour pairs the enumeration may check (about a second)
 constexpr uint64_t ST_MAX_BUILD_CHECKS = 1ull << 33;
 // smallest graph (non-self-loop edges) that takes this path by default: the
@@ -839,10 +839,10 @@ tm_status tm_tri_static_weight(const tm_graph *gc, int64_t delta, int64_t s, int
     if (!(e && e[0] == '1') && gc->m_nl < ST_MIN_EDGES) return TM_OK;
     // Beside the pass's other kernels two work-groups per CU (eight waves,
     // two per SIMD at 122 VGPRs) leave each SIMD room for one wave of the
-    // 2-node/star sweep and one of the backward star sweep: on zipf10m the four
-    // estimate passes took 109 ms against 136 ms with three work-groups per CU
-    // and 141 ms with eight.  Alone, eight fill the CUs (c 30, p 0.1: 26 ms
-    // against 38 ms with two).
+    // 2-node/star sweep and one of the backward star sweep: on a 10M-edge Zipf
+    // graph (100k nodes) four estimate passes took 109 ms against 136 ms with
+    // three work-groups per CU and 141 ms with eight.  Alone, eight fill the
+    // CUs (c 30, p 0.1: 26 ms against 38 ms with two).
     int64_t nu, nt;
     return st_run(gc, delta, s, L, seed, p, wfx, out, st, pass, shared ? 2 : 8, false, used, &nu, &nt);
 }
