@@ -248,7 +248,8 @@ def test_static_triangles_equal_list_sweep(tm, monkeypatch):
         tm.profile_enable(True)
         tm.estimate_multi(G, THREE, delta, c, p, seed)
         tm.profile_enable(False)
-        assert tm.profile_read("tri_static_weight")[1] + tm.profile_read("tri_static_prep")[1] >= 1
+        if g.n != 40:  # the bipartite graph has no static triangle: nothing to launch
+            assert tm.profile_read("tri_static_weight")[1] + tm.profile_read("tri_static_prep")[1] >= 1
         assert tm.profile_read("sweep3_tri_weight")[1] == 0
         monkeypatch.delenv("TM_TRI_STATIC")
         assert k1 == k0
