@@ -480,7 +480,8 @@ int tm_sweep_code_of(const tm_motif *M);  // -1 when M is not one of them
 // kernels one after another on st instead of forking them onto the calling
 // thread's side streams (which are created on first use).  Accumulators and
 // counters are cleared by a kernel, not a memset.  static_tri: in mode 1
-// over kept windows, count the triangle codes over the static triangles
+// over kept windows (windowed 1 or 3), count the triangle codes over the
+// static triangles
 // (tm_tri_static_weight, which allocates and synchronises st) instead of the
 // incidence lists.  Allocates nothing in modes 1 and 2 without static_tri;
 // the exact triangle sweep of mode 0 sorts its claim order in
@@ -491,7 +492,9 @@ tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask, int mode, int64_t del
                     uint64_t *win_dev = nullptr, bool single_stream = false, bool static_tri = false);
 
 // Weighted triangle sums (codes 20..27 of out, added to) of the kept windows
-// of (s, L, seed, p) over the graph's static triangles, built on first use.
+// of (s, L, seed, p) over the graph's static triangles, built on first use;
+// with kidx (window j kept when kidx[j] >= 0, j = 1 .. the last window of the
+// graph) the sums of each kept window go to its own 36 x 4 slot of win.
 // *used = false (nothing enqueued) when the graph keeps no static triangles,
 // has fewer than 2^20 non-self-loop edges (unless TM_TRI_STATIC=1; =0 turns
 // the path off), or the calling thread has switched the path off; then the
@@ -499,8 +502,8 @@ tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask, int mode, int64_t del
 // back to the host (the stream is synchronised).  shared: other kernels of
 // the pass run beside it on other streams (it then takes a smaller grid).
 tm_status tm_tri_static_weight(const tm_graph *g, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,
-                               const uint64_t *wfx, uint64_t *out, hipStream_t st, uint64_t pass, bool shared,
-                               bool *used);
+                               const int32_t *kidx, const uint64_t *wfx, uint64_t *out, uint64_t *win,
+                               hipStream_t st, uint64_t pass, bool shared, bool *used);
 // Off for the calling thread: the query server charges its batches the
 // incidence-list sweep's bytes.
 void tm_tri_static_enable(bool on);

@@ -461,8 +461,8 @@ tm_status launch_pair(const tm_graph *g, SweepArgs a, bool fwd, bool bwd, bool s
     const bool defer_tri = MODE == MODE_WEIGHT && a.static_tri && todo[0].kind == 2;
     if (defer_tri) {
         bool used = false;
-        TM_TRY(tm_tri_static_weight(g, a.delta, a.s, a.L, a.seed, a.p, a.wfx, a.out, st, pass, side != nullptr,
-                                    &used));
+        TM_TRY(tm_tri_static_weight(g, a.delta, a.s, a.L, a.seed, a.p, a.windowed == 3 ? a.kidx : nullptr, a.wfx,
+                                    a.out, a.windowed == 3 ? a.win : nullptr, st, pass, side != nullptr, &used));
         if (!used) {
             SweepArgs b = a;
             b.counter = a.counter + TM_SWEEP_PARTS * 2;
@@ -786,7 +786,7 @@ tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask_lo, int mode, int64_t 
     a.out = out_dev;
     a.counter = counter_dev;
     a.n_entries = 2 * g->m_nl;
-    a.static_tri = static_tri && mode == MODE_WEIGHT && windowed == 1;
+    a.static_tri = static_tri && mode == MODE_WEIGHT && (windowed == 1 || windowed == 3);
     uint32_t wf = 0;
     if (code_mask_lo & 0xFull) wf |= 1;
     if (code_mask_lo & 0xFF0ull) wf |= 2;

@@ -204,26 +204,33 @@ __device__ inline int64_t st_lower(const DevGraph &G, const StPairs &P, int r, i
     return pair_lower<false>(G, P.m[r], P.en[r], P.n[r], t, &c0, &be);
 }
 
-// kept window ids of the call, ascending: flags, then a scan, then the ids
-__global__ void k_st_kept_flags(int64_t J, uint64_t seed, double p, int64_t *flag) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
-    if (j <= J) flag[j - 1] = keep_window(seed, (uint64_t)j, p) ? 1 : 0;
+// whether window j is kept: its draw against p, or (kidx) its kept index
+__device__ inline bool st_keep(const int32_t *kidx, uint64_t seed, double p, int64_t j) {
+    return kidx ? kidx[j] >= 0 : keep_window(seed, (uint64_t)j, p);
 }
 
-__global__ void k_st_kept_fill(int64_t J, uint64_t seed, double p, const int64_t *pos, int64_t *kept) {
+// kept window ids of the call, ascending: flags, then a scan, then the ids
+__global__ void k_st_kept_flags(int64_t J, const int32_t *kidx, uint64_t seed, double p, int64_t *flag) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
-    if (j <= J && keep_window(seed, (uint64_t)j, p)) kept[pos[j - 1]] = j;
+    if (j <= J) flag[j - 1] = st_keep(kidx, seed, p, j) ? 1 : 0;
+}
+
+__global__ void k_st_kept_fill(int64_t J, const int32_t *kidx, uint64_t seed, double p, const int64_t *pos,
+                               int64_t *kept) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (j <= J && st_keep(kidx, seed, p, j)) kept[pos[j - 1]] = j;
 }
 
 // The kept windows in which all three pairs of triangle i have entries:
 // walked along the lightest pair's entries, from one kept window it touches
 // to the next (kept: the call's kept window ids ascending, *nkept of them;
-// nullptr: every window it touches, with its draw).  FILL writes each as a
-// unit at units[uoff[i]...] with its task count.
+// nullptr: every window it touches, kept by its draw or, with kidx, by its
+// kept index).  FILL writes each as a unit at units[uoff[i]...] with its
+// task count.
 template <bool FILL>
 __global__ void k_st_units(DevGraph G, const StTri *tris, int64_t ntri, int64_t s, int64_t L, uint64_t seed,
-                           double p, const int64_t *kept, const int64_t *nkept, int64_t *ucnt, StUnit *units,
-                           int64_t *tcnt) {
+                           double p, const int32_t *kidx, const int64_t *kept, const int64_t *nkept, int64_t *ucnt,
+                           StUnit *units, int64_t *tcnt) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ntri) return;
     const StTri T = tris[i];
@@ -252,7 +259,7 @@ __global__ void k_st_units(DevGraph G, const StTri *tris, int64_t ntri, int64_t 
         }
         const int64_t wlo = s + (jw - 1) * L, whi = wlo > LLONG_MAX - L ? LLONG_MAX - 1 : wlo + L - 1;
         const int64_t kn = st_lower(G, P, li, whi + 1);
-        if (kept || keep_window(seed, (uint64_t)jw, p)) {
+        if (kept || st_keep(kidx, seed, p, jw)) {
             int64_t lo[3], hi[3];
             bool all = true;
 #pragma unroll
@@ -371,6 +378,10 @@ struct StArgs {
     int64_t ntask;
     unsigned long long *counter;
     uint64_t *out;  // 36 x {count lo, hi, weight lo, hi}; codes 20..27 are added to
+    // per-window sums instead: window j's kept index kidx[j] picks its 36 x 4
+    // slot of win (nullptr: the shared sums of out)
+    const int32_t *kidx;
+    uint64_t *win;
 };
 
 // first index k' in [lo, k] such that every index in [k', k) has a time after
@@ -506,6 +517,30 @@ __device__ inline void st_flush(const StAcc &A, const int codes[4], unsigned lon
     }
 }
 
+// The four sums of every lane added over the wave, then by lane 0 into a
+// window's slot in device memory (per-lane counts of a task stay below 2^55,
+// so the wave's count sum needs no carry).
+__device__ inline void st_flush_global(const StAcc &A, const int codes[4], uint64_t *dst, int lane) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        uint64_t c = A.c[k], wl = A.wl[k], wh = A.wh[k];
+        for (int off = TM_WAVE / 2; off > 0; off >>= 1) {
+            const uint64_t oc = __shfl_xor(c, off, TM_WAVE);
+            const uint64_t ol = __shfl_xor(wl, off, TM_WAVE);
+            const uint64_t oh = __shfl_xor(wh, off, TM_WAVE);
+            c += oc;
+            const uint64_t nl = wl + ol;
+            wh += oh + (nl < wl ? 1ull : 0ull);
+            wl = nl;
+        }
+        if (lane == 0) {
+            uint64_t *o = dst + 4 * codes[k];
+            if (c) tm_atomic_add_u128(o, o + 1, c, 0);
+            if (wl | wh) tm_atomic_add_u128(o + 2, o + 3, wl, wh);
+        }
+    }
+}
+
 // One task, by the whole wave: the driver entries one after another (every
 // lane computes the same pointers), the inner ranges 64 entries at a time.
 // Sums go to two accumulator sets chosen by the driver entry's direction
@@ -551,8 +586,14 @@ __device__ void st_task(const DevGraph &G, const StArgs &a, uint64_t tw, int lan
         if constexpr (CENSUS) return;
         // set d1, slot 2 dm + d3 -> code 20 + 4 d1 + 2 dm + d3
         const int c0[4] = {20, 21, 22, 23}, c1[4] = {24, 25, 26, 27};
-        st_flush(A0, c0, lds);
-        st_flush(A1, c1, lds);
+        if (a.kidx) {
+            uint64_t *dst = a.win + (int64_t)a.kidx[u.jw] * 36 * 4;
+            st_flush_global(A0, c0, dst, lane);
+            st_flush_global(A1, c1, dst, lane);
+        } else {
+            st_flush(A0, c0, lds);
+            st_flush(A1, c1, lds);
+        }
     } else {
         const int64_t d0 = loC + chunk * ST_K, d1e = d0 + ST_K < hiC ? d0 + ST_K : hiC;
         int64_t pb = loB, i0 = loA;
@@ -576,8 +617,14 @@ __device__ void st_task(const DevGraph &G, const StArgs &a, uint64_t tw, int lan
         if constexpr (CENSUS) return;
         // set d3, slot 2 dm + d1 -> code 20 + 4 d1 + 2 dm + d3
         const int c0[4] = {20, 24, 22, 26}, c1[4] = {21, 25, 23, 27};
-        st_flush(A0, c0, lds);
-        st_flush(A1, c1, lds);
+        if (a.kidx) {
+            uint64_t *dst = a.win + (int64_t)a.kidx[u.jw] * 36 * 4;
+            st_flush_global(A0, c0, dst, lane);
+            st_flush_global(A1, c1, dst, lane);
+        } else {
+            st_flush(A0, c0, lds);
+            st_flush(A1, c1, lds);
+        }
     }
 }
 
@@ -729,8 +776,8 @@ namespace {
 // *used = false when the path is off or the graph keeps no static triangles;
 // nu, nt: units and tasks.
 tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,
-                 const uint64_t *wfx, uint64_t *out, hipStream_t st, uint64_t pass, int groups_per_cu, bool census,
-                 bool *used, int64_t *nu_out, int64_t *nt_out) {
+                 const int32_t *kidx, const uint64_t *wfx, uint64_t *out, uint64_t *win, hipStream_t st,
+                 uint64_t pass, int groups_per_cu, bool census, bool *used, int64_t *nu_out, int64_t *nt_out) {
     *used = false;
     *nu_out = *nt_out = 0;
     if (L <= 0) return TM_OK;
@@ -752,18 +799,18 @@ tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64
     if (J <= ST_MAX_WINDOW_LIST) {
         TM_TRY(W.kflag.reserve((size_t)(J + 1) * 8));
         TM_TRY(W.kept.reserve((size_t)J * 8));
-        hipLaunchKernelGGL(k_st_kept_flags, dim3(tm_blocks(J, 256)), dim3(256), 0, st, J, seed, p,
+        hipLaunchKernelGGL(k_st_kept_flags, dim3(tm_blocks(J, 256)), dim3(256), 0, st, J, kidx, seed, p,
                            W.kflag.as<int64_t>());
         TM_HIP(hipGetLastError());
         TM_TRY(tm_scan_i64(W.kflag.as<int64_t>(), J, W.kflag.as<int64_t>() + J, st));
-        hipLaunchKernelGGL(k_st_kept_fill, dim3(tm_blocks(J, 256)), dim3(256), 0, st, J, seed, p,
+        hipLaunchKernelGGL(k_st_kept_fill, dim3(tm_blocks(J, 256)), dim3(256), 0, st, J, kidx, seed, p,
                            W.kflag.as<int64_t>(), W.kept.as<int64_t>());
         TM_HIP(hipGetLastError());
         kept = W.kept.as<int64_t>();
         nkept = W.kflag.as<int64_t>() + J;
     }
     hipLaunchKernelGGL((k_st_units<false>), dim3(tm_blocks(ntri, 256)), dim3(256), 0, st, G, tris, ntri, s, L, seed,
-                       p, kept, nkept, W.cnt.as<int64_t>(), (StUnit *)nullptr, (int64_t *)nullptr);
+                       p, kidx, kept, nkept, W.cnt.as<int64_t>(), (StUnit *)nullptr, (int64_t *)nullptr);
     TM_HIP(hipGetLastError());
     TM_TRY(tm_scan_i64(W.cnt.as<int64_t>(), ntri, W.cnt.as<int64_t>() + ntri, st));
     int64_t nu = 0;
@@ -776,7 +823,7 @@ tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64
     TM_TRY(W.units.reserve((size_t)nu * sizeof(StUnit)));
     TM_TRY(W.tcnt.reserve((size_t)(nu + 1) * 8));
     hipLaunchKernelGGL((k_st_units<true>), dim3(tm_blocks(ntri, 256)), dim3(256), 0, st, G, tris, ntri, s, L, seed,
-                       p, kept, nkept, W.cnt.as<int64_t>(), W.units.as<StUnit>(), W.tcnt.as<int64_t>());
+                       p, kidx, kept, nkept, W.cnt.as<int64_t>(), W.units.as<StUnit>(), W.tcnt.as<int64_t>());
     TM_HIP(hipGetLastError());
     TM_TRY(tm_scan_i64(W.tcnt.as<int64_t>(), nu, W.tcnt.as<int64_t>() + nu, st));
     int64_t nt = 0;
@@ -807,6 +854,8 @@ tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64
     a.ntask = nt;
     a.counter = W.ctr.as<unsigned long long>();
     a.out = out;
+    a.kidx = kidx;
+    a.win = win;
     int dev = g->device, ncu = 0;
     TM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     if (ncu <= 0) ncu = 256;
@@ -827,8 +876,8 @@ tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64
 }  // namespace
 
 tm_status tm_tri_static_weight(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,
-                               const uint64_t *wfx, uint64_t *out, hipStream_t st, uint64_t pass, bool shared,
-                               bool *used) {
+                               const int32_t *kidx, const uint64_t *wfx, uint64_t *out, uint64_t *win,
+                               hipStream_t st, uint64_t pass, bool shared, bool *used) {
     *used = false;
     if (!t_st_enabled) return TM_OK;
     // TM_TRI_STATIC=0 keeps the incidence-list sweep, =1 takes this path on
@@ -844,7 +893,7 @@ tm_status tm_tri_static_weight(const tm_graph *gc, int64_t delta, int64_t s, int
     // three work-groups per CU and 141 ms with eight.  Alone, eight fill the
     // CUs (c 30, p 0.1: 26 ms against 38 ms with two).
     int64_t nu, nt;
-    return st_run(gc, delta, s, L, seed, p, wfx, out, st, pass, shared ? 2 : 8, false, used, &nu, &nt);
+    return st_run(gc, delta, s, L, seed, p, kidx, wfx, out, win, st, pass, shared ? 2 : 8, false, used, &nu, &nt);
 }
 
 tm_status tm_tri_static_census_impl(const tm_graph *g, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,
@@ -855,7 +904,8 @@ tm_status tm_tri_static_census_impl(const tm_graph *g, int64_t delta, int64_t s,
     TM_HIP(hipGetLastError());
     bool used = false;
     int64_t nu = 0, nt = 0;
-    TM_TRY(st_run(g, delta, s, L, seed, p, nullptr, o.as<uint64_t>(), st, 0, 8, true, &used, &nu, &nt));
+    TM_TRY(st_run(g, delta, s, L, seed, p, nullptr, nullptr, o.as<uint64_t>(), nullptr, st, 0, 8, true, &used, &nu,
+                  &nt));
     if (!used) return TM_EUNSUPPORTED;
     uint64_t h[4];
     TM_HIP(hipMemcpyAsync(h, o.p, 32, hipMemcpyDeviceToHost, st));

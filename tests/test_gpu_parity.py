@@ -295,6 +295,34 @@ def test_static_triangles_huge_span(tm, monkeypatch):
     assert kept_tri > 0
 
 
+def test_static_triangles_per_window(tm, monkeypatch):
+    """Edge-proportional estimates (b shifts, each kept window's weighted
+    counts Y_{s,j} kept apart) with the triangle sums over the static
+    triangles equal those over the incidence lists bit for bit: estimates,
+    kept windows and every window's Y_{s,j}; the oracle checks the small
+    case."""
+    cases = [
+        (ti.config_zipf(200_000, 2_000, 1.8, 2_000_000, 7), 3600, 10, 6.0, 3, 4),
+        (_one_triangle_graph(8), 40, 2, 3.0, 2, 5),
+    ]
+    for g, delta, c, r, b, seed in cases:
+        say("static_per_window", g.m, delta, c, r, b, seed)
+        G = load(tm, g)
+        monkeypatch.setenv("TM_TRI_STATIC", "0")
+        e0, w0 = tm.estimate_q(G, THREE, delta, c, r, b, seed)
+        monkeypatch.setenv("TM_TRI_STATIC", "1")
+        e1, w1 = tm.estimate_q(G, THREE, delta, c, r, b, seed)
+        monkeypatch.delenv("TM_TRI_STATIC")
+        assert w0["n_kept"] == w1["n_kept"] > 0 and e0 == e1
+        for key in ("k", "j", "q", "y"):
+            assert np.array_equal(w0[key], w1[key]), key
+        if g.n == 4:
+            for i, M in enumerate(THREE):
+                if len({x for e in M for x in e}) == 3 and len({frozenset(e) for e in M}) == 3:
+                    o = oracle.estimate_q(g.src, g.dst, g.t, M, delta, c, r, b, seed)
+                    assert close(e1[i], o["Z"]), (M, e1[i], o["Z"])
+
+
 def test_tri_static_census(tm):
     """The census of the static-triangle path counts, by brute force over the
     oracle's shift and kept windows: the (static triangle, kept window) units
