@@ -195,6 +195,15 @@ tm_status tm_estimate(const tm_graph *g, const tm_motif *M, int64_t delta, int64
  * shift and kept windows for all of them (one pass when all have three
  * edges).  estimates[i] for motifs[i]; kept_counts (nullable) the exact
  * per-motif instance counts over the kept windows.
+ *
+ * Three-node triangle motifs (their three edges on three node pairs) are
+ * summed over the graph's static triangles on graphs of at least 2^20
+ * non-self-loop edges (tm_tri_static_census describes that work; the static
+ * triangles are found on the first such call and kept with the graph), over
+ * the incidence lists otherwise; both give the same bits.  The environment
+ * variable TM_TRI_STATIC=0 keeps the incidence lists, =1 takes the static
+ * triangles on any graph.  Calls made by the query server's slot threads
+ * keep the incidence lists.  The same holds for tm_estimate and tm_estimate_q.
  */
 tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, const tm_motif *motifs,
                             int64_t delta, int64_t c, double p, uint64_t seed, double *estimates,
