@@ -52,8 +52,15 @@ using namespace sweepdev;
 
 constexpr int ST_TPB = 256;
 constexpr int64_t ST_K = 32;  // driver entries per task (on a 10M-edge Zipf graph 16 ran 3% slower, 64 25%)
-// candidate out-neighbour pairs the enumeration may check (about a second)
+// candidate out-neighbour pairs the enumeration may check: at most about a
+// second's worth, and at most ST_CHECKS_PER_EDGE per edge; and static
+// triangles kept: at most one per edge.  Every estimate walks every static
+// triangle, while the incidence-list sweep's work follows the kept windows'
+// edges, so a graph whose node pairs are nearly all joined (2,000 nodes,
+// 4e6 edges: 1.3e9 static triangles, 32 GB) keeps the list sweep, which there
+// took 1.7 ms against 275 ms.
 constexpr uint64_t ST_MAX_BUILD_CHECKS = 1ull << 33;
+constexpr uint64_t ST_CHECKS_PER_EDGE = 64;
 // smallest graph (non-self-loop edges) that takes this path by default: the
 // set-up costs about fifteen launches and two reads back to the host, about
 // a millisecond, which a list sweep of a smaller graph does not
@@ -724,7 +731,9 @@ tm_status st_index(tm_graph *g, hipStream_t st, bool *ok) {
     int64_t checks[2] = {0, 0};  // candidate checks, largest pair
     TM_HIP(hipMemcpyAsync(checks, tot.p, 16, hipMemcpyDeviceToHost, st));
     TM_HIP(hipStreamSynchronize(st));
-    if ((uint64_t)checks[0] > ST_MAX_BUILD_CHECKS || checks[1] >= ((int64_t)1 << 28)) return TM_OK;
+    if ((uint64_t)checks[0] > ST_MAX_BUILD_CHECKS || (uint64_t)checks[0] > ST_CHECKS_PER_EDGE * (uint64_t)g->m_nl ||
+        checks[1] >= ((int64_t)1 << 28))
+        return TM_OK;
     TM_TRY(cnt.alloc((size_t)(U + 1) * 8));
     hipLaunchKernelGGL((k_st_tris<false>), dim3(tm_blocks(U, 256)), dim3(256), 0, st, G, off.as<int64_t>(), n, U,
                        onbr.as<uint32_t>(), opid.as<int32_t>(), cnt.as<int64_t>(), (StTri *)nullptr);
@@ -734,7 +743,7 @@ tm_status st_index(tm_graph *g, hipStream_t st, bool *ok) {
     TM_TRY(read_i64(cnt.as<int64_t>() + U, &ntri, st));
     size_t free_b = 0, total_b = 0;
     TM_HIP(hipMemGetInfo(&free_b, &total_b));
-    if (ntri > INT32_MAX || (double)ntri * sizeof(StTri) > (double)free_b / 8) return TM_OK;
+    if (ntri > INT32_MAX || ntri > g->m_nl || (double)ntri * sizeof(StTri) > (double)free_b / 8) return TM_OK;
     DevBuf tri;
     TM_TRY(tri.alloc((size_t)(ntri > 0 ? ntri : 1) * sizeof(StTri)));
     hipLaunchKernelGGL((k_st_tris<true>), dim3(tm_blocks(U, 256)), dim3(256), 0, st, G, off.as<int64_t>(), n, U,

@@ -323,6 +323,34 @@ def test_static_triangles_per_window(tm, monkeypatch):
                     assert close(e1[i], o["Z"]), (M, e1[i], o["Z"])
 
 
+def test_static_triangles_not_kept_on_dense_graph(tm, monkeypatch):
+    """A graph whose node pairs are nearly all joined has far more static
+    triangles than edges: the index is not kept (the census reports the path
+    as unsupported), and estimates, even with the static path forced, count
+    triangles over the incidence lists, with the same results."""
+    rng = np.random.default_rng(11)
+    n, m = 300, 60_000
+    src = rng.integers(0, n, m)
+    dst = (src + rng.integers(1, n, m)) % n  # no self-loops
+    g = ti.Graph(src.astype(np.int32), dst.astype(np.int32), np.sort(rng.integers(0, 2_000_000, m)).astype(np.int64),
+                 n)
+    say("static_not_kept", g.m, g.n)
+    G = load(tm, g)
+    with pytest.raises(tm.TMError) as e:
+        tm.tri_static_census(G, 600, 3, 0.5, 1)
+    assert e.value.status == 2
+    monkeypatch.setenv("TM_TRI_STATIC", "0")
+    z0, k0 = tm.estimate_multi(G, THREE, 600, 3, 0.5, 1)
+    monkeypatch.setenv("TM_TRI_STATIC", "1")
+    tm.profile_reset()
+    tm.profile_enable(True)
+    z1, k1 = tm.estimate_multi(G, THREE, 600, 3, 0.5, 1)
+    tm.profile_enable(False)
+    monkeypatch.delenv("TM_TRI_STATIC")
+    assert z1 == z0 and k1 == k0
+    assert tm.profile_read("sweep3_tri_weight")[1] == 1 and tm.profile_read("tri_static_weight")[1] == 0
+
+
 def test_tri_static_census(tm):
     """The census of the static-triangle path counts, by brute force over the
     oracle's shift and kept windows: the (static triangle, kept window) units
