@@ -501,17 +501,10 @@ def run_serve(args):
     slots, budget = 4, args.serve_budget_gib << 30
 
     def direct(q):
-        # the server's slot threads count weighted triangles over the incidence
-        # lists (their admission charges that path's bytes); one query at a
-        # time does the same, so that both sides run the same kernels
         G = Gs[q["graph"]]
         if q["kind"] == 0:
             return tm.count_exact(G, q["edges"], q["delta"])
-        os.environ["TM_TRI_STATIC"] = "0"
-        try:
-            r = tm.estimate(G, q["edges"], q["delta"], q["c"], q["p"], q["seed"], info=(q["edges"] == ti.CYCLE4))
-        finally:
-            del os.environ["TM_TRI_STATIC"]
+        r = tm.estimate(G, q["edges"], q["delta"], q["c"], q["p"], q["seed"], info=(q["edges"] == ti.CYCLE4))
         return r["Z"] if isinstance(r, dict) else r
 
     warm = serving_queries(np.random.default_rng(1), sizes, 60, 1000.0)

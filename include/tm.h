@@ -202,8 +202,9 @@ tm_status tm_estimate(const tm_graph *g, const tm_motif *M, int64_t delta, int64
  * triangles are found on the first such call and kept with the graph), over
  * the incidence lists otherwise; both give the same bits.  The environment
  * variable TM_TRI_STATIC=0 keeps the incidence lists, =1 takes the static
- * triangles on any graph.  Calls made by the query server's slot threads
- * keep the incidence lists.  The same holds for tm_estimate and tm_estimate_q.
+ * triangles on any graph.  The query server's slot threads take them for a
+ * lone triangle estimate charged their workspace, within that charge (else
+ * the incidence lists).  The same holds for tm_estimate and tm_estimate_q.
  */
 tm_status tm_estimate_multi(const tm_graph *g, int32_t n_motifs, const tm_motif *motifs,
                             int64_t delta, int64_t c, double p, uint64_t seed, double *estimates,
@@ -413,7 +414,10 @@ typedef struct {
  * sweep; estimates of three-edge motifs on the same graph share the launch
  * sequence of tm_estimate_mixed, enqueued on the slot's stream rather than
  * captured, whatever their motifs, deltas, c, p and seeds; a lone estimate,
- * or one on a heavy graph, takes tm_estimate_multi's sweep), up to 256 per
+ * or one on a heavy graph, takes tm_estimate_multi's sweep; a lone triangle
+ * estimate is charged 256 MiB more, when that fits the budget, and may then
+ * sum its triangles over the graph's static triangles, which
+ * tm_server_add_graph finds for graphs of 2^20 edges or more), up to 256 per
  * batch, and starts it on a
  * free slot; batches on graphs with at least an eighth of the largest
  * graph's edges take at most half the slots while lighter graphs are

@@ -504,9 +504,17 @@ tm_status tm_sweep3(const tm_graph *g, uint64_t code_mask, int mode, int64_t del
 tm_status tm_tri_static_weight(const tm_graph *g, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,
                                const int32_t *kidx, const uint64_t *wfx, uint64_t *out, uint64_t *win,
                                hipStream_t st, uint64_t pass, bool shared, bool *used);
-// Off for the calling thread: the query server charges its batches the
-// incidence-list sweep's bytes.
+// On or off for the calling thread (the query server decides per batch).
 void tm_tri_static_enable(bool on);
+// Most device bytes one call may add to the calling thread's workspaces (0:
+// no limit).  With a limit the static triangles are not built by the call
+// (tm_tri_static_prepare builds them), and a call whose workspace would pass
+// the limit counts its triangles over the incidence lists.
+void tm_tri_static_set_cap(int64_t bytes);
+// Builds the static triangles of a graph that takes the path by default
+// (2^20 edges or more); *kept: they are kept and estimates will use them.
+tm_status tm_tri_static_prepare(tm_graph *g, hipStream_t st, bool *kept);
+bool tm_tri_static_kept(const tm_graph *g);
 // Work counts of that path (tm_tri_static_census); TM_EUNSUPPORTED when the
 // graph keeps no static triangles.
 tm_status tm_tri_static_census_impl(const tm_graph *g, int64_t delta, int64_t s, int64_t L, uint64_t seed, double p,

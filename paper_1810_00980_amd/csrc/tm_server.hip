@@ -8,7 +8,9 @@
 // three-edge motifs on the same graph share one persistent launch sequence,
 // whatever their motifs, deltas, c, p and seeds (each is its own estimator
 // in the mixed batch; a lone one, or one on a heavy graph, takes the plain
-// weighted sweep).  It
+// weighted sweep, and a lone triangle estimate charged the static path's
+// capped workspace may sum its triangles over the graph's static
+// triangles, found when the graph was added).  It
 // reserves the batch's device workspace from the budget and hands the batch
 // to the slot.  Each slot is a host thread with its own
 // HIP stream (default priority), so batches on different slots overlap on the
@@ -59,13 +61,25 @@ struct Pending {
 };
 
 constexpr size_t TM_SERVER_MAX_BATCH = 256;
+// A lone triangle estimate on a graph whose static triangles are kept may sum
+// them over those triangles when this much more workspace fits the budget; the
+// call stays within it or counts the triangles over the incidence lists.
+constexpr int64_t TM_SERVER_STATIC_WS = (int64_t)256 << 20;
 
 int64_t buf(int64_t b) { return b > 0 ? b : 256; }  // DevBuf's size for a request of b bytes
 
 // Device bytes of the path a batch takes (the DevBufs it allocates, alive
 // together).  All queries of a batch share graph and kind; a batch of more
 // than one query holds three-edge motifs only.
-int64_t batch_ws_bytes(const tm_graph *g, const std::vector<tm_query> &b) {
+// whether a batch of these queries may take the static triangles: one
+// estimate of a triangle motif on a graph whose static triangles are kept
+bool static_candidate(const tm_graph *g, const std::vector<tm_query> &b) {
+    if (b.size() != 1 || b[0].kind != 1) return false;
+    const int c = tm_sweep_code_of(&b[0].motif);
+    return c >= 20 && c < 28 && tm_tri_static_kept(g);
+}
+
+int64_t batch_ws_bytes(const tm_graph *g, const std::vector<tm_query> &b, bool with_static = false) {
     const tm_query &q0 = b[0];
     const bool three = tm_sweep_code_of(&q0.motif) >= 0;
     const int64_t m1 = g->m > 0 ? g->m : 1;
@@ -89,8 +103,10 @@ int64_t batch_ws_bytes(const tm_graph *g, const std::vector<tm_query> &b) {
         return buf(64) + tm_generic_bytes(g->m, q0.motif.l);
     }
     if (three && b.size() == 1) {
-        // the plain weighted sweep: accumulators, work counters, weights
-        return buf(36 * 4 * 8) + buf(TM_SWEEP_COUNTER_BYTES) + buf((q0.delta + 1) * 8);
+        // the plain weighted sweep: accumulators, work counters, weights; and
+        // the static triangles' capped workspace when the batch may take them
+        return buf(36 * 4 * 8) + buf(TM_SWEEP_COUNTER_BYTES) + buf((q0.delta + 1) * 8) +
+               (with_static ? TM_SERVER_STATIC_WS : 0);
     }
     if (three) {
         std::vector<int64_t> delta, L;
@@ -144,6 +160,7 @@ struct tm_server {
     std::vector<hipStream_t> streams;
     std::vector<bool> slot_busy;
     std::vector<bool> slot_heavy;      // the running batch is on a heavy graph
+    std::vector<bool> slot_static;     // the running batch may take the static triangles
     // heavy: at least an eighth of the edges of the largest graph added,
     // when some graph is lighter than that (one size class: none is heavy)
     bool is_heavy(const tm_graph *g) const {
@@ -219,6 +236,14 @@ struct tm_server {
                 const bool heavy = is_heavy(g);
                 if (heavy && heavy_running >= heavy_cap) continue;
                 int64_t need = batch_ws_bytes(g, {head.q});
+                bool use_static = false;
+                if (static_candidate(g, {head.q})) {
+                    const int64_t ns = batch_ws_bytes(g, {head.q}, true);
+                    if (ns <= budget) {
+                        need = ns;
+                        use_static = true;
+                    }
+                }
                 if (need > budget) {
                     tm_result r;
                     memset(&r, 0, sizeof r);
@@ -254,6 +279,7 @@ struct tm_server {
                             take = false;
                         } else {
                             need = more;
+                            use_static = false;  // several queries take the mixed launch
                         }
                     }
                     if (take) {
@@ -267,6 +293,7 @@ struct tm_server {
                 peak = std::max(peak, in_use);
                 slot_busy[(size_t)slot] = true;
                 slot_heavy[(size_t)slot] = heavy;
+                slot_static[(size_t)slot] = use_static;
                 slot_bytes[(size_t)slot] = need;
                 slot_work[(size_t)slot] = std::move(batch);
                 ++batches;
@@ -352,10 +379,11 @@ struct tm_server {
     void worker_loop(int slot) {
         (void)hipSetDevice(device);
         t_dev_tally.live = t_dev_tally.peak = 0;  // this thread's own allocations only
-        tm_tri_static_enable(false);              // batches are charged the list sweep's bytes
+        tm_tri_static_set_cap(TM_SERVER_STATIC_WS);  // a batch allocates no more than it was charged
         while (true) {
             std::vector<Pending> batch;
             int64_t charged = 0;
+            bool use_static = false;
             {
                 std::unique_lock<std::mutex> lk(mu);
                 cv_slot.wait(lk, [&] {
@@ -374,7 +402,9 @@ struct tm_server {
                 batch = std::move(slot_work[(size_t)slot]);
                 slot_work[(size_t)slot].clear();
                 charged = slot_bytes[(size_t)slot];
+                use_static = slot_static[(size_t)slot];
             }
+            tm_tri_static_enable(use_static);
             run_batch(slot, batch, charged);
             {
                 std::lock_guard<std::mutex> lk(mu);
@@ -403,6 +433,7 @@ extern "C" tm_status tm_server_create(int32_t slots, int64_t budget_bytes, tm_se
     S->release_req.assign((size_t)slots, false);
     S->slot_busy.assign((size_t)slots, false);
     S->slot_heavy.assign((size_t)slots, false);
+    S->slot_static.assign((size_t)slots, false);
     for (int i = 0; i < slots; ++i) {
         hipStream_t st;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -420,6 +451,12 @@ extern "C" tm_status tm_server_create(int32_t slots, int64_t budget_bytes, tm_se
 
 extern "C" tm_status tm_server_add_graph(tm_server *S, const tm_graph *g, int32_t *graph_id) {
     if (!S || !g || !graph_id) return TM_EINVAL;
+    // the static triangles of a large graph, found here once (their search's
+    // temporaries are not any batch's), so that lone triangle estimates can
+    // sum over them
+    bool kept = false;
+    TM_TRY(tm_tri_static_prepare(const_cast<tm_graph *>(g), nullptr, &kept));
+    TM_HIP(hipStreamSynchronize(nullptr));
     std::lock_guard<std::mutex> lk(S->mu);
     S->graphs.push_back(g);
     *graph_id = (int32_t)S->graphs.size() - 1;

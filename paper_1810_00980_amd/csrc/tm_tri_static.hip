@@ -675,6 +675,9 @@ struct StWs {
 thread_local StWs t_st;
 
 thread_local bool t_st_enabled = true;
+// most device bytes a call may add to the calling thread's workspaces (0:
+// no limit; the index is then also built on first use)
+thread_local int64_t t_st_cap = 0;
 
 tm_status read_i64(const int64_t *d, int64_t *h, hipStream_t st) {
     TM_HIP(hipMemcpyAsync(h, d, 8, hipMemcpyDeviceToHost, st));
@@ -685,14 +688,14 @@ tm_status read_i64(const int64_t *d, int64_t *h, hipStream_t st) {
 // The graph's static triangles, built on first use; false when there are too
 // many candidates to check or triangles to keep (then the incidence-list
 // sweep counts the triangles).
-tm_status st_index(tm_graph *g, hipStream_t st, bool *ok) {
+tm_status st_index(tm_graph *g, hipStream_t st, bool may_build, bool *ok) {
     std::lock_guard<std::mutex> lk(g_st_mu);
     *ok = false;
     if (g->st_state == 1) {
         *ok = true;
         return TM_OK;
     }
-    if (g->st_state == 2) return TM_OK;
+    if (g->st_state == 2 || !may_build) return TM_OK;
     const int64_t U = g->U, n = g->n;
     g->st_state = 2;
     if (U == 0 || n == 0) {
@@ -766,6 +769,19 @@ tm_status st_index(tm_graph *g, hipStream_t st, bool *ok) {
 
 void tm_tri_static_enable(bool on) { t_st_enabled = on; }
 
+void tm_tri_static_set_cap(int64_t bytes) { t_st_cap = bytes > 0 ? bytes : 0; }
+
+tm_status tm_tri_static_prepare(tm_graph *g, hipStream_t st, bool *kept) {
+    *kept = false;
+    if (g->m_nl < ST_MIN_EDGES) return TM_OK;
+    return st_index(g, st, true, kept);
+}
+
+bool tm_tri_static_kept(const tm_graph *g) {
+    std::lock_guard<std::mutex> lk(g_st_mu);
+    return g->st_state == 1 && g->m_nl >= ST_MIN_EDGES;
+}
+
 void tm_tri_static_release_thread_ws() {
     t_st.cnt.release();
     t_st.units.release();
@@ -791,19 +807,28 @@ tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64
     *nu_out = *nt_out = 0;
     if (L <= 0) return TM_OK;
     tm_graph *g = const_cast<tm_graph *>(gc);  // the index is a cache of the immutable graph
+    const int64_t cap = census ? 0 : t_st_cap;
     bool ok = false;
-    TM_TRY(st_index(g, st, &ok));
+    TM_TRY(st_index(g, st, cap == 0, &ok));
     if (!ok) return TM_OK;
-    *used = true;
     const int64_t ntri = g->st_ntri;
-    if (ntri == 0) return TM_OK;
+    if (ntri == 0) {
+        *used = true;
+        return TM_OK;
+    }
+    // the kept window ids, when their list is small enough to build per call
+    const int64_t J = (g->t_span - s) / L + 1;
+    // with a cap, the path is left to the incidence-list sweep as soon as its
+    // workspace (counts, window list, scans, units, tasks, sort) would pass it
+    int64_t ws = (ntri + 1) * 8 + (J <= ST_MAX_WINDOW_LIST ? (2 * J + 1) * 8 : 0) +
+                 tm_scan_ws_bytes(ntri > J ? ntri : J);
+    if (cap && ws > cap) return TM_OK;
+    *used = true;
     const DevGraph G = dev_view(g);
     const StTri *tris = g->st_tri.as<StTri>();
     StWs &W = t_st;
     void *tok = census ? nullptr : tm_prof_begin("tri_static_prep", st, pass);
     TM_TRY(W.cnt.reserve((size_t)(ntri + 1) * 8));
-    // the kept window ids, when their list is small enough to build per call
-    const int64_t J = (g->t_span - s) / L + 1;
     const int64_t *kept = nullptr, *nkept = nullptr;
     if (J <= ST_MAX_WINDOW_LIST) {
         TM_TRY(W.kflag.reserve((size_t)(J + 1) * 8));
@@ -829,6 +854,12 @@ tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64
         return TM_OK;
     }
     if (nu > UINT32_MAX) return TM_ENOMEM;
+    ws += (int64_t)nu * (int64_t)(sizeof(StUnit) + 8) + 8 + tm_scan_ws_bytes(nu);
+    if (cap && ws > cap) {
+        tm_prof_end(tok, st);
+        *used = false;
+        return TM_OK;
+    }
     TM_TRY(W.units.reserve((size_t)nu * sizeof(StUnit)));
     TM_TRY(W.tcnt.reserve((size_t)(nu + 1) * 8));
     hipLaunchKernelGGL((k_st_units<true>), dim3(tm_blocks(ntri, 256)), dim3(256), 0, st, G, tris, ntri, s, L, seed,
@@ -838,6 +869,12 @@ tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64
     int64_t nt = 0;
     TM_TRY(read_i64(W.tcnt.as<int64_t>() + nu, &nt, st));
     if (nt > UINT32_MAX) return TM_ENOMEM;
+    ws += nt * 20 + 8 + tm_radix_sort_bytes(nt);
+    if (cap && ws > cap) {
+        tm_prof_end(tok, st);
+        *used = false;
+        return TM_OK;
+    }
     *nu_out = nu;
     *nt_out = nt;
     TM_TRY(W.tasks.reserve((size_t)nt * 8));

@@ -149,3 +149,38 @@ def test_server_heavy_graph_cap(tm):
             assert r["batch_size"] == 1, q
     assert S.stats()["completed"] == len(qs)
     S.close()
+
+
+def test_server_static_triangles(tm):
+    """A graph of 2^20 edges or more gets its static triangles when it is
+    added to the server.  Under a budget with room for that path's capped
+    workspace, a lone triangle estimate (a batch of its own) is charged it
+    and sums its triangles
+    over the static triangles; under a budget without that room it is charged
+    the incidence-list sweep's bytes and runs that sweep.  Every result equals
+    the direct call's, and no batch allocates more than it was charged."""
+    g = ti.config_zipf(1_200_000, 10_000, 1.8, 3_600_000, 5)
+    G = tm.load_graph(g.src, g.dst, g.t, g.n)
+    say("server static triangles", g.m)
+    qs = [(ti.TRIANGLE, 3600, 30, 0.1, sd) for sd in range(3)]
+    qs += [(((0, 1), (2, 0), (1, 2)), 3600, 10, 0.1, 7), (((0, 1), (0, 2), (0, 2)), 3600, 30, 0.1, 8)]
+    want = [tm.estimate(G, M, d, c, p, sd) for M, d, c, p, sd in qs]
+    for budget, static in ((16 << 30, True), (64 << 20, False)):
+        tm.profile_reset()
+        tm.profile_enable(True)
+        try:
+            S = tm.Server(slots=2, budget_bytes=budget)
+            gid = S.add_graph(G)
+            # one at a time: each query is a batch of its own (queries queued
+            # together on this graph would share a mixed launch)
+            res = [S.wait(S.submit(gid, M, d, 1, c, p, sd)) for M, d, c, p, sd in qs]
+            st = S.stats()
+            S.close()
+        finally:
+            tm.profile_enable(False)
+        assert all(r["status"] == 0 and r["batch_size"] == 1 for r in res), [r["status"] for r in res]
+        assert [r["estimate"] for r in res] == want
+        assert all(0 <= r["ws_measured"] <= r["ws_charged"] for r in res)
+        assert st["over_charge"] == 0
+        assert (tm.profile_read("tri_static_weight")[1] > 0) == static, budget
+        assert (tm.profile_read("sweep3_tri_weight")[1] > 0) == (not static), budget
