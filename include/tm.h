@@ -415,10 +415,12 @@ typedef struct {
  * sequence of tm_estimate_mixed, enqueued on the slot's stream rather than
  * captured, whatever their motifs, deltas, c, p and seeds; a lone estimate,
  * or one on a heavy graph, takes tm_estimate_multi's sweep; a lone triangle
- * estimate is charged 256 MiB more, when that fits the budget, and may then
- * sum its triangles over the graph's static triangles, which
- * tm_server_add_graph finds for graphs of 2^20 edges or more), up to 256 per
- * batch, and starts it on a
+ * estimate may sum its triangles over the graph's static triangles, which
+ * tm_server_add_graph finds for graphs of 2^20 edges or more: that path's
+ * per-call workspace is known only on the device, so the running batch asks
+ * for it before allocating and its charge grows by what fits the budget then,
+ * or the estimate counts its triangles over the incidence lists), up to 256
+ * per batch, and starts it on a
  * free slot; batches on graphs with at least an eighth of the largest
  * graph's edges take at most half the slots while lighter graphs are
  * resident.  A batch is charged the

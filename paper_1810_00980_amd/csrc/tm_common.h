@@ -506,11 +506,13 @@ tm_status tm_tri_static_weight(const tm_graph *g, int64_t delta, int64_t s, int6
                                hipStream_t st, uint64_t pass, bool shared, bool *used);
 // On or off for the calling thread (the query server decides per batch).
 void tm_tri_static_enable(bool on);
-// Most device bytes one call may add to the calling thread's workspaces (0:
-// no limit).  With a limit the static triangles are not built by the call
-// (tm_tri_static_prepare builds them), and a call whose workspace would pass
-// the limit counts its triangles over the incidence lists.
-void tm_tri_static_set_cap(int64_t bytes);
+// A grant hook for the calling thread (nullptr: none).  With one, each call
+// asks it, before each of its allocation steps, for the device bytes its
+// workspace needs in all so far; a refusal leaves the call's triangles to the
+// incidence lists.  The static triangles are then not built by the call
+// (tm_tri_static_prepare builds them).
+typedef bool (*tm_st_grant_fn)(void *ctx, int64_t bytes);
+void tm_tri_static_set_grant(tm_st_grant_fn fn, void *ctx);
 // Builds the static triangles of a graph that takes the path by default
 // (2^20 edges or more); *kept: they are kept and estimates will use them.
 tm_status tm_tri_static_prepare(tm_graph *g, hipStream_t st, bool *kept);

@@ -8,11 +8,14 @@
 // three-edge motifs on the same graph share one persistent launch sequence,
 // whatever their motifs, deltas, c, p and seeds (each is its own estimator
 // in the mixed batch; a lone one, or one on a heavy graph, takes the plain
-// weighted sweep, and a lone triangle estimate charged the static path's
-// capped workspace may sum its triangles over the graph's static
-// triangles, found when the graph was added).  It
-// reserves the batch's device workspace from the budget and hands the batch
-// to the slot.  Each slot is a host thread with its own
+// weighted sweep, and a lone triangle estimate may sum its triangles over the
+// graph's static triangles, found when the graph was added).  It reserves
+// the batch's device workspace from the budget and hands the batch to the
+// slot.  The static triangles' per-call workspace depends on the query's
+// windows and is only known on the device, so that path asks the slot for it
+// step by step before it allocates: what fits the budget then is added to the
+// batch's charge, and otherwise the estimate counts its triangles over the
+// incidence lists.  Each slot is a host thread with its own
 // HIP stream (default priority), so batches on different slots overlap on the
 // device; finishing a batch returns its workspace to the budget and wakes the
 // dispatcher, which admits waiting queries as memory and slots free up.
@@ -61,11 +64,6 @@ struct Pending {
 };
 
 constexpr size_t TM_SERVER_MAX_BATCH = 256;
-// A lone triangle estimate on a graph whose static triangles are kept may sum
-// them over those triangles when this much more workspace fits the budget; the
-// call stays within it or counts the triangles over the incidence lists.
-constexpr int64_t TM_SERVER_STATIC_WS = (int64_t)256 << 20;
-
 int64_t buf(int64_t b) { return b > 0 ? b : 256; }  // DevBuf's size for a request of b bytes
 
 // Device bytes of the path a batch takes (the DevBufs it allocates, alive
@@ -79,7 +77,7 @@ bool static_candidate(const tm_graph *g, const std::vector<tm_query> &b) {
     return c >= 20 && c < 28 && tm_tri_static_kept(g);
 }
 
-int64_t batch_ws_bytes(const tm_graph *g, const std::vector<tm_query> &b, bool with_static = false) {
+int64_t batch_ws_bytes(const tm_graph *g, const std::vector<tm_query> &b) {
     const tm_query &q0 = b[0];
     const bool three = tm_sweep_code_of(&q0.motif) >= 0;
     const int64_t m1 = g->m > 0 ? g->m : 1;
@@ -103,10 +101,9 @@ int64_t batch_ws_bytes(const tm_graph *g, const std::vector<tm_query> &b, bool w
         return buf(64) + tm_generic_bytes(g->m, q0.motif.l);
     }
     if (three && b.size() == 1) {
-        // the plain weighted sweep: accumulators, work counters, weights; and
-        // the static triangles' capped workspace when the batch may take them
-        return buf(36 * 4 * 8) + buf(TM_SWEEP_COUNTER_BYTES) + buf((q0.delta + 1) * 8) +
-               (with_static ? TM_SERVER_STATIC_WS : 0);
+        // the plain weighted sweep: accumulators, work counters, weights (the
+        // static triangles' workspace is granted while the batch runs)
+        return buf(36 * 4 * 8) + buf(TM_SWEEP_COUNTER_BYTES) + buf((q0.delta + 1) * 8);
     }
     if (three) {
         std::vector<int64_t> delta, L;
@@ -161,6 +158,7 @@ struct tm_server {
     std::vector<bool> slot_busy;
     std::vector<bool> slot_heavy;      // the running batch is on a heavy graph
     std::vector<bool> slot_static;     // the running batch may take the static triangles
+    std::vector<int64_t> slot_granted; // of the charge, what the static triangles were granted
     // heavy: at least an eighth of the edges of the largest graph added,
     // when some graph is lighter than that (one size class: none is heavy)
     bool is_heavy(const tm_graph *g) const {
@@ -236,14 +234,7 @@ struct tm_server {
                 const bool heavy = is_heavy(g);
                 if (heavy && heavy_running >= heavy_cap) continue;
                 int64_t need = batch_ws_bytes(g, {head.q});
-                bool use_static = false;
-                if (static_candidate(g, {head.q})) {
-                    const int64_t ns = batch_ws_bytes(g, {head.q}, true);
-                    if (ns <= budget) {
-                        need = ns;
-                        use_static = true;
-                    }
-                }
+                bool use_static = static_candidate(g, {head.q});
                 if (need > budget) {
                     tm_result r;
                     memset(&r, 0, sizeof r);
@@ -308,7 +299,7 @@ struct tm_server {
         }
     }
 
-    void run_batch(int slot, std::vector<Pending> &batch, int64_t charged) {
+    void run_batch(int slot, std::vector<Pending> &batch) {
         hipStream_t st = streams[(size_t)slot];
         const int64_t base = t_dev_tally.live;
         t_dev_tally.peak = base;
@@ -353,6 +344,7 @@ struct tm_server {
         Clock::time_point end = Clock::now();
         const int64_t measured = t_dev_tally.peak - base;
         std::lock_guard<std::mutex> lk(mu);
+        const int64_t charged = slot_bytes[(size_t)slot];  // with what the static triangles were granted
         measured_max = std::max(measured_max, measured);
         if (measured > charged) ++over_charge;
         for (int i = 0; i < n; ++i) {
@@ -368,6 +360,28 @@ struct tm_server {
         cv_done.notify_all();
     }
 
+    // The static triangles' set-up on a slot thread asks for the bytes its
+    // call allocates in all: the part beyond what the batch was granted so
+    // far is added to the batch's charge when it fits the budget.
+    struct GrantCtx {
+        tm_server *S;
+        int slot;
+    };
+    static bool grant(void *ctx, int64_t bytes) {
+        const GrantCtx *c = static_cast<const GrantCtx *>(ctx);
+        tm_server *S = c->S;
+        std::lock_guard<std::mutex> lk(S->mu);
+        const size_t k = (size_t)c->slot;
+        const int64_t more = bytes - S->slot_granted[k];
+        if (more <= 0) return true;
+        if (S->in_use + more > S->budget) return false;
+        S->in_use += more;
+        S->slot_bytes[k] += more;
+        S->slot_granted[k] = bytes;
+        S->peak = std::max(S->peak, S->in_use);
+        return true;
+    }
+
     // what this slot thread holds now replaces what it held (lock held)
     void set_held(int slot) {
         const int64_t h = std::max<int64_t>(0, t_dev_tally.live);
@@ -379,10 +393,10 @@ struct tm_server {
     void worker_loop(int slot) {
         (void)hipSetDevice(device);
         t_dev_tally.live = t_dev_tally.peak = 0;  // this thread's own allocations only
-        tm_tri_static_set_cap(TM_SERVER_STATIC_WS);  // a batch allocates no more than it was charged
+        GrantCtx gc{this, slot};
+        tm_tri_static_set_grant(&tm_server::grant, &gc);  // a batch allocates no more than it was charged
         while (true) {
             std::vector<Pending> batch;
-            int64_t charged = 0;
             bool use_static = false;
             {
                 std::unique_lock<std::mutex> lk(mu);
@@ -401,15 +415,15 @@ struct tm_server {
                 if (slot_work[(size_t)slot].empty()) return;  // stop requested, no work
                 batch = std::move(slot_work[(size_t)slot]);
                 slot_work[(size_t)slot].clear();
-                charged = slot_bytes[(size_t)slot];
                 use_static = slot_static[(size_t)slot];
             }
             tm_tri_static_enable(use_static);
-            run_batch(slot, batch, charged);
+            run_batch(slot, batch);
             {
                 std::lock_guard<std::mutex> lk(mu);
                 in_use -= slot_bytes[(size_t)slot];
                 slot_bytes[(size_t)slot] = 0;
+                slot_granted[(size_t)slot] = 0;
                 set_held(slot);
                 slot_busy[(size_t)slot] = false;
             }
@@ -434,6 +448,7 @@ extern "C" tm_status tm_server_create(int32_t slots, int64_t budget_bytes, tm_se
     S->slot_busy.assign((size_t)slots, false);
     S->slot_heavy.assign((size_t)slots, false);
     S->slot_static.assign((size_t)slots, false);
+    S->slot_granted.assign((size_t)slots, 0);
     for (int i = 0; i < slots; ++i) {
         hipStream_t st;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {

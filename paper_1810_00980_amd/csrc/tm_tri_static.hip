@@ -675,9 +675,10 @@ struct StWs {
 thread_local StWs t_st;
 
 thread_local bool t_st_enabled = true;
-// most device bytes a call may add to the calling thread's workspaces (0:
-// no limit; the index is then also built on first use)
-thread_local int64_t t_st_cap = 0;
+// asked for a call's workspace bytes before it allocates them (nullptr: no
+// limit, and the index is then also built on first use)
+thread_local tm_st_grant_fn t_st_grant = nullptr;
+thread_local void *t_st_grant_ctx = nullptr;
 
 tm_status read_i64(const int64_t *d, int64_t *h, hipStream_t st) {
     TM_HIP(hipMemcpyAsync(h, d, 8, hipMemcpyDeviceToHost, st));
@@ -769,7 +770,10 @@ tm_status st_index(tm_graph *g, hipStream_t st, bool may_build, bool *ok) {
 
 void tm_tri_static_enable(bool on) { t_st_enabled = on; }
 
-void tm_tri_static_set_cap(int64_t bytes) { t_st_cap = bytes > 0 ? bytes : 0; }
+void tm_tri_static_set_grant(tm_st_grant_fn fn, void *ctx) {
+    t_st_grant = fn;
+    t_st_grant_ctx = ctx;
+}
 
 tm_status tm_tri_static_prepare(tm_graph *g, hipStream_t st, bool *kept) {
     *kept = false;
@@ -807,9 +811,10 @@ tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64
     *nu_out = *nt_out = 0;
     if (L <= 0) return TM_OK;
     tm_graph *g = const_cast<tm_graph *>(gc);  // the index is a cache of the immutable graph
-    const int64_t cap = census ? 0 : t_st_cap;
+    const tm_st_grant_fn grant = census ? nullptr : t_st_grant;
+    auto fits = [&](int64_t bytes) { return !grant || grant(t_st_grant_ctx, bytes); };
     bool ok = false;
-    TM_TRY(st_index(g, st, cap == 0, &ok));
+    TM_TRY(st_index(g, st, grant == nullptr, &ok));
     if (!ok) return TM_OK;
     const int64_t ntri = g->st_ntri;
     if (ntri == 0) {
@@ -818,11 +823,12 @@ tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64
     }
     // the kept window ids, when their list is small enough to build per call
     const int64_t J = (g->t_span - s) / L + 1;
-    // with a cap, the path is left to the incidence-list sweep as soon as its
-    // workspace (counts, window list, scans, units, tasks, sort) would pass it
+    // with a grant hook, the path is left to the incidence-list sweep as soon
+    // as the hook refuses its workspace (counts, window list, scans, units,
+    // tasks, sort)
     int64_t ws = (ntri + 1) * 8 + (J <= ST_MAX_WINDOW_LIST ? (2 * J + 1) * 8 : 0) +
                  tm_scan_ws_bytes(ntri > J ? ntri : J);
-    if (cap && ws > cap) return TM_OK;
+    if (!fits(ws)) return TM_OK;
     *used = true;
     const DevGraph G = dev_view(g);
     const StTri *tris = g->st_tri.as<StTri>();
@@ -855,7 +861,7 @@ tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64
     }
     if (nu > UINT32_MAX) return TM_ENOMEM;
     ws += (int64_t)nu * (int64_t)(sizeof(StUnit) + 8) + 8 + tm_scan_ws_bytes(nu);
-    if (cap && ws > cap) {
+    if (!fits(ws)) {
         tm_prof_end(tok, st);
         *used = false;
         return TM_OK;
@@ -870,7 +876,7 @@ tm_status st_run(const tm_graph *gc, int64_t delta, int64_t s, int64_t L, uint64
     TM_TRY(read_i64(W.tcnt.as<int64_t>() + nu, &nt, st));
     if (nt > UINT32_MAX) return TM_ENOMEM;
     ws += nt * 20 + 8 + tm_radix_sort_bytes(nt);
-    if (cap && ws > cap) {
+    if (!fits(ws)) {
         tm_prof_end(tok, st);
         *used = false;
         return TM_OK;
