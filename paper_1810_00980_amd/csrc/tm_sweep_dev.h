@@ -476,6 +476,13 @@ __device__ inline void tri_rank(const DevGraph &G, uint32_t yi, uint32_t di, int
 // triangle sweep gains too, though it drops from five resident waves to
 // four: on a 10M-edge Zipf graph at c 30, p 0.1, 91 -> 84 ms.)
 constexpr int SCAN_U = 4;
+// The fused forward 2-node/star sweep (all three of its classes in one
+// kernel) reads eight at a time: 166 VGPRs instead of 146, still three waves
+// per SIMD, and beside the static triangles and the backward sweep the four
+// estimate passes on that graph went 109 -> 107 ms.
+// The backward sweep at eight takes 106 VGPRs instead of 84 and no longer
+// fits beside the other two (120 ms).
+constexpr int SCAN_U_FWD = 8;
 
 // forward: entries j = first, first + 1, ... < end (times tv, endpoint words
 // ndv) with time <= hi; visit(t, nd, w) with w = the weight of duration
@@ -561,7 +568,8 @@ __device__ inline void sweep_fwd(const DevGraph &G, const SweepArgs &a, int64_t 
     uint64_t cs0 = 0, cs1 = 0, ca0 = 0, ca1 = 0;  // middles before the current time group
     uint64_t ps0 = 0, ps1 = 0, pa0 = 0, pa1 = 0;  // entries of the current time group
     int64_t tg = t1;
-    scan_up<MODE, SCAN_U>(G.inc_t, G.inc_nd, a, i + 1, end, t1, hi, [&](int64_t tj, uint32_t nd, uint64_t w) {
+    scan_up<MODE, CLS == 7u ? SCAN_U_FWD : SCAN_U>(G.inc_t, G.inc_nd, a, i + 1, end, t1, hi,
+                                                 [&](int64_t tj, uint32_t nd, uint64_t w) {
         if (tj == t1) return;
         if (tj != tg) {
             cs0 += ps0; cs1 += ps1; ca0 += pa0; ca1 += pa1;
